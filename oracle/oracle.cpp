@@ -1,0 +1,668 @@
+/*
+ * CPU oracle for the barrier-repair path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only tests/, the smoke entry point and the benchmark's CPU-baseline leg
+ * load this library.  It is deliberately plain: records are materialised,
+ * grouped with std::sort and compared pairwise; clauses are reduced by an
+ * O(n^2) subsumption sweep; the solver enumerates assignments (or runs a
+ * plain depth-first branch and bound on large components).
+ *
+ * Definitions followed (Joshi & Muduganti, arXiv 2011.08373):
+ *   - data race: two threads touch one location, at least one writes, with
+ *     no barrier in between (Section 1, Listing 1);
+ *   - barrier divergence: a barrier reached by only part of a block
+ *     (Section 1, Listing 2);
+ *   - a block-level barrier orders threads of one block, a grid-level
+ *     barrier orders every pair of threads (Section 1; Section 2.2);
+ *   - instrumented barriers guarded by barrier variables, pre-existing
+ *     barriers guarded too (Section 2.2);
+ *   - race -> positive clause over the barrier variables disabled in the
+ *     trace, divergence -> negative clause (Section 2.4);
+ *   - Solve: weighted partial MaxSAT, hard clauses phi, soft {not b_i}
+ *     weighted per Section 2.4 (weights are inputs here);
+ *   - the repair loop of Alg. 1.
+ *
+ * Readings where the text is silent (each is listed in the design notes):
+ * "between" means strictly between two program positions; an enabled
+ * barrier separates every thread pair whether or not it diverges; a thread
+ * never races with itself; read-read never races; each divergence clause is
+ * the unit {not b_s}; ties in Solve are broken by (weight, number of enabled
+ * barriers, mask as an unsigned integer); Solve returns a total assignment
+ * with unconstrained variables false.
+ *
+ * Parity pins: every function here is exercised against worked examples of
+ * the paper, closed forms and brute force in tests/test_oracle_*.py.
+ */
+#include "oracle.h"
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+typedef unsigned __int128 u128;
+
+const int ACCESS = 0, BARRIER = 1;
+const int GLOBAL = 1;
+const int GRID = 1;
+
+// ---------------------------------------------------------------- validation
+int validate(const or_kernel* k) {
+  if (!k) return OR_ERR_INVALID;
+  if (k->blocks < 1 || k->threads < 1) return OR_ERR_INVALID;
+  if (k->n_slots > 64 || k->n_points > 4096) return OR_ERR_INVALID;
+  if ((k->n_arrays && !k->arrays) || (k->n_guards && !k->guards) ||
+      (k->n_points && !k->points) || (k->n_slots && !k->slots))
+    return OR_ERR_INVALID;
+  for (u32 a = 0; a < k->n_arrays; a++)
+    if (k->arrays[a].words < 1 || k->arrays[a].space > 1) return OR_ERR_INVALID;
+  for (u32 g = 0; g < k->n_guards; g++)
+    if (k->guards[g].m < 1 || k->guards[g].r >= k->guards[g].m) return OR_ERR_INVALID;
+  for (u32 s = 0; s < k->n_slots; s++)
+    if (k->slots[s].level > 1 || k->slots[s].preexisting > 1 || k->slots[s].weight < 1)
+      return OR_ERR_INVALID;
+  std::vector<int> slot_guard(k->n_slots, -1);
+  u32 next_slot = 0;
+  for (u32 i = 0; i < k->n_points; i++) {
+    const or_point& p = k->points[i];
+    if (p.kind > 2) return OR_ERR_INVALID;
+    if (p.kind == ACCESS) {
+      if (p.array >= k->n_arrays || p.guard >= k->n_guards || p.is_write > 1)
+        return OR_ERR_INVALID;
+    } else if (p.kind == BARRIER) {
+      if (p.slot >= k->n_slots || p.guard >= k->n_guards) return OR_ERR_INVALID;
+      if (slot_guard[p.slot] < 0) {
+        // slots are numbered by first occurrence
+        if (p.slot != next_slot) return OR_ERR_INVALID;
+        next_slot++;
+        slot_guard[p.slot] = p.guard;
+      } else if (slot_guard[p.slot] != (int)p.guard) {
+        return OR_ERR_INVALID;  // all occurrences of a slot share a guard
+      }
+    }
+  }
+  if (next_slot != k->n_slots) return OR_ERR_INVALID;  // every slot occurs
+  return OR_OK;
+}
+
+// ------------------------------------------------------------ model helpers
+bool active(const or_kernel* k, u32 i, u32 t) {
+  const or_guard& g = k->guards[k->points[i].guard];
+  return t % g.m == g.r;
+}
+
+u64 address(const or_kernel* k, u32 i, u32 blk, u32 t) {
+  const or_point& p = k->points[i];
+  i64 n = (i64)k->arrays[p.array].words;
+  i64 v = (i64)p.a * (i64)t + (i64)p.b * (i64)blk + (i64)p.c;
+  return (u64)(((v % n) + n) % n);  // Euclidean residue in [0, n)
+}
+
+bool is_global(const or_kernel* k, u32 i) {
+  return k->arrays[k->points[i].array].space == GLOBAL;
+}
+
+// An enabled barrier occurrence strictly between positions i < j.
+// grid_only: only grid-level barriers count (they alone order threads of
+// different blocks).
+bool separated(const or_kernel* k, u64 x, u32 i, u32 j, bool grid_only) {
+  for (u32 u = i + 1; u < j; u++) {
+    const or_point& p = k->points[u];
+    if (p.kind != BARRIER) continue;
+    if (!((x >> p.slot) & 1)) continue;
+    if (grid_only && k->slots[p.slot].level != GRID) continue;
+    return true;
+  }
+  return false;
+}
+
+// Number of threads of one block that execute a barrier with guard g.
+u64 reached(const or_kernel* k, u32 guard) {
+  u64 n = 0;
+  for (u32 t = 0; t < k->threads; t++)
+    if (t % k->guards[guard].m == k->guards[guard].r) n++;
+  return n;
+}
+
+// Slots that diverge when enabled: reached by some but not all threads of
+// a block.  literal: count per block (the guard reads only the thread id,
+// so every block gives the same count).
+u64 divergent_if_enabled(const or_kernel* k, bool literal) {
+  u64 mask = 0;
+  for (u32 u = 0; u < k->n_points; u++) {
+    const or_point& p = k->points[u];
+    if (p.kind != BARRIER) continue;
+    u32 nb = literal ? k->blocks : 1;
+    for (u32 blk = 0; blk < nb; blk++) {
+      u64 n = reached(k, p.guard);
+      if (n > 0 && n < k->threads) mask |= 1ull << p.slot;
+    }
+  }
+  return mask;
+}
+
+u64 count_records(const or_kernel* k) {
+  u64 n = 0;
+  for (u32 i = 0; i < k->n_points; i++)
+    if (k->points[i].kind == ACCESS) n += reached(k, k->points[i].guard) * k->blocks;
+  return n;
+}
+
+// Pair set as a bitmap over (level, i, j), i <= j.
+struct PairSet {
+  u32 P;
+  std::vector<uint8_t> bits;
+  explicit PairSet(u32 p) : P(p), bits(2ull * p * p, 0) {}
+  void set(int lv, u32 i, u32 j) { bits[(u64)lv * P * P + (u64)i * P + j] = 1; }
+  bool get(int lv, u32 i, u32 j) const { return bits[(u64)lv * P * P + (u64)i * P + j]; }
+};
+
+// -------------------------------------------- conflicts, literal definition
+// Every pair of access records (i, blk, t) / (j, blk', t') is compared.
+void conflicts_literal(const or_kernel* k, u64 x, bool apply_x, PairSet& out) {
+  struct R { u32 i, blk, t; };
+  std::vector<R> recs;
+  for (u32 i = 0; i < k->n_points; i++) {
+    if (k->points[i].kind != ACCESS) continue;
+    for (u32 blk = 0; blk < k->blocks; blk++)
+      for (u32 t = 0; t < k->threads; t++)
+        if (active(k, i, t)) recs.push_back({i, blk, t});
+  }
+  for (size_t r1 = 0; r1 < recs.size(); r1++) {
+    for (size_t r2 = r1 + 1; r2 < recs.size(); r2++) {
+      const R& A = recs[r1];
+      const R& B = recs[r2];  // enumeration order gives A.i <= B.i
+      const or_point& pa = k->points[A.i];
+      const or_point& pb = k->points[B.i];
+      if (pa.array != pb.array) continue;
+      if (!pa.is_write && !pb.is_write) continue;          // read-read never races
+      if (A.blk == B.blk && A.t == B.t) continue;           // one thread
+      bool same_block = A.blk == B.blk;
+      if (!same_block && !is_global(k, A.i)) continue;      // distinct shared instances
+      if (address(k, A.i, A.blk, A.t) != address(k, B.i, B.blk, B.t)) continue;
+      int lv = same_block ? 0 : 1;
+      if (apply_x && separated(k, x, A.i, B.i, lv == 1)) continue;
+      out.set(lv, A.i, B.i);
+    }
+  }
+}
+
+// ------------------------------------------- conflicts, grouped by location
+// Same definition, evaluated per memory location: records are grouped by
+// (array, block, address) for the same-block relation and by (array,
+// address) for the cross-block relation; within a location every pair of
+// points is examined.  Independent of any barrier assignment.
+void conflicts_grouped(const or_kernel* k, PairSet& out) {
+  // same block
+  {
+    struct R { u32 arr, blk; u64 addr; u32 i, t; };
+    std::vector<R> recs;
+    for (u32 i = 0; i < k->n_points; i++) {
+      if (k->points[i].kind != ACCESS) continue;
+      for (u32 blk = 0; blk < k->blocks; blk++)
+        for (u32 t = 0; t < k->threads; t++)
+          if (active(k, i, t))
+            recs.push_back({k->points[i].array, blk, address(k, i, blk, t), i, t});
+    }
+    std::sort(recs.begin(), recs.end(), [](const R& a, const R& b) {
+      if (a.arr != b.arr) return a.arr < b.arr;
+      if (a.blk != b.blk) return a.blk < b.blk;
+      if (a.addr != b.addr) return a.addr < b.addr;
+      if (a.i != b.i) return a.i < b.i;
+      return a.t < b.t;
+    });
+    struct G { u32 i; u64 n; u32 t0; };
+    std::vector<G> pts;
+    size_t s = 0;
+    while (s < recs.size()) {
+      size_t e = s;
+      while (e < recs.size() && recs[e].arr == recs[s].arr && recs[e].blk == recs[s].blk &&
+             recs[e].addr == recs[s].addr)
+        e++;
+      pts.clear();
+      for (size_t r = s; r < e; r++) {
+        if (pts.empty() || pts.back().i != recs[r].i) pts.push_back({recs[r].i, 0, recs[r].t});
+        pts.back().n++;  // distinct threads: one record per (point, block, thread)
+      }
+      for (size_t a = 0; a < pts.size(); a++) {
+        const or_point& pa = k->points[pts[a].i];
+        if (pa.is_write && pts[a].n >= 2) out.set(0, pts[a].i, pts[a].i);
+        for (size_t b = a + 1; b < pts.size(); b++) {
+          const or_point& pb = k->points[pts[b].i];
+          if (!pa.is_write && !pb.is_write) continue;
+          bool one_same_thread = pts[a].n == 1 && pts[b].n == 1 && pts[a].t0 == pts[b].t0;
+          if (!one_same_thread) out.set(0, pts[a].i, pts[b].i);
+        }
+      }
+      s = e;
+    }
+  }
+  // different blocks (global arrays)
+  {
+    struct R { u32 arr; u64 addr; u32 i, blk; };
+    std::vector<R> recs;
+    for (u32 i = 0; i < k->n_points; i++) {
+      if (k->points[i].kind != ACCESS || !is_global(k, i)) continue;
+      for (u32 blk = 0; blk < k->blocks; blk++)
+        for (u32 t = 0; t < k->threads; t++)
+          if (active(k, i, t))
+            recs.push_back({k->points[i].array, address(k, i, blk, t), i, blk});
+    }
+    std::sort(recs.begin(), recs.end(), [](const R& a, const R& b) {
+      if (a.arr != b.arr) return a.arr < b.arr;
+      if (a.addr != b.addr) return a.addr < b.addr;
+      if (a.i != b.i) return a.i < b.i;
+      return a.blk < b.blk;
+    });
+    struct G { u32 i; u64 nblk; u32 b0; };
+    std::vector<G> pts;
+    size_t s = 0;
+    while (s < recs.size()) {
+      size_t e = s;
+      while (e < recs.size() && recs[e].arr == recs[s].arr && recs[e].addr == recs[s].addr) e++;
+      pts.clear();
+      for (size_t r = s; r < e; r++) {
+        if (pts.empty() || pts.back().i != recs[r].i) {
+          pts.push_back({recs[r].i, 1, recs[r].blk});
+        } else if (recs[r].blk != recs[r - 1].blk) {
+          pts.back().nblk++;  // distinct blocks of this point here
+        }
+      }
+      for (size_t a = 0; a < pts.size(); a++) {
+        const or_point& pa = k->points[pts[a].i];
+        if (pa.is_write && pts[a].nblk >= 2) out.set(1, pts[a].i, pts[a].i);
+        for (size_t b = a + 1; b < pts.size(); b++) {
+          const or_point& pb = k->points[pts[b].i];
+          if (!pa.is_write && !pb.is_write) continue;
+          bool one_same_block = pts[a].nblk == 1 && pts[b].nblk == 1 && pts[a].b0 == pts[b].b0;
+          if (!one_same_block) out.set(1, pts[a].i, pts[b].i);
+        }
+      }
+      s = e;
+    }
+  }
+}
+
+// Races under x, emitted in (level, i, j) order.
+void races(const or_kernel* k, u64 x, bool literal, std::vector<or_pair>& out) {
+  PairSet ps(k->n_points);
+  if (literal) {
+    conflicts_literal(k, x, true, ps);
+  } else {
+    conflicts_grouped(k, ps);
+  }
+  out.clear();
+  for (int lv = 0; lv < 2; lv++)
+    for (u32 i = 0; i < k->n_points; i++)
+      for (u32 j = i; j < k->n_points; j++) {
+        if (!ps.get(lv, i, j)) continue;
+        if (!literal && separated(k, x, i, j, lv == 1)) continue;
+        out.push_back({(uint16_t)i, (uint16_t)j, (uint8_t)lv, 0});
+      }
+}
+
+// Positive clause of a race between i and j: the barrier variables of every
+// occurrence strictly between them (only grid-level ones for a cross-block
+// race).  An empty clause means no barrier can separate the pair.
+u64 race_clause(const or_kernel* k, u32 i, u32 j, int lv) {
+  u64 pos = 0;
+  for (u32 u = i + 1; u < j; u++) {
+    const or_point& p = k->points[u];
+    if (p.kind != BARRIER) continue;
+    if (lv == 1 && k->slots[p.slot].level != GRID) continue;
+    pos |= 1ull << p.slot;
+  }
+  return pos;
+}
+
+bool clause_less(const or_clause& a, const or_clause& b) {
+  return a.pos != b.pos ? a.pos < b.pos : a.neg < b.neg;
+}
+
+std::vector<or_clause> reduce(std::vector<or_clause> c) {
+  std::sort(c.begin(), c.end(), clause_less);
+  c.erase(std::unique(c.begin(), c.end(),
+                      [](const or_clause& a, const or_clause& b) {
+                        return a.pos == b.pos && a.neg == b.neg;
+                      }),
+          c.end());
+  std::vector<or_clause> out;
+  for (size_t a = 0; a < c.size(); a++) {
+    bool subsumed = false;
+    for (size_t b = 0; b < c.size() && !subsumed; b++) {
+      if (a == b) continue;
+      // c[b] subsumes c[a] when its literals are a subset of c[a]'s
+      if ((c[b].pos & ~c[a].pos) == 0 && (c[b].neg & ~c[a].neg) == 0) subsumed = true;
+    }
+    if (!subsumed) out.push_back(c[a]);
+  }
+  return out;
+}
+
+std::vector<or_clause> clauses_under(const or_kernel* k, u64 x) {
+  std::vector<or_pair> rp;
+  races(k, x, false, rp);
+  std::vector<or_clause> c;
+  for (const or_pair& p : rp) c.push_back({race_clause(k, p.i, p.j, p.level), 0});
+  u64 div = divergent_if_enabled(k, false) & x;
+  for (u32 s = 0; s < 64; s++)
+    if ((div >> s) & 1) c.push_back({0, 1ull << s});
+  return reduce(c);
+}
+
+// ------------------------------------------------------------------- solver
+// key(x) = (W(x), popcount(x), x) lexicographic; as one integer it is the
+// sum over enabled slots of w_s*2^71 + 2^64 + 2^s, which is additive.
+u128 slot_key(const uint32_t* w, u32 s) {
+  return ((u128)w[s] << 71) + ((u128)1 << 64) + ((u128)1 << s);
+}
+
+bool satisfies(const or_clause& c, u64 x) {
+  return (x & c.pos) != 0 || (~x & c.neg) != 0;
+}
+
+int solve_exhaustive(const std::vector<or_clause>& c, const uint32_t* w, u32 S, u64* best_x) {
+  bool found = false;
+  u128 best = 0;
+  for (u64 x = 0; x < (1ull << S); x++) {
+    bool ok = true;
+    for (const or_clause& cl : c)
+      if (!satisfies(cl, x)) { ok = false; break; }
+    if (!ok) continue;
+    u128 key = 0;
+    for (u32 s = 0; s < S; s++)
+      if ((x >> s) & 1) key += slot_key(w, s);
+    if (!found || key < best) { best = key; *best_x = x; found = true; }
+  }
+  return found ? OR_OK : OR_UNSAT;
+}
+
+struct BnB {
+  const std::vector<or_clause>* c;
+  const uint32_t* w;
+  std::vector<u32> slots;  // component slots, ascending
+  bool found = false;
+  u128 best = 0;
+  u64 best_x = 0;
+  void dfs(size_t idx, u64 decided, u64 x, u128 key) {
+    if (found && key >= best) return;  // every extension costs at least key
+    for (const or_clause& cl : *c) {
+      bool pos_dead = (cl.pos & ~(decided & ~x)) == 0;
+      bool neg_dead = (cl.neg & ~(decided & x)) == 0;
+      if (pos_dead && neg_dead) return;  // clause already falsified
+    }
+    if (idx == slots.size()) {
+      found = true; best = key; best_x = x;
+      return;
+    }
+    u64 bit = 1ull << slots[idx];
+    dfs(idx + 1, decided | bit, x, key);
+    dfs(idx + 1, decided | bit, x | bit, key + slot_key(w, slots[idx]));
+  }
+};
+
+// Exact solve: slots in no positive literal stay false; the remaining
+// clauses split into independent components (the key is additive), each
+// solved by enumeration (<= 20 slots) or depth-first branch and bound.
+int solve_reduced(const std::vector<or_clause>& in, const uint32_t* w, u32 S, u64* out) {
+  u64 core = 0;
+  for (const or_clause& c : in) core |= c.pos;
+  std::vector<or_clause> cl;
+  for (const or_clause& c : in) {
+    if (c.neg & ~core) continue;  // satisfied: that slot stays false
+    if ((c.pos | c.neg) == 0) return OR_UNSAT;
+    cl.push_back(c);
+  }
+  // components by repeated closure over clause literal sets
+  u64 left = core;
+  u64 result = 0;
+  while (left) {
+    u64 comp = left & (~left + 1);
+    bool grew = true;
+    while (grew) {
+      grew = false;
+      for (const or_clause& c : cl) {
+        u64 lit = c.pos | c.neg;
+        if ((lit & comp) && (lit & ~comp)) { comp |= lit; grew = true; }
+      }
+    }
+    left &= ~comp;
+    std::vector<or_clause> cc;
+    for (const or_clause& c : cl)
+      if ((c.pos | c.neg) & comp) cc.push_back(c);
+    std::vector<u32> ids;
+    for (u32 s = 0; s < S; s++)
+      if ((comp >> s) & 1) ids.push_back(s);
+    if (ids.size() <= 20) {
+      // enumerate the component's slots
+      bool found = false;
+      u128 best = 0;
+      u64 best_x = 0;
+      for (u64 m = 0; m < (1ull << ids.size()); m++) {
+        u64 x = 0;
+        u128 key = 0;
+        for (size_t b = 0; b < ids.size(); b++)
+          if ((m >> b) & 1) { x |= 1ull << ids[b]; key += slot_key(w, ids[b]); }
+        bool ok = true;
+        for (const or_clause& c : cc)
+          if (!satisfies(c, x)) { ok = false; break; }
+        if (ok && (!found || key < best)) { found = true; best = key; best_x = x; }
+      }
+      if (!found) return OR_UNSAT;
+      result |= best_x;
+    } else {
+      BnB b;
+      b.c = &cc; b.w = w; b.slots = ids;
+      b.dfs(0, 0, 0, 0);
+      if (!b.found) return OR_UNSAT;
+      result |= b.best_x;
+    }
+  }
+  *out = result;
+  return OR_OK;
+}
+
+u64 weight_of(const uint32_t* w, u32 S, u64 x) {
+  u64 W = 0;
+  for (u32 s = 0; s < S; s++)
+    if ((x >> s) & 1) W += w[s];
+  return W;
+}
+
+}  // namespace
+
+// =========================================================== C entry points
+extern "C" int or_validate(const or_kernel* k) { return validate(k); }
+
+extern "C" int or_check(const or_kernel* k, uint64_t x, int literal, or_pair* pairs,
+                        uint64_t cap, uint64_t* n_pairs, uint64_t* divergent,
+                        uint64_t* n_records) {
+  int v = validate(k);
+  if (v != OR_OK) return v;
+  std::vector<or_pair> rp;
+  races(k, x, literal != 0, rp);
+  if (n_records) *n_records = count_records(k);
+  if (divergent) *divergent = divergent_if_enabled(k, literal != 0) & x;
+  if (n_pairs) *n_pairs = rp.size();
+  if (rp.size() > cap) return OR_ERR_CAPACITY;
+  for (size_t n = 0; n < rp.size(); n++) pairs[n] = rp[n];
+  return OR_OK;
+}
+
+extern "C" int or_pair_conflict(const or_kernel* k, uint32_t i, uint32_t j, int level) {
+  if (validate(k) != OR_OK || i >= k->n_points || j >= k->n_points || i > j) return -1;
+  const or_point& pa = k->points[i];
+  const or_point& pb = k->points[j];
+  if (pa.kind != ACCESS || pb.kind != ACCESS || pa.array != pb.array) return 0;
+  if (!pa.is_write && !pb.is_write) return 0;
+  if (level == 1 && !is_global(k, i)) return 0;
+  // location -> distinct ids (thread for the same-block relation, block for
+  // the cross-block one)
+  struct E { u64 loc; u32 id; };
+  auto collect = [&](u32 p, std::vector<E>& v) {
+    for (u32 blk = 0; blk < k->blocks; blk++)
+      for (u32 t = 0; t < k->threads; t++)
+        if (active(k, p, t)) {
+          u64 a = address(k, p, blk, t);
+          if (level == 0) v.push_back({((u64)blk << 32) | a, t});
+          else v.push_back({a, blk});
+        }
+    std::sort(v.begin(), v.end(), [](const E& x, const E& y) {
+      return x.loc != y.loc ? x.loc < y.loc : x.id < y.id;
+    });
+  };
+  std::vector<E> A, B;
+  collect(i, A);
+  if (i == j) {
+    for (size_t n = 1; n < A.size(); n++)
+      if (A[n].loc == A[n - 1].loc && A[n].id != A[n - 1].id) return pa.is_write ? 1 : 0;
+    return 0;
+  }
+  collect(j, B);
+  size_t a = 0, b = 0;
+  while (a < A.size() && b < B.size()) {
+    if (A[a].loc < B[b].loc) { a++; continue; }
+    if (B[b].loc < A[a].loc) { b++; continue; }
+    u64 loc = A[a].loc;
+    size_t ae = a, be = b;
+    while (ae < A.size() && A[ae].loc == loc) ae++;
+    while (be < B.size() && B[be].loc == loc) be++;
+    bool a_one = A[a].id == A[ae - 1].id, b_one = B[b].id == B[be - 1].id;
+    if (!(a_one && b_one && A[a].id == B[b].id)) return 1;
+    a = ae; b = be;
+  }
+  return 0;
+}
+
+extern "C" int or_clauses(const or_kernel* k, uint64_t x, or_clause* out, uint64_t cap,
+                          uint64_t* n) {
+  int v = validate(k);
+  if (v != OR_OK) return v;
+  std::vector<or_clause> c = clauses_under(k, x);
+  if (n) *n = c.size();
+  if (c.size() > cap) return OR_ERR_CAPACITY;
+  for (size_t q = 0; q < c.size(); q++) out[q] = c[q];
+  return OR_OK;
+}
+
+extern "C" int or_full_clauses(const or_kernel* k, or_clause* out, uint64_t cap, uint64_t* n) {
+  int v = validate(k);
+  if (v != OR_OK) return v;
+  // with no barrier enabled nothing separates, so the races under x = 0
+  // are all conflicting pairs
+  std::vector<or_clause> c;
+  std::vector<or_pair> rp;
+  races(k, 0, false, rp);
+  for (const or_pair& p : rp) c.push_back({race_clause(k, p.i, p.j, p.level), 0});
+  u64 div = divergent_if_enabled(k, false);
+  for (u32 s = 0; s < 64; s++)
+    if ((div >> s) & 1) c.push_back({0, 1ull << s});
+  c = reduce(c);
+  if (n) *n = c.size();
+  if (c.size() > cap) return OR_ERR_CAPACITY;
+  for (size_t q = 0; q < c.size(); q++) out[q] = c[q];
+  return OR_OK;
+}
+
+extern "C" uint64_t or_reduce(or_clause* c, uint64_t n) {
+  std::vector<or_clause> v(c, c + n);
+  v = reduce(v);
+  for (size_t q = 0; q < v.size(); q++) c[q] = v[q];
+  return v.size();
+}
+
+extern "C" int or_min_barriers(const or_clause* c, uint64_t n, const uint32_t* weights,
+                               uint32_t n_slots, int method, uint64_t* assign,
+                               uint64_t* weight) {
+  if (n_slots > 64 || (n && !c)) return OR_ERR_INVALID;
+  for (u32 s = 0; s < n_slots; s++)
+    if (weights[s] < 1) return OR_ERR_INVALID;
+  u64 valid = n_slots == 64 ? ~0ull : ((1ull << n_slots) - 1);
+  for (u64 q = 0; q < n; q++)
+    if ((c[q].pos | c[q].neg) & ~valid) return OR_ERR_INVALID;
+  std::vector<or_clause> cl(c, c + n);
+  u64 x = 0;
+  int st;
+  if (method == 1) {
+    if (n_slots > 26) return OR_ERR_INVALID;
+    st = solve_exhaustive(cl, weights, n_slots, &x);
+  } else {
+    st = solve_reduced(cl, weights, n_slots, &x);
+  }
+  if (st == OR_OK) {
+    if (assign) *assign = x;
+    if (weight) *weight = weight_of(weights, n_slots, x);
+  }
+  return st;
+}
+
+extern "C" int or_repair(const or_kernel* k, const or_opts* o, or_result* out,
+                         uint64_t* trajectory, uint32_t traj_cap) {
+  int v = validate(k);
+  if (v != OR_OK) return v;
+  or_opts opt = o ? *o : or_opts{0, 1, 1, 0, 0};
+  std::vector<uint32_t> w(k->n_slots);
+  u64 pre = 0;
+  for (u32 s = 0; s < k->n_slots; s++) {
+    w[s] = k->slots[s].weight;
+    if (k->slots[s].preexisting) pre |= 1ull << s;
+  }
+  // phi := true, plus the option units (grid-level barriers disallowed;
+  // pre-existing barriers kept when they are not inspected)
+  std::vector<or_clause> phi;
+  for (u32 s = 0; s < k->n_slots; s++) {
+    if (!opt.grid && k->slots[s].level == GRID) phi.push_back({0, 1ull << s});
+    if (!opt.inspect && k->slots[s].preexisting) phi.push_back({1ull << s, 0});
+  }
+  phi = reduce(phi);
+  or_result r;
+  std::memset(&r, 0, sizeof(r));
+  u32 rounds = 0;
+  for (;;) {
+    u64 x = 0;
+    int st = solve_reduced(phi, w.data(), k->n_slots, &x);   // Solve(phi)
+    if (st == OR_UNSAT) { r.status = OR_UNSAT; break; }      // cannot be repaired
+    if (opt.max_rounds && rounds == opt.max_rounds) { r.status = OR_ERR_ROUNDS; break; }
+    if (trajectory && rounds < traj_cap) trajectory[rounds] = x;
+    rounds++;
+    std::vector<or_pair> rp;                                  // Verify(P_sol)
+    races(k, x, false, rp);
+    u64 div = divergent_if_enabled(k, false) & x;
+    if (rp.empty() && div == 0) {                             // SAFE
+      r.status = OR_OK;
+      r.assign = x;
+      r.weight = weight_of(w.data(), k->n_slots, x);
+      r.added = x & ~pre;
+      r.removed = pre & ~x;
+      break;
+    }
+    std::vector<or_clause> learned;                           // GenerateClause
+    if (opt.policy == 0) {
+      learned = clauses_under(k, x);
+    } else if (div) {
+      learned.push_back({0, div & (~div + 1)});
+    } else {
+      learned.push_back({race_clause(k, rp[0].i, rp[0].j, rp[0].level), 0});
+    }
+    phi.insert(phi.end(), learned.begin(), learned.end());
+    phi = reduce(phi);
+  }
+  r.rounds = rounds;
+  r.n_clauses = (u32)phi.size();
+  if (out) *out = r;
+  return r.status;
+}
+
+extern "C" int or_safe_literal(const or_kernel* k, uint64_t x) {
+  if (validate(k) != OR_OK) return -1;
+  PairSet ps(k->n_points);
+  conflicts_literal(k, x, true, ps);
+  for (size_t q = 0; q < ps.bits.size(); q++)
+    if (ps.bits[q]) return 0;
+  if (divergent_if_enabled(k, true) & x) return 0;
+  return 1;
+}
