@@ -1,0 +1,191 @@
+/*
+ * librepair -- data-parallel hot path of the counterexample-guided barrier
+ * repair loop of Joshi & Muduganti, "GPURepair: Automated Repair of GPU
+ * Kernels" (arXiv 2011.08373), for AMD Instinct MI355X (gfx950).
+ *
+ * The paper repairs a kernel by alternating Solve (a weighted partial MaxSAT
+ * query over barrier variables) and Verify (a GPUVerify run) in Alg. 1.  This
+ * library computes the concrete counterpart on a finite kernel model: Verify
+ * enumerates every thread of every block, so it decides races and barrier
+ * divergence exactly for the model; Solve is an exact minimum-weight search.
+ *
+ * Kernel model (the instrumented program P of Section 2.3):
+ *   - `blocks` x `threads` threads; thread (bid, tid);
+ *   - arrays: SHARED (one instance per block) or GLOBAL (one instance),
+ *     `words` 32-bit words each;
+ *   - points 0..n_points-1 in program order after loop unrolling.  An ACCESS
+ *     reads or writes `array` at word ((a*tid + b*bid + c) mod words), taken
+ *     as the Euclidean residue in [0, words).  A BARRIER is one occurrence of
+ *     barrier slot `slot` (barrier variable b_slot, Section 2.2); unrolled
+ *     copies of one instrumented barrier share the slot.  NOP does nothing;
+ *   - every ACCESS and BARRIER is executed by the threads with
+ *     tid % guards[guard].m == guards[guard].r (guard {1,0}: all threads);
+ *   - slots: level BLOCK (orders the threads of one block) or GRID (orders
+ *     every pair of threads, Section 2.2), a pre-existing flag (the
+ *     programmer's barrier, which the paper also guards so that it may be
+ *     removed) and a weight >= 1 (Section 2.4: gw*gb + lw^ld).
+ *
+ * Semantics under an assignment x (bit s = barrier variable b_s enabled):
+ *   - two access records conflict when they touch the same array instance
+ *     and word from two different threads and at least one writes
+ *     (Section 1); a same-block pair races unless an enabled barrier of any
+ *     level occurs strictly between the two points; a pair from different
+ *     blocks (GLOBAL arrays only) races unless an enabled GRID barrier does;
+ *   - an enabled barrier diverges when some block has 0 < n < threads of its
+ *     threads executing it (Section 1, Listing 2);
+ *   - a race between points i <= j yields the positive clause of the slots
+ *     strictly between them (GRID slots only for a cross-block race); a
+ *     divergent slot s yields the negative unit {not b_s} (Section 2.4);
+ *   - Solve minimises, lexicographically, (total weight, number of enabled
+ *     barriers, x as an unsigned integer) over the clauses; the optimum is
+ *     unique.
+ *
+ * Calling convention (every entry point):
+ *   - descriptors and output arrays are caller-owned HOST memory, read or
+ *     written only during the call;
+ *   - `ws` is a caller-owned DEVICE buffer of at least the size returned by
+ *     the matching *_workspace_bytes() call, not shared with a concurrent
+ *     call; `stream` is a hipStream_t (NULL = default stream).  Work is
+ *     ordered on that stream and every call synchronises it before return;
+ *   - errors are reported only by the return code.  A validation failure does
+ *     no device work.  RP_UNSAT is a result (Alg. 1: the program cannot be
+ *     repaired), not a failure.  On RP_ERR_CAPACITY the needed count is
+ *     written and nothing else is;
+ *   - limits: 1 <= blocks, threads; n_slots <= 64; n_points <= 4096; the
+ *     packed access record (array, word, block, point, thread indices) must
+ *     fit 64 bits: bits(n_arrays-1) + bits(max words-1) + bits(blocks-1) +
+ *     bits(n_points-1) + bits(threads-1) <= 64.
+ */
+#ifndef LIBREPAIR_H
+#define LIBREPAIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RP_OK = 0,
+  RP_UNSAT = 1,             /* Alg. 1: no assignment avoids every trace seen */
+  RP_ERR_INVALID = -1,      /* descriptor or argument rejected; no device work */
+  RP_ERR_CAPACITY = -2,     /* output (or an internal table) too small */
+  RP_ERR_WORKSPACE = -3,    /* ws smaller than the required size */
+  RP_ERR_DEVICE = -4,       /* a HIP call or a device-side check failed */
+  RP_ERR_ROUNDS = -5,       /* max_rounds Verify calls made without a verdict */
+  RP_ERR_BUDGET = -6        /* server: the job can never fit the memory budget */
+} rp_status;
+
+enum { RP_ACCESS = 0, RP_BARRIER = 1, RP_NOP = 2 };
+enum { RP_SHARED = 0, RP_GLOBAL = 1 };
+enum { RP_BLOCK = 0, RP_GRID = 1 };
+enum { RP_OP_CHECK = 0, RP_OP_CLAUSES = 1, RP_OP_REPAIR = 2 };
+
+typedef struct { uint32_t words; uint8_t space; } rp_array;              /* 8 B */
+typedef struct { uint32_t m, r; } rp_guard;                              /* 8 B */
+typedef struct {
+  uint8_t kind, is_write;
+  uint16_t array, guard, slot;
+  int32_t a, b, c;
+} rp_point;                                                              /* 20 B */
+typedef struct { uint8_t level, preexisting; uint32_t weight; } rp_slot; /* 8 B */
+typedef struct {
+  uint32_t blocks, threads, n_arrays, n_guards, n_points, n_slots;
+  const rp_array* arrays;
+  const rp_guard* guards;
+  const rp_point* points;
+  const rp_slot* slots;
+} rp_kernel;
+
+/* clause: satisfied by x iff (x & pos) != 0 or (~x & neg) != 0 */
+typedef struct { uint64_t pos, neg; } rp_clause;
+/* racing pair of points i <= j; level 0 same block, 1 different blocks */
+typedef struct { uint16_t i, j; uint8_t level, pad; } rp_pair;
+
+typedef struct {
+  uint8_t policy;     /* 0: learn every race/divergence of a Verify call;
+                         1: learn one trace per call (the smallest of
+                            divergence < same-block race < cross-block race) */
+  uint8_t grid;       /* 0: grid-level barriers disallowed (unit not b_s) */
+  uint8_t inspect;    /* 0: pre-existing barriers kept (unit b_s) */
+  uint8_t pad;
+  uint32_t max_rounds;/* Verify calls allowed; 0 = unlimited */
+} rp_repair_opts;
+
+typedef struct {
+  int32_t status;     /* RP_OK (repaired), RP_UNSAT or an error */
+  uint32_t rounds;    /* Verify calls made, the final SAFE one included */
+  uint32_t n_clauses; /* size of the reduced constraint set at exit */
+  uint32_t pad;
+  uint64_t assign;    /* repaired barrier assignment (0 unless RP_OK) */
+  uint64_t weight;    /* its total weight */
+  uint64_t added;     /* enabled instrumented (not pre-existing) barriers */
+  uint64_t removed;   /* pre-existing barriers left disabled */
+} rp_repair_out;
+
+/* Timings of the last call made on this thread (hipEvent milliseconds on the
+ * call's stream) and the work it did. */
+typedef struct {
+  double ms_gen, ms_sort, ms_check, ms_clause, ms_solve, ms_total;
+  double ms_sort_pass_max;       /* longest single sort pass */
+  double ms_sort_kernels;        /* sum of the radix-pass kernel durations */
+  uint64_t records;              /* access records generated (both views) */
+  uint64_t accesses;             /* (point, block, thread) accesses */
+  uint64_t records_scanned;      /* records read by conflict scans */
+  uint32_t sort_passes, sort_launches, rounds, conf_launches;
+} rp_stats;
+
+const char* rp_status_string(int status);
+
+/* Checks every rule above; RP_OK or RP_ERR_INVALID. */
+rp_status rp_validate(const rp_kernel* k);
+
+/* Device workspace needed by rp_check / rp_clauses / rp_repair (op =
+ * RP_OP_*) on this kernel; 0 when the kernel is invalid. */
+size_t rp_workspace_bytes(const rp_kernel* k, int op);
+
+/* Verify(P_x) of Alg. 1: every race and every divergent enabled barrier
+ * under assignment x.  pairs: up to `cap` racing point pairs in ascending
+ * (level, i, j) order; *n_pairs = their number.  *divergent = enabled slots
+ * that diverge.  *n_records = (point, block, thread) accesses examined.
+ * The kernel is safe under x iff *n_pairs == 0 and *divergent == 0. */
+rp_status rp_check(const rp_kernel* k, uint64_t x,
+                   rp_pair* pairs, uint64_t cap, uint64_t* n_pairs,
+                   uint64_t* divergent, uint64_t* n_records,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* GenerateClause of Alg. 1 over every trace under x, reduced: sorted by
+ * (pos, neg) ascending, duplicates and subsumed clauses removed. */
+rp_status rp_clauses(const rp_kernel* k, uint64_t x,
+                     rp_clause* out, uint64_t cap, uint64_t* n_out,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Solve of Alg. 1 (Sections 2.3-2.4): the canonical minimum-weight
+ * assignment satisfying every clause.  RP_OK with *assign / *weight, or
+ * RP_UNSAT.  n_slots <= 64; weights >= 1; clause literals < n_slots. */
+size_t rp_solve_workspace_bytes(uint64_t n_clauses);
+rp_status rp_min_barriers(const rp_clause* clauses, uint64_t n_clauses,
+                          const uint32_t* weights, uint32_t n_slots,
+                          uint64_t* assign, uint64_t* weight,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* The repair loop of Alg. 1: phi starts with the option units; each round
+ * solves phi, verifies the solution and learns clauses until SAFE or UNSAT.
+ * trajectory (optional, may be NULL) receives the assignment verified in
+ * each round, up to traj_cap entries. */
+rp_status rp_repair(const rp_kernel* k, const rp_repair_opts* opts,
+                    rp_repair_out* out, uint64_t* trajectory, uint32_t traj_cap,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Statistics of the last call made on this thread. */
+void rp_last_stats(rp_stats* out);
+
+/* Sort autotuning: digit width of the LSD radix passes (0 = automatic,
+ * else 8..11 bits).  Process-wide; returns the previous value. */
+int rp_set_sort_digit_bits(int bits);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

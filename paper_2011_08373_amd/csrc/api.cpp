@@ -1,0 +1,230 @@
+// The C ABI of librepair (declared in include/librepair.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "plan.h"
+
+namespace rp {
+static thread_local rp_stats t_stats;
+constexpr uint32_t TRAJ_CAP = 4096;
+extern int g_digit_bits_ref(int v, bool set);
+
+static std::vector<rp_clause> option_units(const Plan& pl, const rp_repair_opts& o) {
+  std::vector<rp_clause> u;
+  for (uint32_t s = 0; s < pl.S; s++) {
+    const uint64_t b = 1ull << s;
+    if (!o.grid && (pl.grid_slots & b)) u.push_back(rp_clause{0, b});
+    if (!o.inspect && (pl.pre_slots & b)) u.push_back(rp_clause{b, 0});
+  }
+  std::sort(u.begin(), u.end(), [](const rp_clause& a, const rp_clause& b) {
+    return a.pos != b.pos ? a.pos < b.pos : a.neg < b.neg;
+  });
+  return u;
+}
+
+static void worst_units(const Plan& pl, std::vector<rp_clause>& u) {
+  u.assign(2 * pl.S, rp_clause{0, 0});
+}
+
+}  // namespace rp
+
+using namespace rp;
+
+extern "C" {
+
+const char* rp_status_string(int s) {
+  switch (s) {
+    case RP_OK: return "ok";
+    case RP_UNSAT: return "unsat: the kernel cannot be repaired";
+    case RP_ERR_INVALID: return "invalid descriptor or argument";
+    case RP_ERR_CAPACITY: return "capacity exceeded";
+    case RP_ERR_WORKSPACE: return "workspace too small";
+    case RP_ERR_DEVICE: return "device error";
+    case RP_ERR_ROUNDS: return "round limit reached";
+    case RP_ERR_BUDGET: return "job exceeds the memory budget";
+    default: return "unknown status";
+  }
+}
+
+rp_status rp_validate(const rp_kernel* k) { return (rp_status)validate_kernel(k); }
+
+size_t rp_workspace_bytes(const rp_kernel* k, int op) {
+  if (validate_kernel(k) != RP_OK || op < RP_OP_CHECK || op > RP_OP_REPAIR) return 0;
+  Plan pl;
+  make_plan(k, pl);
+  JobInput ji;
+  ji.plan = &pl;
+  EngineOpts o;
+  o.op = (Op)op;
+  if (op == RP_OP_REPAIR) {
+    worst_units(pl, ji.phi0);
+    o.traj_cap = TRAJ_CAP;
+  }
+  std::vector<JobInput> v{ji};
+  return engine_workspace(v, o);
+}
+
+rp_status rp_check(const rp_kernel* k, uint64_t x, rp_pair* pairs, uint64_t cap,
+                   uint64_t* n_pairs, uint64_t* divergent, uint64_t* n_records, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (validate_kernel(k) != RP_OK || (cap && !pairs)) return RP_ERR_INVALID;
+  Plan pl;
+  make_plan(k, pl);
+  JobInput ji;
+  ji.plan = &pl;
+  ji.x = x;
+  EngineOpts o;
+  o.op = OP_CHECK;
+  o.pair_cap = cap;
+  std::vector<JobInput> v{ji};
+  std::vector<JobResult> res;
+  rp_stats st;
+  int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
+  t_stats = st;
+  if (rc != RP_OK) return (rp_status)rc;
+  if (n_pairs) *n_pairs = res[0].n_pairs;
+  if (res[0].n_pairs > cap) return RP_ERR_CAPACITY;
+  if (res[0].n_pairs) std::memcpy(pairs, res[0].pairs.data(), res[0].n_pairs * sizeof(rp_pair));
+  if (divergent) *divergent = res[0].st.divergent;
+  if (n_records) *n_records = pl.accesses;
+  return RP_OK;
+}
+
+rp_status rp_clauses(const rp_kernel* k, uint64_t x, rp_clause* out, uint64_t cap,
+                     uint64_t* n_out, void* ws, size_t ws_bytes, void* stream) {
+  if (validate_kernel(k) != RP_OK || (cap && !out)) return RP_ERR_INVALID;
+  Plan pl;
+  make_plan(k, pl);
+  JobInput ji;
+  ji.plan = &pl;
+  ji.x = x;
+  EngineOpts o;
+  o.op = OP_CLAUSES;
+  std::vector<JobInput> v{ji};
+  std::vector<JobResult> res;
+  rp_stats st;
+  int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
+  t_stats = st;
+  if (rc != RP_OK) return (rp_status)rc;
+  const uint64_t n = res[0].phi.size();
+  if (n_out) *n_out = n;
+  if (n > cap) return RP_ERR_CAPACITY;
+  if (n) std::memcpy(out, res[0].phi.data(), n * sizeof(rp_clause));
+  return RP_OK;
+}
+
+static bool solve_args_ok(const rp_clause* c, uint64_t n, const uint32_t* w, uint32_t S) {
+  if (S > 64 || (n && !c) || (S && !w) || n > (1u << 20)) return false;
+  for (uint32_t s = 0; s < S; s++)
+    if (w[s] < 1) return false;
+  const uint64_t valid = S >= 64 ? ~0ull : ((1ull << S) - 1);
+  for (uint64_t q = 0; q < n; q++)
+    if ((c[q].pos | c[q].neg) & ~valid) return false;
+  return true;
+}
+
+static void solve_plan(uint32_t S, const uint32_t* w, Plan& pl) {
+  pl.P = 0;
+  pl.S = S;
+  pl.B = pl.T = 1;
+  pl.weights.assign(w, w + S);
+  pl.cnt_pre.assign(1, 0);
+  pl.gcnt_pre.assign(1, 0);
+}
+
+size_t rp_solve_workspace_bytes(uint64_t n_clauses) {
+  Plan pl;
+  std::vector<uint32_t> w(64, 1);
+  solve_plan(64, w.data(), pl);
+  JobInput ji;
+  ji.plan = &pl;
+  ji.phi0.assign(n_clauses, rp_clause{0, 0});
+  EngineOpts o;
+  o.op = OP_SOLVE;
+  std::vector<JobInput> v{ji};
+  return engine_workspace(v, o);
+}
+
+rp_status rp_min_barriers(const rp_clause* clauses, uint64_t n_clauses, const uint32_t* weights,
+                          uint32_t n_slots, uint64_t* assign, uint64_t* weight, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (!solve_args_ok(clauses, n_clauses, weights, n_slots)) return RP_ERR_INVALID;
+  Plan pl;
+  solve_plan(n_slots, weights, pl);
+  JobInput ji;
+  ji.plan = &pl;
+  ji.phi0.assign(clauses, clauses + n_clauses);
+  EngineOpts o;
+  o.op = OP_SOLVE;
+  std::vector<JobInput> v{ji};
+  std::vector<JobResult> res;
+  rp_stats st;
+  int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
+  t_stats = st;
+  if (rc != RP_OK) return (rp_status)rc;
+  if (res[0].st.state == ST_UNSAT) return RP_UNSAT;
+  if (assign) *assign = res[0].st.x;
+  if (weight) *weight = res[0].st.weight;
+  return RP_OK;
+}
+
+rp_status rp_repair(const rp_kernel* k, const rp_repair_opts* opts, rp_repair_out* out,
+                    uint64_t* trajectory, uint32_t traj_cap, void* ws, size_t ws_bytes,
+                    void* stream) {
+  if (validate_kernel(k) != RP_OK || !out || (traj_cap && !trajectory)) return RP_ERR_INVALID;
+  rp_repair_opts op = opts ? *opts : rp_repair_opts{0, 1, 1, 0, 0};
+  if (op.policy > 1) return RP_ERR_INVALID;
+  Plan pl;
+  make_plan(k, pl);
+  JobInput ji;
+  ji.plan = &pl;
+  ji.phi0 = option_units(pl, op);
+  ji.policy = op.policy;
+  ji.max_rounds = op.max_rounds;
+  EngineOpts o;
+  o.op = OP_REPAIR;
+  o.traj_cap = TRAJ_CAP;
+  std::vector<JobInput> v{ji};
+  std::vector<JobResult> res;
+  rp_stats st;
+  int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
+  t_stats = st;
+  if (rc != RP_OK) return (rp_status)rc;
+  const JobState& s = res[0].st;
+  std::memset(out, 0, sizeof(*out));
+  out->rounds = s.rounds;
+  out->n_clauses = s.n_phi;
+  if (s.state == ST_SAFE) {
+    out->status = RP_OK;
+    out->assign = s.x;
+    out->weight = s.weight;
+    out->added = s.x & ~pl.pre_slots;
+    out->removed = pl.pre_slots & ~s.x;
+  } else if (s.state == ST_UNSAT) {
+    out->status = RP_UNSAT;
+  } else if (s.state == ST_ROUNDS) {
+    out->status = RP_ERR_ROUNDS;
+  } else {
+    out->status = RP_ERR_DEVICE;
+  }
+  if (traj_cap) {
+    const size_t nt = std::min<size_t>(traj_cap, res[0].traj.size());
+    std::memcpy(trajectory, res[0].traj.data(), nt * sizeof(uint64_t));
+  }
+  return (rp_status)out->status;
+}
+
+void rp_last_stats(rp_stats* out) {
+  if (out) *out = t_stats;
+}
+
+int rp_set_sort_digit_bits(int bits) {
+  if (bits != 0 && (bits < 8 || bits > 11)) return -1;
+  return g_digit_bits_ref(bits, true);
+}
+
+}  // extern "C"

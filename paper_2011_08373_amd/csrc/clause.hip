@@ -1,0 +1,196 @@
+// GenerateClause of Alg. 1 and the maintenance of the constraint set phi.
+//
+// One workgroup per job, after a Verify scan:
+//   - counts the Verify call (and records the verified assignment);
+//   - SAFE when no point has a racing partner and no enabled slot diverges;
+//   - otherwise learns clauses: a race between points i < j gives the
+//     positive clause of the barrier slots with an occurrence strictly
+//     between i and j (grid-level slots only for a cross-block race); a
+//     divergent slot s gives the negative unit {not b_s} (Section 2.4).
+//     Only the first racing partner j of each point is needed: every later
+//     partner's clause is a superset, hence subsumed;
+//   - phi := reduce(phi + learned): sorted by (pos, neg), duplicates and
+//     subsumed clauses dropped.  A subset precedes its supersets in that
+//     order, so each clause is tested against earlier ones only.
+#include "common.h"
+#include "launch.h"
+
+namespace rp {
+
+constexpr int CL_BLOCK = 1024;
+
+__device__ __forceinline__ bool cl_less(const rp_clause& a, const rp_clause& b) {
+  return a.pos != b.pos ? a.pos < b.pos : a.neg < b.neg;
+}
+
+// Bitonic sort of c[0..n2) (n2 a power of two) by one workgroup.
+__device__ void block_bitonic(rp_clause* c, uint32_t n2) {
+  for (uint32_t k = 2; k <= n2; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < n2; i += CL_BLOCK) {
+        const uint32_t l = i ^ j;
+        if (l > i) {
+          const rp_clause a = c[i], b = c[l];
+          const bool up = (i & k) == 0;
+          if (up ? cl_less(b, a) : cl_less(a, b)) { c[i] = b; c[l] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan1024(uint32_t v, uint32_t* sm, uint32_t* total) {
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  uint32_t inc = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(inc, off);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) sm[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+  for (int q = 0; q < CL_BLOCK / 64; q++) {
+    if (q < w) pre += sm[q];
+    tot += sm[q];
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + inc - v;
+}
+
+// learn: 0 = only decide SAFE (the check call), 1 = learn and reduce.
+__global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict__ jobs, int learn) {
+  __shared__ uint32_t s_n, s_races, s_first;
+  __shared__ uint32_t sm[CL_BLOCK / 64];
+  __shared__ uint32_t keep[4096];   // bitset over up to 131072 clauses
+  const Job& J = jobs[blockIdx.x];
+  JobState* st = J.st;
+  if (st->state != ST_RUN) return;
+  const int tid = threadIdx.x;
+  const uint32_t P = J.P;
+  const uint64_t x = st->x;
+  const uint64_t div = st->divergent;
+  if (tid == 0) { s_n = 0; s_races = 0; s_first = NONE32; }
+  __syncthreads();
+  for (uint32_t row = tid; row < 2 * P; row += CL_BLOCK) {
+    if (J.minj[row] != NONE32) {
+      atomicAdd(&s_races, 1u);
+      atomicMin(&s_first, row);
+    }
+  }
+  __syncthreads();
+  const uint32_t races = s_races;
+  if (tid == 0) {
+    if (J.traj && st->rounds < J.traj_cap) J.traj[st->rounds] = x;
+    st->rounds += 1;
+    st->races = races;
+  }
+  if (races == 0 && div == 0) {
+    if (tid == 0) st->state = ST_SAFE;
+    return;
+  }
+  if (!learn) return;
+  // phi first, then the learned clauses, in scratch
+  const uint32_t n_phi = st->n_phi;
+  rp_clause* sc = J.scratch;
+  for (uint32_t q = tid; q < n_phi; q += CL_BLOCK) sc[q] = J.phi[q];
+  const bool one = J.policy == 1;
+  if (one) {
+    if (tid == 0) {
+      rp_clause c;
+      if (div) {
+        c.pos = 0;
+        c.neg = div & (~div + 1);       // smallest divergent slot
+      } else {
+        const uint32_t row = s_first;   // smallest (level, i)
+        const uint32_t lv = row / P, i = row % P, j = J.minj[row];
+        const uint64_t* bits = lv ? J.bits_grid : J.bits_any;
+        uint64_t pos = 0;
+        for (uint32_t u = i + 1; u < j; u++) pos |= bits[u];
+        c.pos = pos;
+        c.neg = 0;
+      }
+      sc[n_phi] = c;
+      s_n = 1;
+    }
+  } else {
+    for (uint32_t row = tid; row < 2 * P; row += CL_BLOCK) {
+      const uint32_t j = J.minj[row];
+      if (j == NONE32) continue;
+      const uint32_t lv = row / P, i = row % P;
+      const uint64_t* bits = lv ? J.bits_grid : J.bits_any;
+      uint64_t pos = 0;
+      for (uint32_t u = i + 1; u < j; u++) pos |= bits[u];
+      const uint32_t slot = atomicAdd(&s_n, 1u);
+      rp_clause c;
+      c.pos = pos;
+      c.neg = 0;
+      sc[n_phi + slot] = c;
+    }
+    if (tid < 64 && ((div >> tid) & 1)) {
+      const uint32_t slot = atomicAdd(&s_n, 1u);
+      rp_clause c;
+      c.pos = 0;
+      c.neg = 1ull << tid;
+      sc[n_phi + slot] = c;
+    }
+  }
+  __syncthreads();
+  const uint32_t n = n_phi + s_n;
+  uint32_t n2 = 1;
+  while (n2 < n) n2 <<= 1;
+  if (n2 > J.scratch_cap || n > 4096u * 32u) {
+    if (tid == 0) { st->err = ERR_SCRATCH; st->state = ST_ERROR; }
+    return;
+  }
+  for (uint32_t q = n + tid; q < n2; q += CL_BLOCK) {
+    rp_clause pad;
+    pad.pos = ~0ull;
+    pad.neg = ~0ull;
+    sc[q] = pad;
+  }
+  __syncthreads();
+  block_bitonic(sc, n2);
+  // keep = first of its duplicates and not a strict superset of an earlier clause
+  for (uint32_t q = tid; q < (n + 31) / 32; q += CL_BLOCK) keep[q] = 0;
+  __syncthreads();
+  for (uint32_t a = tid; a < n; a += CL_BLOCK) {
+    const rp_clause ca = sc[a];
+    bool k = a == 0 || sc[a - 1].pos != ca.pos || sc[a - 1].neg != ca.neg;
+    for (uint32_t b = 0; k && b < a; b++) {
+      const rp_clause cb = sc[b];
+      if ((cb.pos & ~ca.pos) == 0 && (cb.neg & ~ca.neg) == 0 &&
+          (cb.pos != ca.pos || cb.neg != ca.neg))
+        k = false;
+    }
+    if (k) atomicOr(&keep[a >> 5], 1u << (a & 31));
+  }
+  __syncthreads();
+  // compaction in order: thread t owns clauses [t*per, (t+1)*per)
+  const uint32_t per = (n + CL_BLOCK - 1) / CL_BLOCK;
+  uint32_t mine = 0;
+  for (uint32_t q = 0; q < per; q++) {
+    const uint32_t a = tid * per + q;
+    if (a < n && ((keep[a >> 5] >> (a & 31)) & 1)) mine++;
+  }
+  uint32_t total;
+  uint32_t pos = block_excl_scan1024(mine, sm, &total);
+  if (total > J.phi_cap) {
+    if (tid == 0) { st->err = ERR_PHI_CAP; st->state = ST_ERROR; }
+    return;
+  }
+  for (uint32_t q = 0; q < per; q++) {
+    const uint32_t a = tid * per + q;
+    if (a < n && ((keep[a >> 5] >> (a & 31)) & 1)) J.phi[pos++] = sc[a];
+  }
+  if (tid == 0) st->n_phi = total;
+}
+
+hipError_t launch_clause(const Job* jobs, uint32_t njobs, int learn, hipStream_t s) {
+  if (njobs == 0) return hipSuccess;
+  clause_kernel<<<njobs, CL_BLOCK, 0, s>>>(jobs, learn);
+  return hipGetLastError();
+}
+
+}  // namespace rp

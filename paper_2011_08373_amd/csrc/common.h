@@ -1,0 +1,126 @@
+// Internal device-side data layout of librepair (not part of the public ABI).
+//
+// Access records are packed 64-bit integers.  With field widths tb = bits of
+// (threads-1), bb = bits of (blocks-1), pb = bits of (points-1), nb = bits of
+// (max words-1), ab = bits of (arrays-1):
+//
+//   same-block view  (one record per (point, block, thread) access):
+//       [ array | word | block | point | thread ]
+//   cross-block view (GLOBAL arrays only):
+//       [ array | word | point | block | 0...0  ]
+//
+// The sort key is the top field pair (array, word) at key_shift =
+// tb + bb + pb.  Records are generated in increasing order of their low
+// fields (block-major for the same-block view, point-major for the
+// cross-block view), so a stable LSD radix sort on the key bits leaves the
+// whole log sorted as plain 64-bit integers.  Inside one memory location the
+// records are then ordered by point, which is program order: the interval
+// between two enabled barriers is a contiguous run for every assignment, so
+// the log is sorted once per kernel and rescanned per Verify call.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/librepair.h"
+
+namespace rp {
+
+constexpr uint32_t NONE32 = 0xFFFFFFFFu;
+constexpr int MAX_POINTS = 4096;
+constexpr int MAX_SORT_PASSES = 8;
+
+// flags of DPoint::flags
+constexpr uint8_t PF_WRITE = 1, PF_GLOBAL = 2, PF_POW2 = 4;
+
+struct DPoint {          // 32 B, one per program point
+  int32_t a, b, c;
+  uint32_t words;        // array size (words)
+  uint32_t m, r;         // guard: tid % m == r
+  uint32_t cnt;          // threads of one block executing the point
+  uint16_t array;
+  uint8_t kind;          // RP_ACCESS / RP_BARRIER / RP_NOP
+  uint8_t flags;         // PF_*
+};
+
+struct JobState {        // device-resident per-job state; the host reads it
+  uint64_t x;            // current assignment
+  uint64_t weight;       // weight of x
+  uint64_t divergent;    // enabled divergent slots at the last Verify
+  uint32_t n_phi;        // clauses in phi (reduced)
+  uint32_t state;        // 0 running, 1 safe, 2 unsat, 3 error
+  uint32_t rounds;       // Verify calls made
+  uint32_t races;        // (point, level) rows with a race at the last Verify
+  uint32_t err;          // device-side error code (0 = none)
+  uint32_t max_rounds;   // 0 = unlimited
+  uint64_t traj_pad;
+};
+constexpr uint32_t ST_RUN = 0, ST_SAFE = 1, ST_UNSAT = 2, ST_ERROR = 3, ST_ROUNDS = 4;
+constexpr uint32_t ERR_PHI_CAP = 1, ERR_SORT = 2, ERR_SCRATCH = 3, ERR_RANGE = 4;
+
+struct Job {
+  uint32_t P, S, B, T;
+  uint32_t tbits, bbits, pbits, key_shift;
+  uint32_t nbits, policy;     // word-field width; learning policy
+  const DPoint* pts;          // [P]
+  const uint64_t* bits_any;   // [P] slot bit of a barrier occurrence, else 0
+  const uint64_t* bits_grid;  // [P] slot bit of a GRID barrier occurrence, else 0
+  const uint32_t* weights;    // [S]
+  const uint64_t* cnt_pre;    // [P+1] prefix of executing threads over access points
+  const uint64_t* gcnt_pre;   // [P+1] the same over access points of GLOBAL arrays
+  uint64_t rblk;              // same-block records per block (= cnt_pre[P])
+  uint64_t div_if_enabled;    // slots whose guard splits a block
+  const uint64_t* log[2];     // sorted logs: same-block, cross-block
+  uint64_t nlog[2];
+  uint32_t* ivl;              // [2][P] interval id: any level, grid level
+  uint32_t* minj;             // [2][P] first racing partner per point
+  uint64_t* bitmap;           // [2][P][wpr] racing pairs (check mode) or null
+  uint32_t wpr, pad1;         // 64-bit words per bitmap row
+  rp_clause* phi;             // [phi_cap]
+  rp_clause* scratch;         // [scratch_cap] (power of two)
+  uint32_t phi_cap, scratch_cap;
+  JobState* st;
+  uint64_t* traj;             // [traj_cap] assignment verified per round
+  uint32_t traj_cap, pad2;
+};
+
+// sort segment: one log of one job in the record buffer
+struct SortSeg {
+  uint64_t beg, end;     // record range
+  uint32_t shift;        // key_shift of the job
+  uint32_t tile_beg;     // first global tile of the segment
+};
+
+// generation work item: records [o0, o1) of one log (segment-local indices)
+struct GenItem {
+  uint64_t o0, o1;
+  uint32_t job, view;    // view 0 same-block log, 1 cross-block log
+  uint32_t seg, pad;
+};
+
+// conflict-scan segment: one log of one job
+struct ConfSeg {
+  const uint64_t* log;
+  uint64_t n;
+  uint32_t job, level;
+  uint32_t tile_beg, pad;
+};
+
+__device__ __forceinline__ uint32_t word_of(const DPoint& p, uint32_t t, uint32_t k) {
+  int64_t v = (int64_t)p.a * (int64_t)t + (int64_t)p.b * (int64_t)k + (int64_t)p.c;
+  if (p.flags & PF_POW2) return (uint32_t)((uint64_t)v & (uint64_t)(p.words - 1));
+  int64_t n = (int64_t)p.words;
+  int64_t r = v % n;
+  return (uint32_t)(r < 0 ? r + n : r);
+}
+
+// radix digit of a record for a pass starting at bit `shift` (0 past bit 63)
+__device__ __forceinline__ uint32_t digit_at(uint64_t rec, int shift, uint32_t mask) {
+  return shift < 64 ? (uint32_t)(rec >> shift) & mask : 0u;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  uint32_t lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+}  // namespace rp

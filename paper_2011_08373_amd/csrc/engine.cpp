@@ -1,0 +1,426 @@
+// Execution engine: lays out one or many jobs in a device workspace and runs
+// record generation, the radix sort and the per-round Verify / GenerateClause /
+// Solve kernels of Alg. 1 on a stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "launch.h"
+#include "plan.h"
+
+namespace rp {
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  size_t total = 0, meta = 0;
+  size_t o_jobs = 0, o_states = 0, o_items = 0, o_seg_item_beg = 0, o_ssegs = 0, o_csegs = 0;
+  size_t o_phi0 = 0;
+  std::vector<size_t> o_pts, o_bany, o_bgrid, o_w, o_cpre, o_gpre, o_phi0j;
+  size_t o_recA = 0, o_recB = 0, o_hist = 0, o_dbase = 0, o_status = 0, o_err = 0;
+  std::vector<size_t> o_ivl, o_minj, o_phi, o_scratch, o_traj, o_bitmap, o_pairs, o_ptotal;
+  std::vector<uint32_t> phi_cap, scratch_cap;
+  uint64_t n_rec = 0;
+  uint32_t rb = 8, passes = 0, n_tiles = 0, n_conf_tiles = 0;
+  std::vector<GenItem> items;
+  std::vector<uint32_t> seg_item_beg;
+  std::vector<SortSeg> ssegs;
+  std::vector<uint32_t> seg_job, seg_level;
+  uint64_t status_words = 0;
+};
+
+uint32_t pow2_at_least(uint64_t n) {
+  uint32_t p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout& L) {
+  const size_t N = jobs.size();
+  // records and sort segments (two logs per job)
+  uint32_t key_bits = 0;
+  for (const JobInput& j : jobs) key_bits = std::max(key_bits, j.plan->key_bits);
+  L.rb = (uint32_t)pick_digit_bits(key_bits);
+  L.passes = (uint32_t)sort_passes(key_bits, (int)L.rb);
+  const uint32_t tile = sort_tile_size();
+  uint64_t rec = 0;
+  uint32_t tiles = 0, ctiles = 0;
+  const uint32_t ctile = conf_tile_size();
+  for (size_t j = 0; j < N; j++) {
+    const Plan& p = *jobs[j].plan;
+    for (int v = 0; v < 2; v++) {
+      const uint64_t n = v == 0 ? p.n_intra : p.n_inter;
+      if (n == 0) continue;
+      SortSeg s{};
+      s.beg = rec;
+      s.end = rec + n;
+      s.shift = p.key_shift;
+      s.tile_beg = tiles;
+      L.ssegs.push_back(s);
+      L.seg_job.push_back((uint32_t)j);
+      L.seg_level.push_back((uint32_t)v);
+      rec += n;
+      tiles += (uint32_t)((n + tile - 1) / tile);
+      ctiles += (uint32_t)((n + ctile - 1) / ctile);
+    }
+  }
+  L.n_rec = rec;
+  L.n_tiles = tiles;
+  L.n_conf_tiles = ctiles;
+  // generation items: equal chunks of every log
+  const uint64_t chunk = std::max<uint64_t>(16384, (rec + 16383) / 16384);
+  L.seg_item_beg.push_back(0);
+  for (size_t s = 0; s < L.ssegs.size(); s++) {
+    const uint64_t n = L.ssegs[s].end - L.ssegs[s].beg;
+    for (uint64_t o0 = 0; o0 < n; o0 += chunk) {
+      GenItem it{};
+      it.o0 = o0;
+      it.o1 = std::min(n, o0 + chunk);
+      it.job = L.seg_job[s];
+      it.view = L.seg_level[s];
+      it.seg = (uint32_t)s;
+      L.items.push_back(it);
+    }
+    L.seg_item_beg.push_back((uint32_t)L.items.size());
+  }
+  const uint32_t R = 1u << L.rb;
+  // ---- meta region (uploaded)
+  size_t off = 0;
+  L.o_jobs = off; off = up(off + N * sizeof(Job));
+  L.o_states = off; off = up(off + N * sizeof(JobState));
+  L.o_items = off; off = up(off + L.items.size() * sizeof(GenItem));
+  L.o_seg_item_beg = off; off = up(off + L.seg_item_beg.size() * sizeof(uint32_t));
+  L.o_ssegs = off; off = up(off + L.ssegs.size() * sizeof(SortSeg));
+  L.o_csegs = off; off = up(off + L.ssegs.size() * sizeof(ConfSeg));
+  L.o_pts.resize(N); L.o_bany.resize(N); L.o_bgrid.resize(N); L.o_w.resize(N);
+  L.o_cpre.resize(N); L.o_gpre.resize(N); L.o_phi0j.resize(N);
+  for (size_t j = 0; j < N; j++) {
+    const Plan& p = *jobs[j].plan;
+    L.o_pts[j] = off; off = up(off + p.P * sizeof(DPoint));
+    L.o_bany[j] = off; off = up(off + p.P * sizeof(uint64_t));
+    L.o_bgrid[j] = off; off = up(off + p.P * sizeof(uint64_t));
+    L.o_w[j] = off; off = up(off + p.S * sizeof(uint32_t));
+    L.o_cpre[j] = off; off = up(off + (p.P + 1) * sizeof(uint64_t));
+    L.o_gpre[j] = off; off = up(off + (p.P + 1) * sizeof(uint64_t));
+    L.o_phi0j[j] = off; off = up(off + jobs[j].phi0.size() * sizeof(rp_clause));
+  }
+  L.meta = off;
+  // ---- device-only region
+  L.o_recA = off; off = up(off + L.n_rec * sizeof(uint64_t));
+  L.o_recB = off; off = up(off + (L.passes ? L.n_rec : 0) * sizeof(uint64_t));
+  L.o_hist = off; off = up(off + (size_t)L.items.size() * std::max(1u, L.passes) * R * sizeof(uint32_t));
+  L.o_dbase = off; off = up(off + L.ssegs.size() * std::max(1u, L.passes) * R * sizeof(uint64_t));
+  L.status_words = (uint64_t)L.n_tiles * R + 1;   // + the tile counter
+  L.o_status = off; off = up(off + L.status_words * sizeof(uint64_t));
+  L.o_err = off; off = up(off + 64);
+  L.o_ivl.resize(N); L.o_minj.resize(N); L.o_phi.resize(N); L.o_scratch.resize(N);
+  L.o_traj.resize(N); L.o_bitmap.resize(N); L.o_pairs.resize(N); L.o_ptotal.resize(N);
+  L.phi_cap.resize(N); L.scratch_cap.resize(N);
+  for (size_t j = 0; j < N; j++) {
+    const Plan& p = *jobs[j].plan;
+    // reduced phi holds at most one race clause per (point, level), one
+    // divergence unit per slot and the option units
+    const uint32_t cap = 2 * p.P + 2 * 64 + 64 + (uint32_t)jobs[j].phi0.size();
+    L.phi_cap[j] = cap;
+    L.scratch_cap[j] = pow2_at_least((uint64_t)cap + 2 * p.P + 64);
+    L.o_ivl[j] = off; off = up(off + 2 * p.P * sizeof(uint32_t));
+    L.o_minj[j] = off; off = up(off + 2 * p.P * sizeof(uint32_t));
+    L.o_phi[j] = off; off = up(off + L.phi_cap[j] * sizeof(rp_clause));
+    L.o_scratch[j] = off; off = up(off + L.scratch_cap[j] * sizeof(rp_clause));
+    L.o_traj[j] = off; off = up(off + o.traj_cap * sizeof(uint64_t));
+    if (o.op == OP_CHECK) {
+      const uint64_t wpr = (p.P + 63) / 64;
+      L.o_bitmap[j] = off; off = up(off + 2 * (uint64_t)p.P * wpr * sizeof(uint64_t));
+      L.o_pairs[j] = off; off = up(off + (uint64_t)p.P * (p.P + 1) * sizeof(rp_pair));
+      L.o_ptotal[j] = off; off = up(off + sizeof(uint64_t));
+    }
+  }
+  L.total = off;
+}
+
+struct Timer {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> tag;
+  hipStream_t s;
+  bool ok = true;
+  explicit Timer(hipStream_t st) : s(st) {}
+  void mark(int t) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) { ok = false; return; }
+    if (hipEventRecord(e, s) != hipSuccess) ok = false;
+    ev.push_back(e);
+    tag.push_back(t);
+  }
+  ~Timer() { for (hipEvent_t e : ev) (void)hipEventDestroy(e); }
+};
+
+// phase tags for the stats
+enum { T_START = 0, T_GEN, T_SORTPASS, T_SORT, T_CHECK, T_CLAUSE, T_SOLVE, T_END };
+
+}  // namespace
+
+size_t engine_workspace(const std::vector<JobInput>& jobs, const EngineOpts& o) {
+  Layout L;
+  plan_layout(jobs, o, L);
+  return L.total;
+}
+
+#define HIPCHK(x)                          \
+  do {                                     \
+    if ((x) != hipSuccess) return RP_ERR_DEVICE; \
+  } while (0)
+
+int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws, size_t ws_bytes,
+               hipStream_t s, std::vector<JobResult>& res, rp_stats* stats) {
+  Layout L;
+  plan_layout(jobs, o, L);
+  if (ws_bytes < L.total) return RP_ERR_WORKSPACE;
+  if (!ws && L.total) return RP_ERR_WORKSPACE;
+  const size_t N = jobs.size();
+  uint8_t* d = (uint8_t*)ws;
+  const uint32_t R = 1u << L.rb;
+  // ---- host staging of the meta region
+  std::vector<uint8_t> h(L.meta, 0);
+  Job* hj = (Job*)(h.data() + L.o_jobs);
+  JobState* hs = (JobState*)(h.data() + L.o_states);
+  for (size_t j = 0; j < N; j++) {
+    const Plan& p = *jobs[j].plan;
+    Job& J = hj[j];
+    J.P = p.P; J.S = p.S; J.B = p.B; J.T = p.T;
+    J.tbits = p.tbits; J.bbits = p.bbits; J.pbits = p.pbits; J.key_shift = p.key_shift;
+    J.nbits = p.nbits; J.policy = jobs[j].policy;
+    J.pts = (const DPoint*)(d + L.o_pts[j]);
+    J.bits_any = (const uint64_t*)(d + L.o_bany[j]);
+    J.bits_grid = (const uint64_t*)(d + L.o_bgrid[j]);
+    J.weights = (const uint32_t*)(d + L.o_w[j]);
+    J.cnt_pre = (const uint64_t*)(d + L.o_cpre[j]);
+    J.gcnt_pre = (const uint64_t*)(d + L.o_gpre[j]);
+    J.rblk = p.cnt_pre.empty() ? 0 : p.cnt_pre[p.P];
+    J.div_if_enabled = p.div_if_enabled;
+    J.log[0] = J.log[1] = nullptr;
+    J.nlog[0] = p.n_intra;
+    J.nlog[1] = p.n_inter;
+    J.ivl = (uint32_t*)(d + L.o_ivl[j]);
+    J.minj = (uint32_t*)(d + L.o_minj[j]);
+    J.bitmap = o.op == OP_CHECK ? (uint64_t*)(d + L.o_bitmap[j]) : nullptr;
+    J.wpr = (p.P + 63) / 64;
+    J.phi = (rp_clause*)(d + L.o_phi[j]);
+    J.scratch = (rp_clause*)(d + L.o_scratch[j]);
+    J.phi_cap = L.phi_cap[j];
+    J.scratch_cap = L.scratch_cap[j];
+    J.st = (JobState*)(d + L.o_states) + j;
+    J.traj = o.traj_cap ? (uint64_t*)(d + L.o_traj[j]) : nullptr;
+    J.traj_cap = o.traj_cap;
+    JobState& S = hs[j];
+    std::memset(&S, 0, sizeof(S));
+    S.x = jobs[j].x;
+    S.n_phi = (uint32_t)jobs[j].phi0.size();
+    S.state = ST_RUN;
+    S.max_rounds = jobs[j].max_rounds;
+    std::memcpy(h.data() + L.o_pts[j], p.pts.data(), p.P * sizeof(DPoint));
+    std::memcpy(h.data() + L.o_bany[j], p.bits_any.data(), p.P * sizeof(uint64_t));
+    std::memcpy(h.data() + L.o_bgrid[j], p.bits_grid.data(), p.P * sizeof(uint64_t));
+    std::memcpy(h.data() + L.o_w[j], p.weights.data(), p.S * sizeof(uint32_t));
+    std::memcpy(h.data() + L.o_cpre[j], p.cnt_pre.data(), (p.P + 1) * sizeof(uint64_t));
+    std::memcpy(h.data() + L.o_gpre[j], p.gcnt_pre.data(), (p.P + 1) * sizeof(uint64_t));
+    std::memcpy(h.data() + L.o_phi0j[j], jobs[j].phi0.data(), jobs[j].phi0.size() * sizeof(rp_clause));
+  }
+  std::memcpy(h.data() + L.o_items, L.items.data(), L.items.size() * sizeof(GenItem));
+  std::memcpy(h.data() + L.o_seg_item_beg, L.seg_item_beg.data(), L.seg_item_beg.size() * sizeof(uint32_t));
+  std::memcpy(h.data() + L.o_ssegs, L.ssegs.data(), L.ssegs.size() * sizeof(SortSeg));
+  // sorted logs end in buffer A after an even number of passes, else B
+  uint8_t* sorted = d + ((L.passes % 2 == 0) ? L.o_recA : L.o_recB);
+  ConfSeg* hc = (ConfSeg*)(h.data() + L.o_csegs);
+  for (size_t q = 0; q < L.ssegs.size(); q++) {
+    ConfSeg c{};
+    c.log = (const uint64_t*)sorted + L.ssegs[q].beg;
+    c.n = L.ssegs[q].end - L.ssegs[q].beg;
+    c.job = L.seg_job[q];
+    c.level = L.seg_level[q];
+    c.tile_beg = 0;
+    hc[q] = c;
+    hj[c.job].log[c.level] = c.log;
+  }
+  {
+    uint32_t t = 0;
+    const uint32_t ct = conf_tile_size();
+    for (size_t q = 0; q < L.ssegs.size(); q++) {
+      hc[q].tile_beg = t;
+      t += (uint32_t)((hc[q].n + ct - 1) / ct);
+    }
+  }
+  Timer tm(s);
+  tm.mark(T_START);
+  HIPCHK(hipMemcpyAsync(d, h.data(), L.meta, hipMemcpyHostToDevice, s));
+  for (size_t j = 0; j < N; j++)
+    if (!jobs[j].phi0.empty())
+      HIPCHK(hipMemcpyAsync(d + L.o_phi[j], d + L.o_phi0j[j],
+                            jobs[j].phi0.size() * sizeof(rp_clause), hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_fill_u64((uint64_t*)(d + L.o_err), 8, 0, s));
+  const Job* djobs = (const Job*)(d + L.o_jobs);
+  uint32_t* derr = (uint32_t*)(d + L.o_err);
+  // ---- records and sort
+  const int passes = (int)L.passes;
+  HIPCHK(launch_gen((int)L.rb, (const GenItem*)(d + L.o_items), (uint32_t)L.items.size(), djobs,
+                    (const SortSeg*)(d + L.o_ssegs), (uint64_t*)(d + L.o_recA),
+                    (uint32_t*)(d + L.o_hist), passes, s));
+  tm.mark(T_GEN);
+  if (passes > 0) {
+    HIPCHK(launch_hist_scan((int)L.rb, (const uint32_t*)(d + L.o_hist),
+                            (const uint32_t*)(d + L.o_seg_item_beg), (const SortSeg*)(d + L.o_ssegs),
+                            (uint32_t)L.ssegs.size(), passes, (uint64_t*)(d + L.o_dbase), s));
+    uint64_t* status = (uint64_t*)(d + L.o_status);
+    uint32_t* counter = (uint32_t*)(status + (uint64_t)L.n_tiles * R);
+    for (int p = 0; p < passes; p++) {
+      const uint64_t* in = (const uint64_t*)(d + ((p % 2 == 0) ? L.o_recA : L.o_recB));
+      uint64_t* out = (uint64_t*)(d + ((p % 2 == 0) ? L.o_recB : L.o_recA));
+      HIPCHK(launch_fill_u64(status, L.status_words, 0, s));
+      tm.mark(T_SORTPASS);
+      HIPCHK(launch_sort_pass((int)L.rb, in, out, (const SortSeg*)(d + L.o_ssegs),
+                              (int)L.ssegs.size(), L.n_tiles, p, passes,
+                              (const uint64_t*)(d + L.o_dbase), status, counter, derr, s));
+      tm.mark(T_SORT);
+    }
+  }
+  tm.mark(T_SORT);
+  // ---- per-round kernels
+  const ConfSeg* dcs = (const ConfSeg*)(d + L.o_csegs);
+  const int nseg = (int)L.ssegs.size();
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const uint32_t conf_grid = (uint32_t)ncu * 8;
+  std::vector<JobState> hst(N);
+  uint64_t scanned = 0;
+  uint32_t rounds_run = 0, conf_launches = 0;
+  if (o.op == OP_CHECK) {
+    HIPCHK(launch_ivl(djobs, (uint32_t)N, 1, s));
+    HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, 1, s));
+    conf_launches++;
+    scanned += L.n_rec;
+    tm.mark(T_CHECK);
+    for (size_t j = 0; j < N; j++)
+      HIPCHK(launch_pairs(djobs + j, (rp_pair*)(d + L.o_pairs[j]), (uint64_t*)(d + L.o_ptotal[j]), s));
+    tm.mark(T_CLAUSE);
+  } else if (o.op == OP_SOLVE) {
+    HIPCHK(launch_solve(djobs, (uint32_t)N, s));
+    tm.mark(T_SOLVE);
+  } else if (o.op == OP_CLAUSES) {
+    HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
+    HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, 0, s));
+    conf_launches++;
+    scanned += L.n_rec;
+    tm.mark(T_CHECK);
+    HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));
+    tm.mark(T_CLAUSE);
+  } else {
+    HIPCHK(launch_solve(djobs, (uint32_t)N, s));
+    tm.mark(T_SOLVE);
+    for (;;) {
+      HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
+      HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, 0, s));
+      conf_launches++;
+      tm.mark(T_CHECK);
+      HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));
+      tm.mark(T_CLAUSE);
+      HIPCHK(launch_solve(djobs, (uint32_t)N, s));
+      tm.mark(T_SOLVE);
+      HIPCHK(hipMemcpyAsync(hst.data(), d + L.o_states, N * sizeof(JobState),
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      rounds_run++;
+      bool any = false;
+      for (size_t j = 0; j < N; j++) {
+        if (hst[j].state == ST_RUN) any = true;
+      }
+      // records scanned this round: logs of jobs that were verified
+      for (size_t q = 0; q < L.ssegs.size(); q++) {
+        const JobState& st = hst[L.seg_job[q]];
+        if (st.rounds >= rounds_run) scanned += L.ssegs[q].end - L.ssegs[q].beg;
+      }
+      if (!any) break;
+      if (rounds_run > 100000) return RP_ERR_DEVICE;
+    }
+  }
+  tm.mark(T_END);
+  HIPCHK(hipMemcpyAsync(hst.data(), d + L.o_states, N * sizeof(JobState), hipMemcpyDeviceToHost, s));
+  uint32_t herr[16];
+  HIPCHK(hipMemcpyAsync(herr, derr, sizeof(herr), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (herr[0]) return RP_ERR_DEVICE;
+  res.assign(N, JobResult{});
+  for (size_t j = 0; j < N; j++) {
+    res[j].st = hst[j];
+    if (hst[j].state == ST_ERROR) {
+      return hst[j].err == ERR_PHI_CAP || hst[j].err == ERR_SCRATCH ? RP_ERR_CAPACITY
+                                                                   : RP_ERR_DEVICE;
+    }
+    if (o.op == OP_CLAUSES) {
+      res[j].phi.resize(hst[j].n_phi);
+      if (hst[j].n_phi)
+        HIPCHK(hipMemcpyAsync(res[j].phi.data(), d + L.o_phi[j], hst[j].n_phi * sizeof(rp_clause),
+                              hipMemcpyDeviceToHost, s));
+    }
+    if (o.op == OP_CHECK) {
+      uint64_t tot = 0;
+      HIPCHK(hipMemcpyAsync(&tot, d + L.o_ptotal[j], sizeof(tot), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      res[j].n_pairs = tot;
+      if (o.want_pairs && tot <= o.pair_cap && tot) {
+        res[j].pairs.resize(tot);
+        HIPCHK(hipMemcpyAsync(res[j].pairs.data(), d + L.o_pairs[j], tot * sizeof(rp_pair),
+                              hipMemcpyDeviceToHost, s));
+      }
+    }
+    if (o.traj_cap) {
+      const uint32_t nt = std::min(hst[j].rounds, o.traj_cap);
+      res[j].traj.resize(nt);
+      if (nt)
+        HIPCHK(hipMemcpyAsync(res[j].traj.data(), d + L.o_traj[j], nt * sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, s));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    for (size_t q = 1; q < tm.ev.size(); q++) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, tm.ev[q - 1], tm.ev[q]) != hipSuccess) continue;
+      switch (tm.tag[q]) {
+        case T_GEN: stats->ms_gen += ms; break;
+        case T_SORTPASS: stats->ms_sort += ms; break;
+        case T_SORT:
+          stats->ms_sort += ms;
+          if (tm.tag[q - 1] == T_SORTPASS) {
+            stats->ms_sort_kernels += ms;
+            stats->ms_sort_pass_max = std::max(stats->ms_sort_pass_max, (double)ms);
+            stats->sort_launches++;
+          }
+          break;
+        case T_CHECK: stats->ms_check += ms; break;
+        case T_CLAUSE: stats->ms_clause += ms; break;
+        case T_SOLVE: stats->ms_solve += ms; break;
+        default: break;
+      }
+    }
+    float tot = 0;
+    if (tm.ev.size() >= 2 && hipEventElapsedTime(&tot, tm.ev.front(), tm.ev.back()) == hipSuccess)
+      stats->ms_total = tot;
+    stats->records = L.n_rec;
+    for (const JobInput& j : jobs) stats->accesses += j.plan->accesses;
+    stats->records_scanned = scanned;
+    stats->sort_passes = L.passes;
+    stats->rounds = rounds_run;
+    stats->conf_launches = conf_launches;
+  }
+  return RP_OK;
+}
+
+}  // namespace rp

@@ -1,0 +1,144 @@
+// librepair host side: descriptor validation and the per-kernel plan (field
+// widths of the packed records, executing-thread counts, barrier tables).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "launch.h"
+#include "plan.h"
+
+namespace rp {
+
+static int g_digit_bits = 0;          // 0 = automatic
+
+int g_digit_bits_ref(int v, bool set) {
+  const int old = g_digit_bits;
+  if (set) g_digit_bits = v;
+  return old;
+}
+
+static uint32_t bits_for(uint64_t maxval) {   // bits to hold 0..maxval
+  return maxval == 0 ? 0u : (uint32_t)(64 - __builtin_clzll(maxval));
+}
+
+int validate_kernel(const rp_kernel* k) {
+  if (!k) return RP_ERR_INVALID;
+  if (k->blocks < 1 || k->threads < 1) return RP_ERR_INVALID;
+  if (k->n_slots > 64 || k->n_points > (uint32_t)MAX_POINTS) return RP_ERR_INVALID;
+  if ((k->n_arrays && !k->arrays) || (k->n_guards && !k->guards) ||
+      (k->n_points && !k->points) || (k->n_slots && !k->slots))
+    return RP_ERR_INVALID;
+  uint64_t maxw = 1;
+  for (uint32_t a = 0; a < k->n_arrays; a++) {
+    if (k->arrays[a].words < 1 || k->arrays[a].space > 1) return RP_ERR_INVALID;
+    maxw = std::max<uint64_t>(maxw, k->arrays[a].words);
+  }
+  for (uint32_t g = 0; g < k->n_guards; g++)
+    if (k->guards[g].m < 1 || k->guards[g].r >= k->guards[g].m) return RP_ERR_INVALID;
+  for (uint32_t s = 0; s < k->n_slots; s++)
+    if (k->slots[s].level > 1 || k->slots[s].preexisting > 1 || k->slots[s].weight < 1)
+      return RP_ERR_INVALID;
+  int32_t slot_guard[64];
+  for (int s = 0; s < 64; s++) slot_guard[s] = -1;
+  uint32_t next = 0;
+  for (uint32_t i = 0; i < k->n_points; i++) {
+    const rp_point& p = k->points[i];
+    if (p.kind > RP_NOP) return RP_ERR_INVALID;
+    if (p.kind == RP_ACCESS) {
+      if (p.array >= k->n_arrays || p.guard >= k->n_guards || p.is_write > 1)
+        return RP_ERR_INVALID;
+    } else if (p.kind == RP_BARRIER) {
+      if (p.slot >= k->n_slots || p.guard >= k->n_guards) return RP_ERR_INVALID;
+      if (slot_guard[p.slot] < 0) {
+        if (p.slot != next) return RP_ERR_INVALID;   // numbered by first occurrence
+        next++;
+        slot_guard[p.slot] = p.guard;
+      } else if (slot_guard[p.slot] != (int32_t)p.guard) {
+        return RP_ERR_INVALID;                         // one guard per slot
+      }
+    }
+  }
+  if (next != k->n_slots) return RP_ERR_INVALID;     // every slot occurs
+  const uint32_t total = bits_for(k->n_arrays ? k->n_arrays - 1 : 0) + bits_for(maxw - 1) +
+                         bits_for(k->blocks - 1) + bits_for(k->n_points ? k->n_points - 1 : 0) +
+                         bits_for(k->threads - 1);
+  if (total > 64) return RP_ERR_INVALID;
+  return RP_OK;
+}
+
+void make_plan(const rp_kernel* k, Plan& pl) {
+  pl.P = k->n_points;
+  pl.S = k->n_slots;
+  pl.B = k->blocks;
+  pl.T = k->threads;
+  uint64_t maxw = 1;
+  for (uint32_t a = 0; a < k->n_arrays; a++) maxw = std::max<uint64_t>(maxw, k->arrays[a].words);
+  pl.abits = bits_for(k->n_arrays ? k->n_arrays - 1 : 0);
+  pl.nbits = bits_for(maxw - 1);
+  pl.bbits = bits_for(pl.B - 1);
+  pl.pbits = bits_for(pl.P ? pl.P - 1 : 0);
+  pl.tbits = bits_for(pl.T - 1);
+  pl.key_shift = pl.tbits + pl.bbits + pl.pbits;
+  pl.key_bits = pl.abits + pl.nbits;
+  pl.pts.assign(pl.P, DPoint{});
+  pl.bits_any.assign(pl.P, 0);
+  pl.bits_grid.assign(pl.P, 0);
+  pl.cnt_pre.assign(pl.P + 1, 0);
+  pl.gcnt_pre.assign(pl.P + 1, 0);
+  pl.div_if_enabled = 0;
+  pl.accesses = 0;
+  for (uint32_t i = 0; i < pl.P; i++) {
+    const rp_point& p = k->points[i];
+    DPoint& d = pl.pts[i];
+    d.kind = p.kind;
+    d.flags = 0;
+    d.cnt = 0;
+    if (p.kind != RP_NOP) {
+      const rp_guard& g = k->guards[p.guard];
+      d.m = g.m;
+      d.r = g.r;
+      // threads t < T with t % m == r
+      d.cnt = g.r < pl.T ? (pl.T - 1 - g.r) / g.m + 1 : 0;
+    }
+    if (p.kind == RP_ACCESS) {
+      const rp_array& a = k->arrays[p.array];
+      d.a = p.a; d.b = p.b; d.c = p.c;
+      d.words = a.words;
+      d.array = p.array;
+      if (p.is_write) d.flags |= PF_WRITE;
+      if (a.space == RP_GLOBAL) d.flags |= PF_GLOBAL;
+      if ((a.words & (a.words - 1)) == 0) d.flags |= PF_POW2;
+      pl.accesses += (uint64_t)d.cnt * pl.B;
+    }
+    if (p.kind == RP_BARRIER) {
+      pl.bits_any[i] = 1ull << p.slot;
+      if (k->slots[p.slot].level == RP_GRID) pl.bits_grid[i] = 1ull << p.slot;
+      if (d.cnt > 0 && d.cnt < pl.T) pl.div_if_enabled |= 1ull << p.slot;
+    }
+    const uint64_t ca = p.kind == RP_ACCESS ? d.cnt : 0;
+    pl.cnt_pre[i + 1] = pl.cnt_pre[i] + ca;
+    pl.gcnt_pre[i + 1] = pl.gcnt_pre[i] + ((p.kind == RP_ACCESS && (d.flags & PF_GLOBAL)) ? ca : 0);
+  }
+  pl.weights.assign(pl.S, 0);
+  pl.grid_slots = pl.pre_slots = 0;
+  for (uint32_t s = 0; s < pl.S; s++) {
+    pl.weights[s] = k->slots[s].weight;
+    if (k->slots[s].level == RP_GRID) pl.grid_slots |= 1ull << s;
+    if (k->slots[s].preexisting) pl.pre_slots |= 1ull << s;
+  }
+  pl.n_intra = pl.cnt_pre[pl.P] * pl.B;
+  pl.n_inter = pl.gcnt_pre[pl.P] * pl.B;
+}
+
+int pick_digit_bits(uint32_t key_bits) {
+  if (g_digit_bits) return g_digit_bits;
+  (void)key_bits;
+  return 8;
+}
+
+int sort_passes(uint32_t key_bits, int rb) { return (int)((key_bits + rb - 1) / rb); }
+
+}  // namespace rp

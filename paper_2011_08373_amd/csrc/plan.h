@@ -1,0 +1,57 @@
+// Host-side plan of a kernel model and the multi-job execution engine.
+#pragma once
+#include <vector>
+
+#include "common.h"
+
+namespace rp {
+
+struct Plan {
+  uint32_t P = 0, S = 0, B = 0, T = 0;
+  uint32_t tbits = 0, bbits = 0, pbits = 0, nbits = 0, abits = 0, key_shift = 0, key_bits = 0;
+  std::vector<DPoint> pts;
+  std::vector<uint64_t> bits_any, bits_grid;
+  std::vector<uint32_t> weights;
+  std::vector<uint64_t> cnt_pre;    // prefix of executing threads over access points
+  std::vector<uint64_t> gcnt_pre;   // the same over access points of GLOBAL arrays
+  uint64_t div_if_enabled = 0, grid_slots = 0, pre_slots = 0;
+  uint64_t n_intra = 0, n_inter = 0, accesses = 0;
+};
+
+int validate_kernel(const rp_kernel* k);
+void make_plan(const rp_kernel* k, Plan& pl);
+int pick_digit_bits(uint32_t key_bits);
+int sort_passes(uint32_t key_bits, int rb);
+
+enum Op { OP_CHECK = 0, OP_CLAUSES = 1, OP_REPAIR = 2, OP_SOLVE = 3 };
+
+struct JobInput {
+  const Plan* plan;
+  uint64_t x;                       // assignment (check / clauses)
+  std::vector<rp_clause> phi0;      // initial constraint set (repair: option units)
+  uint32_t policy = 0, max_rounds = 0;
+};
+
+struct JobResult {
+  JobState st;
+  std::vector<rp_clause> phi;       // clauses mode: reduced learned clauses
+  std::vector<rp_pair> pairs;       // check mode
+  uint64_t n_pairs = 0;
+  std::vector<uint64_t> traj;
+};
+
+struct EngineOpts {
+  Op op = OP_REPAIR;
+  uint64_t pair_cap = 0;            // check: caller's capacity
+  uint32_t traj_cap = 0;
+  bool want_pairs = true;
+};
+
+// Bytes of workspace the engine needs for these jobs.
+size_t engine_workspace(const std::vector<JobInput>& jobs, const EngineOpts& o);
+
+// Runs the op over all jobs; returns RP_OK or an error status.
+int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws, size_t ws_bytes,
+               hipStream_t s, std::vector<JobResult>& res, rp_stats* stats);
+
+}  // namespace rp

@@ -1,0 +1,229 @@
+"""ctypes binding of librepair.so (the C ABI declared in include/librepair.h).
+
+Argument marshalling only: every step of the repair path runs in the HIP
+library.  PyTorch provides the device workspace (``torch.empty`` on the
+current CUDA/HIP device) and the stream handle.  Importing this module fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "librepair.so")
+
+OK, UNSAT = 0, 1
+ERR_INVALID, ERR_CAPACITY, ERR_WORKSPACE, ERR_DEVICE, ERR_ROUNDS, ERR_BUDGET = -1, -2, -3, -4, -5, -6
+OP_CHECK, OP_CLAUSES, OP_REPAIR = 0, 1, 2
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("librepair.so is not built (run paper_2011_08373_amd/build.py): %s"
+                      % LIB_PATH)
+
+
+class RpKernel(C.Structure):
+    _fields_ = [("blocks", C.c_uint32), ("threads", C.c_uint32), ("n_arrays", C.c_uint32),
+                ("n_guards", C.c_uint32), ("n_points", C.c_uint32), ("n_slots", C.c_uint32),
+                ("arrays", C.c_void_p), ("guards", C.c_void_p), ("points", C.c_void_p),
+                ("slots", C.c_void_p)]
+
+
+class RpClause(C.Structure):
+    _fields_ = [("pos", C.c_uint64), ("neg", C.c_uint64)]
+
+
+class RpOpts(C.Structure):
+    _fields_ = [("policy", C.c_uint8), ("grid", C.c_uint8), ("inspect", C.c_uint8),
+                ("pad", C.c_uint8), ("max_rounds", C.c_uint32)]
+
+
+class RpOut(C.Structure):
+    _fields_ = [("status", C.c_int32), ("rounds", C.c_uint32), ("n_clauses", C.c_uint32),
+                ("pad", C.c_uint32), ("assign", C.c_uint64), ("weight", C.c_uint64),
+                ("added", C.c_uint64), ("removed", C.c_uint64)]
+
+
+class RpStats(C.Structure):
+    _fields_ = [("ms_gen", C.c_double), ("ms_sort", C.c_double), ("ms_check", C.c_double),
+                ("ms_clause", C.c_double), ("ms_solve", C.c_double), ("ms_total", C.c_double),
+                ("ms_sort_pass_max", C.c_double), ("ms_sort_kernels", C.c_double),
+                ("records", C.c_uint64),
+                ("accesses", C.c_uint64), ("records_scanned", C.c_uint64),
+                ("sort_passes", C.c_uint32), ("sort_launches", C.c_uint32),
+                ("rounds", C.c_uint32), ("conf_launches", C.c_uint32)]
+
+
+PAIR_DT = np.dtype([("i", "<u2"), ("j", "<u2"), ("level", "u1"), ("pad", "u1")])
+assert PAIR_DT.itemsize == 6
+
+_L = C.CDLL(LIB_PATH)
+_K = C.POINTER(RpKernel)
+_u64p = C.POINTER(C.c_uint64)
+_L.rp_status_string.restype = C.c_char_p
+_L.rp_validate.argtypes = [_K]
+_L.rp_workspace_bytes.argtypes = [_K, C.c_int]
+_L.rp_workspace_bytes.restype = C.c_size_t
+_L.rp_check.argtypes = [_K, C.c_uint64, C.c_void_p, C.c_uint64, _u64p, _u64p, _u64p,
+                        C.c_void_p, C.c_size_t, C.c_void_p]
+_L.rp_clauses.argtypes = [_K, C.c_uint64, C.c_void_p, C.c_uint64, _u64p, C.c_void_p,
+                          C.c_size_t, C.c_void_p]
+_L.rp_solve_workspace_bytes.argtypes = [C.c_uint64]
+_L.rp_solve_workspace_bytes.restype = C.c_size_t
+_L.rp_min_barriers.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32, _u64p, _u64p,
+                               C.c_void_p, C.c_size_t, C.c_void_p]
+_L.rp_repair.argtypes = [_K, C.POINTER(RpOpts), C.POINTER(RpOut), C.c_void_p, C.c_uint32,
+                         C.c_void_p, C.c_size_t, C.c_void_p]
+_L.rp_last_stats.argtypes = [C.POINTER(RpStats)]
+_L.rp_last_stats.restype = None
+_L.rp_set_sort_digit_bits.argtypes = [C.c_int]
+
+
+def lib():
+    return _L
+
+
+def status_string(st: int) -> str:
+    return _L.rp_status_string(int(st)).decode()
+
+
+class KernelArg:
+    """C view of a kernel model; keeps the numpy buffers alive."""
+
+    def __init__(self, km):
+        from . import synth
+        self.arrays = np.ascontiguousarray(km.arrays, dtype=synth.ARRAY_DT)
+        self.guards = np.ascontiguousarray(km.guards, dtype=synth.GUARD_DT)
+        self.points = np.ascontiguousarray(km.points, dtype=synth.POINT_DT)
+        self.slots = np.ascontiguousarray(km.slots, dtype=synth.SLOT_DT)
+
+        def ptr(a):
+            return a.ctypes.data if a.size else None
+
+        self.k = RpKernel(int(km.blocks), int(km.threads), len(self.arrays), len(self.guards),
+                          len(self.points), len(self.slots), ptr(self.arrays), ptr(self.guards),
+                          ptr(self.points), ptr(self.slots))
+
+    @property
+    def ref(self):
+        return C.byref(self.k)
+
+
+class Workspace:
+    """A reusable device workspace (a torch uint8 tensor)."""
+
+    def __init__(self):
+        self.t = None
+
+    def get(self, nbytes: int):
+        import torch
+        if self.t is None or self.t.numel() < nbytes:
+            self.t = None
+            torch.cuda.empty_cache()
+            self.t = torch.empty(max(1, int(nbytes)), dtype=torch.uint8, device="cuda")
+        return self.t.data_ptr(), self.t.numel()
+
+
+_ws = Workspace()
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def validate(km) -> int:
+    return _L.rp_validate(KernelArg(km).ref)
+
+
+def workspace_bytes(km, op: int) -> int:
+    return int(_L.rp_workspace_bytes(KernelArg(km).ref, int(op)))
+
+
+def check(km, x: int = 0, cap: int | None = None, ws=None, stream=None):
+    """Verify under x.  Returns (status, pairs, divergent, n_records, n_pairs)
+    with pairs a list of (level, i, j) in ascending order (empty unless OK)."""
+    ka = KernelArg(km)
+    need = int(_L.rp_workspace_bytes(ka.ref, OP_CHECK))
+    if need == 0:
+        return ERR_INVALID, [], 0, 0, 0
+    ptr, size = (ws or _ws).get(need)
+    P = int(km.n_points)
+    cap = P * (P + 1) if cap is None else int(cap)
+    buf = np.zeros(max(1, cap), PAIR_DT)
+    n = C.c_uint64(0)
+    div = C.c_uint64(0)
+    nrec = C.c_uint64(0)
+    st = _L.rp_check(ka.ref, C.c_uint64(int(x)), buf.ctypes.data if cap else None, cap,
+                     C.byref(n), C.byref(div), C.byref(nrec), C.c_void_p(ptr), size,
+                     _stream(stream))
+    if st != OK:
+        return st, [], div.value, nrec.value, n.value
+    b = buf[:n.value]
+    pairs = list(zip(b["level"].tolist(), b["i"].tolist(), b["j"].tolist()))
+    return st, pairs, div.value, nrec.value, n.value
+
+
+def clauses(km, x: int = 0, cap: int | None = None, ws=None, stream=None):
+    """(status, [(pos, neg), ...]) reduced and sorted."""
+    ka = KernelArg(km)
+    need = int(_L.rp_workspace_bytes(ka.ref, OP_CLAUSES))
+    if need == 0:
+        return ERR_INVALID, []
+    ptr, size = (ws or _ws).get(need)
+    cap = 4 * int(km.n_points) + 256 if cap is None else int(cap)
+    buf = (RpClause * max(1, cap))()
+    n = C.c_uint64(0)
+    st = _L.rp_clauses(ka.ref, C.c_uint64(int(x)), buf if cap else None, cap, C.byref(n),
+                       C.c_void_p(ptr), size, _stream(stream))
+    if st != OK:
+        return st, []
+    return st, [(buf[q].pos, buf[q].neg) for q in range(n.value)]
+
+
+def min_barriers(cl, weights, n_slots: int, ws=None, stream=None):
+    """(status, assign, weight)."""
+    n = len(cl)
+    buf = (RpClause * max(1, n))()
+    for q, (p, g) in enumerate(cl):
+        buf[q].pos, buf[q].neg = int(p), int(g)
+    w = (C.c_uint32 * max(1, n_slots))(*[int(v) for v in list(weights)[:n_slots]])
+    need = int(_L.rp_solve_workspace_bytes(n))
+    ptr, size = (ws or _ws).get(need)
+    a = C.c_uint64(0)
+    wt = C.c_uint64(0)
+    st = _L.rp_min_barriers(buf, n, w, int(n_slots), C.byref(a), C.byref(wt), C.c_void_p(ptr),
+                            size, _stream(stream))
+    return st, a.value, wt.value
+
+
+def repair(km, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int = 0,
+           ws=None, stream=None, traj_cap: int = 4096):
+    """Alg. 1 on the GPU; dict like the oracle's repair()."""
+    ka = KernelArg(km)
+    need = int(_L.rp_workspace_bytes(ka.ref, OP_REPAIR))
+    if need == 0:
+        return dict(status=ERR_INVALID, ret=ERR_INVALID)
+    ptr, size = (ws or _ws).get(need)
+    o = RpOpts(policy, grid, inspect, 0, max_rounds)
+    out = RpOut()
+    traj = (C.c_uint64 * max(1, traj_cap))()
+    st = _L.rp_repair(ka.ref, C.byref(o), C.byref(out), traj, traj_cap, C.c_void_p(ptr), size,
+                      _stream(stream))
+    r = dict(status=out.status, assign=out.assign, weight=out.weight, added=out.added,
+             removed=out.removed, rounds=out.rounds, n_clauses=out.n_clauses, ret=st)
+    r["trajectory"] = [traj[q] for q in range(min(out.rounds, traj_cap))]
+    return r
+
+
+def last_stats() -> dict:
+    s = RpStats()
+    _L.rp_last_stats(C.byref(s))
+    return {f: getattr(s, f) for f, _ in RpStats._fields_}
+
+
+def set_sort_digit_bits(bits: int) -> int:
+    return _L.rp_set_sort_digit_bits(int(bits))

@@ -1,0 +1,246 @@
+"""HIP path (through the C ABI) against the CPU oracle, element by element.
+
+The whole path is integer: every comparison is exact.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2011_08373_amd import synth
+import bruteforce as BF
+from golden_util import GOLDEN, kernel_from_json, listing_fixtures
+
+pytestmark = pytest.mark.gpu
+
+FIXTURES = listing_fixtures()
+REPAIR_KEYS = ("status", "assign", "weight", "added", "removed", "rounds", "n_clauses",
+               "trajectory")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2011_08373_amd import librepair
+    return librepair
+
+
+def same_repair(g, o):
+    return {k: g[k] for k in REPAIR_KEYS} == {k: o[k] for k in REPAIR_KEYS}
+
+
+@pytest.mark.parametrize("name,fx", FIXTURES, ids=[n for n, _ in FIXTURES])
+def test_listing(L, name, fx):
+    km = kernel_from_json(fx)
+    for x, exp in fx["expect"].get("check", {}).items():
+        g = L.check(km, int(x))
+        o = O.check(km, int(x))
+        assert g[:4] == o, (name, x)
+        assert [list(p) for p in g[1]] == exp["pairs"]
+        assert g[2] == exp["divergent"]
+    for x, exp in fx["expect"].get("clauses", {}).items():
+        g = L.clauses(km, int(x))
+        assert g == O.clauses(km, int(x)), (name, x)
+        assert [list(c) for c in g[1]] == exp
+    for policy in (0, 1):
+        g = L.repair(km, policy=policy)
+        o = O.repair(km, policy=policy)
+        assert same_repair(g, o), (name, policy, g, o)
+
+
+def test_plain_small_1000_seeds(L):
+    # the small plain configuration: 1 block x 64 threads, 16 points
+    mism = []
+    for seed in range(1000):
+        km = synth.generate("plain-small", seed=seed)
+        g = L.repair(km)
+        o = O.repair(km)
+        if not same_repair(g, o):
+            mism.append((seed, g, o))
+        if seed % 25 == 0:
+            rng = np.random.default_rng(seed)
+            for x in [0] + rng.integers(0, 16, size=2).tolist():
+                assert L.check(km, x)[:4] == O.check(km, x), (seed, x)
+                assert L.clauses(km, x) == O.clauses(km, x), (seed, x)
+    assert not mism, mism[:3]
+
+
+def test_plain_small_planted(L):
+    for seed in range(200):
+        km = synth.generate("plain-small", mode="planted", seed=seed)
+        for policy in (0, 1):
+            g = L.repair(km, policy=policy)
+            o = O.repair(km, policy=policy)
+            assert same_repair(g, o), (seed, policy)
+
+
+def test_tiny_random_kernels(L):
+    for seed in range(400):
+        rng = np.random.default_rng(40_000 + seed)
+        km = BF.tiny_kernel(rng)
+        for policy in (0, 1):
+            g = L.repair(km, policy=policy)
+            o = O.repair(km, policy=policy)
+            assert same_repair(g, o), (seed, policy, g, o)
+        for x in rng.integers(0, 1 << max(1, km.n_slots), size=3).tolist():
+            assert L.check(km, x)[:4] == O.check(km, x), (seed, x)
+            assert L.clauses(km, x) == O.clauses(km, x), (seed, x)
+
+
+def test_tiny_options(L):
+    for seed in range(150):
+        rng = np.random.default_rng(50_000 + seed)
+        km = BF.tiny_kernel(rng)
+        for grid, inspect in ((0, 1), (1, 0), (0, 0)):
+            g = L.repair(km, grid=grid, inspect=inspect)
+            o = O.repair(km, grid=grid, inspect=inspect)
+            assert same_repair(g, o), (seed, grid, inspect)
+        g = L.repair(km, max_rounds=1)
+        o = O.repair(km, max_rounds=1)
+        assert same_repair(g, o), seed
+
+
+def _clause_sets(rng, S, n):
+    out = []
+    for _ in range(n):
+        u = rng.random()
+        p = int(rng.integers(0, 1 << S))
+        q = int(rng.integers(0, 1 << S))
+        if u < 0.6:
+            out.append((p | (1 << int(rng.integers(0, S))), 0))
+        elif u < 0.85:
+            out.append((0, 1 << int(rng.integers(0, S))))
+        else:
+            out.append((p & ~q, q & ~p))
+    return out
+
+
+def test_solver_random(L):
+    rng = np.random.default_rng(5)
+    for _ in range(300):
+        S = int(rng.integers(1, 16))
+        cl = _clause_sets(rng, S, int(rng.integers(0, 20)))
+        w = rng.integers(1, 9, size=S).tolist()
+        g = L.min_barriers(cl, w, S)
+        o = O.min_barriers(cl, w, S)
+        if o[0] == 1:
+            assert g[0] == 1
+        else:
+            assert g == o, (cl, w)
+
+
+def test_solver_wide_components(L):
+    # components wider than the enumeration limit take the branch and bound
+    rng = np.random.default_rng(6)
+    for trial in range(20):
+        S = int(rng.integers(21, 65))
+        cl = []
+        for _ in range(int(rng.integers(20, 80))):
+            lo = int(rng.integers(0, S - 1))
+            hi = int(rng.integers(lo, min(S, lo + 6)))
+            cl.append((((1 << (hi + 1)) - 1) & ~((1 << lo) - 1), 0))
+        cl += [(0, 1 << int(rng.integers(0, S))) for _ in range(3)]
+        cl.append((((1 << S) - 1) if S < 64 else (1 << 64) - 1, 0))
+        w = rng.integers(1, 5, size=S).tolist()
+        g = L.min_barriers(cl, w, S)
+        o = O.min_barriers(cl, w, S)
+        assert g == o, trial
+
+
+def test_solver_examples(L):
+    with open(os.path.join(GOLDEN, "solver_examples.json")) as f:
+        fx = json.load(f)
+    for case in fx["cases"]:
+        g = L.min_barriers(case["clauses"], case["weights"], case["n_slots"])
+        exp = case["expect"]
+        assert g[0] == exp["status"], case["name"]
+        if g[0] == 0:
+            assert (g[1], g[2]) == (exp["assign"], exp["weight"]), case["name"]
+
+
+def _expected(name):
+    path = os.path.join(GOLDEN, "expected_%s.json" % name)
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name,mode", [("plain_large_literal", "literal"),
+                                       ("plain_large_planted", "planted")])
+def test_plain_large_full_size(L, name, mode):
+    # 256 blocks x 256 threads, 512 points, 32 slots, four 1M-word arrays
+    exp = _expected(name)
+    km = synth.generate("plain-large", mode=mode)
+    for x, c in exp["checks"].items():
+        g = L.check(km, int(x))
+        assert g[0] == 0
+        assert g[3] == c["n_records"]
+        assert g[2] == c["divergent"]
+        assert [list(p) for p in g[1]] == c["pairs"], x
+        assert [list(q) for q in L.clauses(km, int(x))[1]] == exp["clauses"][x], x
+    g = L.repair(km, policy=0)
+    o = exp["repair_policy0"]
+    assert same_repair(g, o), (g, o)
+
+
+def test_edge_empty_and_degenerate(L):
+    km = synth.make_kernel(1, 1, [], [(1, 0)], [], [])
+    assert L.check(km, 0)[:4] == O.check(km, 0)
+    assert same_repair(L.repair(km), O.repair(km))
+    # no slots, one racing write: UNSAT
+    km = synth.make_kernel(1, 8, [(16, 0)], [(1, 0)], [dict(kind=0, is_write=1, a=0)], [])
+    assert L.check(km, 0)[:4] == O.check(km, 0)
+    assert same_repair(L.repair(km), O.repair(km))
+    # one thread, one block: nothing can race
+    km = synth.make_kernel(1, 1, [(4, 1)], [(1, 0)],
+                           [dict(kind=0, is_write=1), dict(kind=1, slot=0),
+                            dict(kind=0, is_write=1)], [(0, 1, 1)])
+    assert same_repair(L.repair(km), O.repair(km))
+    # array sizes that are not powers of two, negative strides
+    pts = [dict(kind=0, is_write=1, a=-1, b=3, c=-2), dict(kind=1, slot=0),
+           dict(kind=0, is_write=0, a=2, b=5, c=1), dict(kind=1, slot=1, guard=1),
+           dict(kind=0, is_write=1, a=1, b=7, c=0)]
+    km = synth.make_kernel(3, 7, [(13, 1)], [(1, 0), (3, 1)], pts,
+                           [(0, 0, 2), (1, 1, 5)])
+    for x in range(4):
+        assert L.check(km, x)[:4] == O.check(km, x, literal=True), x
+    assert same_repair(L.repair(km), O.repair(km))
+
+
+def test_ragged_tiles(L):
+    # record counts that leave partial sort and scan tiles, several blocks
+    for T, B in ((63, 3), (65, 5), (200, 41), (257, 2)):
+        cfg = synth.config("plain-small")
+        cfg.update(blocks=B, threads=T, arrays=[(4096, 0), (8192, 1)], P=40, S=8, S_grid=2,
+                   a_set=(-1, 0, 1, 2), b_set=(0, T), guard_frac=0.3, loop_frac=0.3, unroll=3)
+        for seed in range(3):
+            rng = np.random.default_rng(seed)
+            km = synth.planted_kernel(cfg, rng)
+            assert same_repair(L.repair(km), O.repair(km)), (T, B, seed)
+            assert L.check(km, 0)[:4] == O.check(km, 0), (T, B, seed)
+
+
+def test_errors(L):
+    good = synth.generate("plain-small", seed=1)
+    bad = good.copy()
+    bad.points["array"][0] = 7
+    assert L.validate(bad) == L.ERR_INVALID
+    assert L.check(bad, 0)[0] == L.ERR_INVALID
+    assert L.repair(bad)["status"] == L.ERR_INVALID
+    # output capacity: the needed count comes back
+    st, pairs, div, nrec, n = L.check(good, 0, cap=0)
+    o = O.check(good, 0)
+    if o[1]:
+        assert st == L.ERR_CAPACITY and n == len(o[1])
+    # workspace too small
+    ws = L.Workspace()
+    ws.get(16)
+    import ctypes as C
+    ka = L.KernelArg(good)
+    out = L.RpOut()
+    o = L.RpOpts(0, 1, 1, 0, 0)
+    st = L.lib().rp_repair(ka.ref, C.byref(o), C.byref(out), None, 0,
+                           C.c_void_p(ws.t.data_ptr()), 16, None)
+    assert st == L.ERR_WORKSPACE
