@@ -185,6 +185,13 @@ void rp_last_stats(rp_stats* out);
  * else 8..11 bits).  Process-wide; returns the previous value. */
 int rp_set_sort_digit_bits(int bits);
 
+/* Tuning knobs (process-wide; return the previous value, -1 if rejected):
+ *   RP_TUNE_SORT_DIGIT_BITS  0 = automatic, else 8..11;
+ *   RP_TUNE_SCATTER_SHAPE    radix-scatter tile: 0 = 512x16, 1 = 256x16,
+ *                            2 = 256x32, 3 = 1024x8 (threads x records). */
+enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1 };
+int rp_set_tuning(int knob, int value);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@ namespace rp {
 static thread_local rp_stats t_stats;
 constexpr uint32_t TRAJ_CAP = 4096;
 extern int g_digit_bits_ref(int v, bool set);
+int scatter_variant(int v, bool set);
 
 static std::vector<rp_clause> option_units(const Plan& pl, const rp_repair_opts& o) {
   std::vector<rp_clause> u;
@@ -225,6 +226,19 @@ void rp_last_stats(rp_stats* out) {
 int rp_set_sort_digit_bits(int bits) {
   if (bits != 0 && (bits < 8 || bits > 11)) return -1;
   return g_digit_bits_ref(bits, true);
+}
+
+int rp_set_tuning(int knob, int value) {
+  switch (knob) {
+    case RP_TUNE_SORT_DIGIT_BITS:
+      if (value != 0 && (value < 8 || value > 11)) return -1;
+      return g_digit_bits_ref(value, true);
+    case RP_TUNE_SCATTER_SHAPE:
+      if (value < 0 || value > 3) return -1;
+      return scatter_variant(value, true);
+    default:
+      return -1;
+  }
 }
 
 }  // extern "C"

@@ -87,7 +87,14 @@ struct Job {
 struct SortSeg {
   uint64_t beg, end;     // record range
   uint32_t shift;        // key_shift of the job
-  uint32_t tile_beg;     // first global tile of the segment
+  uint32_t chunk_beg, chunk_end;  // its chunks
+  uint32_t pad;
+};
+
+// sort chunk: a record range inside one segment, one workgroup per pass
+struct SortChunk {
+  uint64_t beg, end;
+  uint32_t seg, pad;
 };
 
 // generation work item: records [o0, o1) of one log (segment-local indices)

@@ -20,19 +20,19 @@ size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t total = 0, meta = 0;
-  size_t o_jobs = 0, o_states = 0, o_items = 0, o_seg_item_beg = 0, o_ssegs = 0, o_csegs = 0;
+  size_t o_jobs = 0, o_states = 0, o_items = 0, o_ssegs = 0, o_csegs = 0;
   size_t o_phi0 = 0;
   std::vector<size_t> o_pts, o_bany, o_bgrid, o_w, o_cpre, o_gpre, o_phi0j;
-  size_t o_recA = 0, o_recB = 0, o_hist = 0, o_dbase = 0, o_status = 0, o_err = 0;
+  size_t o_chunks = 0;
+  size_t o_recA = 0, o_recB = 0, o_cnt = 0, o_tot = 0, o_off = 0, o_err = 0;
   std::vector<size_t> o_ivl, o_minj, o_phi, o_scratch, o_traj, o_bitmap, o_pairs, o_ptotal;
   std::vector<uint32_t> phi_cap, scratch_cap;
   uint64_t n_rec = 0;
-  uint32_t rb = 8, passes = 0, n_tiles = 0, n_conf_tiles = 0;
+  uint32_t rb = 8, passes = 0, n_conf_tiles = 0;
   std::vector<GenItem> items;
-  std::vector<uint32_t> seg_item_beg;
+  std::vector<SortChunk> chunks;
   std::vector<SortSeg> ssegs;
   std::vector<uint32_t> seg_job, seg_level;
-  uint64_t status_words = 0;
 };
 
 uint32_t pow2_at_least(uint64_t n) {
@@ -48,9 +48,8 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   for (const JobInput& j : jobs) key_bits = std::max(key_bits, j.plan->key_bits);
   L.rb = (uint32_t)pick_digit_bits(key_bits);
   L.passes = (uint32_t)sort_passes(key_bits, (int)L.rb);
-  const uint32_t tile = sort_tile_size();
   uint64_t rec = 0;
-  uint32_t tiles = 0, ctiles = 0;
+  uint32_t ctiles = 0;
   const uint32_t ctile = conf_tile_size();
   for (size_t j = 0; j < N; j++) {
     const Plan& p = *jobs[j].plan;
@@ -61,23 +60,22 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
       s.beg = rec;
       s.end = rec + n;
       s.shift = p.key_shift;
-      s.tile_beg = tiles;
       L.ssegs.push_back(s);
       L.seg_job.push_back((uint32_t)j);
       L.seg_level.push_back((uint32_t)v);
       rec += n;
-      tiles += (uint32_t)((n + tile - 1) / tile);
       ctiles += (uint32_t)((n + ctile - 1) / ctile);
     }
   }
   L.n_rec = rec;
-  L.n_tiles = tiles;
   L.n_conf_tiles = ctiles;
-  // generation items: equal chunks of every log
-  const uint64_t chunk = std::max<uint64_t>(16384, (rec + 16383) / 16384);
-  L.seg_item_beg.push_back(0);
+  // sort chunks (= generation items): whole sort tiles, at most ~64K chunks
+  const uint64_t tile = sort_tile_size();
+  uint64_t chunk = std::max<uint64_t>(2 * tile, (rec + 65535) / 65536);
+  chunk = (chunk + tile - 1) / tile * tile;
   for (size_t s = 0; s < L.ssegs.size(); s++) {
     const uint64_t n = L.ssegs[s].end - L.ssegs[s].beg;
+    L.ssegs[s].chunk_beg = (uint32_t)L.chunks.size();
     for (uint64_t o0 = 0; o0 < n; o0 += chunk) {
       GenItem it{};
       it.o0 = o0;
@@ -86,8 +84,13 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
       it.view = L.seg_level[s];
       it.seg = (uint32_t)s;
       L.items.push_back(it);
+      SortChunk c{};
+      c.beg = L.ssegs[s].beg + it.o0;
+      c.end = L.ssegs[s].beg + it.o1;
+      c.seg = (uint32_t)s;
+      L.chunks.push_back(c);
     }
-    L.seg_item_beg.push_back((uint32_t)L.items.size());
+    L.ssegs[s].chunk_end = (uint32_t)L.chunks.size();
   }
   const uint32_t R = 1u << L.rb;
   // ---- meta region (uploaded)
@@ -95,7 +98,7 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   L.o_jobs = off; off = up(off + N * sizeof(Job));
   L.o_states = off; off = up(off + N * sizeof(JobState));
   L.o_items = off; off = up(off + L.items.size() * sizeof(GenItem));
-  L.o_seg_item_beg = off; off = up(off + L.seg_item_beg.size() * sizeof(uint32_t));
+  L.o_chunks = off; off = up(off + L.chunks.size() * sizeof(SortChunk));
   L.o_ssegs = off; off = up(off + L.ssegs.size() * sizeof(SortSeg));
   L.o_csegs = off; off = up(off + L.ssegs.size() * sizeof(ConfSeg));
   L.o_pts.resize(N); L.o_bany.resize(N); L.o_bgrid.resize(N); L.o_w.resize(N);
@@ -114,10 +117,9 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   // ---- device-only region
   L.o_recA = off; off = up(off + L.n_rec * sizeof(uint64_t));
   L.o_recB = off; off = up(off + (L.passes ? L.n_rec : 0) * sizeof(uint64_t));
-  L.o_hist = off; off = up(off + (size_t)L.items.size() * std::max(1u, L.passes) * R * sizeof(uint32_t));
-  L.o_dbase = off; off = up(off + L.ssegs.size() * std::max(1u, L.passes) * R * sizeof(uint64_t));
-  L.status_words = (uint64_t)L.n_tiles * R + 1;   // + the tile counter
-  L.o_status = off; off = up(off + L.status_words * sizeof(uint64_t));
+  L.o_cnt = off; off = up(off + L.chunks.size() * (size_t)R * sizeof(uint32_t));
+  L.o_tot = off; off = up(off + L.ssegs.size() * (size_t)R * sizeof(uint64_t));
+  L.o_off = off; off = up(off + L.chunks.size() * (size_t)R * sizeof(uint64_t));
   L.o_err = off; off = up(off + 64);
   L.o_ivl.resize(N); L.o_minj.resize(N); L.o_phi.resize(N); L.o_scratch.resize(N);
   L.o_traj.resize(N); L.o_bitmap.resize(N); L.o_pairs.resize(N); L.o_ptotal.resize(N);
@@ -184,7 +186,6 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   if (!ws && L.total) return RP_ERR_WORKSPACE;
   const size_t N = jobs.size();
   uint8_t* d = (uint8_t*)ws;
-  const uint32_t R = 1u << L.rb;
   // ---- host staging of the meta region
   std::vector<uint8_t> h(L.meta, 0);
   Job* hj = (Job*)(h.data() + L.o_jobs);
@@ -232,7 +233,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     std::memcpy(h.data() + L.o_phi0j[j], jobs[j].phi0.data(), jobs[j].phi0.size() * sizeof(rp_clause));
   }
   std::memcpy(h.data() + L.o_items, L.items.data(), L.items.size() * sizeof(GenItem));
-  std::memcpy(h.data() + L.o_seg_item_beg, L.seg_item_beg.data(), L.seg_item_beg.size() * sizeof(uint32_t));
+  std::memcpy(h.data() + L.o_chunks, L.chunks.data(), L.chunks.size() * sizeof(SortChunk));
   std::memcpy(h.data() + L.o_ssegs, L.ssegs.data(), L.ssegs.size() * sizeof(SortSeg));
   // sorted logs end in buffer A after an even number of passes, else B
   uint8_t* sorted = d + ((L.passes % 2 == 0) ? L.o_recA : L.o_recB);
@@ -267,26 +268,23 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   uint32_t* derr = (uint32_t*)(d + L.o_err);
   // ---- records and sort
   const int passes = (int)L.passes;
+  const SortSeg* dss = (const SortSeg*)(d + L.o_ssegs);
+  const SortChunk* dch = (const SortChunk*)(d + L.o_chunks);
+  const uint32_t nch = (uint32_t)L.chunks.size();
+  uint32_t* dcnt = (uint32_t*)(d + L.o_cnt);
+  uint64_t* dtot = (uint64_t*)(d + L.o_tot);
+  uint64_t* doff = (uint64_t*)(d + L.o_off);
   HIPCHK(launch_gen((int)L.rb, (const GenItem*)(d + L.o_items), (uint32_t)L.items.size(), djobs,
-                    (const SortSeg*)(d + L.o_ssegs), (uint64_t*)(d + L.o_recA),
-                    (uint32_t*)(d + L.o_hist), passes, s));
+                    dss, (uint64_t*)(d + L.o_recA), dcnt, passes > 0 ? 1 : 0, s));
   tm.mark(T_GEN);
-  if (passes > 0) {
-    HIPCHK(launch_hist_scan((int)L.rb, (const uint32_t*)(d + L.o_hist),
-                            (const uint32_t*)(d + L.o_seg_item_beg), (const SortSeg*)(d + L.o_ssegs),
-                            (uint32_t)L.ssegs.size(), passes, (uint64_t*)(d + L.o_dbase), s));
-    uint64_t* status = (uint64_t*)(d + L.o_status);
-    uint32_t* counter = (uint32_t*)(status + (uint64_t)L.n_tiles * R);
-    for (int p = 0; p < passes; p++) {
-      const uint64_t* in = (const uint64_t*)(d + ((p % 2 == 0) ? L.o_recA : L.o_recB));
-      uint64_t* out = (uint64_t*)(d + ((p % 2 == 0) ? L.o_recB : L.o_recA));
-      HIPCHK(launch_fill_u64(status, L.status_words, 0, s));
-      tm.mark(T_SORTPASS);
-      HIPCHK(launch_sort_pass((int)L.rb, in, out, (const SortSeg*)(d + L.o_ssegs),
-                              (int)L.ssegs.size(), L.n_tiles, p, passes,
-                              (const uint64_t*)(d + L.o_dbase), status, counter, derr, s));
-      tm.mark(T_SORT);
-    }
+  for (int p = 0; p < passes; p++) {
+    const uint64_t* in = (const uint64_t*)(d + ((p % 2 == 0) ? L.o_recA : L.o_recB));
+    uint64_t* out = (uint64_t*)(d + ((p % 2 == 0) ? L.o_recB : L.o_recA));
+    HIPCHK(launch_sort_scan((int)L.rb, in, dss, (uint32_t)L.ssegs.size(), dch, nch, p, dcnt, dtot,
+                            doff, p == 0, s));
+    tm.mark(T_SORTPASS);
+    HIPCHK(launch_sort_scatter((int)L.rb, in, out, dss, dch, nch, p, doff, derr, s));
+    tm.mark(T_SORT);
   }
   tm.mark(T_SORT);
   // ---- per-round kernels
@@ -296,13 +294,15 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   HIPCHK(hipGetDevice(&dev));
   int ncu = 256;
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const uint32_t conf_grid = (uint32_t)ncu * 8;
+  const uint32_t conf_grid = (uint32_t)ncu * 4;
+  uint32_t maxP = 1;
+  for (const JobInput& j : jobs) maxP = std::max(maxP, j.plan->P);
   std::vector<JobState> hst(N);
   uint64_t scanned = 0;
   uint32_t rounds_run = 0, conf_launches = 0;
   if (o.op == OP_CHECK) {
     HIPCHK(launch_ivl(djobs, (uint32_t)N, 1, s));
-    HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, 1, s));
+    HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 1, s));
     conf_launches++;
     scanned += L.n_rec;
     tm.mark(T_CHECK);
@@ -314,7 +314,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     tm.mark(T_SOLVE);
   } else if (o.op == OP_CLAUSES) {
     HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
-    HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, 0, s));
+    HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s));
     conf_launches++;
     scanned += L.n_rec;
     tm.mark(T_CHECK);
@@ -325,7 +325,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     tm.mark(T_SOLVE);
     for (;;) {
       HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
-      HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, 0, s));
+      HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s));
       conf_launches++;
       tm.mark(T_CHECK);
       HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));

@@ -1,14 +1,13 @@
-// Access-record generation and the digit histograms of every sort pass.
+// Access-record generation.
 //
-// One work item writes a contiguous run of records: either one block's
-// accesses over a range of points (same-block view, block-major order) or
-// one point's accesses over a range of blocks (cross-block view,
-// point-major order).  Each record is a pure function of (point, block,
-// thread): the word is (a*tid + b*bid + c) mod words (Euclidean residue),
-// and the executing threads are those with tid % m == r.  While writing,
-// every item counts the radix digits of all sort passes in LDS and stores
-// the counts to its own row of a histogram table; hist_scan_kernel sums the
-// rows of a sort segment and turns them into each pass's digit offsets.
+// One work item writes a contiguous run of records of one log: the
+// same-block log in block-major order, the cross-block log (GLOBAL arrays
+// only) in point-major order; common.h describes the packing.  Each record
+// is a pure function of (point, block, thread): the word is
+// (a*tid + b*bid + c) mod words (Euclidean residue), and the executing
+// threads are those with tid % m == r.  Items coincide with the sort's
+// chunks: while writing, an item counts the radix digits of the first sort
+// pass in LDS and stores them as its chunk's count row.
 #include "common.h"
 #include "launch.h"
 
@@ -135,56 +134,6 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
   for (uint32_t q = threadIdx.x; q < (uint32_t)passes * R; q += GEN_BLOCK) row[q] = hist[q];
 }
 
-// Block-wide exclusive scan of 64-bit values over 256 threads.
-__device__ __forceinline__ uint64_t block_excl_scan256(uint64_t v, uint64_t* sm, uint64_t* total) {
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  uint64_t inc = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    uint64_t y = __shfl_up(inc, off);
-    if (lane >= off) inc += y;
-  }
-  if (lane == 63) sm[w] = inc;
-  __syncthreads();
-  uint64_t pre = 0, tot = 0;
-  for (int q = 0; q < 4; q++) {
-    if (q < w) pre += sm[q];
-    tot += sm[q];
-  }
-  __syncthreads();
-  *total = tot;
-  return pre + inc - v;
-}
-
-// One workgroup per (segment, pass): digit totals over the segment's items,
-// exclusive scan over digits, offset by the segment's first record.
-template <int RB>
-__global__ __launch_bounds__(256) void hist_scan_kernel(const uint32_t* __restrict__ item_hist,
-                                                        const uint32_t* __restrict__ seg_item_beg,
-                                                        const SortSeg* __restrict__ segs,
-                                                        int passes, uint64_t* __restrict__ dbase) {
-  constexpr uint32_t R = 1u << RB;
-  constexpr uint32_t PER = R / 256;   // digits per thread (R >= 256)
-  __shared__ uint64_t sm[4];
-  const uint32_t seg = blockIdx.x / passes, p = blockIdx.x % passes;
-  const uint32_t i0 = seg_item_beg[seg], i1 = seg_item_beg[seg + 1];
-  uint64_t cnt[PER];
-  uint64_t local = 0;
-  for (uint32_t q = 0; q < PER; q++) {
-    const uint32_t d = threadIdx.x * PER + q;
-    uint64_t s = 0;
-    for (uint32_t it = i0; it < i1; it++) s += item_hist[((size_t)it * passes + p) * R + d];
-    cnt[q] = s;
-    local += s;
-  }
-  uint64_t total;
-  uint64_t run = block_excl_scan256(local, sm, &total) + segs[seg].beg;
-  uint64_t* out = dbase + ((size_t)seg * passes + p) * R;
-  for (uint32_t q = 0; q < PER; q++) {
-    out[threadIdx.x * PER + q] = run;
-    run += cnt[q];
-  }
-}
-
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,
                       const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int passes,
                       hipStream_t s) {
@@ -194,21 +143,6 @@ hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job*
     case 9: gen_kernel<9><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, passes); break;
     case 10: gen_kernel<10><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, passes); break;
     case 11: gen_kernel<11><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, passes); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_hist_scan(int rb, const uint32_t* item_hist, const uint32_t* seg_item_beg,
-                            const SortSeg* segs, uint32_t nseg, int passes, uint64_t* dbase,
-                            hipStream_t s) {
-  if (nseg == 0 || passes == 0) return hipSuccess;
-  const uint32_t g = nseg * passes;
-  switch (rb) {
-    case 8: hist_scan_kernel<8><<<g, 256, 0, s>>>(item_hist, seg_item_beg, segs, passes, dbase); break;
-    case 9: hist_scan_kernel<9><<<g, 256, 0, s>>>(item_hist, seg_item_beg, segs, passes, dbase); break;
-    case 10: hist_scan_kernel<10><<<g, 256, 0, s>>>(item_hist, seg_item_beg, segs, passes, dbase); break;
-    case 11: hist_scan_kernel<11><<<g, 256, 0, s>>>(item_hist, seg_item_beg, segs, passes, dbase); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -11,17 +11,16 @@ uint32_t conf_tile_size();
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,
                       const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int passes,
                       hipStream_t s);
-hipError_t launch_hist_scan(int rb, const uint32_t* item_hist, const uint32_t* seg_item_beg,
-                            const SortSeg* segs, uint32_t nseg, int passes, uint64_t* dbase,
-                            hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
-hipError_t launch_sort_pass(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
-                            int nseg, uint32_t n_tiles, int pass, int passes,
-                            const uint64_t* dbase, uint64_t* status, uint32_t* counter,
-                            uint32_t* err, hipStream_t s);
+hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uint32_t nseg,
+                            const SortChunk* chunks, uint32_t nchunks, int pass, uint32_t* cnt,
+                            uint64_t* tot, uint64_t* off, bool counts_ready, hipStream_t s);
+hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
+                               const SortChunk* chunks, uint32_t nchunks, int pass,
+                               const uint64_t* off, uint32_t* err, hipStream_t s);
 hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int with_bitmap, hipStream_t s);
 hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t n_tiles,
-                       uint32_t grid, int all_pairs, hipStream_t s);
+                       uint32_t grid, uint32_t max_points, int all_pairs, hipStream_t s);
 hipError_t launch_pairs(const Job* job, rp_pair* out, uint64_t* total, hipStream_t s);
 hipError_t launch_clause(const Job* jobs, uint32_t njobs, int learn, hipStream_t s);
 hipError_t launch_solve(const Job* jobs, uint32_t njobs, hipStream_t s);

@@ -1,29 +1,23 @@
-// Stable LSD radix sort of the access records, one launch per digit pass.
+// Stable LSD radix sort of the access records (reduce-then-scan per pass).
 //
-// Single-pass ("onesweep") scheme for CDNA4: each 512-thread workgroup takes
-// the next tile of 8192 records (tile ids come from an atomic counter, so a
-// tile only ever waits for tiles that already started), ranks the keys of
-// its tile stably with 64-lane ballots, publishes its digit counts, obtains
-// the records of earlier tiles with the same digit by decoupled look-back,
-// stages the tile in LDS in digit order and writes digit runs out in order.
-// Global digit offsets of every pass come from the histograms counted while
-// the records were generated.  Several sort segments (logs) are sorted by
-// one launch; look-back never crosses a segment's first tile.
-//
-// The look-back wait is bounded: a tile that waits too long records an error
-// (checked by the host) and carries on, so the grid always drains.
+// The record buffer is cut into chunks that never straddle a sort segment
+// (one log of one job).  Per digit pass:
+//   count_kernel     per chunk, how many records carry each digit (pass 0
+//                    takes these counts from record generation instead);
+//   colsum_kernel    per (segment, digit), the total over the segment's chunks;
+//   colscan_kernel   per (segment, digit), the exclusive scan over the chunks,
+//                    offset by the segment start and the totals of smaller
+//                    digits: the first output slot of every (chunk, digit);
+//   scatter_kernel   per chunk, tiles of records are ranked stably with
+//                    64-lane ballots, staged in LDS in digit order and written
+//                    out as contiguous digit runs.
+// No workgroup ever waits on another, so nothing here can stall the grid.
 #include "common.h"
 #include "launch.h"
 
 namespace rp {
 
-constexpr int SORT_BLOCK = 512;
-constexpr int SORT_WAVES = SORT_BLOCK / 64;
-constexpr int SORT_IPT = 16;
-constexpr uint32_t SORT_TILE = SORT_BLOCK * SORT_IPT;  // 8192 records
-constexpr uint64_t FLAG_AGG = 1ull << 62, FLAG_INC = 2ull << 62;
-constexpr uint64_t VAL_MASK = (1ull << 62) - 1;
-constexpr uint32_t SPIN_LIMIT = 1u << 22;
+constexpr uint32_t SC_MAX_TILE = 8192;   // chunks are multiples of every tile shape
 
 __global__ void fill_u64_kernel(uint64_t* p, uint64_t n, uint64_t v) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -31,171 +25,220 @@ __global__ void fill_u64_kernel(uint64_t* p, uint64_t n, uint64_t v) {
   for (; i < n; i += stride) p[i] = v;
 }
 
-__device__ __forceinline__ void st_status(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t ld_status(uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// Per-chunk digit counts of one pass: cnt[chunk][d].
 template <int RB>
-__global__ __launch_bounds__(SORT_BLOCK) void onesweep_kernel(
-    const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
-    const SortSeg* __restrict__ segs, int nseg, int pass, int passes,
-    const uint64_t* __restrict__ dbase, uint64_t* status, uint32_t* counter, uint32_t* err) {
+__global__ __launch_bounds__(256) void count_kernel(const uint64_t* __restrict__ in,
+                                                    const SortChunk* __restrict__ chunks,
+                                                    const SortSeg* __restrict__ segs, int pass,
+                                                    uint32_t* __restrict__ cnt) {
   constexpr uint32_t R = 1u << RB;
-  __shared__ uint64_t sk[SORT_TILE];                // 64 KiB
-  __shared__ uint16_t whist[SORT_WAVES][R];         // per-wave counts, then prefixes
-  __shared__ uint32_t lstart[R];                    // tile-local digit starts
-  __shared__ uint64_t gexcl[R];                     // global offset of the tile's digit run
-  __shared__ uint32_t s_tile, s_seg;
-  __shared__ uint32_t scan_sm[SORT_WAVES];
-
-  const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
-  if (tid == 0) {
-    const uint32_t t = atomicAdd(counter, 1u);
-    int lo = 0, hi = nseg - 1;           // largest segment with tile_beg <= t
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (segs[mid].tile_beg <= t) lo = mid; else hi = mid - 1;
-    }
-    s_tile = t;
-    s_seg = (uint32_t)lo;
-  }
-  for (uint32_t q = tid; q < SORT_WAVES * R; q += SORT_BLOCK) (&whist[0][0])[q] = 0;
+  __shared__ uint32_t hist[R];
+  const SortChunk ch = chunks[blockIdx.x];
+  const int shift = (int)segs[ch.seg].shift + pass * RB;
+  for (uint32_t d = threadIdx.x; d < R; d += 256) hist[d] = 0;
   __syncthreads();
-  const uint32_t tile = s_tile, segi = s_seg;
-  const SortSeg sg = segs[segi];
-  const uint32_t tin = tile - sg.tile_beg;
-  const uint64_t base = sg.beg + (uint64_t)tin * SORT_TILE;
-  const uint64_t rem = sg.end - base;
-  const uint32_t n_here = rem < SORT_TILE ? (uint32_t)rem : SORT_TILE;
-  const int shift = (int)sg.shift + pass * RB;
-
-  // load: wave w owns 64*IPT consecutive records, item k of lane l is record
-  // w*64*IPT + k*64 + l (coalesced; rank order == input order)
-  uint64_t key[SORT_IPT];
-  uint32_t rank[SORT_IPT];
-  const uint32_t wbase = (uint32_t)w * 64 * SORT_IPT;
-#pragma unroll
-  for (int k = 0; k < SORT_IPT; k++) {
-    const uint32_t idx = wbase + k * 64 + lane;
-    key[k] = idx < n_here ? in[base + idx] : 0;
-  }
-  const uint64_t lt = lanemask_lt();
-#pragma unroll
-  for (int k = 0; k < SORT_IPT; k++) {
-    const bool valid = (wbase + k * 64 + lane) < n_here;
-    const uint32_t d = digit_at(key[k], shift, R - 1);
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < RB; b++) {
-      const bool bit = (d >> b) & 1;
-      const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
-    }
-    uint32_t before = 0;
-    if (valid) before = whist[w][d];
-    rank[k] = before + (uint32_t)__popcll(peers & lt);
-    if (valid && (peers & lt) == 0) whist[w][d] = (uint16_t)(before + __popcll(peers));
-    // the wave's lanes run in lock step; keep the compiler from moving the
-    // next item's counter read above this write
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
-
-  // per digit: prefix over waves, tile count, publish, look back
-  for (uint32_t d = tid; d < R; d += SORT_BLOCK) {
-    uint32_t run = 0;
-    for (int v = 0; v < SORT_WAVES; v++) {
-      const uint32_t c = whist[v][d];
-      whist[v][d] = (uint16_t)run;
-      run += c;
-    }
-    lstart[d] = run;  // tile count for now
-    uint64_t* my = status + (uint64_t)tile * R + d;
-    if (tin == 0) {
-      const uint64_t g = dbase[((size_t)segi * passes + pass) * R + d];
-      st_status(my, FLAG_INC | (g + run));
-      gexcl[d] = g;
-    } else {
-      st_status(my, FLAG_AGG | run);
-    }
-  }
-  for (uint32_t d = tid; d < R; d += SORT_BLOCK) {
-    if (tin == 0) continue;
-    uint64_t excl = 0;
-    uint32_t t = tile - 1;
-    uint32_t spins = 0;
-    for (;;) {
-      const uint64_t s = ld_status(status + (uint64_t)t * R + d);
-      const uint64_t f = s & ~VAL_MASK;
-      if (f == 0) {
-        if (++spins > SPIN_LIMIT) { atomicOr(err, ERR_SORT); break; }
-        __builtin_amdgcn_s_sleep(1);
-        continue;
-      }
-      excl += s & VAL_MASK;
-      if (f == FLAG_INC || t == sg.tile_beg) break;
-      t--;
-    }
-    st_status(status + (uint64_t)tile * R + d, FLAG_INC | (excl + lstart[d]));
-    gexcl[d] = excl;
-  }
-  __syncthreads();
-
-  // tile-local exclusive scan of the digit counts -> lstart
-  {
-    constexpr uint32_t PER = (R + SORT_BLOCK - 1) / SORT_BLOCK;
-    uint32_t c[PER];
-    uint32_t local = 0;
-    for (uint32_t q = 0; q < PER; q++) {
-      const uint32_t d = tid * PER + q;
-      c[q] = d < R ? lstart[d] : 0;
-      local += c[q];
-    }
-    uint32_t inc = local;
-    for (int off = 1; off < 64; off <<= 1) {
-      uint32_t y = __shfl_up(inc, off);
-      if (lane >= off) inc += y;
-    }
-    if (lane == 63) scan_sm[w] = inc;
-    __syncthreads();
-    uint32_t pre = 0;
-    for (int v = 0; v < w; v++) pre += scan_sm[v];
-    uint32_t run = pre + inc - local;
-    __syncthreads();
-    for (uint32_t q = 0; q < PER; q++) {
-      const uint32_t d = tid * PER + q;
-      if (d < R) lstart[d] = run;
-      run += c[q];
-    }
-  }
-  __syncthreads();
-
-  // scatter into LDS in digit order
-#pragma unroll
-  for (int k = 0; k < SORT_IPT; k++) {
-    const bool valid = (wbase + k * 64 + lane) < n_here;
+  for (uint64_t r0 = ch.beg; r0 < ch.end; r0 += 256) {
+    const uint64_t r = r0 + threadIdx.x;
+    const bool valid = r < ch.end;
+    const uint32_t d = valid ? digit_at(in[r], shift, R - 1) : 0u;
+    const uint64_t act = __ballot(valid);
     if (valid) {
-      const uint32_t d = digit_at(key[k], shift, R - 1);
-      sk[lstart[d] + whist[w][d] + rank[k]] = key[k];
+      const int first = __ffsll((unsigned long long)act) - 1;
+      const uint32_t d0 = __shfl(d, first);
+      const uint64_t same = __ballot(d == d0);
+      if (same == act) {
+        if ((int)__lane_id() == first) atomicAdd(&hist[d], (uint32_t)__popcll(act));
+      } else {
+        atomicAdd(&hist[d], 1u);
+      }
     }
   }
   __syncthreads();
-  // write digit runs in order (consecutive threads -> consecutive addresses)
-  for (uint32_t p = tid; p < n_here; p += SORT_BLOCK) {
-    const uint64_t kv = sk[p];
-    const uint32_t d = digit_at(kv, shift, R - 1);
-    const uint64_t dst = gexcl[d] + (p - lstart[d]);
-    // a destination outside the segment can only come from inconsistent
-    // counts: report it instead of writing
-    if (dst >= sg.beg && dst < sg.end) out[dst] = kv;
-    else atomicOr(err, ERR_RANGE);
+  uint32_t* row = cnt + (size_t)blockIdx.x * R;
+  for (uint32_t d = threadIdx.x; d < R; d += 256) row[d] = hist[d];
+}
+
+// Column totals: tot[seg][d] = sum over the segment's chunks of cnt[chunk][d].
+template <int RB>
+__global__ __launch_bounds__(256) void colsum_kernel(const uint32_t* __restrict__ cnt,
+                                                     const SortSeg* __restrict__ segs,
+                                                     uint64_t* __restrict__ tot) {
+  constexpr uint32_t R = 1u << RB;
+  __shared__ uint64_t sm[4];
+  const uint32_t seg = blockIdx.x / R, d = blockIdx.x % R;
+  const uint32_t c0 = segs[seg].chunk_beg, c1 = segs[seg].chunk_end;
+  uint64_t s = 0;
+  for (uint32_t c = c0 + threadIdx.x; c < c1; c += 256) s += cnt[(size_t)c * R + d];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (__lane_id() == 0) sm[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) tot[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+}
+
+// First output slot of every (chunk, digit).
+template <int RB>
+__global__ __launch_bounds__(256) void colscan_kernel(const uint32_t* __restrict__ cnt,
+                                                      const SortSeg* __restrict__ segs,
+                                                      const uint64_t* __restrict__ tot,
+                                                      uint64_t* __restrict__ off) {
+  constexpr uint32_t R = 1u << RB;
+  __shared__ uint64_t sm[4];
+  __shared__ uint64_t s_base;
+  const uint32_t seg = blockIdx.x / R, d = blockIdx.x % R;
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  // records of smaller digits in this segment
+  uint64_t b = 0;
+  for (uint32_t q = threadIdx.x; q < d; q += 256) b += tot[(size_t)seg * R + q];
+  for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o);
+  if (lane == 0) sm[w] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) s_base = segs[seg].beg + sm[0] + sm[1] + sm[2] + sm[3];
+  __syncthreads();
+  uint64_t run = s_base;
+  const uint32_t c0 = segs[seg].chunk_beg, c1 = segs[seg].chunk_end;
+  for (uint32_t cb = c0; cb < c1; cb += 256) {
+    const uint32_t c = cb + threadIdx.x;
+    const uint64_t v = c < c1 ? cnt[(size_t)c * R + d] : 0;
+    uint64_t inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      uint64_t y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) sm[w] = inc;
+    __syncthreads();
+    uint64_t pre = 0, all = 0;
+    for (int q = 0; q < 4; q++) {
+      if (q < w) pre += sm[q];
+      all += sm[q];
+    }
+    if (c < c1) off[(size_t)c * R + d] = run + pre + inc - v;
+    run += all;
+    __syncthreads();
   }
 }
 
-uint32_t sort_tile_size() { return SORT_TILE; }
+// Stable scatter of one chunk, tile by tile (SC_BLOCK threads x SC_IPT
+// records per tile).
+template <int RB, int SC_BLOCK, int SC_IPT>
+__global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __restrict__ in,
+                                                           uint64_t* __restrict__ out,
+                                                           const SortChunk* __restrict__ chunks,
+                                                           const SortSeg* __restrict__ segs,
+                                                           int pass,
+                                                           const uint64_t* __restrict__ off,
+                                                           uint32_t* err) {
+  constexpr uint32_t R = 1u << RB;
+  constexpr int SC_WAVES = SC_BLOCK / 64;
+  constexpr uint32_t SC_TILE = SC_BLOCK * SC_IPT;
+  __shared__ uint64_t sk[SC_TILE];
+  __shared__ uint16_t whist[SC_WAVES][R];      // per-wave counts, then prefixes
+  __shared__ uint32_t lstart[R];               // tile-local digit starts
+  __shared__ uint32_t tcount[R];
+  __shared__ uint64_t grun[R];                 // next output slot per digit
+  __shared__ uint32_t scan_sm[SC_WAVES];
+
+  const SortChunk ch = chunks[blockIdx.x];
+  const SortSeg sg = segs[ch.seg];
+  const int shift = (int)sg.shift + pass * RB;
+  const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+  for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] = off[(size_t)blockIdx.x * R + d];
+  const uint64_t lt = lanemask_lt();
+  const uint32_t wbase = (uint32_t)w * 64 * SC_IPT;
+
+  for (uint64_t base = ch.beg; base < ch.end; base += SC_TILE) {
+    const uint64_t rem = ch.end - base;
+    const uint32_t n_here = rem < SC_TILE ? (uint32_t)rem : SC_TILE;
+    for (uint32_t q = tid; q < SC_WAVES * R; q += SC_BLOCK) (&whist[0][0])[q] = 0;
+    __syncthreads();
+    // wave w owns records [w*64*IPT, (w+1)*64*IPT) of the tile; item k of
+    // lane l is record w*64*IPT + k*64 + l (coalesced; rank order = input order)
+    uint64_t key[SC_IPT];
+    uint32_t rank[SC_IPT];
+#pragma unroll
+    for (int k = 0; k < SC_IPT; k++) {
+      const uint32_t idx = wbase + k * 64 + lane;
+      key[k] = idx < n_here ? in[base + idx] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < SC_IPT; k++) {
+      const bool valid = (wbase + k * 64 + lane) < n_here;
+      const uint32_t d = digit_at(key[k], shift, R - 1);
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < RB; b++) {
+        const bool bit = (d >> b) & 1;
+        const uint64_t bb = __ballot(bit);
+        peers &= bit ? bb : ~bb;
+      }
+      uint32_t before = 0;
+      if (valid) before = whist[w][d];
+      rank[k] = before + (uint32_t)__popcll(peers & lt);
+      if (valid && (peers & lt) == 0) whist[w][d] = (uint16_t)(before + __popcll(peers));
+      // lanes of a wave run in lock step; keep the next read after this write
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    for (uint32_t d = tid; d < R; d += SC_BLOCK) {
+      uint32_t run = 0;
+      for (int v = 0; v < SC_WAVES; v++) {
+        const uint32_t c = whist[v][d];
+        whist[v][d] = (uint16_t)run;
+        run += c;
+      }
+      tcount[d] = run;
+    }
+    __syncthreads();
+    {  // tile-local exclusive scan of the digit counts
+      constexpr uint32_t PER = (R + SC_BLOCK - 1) / SC_BLOCK;
+      uint32_t c[PER];
+      uint32_t local = 0;
+      for (uint32_t q = 0; q < PER; q++) {
+        const uint32_t d = tid * PER + q;
+        c[q] = d < R ? tcount[d] : 0;
+        local += c[q];
+      }
+      uint32_t inc = local;
+      for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+      }
+      if (lane == 63) scan_sm[w] = inc;
+      __syncthreads();
+      uint32_t pre = 0;
+      for (int v = 0; v < w; v++) pre += scan_sm[v];
+      uint32_t run = pre + inc - local;
+      for (uint32_t q = 0; q < PER; q++) {
+        const uint32_t d = tid * PER + q;
+        if (d < R) lstart[d] = run;
+        run += c[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SC_IPT; k++) {
+      const bool valid = (wbase + k * 64 + lane) < n_here;
+      if (valid) {
+        const uint32_t d = digit_at(key[k], shift, R - 1);
+        sk[lstart[d] + whist[w][d] + rank[k]] = key[k];
+      }
+    }
+    __syncthreads();
+    for (uint32_t p = tid; p < n_here; p += SC_BLOCK) {
+      const uint64_t kv = sk[p];
+      const uint32_t d = digit_at(kv, shift, R - 1);
+      const uint64_t dst = grun[d] + (p - lstart[d]);
+      // a destination outside the segment can only come from inconsistent
+      // counts: report it instead of writing
+      if (dst >= sg.beg && dst < sg.end) out[dst] = kv;
+      else atomicOr(err, ERR_RANGE);
+    }
+    __syncthreads();
+    for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] += tcount[d];
+    __syncthreads();
+  }
+}
+
+uint32_t sort_tile_size() { return SC_MAX_TILE; }
 
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -205,18 +248,60 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sort_pass(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
-                            int nseg, uint32_t n_tiles, int pass, int passes,
-                            const uint64_t* dbase, uint64_t* status, uint32_t* counter,
-                            uint32_t* err, hipStream_t s) {
-  if (n_tiles == 0) return hipSuccess;
-  switch (rb) {
-    case 8: onesweep_kernel<8><<<n_tiles, SORT_BLOCK, 0, s>>>(in, out, segs, nseg, pass, passes, dbase, status, counter, err); break;
-    case 9: onesweep_kernel<9><<<n_tiles, SORT_BLOCK, 0, s>>>(in, out, segs, nseg, pass, passes, dbase, status, counter, err); break;
-    case 10: onesweep_kernel<10><<<n_tiles, SORT_BLOCK, 0, s>>>(in, out, segs, nseg, pass, passes, dbase, status, counter, err); break;
-    case 11: onesweep_kernel<11><<<n_tiles, SORT_BLOCK, 0, s>>>(in, out, segs, nseg, pass, passes, dbase, status, counter, err); break;
-    default: return hipErrorInvalidValue;
+#define RB_SWITCH(rb, CALL)                             \
+  switch (rb) {                                         \
+    case 8: { constexpr int RBV = 8; CALL; } break;     \
+    case 9: { constexpr int RBV = 9; CALL; } break;     \
+    case 10: { constexpr int RBV = 10; CALL; } break;   \
+    case 11: { constexpr int RBV = 11; CALL; } break;   \
+    default: return hipErrorInvalidValue;               \
   }
+
+hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uint32_t nseg,
+                            const SortChunk* chunks, uint32_t nchunks, int pass, uint32_t* cnt,
+                            uint64_t* tot, uint64_t* off, bool counts_ready, hipStream_t s) {
+  if (nchunks == 0) return hipSuccess;
+  const uint32_t R = 1u << rb;
+  if (!counts_ready) {
+    RB_SWITCH(rb, (count_kernel<RBV><<<nchunks, 256, 0, s>>>(in, chunks, segs, pass, cnt)));
+  }
+  RB_SWITCH(rb, (colsum_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot)));
+  RB_SWITCH(rb, (colscan_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot, off)));
+  return hipGetLastError();
+}
+
+static int g_scatter_variant = 0;
+int scatter_variant(int v, bool set) {
+  const int old = g_scatter_variant;
+  if (set) g_scatter_variant = v;
+  return old;
+}
+
+template <int RB>
+static void scatter_launch(int variant, uint32_t nchunks, const uint64_t* in, uint64_t* out,
+                           const SortChunk* chunks, const SortSeg* segs, int pass,
+                           const uint64_t* off, uint32_t* err, hipStream_t s) {
+  switch (variant) {
+    case 1: scatter_kernel<RB, 256, 16><<<nchunks, 256, 0, s>>>(in, out, chunks, segs, pass, off, err); break;
+    case 2: scatter_kernel<RB, 256, 32><<<nchunks, 256, 0, s>>>(in, out, chunks, segs, pass, off, err); break;
+    case 3:
+      // 16 waves of per-digit counters do not fit LDS beside the tile for
+      // wide digits
+      if constexpr (RB <= 9) {
+        scatter_kernel<RB, 1024, 8><<<nchunks, 1024, 0, s>>>(in, out, chunks, segs, pass, off, err);
+        break;
+      }
+      [[fallthrough]];
+    default: scatter_kernel<RB, 512, 16><<<nchunks, 512, 0, s>>>(in, out, chunks, segs, pass, off, err); break;
+  }
+}
+
+hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
+                               const SortChunk* chunks, uint32_t nchunks, int pass,
+                               const uint64_t* off, uint32_t* err, hipStream_t s) {
+  if (nchunks == 0) return hipSuccess;
+  const int v = g_scatter_variant;
+  RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, pass, off, err, s)));
   return hipGetLastError();
 }
 

@@ -79,6 +79,8 @@ _L.rp_repair.argtypes = [_K, C.POINTER(RpOpts), C.POINTER(RpOut), C.c_void_p, C.
 _L.rp_last_stats.argtypes = [C.POINTER(RpStats)]
 _L.rp_last_stats.restype = None
 _L.rp_set_sort_digit_bits.argtypes = [C.c_int]
+_L.rp_set_tuning.argtypes = [C.c_int, C.c_int]
+TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE = 0, 1
 
 
 def lib():
@@ -227,3 +229,7 @@ def last_stats() -> dict:
 
 def set_sort_digit_bits(bits: int) -> int:
     return _L.rp_set_sort_digit_bits(int(bits))
+
+
+def set_tuning(knob: int, value: int) -> int:
+    return _L.rp_set_tuning(int(knob), int(value))
