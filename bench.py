@@ -7,11 +7,20 @@ points, 32 barrier slots (8 grid-level), two shared and two global arrays of
 1M int32 words.  The metric is race-checked accesses per second: every
 (point, block, thread) access is race-checked once per Verify call.
 
+Two more legs are reported beside the headline (same JSON line):
+  batched  the 1,024-kernel batched workload (planted mode): repaired kernels
+           per second of one rp_repair_batch call against the plain
+           one-kernel-at-a-time rp_repair loop on the same kernels;
+  served   Poisson arrivals (2,000 jobs/s by default) drawn from the same
+           1,024 kernels into a continuous-batching server with a 64 GB
+           arena: p50/p99 latency from submission to verdict, throughput.
+
 Prints one JSON line.  Inputs are synthetic and seeded; device buffers are
 resident before the timed region starts.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -42,6 +51,84 @@ def cpu_baseline(km, rounds_gpu):
                 matches_gpu_rounds=r["rounds"] == rounds_gpu)
 
 
+def batched_leg(L, torch, kms):
+    """One batched call over all kernels vs the plain per-kernel loop."""
+    from paper_2011_08373_amd import autotune
+    b = L.BatchArg(kms)
+    ws = L.Workspace()
+    ws.get(L.batch_workspace_bytes(b))
+    tuned = autotune.apply(sum(int(k.blocks) * int(k.threads) for k in kms) * 256)
+    L.repair_batch(b, ws=ws)                       # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st, res = L.repair_batch(b, ws=ws)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    bstats = L.last_stats()
+    # plain loop: one rp_repair per kernel, in order
+    ws1 = L.Workspace()
+    ws1.get(max(L.workspace_bytes(k, L.OP_REPAIR) for k in kms))
+    L.repair(kms[0], ws=ws1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain = [L.repair(k, ws=ws1) for k in kms]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    same = all(plain[q]["status"] == res[q]["status"] and plain[q]["assign"] == res[q]["assign"]
+               for q in range(len(kms)))
+    rep = sum(1 for r in res if r["status"] == 0)
+    uns = sum(1 for r in res if r["status"] == 1)
+    return {"workload": "batched planted: %d kernels, threads log-uniform in [64, 65536], "
+                        "points uniform in [16, 1024], slots uniform in [2, 40], seed 3" % len(kms),
+            "kernels_per_s_batched": len(kms) / tb, "kernels_per_s_plain": len(kms) / tp,
+            "speedup": tp / tb, "ms_batched": tb * 1e3, "ms_plain": tp * 1e3,
+            "repaired": rep, "unsat": uns, "other": len(kms) - rep - uns,
+            "batched_equals_plain": same, "records": bstats["records"],
+            "accesses": bstats["accesses"], "rounds": bstats["rounds"],
+            "phases_ms": {k: bstats[k] for k in ("ms_gen", "ms_sort", "ms_runs", "ms_check",
+                                                 "ms_clause", "ms_solve", "ms_total")},
+            "autotuned": tuned}
+
+
+def served_leg(L, torch, kms, rate, seconds, arena_gb):
+    """Poisson arrivals into the continuous-batching server."""
+    from paper_2011_08373_amd import synth
+    warm = 1.0
+    arr = synth.poisson_arrivals(rate, warm + seconds, seed=4)
+    srv = L.Server(arena_bytes=int(arena_gb * (1 << 30)), max_resident=1024)
+    lat = {}
+    n_sub = 0
+    t0 = time.perf_counter()
+    max_res = 0
+    limit = warm + seconds + 60.0          # drain the backlog, but not forever
+    while len(lat) < len(arr) and time.perf_counter() - t0 < limit:
+        now = time.perf_counter() - t0
+        while n_sub < len(arr) and arr[n_sub] <= now:
+            st = srv.submit(kms[n_sub % len(kms)], n_sub)
+            if st != 0:
+                raise RuntimeError("submit failed: %d" % st)
+            n_sub += 1
+        nres, npend = srv.step()
+        max_res = max(max_res, nres)
+        for jid, r, l in srv.poll():
+            lat[jid] = l
+        if nres == 0 and npend == 0 and n_sub < len(arr):
+            time.sleep(max(0.0, min(0.001, arr[n_sub] - (time.perf_counter() - t0))))
+    t_end = time.perf_counter() - t0
+    srv.close()
+    ids = [i for i in range(len(arr)) if arr[i] >= warm]
+    ls = sorted(lat[i] for i in ids if i in lat)
+
+    def pct(p):
+        return ls[min(len(ls) - 1, max(0, int(math.ceil(p * len(ls))) - 1))] if ls else None
+    return {"workload": "served: Poisson arrivals at %.0f jobs/s drawn from the batched "
+                        "kernels, %.0f GB arena, 1 s warm-up + %.1f s measured" % (rate, arena_gb, seconds),
+            "jobs_measured": len(ids), "jobs_finished": len(ls),
+            "p50_s": pct(0.50), "p99_s": pct(0.99),
+            "throughput_jobs_per_s": len(arr) / t_end, "offered_jobs_per_s": rate,
+            "max_resident": max_res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +136,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="literal", choices=("literal", "planted"))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--legs", default="main,batched,served")
+    ap.add_argument("--batched-n", type=int, default=1024)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-arena-gb", type=float, default=64.0)
     ap.add_argument("--calib", action="store_true",
                     help="run a 512 MiB device copy first (reference for byte counters)")
     args = ap.parse_args()
@@ -113,11 +205,21 @@ def main():
                      "kernel": "scatter_kernel (one radix pass: reads and writes 8 B per record)",
                      "avg_launch_ms": pass_ms},
         "phases_ms": {k: sum(s[k] for s in stats) / len(stats)
-                      for k in ("ms_gen", "ms_sort", "ms_check", "ms_clause", "ms_solve",
+                      for k in ("ms_gen", "ms_sort", "ms_runs", "ms_check", "ms_clause", "ms_solve",
                                 "ms_total")},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(km, r["rounds"])
+    legs = set(args.legs.split(","))
+    del ws
+    torch.cuda.empty_cache()
+    if "batched" in legs or "served" in legs:
+        kms = synth.generate_batch(n=args.batched_n, mode="planted")
+        if "batched" in legs:
+            out["batched"] = batched_leg(L, torch, kms)
+        if "served" in legs:
+            out["served"] = served_leg(L, torch, kms, args.serve_rate, args.serve_seconds,
+                                       args.serve_arena_gb)
     print(json.dumps(out))
 
 

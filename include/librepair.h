@@ -80,7 +80,7 @@ typedef enum {
 enum { RP_ACCESS = 0, RP_BARRIER = 1, RP_NOP = 2 };
 enum { RP_SHARED = 0, RP_GLOBAL = 1 };
 enum { RP_BLOCK = 0, RP_GRID = 1 };
-enum { RP_OP_CHECK = 0, RP_OP_CLAUSES = 1, RP_OP_REPAIR = 2 };
+enum { RP_OP_CHECK = 0, RP_OP_CLAUSES = 1, RP_OP_REPAIR = 2, RP_OP_FIRST = 4 };
 
 typedef struct { uint32_t words; uint8_t space; } rp_array;              /* 8 B */
 typedef struct { uint32_t m, r; } rp_guard;                              /* 8 B */
@@ -130,6 +130,7 @@ typedef struct {
   double ms_gen, ms_sort, ms_check, ms_clause, ms_solve, ms_total;
   double ms_sort_pass_max;       /* longest single sort pass */
   double ms_sort_kernels;        /* sum of the radix-pass kernel durations */
+  double ms_runs;                /* run-log build (once per kernel) */
   uint64_t records;              /* access records generated (both views) */
   uint64_t accesses;             /* (point, block, thread) accesses */
   uint64_t records_scanned;      /* records read by conflict scans */
@@ -155,6 +156,14 @@ rp_status rp_check(const rp_kernel* k, uint64_t x,
                    uint64_t* divergent, uint64_t* n_records,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* The part of Verify under x that the repair loop uses: for every point i
+ * and view (first[i]: same block, first[n_points + i]: different blocks),
+ * the smallest point j >= i that races with i, or UINT32_MAX.  Every race
+ * (i, j') has j' >= first[i], and its clause contains the clause of
+ * (i, first[i]).  Workspace: rp_workspace_bytes(k, RP_OP_FIRST). */
+rp_status rp_first_partners(const rp_kernel* k, uint64_t x, uint32_t* first,
+                            uint64_t* divergent, void* ws, size_t ws_bytes, void* stream);
+
 /* GenerateClause of Alg. 1 over every trace under x, reduced: sorted by
  * (pos, neg) ascending, duplicates and subsumed clauses removed. */
 rp_status rp_clauses(const rp_kernel* k, uint64_t x,
@@ -177,6 +186,37 @@ rp_status rp_min_barriers(const rp_clause* clauses, uint64_t n_clauses,
 rp_status rp_repair(const rp_kernel* k, const rp_repair_opts* opts,
                     rp_repair_out* out, uint64_t* trajectory, uint32_t traj_cap,
                     void* ws, size_t ws_bytes, void* stream);
+
+/* Batched Alg. 1 over n kernels of any sizes: one launch per phase covers
+ * every kernel (records, sort, run logs), each round is one captured hipGraph
+ * (when `stream` is not NULL) over every kernel still running, and the host
+ * reads one 32-bit count per round.  outs[j] gets kernel j's result exactly
+ * as rp_repair would give it; a kernel that fails validation gets
+ * RP_ERR_INVALID and the others still run.  Returns RP_OK unless the whole
+ * call failed.  Workspace: rp_batch_workspace_bytes over the same kernels. */
+size_t rp_batch_workspace_bytes(const rp_kernel* const* ks, uint32_t n);
+rp_status rp_repair_batch(const rp_kernel* const* ks, uint32_t n, const rp_repair_opts* opts,
+                          rp_repair_out* outs, void* ws, size_t ws_bytes, void* stream);
+
+/* Serving (continuous batching).  The arena is caller-owned device memory
+ * (e.g. a torch allocation) that the server uses until rp_server_destroy:
+ * fixed tables for up to `max_resident` jobs, then first-fit ranges for the
+ * resident jobs (records, run logs, clause sets stay there until a job
+ * finishes).  rp_server_submit copies the descriptor (RP_ERR_BUDGET when the
+ * job's footprint exceeds the arena); rp_server_step admits pending jobs in
+ * arrival order while they fit, runs one round of Alg. 1 over every resident
+ * job and retires finished ones; rp_server_poll returns finished jobs with
+ * their results (as rp_repair gives them) and latency from submission to
+ * verdict.  A server is not thread-safe; its calls must not overlap. */
+size_t rp_server_tables_bytes(uint32_t max_resident);
+size_t rp_server_job_bytes(const rp_kernel* k);
+rp_status rp_server_create(void* arena, size_t arena_bytes, const rp_repair_opts* opts,
+                           uint32_t max_resident, void* stream, void** server);
+rp_status rp_server_submit(void* server, const rp_kernel* k, uint64_t job_id);
+rp_status rp_server_step(void* server, uint32_t* n_resident, uint32_t* n_pending);
+rp_status rp_server_poll(void* server, uint64_t* job_ids, rp_repair_out* outs,
+                         double* latency_s, uint32_t cap, uint32_t* n_done);
+rp_status rp_server_destroy(void* server);
 
 /* Statistics of the last call made on this thread. */
 void rp_last_stats(rp_stats* out);

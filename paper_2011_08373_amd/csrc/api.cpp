@@ -54,7 +54,7 @@ const char* rp_status_string(int s) {
 rp_status rp_validate(const rp_kernel* k) { return (rp_status)validate_kernel(k); }
 
 size_t rp_workspace_bytes(const rp_kernel* k, int op) {
-  if (validate_kernel(k) != RP_OK || op < RP_OP_CHECK || op > RP_OP_REPAIR) return 0;
+  if (validate_kernel(k) != RP_OK || op < RP_OP_CHECK || op > RP_OP_FIRST) return 0;
   Plan pl;
   make_plan(k, pl);
   JobInput ji;
@@ -115,6 +115,27 @@ rp_status rp_clauses(const rp_kernel* k, uint64_t x, rp_clause* out, uint64_t ca
   if (n_out) *n_out = n;
   if (n > cap) return RP_ERR_CAPACITY;
   if (n) std::memcpy(out, res[0].phi.data(), n * sizeof(rp_clause));
+  return RP_OK;
+}
+
+rp_status rp_first_partners(const rp_kernel* k, uint64_t x, uint32_t* first,
+                            uint64_t* divergent, void* ws, size_t ws_bytes, void* stream) {
+  if (validate_kernel(k) != RP_OK || (k->n_points && !first)) return RP_ERR_INVALID;
+  Plan pl;
+  make_plan(k, pl);
+  JobInput ji;
+  ji.plan = &pl;
+  ji.x = x;
+  EngineOpts o;
+  o.op = OP_FIRST;
+  std::vector<JobInput> v{ji};
+  std::vector<JobResult> res;
+  rp_stats st;
+  int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
+  t_stats = st;
+  if (rc != RP_OK) return (rp_status)rc;
+  if (pl.P) std::memcpy(first, res[0].first.data(), 2 * (size_t)pl.P * sizeof(uint32_t));
+  if (divergent) *divergent = res[0].st.divergent;
   return RP_OK;
 }
 
@@ -217,6 +238,80 @@ rp_status rp_repair(const rp_kernel* k, const rp_repair_opts* opts, rp_repair_ou
     std::memcpy(trajectory, res[0].traj.data(), nt * sizeof(uint64_t));
   }
   return (rp_status)out->status;
+}
+
+size_t rp_batch_workspace_bytes(const rp_kernel* const* ks, uint32_t n) {
+  if (!ks) return 0;
+  std::vector<Plan> plans;
+  plans.reserve(n);
+  for (uint32_t j = 0; j < n; j++) {
+    if (validate_kernel(ks[j]) != RP_OK) continue;
+    plans.emplace_back();
+    make_plan(ks[j], plans.back());
+  }
+  std::vector<JobInput> v(plans.size());
+  for (size_t j = 0; j < plans.size(); j++) {
+    v[j].plan = &plans[j];
+    worst_units(plans[j], v[j].phi0);
+  }
+  EngineOpts o;
+  o.op = OP_REPAIR;
+  return engine_workspace(v, o);
+}
+
+rp_status rp_repair_batch(const rp_kernel* const* ks, uint32_t n, const rp_repair_opts* opts,
+                          rp_repair_out* outs, void* ws, size_t ws_bytes, void* stream) {
+  if (!ks || !outs) return RP_ERR_INVALID;
+  rp_repair_opts op = opts ? *opts : rp_repair_opts{0, 1, 1, 0, 0};
+  if (op.policy > 1) return RP_ERR_INVALID;
+  std::vector<Plan> plans;
+  std::vector<uint32_t> idx;
+  plans.reserve(n);
+  for (uint32_t j = 0; j < n; j++) {
+    std::memset(&outs[j], 0, sizeof(outs[j]));
+    if (validate_kernel(ks[j]) != RP_OK) {
+      outs[j].status = RP_ERR_INVALID;   // this job only; the others run
+      continue;
+    }
+    plans.emplace_back();
+    make_plan(ks[j], plans.back());
+    idx.push_back(j);
+  }
+  std::vector<JobInput> v(plans.size());
+  for (size_t q = 0; q < plans.size(); q++) {
+    v[q].plan = &plans[q];
+    v[q].phi0 = option_units(plans[q], op);
+    v[q].policy = op.policy;
+    v[q].max_rounds = op.max_rounds;
+  }
+  if (v.empty()) return RP_OK;
+  EngineOpts o;
+  o.op = OP_REPAIR;
+  std::vector<JobResult> res;
+  rp_stats st;
+  int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
+  t_stats = st;
+  if (rc != RP_OK) return (rp_status)rc;
+  for (size_t q = 0; q < v.size(); q++) {
+    const JobState& s = res[q].st;
+    rp_repair_out& out = outs[idx[q]];
+    out.rounds = s.rounds;
+    out.n_clauses = s.n_phi;
+    if (s.state == ST_SAFE) {
+      out.status = RP_OK;
+      out.assign = s.x;
+      out.weight = s.weight;
+      out.added = s.x & ~plans[q].pre_slots;
+      out.removed = plans[q].pre_slots & ~s.x;
+    } else if (s.state == ST_UNSAT) {
+      out.status = RP_UNSAT;
+    } else if (s.state == ST_ROUNDS) {
+      out.status = RP_ERR_ROUNDS;
+    } else {
+      out.status = RP_ERR_DEVICE;
+    }
+  }
+  return RP_OK;
 }
 
 void rp_last_stats(rp_stats* out) {

@@ -5,15 +5,13 @@
 //              barrier occurrences before each point (any level, and grid
 //              level only), the divergent enabled slots, and the reset of the
 //              per-round outputs.
-// conf_kernel  persistent scan of the sorted logs.  A "run" is the records of
-//              one point at one location; runs are in program order inside a
-//              location, so the runs of one interval are contiguous.  Each run
-//              head walks the following runs of its location and interval and
-//              reports racing partners: two runs race when one writes and they
-//              are not the same single thread (same-block view) or the same
-//              single block (cross-block view).  In "first" mode a run stops
-//              at its first racing partner (enough for the reduced clause set);
-//              in "all" mode every racing pair goes into a bitmap.
+// conf_kernel  scan of the run logs (runs.hip).  Runs are in program order
+//              inside a location, so the runs of one interval are contiguous.
+//              Two runs race when one writes and they are not the same single
+//              thread (same-block view) or the same single block (cross-block
+//              view).  In "first" mode a run stops at its first racing
+//              partner (enough for the reduced clause set); in "all" mode
+//              every racing pair goes into a bitmap.
 // pairs_kernel turns the bitmap into the (level, i, j)-ordered pair list.
 #include "common.h"
 #include "launch.h"
@@ -22,8 +20,8 @@ namespace rp {
 
 constexpr int IVL_BLOCK = 1024;
 constexpr int CONF_BLOCK = 256;
-constexpr uint32_t CONF_TILE = 2048;                     // records owned per tile
-constexpr uint32_t CONF_WIN = CONF_TILE + 1024;          // staged: tile + lookahead
+constexpr uint32_t CONF_TILE = 4096;                     // runs owned per tile
+constexpr uint32_t CONF_WIN = CONF_TILE + 2048;          // staged: tile + lookahead
 
 __global__ __launch_bounds__(IVL_BLOCK) void ivl_kernel(const Job* __restrict__ jobs, int with_bitmap) {
   __shared__ uint64_t wsum[IVL_BLOCK / 64];
@@ -72,38 +70,6 @@ __global__ __launch_bounds__(IVL_BLOCK) void ivl_kernel(const Job* __restrict__ 
   if (tid == 0) st->divergent = x & J.div_if_enabled;
 }
 
-// The records of one tile plus a lookahead are staged in LDS; reads past
-// the staged window fall back to global memory.
-struct Win {
-  const uint64_t* __restrict__ g;
-  const uint64_t* s;
-  uint64_t base, len;
-  __device__ __forceinline__ uint64_t operator()(uint64_t i) const {
-    const uint64_t o = i - base;   // callers never read below base
-    return o < len ? s[o] : g[i];
-  }
-};
-
-// First index after q whose (location, point) prefix differs from pv.
-__device__ __forceinline__ uint64_t run_end(const Win& at, uint64_t n, uint64_t q, uint64_t pv,
-                                            int psh) {
-  uint64_t lo = q + 1;
-  if (lo >= n || (at(lo) >> psh) != pv) return lo;
-  uint64_t step = 1, hi;
-  for (;;) {
-    hi = lo + step;
-    if (hi >= n) { hi = n; break; }
-    if ((at(hi) >> psh) != pv) break;
-    lo = hi;
-    step <<= 1;
-  }
-  while (hi - lo > 1) {
-    const uint64_t mid = lo + ((hi - lo) >> 1);
-    if ((at(mid) >> psh) == pv) lo = mid; else hi = mid;
-  }
-  return hi;
-}
-
 __device__ __forceinline__ void set_pair(uint64_t* bm, uint32_t wpr, uint32_t P, uint32_t lv,
                                          uint32_t i, uint32_t j) {
   uint64_t* wp = bm + ((uint64_t)lv * P + i) * wpr + (j >> 6);
@@ -111,52 +77,29 @@ __device__ __forceinline__ void set_pair(uint64_t* bm, uint32_t wpr, uint32_t P,
   if (!(*wp & bit)) atomicOr((unsigned long long*)wp, (unsigned long long)bit);
 }
 
-// run-table entry: id | point << 32 | write << 44 | multi << 45 | sub << 47
-constexpr int RT_PT = 32, RT_W = 44, RT_MULTI = 45, RT_SUB = 47;
-
-__device__ __forceinline__ uint64_t block_excl_scan256_u64(uint64_t v, uint64_t* sm,
-                                                          uint64_t* total) {
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  uint64_t inc = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    uint64_t y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
-  }
-  if (lane == 63) sm[w] = inc;
-  __syncthreads();
-  uint64_t pre = 0, tot = 0;
-  for (int q = 0; q < CONF_BLOCK / 64; q++) {
-    if (q < w) pre += sm[q];
-    tot += sm[q];
-  }
-  __syncthreads();
-  *total = tot;
-  return pre + inc - v;
-}
-
+// Racing partners over the run log.  A sub-segment (one location, one
+// interval) is a contiguous stretch of runs; each run looks at the runs after
+// it in its sub-segment.  Tiles of runs plus a lookahead are staged in LDS,
+// reads past the staged window go to global memory.
 __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict__ jobs,
                                                           const ConfSeg* __restrict__ segs,
                                                           int nseg, uint32_t n_tiles,
                                                           uint32_t tiles_per_wg, int all_pairs) {
-  __shared__ uint64_t s_rec[CONF_WIN];        // records of the tile and the lookahead
-  __shared__ uint64_t s_info[CONF_WIN];       // run table
-  __shared__ uint16_t s_rstart[CONF_WIN + 1]; // run start positions in the window
-  __shared__ uint64_t s_sm[CONF_BLOCK / 64];
-  __shared__ uint64_t s_prev;
-  extern __shared__ uint32_t s_dyn[];         // [P] (interval << 1) | write, [P] first partner
+  __shared__ uint64_t s_run[CONF_WIN];
+  extern __shared__ uint32_t s_dyn[];        // [P] interval of each point, [P] first partner
   const int tid = threadIdx.x;
   const uint32_t t0 = blockIdx.x * tiles_per_wg;
   uint32_t t1 = t0 + tiles_per_wg;
   if (t1 > n_tiles) t1 = n_tiles;
   int cur = -1;
   bool live = false;
-  uint32_t* s_pt = s_dyn;
-  uint32_t* s_minj = s_dyn;   // placed after s_pt once P is known
+  uint32_t* s_iv = s_dyn;
+  uint32_t* s_minj = s_dyn;   // placed after s_iv once P is known
   for (uint32_t tile = t0; tile < t1; tile++) {
-    int lo = 0, hi = nseg - 1;   // largest segment with tile_beg <= tile
+    int lo = 0, hi = nseg - 1;   // largest segment with ctile_beg <= tile
     while (lo < hi) {
       int mid = (lo + hi + 1) >> 1;
-      if (segs[mid].tile_beg <= tile) lo = mid; else hi = mid - 1;
+      if (segs[mid].ctile_beg <= tile) lo = mid; else hi = mid - 1;
     }
     if (lo != cur) {
       if (cur >= 0 && live && !all_pairs) {
@@ -174,7 +117,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
       if (live) {
         const uint32_t* iv = J.ivl + (uint64_t)segs[cur].level * J.P;
         for (uint32_t i = tid; i < J.P; i += CONF_BLOCK) {
-          s_pt[i] = (iv[i] << 1) | ((J.pts[i].flags & PF_WRITE) ? 1u : 0u);
+          s_iv[i] = iv[i];
           s_minj[i] = NONE32;
         }
       }
@@ -182,150 +125,40 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
     }
     if (!live) continue;
     const ConfSeg sg = segs[cur];
+    const uint64_t n = sg.n_runs_at ? *sg.n_runs_at : sg.n_runs;
+    const uint64_t base = (uint64_t)(tile - sg.ctile_beg) * CONF_TILE;
+    if (base >= n) continue;   // run counts are known on the device only
     const Job& J = jobs[sg.job];
     const uint32_t P = J.P;
-    const uint64_t* __restrict__ log = sg.log;
-    const uint64_t n = sg.n;
-    const uint64_t base = (uint64_t)(tile - sg.tile_beg) * CONF_TILE;
+    const uint64_t* __restrict__ runs = sg.runs;
     const uint32_t wlen = (uint32_t)((n - base) < CONF_WIN ? (n - base) : CONF_WIN);
-    const bool at_end = base + wlen == n;
-    const uint32_t tb = J.tbits, bb = J.bbits, pb = J.pbits;
-    const uint32_t pmask = (1u << pb) - 1u;
-    // same-block view: location = (array, word, block), id = thread
-    // cross-block view: location = (array, word), id = block
-    const int psh = sg.level == 0 ? (int)tb : (int)(bb + tb);
-    const int lsh = psh + (int)pb;
-    const int ish = sg.level == 0 ? 0 : (int)tb;
-    const uint64_t imask = sg.level == 0 ? ((1ull << tb) - 1) : ((1ull << bb) - 1);
-    __syncthreads();
-    for (uint32_t q = tid; q < wlen; q += CONF_BLOCK) s_rec[q] = log[base + q];
-    if (tid == 0) s_prev = base > 0 ? log[base - 1] : 0;
-    __syncthreads();
-
-    // ---- 1. run heads and sub-segment starts (contiguous positions per thread)
-    constexpr uint32_t PER = CONF_WIN / CONF_BLOCK;
-    const uint32_t p0 = tid * PER;
-    uint32_t hmask = 0, smask = 0;
-    for (uint32_t q = 0; q < PER; q++) {
-      const uint32_t p = p0 + q;
-      if (p >= wlen) break;
-      const uint64_t v = s_rec[p];
-      const bool has_prev = p > 0 || base > 0;
-      if (!has_prev) { hmask |= 1u << q; smask |= 1u << q; continue; }
-      const uint64_t pr = p > 0 ? s_rec[p - 1] : s_prev;
-      if ((pr >> psh) == (v >> psh)) continue;
-      hmask |= 1u << q;
-      const uint32_t i = (uint32_t)(v >> psh) & pmask, ip = (uint32_t)(pr >> psh) & pmask;
-      if ((pr >> lsh) != (v >> lsh) || i >= P || ip >= P || (s_pt[i] >> 1) != (s_pt[ip] >> 1))
-        smask |= 1u << q;
-    }
-    uint64_t tot;
-    const uint64_t ex = block_excl_scan256_u64(((uint64_t)__popc(smask) << 32) | __popc(hmask),
-                                               s_sm, &tot);
-    const uint32_t n_runs = (uint32_t)tot;
-    uint32_t ri = (uint32_t)ex, sub = (uint32_t)(ex >> 32);
-    for (uint32_t q = 0; q < PER; q++) {
-      if (!((hmask >> q) & 1)) continue;
-      const uint32_t p = p0 + q;
-      sub += (smask >> q) & 1;
-      const uint64_t v = s_rec[p];
-      const uint32_t i = (uint32_t)(v >> psh) & pmask;
-      const uint64_t w = (i < P) ? (uint64_t)(s_pt[i] & 1) : 0;
-      s_rstart[ri] = (uint16_t)p;
-      s_info[ri] = ((v >> ish) & imask) | ((uint64_t)i << RT_PT) | (w << RT_W) |
-                   ((uint64_t)sub << RT_SUB);
-      ri++;
-    }
-    if (tid == 0) s_rstart[n_runs] = (uint16_t)wlen;
-    __syncthreads();
-
-    // ---- 2. multiplicity (two threads, or two blocks, in the run)
-    for (uint32_t r = tid; r < n_runs; r += CONF_BLOCK) {
-      const uint32_t st = s_rstart[r], en = s_rstart[r + 1];
-      const bool open = r + 1 == n_runs && !at_end;
-      const uint64_t first = s_rec[st];
-      bool multi;
-      if (sg.level == 0) {
-        multi = en - st >= 2;
-        if (!multi && open) multi = (log[base + wlen] >> psh) == (first >> psh);
-      } else {
-        const uint64_t oid = (first >> ish) & imask;
-        multi = ((s_rec[en - 1] >> ish) & imask) != oid;
-        if (!multi && open) {
-          const Win at{log, s_rec, base, wlen};
-          const uint64_t e = run_end(at, n, base + en - 1, first >> psh, psh);
-          multi = ((log[e - 1] >> ish) & imask) != oid;
-        }
-      }
-      if (multi) s_info[r] |= 1ull << RT_MULTI;
-    }
-    __syncthreads();
-
-    // ---- 3. partners of the runs that start in this tile
     const uint32_t own = wlen < CONF_TILE ? wlen : CONF_TILE;
-    for (uint32_t r = tid; r < n_runs; r += CONF_BLOCK) {
-      const uint32_t st = s_rstart[r];
-      if (st >= own) break;
-      const uint64_t ei = s_info[r];
-      const uint32_t i = (uint32_t)(ei >> RT_PT) & 0xFFFu;
+    __syncthreads();
+    for (uint32_t q = tid; q < wlen; q += CONF_BLOCK) s_run[q] = runs[base + q];
+    __syncthreads();
+    for (uint32_t r = tid; r < own; r += CONF_BLOCK) {
+      const uint64_t ei = s_run[r];
+      const uint32_t i = (uint32_t)(ei >> RUN_PT) & 0xFFFu;
       if (i >= P) continue;
-      const bool wi = (ei >> RT_W) & 1, mi = (ei >> RT_MULTI) & 1;
-      const uint32_t idi = (uint32_t)ei, subi = (uint32_t)(ei >> RT_SUB);
+      const bool wi = (ei >> RUN_W) & 1, mi = (ei >> RUN_MULTI) & 1;
+      const uint32_t idi = (uint32_t)ei, iv = s_iv[i];
       if (wi && mi) {
         if (all_pairs) set_pair(J.bitmap, J.wpr, P, sg.level, i, i);
         else { atomicMin(&s_minj[i], i); continue; }
       }
-      bool done = false;
-      uint32_t rj = r + 1;
-      for (; rj < n_runs; rj++) {
-        const uint64_t ej = s_info[rj];
-        if ((uint32_t)(ej >> RT_SUB) != subi) { done = true; break; }
-        const uint32_t j = (uint32_t)(ej >> RT_PT) & 0xFFFu;
-        if (j >= P) continue;
-        if ((wi || ((ej >> RT_W) & 1)) && (mi || ((ej >> RT_MULTI) & 1) || idi != (uint32_t)ej)) {
+      for (uint64_t q = base + r + 1; q < n; q++) {
+        const uint64_t ej = (q - base) < wlen ? s_run[q - base] : runs[q];
+        if ((ej >> RUN_LOC) & 1) break;             // next location
+        const uint32_t j = (uint32_t)(ej >> RUN_PT) & 0xFFFu;
+        if (j >= P || s_iv[j] != iv) break;          // next interval
+        if ((wi || ((ej >> RUN_W) & 1)) && (mi || ((ej >> RUN_MULTI) & 1) || idi != (uint32_t)ej)) {
           if (all_pairs) {
             set_pair(J.bitmap, J.wpr, P, sg.level, i, j);
           } else {
             atomicMin(&s_minj[i], j);
-            done = true;
             break;
           }
         }
-      }
-      if (done || at_end) continue;
-      // the sub-segment may continue past the window: walk on in global memory
-      const Win at{log, s_rec, base, wlen};
-      const uint64_t v = s_rec[st];
-      const uint64_t loc = v >> lsh;
-      const uint32_t iv = s_pt[i] >> 1;
-      uint64_t q;
-      {
-        const uint32_t lr = n_runs - 1;   // last run of the window, maybe open
-        const uint64_t lv = s_rec[s_rstart[lr]];
-        q = run_end(at, n, base + s_rstart[lr], lv >> psh, psh);
-      }
-      while (q < n) {
-        const uint64_t vq = at(q);
-        if ((vq >> lsh) != loc) break;
-        const uint64_t pq = vq >> psh;
-        const uint32_t j = (uint32_t)pq & pmask;
-        if (j >= P) break;
-        const uint32_t jpt = s_pt[j];
-        if ((jpt >> 1) != iv) break;
-        const uint64_t eq = run_end(at, n, q, pq, psh);
-        if (wi || (jpt & 1)) {
-          const uint64_t jid = (vq >> ish) & imask;
-          const bool jmulti = sg.level == 0 ? (eq - q >= 2) : (((at(eq - 1) >> ish) & imask) != jid);
-          if (mi || jmulti || (uint64_t)idi != jid) {
-            if (all_pairs) {
-              set_pair(J.bitmap, J.wpr, P, sg.level, i, j);
-            } else {
-              atomicMin(&s_minj[i], j);
-              break;
-            }
-          }
-        }
-        q = eq;
       }
     }
   }

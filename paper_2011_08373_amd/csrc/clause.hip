@@ -187,6 +187,24 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
   if (tid == 0) st->n_phi = total;
 }
 
+// Number of jobs still running, for the host's per-round check (4 bytes).
+__global__ __launch_bounds__(256) void count_active_kernel(const Job* __restrict__ jobs,
+                                                           uint32_t njobs, uint32_t* out) {
+  __shared__ uint32_t s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  uint32_t c = 0;
+  for (uint32_t j = threadIdx.x; j < njobs; j += 256) c += jobs[j].st->state == ST_RUN;
+  if (c) atomicAdd(&s_n, c);
+  __syncthreads();
+  if (threadIdx.x == 0) *out = s_n;
+}
+
+hipError_t launch_count_active(const Job* jobs, uint32_t njobs, uint32_t* out, hipStream_t s) {
+  count_active_kernel<<<1, 256, 0, s>>>(jobs, njobs, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_clause(const Job* jobs, uint32_t njobs, int learn, hipStream_t s) {
   if (njobs == 0) return hipSuccess;
   clause_kernel<<<njobs, CL_BLOCK, 0, s>>>(jobs, learn);

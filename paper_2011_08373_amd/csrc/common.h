@@ -104,13 +104,28 @@ struct GenItem {
   uint32_t seg, pad;
 };
 
-// conflict-scan segment: one log of one job
+// one log of one job: its sorted records and its run log
 struct ConfSeg {
-  const uint64_t* log;
-  uint64_t n;
-  uint32_t job, level;
-  uint32_t tile_beg, pad;
+  const uint64_t* log;   // sorted access records
+  uint64_t n;            // records
+  uint64_t* runs;        // run log: one entry per (location, point) group
+  uint64_t n_runs;       // written on the device by runs_scan_kernel
+  uint32_t job, level;   // level 0 same-block view, 1 cross-block view
+  uint32_t btile_beg;    // first record tile (run-log build)
+  uint32_t ctile_beg;    // first run tile (conflict scan)
+  const uint64_t* n_runs_at;  // where the run count lives when this entry is a copy
 };
+
+// Run-log entry (64 bits): the records of one point at one location, in
+// location order and, inside a location, in program order.
+//   bits  0..31  id of the first record (thread in the same-block view,
+//                block in the cross-block view)
+//   bits 32..43  point
+//   bit  44      the point writes
+//   bit  45      multi: the run holds two or more threads (same-block view)
+//                or two or more blocks (cross-block view)
+//   bit  46      first run of its location
+constexpr int RUN_PT = 32, RUN_W = 44, RUN_MULTI = 45, RUN_LOC = 46;
 
 __device__ __forceinline__ uint32_t word_of(const DPoint& p, uint32_t t, uint32_t k) {
   int64_t v = (int64_t)p.a * (int64_t)t + (int64_t)p.b * (int64_t)k + (int64_t)p.c;

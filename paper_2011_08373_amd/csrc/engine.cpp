@@ -25,6 +25,8 @@ struct Layout {
   std::vector<size_t> o_pts, o_bany, o_bgrid, o_w, o_cpre, o_gpre, o_phi0j;
   size_t o_chunks = 0;
   size_t o_recA = 0, o_recB = 0, o_cnt = 0, o_tot = 0, o_off = 0, o_err = 0;
+  size_t o_rcnt = 0, o_roff = 0;
+  uint32_t n_btiles = 0;
   std::vector<size_t> o_ivl, o_minj, o_phi, o_scratch, o_traj, o_bitmap, o_pairs, o_ptotal;
   std::vector<uint32_t> phi_cap, scratch_cap;
   uint64_t n_rec = 0;
@@ -49,8 +51,8 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   L.rb = (uint32_t)pick_digit_bits(key_bits);
   L.passes = (uint32_t)sort_passes(key_bits, (int)L.rb);
   uint64_t rec = 0;
-  uint32_t ctiles = 0;
-  const uint32_t ctile = conf_tile_size();
+  uint32_t ctiles = 0, btiles = 0;
+  const uint32_t ctile = conf_tile_size(), btile = runs_tile_size();
   for (size_t j = 0; j < N; j++) {
     const Plan& p = *jobs[j].plan;
     for (int v = 0; v < 2; v++) {
@@ -64,11 +66,13 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
       L.seg_job.push_back((uint32_t)j);
       L.seg_level.push_back((uint32_t)v);
       rec += n;
-      ctiles += (uint32_t)((n + ctile - 1) / ctile);
+      ctiles += (uint32_t)((n + ctile - 1) / ctile);   // runs <= records
+      btiles += (uint32_t)((n + btile - 1) / btile);
     }
   }
   L.n_rec = rec;
   L.n_conf_tiles = ctiles;
+  L.n_btiles = btiles;
   // sort chunks (= generation items): whole sort tiles, at most ~64K chunks
   const uint64_t tile = sort_tile_size();
   uint64_t chunk = std::max<uint64_t>(2 * tile, (rec + 65535) / 65536);
@@ -116,7 +120,9 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   L.meta = off;
   // ---- device-only region
   L.o_recA = off; off = up(off + L.n_rec * sizeof(uint64_t));
-  L.o_recB = off; off = up(off + (L.passes ? L.n_rec : 0) * sizeof(uint64_t));
+  L.o_recB = off; off = up(off + L.n_rec * sizeof(uint64_t));   // sort ping-pong, then run log
+  L.o_rcnt = off; off = up(off + (size_t)L.n_btiles * sizeof(uint32_t));
+  L.o_roff = off; off = up(off + (size_t)L.n_btiles * sizeof(uint64_t));
   L.o_cnt = off; off = up(off + L.chunks.size() * (size_t)R * sizeof(uint32_t));
   L.o_tot = off; off = up(off + L.ssegs.size() * (size_t)R * sizeof(uint64_t));
   L.o_off = off; off = up(off + L.chunks.size() * (size_t)R * sizeof(uint64_t));
@@ -151,8 +157,10 @@ struct Timer {
   std::vector<int> tag;
   hipStream_t s;
   bool ok = true;
-  explicit Timer(hipStream_t st) : s(st) {}
+  bool on = true;
+  explicit Timer(hipStream_t st, bool enabled = true) : s(st), on(enabled) {}
   void mark(int t) {
+    if (!on) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) { ok = false; return; }
     if (hipEventRecord(e, s) != hipSuccess) ok = false;
@@ -163,7 +171,7 @@ struct Timer {
 };
 
 // phase tags for the stats
-enum { T_START = 0, T_GEN, T_SORTPASS, T_SORT, T_CHECK, T_CLAUSE, T_SOLVE, T_END };
+enum { T_START = 0, T_GEN, T_SORTPASS, T_SORT, T_RUNS, T_CHECK, T_CLAUSE, T_SOLVE, T_END };
 
 }  // namespace
 
@@ -178,16 +186,14 @@ size_t engine_workspace(const std::vector<JobInput>& jobs, const EngineOpts& o) 
     if ((x) != hipSuccess) return RP_ERR_DEVICE; \
   } while (0)
 
-int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws, size_t ws_bytes,
-               hipStream_t s, std::vector<JobResult>& res, rp_stats* stats) {
-  Layout L;
-  plan_layout(jobs, o, L);
-  if (ws_bytes < L.total) return RP_ERR_WORKSPACE;
-  if (!ws && L.total) return RP_ERR_WORKSPACE;
+namespace {
+
+// Host staging, upload, record generation, sort and run-log build for the
+// jobs laid out by L in the device buffer d (all enqueued on s, no sync).
+int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const Layout& L,
+                 uint8_t* d, std::vector<uint8_t>& h, hipStream_t s, Timer& tm) {
   const size_t N = jobs.size();
-  uint8_t* d = (uint8_t*)ws;
-  // ---- host staging of the meta region
-  std::vector<uint8_t> h(L.meta, 0);
+  h.assign(L.meta, 0);
   Job* hj = (Job*)(h.data() + L.o_jobs);
   JobState* hs = (JobState*)(h.data() + L.o_states);
   for (size_t j = 0; j < N; j++) {
@@ -235,28 +241,30 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   std::memcpy(h.data() + L.o_items, L.items.data(), L.items.size() * sizeof(GenItem));
   std::memcpy(h.data() + L.o_chunks, L.chunks.data(), L.chunks.size() * sizeof(SortChunk));
   std::memcpy(h.data() + L.o_ssegs, L.ssegs.data(), L.ssegs.size() * sizeof(SortSeg));
-  // sorted logs end in buffer A after an even number of passes, else B
+  // sorted logs end in buffer A after an even number of passes, else B; the
+  // run log goes to the other buffer
   uint8_t* sorted = d + ((L.passes % 2 == 0) ? L.o_recA : L.o_recB);
+  uint8_t* runbuf = d + ((L.passes % 2 == 0) ? L.o_recB : L.o_recA);
   ConfSeg* hc = (ConfSeg*)(h.data() + L.o_csegs);
-  for (size_t q = 0; q < L.ssegs.size(); q++) {
-    ConfSeg c{};
-    c.log = (const uint64_t*)sorted + L.ssegs[q].beg;
-    c.n = L.ssegs[q].end - L.ssegs[q].beg;
-    c.job = L.seg_job[q];
-    c.level = L.seg_level[q];
-    c.tile_beg = 0;
-    hc[q] = c;
-    hj[c.job].log[c.level] = c.log;
-  }
   {
-    uint32_t t = 0;
-    const uint32_t ct = conf_tile_size();
+    uint32_t bt = 0, ct = 0;
+    const uint32_t btile = runs_tile_size(), ctile = conf_tile_size();
     for (size_t q = 0; q < L.ssegs.size(); q++) {
-      hc[q].tile_beg = t;
-      t += (uint32_t)((hc[q].n + ct - 1) / ct);
+      ConfSeg c{};
+      c.log = (const uint64_t*)sorted + L.ssegs[q].beg;
+      c.n = L.ssegs[q].end - L.ssegs[q].beg;
+      c.runs = (uint64_t*)runbuf + L.ssegs[q].beg;
+      c.n_runs = 0;
+      c.job = L.seg_job[q];
+      c.level = L.seg_level[q];
+      c.btile_beg = bt;
+      c.ctile_beg = ct;
+      bt += (uint32_t)((c.n + btile - 1) / btile);
+      ct += (uint32_t)((c.n + ctile - 1) / ctile);
+      hc[q] = c;
+      hj[c.job].log[c.level] = c.log;
     }
   }
-  Timer tm(s);
   tm.mark(T_START);
   HIPCHK(hipMemcpyAsync(d, h.data(), L.meta, hipMemcpyHostToDevice, s));
   for (size_t j = 0; j < N; j++)
@@ -287,8 +295,82 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     tm.mark(T_SORT);
   }
   tm.mark(T_SORT);
+  // ---- run logs (once per job)
+  ConfSeg* dcs = (ConfSeg*)(d + L.o_csegs);
+  HIPCHK(launch_runs_build(djobs, dcs, (int)L.ssegs.size(), L.n_btiles,
+                           (uint32_t*)(d + L.o_rcnt), (uint64_t*)(d + L.o_roff), s));
+  return RP_OK;
+}
+
+}  // namespace
+
+static uint32_t conf_grid_size() {
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  return (uint32_t)ncu * 4;
+}
+
+size_t engine_job_bytes(const JobInput& job) {
+  EngineOpts o;
+  o.op = OP_REPAIR;
+  std::vector<JobInput> v{job};
+  return engine_workspace(v, o);
+}
+
+int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStream_t s,
+                       PreparedJob& out, std::vector<uint8_t>& staging) {
+  EngineOpts o;
+  o.op = OP_REPAIR;
+  std::vector<JobInput> v{job};
+  Layout L;
+  plan_layout(v, o, L);
+  if (bytes < L.total || !region) return RP_ERR_WORKSPACE;
+  uint8_t* d = (uint8_t*)region;
+  Timer tm(s, false);
+  const int rc = prepare_jobs(v, o, L, d, staging, s, tm);
+  if (rc != RP_OK) return rc;
+  HIPCHK(launch_solve((const Job*)(d + L.o_jobs), 1, s));
+  std::memcpy(&out.job, staging.data() + L.o_jobs, sizeof(Job));
+  out.nseg = (uint32_t)L.ssegs.size();
+  const ConfSeg* hc = (const ConfSeg*)(staging.data() + L.o_csegs);
+  for (uint32_t q = 0; q < out.nseg; q++) {
+    out.segs[q] = hc[q];
+    out.segs[q].n_runs_at = &((const ConfSeg*)(d + L.o_csegs))[q].n_runs;
+    out.n_rec[q] = hc[q].n;
+  }
+  return RP_OK;
+}
+
+int engine_round(const Job* djobs, uint32_t njobs, const ConfSeg* dcs, uint32_t nseg,
+                 uint32_t n_conf_tiles, uint32_t maxP, uint32_t* dactive, hipStream_t s) {
+  HIPCHK(launch_ivl(djobs, njobs, 0, s));
+  HIPCHK(launch_conf(djobs, dcs, (int)nseg, n_conf_tiles, conf_grid_size(), maxP, 0, s));
+  HIPCHK(launch_clause(djobs, njobs, 1, s));
+  HIPCHK(launch_solve(djobs, njobs, s));
+  HIPCHK(launch_count_active(djobs, njobs, dactive, s));
+  return RP_OK;
+}
+
+int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws, size_t ws_bytes,
+               hipStream_t s, std::vector<JobResult>& res, rp_stats* stats) {
+  Layout L;
+  plan_layout(jobs, o, L);
+  if (ws_bytes < L.total) return RP_ERR_WORKSPACE;
+  if (!ws && L.total) return RP_ERR_WORKSPACE;
+  const size_t N = jobs.size();
+  uint8_t* d = (uint8_t*)ws;
+  std::vector<uint8_t> h;
+  Timer tm(s);
+  {
+    const int rc = prepare_jobs(jobs, o, L, d, h, s, tm);
+    if (rc != RP_OK) return rc;
+  }
+  const Job* djobs = (const Job*)(d + L.o_jobs);
+  uint32_t* derr = (uint32_t*)(d + L.o_err);
+  ConfSeg* dcs = (ConfSeg*)(d + L.o_csegs);
+  tm.mark(T_RUNS);
   // ---- per-round kernels
-  const ConfSeg* dcs = (const ConfSeg*)(d + L.o_csegs);
   const int nseg = (int)L.ssegs.size();
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -312,6 +394,12 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   } else if (o.op == OP_SOLVE) {
     HIPCHK(launch_solve(djobs, (uint32_t)N, s));
     tm.mark(T_SOLVE);
+  } else if (o.op == OP_FIRST) {
+    HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
+    HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s));
+    conf_launches++;
+    scanned += L.n_rec;
+    tm.mark(T_CHECK);
   } else if (o.op == OP_CLAUSES) {
     HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
     HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s));
@@ -321,33 +409,62 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));
     tm.mark(T_CLAUSE);
   } else {
+    uint32_t* dactive = (uint32_t*)(d + L.o_err) + 8;
     HIPCHK(launch_solve(djobs, (uint32_t)N, s));
     tm.mark(T_SOLVE);
-    for (;;) {
-      HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
-      HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s));
-      conf_launches++;
-      tm.mark(T_CHECK);
-      HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));
-      tm.mark(T_CLAUSE);
-      HIPCHK(launch_solve(djobs, (uint32_t)N, s));
-      tm.mark(T_SOLVE);
-      HIPCHK(hipMemcpyAsync(hst.data(), d + L.o_states, N * sizeof(JobState),
-                            hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      rounds_run++;
-      bool any = false;
-      for (size_t j = 0; j < N; j++) {
-        if (hst[j].state == ST_RUN) any = true;
+    auto round = [&]() -> hipError_t {
+      hipError_t e;
+      if ((e = launch_ivl(djobs, (uint32_t)N, 0, s)) != hipSuccess) return e;
+      if ((e = launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s)) != hipSuccess)
+        return e;
+      if ((e = launch_clause(djobs, (uint32_t)N, 1, s)) != hipSuccess) return e;
+      if ((e = launch_solve(djobs, (uint32_t)N, s)) != hipSuccess) return e;
+      return launch_count_active(djobs, (uint32_t)N, dactive, s);
+    };
+    // one captured graph per round, replayed until every job has a verdict
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (o.use_graph && s != nullptr) {
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        const hipError_t e = round();
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (e != hipSuccess || ec != hipSuccess ||
+            hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
+          graph = nullptr;
+          gexec = nullptr;
+          (void)hipGetLastError();
+        }
       }
-      // records scanned this round: logs of jobs that were verified
-      for (size_t q = 0; q < L.ssegs.size(); q++) {
-        const JobState& st = hst[L.seg_job[q]];
-        if (st.rounds >= rounds_run) scanned += L.ssegs[q].end - L.ssegs[q].beg;
-      }
-      if (!any) break;
-      if (rounds_run > 100000) return RP_ERR_DEVICE;
     }
+    uint32_t active = 1;
+    int rc_loop = RP_OK;
+    while (active) {
+      if (gexec) {
+        if (hipGraphLaunch(gexec, s) != hipSuccess) { rc_loop = RP_ERR_DEVICE; break; }
+        tm.mark(T_CHECK);
+      } else {
+        HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
+        HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s));
+        tm.mark(T_CHECK);
+        HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));
+        tm.mark(T_CLAUSE);
+        HIPCHK(launch_solve(djobs, (uint32_t)N, s));
+        tm.mark(T_SOLVE);
+        HIPCHK(launch_count_active(djobs, (uint32_t)N, dactive, s));
+      }
+      conf_launches++;
+      if (hipMemcpyAsync(&active, dactive, sizeof(active), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        rc_loop = RP_ERR_DEVICE;
+        break;
+      }
+      rounds_run++;
+      if (rounds_run > 100000) { rc_loop = RP_ERR_DEVICE; break; }
+    }
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc_loop != RP_OK) return rc_loop;
   }
   tm.mark(T_END);
   HIPCHK(hipMemcpyAsync(hst.data(), d + L.o_states, N * sizeof(JobState), hipMemcpyDeviceToHost, s));
@@ -355,12 +472,23 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   HIPCHK(hipMemcpyAsync(herr, derr, sizeof(herr), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (herr[0]) return RP_ERR_DEVICE;
+  if (o.op == OP_REPAIR) {
+    scanned = 0;
+    for (size_t q = 0; q < L.ssegs.size(); q++)
+      scanned += (uint64_t)hst[L.seg_job[q]].rounds * (L.ssegs[q].end - L.ssegs[q].beg);
+  }
   res.assign(N, JobResult{});
   for (size_t j = 0; j < N; j++) {
     res[j].st = hst[j];
     if (hst[j].state == ST_ERROR) {
       return hst[j].err == ERR_PHI_CAP || hst[j].err == ERR_SCRATCH ? RP_ERR_CAPACITY
                                                                    : RP_ERR_DEVICE;
+    }
+    if (o.op == OP_FIRST) {
+      res[j].first.resize(2 * (size_t)jobs[j].plan->P);
+      if (!res[j].first.empty())
+        HIPCHK(hipMemcpyAsync(res[j].first.data(), d + L.o_minj[j],
+                              res[j].first.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     }
     if (o.op == OP_CLAUSES) {
       res[j].phi.resize(hst[j].n_phi);
@@ -404,6 +532,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
             stats->sort_launches++;
           }
           break;
+        case T_RUNS: stats->ms_runs += ms; break;
         case T_CHECK: stats->ms_check += ms; break;
         case T_CLAUSE: stats->ms_clause += ms; break;
         case T_SOLVE: stats->ms_solve += ms; break;

@@ -7,6 +7,7 @@ namespace rp {
 
 uint32_t sort_tile_size();
 uint32_t conf_tile_size();
+uint32_t runs_tile_size();
 
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,
                       const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int passes,
@@ -18,11 +19,14 @@ hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uin
 hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
                                const SortChunk* chunks, uint32_t nchunks, int pass,
                                const uint64_t* off, uint32_t* err, hipStream_t s);
+hipError_t launch_runs_build(const Job* jobs, ConfSeg* segs, int nseg, uint32_t n_btiles,
+                             uint32_t* cnt, uint64_t* off, hipStream_t s);
 hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int with_bitmap, hipStream_t s);
 hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t n_tiles,
                        uint32_t grid, uint32_t max_points, int all_pairs, hipStream_t s);
 hipError_t launch_pairs(const Job* job, rp_pair* out, uint64_t* total, hipStream_t s);
 hipError_t launch_clause(const Job* jobs, uint32_t njobs, int learn, hipStream_t s);
 hipError_t launch_solve(const Job* jobs, uint32_t njobs, hipStream_t s);
+hipError_t launch_count_active(const Job* jobs, uint32_t njobs, uint32_t* out, hipStream_t s);
 
 }  // namespace rp

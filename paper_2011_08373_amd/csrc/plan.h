@@ -23,7 +23,7 @@ void make_plan(const rp_kernel* k, Plan& pl);
 int pick_digit_bits(uint32_t key_bits);
 int sort_passes(uint32_t key_bits, int rb);
 
-enum Op { OP_CHECK = 0, OP_CLAUSES = 1, OP_REPAIR = 2, OP_SOLVE = 3 };
+enum Op { OP_CHECK = 0, OP_CLAUSES = 1, OP_REPAIR = 2, OP_SOLVE = 3, OP_FIRST = 4 };
 
 struct JobInput {
   const Plan* plan;
@@ -36,6 +36,7 @@ struct JobResult {
   JobState st;
   std::vector<rp_clause> phi;       // clauses mode: reduced learned clauses
   std::vector<rp_pair> pairs;       // check mode
+  std::vector<uint32_t> first;      // first-partner mode: [2][P]
   uint64_t n_pairs = 0;
   std::vector<uint64_t> traj;
 };
@@ -45,10 +46,29 @@ struct EngineOpts {
   uint64_t pair_cap = 0;            // check: caller's capacity
   uint32_t traj_cap = 0;
   bool want_pairs = true;
+  bool use_graph = true;            // capture each round in a hipGraph (non-null stream)
 };
 
 // Bytes of workspace the engine needs for these jobs.
 size_t engine_workspace(const std::vector<JobInput>& jobs, const EngineOpts& o);
+
+// One job prepared in its own device region (serving): host copies of its
+// device tables, with absolute device pointers.
+struct PreparedJob {
+  Job job;
+  ConfSeg segs[2];
+  uint32_t nseg = 0;
+  uint64_t n_rec[2] = {0, 0};
+};
+size_t engine_job_bytes(const JobInput& job);
+// Enqueues upload, record generation, sort, run log and the first Solve of
+// one job into `region`; staging must stay alive until the stream is synced.
+int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStream_t s,
+                       PreparedJob& out, std::vector<uint8_t>& staging);
+// Enqueues one round (Verify, GenerateClause, Solve, active count) over
+// device tables of njobs jobs and nseg logs.
+int engine_round(const Job* djobs, uint32_t njobs, const ConfSeg* dcs, uint32_t nseg,
+                 uint32_t n_conf_tiles, uint32_t maxP, uint32_t* dactive, hipStream_t s);
 
 // Runs the op over all jobs; returns RP_OK or an error status.
 int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws, size_t ws_bytes,

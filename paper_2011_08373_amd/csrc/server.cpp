@@ -1,0 +1,335 @@
+// Serving: continuous batching of repair jobs over a caller-owned device arena.
+//
+// Jobs are submitted at any time (the server copies their descriptors).  Each
+// rp_server_step():
+//   1. admits pending jobs in arrival order while the head job's footprint
+//      fits a free range of the arena (first fit) and a resident slot is
+//      free; an admitted job is prepared in its own range (upload, records,
+//      sort, run log, first Solve) -- its logs and clause set then stay
+//      resident until it finishes;
+//   2. runs one round of Alg. 1 (Verify, GenerateClause, Solve) over every
+//      resident job at once, newly admitted ones included;
+//   3. retires the jobs that reached a verdict, frees their ranges and
+//      stamps their latency (submission to verdict).
+// Each job's result is the one rp_repair gives for it alone: rounds only
+// batch independent jobs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "common.h"
+#include "launch.h"
+#include "plan.h"
+
+namespace rp {
+
+namespace {
+
+constexpr size_t SALIGN = 256;
+size_t sup(size_t x) { return (x + SALIGN - 1) / SALIGN * SALIGN; }
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct OwnedKernel {   // deep copy of a descriptor
+  std::vector<rp_array> arrays;
+  std::vector<rp_guard> guards;
+  std::vector<rp_point> points;
+  std::vector<rp_slot> slots;
+  rp_kernel k;
+  void take(const rp_kernel* src) {
+    arrays.assign(src->arrays, src->arrays + src->n_arrays);
+    guards.assign(src->guards, src->guards + src->n_guards);
+    points.assign(src->points, src->points + src->n_points);
+    slots.assign(src->slots, src->slots + src->n_slots);
+    k = *src;
+    k.arrays = arrays.data();
+    k.guards = guards.data();
+    k.points = points.data();
+    k.slots = slots.data();
+  }
+};
+
+struct SJob {
+  uint64_t id = 0;
+  OwnedKernel desc;
+  Plan plan;
+  JobInput input;
+  size_t bytes = 0, off = 0;
+  PreparedJob prep;
+  double t_submit = 0;
+};
+
+// first-fit allocator over [0, size)
+struct Arena {
+  std::map<size_t, size_t> free_;   // offset -> length
+  void init(size_t base, size_t size) { free_.clear(); if (size) free_[base] = size; }
+  bool alloc(size_t n, size_t& off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        off = it->first;
+        const size_t rest = it->second - n;
+        free_.erase(it);
+        if (rest) free_[off + n] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+__global__ void gather_states_kernel(const Job* jobs, uint32_t n, JobState* out) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) out[j] = *jobs[j].st;
+}
+
+}  // namespace
+
+struct Server {
+  uint8_t* arena = nullptr;
+  size_t arena_bytes = 0;
+  rp_repair_opts opts{};
+  hipStream_t s = nullptr;
+  uint32_t max_resident = 0;
+  // fixed tables at the start of the arena
+  Job* d_jobs = nullptr;
+  ConfSeg* d_segs = nullptr;
+  JobState* d_states = nullptr;
+  uint32_t* d_active = nullptr;
+  size_t tables = 0;
+  Arena alloc;
+  std::deque<std::unique_ptr<SJob>> pending;
+  std::vector<std::unique_ptr<SJob>> resident;
+  struct Done { uint64_t id; rp_repair_out out; double latency; };
+  std::deque<Done> done;
+  std::vector<std::vector<uint8_t>> staging;
+  std::vector<Job> h_jobs;
+  std::vector<ConfSeg> h_segs;
+  std::vector<JobState> h_states;
+  uint64_t rounds = 0;
+};
+
+}  // namespace rp
+
+using namespace rp;
+
+static void fill_out(const SJob& j, const JobState& st, rp_repair_out& out) {
+  std::memset(&out, 0, sizeof(out));
+  out.rounds = st.rounds;
+  out.n_clauses = st.n_phi;
+  if (st.state == ST_SAFE) {
+    out.status = RP_OK;
+    out.assign = st.x;
+    out.weight = st.weight;
+    out.added = st.x & ~j.plan.pre_slots;
+    out.removed = j.plan.pre_slots & ~st.x;
+  } else if (st.state == ST_UNSAT) {
+    out.status = RP_UNSAT;
+  } else if (st.state == ST_ROUNDS) {
+    out.status = RP_ERR_ROUNDS;
+  } else if (st.state == ST_ERROR) {
+    out.status = (st.err == ERR_PHI_CAP || st.err == ERR_SCRATCH) ? RP_ERR_CAPACITY : RP_ERR_DEVICE;
+  } else {
+    out.status = RP_ERR_DEVICE;
+  }
+}
+
+static std::vector<rp_clause> server_units(const Plan& pl, const rp_repair_opts& o) {
+  std::vector<rp_clause> u;
+  for (uint32_t s = 0; s < pl.S; s++) {
+    const uint64_t b = 1ull << s;
+    if (!o.grid && (pl.grid_slots & b)) u.push_back(rp_clause{0, b});
+    if (!o.inspect && (pl.pre_slots & b)) u.push_back(rp_clause{b, 0});
+  }
+  std::sort(u.begin(), u.end(), [](const rp_clause& a, const rp_clause& b) {
+    return a.pos != b.pos ? a.pos < b.pos : a.neg < b.neg;
+  });
+  return u;
+}
+
+extern "C" {
+
+size_t rp_server_tables_bytes(uint32_t max_resident) {
+  return sup(max_resident * sizeof(Job)) + sup(2 * max_resident * sizeof(ConfSeg)) +
+         sup(max_resident * sizeof(JobState)) + SALIGN;
+}
+
+size_t rp_server_job_bytes(const rp_kernel* k) {
+  if (validate_kernel(k) != RP_OK) return 0;
+  Plan pl;
+  make_plan(k, pl);
+  JobInput ji;
+  ji.plan = &pl;
+  ji.phi0.assign(2 * pl.S, rp_clause{0, 0});
+  return sup(engine_job_bytes(ji));
+}
+
+rp_status rp_server_create(void* arena, size_t arena_bytes, const rp_repair_opts* opts,
+                           uint32_t max_resident, void* stream, void** out) {
+  if (!arena || !out || max_resident == 0 || max_resident > (1u << 16)) return RP_ERR_INVALID;
+  const rp_repair_opts op = opts ? *opts : rp_repair_opts{0, 1, 1, 0, 0};
+  if (op.policy > 1) return RP_ERR_INVALID;
+  const size_t tb = rp_server_tables_bytes(max_resident);
+  if (arena_bytes < tb) return RP_ERR_WORKSPACE;
+  Server* sv = new Server();
+  sv->arena = (uint8_t*)arena;
+  sv->arena_bytes = arena_bytes;
+  sv->opts = op;
+  sv->s = (hipStream_t)stream;
+  sv->max_resident = max_resident;
+  size_t o = 0;
+  sv->d_jobs = (Job*)(sv->arena + o); o += sup(max_resident * sizeof(Job));
+  sv->d_segs = (ConfSeg*)(sv->arena + o); o += sup(2 * max_resident * sizeof(ConfSeg));
+  sv->d_states = (JobState*)(sv->arena + o); o += sup(max_resident * sizeof(JobState));
+  sv->d_active = (uint32_t*)(sv->arena + o); o += SALIGN;
+  sv->tables = o;
+  sv->alloc.init(o, arena_bytes - o);
+  *out = sv;
+  return RP_OK;
+}
+
+rp_status rp_server_submit(void* srv, const rp_kernel* k, uint64_t job_id) {
+  Server* sv = (Server*)srv;
+  if (!sv || validate_kernel(k) != RP_OK) return RP_ERR_INVALID;
+  std::unique_ptr<SJob> j(new SJob());
+  j->id = job_id;
+  j->desc.take(k);
+  make_plan(&j->desc.k, j->plan);
+  j->input.plan = &j->plan;
+  j->input.phi0 = server_units(j->plan, sv->opts);
+  j->input.policy = sv->opts.policy;
+  j->input.max_rounds = sv->opts.max_rounds;
+  j->bytes = sup(engine_job_bytes(j->input));
+  if (j->bytes > sv->arena_bytes - sv->tables) return RP_ERR_BUDGET;   // can never fit
+  j->t_submit = now_s();
+  sv->pending.push_back(std::move(j));
+  return RP_OK;
+}
+
+rp_status rp_server_step(void* srv, uint32_t* n_resident, uint32_t* n_pending) {
+  Server* sv = (Server*)srv;
+  if (!sv) return RP_ERR_INVALID;
+  hipStream_t s = sv->s;
+  // 1. admission by footprint, arrival order
+  while (!sv->pending.empty() && sv->resident.size() < sv->max_resident) {
+    SJob& j = *sv->pending.front();
+    size_t off;
+    if (!sv->alloc.alloc(j.bytes, off)) break;
+    j.off = off;
+    sv->staging.emplace_back();
+    const int rc = engine_prepare_job(j.input, sv->arena + off, j.bytes, s, j.prep,
+                                      sv->staging.back());
+    if (rc != RP_OK) return (rp_status)rc;
+    sv->resident.push_back(std::move(sv->pending.front()));
+    sv->pending.pop_front();
+  }
+  const uint32_t n = (uint32_t)sv->resident.size();
+  if (n) {
+    // 2. one round over every resident job
+    sv->h_jobs.resize(n);
+    sv->h_segs.clear();
+    uint32_t tiles = 0, maxP = 1;
+    const uint32_t ct = conf_tile_size();
+    for (uint32_t q = 0; q < n; q++) {
+      SJob& j = *sv->resident[q];
+      sv->h_jobs[q] = j.prep.job;
+      maxP = std::max(maxP, j.plan.P);
+      for (uint32_t g = 0; g < j.prep.nseg; g++) {
+        ConfSeg c = j.prep.segs[g];
+        c.job = q;
+        c.ctile_beg = tiles;
+        tiles += (uint32_t)((j.prep.n_rec[g] + ct - 1) / ct);
+        sv->h_segs.push_back(c);
+      }
+    }
+    if (hipMemcpyAsync(sv->d_jobs, sv->h_jobs.data(), n * sizeof(Job), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        (!sv->h_segs.empty() &&
+         hipMemcpyAsync(sv->d_segs, sv->h_segs.data(), sv->h_segs.size() * sizeof(ConfSeg),
+                        hipMemcpyHostToDevice, s) != hipSuccess))
+      return RP_ERR_DEVICE;
+    const int rc = engine_round(sv->d_jobs, n, sv->d_segs, (uint32_t)sv->h_segs.size(), tiles,
+                                maxP, sv->d_active, s);
+    if (rc != RP_OK) return (rp_status)rc;
+    gather_states_kernel<<<(n + 255) / 256, 256, 0, s>>>(sv->d_jobs, n, sv->d_states);
+    sv->h_states.resize(n);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(sv->h_states.data(), sv->d_states, n * sizeof(JobState),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return RP_ERR_DEVICE;
+    sv->rounds++;
+    // 3. retire
+    const double t = now_s();
+    std::vector<std::unique_ptr<SJob>> keep;
+    keep.reserve(n);
+    for (uint32_t q = 0; q < n; q++) {
+      std::unique_ptr<SJob>& j = sv->resident[q];
+      if (sv->h_states[q].state == ST_RUN) {
+        keep.push_back(std::move(j));
+        continue;
+      }
+      Server::Done dn;
+      dn.id = j->id;
+      fill_out(*j, sv->h_states[q], dn.out);
+      dn.latency = t - j->t_submit;
+      sv->done.push_back(dn);
+      sv->alloc.release(j->off, j->bytes);
+    }
+    sv->resident.swap(keep);
+  } else if (hipStreamSynchronize(s) != hipSuccess) {
+    return RP_ERR_DEVICE;
+  }
+  sv->staging.clear();
+  if (n_resident) *n_resident = (uint32_t)sv->resident.size();
+  if (n_pending) *n_pending = (uint32_t)sv->pending.size();
+  return RP_OK;
+}
+
+rp_status rp_server_poll(void* srv, uint64_t* ids, rp_repair_out* outs, double* latency_s,
+                         uint32_t cap, uint32_t* n_done) {
+  Server* sv = (Server*)srv;
+  if (!sv || (cap && (!ids || !outs))) return RP_ERR_INVALID;
+  uint32_t m = 0;
+  while (m < cap && !sv->done.empty()) {
+    const Server::Done& dn = sv->done.front();
+    ids[m] = dn.id;
+    outs[m] = dn.out;
+    if (latency_s) latency_s[m] = dn.latency;
+    sv->done.pop_front();
+    m++;
+  }
+  if (n_done) *n_done = m;
+  return RP_OK;
+}
+
+rp_status rp_server_destroy(void* srv) {
+  Server* sv = (Server*)srv;
+  if (!sv) return RP_ERR_INVALID;
+  (void)hipStreamSynchronize(sv->s);
+  delete sv;
+  return RP_OK;
+}
+
+}  // extern "C"

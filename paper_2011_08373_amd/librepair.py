@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "lib", "librepair.so")
 
 OK, UNSAT = 0, 1
 ERR_INVALID, ERR_CAPACITY, ERR_WORKSPACE, ERR_DEVICE, ERR_ROUNDS, ERR_BUDGET = -1, -2, -3, -4, -5, -6
-OP_CHECK, OP_CLAUSES, OP_REPAIR = 0, 1, 2
+OP_CHECK, OP_CLAUSES, OP_REPAIR, OP_FIRST = 0, 1, 2, 4
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("librepair.so is not built (run paper_2011_08373_amd/build.py): %s"
@@ -50,6 +50,7 @@ class RpStats(C.Structure):
     _fields_ = [("ms_gen", C.c_double), ("ms_sort", C.c_double), ("ms_check", C.c_double),
                 ("ms_clause", C.c_double), ("ms_solve", C.c_double), ("ms_total", C.c_double),
                 ("ms_sort_pass_max", C.c_double), ("ms_sort_kernels", C.c_double),
+                ("ms_runs", C.c_double),
                 ("records", C.c_uint64),
                 ("accesses", C.c_uint64), ("records_scanned", C.c_uint64),
                 ("sort_passes", C.c_uint32), ("sort_launches", C.c_uint32),
@@ -70,12 +71,29 @@ _L.rp_check.argtypes = [_K, C.c_uint64, C.c_void_p, C.c_uint64, _u64p, _u64p, _u
                         C.c_void_p, C.c_size_t, C.c_void_p]
 _L.rp_clauses.argtypes = [_K, C.c_uint64, C.c_void_p, C.c_uint64, _u64p, C.c_void_p,
                           C.c_size_t, C.c_void_p]
+_L.rp_first_partners.argtypes = [_K, C.c_uint64, C.c_void_p, _u64p, C.c_void_p, C.c_size_t,
+                                 C.c_void_p]
 _L.rp_solve_workspace_bytes.argtypes = [C.c_uint64]
 _L.rp_solve_workspace_bytes.restype = C.c_size_t
 _L.rp_min_barriers.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32, _u64p, _u64p,
                                C.c_void_p, C.c_size_t, C.c_void_p]
 _L.rp_repair.argtypes = [_K, C.POINTER(RpOpts), C.POINTER(RpOut), C.c_void_p, C.c_uint32,
                          C.c_void_p, C.c_size_t, C.c_void_p]
+_L.rp_batch_workspace_bytes.argtypes = [C.POINTER(C.POINTER(RpKernel)), C.c_uint32]
+_L.rp_batch_workspace_bytes.restype = C.c_size_t
+_L.rp_repair_batch.argtypes = [C.POINTER(C.POINTER(RpKernel)), C.c_uint32, C.POINTER(RpOpts),
+                               C.POINTER(RpOut), C.c_void_p, C.c_size_t, C.c_void_p]
+_L.rp_server_tables_bytes.argtypes = [C.c_uint32]
+_L.rp_server_tables_bytes.restype = C.c_size_t
+_L.rp_server_job_bytes.argtypes = [_K]
+_L.rp_server_job_bytes.restype = C.c_size_t
+_L.rp_server_create.argtypes = [C.c_void_p, C.c_size_t, C.POINTER(RpOpts), C.c_uint32,
+                                C.c_void_p, C.POINTER(C.c_void_p)]
+_L.rp_server_submit.argtypes = [C.c_void_p, _K, C.c_uint64]
+_L.rp_server_step.argtypes = [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+_L.rp_server_poll.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(RpOut),
+                              C.POINTER(C.c_double), C.c_uint32, C.POINTER(C.c_uint32)]
+_L.rp_server_destroy.argtypes = [C.c_void_p]
 _L.rp_last_stats.argtypes = [C.POINTER(RpStats)]
 _L.rp_last_stats.restype = None
 _L.rp_set_sort_digit_bits.argtypes = [C.c_int]
@@ -169,6 +187,20 @@ def check(km, x: int = 0, cap: int | None = None, ws=None, stream=None):
     return st, pairs, div.value, nrec.value, n.value
 
 
+def first_partners(km, x: int = 0, ws=None, stream=None):
+    """(status, first[2][P] as a numpy array, divergent); 0xFFFFFFFF = none."""
+    ka = KernelArg(km)
+    need = int(_L.rp_workspace_bytes(ka.ref, OP_FIRST))
+    if need == 0:
+        return ERR_INVALID, None, 0
+    ptr, size = (ws or _ws).get(need)
+    out = np.zeros((2, max(1, int(km.n_points))), np.uint32)
+    div = C.c_uint64(0)
+    st = _L.rp_first_partners(ka.ref, C.c_uint64(int(x)), out.ctypes.data, C.byref(div),
+                              C.c_void_p(ptr), size, _stream(stream))
+    return st, out[:, :int(km.n_points)], div.value
+
+
 def clauses(km, x: int = 0, cap: int | None = None, ws=None, stream=None):
     """(status, [(pos, neg), ...]) reduced and sorted."""
     ka = KernelArg(km)
@@ -219,6 +251,116 @@ def repair(km, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int
              removed=out.removed, rounds=out.rounds, n_clauses=out.n_clauses, ret=st)
     r["trajectory"] = [traj[q] for q in range(min(out.rounds, traj_cap))]
     return r
+
+
+class BatchArg:
+    """C views of many kernel models."""
+
+    def __init__(self, kms):
+        self.args = [KernelArg(k) for k in kms]
+        self.ptrs = (C.POINTER(RpKernel) * max(1, len(kms)))(
+            *[C.pointer(a.k) for a in self.args])
+        self.n = len(kms)
+
+
+def batch_workspace_bytes(kms) -> int:
+    b = kms if isinstance(kms, BatchArg) else BatchArg(kms)
+    return int(_L.rp_batch_workspace_bytes(b.ptrs, b.n))
+
+
+def repair_batch(kms, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int = 0,
+                 ws=None, stream=None):
+    """Alg. 1 over many kernels in one batched run; (status, [result dict per kernel]).
+    Runs on a dedicated non-default stream unless one is given, so that each
+    round can be replayed as a captured graph."""
+    import torch
+    b = kms if isinstance(kms, BatchArg) else BatchArg(kms)
+    need = int(_L.rp_batch_workspace_bytes(b.ptrs, b.n))
+    ptr, size = (ws or _ws).get(need)
+    o = RpOpts(policy, grid, inspect, 0, max_rounds)
+    outs = (RpOut * max(1, b.n))()
+    st_obj = stream if stream is not None else _batch_stream()
+    torch.cuda.current_stream().synchronize()
+    st = _L.rp_repair_batch(b.ptrs, b.n, C.byref(o), outs, C.c_void_p(ptr), size,
+                            C.c_void_p(st_obj.cuda_stream))
+    res = []
+    for q in range(b.n):
+        r = outs[q]
+        res.append(dict(status=r.status, assign=r.assign, weight=r.weight, added=r.added,
+                        removed=r.removed, rounds=r.rounds, n_clauses=r.n_clauses))
+    return st, res
+
+
+_bstream = None
+
+
+def _batch_stream():
+    global _bstream
+    import torch
+    if _bstream is None:
+        _bstream = torch.cuda.Stream()
+    return _bstream
+
+
+class Server:
+    """Continuous-batching repair server over a torch-allocated device arena."""
+
+    def __init__(self, arena_bytes: int, max_resident: int = 1024, policy: int = 0, grid: int = 1,
+                 inspect: int = 1, max_rounds: int = 0, stream=None):
+        import torch
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        torch.cuda.current_stream().synchronize()
+        o = RpOpts(policy, grid, inspect, 0, max_rounds)
+        h = C.c_void_p()
+        st = _L.rp_server_create(C.c_void_p(self.arena.data_ptr()), int(arena_bytes), C.byref(o),
+                                 int(max_resident), C.c_void_p(self.stream.cuda_stream),
+                                 C.byref(h))
+        if st != OK:
+            raise RuntimeError("rp_server_create: " + status_string(st))
+        self.h = h
+        self._held = {}
+
+    def job_bytes(self, km) -> int:
+        return int(_L.rp_server_job_bytes(KernelArg(km).ref))
+
+    def submit(self, km, job_id: int) -> int:
+        return _L.rp_server_submit(self.h, KernelArg(km).ref, C.c_uint64(int(job_id)))
+
+    def step(self):
+        nr = C.c_uint32(0)
+        npd = C.c_uint32(0)
+        st = _L.rp_server_step(self.h, C.byref(nr), C.byref(npd))
+        if st != OK:
+            raise RuntimeError("rp_server_step: " + status_string(st))
+        return nr.value, npd.value
+
+    def poll(self, cap: int = 4096):
+        ids = (C.c_uint64 * cap)()
+        outs = (RpOut * cap)()
+        lat = (C.c_double * cap)()
+        n = C.c_uint32(0)
+        st = _L.rp_server_poll(self.h, ids, outs, lat, cap, C.byref(n))
+        if st != OK:
+            raise RuntimeError("rp_server_poll: " + status_string(st))
+        res = []
+        for q in range(n.value):
+            r = outs[q]
+            res.append((ids[q], dict(status=r.status, assign=r.assign, weight=r.weight,
+                                     added=r.added, removed=r.removed, rounds=r.rounds,
+                                     n_clauses=r.n_clauses), lat[q]))
+        return res
+
+    def close(self):
+        if self.h:
+            _L.rp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def last_stats() -> dict:

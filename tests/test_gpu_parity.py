@@ -244,3 +244,170 @@ def test_errors(L):
     st = L.lib().rp_repair(ka.ref, C.byref(o), C.byref(out), None, 0,
                            C.c_void_p(ws.t.data_ptr()), 16, None)
     assert st == L.ERR_WORKSPACE
+
+
+def _mixed_kernels():
+    kms = []
+    for seed in range(12):
+        kms.append(synth.generate("plain-small", mode="planted", seed=seed))
+        kms.append(synth.generate("plain-small", seed=100 + seed))
+    for seed in range(16):
+        kms.append(BF.tiny_kernel(np.random.default_rng(60_000 + seed)))
+    # a few medium kernels from the batched distribution (small sizes)
+    cfg = synth.config("batched")
+    for seed in range(6):
+        rng = np.random.default_rng(70_000 + seed)
+        c = dict(cfg)
+        c.update(blocks=int(rng.integers(1, 5)), threads=64 * int(rng.integers(1, 5)),
+                 P=int(rng.integers(16, 200)), S=int(rng.integers(2, 20)), S_grid=2)
+        kms.append(synth.planted_kernel(c, rng))
+    return kms
+
+
+def test_batch_equals_plain(L):
+    kms = _mixed_kernels()
+    st, res = L.repair_batch(kms)
+    assert st == 0
+    for q, km in enumerate(kms):
+        o = O.repair(km)
+        g = {k: res[q][k] for k in REPAIR_KEYS if k != "trajectory"}
+        assert g == {k: o[k] for k in REPAIR_KEYS if k != "trajectory"}, q
+    # order does not matter
+    perm = np.random.default_rng(1).permutation(len(kms)).tolist()
+    st, res2 = L.repair_batch([kms[q] for q in perm])
+    assert st == 0
+    for a, q in enumerate(perm):
+        assert res2[a] == res[q], (a, q)
+
+
+def test_batch_policy_and_options(L):
+    kms = _mixed_kernels()[:24]
+    for kw in (dict(policy=1), dict(grid=0), dict(inspect=0), dict(max_rounds=1)):
+        st, res = L.repair_batch(kms, **kw)
+        assert st == 0
+        for q, km in enumerate(kms):
+            o = O.repair(km, **kw)
+            g = {k: res[q][k] for k in REPAIR_KEYS if k != "trajectory"}
+            assert g == {k: o[k] for k in REPAIR_KEYS if k != "trajectory"}, (kw, q)
+
+
+def test_batch_invalid_member(L):
+    kms = _mixed_kernels()[:8]
+    bad = kms[3].copy()
+    bad.points["array"][0] = 9
+    bad.points["kind"][0] = 0
+    kms[3] = bad
+    st, res = L.repair_batch(kms)
+    assert st == 0
+    assert res[3]["status"] == L.ERR_INVALID
+    for q in (0, 1, 2, 4, 5, 6, 7):
+        o = O.repair(kms[q])
+        assert res[q]["status"] == o["status"] and res[q]["assign"] == o["assign"], q
+
+
+def test_server_continuous_batching(L):
+    # jobs arrive over several steps; each result equals the job's result
+    # alone, and newly admitted jobs share rounds with resident ones
+    kms = _mixed_kernels()
+    srv = L.Server(arena_bytes=3 << 20, max_resident=8)
+    try:
+        big = synth.generate("plain-large")
+        assert srv.submit(big, 999) == L.ERR_BUDGET
+        results, overlap, nxt, steps = {}, False, 0, 0
+        while len(results) < len(kms):
+            for _ in range(3):   # three arrivals per step
+                if nxt < len(kms):
+                    assert srv.submit(kms[nxt], nxt) == 0
+                    nxt += 1
+            before = {i for i in results}
+            nres, npend = srv.step()
+            steps += 1
+            if nres >= 2:
+                overlap = True
+            for jid, r, lat in srv.poll():
+                assert jid not in before and lat >= 0
+                results[jid] = r
+            assert steps < 2000
+        assert overlap
+        for q, km in enumerate(kms):
+            o = O.repair(km)
+            g = {k: results[q][k] for k in REPAIR_KEYS if k != "trajectory"}
+            assert g == {k: o[k] for k in REPAIR_KEYS if k != "trajectory"}, q
+    finally:
+        srv.close()
+
+
+def test_server_recreate_same_results(L):
+    kms = _mixed_kernels()[:10]
+    outs = []
+    for _ in range(2):
+        srv = L.Server(arena_bytes=64 << 20, max_resident=64)
+        for q, km in enumerate(kms):
+            assert srv.submit(km, q) == 0
+        res = {}
+        while len(res) < len(kms):
+            srv.step()
+            for jid, r, lat in srv.poll():
+                res[jid] = r
+        srv.close()
+        outs.append(res)
+    assert outs[0] == outs[1]
+
+
+NONE = 0xFFFFFFFF
+
+
+def _first_from_pairs(pairs, P):
+    first = np.full((2, P), NONE, np.uint64)
+    for lv, i, j in pairs:
+        if j < first[lv][i]:
+            first[lv][i] = j
+    return first
+
+
+def test_first_partners(L):
+    for seed in range(200):
+        rng = np.random.default_rng(80_000 + seed)
+        km = BF.tiny_kernel(rng)
+        for x in [0] + rng.integers(0, 1 << max(1, km.n_slots), size=2).tolist():
+            st, first, div = L.first_partners(km, x)
+            o = O.check(km, x)
+            assert st == 0 and div == o[2]
+            assert (first.astype(np.uint64) == _first_from_pairs(o[1], km.n_points)).all(), (seed, x)
+    for seed in range(0, 1000, 50):
+        km = synth.generate("plain-small", seed=seed)
+        st, first, div = L.first_partners(km, 0)
+        assert (first.astype(np.uint64) == _first_from_pairs(O.check(km, 0)[1], km.n_points)).all()
+
+
+@pytest.mark.parametrize("mode", ["planted", "literal"])
+def test_stress_sampled(L, mode):
+    # 4096 blocks x 1024 threads, 1024 points, 64 slots, eight 16M-word arrays
+    # (about 2.9G access records).  The oracle checks sampled points one pair
+    # at a time: the reported first partner conflicts, earlier candidates do not.
+    km = synth.generate("stress", mode=mode)
+    st, first, div = L.first_partners(km, 0)
+    assert st == 0 and div == 0
+    rng = np.random.default_rng(7)
+    pts = km.points
+    acc = np.flatnonzero(pts["kind"] == 0)
+    glob = np.flatnonzero((pts["kind"] == 0) & (km.arrays["space"][pts["array"]] == 1))
+    for lv, pool in ((0, acc), (1, glob)):
+        for i in rng.choice(pool, 3, replace=False).tolist():
+            j = int(first[lv][i])
+            same = [q for q in acc.tolist() if q >= i and pts["array"][q] == pts["array"][i]]
+            if j != NONE:
+                assert O.pair_conflict(km, i, j, lv) == 1, (lv, i, j)
+                earlier = [q for q in same if q < j]
+            else:
+                earlier = same
+            for q in rng.choice(earlier, min(2, len(earlier)), replace=False).tolist():
+                assert O.pair_conflict(km, i, int(q), lv) == 0, (lv, i, q)
+    r = L.repair(km)
+    if mode == "planted":
+        assert r["status"] == 0
+        w = km.weights
+        ws = sum(int(w[s]) for s in range(km.n_slots) if (km.meta["x_star"] >> s) & 1)
+        assert r["weight"] <= ws
+        st, first, div = L.first_partners(km, r["assign"])
+        assert st == 0 and div == 0 and (first == NONE).all()
