@@ -11,8 +11,11 @@
 //              thread (same-block view) or the same single block (cross-block
 //              view).  In "first" mode a run stops at its first racing
 //              partner (enough for the reduced clause set); in "all" mode
-//              every racing pair goes into a bitmap.
+//              every racing pair goes into a bitmap.  conf_tiles_kernel lays
+//              the round's tiles over the logs of the jobs still running.
 // pairs_kernel turns the bitmap into the (level, i, j)-ordered pair list.
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 
@@ -20,8 +23,9 @@ namespace rp {
 
 constexpr int IVL_BLOCK = 1024;
 constexpr int CONF_BLOCK = 256;
-constexpr uint32_t CONF_TILE = 4096;                     // runs owned per tile
-constexpr uint32_t CONF_WIN = CONF_TILE + 2048;          // staged: tile + lookahead
+constexpr int CONF_WAVES = CONF_BLOCK / 64;
+constexpr int CONF_CHUNKS = 16;                          // chunks of 64 runs per wave and tile
+constexpr uint32_t CONF_TILE = CONF_WAVES * CONF_CHUNKS * 64;   // runs per tile
 
 __global__ __launch_bounds__(IVL_BLOCK) void ivl_kernel(const Job* __restrict__ jobs, int with_bitmap) {
   __shared__ uint64_t wsum[IVL_BLOCK / 64];
@@ -77,33 +81,77 @@ __device__ __forceinline__ void set_pair(uint64_t* bm, uint32_t wpr, uint32_t P,
   if (!(*wp & bit)) atomicOr((unsigned long long*)wp, (unsigned long long)bit);
 }
 
+// Tile table of one round: runs of the logs of running jobs only, in
+// segment order; one workgroup.
+__global__ __launch_bounds__(1024) void conf_tiles_kernel(const Job* __restrict__ jobs,
+                                                          ConfSeg* segs, uint32_t nseg,
+                                                          uint32_t* total) {
+  __shared__ uint32_t sm[16];
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  uint32_t run = 0;
+  for (uint32_t b = 0; b < nseg; b += 1024) {
+    const uint32_t q = b + threadIdx.x;
+    uint32_t v = 0;
+    if (q < nseg) {
+      const ConfSeg& sg = segs[q];
+      const uint64_t n = sg.n_runs_at ? *sg.n_runs_at : sg.n_runs;
+      if (jobs[sg.job].st->state == ST_RUN) v = (uint32_t)((n + CONF_TILE - 1) / CONF_TILE);
+    }
+    uint32_t inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) sm[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0, all = 0;
+    for (int k = 0; k < 16; k++) {
+      if (k < w) pre += sm[k];
+      all += sm[k];
+    }
+    if (q < nseg) segs[q].ctile_beg = run + pre + inc - v;
+    run += all;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = run;
+}
+
+__device__ __forceinline__ uint64_t run_at(const uint64_t* runs, uint64_t q, uint64_t n) {
+  return q < n ? runs[q] : RUN_SENTINEL;
+}
+
 // Racing partners over the run log.  A sub-segment (one location, one
-// interval) is a contiguous stretch of runs; each run looks at the runs after
-// it in its sub-segment.  Tiles of runs plus a lookahead are staged in LDS,
-// reads past the staged window go to global memory.
+// interval) is a contiguous stretch of runs.  Each wave streams a range of
+// the log in chunks of 64 runs, one run per lane, with the next chunk as a
+// window: ballots give the sub-segment starts, writes and multi runs of the
+// window as 64-bit masks, so a lane finds the runs after its own in its
+// sub-segment with a few mask operations and tests them in order.  Only a
+// sub-segment that runs past the window is followed in global memory.
+template <bool ALL>
 __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict__ jobs,
                                                           const ConfSeg* __restrict__ segs,
-                                                          int nseg, uint32_t n_tiles,
-                                                          uint32_t tiles_per_wg, int all_pairs) {
-  __shared__ uint64_t s_run[CONF_WIN];
+                                                          int nseg,
+                                                          const uint32_t* __restrict__ total_at) {
+  __shared__ uint64_t s_e[CONF_WAVES][128];
   extern __shared__ uint32_t s_dyn[];        // [P] interval of each point, [P] first partner
-  const int tid = threadIdx.x;
-  const uint32_t t0 = blockIdx.x * tiles_per_wg;
-  uint32_t t1 = t0 + tiles_per_wg;
-  if (t1 > n_tiles) t1 = n_tiles;
+  const uint32_t total = *total_at;
+  const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
+  const uint32_t t0 = blockIdx.x * per;
+  const uint32_t t1 = min(t0 + per, total);
+  const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
   int cur = -1;
-  bool live = false;
   uint32_t* s_iv = s_dyn;
-  uint32_t* s_minj = s_dyn;   // placed after s_iv once P is known
+  uint32_t* s_minj = s_dyn;
+  uint32_t P = 0;
   for (uint32_t tile = t0; tile < t1; tile++) {
     int lo = 0, hi = nseg - 1;   // largest segment with ctile_beg <= tile
     while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
+      const int mid = (lo + hi + 1) >> 1;
       if (segs[mid].ctile_beg <= tile) lo = mid; else hi = mid - 1;
     }
     if (lo != cur) {
-      if (cur >= 0 && live && !all_pairs) {
-        __syncthreads();
+      __syncthreads();
+      if (!ALL && cur >= 0) {
         const Job& J = jobs[segs[cur].job];
         uint32_t* g = J.minj + (uint64_t)segs[cur].level * J.P;
         for (uint32_t i = tid; i < J.P; i += CONF_BLOCK)
@@ -112,58 +160,113 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
       __syncthreads();
       cur = lo;
       const Job& J = jobs[segs[cur].job];
-      s_minj = s_dyn + J.P;
-      live = J.st->state == ST_RUN;
-      if (live) {
-        const uint32_t* iv = J.ivl + (uint64_t)segs[cur].level * J.P;
-        for (uint32_t i = tid; i < J.P; i += CONF_BLOCK) {
-          s_iv[i] = iv[i];
-          s_minj[i] = NONE32;
-        }
+      P = J.P;
+      s_minj = s_dyn + P;
+      const uint32_t* iv = J.ivl + (uint64_t)segs[cur].level * P;
+      for (uint32_t i = tid; i < P; i += CONF_BLOCK) {
+        s_iv[i] = iv[i];
+        s_minj[i] = NONE32;
       }
       __syncthreads();
     }
-    if (!live) continue;
-    const ConfSeg sg = segs[cur];
+    const ConfSeg& sg = segs[cur];
     const uint64_t n = sg.n_runs_at ? *sg.n_runs_at : sg.n_runs;
-    const uint64_t base = (uint64_t)(tile - sg.ctile_beg) * CONF_TILE;
-    if (base >= n) continue;   // run counts are known on the device only
+    const uint64_t wbeg = (uint64_t)(tile - sg.ctile_beg) * CONF_TILE + (uint64_t)wv * (CONF_CHUNKS * 64);
+    if (wbeg >= n) continue;
     const Job& J = jobs[sg.job];
-    const uint32_t P = J.P;
+    const uint32_t level = sg.level;
     const uint64_t* __restrict__ runs = sg.runs;
-    const uint32_t wlen = (uint32_t)((n - base) < CONF_WIN ? (n - base) : CONF_WIN);
-    const uint32_t own = wlen < CONF_TILE ? wlen : CONF_TILE;
-    __syncthreads();
-    for (uint32_t q = tid; q < wlen; q += CONF_BLOCK) s_run[q] = runs[base + q];
-    __syncthreads();
-    for (uint32_t r = tid; r < own; r += CONF_BLOCK) {
-      const uint64_t ei = s_run[r];
-      const uint32_t i = (uint32_t)(ei >> RUN_PT) & 0xFFFu;
-      if (i >= P) continue;
-      const bool wi = (ei >> RUN_W) & 1, mi = (ei >> RUN_MULTI) & 1;
-      const uint32_t idi = (uint32_t)ei, iv = s_iv[i];
-      if (wi && mi) {
-        if (all_pairs) set_pair(J.bitmap, J.wpr, P, sg.level, i, i);
-        else { atomicMin(&s_minj[i], i); continue; }
-      }
-      for (uint64_t q = base + r + 1; q < n; q++) {
-        const uint64_t ej = (q - base) < wlen ? s_run[q - base] : runs[q];
-        if ((ej >> RUN_LOC) & 1) break;             // next location
-        const uint32_t j = (uint32_t)(ej >> RUN_PT) & 0xFFFu;
-        if (j >= P || s_iv[j] != iv) break;          // next interval
-        if ((wi || ((ej >> RUN_W) & 1)) && (mi || ((ej >> RUN_MULTI) & 1) || idi != (uint32_t)ej)) {
-          if (all_pairs) {
-            set_pair(J.bitmap, J.wpr, P, sg.level, i, j);
+    uint64_t e0 = run_at(runs, wbeg + lane, n);
+    uint64_t e1 = run_at(runs, wbeg + 64 + lane, n);
+    for (int c = 0; c < CONF_CHUNKS; c++) {
+      const uint64_t p0 = wbeg + (uint64_t)c * 64;
+      if (p0 >= n) break;
+      const uint64_t e2 = run_at(runs, p0 + 128 + lane, n);   // next window, in flight
+      // decode the window: own chunk e0, lookahead chunk e1
+      const bool v0 = !((e0 >> RUN_END) & 1), v1 = !((e1 >> RUN_END) & 1);
+      const uint32_t i0 = (uint32_t)(e0 >> RUN_PT) & 0xFFFu;
+      const uint32_t i1 = (uint32_t)(e1 >> RUN_PT) & 0xFFFu;
+      const uint32_t iv0 = (v0 && i0 < P) ? s_iv[i0] : NONE32;
+      const uint32_t iv1 = (v1 && i1 < P) ? s_iv[i1] : NONE32;
+      uint32_t prev0 = __shfl_up(iv0, 1);
+      uint32_t prev1 = __shfl_up(iv1, 1);
+      const uint32_t last0 = __shfl(iv0, 63);
+      if (lane == 0) prev1 = last0;
+      // a sub-segment starts at a new location or a new interval
+      const uint64_t Bc = __ballot(((e0 >> RUN_LOC) & 1) || iv0 != prev0);
+      const uint64_t Bn = __ballot(((e1 >> RUN_LOC) & 1) || iv1 != prev1);
+      const uint64_t Wc = __ballot((e0 >> RUN_W) & 1), Wn = __ballot((e1 >> RUN_W) & 1);
+      const uint64_t Mc = __ballot((e0 >> RUN_MULTI) & 1), Mn = __ballot((e1 >> RUN_MULTI) & 1);
+      s_e[wv][lane] = e0;
+      s_e[wv][64 + lane] = e1;
+      __builtin_amdgcn_wave_barrier();
+      if (v0 && i0 < P) {
+        const uint32_t i = i0, iv = iv0, id = (uint32_t)e0;
+        const bool w = (e0 >> RUN_W) & 1, m = (e0 >> RUN_MULTI) & 1;
+        uint32_t best = NONE32;
+        if (w && m) {          // two threads (blocks) of one point on one word, one writes
+          if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, i);
+          else best = i;
+        }
+        if (ALL || best == NONE32) {
+          const uint64_t gt = lane == 63 ? 0ull : (~0ull << (lane + 1));
+          const uint64_t sC = Bc & gt;
+          uint64_t cC, cN;
+          bool complete = true;
+          if (sC) {
+            cC = gt & ((sC & (~sC + 1)) - 1);
+            cN = 0;
           } else {
-            atomicMin(&s_minj[i], j);
-            break;
+            cC = gt;
+            if (Bn) cN = (Bn & (~Bn + 1)) - 1;
+            else { cN = ~0ull; complete = false; }
+          }
+          if (!w) { cC &= Wc; cN &= Wn; }
+          while (cC) {
+            const int jj = __ffsll((unsigned long long)cC) - 1;
+            cC &= cC - 1;
+            const uint64_t ej = s_e[wv][jj];
+            const uint32_t j = (uint32_t)(ej >> RUN_PT) & 0xFFFu;
+            if (j < P && (m || ((Mc >> jj) & 1) || id != (uint32_t)ej)) {
+              if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, j);
+              else { best = j; break; }
+            }
+          }
+          if (ALL || best == NONE32) {
+            while (cN) {
+              const int jj = __ffsll((unsigned long long)cN) - 1;
+              cN &= cN - 1;
+              const uint64_t ej = s_e[wv][64 + jj];
+              const uint32_t j = (uint32_t)(ej >> RUN_PT) & 0xFFFu;
+              if (j < P && (m || ((Mn >> jj) & 1) || id != (uint32_t)ej)) {
+                if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, j);
+                else { best = j; break; }
+              }
+            }
+          }
+          if (!complete && (ALL || best == NONE32)) {
+            // the sub-segment continues past the window
+            for (uint64_t q = p0 + 128; q < n; q++) {
+              const uint64_t ej = runs[q];
+              if ((ej >> RUN_LOC) & 1) break;
+              const uint32_t j = (uint32_t)(ej >> RUN_PT) & 0xFFFu;
+              if (j >= P || s_iv[j] != iv) break;
+              if ((w || ((ej >> RUN_W) & 1)) && (m || ((ej >> RUN_MULTI) & 1) || id != (uint32_t)ej)) {
+                if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, j);
+                else { best = j; break; }
+              }
+            }
           }
         }
+        if (!ALL && best != NONE32 && s_minj[i] > best) atomicMin(&s_minj[i], best);
       }
+      __builtin_amdgcn_wave_barrier();
+      e0 = e1;
+      e1 = e2;
     }
   }
-  if (cur >= 0 && live && !all_pairs) {
-    __syncthreads();
+  __syncthreads();
+  if (!ALL && cur >= 0) {
     const Job& J = jobs[segs[cur].job];
     uint32_t* g = J.minj + (uint64_t)segs[cur].level * J.P;
     for (uint32_t i = tid; i < J.P; i += CONF_BLOCK)
@@ -230,14 +333,21 @@ hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int with_bitmap, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t n_tiles,
-                       uint32_t grid, uint32_t max_points, int all_pairs, hipStream_t s) {
-  if (n_tiles == 0 || nseg == 0) return hipSuccess;
-  if (grid > n_tiles) grid = n_tiles;
-  const uint32_t per = (n_tiles + grid - 1) / grid;
-  grid = (n_tiles + per - 1) / per;
+hipError_t launch_conf(const Job* jobs, ConfSeg* segs, int nseg, uint32_t max_points,
+                       int all_pairs, uint32_t* tiles, hipStream_t s) {
+  if (nseg == 0) return hipSuccess;
   const size_t dyn = 2 * (size_t)(max_points ? max_points : 1) * sizeof(uint32_t);
-  conf_kernel<<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, n_tiles, per, all_pairs);
+  int dev = 0, ncu = 256, per_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const hipError_t oe = all_pairs
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conf_kernel<true>, CONF_BLOCK, dyn)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conf_kernel<false>, CONF_BLOCK, dyn);
+  if (oe != hipSuccess || per_cu < 1) per_cu = 1;
+  const uint32_t grid = (uint32_t)ncu * (uint32_t)std::min(per_cu, 8);
+  conf_tiles_kernel<<<1, 1024, 0, s>>>(jobs, segs, (uint32_t)nseg, tiles);
+  if (all_pairs) conf_kernel<true><<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
+  else conf_kernel<false><<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
   return hipGetLastError();
 }
 

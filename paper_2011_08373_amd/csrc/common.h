@@ -4,7 +4,8 @@
 // (threads-1), bb = bits of (blocks-1), pb = bits of (points-1), nb = bits of
 // (max words-1), ab = bits of (arrays-1):
 //
-//   same-block view  (one record per (point, block, thread) access):
+//   same-block view  (one record per (point, block, thread) access, up to
+//                     the reductions below):
 //       [ array | word | block | point | thread ]
 //   cross-block view (GLOBAL arrays only):
 //       [ array | word | point | block | 0...0  ]
@@ -17,6 +18,19 @@
 // records are then ordered by point, which is program order: the interval
 // between two enabled barriers is a contiguous run for every assignment, so
 // the log is sorted once per kernel and rescanned per Verify call.
+//
+// Records that cannot change a run-log entry are not generated.  What a
+// Verify call needs from the records of one point at one location is its
+// first id and whether there are two or more ids (threads in the same-block
+// view, blocks in the cross-block view).  Hence:
+//   - same-block view, word independent of the thread: the first two
+//     executing threads of each block (all threads share one word);
+//   - cross-block view, word independent of the thread: one record per
+//     block (the thread is not part of a cross-block record);
+//   - cross-block view, word independent of the block: blocks 0 and 1 only
+//     (first id 0; a second id exactly when there are two blocks or more);
+//   - one block: no cross-block view (a race needs two blocks).
+// Records are still emitted in increasing order of their low fields.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -29,8 +43,10 @@ constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 constexpr int MAX_POINTS = 4096;
 constexpr int MAX_SORT_PASSES = 8;
 
-// flags of DPoint::flags
-constexpr uint8_t PF_WRITE = 1, PF_GLOBAL = 2, PF_POW2 = 4;
+// flags of DPoint::flags.  PF_TCONST: the word does not depend on the thread
+// (a = 0 mod words); PF_BCONST: it does not depend on the block (b = 0 mod
+// words).
+constexpr uint8_t PF_WRITE = 1, PF_GLOBAL = 2, PF_POW2 = 4, PF_TCONST = 8, PF_BCONST = 16;
 
 struct DPoint {          // 32 B, one per program point
   int32_t a, b, c;
@@ -65,8 +81,8 @@ struct Job {
   const uint64_t* bits_any;   // [P] slot bit of a barrier occurrence, else 0
   const uint64_t* bits_grid;  // [P] slot bit of a GRID barrier occurrence, else 0
   const uint32_t* weights;    // [S]
-  const uint64_t* cnt_pre;    // [P+1] prefix of executing threads over access points
-  const uint64_t* gcnt_pre;   // [P+1] the same over access points of GLOBAL arrays
+  const uint64_t* cnt_pre;    // [P+1] prefix of same-block records per block
+  const uint64_t* gcnt_pre;   // [P+1] prefix of cross-block records
   uint64_t rblk;              // same-block records per block (= cnt_pre[P])
   uint64_t div_if_enabled;    // slots whose guard splits a block
   const uint64_t* log[2];     // sorted logs: same-block, cross-block
@@ -125,7 +141,9 @@ struct ConfSeg {
 //   bit  45      multi: the run holds two or more threads (same-block view)
 //                or two or more blocks (cross-block view)
 //   bit  46      first run of its location
-constexpr int RUN_PT = 32, RUN_W = 44, RUN_MULTI = 45, RUN_LOC = 46;
+//   bit  47      never set in an entry: marks the sentinel read past a log
+constexpr int RUN_PT = 32, RUN_W = 44, RUN_MULTI = 45, RUN_LOC = 46, RUN_END = 47;
+constexpr uint64_t RUN_SENTINEL = (1ull << RUN_LOC) | (1ull << RUN_END);
 
 __device__ __forceinline__ uint32_t word_of(const DPoint& p, uint32_t t, uint32_t k) {
   int64_t v = (int64_t)p.a * (int64_t)t + (int64_t)p.b * (int64_t)k + (int64_t)p.c;

@@ -30,7 +30,7 @@ struct Layout {
   std::vector<size_t> o_ivl, o_minj, o_phi, o_scratch, o_traj, o_bitmap, o_pairs, o_ptotal;
   std::vector<uint32_t> phi_cap, scratch_cap;
   uint64_t n_rec = 0;
-  uint32_t rb = 8, passes = 0, n_conf_tiles = 0;
+  uint32_t rb = 8, passes = 0;
   std::vector<GenItem> items;
   std::vector<SortChunk> chunks;
   std::vector<SortSeg> ssegs;
@@ -51,8 +51,8 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   L.rb = (uint32_t)pick_digit_bits(key_bits);
   L.passes = (uint32_t)sort_passes(key_bits, (int)L.rb);
   uint64_t rec = 0;
-  uint32_t ctiles = 0, btiles = 0;
-  const uint32_t ctile = conf_tile_size(), btile = runs_tile_size();
+  uint32_t btiles = 0;
+  const uint32_t btile = runs_tile_size();
   for (size_t j = 0; j < N; j++) {
     const Plan& p = *jobs[j].plan;
     for (int v = 0; v < 2; v++) {
@@ -66,12 +66,10 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
       L.seg_job.push_back((uint32_t)j);
       L.seg_level.push_back((uint32_t)v);
       rec += n;
-      ctiles += (uint32_t)((n + ctile - 1) / ctile);   // runs <= records
       btiles += (uint32_t)((n + btile - 1) / btile);
     }
   }
   L.n_rec = rec;
-  L.n_conf_tiles = ctiles;
   L.n_btiles = btiles;
   // sort chunks (= generation items): whole sort tiles, at most ~64K chunks
   const uint64_t tile = sort_tile_size();
@@ -247,8 +245,8 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
   uint8_t* runbuf = d + ((L.passes % 2 == 0) ? L.o_recB : L.o_recA);
   ConfSeg* hc = (ConfSeg*)(h.data() + L.o_csegs);
   {
-    uint32_t bt = 0, ct = 0;
-    const uint32_t btile = runs_tile_size(), ctile = conf_tile_size();
+    uint32_t bt = 0;
+    const uint32_t btile = runs_tile_size();
     for (size_t q = 0; q < L.ssegs.size(); q++) {
       ConfSeg c{};
       c.log = (const uint64_t*)sorted + L.ssegs[q].beg;
@@ -258,9 +256,8 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
       c.job = L.seg_job[q];
       c.level = L.seg_level[q];
       c.btile_beg = bt;
-      c.ctile_beg = ct;
+      c.ctile_beg = 0;     // laid out on the device each round
       bt += (uint32_t)((c.n + btile - 1) / btile);
-      ct += (uint32_t)((c.n + ctile - 1) / ctile);
       hc[q] = c;
       hj[c.job].log[c.level] = c.log;
     }
@@ -304,13 +301,6 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
 
 }  // namespace
 
-static uint32_t conf_grid_size() {
-  int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess)
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  return (uint32_t)ncu * 4;
-}
-
 size_t engine_job_bytes(const JobInput& job) {
   EngineOpts o;
   o.op = OP_REPAIR;
@@ -342,10 +332,10 @@ int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStrea
   return RP_OK;
 }
 
-int engine_round(const Job* djobs, uint32_t njobs, const ConfSeg* dcs, uint32_t nseg,
-                 uint32_t n_conf_tiles, uint32_t maxP, uint32_t* dactive, hipStream_t s) {
+int engine_round(const Job* djobs, uint32_t njobs, ConfSeg* dcs, uint32_t nseg, uint32_t maxP,
+                 uint32_t* dactive, hipStream_t s) {
   HIPCHK(launch_ivl(djobs, njobs, 0, s));
-  HIPCHK(launch_conf(djobs, dcs, (int)nseg, n_conf_tiles, conf_grid_size(), maxP, 0, s));
+  HIPCHK(launch_conf(djobs, dcs, (int)nseg, maxP, 0, dactive + 1, s));
   HIPCHK(launch_clause(djobs, njobs, 1, s));
   HIPCHK(launch_solve(djobs, njobs, s));
   HIPCHK(launch_count_active(djobs, njobs, dactive, s));
@@ -372,11 +362,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   tm.mark(T_RUNS);
   // ---- per-round kernels
   const int nseg = (int)L.ssegs.size();
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  int ncu = 256;
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const uint32_t conf_grid = (uint32_t)ncu * 4;
+  uint32_t* dtiles = derr + 9;     // conf tiles of the round
   uint32_t maxP = 1;
   for (const JobInput& j : jobs) maxP = std::max(maxP, j.plan->P);
   std::vector<JobState> hst(N);
@@ -384,7 +370,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   uint32_t rounds_run = 0, conf_launches = 0;
   if (o.op == OP_CHECK) {
     HIPCHK(launch_ivl(djobs, (uint32_t)N, 1, s));
-    HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 1, s));
+    HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 1, dtiles, s));
     conf_launches++;
     scanned += L.n_rec;
     tm.mark(T_CHECK);
@@ -396,13 +382,13 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     tm.mark(T_SOLVE);
   } else if (o.op == OP_FIRST) {
     HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
-    HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s));
+    HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s));
     conf_launches++;
     scanned += L.n_rec;
     tm.mark(T_CHECK);
   } else if (o.op == OP_CLAUSES) {
     HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
-    HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s));
+    HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s));
     conf_launches++;
     scanned += L.n_rec;
     tm.mark(T_CHECK);
@@ -415,7 +401,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     auto round = [&]() -> hipError_t {
       hipError_t e;
       if ((e = launch_ivl(djobs, (uint32_t)N, 0, s)) != hipSuccess) return e;
-      if ((e = launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s)) != hipSuccess)
+      if ((e = launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s)) != hipSuccess)
         return e;
       if ((e = launch_clause(djobs, (uint32_t)N, 1, s)) != hipSuccess) return e;
       if ((e = launch_solve(djobs, (uint32_t)N, s)) != hipSuccess) return e;
@@ -445,7 +431,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
         tm.mark(T_CHECK);
       } else {
         HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
-        HIPCHK(launch_conf(djobs, dcs, nseg, L.n_conf_tiles, conf_grid, maxP, 0, s));
+        HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s));
         tm.mark(T_CHECK);
         HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));
         tm.mark(T_CLAUSE);

@@ -7,32 +7,31 @@
 // (a*tid + b*bid + c) mod words (Euclidean residue), and the executing
 // threads are those with tid % m == r.  Items coincide with the sort's
 // chunks: while writing, an item counts the radix digits of the first sort
-// pass in LDS and stores them as its chunk's count row.
+// pass in LDS and stores them as its chunk's count row.  The item's points
+// (up to 256, from its first point on) are staged in LDS first.
 #include "common.h"
 #include "launch.h"
 
 namespace rp {
 
 constexpr int GEN_BLOCK = 256;
+constexpr uint32_t GEN_CACHE = 256;   // points staged in LDS per item
 
 template <int RB>
-__device__ __forceinline__ void count_digits(uint32_t* hist, uint64_t rec, int shift,
-                                             int passes, bool valid) {
+__device__ __forceinline__ void count_digits(uint32_t* hist, uint64_t rec, int shift, bool valid) {
   constexpr uint32_t R = 1u << RB;
   const uint64_t act = __ballot(valid);
   if (!valid) return;
   const int first = __ffsll((unsigned long long)act) - 1;
-  for (int p = 0; p < passes; p++) {
-    const uint32_t d = digit_at(rec, shift + p * RB, R - 1);
-    const uint32_t d0 = __shfl(d, first);
-    // all active lanes on one digit (the usual case for the high digits):
-    // one LDS add for the wave
-    const uint64_t same = __ballot(d == d0);
-    if (same == act) {
-      if ((int)__lane_id() == first) atomicAdd(&hist[p * R + d], (uint32_t)__popcll(act));
-    } else {
-      atomicAdd(&hist[p * R + d], 1u);
-    }
+  const uint32_t d = digit_at(rec, shift, R - 1);
+  const uint32_t d0 = __shfl(d, first);
+  // all active lanes on one digit (the usual case for the high digits):
+  // one LDS add for the wave
+  const uint64_t same = __ballot(d == d0);
+  if (same == act) {
+    if ((int)__lane_id() == first) atomicAdd(&hist[d], (uint32_t)__popcll(act));
+  } else {
+    atomicAdd(&hist[d], 1u);
   }
 }
 
@@ -44,40 +43,53 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
                                                         uint32_t* __restrict__ item_hist,
                                                         int passes) {
   constexpr uint32_t R = 1u << RB;
-  __shared__ uint32_t hist[MAX_SORT_PASSES * R];
+  __shared__ uint32_t hist[R];
+  __shared__ DPoint s_pts[GEN_CACHE];        // points i0, i0+1, ... (mod P) of the item
+  __shared__ uint64_t s_cnt[GEN_CACHE];      // their records (per block in the same-block log)
   __shared__ uint32_t s_i;
   const GenItem it = items[blockIdx.x];
   const Job& J = jobs[it.job];
   const SortSeg sg = segs[it.seg];
   const int shift = (int)sg.shift;
+  const int count = passes > 0;
   uint64_t* out = recs + sg.beg;
-  for (uint32_t q = threadIdx.x; q < (uint32_t)passes * R; q += GEN_BLOCK) hist[q] = 0;
+  for (uint32_t q = threadIdx.x; q < R; q += GEN_BLOCK) hist[q] = 0;
   const uint32_t ks = J.key_shift, tb = J.tbits, bb = J.bbits, pb = J.pbits, nb = J.nbits;
   const uint32_t P = J.P;
   // first point of the item: largest i with prefix[i] <= offset
   const uint64_t* pre = it.view == 0 ? J.cnt_pre : J.gcnt_pre;
-  const uint64_t scale = it.view == 0 ? 1 : J.B;
-  uint64_t first = it.view == 0 ? it.o0 % J.rblk : it.o0;
+  const uint64_t first = it.view == 0 ? it.o0 % J.rblk : it.o0;
   if (threadIdx.x == 0) {
     uint32_t lo = 0, hi = P - 1;
     while (lo < hi) {
       const uint32_t mid = (lo + hi + 1) >> 1;
-      if (pre[mid] * scale <= first) lo = mid; else hi = mid - 1;
+      if (pre[mid] <= first) lo = mid; else hi = mid - 1;
     }
     s_i = lo;
   }
   __syncthreads();
-  uint32_t i = s_i;
+  const uint32_t i0 = s_i;
+  const uint32_t nc = P < GEN_CACHE ? P : GEN_CACHE;
+  for (uint32_t d = threadIdx.x; d < nc; d += GEN_BLOCK) {
+    uint32_t i = i0 + d;
+    if (i >= P) i -= P;
+    s_pts[d] = J.pts[i];
+    s_cnt[d] = pre[i + 1] - pre[i];
+  }
+  __syncthreads();
+  uint32_t i = i0;
+  uint32_t d = 0;            // cache slot of point i (i0 + d mod P)
   uint64_t pos = it.o0;
   if (it.view == 0) {
     // block-major: block k, points in order, executing threads in order
     uint32_t k = (uint32_t)(it.o0 / J.rblk);
     uint64_t u0 = first - pre[i];
     while (pos < it.o1) {
-      const uint64_t c = pre[i + 1] - pre[i];
+      const bool cached = d < nc;
+      const uint64_t c = cached ? s_cnt[d] : pre[i + 1] - pre[i];
       const uint64_t take = (c - u0) < (it.o1 - pos) ? (c - u0) : (it.o1 - pos);
       if (take) {
-        const DPoint p = J.pts[i];
+        const DPoint p = cached ? s_pts[d] : J.pts[i];
         const uint64_t arr = (uint64_t)p.array << nb;
         const uint64_t low = ((uint64_t)k << (pb + tb)) | ((uint64_t)i << tb);
         for (uint64_t q0 = 0; q0 < take; q0 += GEN_BLOCK) {
@@ -89,24 +101,26 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
             rec = ((arr | word_of(p, t, k)) << ks) | low | t;
             out[pos + q] = rec;
           }
-          count_digits<RB>(hist, rec, shift, passes, valid);
+          if (count) count_digits<RB>(hist, rec, shift, valid);
         }
       }
       pos += take;
       u0 = 0;
+      d++;
       if (++i == P) { i = 0; k++; }
     }
   } else {
     // point-major over GLOBAL access points: point i, blocks in order,
-    // executing threads in order
-    uint64_t j0 = first - pre[i] * J.B;
+    // executing threads in order (one thread when the word does not depend
+    // on it; blocks 0 and 1 only when it does not depend on the block)
+    uint64_t j0 = first - pre[i];
     while (pos < it.o1) {
-      const uint64_t c = pre[i + 1] - pre[i];
-      const uint64_t span = c * J.B;
+      const bool cached = d < nc;
+      const uint64_t span = cached ? s_cnt[d] : pre[i + 1] - pre[i];
       const uint64_t take = (span - j0) < (it.o1 - pos) ? (span - j0) : (it.o1 - pos);
       if (take) {
-        const DPoint p = J.pts[i];
-        const uint32_t cnt = (uint32_t)c;
+        const DPoint p = cached ? s_pts[d] : J.pts[i];
+        const uint32_t cnt = (p.flags & PF_TCONST) ? 1u : p.cnt;
         const uint64_t arr = (uint64_t)p.array << nb;
         const uint64_t pf = (uint64_t)i << (bb + tb);
         for (uint64_t q0 = 0; q0 < take; q0 += GEN_BLOCK) {
@@ -115,23 +129,31 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
           uint64_t rec = 0;
           if (valid) {
             const uint64_t j = j0 + q;
-            const uint32_t kk = (uint32_t)(j / cnt);
-            const uint32_t u = (uint32_t)(j - (uint64_t)kk * cnt);
+            uint32_t kk, u;
+            if (span < (1ull << 32)) {
+              kk = (uint32_t)j / cnt;
+              u = (uint32_t)j - kk * cnt;
+            } else {
+              kk = (uint32_t)(j / cnt);
+              u = (uint32_t)(j - (uint64_t)kk * cnt);
+            }
             const uint32_t t = p.r + p.m * u;
             rec = ((arr | word_of(p, t, kk)) << ks) | pf | ((uint64_t)kk << tb);
             out[pos + q] = rec;
           }
-          count_digits<RB>(hist, rec, shift, passes, valid);
+          if (count) count_digits<RB>(hist, rec, shift, valid);
         }
       }
       pos += take;
       j0 = 0;
+      d++;
       i++;
     }
   }
+  if (!count) return;
   __syncthreads();
-  uint32_t* row = item_hist + (size_t)blockIdx.x * passes * R;
-  for (uint32_t q = threadIdx.x; q < (uint32_t)passes * R; q += GEN_BLOCK) row[q] = hist[q];
+  uint32_t* row = item_hist + (size_t)blockIdx.x * R;
+  for (uint32_t q = threadIdx.x; q < R; q += GEN_BLOCK) row[q] = hist[q];
 }
 
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,

@@ -111,6 +111,9 @@ void make_plan(const rp_kernel* k, Plan& pl) {
       if (p.is_write) d.flags |= PF_WRITE;
       if (a.space == RP_GLOBAL) d.flags |= PF_GLOBAL;
       if ((a.words & (a.words - 1)) == 0) d.flags |= PF_POW2;
+      const int64_t nw = (int64_t)a.words;
+      if ((int64_t)p.a % nw == 0) d.flags |= PF_TCONST;
+      if ((int64_t)p.b % nw == 0) d.flags |= PF_BCONST;
       pl.accesses += (uint64_t)d.cnt * pl.B;
     }
     if (p.kind == RP_BARRIER) {
@@ -118,9 +121,19 @@ void make_plan(const rp_kernel* k, Plan& pl) {
       if (k->slots[p.slot].level == RP_GRID) pl.bits_grid[i] = 1ull << p.slot;
       if (d.cnt > 0 && d.cnt < pl.T) pl.div_if_enabled |= 1ull << p.slot;
     }
-    const uint64_t ca = p.kind == RP_ACCESS ? d.cnt : 0;
-    pl.cnt_pre[i + 1] = pl.cnt_pre[i] + ca;
-    pl.gcnt_pre[i + 1] = pl.gcnt_pre[i] + ((p.kind == RP_ACCESS && (d.flags & PF_GLOBAL)) ? ca : 0);
+    // records emitted per point (the reductions are listed in common.h)
+    uint64_t intra = 0, inter = 0;
+    if (p.kind == RP_ACCESS) {
+      const bool tc = d.flags & PF_TCONST;
+      intra = tc ? std::min<uint64_t>(d.cnt, 2) : d.cnt;
+      if ((d.flags & PF_GLOBAL) && pl.B > 1) {
+        const uint64_t per_block = tc ? std::min<uint64_t>(d.cnt, 1) : d.cnt;
+        const uint64_t blocks = (d.flags & PF_BCONST) ? 2 : pl.B;
+        inter = per_block * blocks;
+      }
+    }
+    pl.cnt_pre[i + 1] = pl.cnt_pre[i] + intra;
+    pl.gcnt_pre[i + 1] = pl.gcnt_pre[i] + inter;
   }
   pl.weights.assign(pl.S, 0);
   pl.grid_slots = pl.pre_slots = 0;
@@ -130,7 +143,7 @@ void make_plan(const rp_kernel* k, Plan& pl) {
     if (k->slots[s].preexisting) pl.pre_slots |= 1ull << s;
   }
   pl.n_intra = pl.cnt_pre[pl.P] * pl.B;
-  pl.n_inter = pl.gcnt_pre[pl.P] * pl.B;
+  pl.n_inter = pl.gcnt_pre[pl.P];
 }
 
 int pick_digit_bits(uint32_t key_bits) {

@@ -12,8 +12,8 @@ struct Plan {
   std::vector<DPoint> pts;
   std::vector<uint64_t> bits_any, bits_grid;
   std::vector<uint32_t> weights;
-  std::vector<uint64_t> cnt_pre;    // prefix of executing threads over access points
-  std::vector<uint64_t> gcnt_pre;   // the same over access points of GLOBAL arrays
+  std::vector<uint64_t> cnt_pre;    // prefix of same-block records per block over points
+  std::vector<uint64_t> gcnt_pre;   // prefix of cross-block records over points
   uint64_t div_if_enabled = 0, grid_slots = 0, pre_slots = 0;
   uint64_t n_intra = 0, n_inter = 0, accesses = 0;
 };
@@ -66,9 +66,10 @@ size_t engine_job_bytes(const JobInput& job);
 int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStream_t s,
                        PreparedJob& out, std::vector<uint8_t>& staging);
 // Enqueues one round (Verify, GenerateClause, Solve, active count) over
-// device tables of njobs jobs and nseg logs.
-int engine_round(const Job* djobs, uint32_t njobs, const ConfSeg* dcs, uint32_t nseg,
-                 uint32_t n_conf_tiles, uint32_t maxP, uint32_t* dactive, hipStream_t s);
+// device tables of njobs jobs and nseg logs.  dactive points to two device
+// words: the count of running jobs after the round and the round's tile count.
+int engine_round(const Job* djobs, uint32_t njobs, ConfSeg* dcs, uint32_t nseg, uint32_t maxP,
+                 uint32_t* dactive, hipStream_t s);
 
 // Runs the op over all jobs; returns RP_OK or an error status.
 int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws, size_t ws_bytes,

@@ -12,16 +12,17 @@
 //   runs_count_kernel  run heads per tile of 4096 records
 //   runs_scan_kernel   per log: exclusive scan of the tile counts, run total
 //   runs_write_kernel  per tile: the entries of the runs that start in it
+// Records are read coalesced, one per lane; run heads and run ends come from
+// 64-lane ballots.
 #include "common.h"
 #include "launch.h"
 
 namespace rp {
 
 constexpr int RB_BLOCK = 256;
-constexpr int RB_PER = 16;                             // contiguous records per thread
-constexpr uint32_t RB_TILE = RB_BLOCK * RB_PER;       // 4096 records
-constexpr uint32_t RB_LOOK = 1024;                     // staged past the tile
-constexpr uint32_t RB_WIN = RB_TILE + RB_LOOK;
+constexpr int RB_WAVES = RB_BLOCK / 64;
+constexpr int RB_ROUNDS = 16;                          // block-wide rows of 256 records
+constexpr uint32_t RB_TILE = RB_BLOCK * RB_ROUNDS;    // 4096 records
 
 struct ViewBits {
   int psh, lsh, ish;     // point field, location, id shifts
@@ -50,33 +51,40 @@ __device__ __forceinline__ int find_seg_by_btile(const ConfSeg* segs, int nseg, 
   return lo;
 }
 
+// Record q of a log and the one before it (coalesced: lane k reads q0 + k;
+// the predecessor comes from the lane below, lane 0 reads it).
+__device__ __forceinline__ void rec_and_prev(const uint64_t* log, uint64_t q, uint64_t n,
+                                             uint64_t& v, uint64_t& pr) {
+  v = q < n ? log[q] : 0;
+  pr = __shfl_up(v, 1);
+  if (__lane_id() == 0) pr = (q > 0 && q <= n) ? log[q - 1] : 0;
+}
+
 __global__ __launch_bounds__(RB_BLOCK) void runs_count_kernel(const Job* __restrict__ jobs,
                                                               const ConfSeg* __restrict__ segs,
                                                               int nseg, uint32_t* __restrict__ cnt) {
-  __shared__ uint64_t s_rec[RB_TILE];
-  __shared__ uint32_t s_sum[RB_BLOCK / 64];
+  __shared__ uint32_t s_sum[RB_WAVES];
   const uint32_t tile = blockIdx.x;
   const int si = find_seg_by_btile(segs, nseg, tile);
-  const ConfSeg sg = segs[si];
+  const ConfSeg& sg = segs[si];
   const ViewBits vb = view_bits(jobs[sg.job], sg.level);
   const uint64_t base = (uint64_t)(tile - sg.btile_beg) * RB_TILE;
-  const uint32_t len = (uint32_t)((sg.n - base) < RB_TILE ? (sg.n - base) : RB_TILE);
-  for (uint32_t q = threadIdx.x; q < len; q += RB_BLOCK) s_rec[q] = sg.log[base + q];
-  const uint64_t prev = base > 0 ? sg.log[base - 1] : 0;
-  __syncthreads();
+  const uint64_t n = sg.n;
   uint32_t c = 0;
-  for (uint32_t q = 0; q < RB_PER; q++) {
-    const uint32_t p = threadIdx.x * RB_PER + q;
-    if (p >= len) break;
-    const uint64_t v = s_rec[p];
-    if (p == 0 && base == 0) { c++; continue; }
-    const uint64_t pr = p ? s_rec[p - 1] : prev;
-    if ((pr >> vb.psh) != (v >> vb.psh)) c++;
+  for (int k = 0; k < RB_ROUNDS; k++) {
+    const uint64_t q = base + (uint64_t)k * RB_BLOCK + threadIdx.x;
+    uint64_t v, pr;
+    rec_and_prev(sg.log, q, n, v, pr);
+    const bool head = q < n && (q == 0 || (pr >> vb.psh) != (v >> vb.psh));
+    c += (uint32_t)__popcll(__ballot(head));
   }
-  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
   if (__lane_id() == 0) s_sum[threadIdx.x >> 6] = c;
   __syncthreads();
-  if (threadIdx.x == 0) cnt[tile] = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < RB_WAVES; w++) t += s_sum[w];
+    cnt[tile] = t;
+  }
 }
 
 // One workgroup per log: exclusive scan of its tile counts.
@@ -110,95 +118,87 @@ __global__ __launch_bounds__(1024) void runs_scan_kernel(ConfSeg* segs, const ui
   if (threadIdx.x == 0) sg.n_runs = run;
 }
 
+// Entries of the runs that start in one tile.  Rows of 256 consecutive
+// records, one per thread, kept in registers across the two passes; a run's
+// end is the next head in the wave's 64 records, else it is followed in
+// global memory (exponential then binary search for long runs).
 __global__ __launch_bounds__(RB_BLOCK) void runs_write_kernel(const Job* __restrict__ jobs,
                                                               const ConfSeg* __restrict__ segs,
                                                               int nseg,
                                                               const uint64_t* __restrict__ off) {
-  __shared__ uint64_t s_rec[RB_WIN];
-  __shared__ uint32_t s_head[RB_WIN / 32];
-  __shared__ uint32_t s_sum[RB_BLOCK / 64];
-  __shared__ uint64_t s_prev;
+  __shared__ uint32_t s_cnt[RB_ROUNDS * RB_WAVES];
+  __shared__ uint64_t s_pre[RB_ROUNDS * RB_WAVES];
   const uint32_t tile = blockIdx.x;
   const int si = find_seg_by_btile(segs, nseg, tile);
-  const ConfSeg sg = segs[si];
+  const ConfSeg& sg = segs[si];
   const Job& J = jobs[sg.job];
   const ViewBits vb = view_bits(J, sg.level);
   const uint64_t n = sg.n;
+  const uint64_t* __restrict__ log = sg.log;
   const uint64_t base = (uint64_t)(tile - sg.btile_beg) * RB_TILE;
-  const uint32_t wlen = (uint32_t)((n - base) < RB_WIN ? (n - base) : RB_WIN);
-  const uint32_t own = wlen < RB_TILE ? wlen : RB_TILE;
-  for (uint32_t q = threadIdx.x; q < wlen; q += RB_BLOCK) s_rec[q] = sg.log[base + q];
-  for (uint32_t q = threadIdx.x; q < RB_WIN / 32; q += RB_BLOCK) s_head[q] = 0;
-  if (threadIdx.x == 0) s_prev = base > 0 ? sg.log[base - 1] : 0;
-  __syncthreads();
-  // head bits over the whole window
-  for (uint32_t p = threadIdx.x; p < wlen; p += RB_BLOCK) {
-    bool h;
-    if (p == 0) h = base == 0 || (s_prev >> vb.psh) != (s_rec[0] >> vb.psh);
-    else h = (s_rec[p - 1] >> vb.psh) != (s_rec[p] >> vb.psh);
-    if (h) atomicOr(&s_head[p >> 5], 1u << (p & 31));
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  uint64_t vv[RB_ROUNDS], pp[RB_ROUNDS], hh[RB_ROUNDS];
+  // pass 1: head masks per (row, wave), in record order
+#pragma unroll
+  for (int k = 0; k < RB_ROUNDS; k++) {
+    const uint64_t q = base + (uint64_t)k * RB_BLOCK + threadIdx.x;
+    rec_and_prev(log, q, n, vv[k], pp[k]);
+    hh[k] = __ballot(q < n && (q == 0 || (pp[k] >> vb.psh) != (vv[k] >> vb.psh)));
+    if (lane == 0) s_cnt[k * RB_WAVES + wv] = (uint32_t)__popcll(hh[k]);
   }
   __syncthreads();
-  // ranks of the owned heads (contiguous positions per thread keep run order)
-  const uint32_t p0 = threadIdx.x * RB_PER;
-  uint32_t mine = 0;
-  for (uint32_t q = 0; q < RB_PER; q++) {
-    const uint32_t p = p0 + q;
-    if (p < own && ((s_head[p >> 5] >> (p & 31)) & 1)) mine++;
-  }
-  uint32_t inc = mine;
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
-  }
-  if (lane == 63) s_sum[w] = inc;
-  __syncthreads();
-  uint32_t pre = 0;
-  for (int q = 0; q < w; q++) pre += s_sum[q];
-  uint64_t idx = off[tile] + pre + inc - mine;
-  for (uint32_t q = 0; q < RB_PER; q++) {
-    const uint32_t p = p0 + q;
-    if (p >= own || !((s_head[p >> 5] >> (p & 31)) & 1)) continue;
-    const uint64_t v = s_rec[p];
-    // run end: the next head in the window, else past it
-    uint32_t e = p + 1;
-    while (e < wlen && !((s_head[e >> 5] >> (e & 31)) & 1)) {
-      if ((e & 31) == 0 && s_head[e >> 5] == 0) { e += 32; continue; }
-      e++;
+  if (threadIdx.x == 0) {
+    uint64_t t = off[tile];
+    for (int q = 0; q < RB_ROUNDS * RB_WAVES; q++) {
+      s_pre[q] = t;
+      t += s_cnt[q];
     }
-    uint64_t last;
-    uint64_t glen;   // run length, exact when it ends inside the window
-    if (e < wlen || base + wlen == n) {
-      if (e > wlen) e = wlen;
-      last = s_rec[e - 1];
-      glen = e - p;
+  }
+  __syncthreads();
+  // pass 2: entries
+#pragma unroll
+  for (int k = 0; k < RB_ROUNDS; k++) {
+    const uint64_t q = base + (uint64_t)k * RB_BLOCK + threadIdx.x;
+    const uint64_t v = vv[k], pr = pp[k], hm = hh[k];
+    const bool head = (hm >> lane) & 1;
+    const uint64_t above = lane == 63 ? 0ull : (hm >> (lane + 1));
+    const int nxt = above ? lane + __ffsll((unsigned long long)above) : 64;   // next head lane
+    const uint64_t last_in = __shfl(v, nxt - 1);
+    if (!head) continue;
+    const uint64_t q_end = q - lane + 64;        // first record past the wave's 64
+    uint64_t last, len;
+    if (nxt < 64) {                              // ends inside the wave
+      last = last_in;
+      len = (uint64_t)(nxt - lane);
+    } else if (q_end >= n) {                     // ends with the log
+      last = log[n - 1];
+      len = n - q;
     } else {
-      // the run continues past the window: find its end in global memory
+      // the run reaches past the wave: find its end in global memory
       const uint64_t pv = v >> vb.psh;
-      uint64_t lo = base + wlen - 1, step = 1, hi;
+      uint64_t lo = q_end - 1, step = 1, hi;
       for (;;) {
         hi = lo + step;
         if (hi >= n) { hi = n; break; }
-        if ((sg.log[hi] >> vb.psh) != pv) break;
+        if ((log[hi] >> vb.psh) != pv) break;
         lo = hi;
         step <<= 1;
       }
       while (hi - lo > 1) {
         const uint64_t mid = lo + ((hi - lo) >> 1);
-        if ((sg.log[mid] >> vb.psh) == pv) lo = mid; else hi = mid;
+        if ((log[mid] >> vb.psh) == pv) lo = mid; else hi = mid;
       }
-      last = sg.log[hi - 1];
-      glen = hi - (base + p);
+      last = log[hi - 1];
+      len = hi - q;
     }
     const uint64_t id = (v >> vb.ish) & vb.imask;
-    const bool multi = sg.level == 0 ? glen >= 2 : ((last >> vb.ish) & vb.imask) != id;
-    const uint64_t prv = p ? s_rec[p - 1] : s_prev;
-    const bool locstart = (p == 0 && base == 0) || (prv >> vb.lsh) != (v >> vb.lsh);
+    const bool multi = sg.level == 0 ? len >= 2 : ((last >> vb.ish) & vb.imask) != id;
+    const bool locstart = q == 0 || (pr >> vb.lsh) != (v >> vb.lsh);
     const uint32_t i = (uint32_t)(v >> vb.psh) & vb.pmask;
     const bool wr = i < J.P && (J.pts[i].flags & PF_WRITE);
-    sg.runs[idx++] = id | ((uint64_t)i << RUN_PT) | ((uint64_t)wr << RUN_W) |
-                     ((uint64_t)multi << RUN_MULTI) | ((uint64_t)locstart << RUN_LOC);
+    const uint64_t idx = s_pre[k * RB_WAVES + wv] + (uint64_t)__popcll(hm & lanemask_lt());
+    sg.runs[idx] = id | ((uint64_t)i << RUN_PT) | ((uint64_t)wr << RUN_W) |
+                   ((uint64_t)multi << RUN_MULTI) | ((uint64_t)locstart << RUN_LOC);
   }
 }
 

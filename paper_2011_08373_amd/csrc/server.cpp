@@ -249,8 +249,7 @@ rp_status rp_server_step(void* srv, uint32_t* n_resident, uint32_t* n_pending) {
     // 2. one round over every resident job
     sv->h_jobs.resize(n);
     sv->h_segs.clear();
-    uint32_t tiles = 0, maxP = 1;
-    const uint32_t ct = conf_tile_size();
+    uint32_t maxP = 1;
     for (uint32_t q = 0; q < n; q++) {
       SJob& j = *sv->resident[q];
       sv->h_jobs[q] = j.prep.job;
@@ -258,8 +257,7 @@ rp_status rp_server_step(void* srv, uint32_t* n_resident, uint32_t* n_pending) {
       for (uint32_t g = 0; g < j.prep.nseg; g++) {
         ConfSeg c = j.prep.segs[g];
         c.job = q;
-        c.ctile_beg = tiles;
-        tiles += (uint32_t)((j.prep.n_rec[g] + ct - 1) / ct);
+        c.ctile_beg = 0;     // laid out on the device each round
         sv->h_segs.push_back(c);
       }
     }
@@ -269,8 +267,8 @@ rp_status rp_server_step(void* srv, uint32_t* n_resident, uint32_t* n_pending) {
          hipMemcpyAsync(sv->d_segs, sv->h_segs.data(), sv->h_segs.size() * sizeof(ConfSeg),
                         hipMemcpyHostToDevice, s) != hipSuccess))
       return RP_ERR_DEVICE;
-    const int rc = engine_round(sv->d_jobs, n, sv->d_segs, (uint32_t)sv->h_segs.size(), tiles,
-                                maxP, sv->d_active, s);
+    const int rc = engine_round(sv->d_jobs, n, sv->d_segs, (uint32_t)sv->h_segs.size(), maxP,
+                                sv->d_active, s);
     if (rc != RP_OK) return (rp_status)rc;
     gather_states_kernel<<<(n + 255) / 256, 256, 0, s>>>(sv->d_jobs, n, sv->d_states);
     sv->h_states.resize(n);
