@@ -51,6 +51,73 @@ def cpu_baseline(km, rounds_gpu):
                 matches_gpu_rounds=r["rounds"] == rounds_gpu)
 
 
+def run_main(L, torch, km, steps, warmup):
+    """Times `steps` full rp_repair calls on one kernel (inputs resident)."""
+    ws = L.Workspace()
+    ws.get(L.workspace_bytes(km, L.OP_REPAIR))
+    for _ in range(warmup):
+        L.repair(km, ws=ws)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = L.repair(km, ws=ws)
+        stats.append(L.last_stats())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    del ws
+    return r, (t1 - t0) * 1e3 / steps, stats
+
+
+def _traffic(kernel):
+    """HBM bytes per launch from committed counter data, if the kernel's
+    source is unchanged since the counters were taken; else None."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        data = json.load(fh)
+    e = data.get(kernel)
+    if not e:
+        return None
+    src = os.path.join(ROOT, e["source"])
+    if not os.path.exists(src):
+        return None
+    with open(src, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != e["sha256"]:
+            return None
+    return e["bytes_per_launch"]
+
+
+def kernel_rooflines(stats):
+    """Algorithmic bytes per launch / average hipEvent launch time, for the
+    kernels timed one by one on the library's stream."""
+    n = len(stats)
+    last = stats[-1]
+    rec, runs = last["records"], last["runs"]
+    out = {}
+
+    def entry(name, bytes_per_launch, total_ms, launches):
+        if launches <= 0 or total_ms <= 0:
+            return
+        avg = total_ms / launches
+        gbs = bytes_per_launch / (avg / 1e3) / 1e9
+        out[name] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic(name),
+                     "avg_launch_ms": avg, "bytes_per_launch": bytes_per_launch,
+                     "ms_per_step": total_ms / n}
+    # radix scatter pass: reads and writes 8 B per record
+    entry("scatter_kernel", 16 * rec, sum(s["ms_sort_kernels"] for s in stats),
+          sum(s["sort_launches"] for s in stats))
+    # conflict scan: reads 8 B per run-log entry
+    entry("conf_kernel", 8 * runs, sum(s["ms_conf_kernels"] for s in stats),
+          sum(s["conf_launches"] for s in stats))
+    # record generation: writes 8 B per record
+    entry("gen_kernel", 8 * rec, sum(s["ms_gen"] for s in stats), n)
+    return out
+
+
 def batched_leg(L, torch, kms):
     """One batched call over all kernels vs the plain per-kernel loop."""
     from paper_2011_08373_amd import autotune
@@ -136,7 +203,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="literal", choices=("literal", "planted"))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--legs", default="main,batched,served")
+    ap.add_argument("--legs", default="main,planted,batched,served")
     ap.add_argument("--batched-n", type=int, default=1024)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -159,29 +226,15 @@ def main():
         torch.cuda.synchronize()
         del a, b
     km = synth.generate("plain-large", mode=args.mode)
-    ws = L.Workspace()
-    ws.get(L.workspace_bytes(km, L.OP_REPAIR))
-    for _ in range(args.warmup):
-        L.repair(km, ws=ws)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = L.repair(km, ws=ws)
-        stats.append(L.last_stats())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    r, ms, stats = run_main(L, torch, km, args.steps, args.warmup)
     acc = stats[-1]["accesses"]
     km.meta["accesses"] = acc
     checked = acc * r["rounds"]
     value = checked / (ms / 1e3)
-    # dominant kernel: the radix-sort pass (reads and writes 8 B per record)
-    launches = sum(s["sort_launches"] for s in stats)
-    kms = sum(s["ms_sort_kernels"] for s in stats)
-    rec = stats[-1]["records"]
-    pass_ms = kms / max(1, launches)
-    achieved = 16.0 * rec / (pass_ms / 1e3) / 1e9 if pass_ms > 0 else 0.0
+    kern = kernel_rooflines(stats)
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    roof = dict(kern[dom])
+    roof["kernel"] = dom
     out = {
         "metric": "race-checked accesses/sec",
         "value": value,
@@ -198,20 +251,37 @@ def main():
         "config": {"workload": "plain-large %s: 256 blocks x 256 threads, 512 points, "
                                "32 slots (8 grid), 2 shared + 2 global arrays of 1M words, "
                                "seed 2" % args.mode,
-                   "accesses": acc, "records": rec, "verify_calls": r["rounds"],
-                   "repair_status": r["status"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "scatter_kernel (one radix pass: reads and writes 8 B per record)",
-                     "avg_launch_ms": pass_ms},
+                   "accesses": acc, "records": stats[-1]["records"], "runs": stats[-1]["runs"],
+                   "verify_calls": r["rounds"], "repair_status": r["status"]},
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
+                                          "kernel", "avg_launch_ms", "bytes_per_launch")},
+        "kernels": kern,
+        # warm: Verify on the resident run log (the conflict-scan kernel of
+        # each round); cold: the whole repair, generation and sort included
+        "warm_check_accesses_per_s": (acc * sum(s["conf_launches"] for s in stats) /
+                                      (sum(s["ms_conf_kernels"] for s in stats) / 1e3)
+                                      if sum(s["ms_conf_kernels"] for s in stats) > 0 else None),
         "phases_ms": {k: sum(s[k] for s in stats) / len(stats)
-                      for k in ("ms_gen", "ms_sort", "ms_runs", "ms_check", "ms_clause", "ms_solve",
-                                "ms_total")},
+                      for k in ("ms_upload", "ms_gen", "ms_sort", "ms_runs", "ms_check",
+                                "ms_clause", "ms_solve", "ms_total")},
     }
+    if args.mode == "literal" and "planted" in set(args.legs.split(",")):
+        # context: the same kernel with a planted safe barrier set (repair
+        # runs several Verify calls and ends SAFE)
+        kp = synth.generate("plain-large", mode="planted")
+        rp, msp, stp = run_main(L, torch, kp, max(1, args.steps // 2), 1)
+        kp_acc = stp[-1]["accesses"]
+        kk = kernel_rooflines(stp)
+        out["planted"] = {"value": kp_acc * rp["rounds"] / (msp / 1e3), "ms_per_step": msp,
+                          "verify_calls": rp["rounds"], "repair_status": rp["status"],
+                          "weight": rp["weight"],
+                          "conf_kernel_frac": kk["conf_kernel"]["frac"],
+                          "phases_ms": {k: sum(s[k] for s in stp) / len(stp)
+                                        for k in ("ms_gen", "ms_sort", "ms_runs", "ms_check",
+                                                  "ms_clause", "ms_solve", "ms_total")}}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(km, r["rounds"])
     legs = set(args.legs.split(","))
-    del ws
     torch.cuda.empty_cache()
     if "batched" in legs or "served" in legs:
         kms = synth.generate_batch(n=args.batched_n, mode="planted")

@@ -135,6 +135,10 @@ typedef struct {
   uint64_t accesses;             /* (point, block, thread) accesses */
   uint64_t records_scanned;      /* records read by conflict scans */
   uint32_t sort_passes, sort_launches, rounds, conf_launches;
+  double ms_upload;              /* descriptor upload before record generation */
+  double ms_conf_kernels;        /* sum of the conflict-scan kernel durations
+                                    (rounds run outside a graph only) */
+  uint64_t runs;                 /* run-log entries (both views, all kernels) */
 } rp_stats;
 
 const char* rp_status_string(int status);

@@ -120,25 +120,48 @@ __device__ __forceinline__ uint64_t run_at(const uint64_t* runs, uint64_t q, uin
   return q < n ? runs[q] : RUN_SENTINEL;
 }
 
+constexpr uint64_t NOPOS = ~0ull;
+
+// First write run at or after position q, before the next location starts
+// (NOPOS if none): wave-cooperative, 64 runs at a time.  A location holds at
+// most one run per point, so this ends within P / 64 + 1 steps.
+__device__ uint64_t first_write_from(const uint64_t* runs, uint64_t q, uint64_t n) {
+  for (; q < n; q += 64) {
+    const uint64_t e = run_at(runs, q + __lane_id(), n);
+    const uint64_t wm = __ballot((e >> RUN_W) & 1);
+    const uint64_t lm = __ballot((e >> RUN_LOC) & 1);
+    if (wm && (!lm || __ffsll((unsigned long long)wm) < __ffsll((unsigned long long)lm)))
+      return q + __ffsll((unsigned long long)wm) - 1;
+    if (lm) return NOPOS;
+  }
+  return NOPOS;
+}
+
 // Racing partners over the run log.  A sub-segment (one location, one
-// interval) is a contiguous stretch of runs.  Each wave streams a range of
-// the log in chunks of 64 runs, one run per lane, with the next chunk as a
-// window: ballots give the sub-segment starts, writes and multi runs of the
-// window as 64-bit masks, so a lane finds the runs after its own in its
-// sub-segment with a few mask operations and tests them in order.  Only a
-// sub-segment that runs past the window is followed in global memory.
+// interval) is a contiguous stretch of runs.  Each wave stages a range of
+// 1024 runs in LDS (all loads in flight at once) and walks it in chunks of
+// 64, one run per lane, from the last chunk to the first.  Inside a chunk,
+// ballots give sub-segment starts, writes and multi runs as 64-bit masks, so
+// a lane finds the runs after its own with mask operations.  Past its chunk,
+// a reading run can only race with the first write that follows in its
+// location: the wave carries that position from chunk to chunk (backwards),
+// so a read costs O(1) however long its sub-segment is.  A writing run's next
+// candidate past the chunk is the next run.  Only a candidate rejected for
+// being the same single thread (block) leads to a walk.
 template <bool ALL>
 __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict__ jobs,
                                                           const ConfSeg* __restrict__ segs,
                                                           int nseg,
                                                           const uint32_t* __restrict__ total_at) {
-  __shared__ uint64_t s_e[CONF_WAVES][128];
+  __shared__ uint64_t s_buf[CONF_WAVES][CONF_CHUNKS * 64];
   extern __shared__ uint32_t s_dyn[];        // [P] interval of each point, [P] first partner
   const uint32_t total = *total_at;
   const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
   const uint32_t t0 = blockIdx.x * per;
   const uint32_t t1 = min(t0 + per, total);
   const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
+  const uint64_t gt = lane == 63 ? 0ull : (~0ull << (lane + 1));
+  uint64_t* buf = s_buf[wv];
   int cur = -1;
   uint32_t* s_iv = s_dyn;
   uint32_t* s_minj = s_dyn;
@@ -173,97 +196,82 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
     const uint64_t n = sg.n_runs_at ? *sg.n_runs_at : sg.n_runs;
     const uint64_t wbeg = (uint64_t)(tile - sg.ctile_beg) * CONF_TILE + (uint64_t)wv * (CONF_CHUNKS * 64);
     if (wbeg >= n) continue;
+    const uint64_t wend = min(wbeg + (uint64_t)(CONF_CHUNKS * 64), n);
     const Job& J = jobs[sg.job];
     const uint32_t level = sg.level;
     const uint64_t* __restrict__ runs = sg.runs;
-    uint64_t e0 = run_at(runs, wbeg + lane, n);
-    uint64_t e1 = run_at(runs, wbeg + 64 + lane, n);
-    for (int c = 0; c < CONF_CHUNKS; c++) {
+    // stage the range
+#pragma unroll
+    for (int k = 0; k < CONF_CHUNKS; k++) buf[k * 64 + lane] = run_at(runs, wbeg + k * 64 + lane, n);
+    // first write past the range in the same location
+    uint64_t carry = first_write_from(runs, wend, n);
+    __builtin_amdgcn_wave_barrier();
+    // entry at an absolute position: staged or global
+    auto entry = [&](uint64_t q) -> uint64_t {
+      return q < wend ? buf[q - wbeg] : run_at(runs, q, n);
+    };
+    const int nch = (int)((wend - wbeg + 63) / 64);
+    for (int c = nch - 1; c >= 0; c--) {
       const uint64_t p0 = wbeg + (uint64_t)c * 64;
-      if (p0 >= n) break;
-      const uint64_t e2 = run_at(runs, p0 + 128 + lane, n);   // next window, in flight
-      // decode the window: own chunk e0, lookahead chunk e1
-      const bool v0 = !((e0 >> RUN_END) & 1), v1 = !((e1 >> RUN_END) & 1);
-      const uint32_t i0 = (uint32_t)(e0 >> RUN_PT) & 0xFFFu;
-      const uint32_t i1 = (uint32_t)(e1 >> RUN_PT) & 0xFFFu;
-      const uint32_t iv0 = (v0 && i0 < P) ? s_iv[i0] : NONE32;
-      const uint32_t iv1 = (v1 && i1 < P) ? s_iv[i1] : NONE32;
-      uint32_t prev0 = __shfl_up(iv0, 1);
-      uint32_t prev1 = __shfl_up(iv1, 1);
-      const uint32_t last0 = __shfl(iv0, 63);
-      if (lane == 0) prev1 = last0;
-      // a sub-segment starts at a new location or a new interval
-      const uint64_t Bc = __ballot(((e0 >> RUN_LOC) & 1) || iv0 != prev0);
-      const uint64_t Bn = __ballot(((e1 >> RUN_LOC) & 1) || iv1 != prev1);
-      const uint64_t Wc = __ballot((e0 >> RUN_W) & 1), Wn = __ballot((e1 >> RUN_W) & 1);
-      const uint64_t Mc = __ballot((e0 >> RUN_MULTI) & 1), Mn = __ballot((e1 >> RUN_MULTI) & 1);
-      s_e[wv][lane] = e0;
-      s_e[wv][64 + lane] = e1;
-      __builtin_amdgcn_wave_barrier();
-      if (v0 && i0 < P) {
-        const uint32_t i = i0, iv = iv0, id = (uint32_t)e0;
-        const bool w = (e0 >> RUN_W) & 1, m = (e0 >> RUN_MULTI) & 1;
+      const uint64_t e = buf[c * 64 + lane];
+      const bool valid = !((e >> RUN_END) & 1);
+      const uint32_t i = (uint32_t)(e >> RUN_PT) & 0xFFFu;
+      const uint32_t iv = (valid && i < P) ? s_iv[i] : NONE32;
+      const uint32_t prev = __shfl_up(iv, 1);
+      const bool w = (e >> RUN_W) & 1, m = (e >> RUN_MULTI) & 1, ls = (e >> RUN_LOC) & 1;
+      const uint64_t Bm = __ballot(ls || iv != prev);     // sub-segment starts (bit 0 unused)
+      const uint64_t Lm = __ballot(ls);
+      const uint64_t Wm = __ballot(w);
+      const uint64_t Mm = __ballot(m);
+      if (valid && i < P) {
+        const uint32_t id = (uint32_t)e;
         uint32_t best = NONE32;
         if (w && m) {          // two threads (blocks) of one point on one word, one writes
           if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, i);
           else best = i;
         }
         if (ALL || best == NONE32) {
-          const uint64_t gt = lane == 63 ? 0ull : (~0ull << (lane + 1));
-          const uint64_t sC = Bc & gt;
-          uint64_t cC, cN;
-          bool complete = true;
-          if (sC) {
-            cC = gt & ((sC & (~sC + 1)) - 1);
-            cN = 0;
-          } else {
-            cC = gt;
-            if (Bn) cN = (Bn & (~Bn + 1)) - 1;
-            else { cN = ~0ull; complete = false; }
-          }
-          if (!w) { cC &= Wc; cN &= Wn; }
-          while (cC) {
-            const int jj = __ffsll((unsigned long long)cC) - 1;
-            cC &= cC - 1;
-            const uint64_t ej = s_e[wv][jj];
+          const uint64_t sC = Bm & gt;
+          uint64_t cand = sC ? gt & ((sC & (~sC + 1)) - 1) : gt;
+          if (!w) cand &= Wm;
+          while (cand) {
+            const int jj = __ffsll((unsigned long long)cand) - 1;
+            cand &= cand - 1;
+            const uint64_t ej = buf[c * 64 + jj];
             const uint32_t j = (uint32_t)(ej >> RUN_PT) & 0xFFFu;
-            if (j < P && (m || ((Mc >> jj) & 1) || id != (uint32_t)ej)) {
+            if (j < P && (m || ((Mm >> jj) & 1) || id != (uint32_t)ej)) {
               if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, j);
               else { best = j; break; }
             }
           }
-          if (ALL || best == NONE32) {
-            while (cN) {
-              const int jj = __ffsll((unsigned long long)cN) - 1;
-              cN &= cN - 1;
-              const uint64_t ej = s_e[wv][64 + jj];
-              const uint32_t j = (uint32_t)(ej >> RUN_PT) & 0xFFFu;
-              if (j < P && (m || ((Mn >> jj) & 1) || id != (uint32_t)ej)) {
-                if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, j);
-                else { best = j; break; }
-              }
-            }
-          }
-          if (!complete && (ALL || best == NONE32)) {
-            // the sub-segment continues past the window
-            for (uint64_t q = p0 + 128; q < n; q++) {
-              const uint64_t ej = runs[q];
+          // the sub-segment reaches the end of the chunk: look past it
+          if (!sC && (ALL || best == NONE32)) {
+            // first candidate past the chunk: the next run (a writing run,
+            // or every run in "all" mode), else the carried first write
+            uint64_t q = (w || ALL) ? p0 + 64 : carry;
+            while (q < n) {
+              const uint64_t ej = entry(q);
               if ((ej >> RUN_LOC) & 1) break;
               const uint32_t j = (uint32_t)(ej >> RUN_PT) & 0xFFFu;
-              if (j >= P || s_iv[j] != iv) break;
-              if ((w || ((ej >> RUN_W) & 1)) && (m || ((ej >> RUN_MULTI) & 1) || id != (uint32_t)ej)) {
+              if (j >= P || s_iv[j] != iv) break;        // next interval
+              const bool wj = (ej >> RUN_W) & 1;
+              if ((w || wj) && (m || ((ej >> RUN_MULTI) & 1) || id != (uint32_t)ej)) {
                 if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, j);
                 else { best = j; break; }
               }
+              q++;
             }
           }
         }
         if (!ALL && best != NONE32 && s_minj[i] > best) atomicMin(&s_minj[i], best);
       }
-      __builtin_amdgcn_wave_barrier();
-      e0 = e1;
-      e1 = e2;
+      // carry for the chunk before: first write from p0 on, before a location start
+      if (Wm && (!Lm || __ffsll((unsigned long long)Wm) < __ffsll((unsigned long long)Lm)))
+        carry = p0 + __ffsll((unsigned long long)Wm) - 1;
+      else if (Lm)
+        carry = NOPOS;
     }
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   if (!ALL && cur >= 0) {
@@ -333,8 +341,15 @@ hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int with_bitmap, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_conf(const Job* jobs, ConfSeg* segs, int nseg, uint32_t max_points,
-                       int all_pairs, uint32_t* tiles, hipStream_t s) {
+hipError_t launch_conf_tiles(const Job* jobs, ConfSeg* segs, int nseg, uint32_t* tiles,
+                             hipStream_t s) {
+  if (nseg == 0) return hipSuccess;
+  conf_tiles_kernel<<<1, 1024, 0, s>>>(jobs, segs, (uint32_t)nseg, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
+                       int all_pairs, const uint32_t* tiles, hipStream_t s) {
   if (nseg == 0) return hipSuccess;
   const size_t dyn = 2 * (size_t)(max_points ? max_points : 1) * sizeof(uint32_t);
   int dev = 0, ncu = 256, per_cu = 0;
@@ -345,7 +360,6 @@ hipError_t launch_conf(const Job* jobs, ConfSeg* segs, int nseg, uint32_t max_po
       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conf_kernel<false>, CONF_BLOCK, dyn);
   if (oe != hipSuccess || per_cu < 1) per_cu = 1;
   const uint32_t grid = (uint32_t)ncu * (uint32_t)std::min(per_cu, 8);
-  conf_tiles_kernel<<<1, 1024, 0, s>>>(jobs, segs, (uint32_t)nseg, tiles);
   if (all_pairs) conf_kernel<true><<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
   else conf_kernel<false><<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
   return hipGetLastError();

@@ -11,7 +11,8 @@
 //     partner's clause is a superset, hence subsumed;
 //   - phi := reduce(phi + learned): sorted by (pos, neg), duplicates and
 //     subsumed clauses dropped.  A subset precedes its supersets in that
-//     order, so each clause is tested against earlier ones only.
+//     order, so each clause is tested against earlier ones only.  Up to 2048
+//     clauses are merged in LDS, more in the job's scratch.
 #include "common.h"
 #include "launch.h"
 
@@ -59,11 +60,14 @@ __device__ __forceinline__ uint32_t block_excl_scan1024(uint32_t v, uint32_t* sm
   return pre + inc - v;
 }
 
+constexpr uint32_t CL_LDS = 2048;   // clauses merged in LDS; more go through the job's scratch
+
 // learn: 0 = only decide SAFE (the check call), 1 = learn and reduce.
 __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict__ jobs, int learn) {
   __shared__ uint32_t s_n, s_races, s_first;
   __shared__ uint32_t sm[CL_BLOCK / 64];
   __shared__ uint32_t keep[4096];   // bitset over up to 131072 clauses
+  __shared__ rp_clause s_cl[CL_LDS];
   const Job& J = jobs[blockIdx.x];
   JobState* st = J.st;
   if (st->state != ST_RUN) return;
@@ -91,11 +95,13 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
     return;
   }
   if (!learn) return;
-  // phi first, then the learned clauses, in scratch
+  // phi first, then the learned clauses: in LDS when they surely fit, else
+  // in the job's scratch
   const uint32_t n_phi = st->n_phi;
-  rp_clause* sc = J.scratch;
-  for (uint32_t q = tid; q < n_phi; q += CL_BLOCK) sc[q] = J.phi[q];
   const bool one = J.policy == 1;
+  const uint64_t most = (uint64_t)n_phi + (one ? 1u : 2u * P + 64u);
+  rp_clause* sc = most <= CL_LDS ? s_cl : J.scratch;
+  for (uint32_t q = tid; q < n_phi; q += CL_BLOCK) sc[q] = J.phi[q];
   if (one) {
     if (tid == 0) {
       rp_clause c;
@@ -140,7 +146,7 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
   const uint32_t n = n_phi + s_n;
   uint32_t n2 = 1;
   while (n2 < n) n2 <<= 1;
-  if (n2 > J.scratch_cap || n > 4096u * 32u) {
+  if (n2 > (sc == s_cl ? CL_LDS : J.scratch_cap) || n > 4096u * 32u) {
     if (tid == 0) { st->err = ERR_SCRATCH; st->state = ST_ERROR; }
     return;
   }

@@ -78,6 +78,7 @@ struct Job {
   uint32_t tbits, bbits, pbits, key_shift;
   uint32_t nbits, policy;     // word-field width; learning policy
   const DPoint* pts;          // [P]
+  const uint64_t* wbits;      // [(P+63)/64] bit i: point i writes
   const uint64_t* bits_any;   // [P] slot bit of a barrier occurrence, else 0
   const uint64_t* bits_grid;  // [P] slot bit of a GRID barrier occurrence, else 0
   const uint32_t* weights;    // [S]

@@ -22,7 +22,7 @@ struct Layout {
   size_t total = 0, meta = 0;
   size_t o_jobs = 0, o_states = 0, o_items = 0, o_ssegs = 0, o_csegs = 0;
   size_t o_phi0 = 0;
-  std::vector<size_t> o_pts, o_bany, o_bgrid, o_w, o_cpre, o_gpre, o_phi0j;
+  std::vector<size_t> o_pts, o_bany, o_bgrid, o_w, o_cpre, o_gpre, o_phi0j, o_wbits;
   size_t o_chunks = 0;
   size_t o_recA = 0, o_recB = 0, o_cnt = 0, o_tot = 0, o_off = 0, o_err = 0;
   size_t o_rcnt = 0, o_roff = 0;
@@ -104,10 +104,12 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   L.o_ssegs = off; off = up(off + L.ssegs.size() * sizeof(SortSeg));
   L.o_csegs = off; off = up(off + L.ssegs.size() * sizeof(ConfSeg));
   L.o_pts.resize(N); L.o_bany.resize(N); L.o_bgrid.resize(N); L.o_w.resize(N);
+  L.o_wbits.resize(N);
   L.o_cpre.resize(N); L.o_gpre.resize(N); L.o_phi0j.resize(N);
   for (size_t j = 0; j < N; j++) {
     const Plan& p = *jobs[j].plan;
     L.o_pts[j] = off; off = up(off + p.P * sizeof(DPoint));
+    L.o_wbits[j] = off; off = up(off + p.wbits.size() * sizeof(uint64_t));
     L.o_bany[j] = off; off = up(off + p.P * sizeof(uint64_t));
     L.o_bgrid[j] = off; off = up(off + p.P * sizeof(uint64_t));
     L.o_w[j] = off; off = up(off + p.S * sizeof(uint32_t));
@@ -169,7 +171,10 @@ struct Timer {
 };
 
 // phase tags for the stats
-enum { T_START = 0, T_GEN, T_SORTPASS, T_SORT, T_RUNS, T_CHECK, T_CLAUSE, T_SOLVE, T_END };
+// T_ROUND opens a repair round: the time since the previous mark (the
+// host's per-round readback) is counted in ms_total only.
+enum { T_START = 0, T_UPLOAD, T_GEN, T_SORTPASS, T_SORT, T_RUNS, T_ROUND, T_CONFPRE, T_CHECK,
+       T_CLAUSE, T_SOLVE, T_END };
 
 }  // namespace
 
@@ -201,6 +206,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     J.tbits = p.tbits; J.bbits = p.bbits; J.pbits = p.pbits; J.key_shift = p.key_shift;
     J.nbits = p.nbits; J.policy = jobs[j].policy;
     J.pts = (const DPoint*)(d + L.o_pts[j]);
+    J.wbits = (const uint64_t*)(d + L.o_wbits[j]);
     J.bits_any = (const uint64_t*)(d + L.o_bany[j]);
     J.bits_grid = (const uint64_t*)(d + L.o_bgrid[j]);
     J.weights = (const uint32_t*)(d + L.o_w[j]);
@@ -229,6 +235,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     S.state = ST_RUN;
     S.max_rounds = jobs[j].max_rounds;
     std::memcpy(h.data() + L.o_pts[j], p.pts.data(), p.P * sizeof(DPoint));
+    std::memcpy(h.data() + L.o_wbits[j], p.wbits.data(), p.wbits.size() * sizeof(uint64_t));
     std::memcpy(h.data() + L.o_bany[j], p.bits_any.data(), p.P * sizeof(uint64_t));
     std::memcpy(h.data() + L.o_bgrid[j], p.bits_grid.data(), p.P * sizeof(uint64_t));
     std::memcpy(h.data() + L.o_w[j], p.weights.data(), p.S * sizeof(uint32_t));
@@ -269,6 +276,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
       HIPCHK(hipMemcpyAsync(d + L.o_phi[j], d + L.o_phi0j[j],
                             jobs[j].phi0.size() * sizeof(rp_clause), hipMemcpyDeviceToDevice, s));
   HIPCHK(launch_fill_u64((uint64_t*)(d + L.o_err), 8, 0, s));
+  tm.mark(T_UPLOAD);
   const Job* djobs = (const Job*)(d + L.o_jobs);
   uint32_t* derr = (uint32_t*)(d + L.o_err);
   // ---- records and sort
@@ -335,6 +343,7 @@ int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStrea
 int engine_round(const Job* djobs, uint32_t njobs, ConfSeg* dcs, uint32_t nseg, uint32_t maxP,
                  uint32_t* dactive, hipStream_t s) {
   HIPCHK(launch_ivl(djobs, njobs, 0, s));
+  HIPCHK(launch_conf_tiles(djobs, dcs, (int)nseg, dactive + 1, s));
   HIPCHK(launch_conf(djobs, dcs, (int)nseg, maxP, 0, dactive + 1, s));
   HIPCHK(launch_clause(djobs, njobs, 1, s));
   HIPCHK(launch_solve(djobs, njobs, s));
@@ -370,6 +379,8 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   uint32_t rounds_run = 0, conf_launches = 0;
   if (o.op == OP_CHECK) {
     HIPCHK(launch_ivl(djobs, (uint32_t)N, 1, s));
+    HIPCHK(launch_conf_tiles(djobs, dcs, nseg, dtiles, s));
+    tm.mark(T_CONFPRE);
     HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 1, dtiles, s));
     conf_launches++;
     scanned += L.n_rec;
@@ -382,12 +393,16 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     tm.mark(T_SOLVE);
   } else if (o.op == OP_FIRST) {
     HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
+    HIPCHK(launch_conf_tiles(djobs, dcs, nseg, dtiles, s));
+    tm.mark(T_CONFPRE);
     HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s));
     conf_launches++;
     scanned += L.n_rec;
     tm.mark(T_CHECK);
   } else if (o.op == OP_CLAUSES) {
     HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
+    HIPCHK(launch_conf_tiles(djobs, dcs, nseg, dtiles, s));
+    tm.mark(T_CONFPRE);
     HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s));
     conf_launches++;
     scanned += L.n_rec;
@@ -401,8 +416,8 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     auto round = [&]() -> hipError_t {
       hipError_t e;
       if ((e = launch_ivl(djobs, (uint32_t)N, 0, s)) != hipSuccess) return e;
-      if ((e = launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s)) != hipSuccess)
-        return e;
+      if ((e = launch_conf_tiles(djobs, dcs, nseg, dtiles, s)) != hipSuccess) return e;
+      if ((e = launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s)) != hipSuccess) return e;
       if ((e = launch_clause(djobs, (uint32_t)N, 1, s)) != hipSuccess) return e;
       if ((e = launch_solve(djobs, (uint32_t)N, s)) != hipSuccess) return e;
       return launch_count_active(djobs, (uint32_t)N, dactive, s);
@@ -426,11 +441,14 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     uint32_t active = 1;
     int rc_loop = RP_OK;
     while (active) {
+      tm.mark(T_ROUND);
       if (gexec) {
         if (hipGraphLaunch(gexec, s) != hipSuccess) { rc_loop = RP_ERR_DEVICE; break; }
         tm.mark(T_CHECK);
       } else {
         HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
+        HIPCHK(launch_conf_tiles(djobs, dcs, nseg, dtiles, s));
+        tm.mark(T_CONFPRE);
         HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s));
         tm.mark(T_CHECK);
         HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));
@@ -518,8 +536,13 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
             stats->sort_launches++;
           }
           break;
+        case T_UPLOAD: stats->ms_upload += ms; break;
         case T_RUNS: stats->ms_runs += ms; break;
-        case T_CHECK: stats->ms_check += ms; break;
+        case T_CONFPRE: stats->ms_check += ms; break;
+        case T_CHECK:
+          stats->ms_check += ms;
+          if (tm.tag[q - 1] == T_CONFPRE) stats->ms_conf_kernels += ms;
+          break;
         case T_CLAUSE: stats->ms_clause += ms; break;
         case T_SOLVE: stats->ms_solve += ms; break;
         default: break;
@@ -529,6 +552,11 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     if (tm.ev.size() >= 2 && hipEventElapsedTime(&tot, tm.ev.front(), tm.ev.back()) == hipSuccess)
       stats->ms_total = tot;
     stats->records = L.n_rec;
+    if (!L.ssegs.empty()) {
+      std::vector<ConfSeg> cs(L.ssegs.size());
+      if (hipMemcpy(cs.data(), dcs, cs.size() * sizeof(ConfSeg), hipMemcpyDeviceToHost) == hipSuccess)
+        for (const ConfSeg& c : cs) stats->runs += c.n_runs;
+    }
     for (const JobInput& j : jobs) stats->accesses += j.plan->accesses;
     stats->records_scanned = scanned;
     stats->sort_passes = L.passes;

@@ -22,10 +22,13 @@ hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const 
 hipError_t launch_runs_build(const Job* jobs, ConfSeg* segs, int nseg, uint32_t n_btiles,
                              uint32_t* cnt, uint64_t* off, hipStream_t s);
 hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int with_bitmap, hipStream_t s);
-// Lays out the round's tiles over the logs of running jobs (ctile_beg of each
-// segment, the total in *tiles) and scans them.
-hipError_t launch_conf(const Job* jobs, ConfSeg* segs, int nseg, uint32_t max_points,
-                       int all_pairs, uint32_t* tiles, hipStream_t s);
+// Lays out the round's tiles over the logs of running jobs: ctile_beg of
+// each segment, the total in *tiles.
+hipError_t launch_conf_tiles(const Job* jobs, ConfSeg* segs, int nseg, uint32_t* tiles,
+                             hipStream_t s);
+// Scans the tiles laid out by launch_conf_tiles.
+hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
+                       int all_pairs, const uint32_t* tiles, hipStream_t s);
 hipError_t launch_pairs(const Job* job, rp_pair* out, uint64_t* total, hipStream_t s);
 hipError_t launch_clause(const Job* jobs, uint32_t njobs, int learn, hipStream_t s);
 hipError_t launch_solve(const Job* jobs, uint32_t njobs, hipStream_t s);

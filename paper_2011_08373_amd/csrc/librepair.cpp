@@ -84,6 +84,7 @@ void make_plan(const rp_kernel* k, Plan& pl) {
   pl.key_shift = pl.tbits + pl.bbits + pl.pbits;
   pl.key_bits = pl.abits + pl.nbits;
   pl.pts.assign(pl.P, DPoint{});
+  pl.wbits.assign((pl.P + 63) / 64, 0);
   pl.bits_any.assign(pl.P, 0);
   pl.bits_grid.assign(pl.P, 0);
   pl.cnt_pre.assign(pl.P + 1, 0);
@@ -108,7 +109,10 @@ void make_plan(const rp_kernel* k, Plan& pl) {
       d.a = p.a; d.b = p.b; d.c = p.c;
       d.words = a.words;
       d.array = p.array;
-      if (p.is_write) d.flags |= PF_WRITE;
+      if (p.is_write) {
+        d.flags |= PF_WRITE;
+        pl.wbits[i >> 6] |= 1ull << (i & 63);
+      }
       if (a.space == RP_GLOBAL) d.flags |= PF_GLOBAL;
       if ((a.words & (a.words - 1)) == 0) d.flags |= PF_POW2;
       const int64_t nw = (int64_t)a.words;

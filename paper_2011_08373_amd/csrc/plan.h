@@ -10,6 +10,7 @@ struct Plan {
   uint32_t P = 0, S = 0, B = 0, T = 0;
   uint32_t tbits = 0, bbits = 0, pbits = 0, nbits = 0, abits = 0, key_shift = 0, key_bits = 0;
   std::vector<DPoint> pts;
+  std::vector<uint64_t> wbits;      // bit i: point i writes
   std::vector<uint64_t> bits_any, bits_grid;
   std::vector<uint32_t> weights;
   std::vector<uint64_t> cnt_pre;    // prefix of same-block records per block over points

@@ -128,10 +128,12 @@ __global__ __launch_bounds__(RB_BLOCK) void runs_write_kernel(const Job* __restr
                                                               const uint64_t* __restrict__ off) {
   __shared__ uint32_t s_cnt[RB_ROUNDS * RB_WAVES];
   __shared__ uint64_t s_pre[RB_ROUNDS * RB_WAVES];
+  __shared__ uint64_t s_wb[MAX_POINTS / 64];
   const uint32_t tile = blockIdx.x;
   const int si = find_seg_by_btile(segs, nseg, tile);
   const ConfSeg& sg = segs[si];
   const Job& J = jobs[sg.job];
+  for (uint32_t q = threadIdx.x; q < (J.P + 63) / 64; q += RB_BLOCK) s_wb[q] = J.wbits[q];
   const ViewBits vb = view_bits(J, sg.level);
   const uint64_t n = sg.n;
   const uint64_t* __restrict__ log = sg.log;
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(RB_BLOCK) void runs_write_kernel(const Job* __restr
     const bool multi = sg.level == 0 ? len >= 2 : ((last >> vb.ish) & vb.imask) != id;
     const bool locstart = q == 0 || (pr >> vb.lsh) != (v >> vb.lsh);
     const uint32_t i = (uint32_t)(v >> vb.psh) & vb.pmask;
-    const bool wr = i < J.P && (J.pts[i].flags & PF_WRITE);
+    const bool wr = i < J.P && ((s_wb[i >> 6] >> (i & 63)) & 1);
     const uint64_t idx = s_pre[k * RB_WAVES + wv] + (uint64_t)__popcll(hm & lanemask_lt());
     sg.runs[idx] = id | ((uint64_t)i << RUN_PT) | ((uint64_t)wr << RUN_W) |
                    ((uint64_t)multi << RUN_MULTI) | ((uint64_t)locstart << RUN_LOC);

@@ -54,7 +54,9 @@ class RpStats(C.Structure):
                 ("records", C.c_uint64),
                 ("accesses", C.c_uint64), ("records_scanned", C.c_uint64),
                 ("sort_passes", C.c_uint32), ("sort_launches", C.c_uint32),
-                ("rounds", C.c_uint32), ("conf_launches", C.c_uint32)]
+                ("rounds", C.c_uint32), ("conf_launches", C.c_uint32),
+                ("ms_upload", C.c_double), ("ms_conf_kernels", C.c_double),
+                ("runs", C.c_uint64)]
 
 
 PAIR_DT = np.dtype([("i", "<u2"), ("j", "<u2"), ("level", "u1"), ("pad", "u1")])
