@@ -109,7 +109,15 @@ typedef struct {
                             divergence < same-block race < cross-block race) */
   uint8_t grid;       /* 0: grid-level barriers disallowed (unit not b_s) */
   uint8_t inspect;    /* 0: pre-existing barriers kept (unit b_s) */
-  uint8_t pad;
+  uint8_t solver;     /* 0: exact Solve every round; 1: the mhs strategy of
+                         Section 2.4 -- the greedy minimal hitting set of the
+                         positive clauses (most clauses hit per unit weight,
+                         ties to the lower slot, then redundant picks dropped
+                         in reverse order), the exact optimum in a round where
+                         it breaks a clause, and once it is SAFE one exact
+                         query; a different optimum is verified in turn and
+                         exact Solve continues.  The result equals solver 0's;
+                         rounds and trajectory may differ. */
   uint32_t max_rounds;/* Verify calls allowed; 0 = unlimited */
 } rp_repair_opts;
 

@@ -466,6 +466,54 @@ int solve_reduced(const std::vector<or_clause>& in, const uint32_t* w, u32 S, u6
   return OR_OK;
 }
 
+// Greedy minimal hitting set of the positive clauses (Section 2.4, the mhs
+// strategy; the greedy of Johnson's set-cover approximation, weighted):
+// repeatedly take the slot that hits the most clauses not yet hit per unit of
+// weight (ties: lower slot id), then drop, in reverse order of choice, every
+// chosen slot whose removal leaves all positive clauses hit.  Negative
+// literals are ignored here.  An empty clause cannot be hit: OR_UNSAT.
+int greedy_mhs(const std::vector<or_clause>& phi, const uint32_t* w, u32 S, u64* out) {
+  std::vector<u64> pos;
+  for (const or_clause& c : phi) {
+    if (c.pos == 0 && c.neg == 0) return OR_UNSAT;
+    if (c.pos && !c.neg) pos.push_back(c.pos);
+  }
+  std::vector<bool> hit(pos.size(), false);
+  std::vector<u32> order;
+  u64 x = 0;
+  for (;;) {
+    std::vector<u64> cnt(S, 0);
+    bool open = false;
+    for (size_t q = 0; q < pos.size(); q++) {
+      if (hit[q]) continue;
+      open = true;
+      for (u32 s = 0; s < S; s++)
+        if ((pos[q] >> s) & 1) cnt[s]++;
+    }
+    if (!open) break;
+    int best = -1;
+    for (u32 s = 0; s < S; s++) {
+      if (cnt[s] == 0) continue;
+      // cnt[s] / w[s] > cnt[best] / w[best], compared exactly
+      if (best < 0 || cnt[s] * w[best] > cnt[best] * w[s]) best = (int)s;
+    }
+    if (best < 0) return OR_UNSAT;
+    x |= 1ull << best;
+    order.push_back((u32)best);
+    for (size_t q = 0; q < pos.size(); q++)
+      if ((pos[q] >> best) & 1) hit[q] = true;
+  }
+  for (size_t k = order.size(); k-- > 0;) {
+    const u64 y = x & ~(1ull << order[k]);
+    bool all = true;
+    for (u64 c : pos)
+      if (!(c & y)) { all = false; break; }
+    if (all) x = y;
+  }
+  *out = x;
+  return OR_OK;
+}
+
 u64 weight_of(const uint32_t* w, u32 S, u64 x) {
   u64 W = 0;
   for (u32 s = 0; s < S; s++)
@@ -600,11 +648,35 @@ extern "C" int or_min_barriers(const or_clause* c, uint64_t n, const uint32_t* w
   return st;
 }
 
+// One Solve call of the repair loop: the exact optimum, or under the mhs
+// strategy the greedy hitting set of the positive clauses, replaced by the
+// exact optimum when it leaves a clause of phi unsatisfied (Section 2.4).
+static int solve_step(const std::vector<or_clause>& phi, const uint32_t* w, u32 S, bool mhs,
+                      u64* x) {
+  if (!mhs) return solve_reduced(phi, w, S, x);
+  int st = greedy_mhs(phi, w, S, x);
+  if (st != OR_OK) return solve_reduced(phi, w, S, x);
+  for (const or_clause& c : phi)
+    if (!satisfies(c, *x)) return solve_reduced(phi, w, S, x);
+  return OR_OK;
+}
+
+extern "C" int or_greedy_mhs(const or_clause* c, uint64_t n, const uint32_t* weights,
+                             uint32_t n_slots, uint64_t* assign) {
+  if (n_slots > 64 || (n && !c)) return OR_ERR_INVALID;
+  std::vector<or_clause> cl(c, c + n);
+  u64 x = 0;
+  const int st = greedy_mhs(cl, weights, n_slots, &x);
+  if (st == OR_OK && assign) *assign = x;
+  return st;
+}
+
 extern "C" int or_repair(const or_kernel* k, const or_opts* o, or_result* out,
                          uint64_t* trajectory, uint32_t traj_cap) {
   int v = validate(k);
   if (v != OR_OK) return v;
   or_opts opt = o ? *o : or_opts{0, 1, 1, 0, 0};
+  if (opt.solver > 1) return OR_ERR_INVALID;
   std::vector<uint32_t> w(k->n_slots);
   u64 pre = 0;
   for (u32 s = 0; s < k->n_slots; s++) {
@@ -622,9 +694,10 @@ extern "C" int or_repair(const or_kernel* k, const or_opts* o, or_result* out,
   or_result r;
   std::memset(&r, 0, sizeof(r));
   u32 rounds = 0;
+  bool mhs = opt.solver == 1;              // greedy rounds until the first SAFE
+  u64 x = 0;
+  int st = solve_step(phi, w.data(), k->n_slots, mhs, &x);   // Solve(phi)
   for (;;) {
-    u64 x = 0;
-    int st = solve_reduced(phi, w.data(), k->n_slots, &x);   // Solve(phi)
     if (st == OR_UNSAT) { r.status = OR_UNSAT; break; }      // cannot be repaired
     if (opt.max_rounds && rounds == opt.max_rounds) { r.status = OR_ERR_ROUNDS; break; }
     if (trajectory && rounds < traj_cap) trajectory[rounds] = x;
@@ -633,6 +706,18 @@ extern "C" int or_repair(const or_kernel* k, const or_opts* o, or_result* out,
     races(k, x, false, rp);
     u64 div = divergent_if_enabled(k, false) & x;
     if (rp.empty() && div == 0) {                             // SAFE
+      if (mhs) {
+        // the one exact query that makes the greedy result minimum; a
+        // different optimum is verified in turn, with exact Solve from now on
+        mhs = false;
+        u64 xo = 0;
+        solve_reduced(phi, w.data(), k->n_slots, &xo);
+        if (xo != x) {
+          x = xo;
+          st = OR_OK;
+          continue;
+        }
+      }
       r.status = OR_OK;
       r.assign = x;
       r.weight = weight_of(w.data(), k->n_slots, x);
@@ -650,6 +735,7 @@ extern "C" int or_repair(const or_kernel* k, const or_opts* o, or_result* out,
     }
     phi.insert(phi.end(), learned.begin(), learned.end());
     phi = reduce(phi);
+    st = solve_step(phi, w.data(), k->n_slots, mhs, &x);
   }
   r.rounds = rounds;
   r.n_clauses = (u32)phi.size();

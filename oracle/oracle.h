@@ -38,7 +38,9 @@ typedef struct {
 } or_kernel;
 typedef struct { uint64_t pos, neg; } or_clause;
 typedef struct { uint16_t i, j; uint8_t level; uint8_t pad; } or_pair;   /* level 0 intra, 1 inter */
-typedef struct { uint8_t policy, grid, inspect, pad; uint32_t max_rounds; } or_opts;
+/* policy 0 learn every trace, 1 one trace; solver 0 exact Solve every round,
+ * 1 greedy minimal hitting set with exact fallback and a final exact query */
+typedef struct { uint8_t policy, grid, inspect, solver; uint32_t max_rounds; } or_opts;
 typedef struct { int32_t status; uint32_t rounds, n_clauses, pad;
                  uint64_t assign, weight, added, removed; } or_result;
 
@@ -69,6 +71,11 @@ uint64_t or_reduce(or_clause* c, uint64_t n);
  * over all slots (n_slots <= 26), 2 branch and bound. */
 int or_min_barriers(const or_clause* c, uint64_t n, const uint32_t* weights,
                     uint32_t n_slots, int method, uint64_t* assign, uint64_t* weight);
+
+/* Greedy minimal hitting set of the positive clauses (Section 2.4, mhs
+ * strategy); OR_UNSAT on an empty clause. */
+int or_greedy_mhs(const or_clause* c, uint64_t n, const uint32_t* weights,
+                  uint32_t n_slots, uint64_t* assign);
 
 /* The repair loop of Alg. 1.  trajectory (optional) receives x_r per round. */
 int or_repair(const or_kernel* k, const or_opts* o, or_result* out,

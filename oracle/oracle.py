@@ -66,7 +66,7 @@ class _Pair(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("policy", C.c_uint8), ("grid", C.c_uint8), ("inspect", C.c_uint8),
-                ("pad", C.c_uint8), ("max_rounds", C.c_uint32)]
+                ("solver", C.c_uint8), ("max_rounds", C.c_uint32)]
 
 
 class _Result(C.Structure):
@@ -96,6 +96,8 @@ def lib():
         L.or_min_barriers.argtypes = [C.POINTER(Clause), C.c_uint64, C.POINTER(C.c_uint32),
                                       C.c_uint32, C.c_int, u64p, u64p]
         L.or_repair.argtypes = [K, C.POINTER(_Opts), C.POINTER(_Result), u64p, C.c_uint32]
+        L.or_greedy_mhs.argtypes = [C.POINTER(Clause), C.c_uint64, C.POINTER(C.c_uint32),
+                                    C.c_uint32, u64p]
         L.or_safe_literal.argtypes = [K, C.c_uint64]
         _lib = L
     return _lib
@@ -206,11 +208,13 @@ def min_barriers(cl, weights, n_slots: int, method: int = 0):
     return st, a.value, wt.value
 
 
-def repair(km, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int = 0):
+def repair(km, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int = 0,
+           solver: int = 0):
     """Alg. 1; returns a dict with status, assign, weight, added, removed,
-    rounds, n_clauses and the trajectory of assignments."""
+    rounds, n_clauses and the trajectory of assignments.  solver 0: exact
+    Solve every round; 1: greedy minimal hitting set (Section 2.4)."""
     h = _Held(km)
-    o = _Opts(policy, grid, inspect, 0, max_rounds)
+    o = _Opts(policy, grid, inspect, solver, max_rounds)
     r = _Result()
     cap = 4096
     traj = (C.c_uint64 * cap)()
@@ -220,6 +224,17 @@ def repair(km, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int
     out["trajectory"] = [traj[q] for q in range(min(r.rounds, cap))]
     out["ret"] = st
     return out
+
+
+def greedy_mhs(cl, weights, n_slots: int):
+    """(status, assign) of the greedy minimal hitting set of the positive clauses."""
+    buf = (Clause * max(1, len(cl)))()
+    for q, (p, n) in enumerate(cl):
+        buf[q].pos, buf[q].neg = int(p), int(n)
+    w = (C.c_uint32 * max(1, n_slots))(*[int(v) for v in weights[:n_slots]])
+    a = C.c_uint64(0)
+    st = lib().or_greedy_mhs(buf, len(cl), w, n_slots, C.byref(a))
+    return st, a.value
 
 
 def safe_literal(km, x: int) -> int:

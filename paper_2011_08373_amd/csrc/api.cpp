@@ -199,7 +199,7 @@ rp_status rp_repair(const rp_kernel* k, const rp_repair_opts* opts, rp_repair_ou
                     void* stream) {
   if (validate_kernel(k) != RP_OK || !out || (traj_cap && !trajectory)) return RP_ERR_INVALID;
   rp_repair_opts op = opts ? *opts : rp_repair_opts{0, 1, 1, 0, 0};
-  if (op.policy > 1) return RP_ERR_INVALID;
+  if (op.policy > 1 || op.solver > 1) return RP_ERR_INVALID;
   Plan pl;
   make_plan(k, pl);
   JobInput ji;
@@ -207,6 +207,7 @@ rp_status rp_repair(const rp_kernel* k, const rp_repair_opts* opts, rp_repair_ou
   ji.phi0 = option_units(pl, op);
   ji.policy = op.policy;
   ji.max_rounds = op.max_rounds;
+  ji.solver = op.solver;
   EngineOpts o;
   o.op = OP_REPAIR;
   o.traj_cap = TRAJ_CAP;
@@ -263,7 +264,7 @@ rp_status rp_repair_batch(const rp_kernel* const* ks, uint32_t n, const rp_repai
                           rp_repair_out* outs, void* ws, size_t ws_bytes, void* stream) {
   if (!ks || !outs) return RP_ERR_INVALID;
   rp_repair_opts op = opts ? *opts : rp_repair_opts{0, 1, 1, 0, 0};
-  if (op.policy > 1) return RP_ERR_INVALID;
+  if (op.policy > 1 || op.solver > 1) return RP_ERR_INVALID;
   std::vector<Plan> plans;
   std::vector<uint32_t> idx;
   plans.reserve(n);
@@ -283,6 +284,7 @@ rp_status rp_repair_batch(const rp_kernel* const* ks, uint32_t n, const rp_repai
     v[q].phi0 = option_units(plans[q], op);
     v[q].policy = op.policy;
     v[q].max_rounds = op.max_rounds;
+    v[q].solver = op.solver;
   }
   if (v.empty()) return RP_OK;
   EngineOpts o;

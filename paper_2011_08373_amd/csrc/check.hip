@@ -3,8 +3,8 @@
 //
 // ivl_kernel   one workgroup per job: interval ids = number of enabled
 //              barrier occurrences before each point (any level, and grid
-//              level only), the divergent enabled slots, and the reset of the
-//              per-round outputs.
+//              level only), the divergent enabled slots, and the first
+//              partners under x resolved from the table j0 (or reset).
 // conf_kernel  scan of the run logs (runs.hip).  Runs are in program order
 //              inside a location, so the runs of one interval are contiguous.
 //              Two runs race when one writes and they are not the same single
@@ -27,12 +27,28 @@ constexpr int CONF_WAVES = CONF_BLOCK / 64;
 constexpr int CONF_CHUNKS = 16;                          // chunks of 64 runs per wave and tile
 constexpr uint32_t CONF_TILE = CONF_WAVES * CONF_CHUNKS * 64;   // runs per tile
 
-__global__ __launch_bounds__(IVL_BLOCK) void ivl_kernel(const Job* __restrict__ jobs, int with_bitmap) {
+// mode IVL_RESOLVE: interval ids under x, then the first partners under x
+//   from the assignment-independent table j0 (see below);
+// mode IVL_CHECK: interval ids under x, first partners cleared, pair bitmap
+//   cleared (the all-pairs scan follows);
+// mode IVL_ZERO: interval ids of the empty assignment (one interval), first
+//   partners cleared: the scan that follows fills j0.
+//
+// Why j0 suffices.  Inside one location the runs are in program order and
+// interval ids never decrease along it, so the first run after r that
+// conflicts with r in its whole location is either inside r's interval --
+// then it is r's first partner under x -- or past its end, and then so is
+// every conflicting run.  Taking the minimum over the runs of point i, the
+// first partner of i under any x is j0[i] (its first partner when no barrier
+// is enabled) if no enabled barrier lies strictly between i and j0[i], and
+// none otherwise.
+__global__ __launch_bounds__(IVL_BLOCK) void ivl_kernel(const Job* __restrict__ jobs, int mode) {
   __shared__ uint64_t wsum[IVL_BLOCK / 64];
+  __shared__ uint32_t s_iv[2][MAX_POINTS];
   const Job& J = jobs[blockIdx.x];
   JobState* st = J.st;
   if (st->state != ST_RUN) return;
-  const uint64_t x = st->x;
+  const uint64_t x = mode == IVL_ZERO ? 0 : st->x;
   const uint32_t P = J.P;
   const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
   // four consecutive points per thread (P <= 4096)
@@ -61,17 +77,32 @@ __global__ __launch_bounds__(IVL_BLOCK) void ivl_kernel(const Job* __restrict__ 
   for (int q = 0; q < 4; q++) {
     const uint32_t i = tid * 4 + q;
     if (i < P) {
-      J.ivl[i] = (uint32_t)run;               // enabled occurrences before i
-      J.ivl[P + i] = (uint32_t)(run >> 32);   // enabled GRID occurrences before i
+      J.ivl[i] = s_iv[0][i] = (uint32_t)run;               // enabled occurrences before i
+      J.ivl[P + i] = s_iv[1][i] = (uint32_t)(run >> 32);   // enabled GRID occurrences before i
     }
     run += cnt[q];
   }
-  for (uint32_t i = tid; i < 2 * P; i += IVL_BLOCK) J.minj[i] = NONE32;
-  if (with_bitmap && J.bitmap) {
+  __syncthreads();
+  if (mode == IVL_RESOLVE) {
+    for (uint32_t r = tid; r < 2 * P; r += IVL_BLOCK) {
+      const uint32_t lv = r >= P, i = r - lv * P;
+      const uint32_t j = J.j0[r];
+      J.minj[r] = (j < P && s_iv[lv][j] == s_iv[lv][i]) ? j : NONE32;
+    }
+  } else {
+    for (uint32_t i = tid; i < 2 * P; i += IVL_BLOCK) J.minj[i] = NONE32;
+  }
+  if (mode == IVL_CHECK && J.bitmap) {
     const uint64_t nw = 2ull * P * J.wpr;
     for (uint64_t q = tid; q < nw; q += IVL_BLOCK) J.bitmap[q] = 0;
   }
-  if (tid == 0) st->divergent = x & J.div_if_enabled;
+  if (tid == 0 && mode != IVL_ZERO) st->divergent = x & J.div_if_enabled;
+}
+
+// j0 := the first partners just computed under the empty assignment.
+__global__ __launch_bounds__(256) void save_j0_kernel(const Job* __restrict__ jobs) {
+  const Job& J = jobs[blockIdx.x];
+  for (uint32_t r = threadIdx.x; r < 2 * J.P; r += 256) J.j0[r] = J.minj[r];
 }
 
 __device__ __forceinline__ void set_pair(uint64_t* bm, uint32_t wpr, uint32_t P, uint32_t lv,
@@ -335,9 +366,15 @@ __global__ __launch_bounds__(1024) void pairs_kernel(const Job* __restrict__ job
 
 uint32_t conf_tile_size() { return CONF_TILE; }
 
-hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int with_bitmap, hipStream_t s) {
+hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int mode, hipStream_t s) {
   if (njobs == 0) return hipSuccess;
-  ivl_kernel<<<njobs, IVL_BLOCK, 0, s>>>(jobs, with_bitmap);
+  ivl_kernel<<<njobs, IVL_BLOCK, 0, s>>>(jobs, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_save_j0(const Job* jobs, uint32_t njobs, hipStream_t s) {
+  if (njobs == 0) return hipSuccess;
+  save_j0_kernel<<<njobs, 256, 0, s>>>(jobs);
   return hipGetLastError();
 }
 

@@ -91,7 +91,11 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
     st->races = races;
   }
   if (races == 0 && div == 0) {
-    if (tid == 0) st->state = ST_SAFE;
+    // SAFE; under the mhs strategy the exact query still decides
+    if (tid == 0) {
+      if (st->phase == PH_GREEDY) st->phase = PH_FINAL;
+      else st->state = ST_SAFE;
+    }
     return;
   }
   if (!learn) return;

@@ -69,8 +69,16 @@ struct JobState {        // device-resident per-job state; the host reads it
   uint32_t err;          // device-side error code (0 = none)
   uint32_t max_rounds;   // 0 = unlimited
   uint64_t traj_pad;
+  uint32_t phase;        // PH_*: which Solve the next call makes
+  uint32_t pad3;
 };
 constexpr uint32_t ST_RUN = 0, ST_SAFE = 1, ST_UNSAT = 2, ST_ERROR = 3, ST_ROUNDS = 4;
+// Solve phases.  PH_EXACT: the exact optimum.  PH_GREEDY (mhs strategy,
+// until the first SAFE): the greedy hitting set of the positive clauses, the
+// exact optimum when it leaves a clause unsatisfied.  PH_FINAL: the verified
+// greedy answer is SAFE; one exact query either confirms it or replaces it,
+// and exact Solve continues.
+constexpr uint32_t PH_EXACT = 0, PH_GREEDY = 1, PH_FINAL = 2;
 constexpr uint32_t ERR_PHI_CAP = 1, ERR_SORT = 2, ERR_SCRATCH = 3, ERR_RANGE = 4;
 
 struct Job {
@@ -89,7 +97,8 @@ struct Job {
   const uint64_t* log[2];     // sorted logs: same-block, cross-block
   uint64_t nlog[2];
   uint32_t* ivl;              // [2][P] interval id: any level, grid level
-  uint32_t* minj;             // [2][P] first racing partner per point
+  uint32_t* minj;             // [2][P] first racing partner per point under x
+  uint32_t* j0;               // [2][P] first racing partner with no barrier enabled
   uint64_t* bitmap;           // [2][P][wpr] racing pairs (check mode) or null
   uint32_t wpr, pad1;         // 64-bit words per bitmap row
   rp_clause* phi;             // [phi_cap]

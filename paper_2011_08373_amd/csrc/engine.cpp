@@ -27,7 +27,7 @@ struct Layout {
   size_t o_recA = 0, o_recB = 0, o_cnt = 0, o_tot = 0, o_off = 0, o_err = 0;
   size_t o_rcnt = 0, o_roff = 0;
   uint32_t n_btiles = 0;
-  std::vector<size_t> o_ivl, o_minj, o_phi, o_scratch, o_traj, o_bitmap, o_pairs, o_ptotal;
+  std::vector<size_t> o_ivl, o_minj, o_j0, o_phi, o_scratch, o_traj, o_bitmap, o_pairs, o_ptotal;
   std::vector<uint32_t> phi_cap, scratch_cap;
   uint64_t n_rec = 0;
   uint32_t rb = 8, passes = 0;
@@ -127,7 +127,7 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   L.o_tot = off; off = up(off + L.ssegs.size() * (size_t)R * sizeof(uint64_t));
   L.o_off = off; off = up(off + L.chunks.size() * (size_t)R * sizeof(uint64_t));
   L.o_err = off; off = up(off + 64);
-  L.o_ivl.resize(N); L.o_minj.resize(N); L.o_phi.resize(N); L.o_scratch.resize(N);
+  L.o_ivl.resize(N); L.o_minj.resize(N); L.o_j0.resize(N); L.o_phi.resize(N); L.o_scratch.resize(N);
   L.o_traj.resize(N); L.o_bitmap.resize(N); L.o_pairs.resize(N); L.o_ptotal.resize(N);
   L.phi_cap.resize(N); L.scratch_cap.resize(N);
   for (size_t j = 0; j < N; j++) {
@@ -139,6 +139,7 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
     L.scratch_cap[j] = pow2_at_least((uint64_t)cap + 2 * p.P + 64);
     L.o_ivl[j] = off; off = up(off + 2 * p.P * sizeof(uint32_t));
     L.o_minj[j] = off; off = up(off + 2 * p.P * sizeof(uint32_t));
+    L.o_j0[j] = off; off = up(off + 2 * p.P * sizeof(uint32_t));
     L.o_phi[j] = off; off = up(off + L.phi_cap[j] * sizeof(rp_clause));
     L.o_scratch[j] = off; off = up(off + L.scratch_cap[j] * sizeof(rp_clause));
     L.o_traj[j] = off; off = up(off + o.traj_cap * sizeof(uint64_t));
@@ -173,8 +174,8 @@ struct Timer {
 // phase tags for the stats
 // T_ROUND opens a repair round: the time since the previous mark (the
 // host's per-round readback) is counted in ms_total only.
-enum { T_START = 0, T_UPLOAD, T_GEN, T_SORTPASS, T_SORT, T_RUNS, T_ROUND, T_CONFPRE, T_CHECK,
-       T_CLAUSE, T_SOLVE, T_END };
+enum { T_START = 0, T_UPLOAD, T_GEN, T_SORTPASS, T_SORT, T_RUNS, T_SUMPRE, T_SUMMARY, T_ROUND,
+       T_CONFPRE, T_CHECK, T_CLAUSE, T_SOLVE, T_END };
 
 }  // namespace
 
@@ -219,6 +220,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     J.nlog[1] = p.n_inter;
     J.ivl = (uint32_t*)(d + L.o_ivl[j]);
     J.minj = (uint32_t*)(d + L.o_minj[j]);
+    J.j0 = (uint32_t*)(d + L.o_j0[j]);
     J.bitmap = o.op == OP_CHECK ? (uint64_t*)(d + L.o_bitmap[j]) : nullptr;
     J.wpr = (p.P + 63) / 64;
     J.phi = (rp_clause*)(d + L.o_phi[j]);
@@ -234,6 +236,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     S.n_phi = (uint32_t)jobs[j].phi0.size();
     S.state = ST_RUN;
     S.max_rounds = jobs[j].max_rounds;
+    S.phase = jobs[j].solver ? PH_GREEDY : PH_EXACT;
     std::memcpy(h.data() + L.o_pts[j], p.pts.data(), p.P * sizeof(DPoint));
     std::memcpy(h.data() + L.o_wbits[j], p.wbits.data(), p.wbits.size() * sizeof(uint64_t));
     std::memcpy(h.data() + L.o_bany[j], p.bits_any.data(), p.P * sizeof(uint64_t));
@@ -304,6 +307,22 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
   ConfSeg* dcs = (ConfSeg*)(d + L.o_csegs);
   HIPCHK(launch_runs_build(djobs, dcs, (int)L.ssegs.size(), L.n_btiles,
                            (uint32_t*)(d + L.o_rcnt), (uint64_t*)(d + L.o_roff), s));
+  tm.mark(T_RUNS);
+  // ---- first partners with no barrier enabled (once per job): every
+  // later Verify call resolves its first partners from them
+  // (a job without access records keeps the cleared table: no partner)
+  if (o.op != OP_CHECK && o.op != OP_SOLVE) {
+    uint32_t maxP = 1;
+    for (const JobInput& j : jobs) maxP = std::max(maxP, j.plan->P);
+    HIPCHK(launch_ivl(djobs, (uint32_t)N, IVL_ZERO, s));
+    if (!L.ssegs.empty()) {
+      HIPCHK(launch_conf_tiles(djobs, dcs, (int)L.ssegs.size(), derr + 9, s));
+      tm.mark(T_SUMPRE);
+      HIPCHK(launch_conf(djobs, dcs, (int)L.ssegs.size(), maxP, 0, derr + 9, s));
+      tm.mark(T_SUMMARY);
+    }
+    HIPCHK(launch_save_j0(djobs, (uint32_t)N, s));
+  }
   return RP_OK;
 }
 
@@ -330,21 +349,11 @@ int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStrea
   if (rc != RP_OK) return rc;
   HIPCHK(launch_solve((const Job*)(d + L.o_jobs), 1, s));
   std::memcpy(&out.job, staging.data() + L.o_jobs, sizeof(Job));
-  out.nseg = (uint32_t)L.ssegs.size();
-  const ConfSeg* hc = (const ConfSeg*)(staging.data() + L.o_csegs);
-  for (uint32_t q = 0; q < out.nseg; q++) {
-    out.segs[q] = hc[q];
-    out.segs[q].n_runs_at = &((const ConfSeg*)(d + L.o_csegs))[q].n_runs;
-    out.n_rec[q] = hc[q].n;
-  }
   return RP_OK;
 }
 
-int engine_round(const Job* djobs, uint32_t njobs, ConfSeg* dcs, uint32_t nseg, uint32_t maxP,
-                 uint32_t* dactive, hipStream_t s) {
-  HIPCHK(launch_ivl(djobs, njobs, 0, s));
-  HIPCHK(launch_conf_tiles(djobs, dcs, (int)nseg, dactive + 1, s));
-  HIPCHK(launch_conf(djobs, dcs, (int)nseg, maxP, 0, dactive + 1, s));
+int engine_round(const Job* djobs, uint32_t njobs, uint32_t* dactive, hipStream_t s) {
+  HIPCHK(launch_ivl(djobs, njobs, IVL_RESOLVE, s));
   HIPCHK(launch_clause(djobs, njobs, 1, s));
   HIPCHK(launch_solve(djobs, njobs, s));
   HIPCHK(launch_count_active(djobs, njobs, dactive, s));
@@ -371,19 +380,20 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   tm.mark(T_RUNS);
   // ---- per-round kernels
   const int nseg = (int)L.ssegs.size();
-  uint32_t* dtiles = derr + 9;     // conf tiles of the round
+  uint32_t* dtiles = derr + 9;     // conf tiles of the all-pairs scan
   uint32_t maxP = 1;
   for (const JobInput& j : jobs) maxP = std::max(maxP, j.plan->P);
   std::vector<JobState> hst(N);
-  uint64_t scanned = 0;
-  uint32_t rounds_run = 0, conf_launches = 0;
+  // the run logs are scanned once: by the all-pairs scan of a check, else
+  // by the first-partner scan of the preparation
+  const uint64_t scanned = o.op == OP_SOLVE ? 0 : L.n_rec;
+  uint32_t rounds_run = 0;
+  const uint32_t conf_launches = o.op == OP_SOLVE ? 0 : 1;
   if (o.op == OP_CHECK) {
-    HIPCHK(launch_ivl(djobs, (uint32_t)N, 1, s));
+    HIPCHK(launch_ivl(djobs, (uint32_t)N, IVL_CHECK, s));
     HIPCHK(launch_conf_tiles(djobs, dcs, nseg, dtiles, s));
     tm.mark(T_CONFPRE);
     HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 1, dtiles, s));
-    conf_launches++;
-    scanned += L.n_rec;
     tm.mark(T_CHECK);
     for (size_t j = 0; j < N; j++)
       HIPCHK(launch_pairs(djobs + j, (rp_pair*)(d + L.o_pairs[j]), (uint64_t*)(d + L.o_ptotal[j]), s));
@@ -392,20 +402,10 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     HIPCHK(launch_solve(djobs, (uint32_t)N, s));
     tm.mark(T_SOLVE);
   } else if (o.op == OP_FIRST) {
-    HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
-    HIPCHK(launch_conf_tiles(djobs, dcs, nseg, dtiles, s));
-    tm.mark(T_CONFPRE);
-    HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s));
-    conf_launches++;
-    scanned += L.n_rec;
+    HIPCHK(launch_ivl(djobs, (uint32_t)N, IVL_RESOLVE, s));
     tm.mark(T_CHECK);
   } else if (o.op == OP_CLAUSES) {
-    HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
-    HIPCHK(launch_conf_tiles(djobs, dcs, nseg, dtiles, s));
-    tm.mark(T_CONFPRE);
-    HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s));
-    conf_launches++;
-    scanned += L.n_rec;
+    HIPCHK(launch_ivl(djobs, (uint32_t)N, IVL_RESOLVE, s));
     tm.mark(T_CHECK);
     HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));
     tm.mark(T_CLAUSE);
@@ -415,9 +415,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     tm.mark(T_SOLVE);
     auto round = [&]() -> hipError_t {
       hipError_t e;
-      if ((e = launch_ivl(djobs, (uint32_t)N, 0, s)) != hipSuccess) return e;
-      if ((e = launch_conf_tiles(djobs, dcs, nseg, dtiles, s)) != hipSuccess) return e;
-      if ((e = launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s)) != hipSuccess) return e;
+      if ((e = launch_ivl(djobs, (uint32_t)N, IVL_RESOLVE, s)) != hipSuccess) return e;
       if ((e = launch_clause(djobs, (uint32_t)N, 1, s)) != hipSuccess) return e;
       if ((e = launch_solve(djobs, (uint32_t)N, s)) != hipSuccess) return e;
       return launch_count_active(djobs, (uint32_t)N, dactive, s);
@@ -446,10 +444,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
         if (hipGraphLaunch(gexec, s) != hipSuccess) { rc_loop = RP_ERR_DEVICE; break; }
         tm.mark(T_CHECK);
       } else {
-        HIPCHK(launch_ivl(djobs, (uint32_t)N, 0, s));
-        HIPCHK(launch_conf_tiles(djobs, dcs, nseg, dtiles, s));
-        tm.mark(T_CONFPRE);
-        HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 0, dtiles, s));
+        HIPCHK(launch_ivl(djobs, (uint32_t)N, IVL_RESOLVE, s));
         tm.mark(T_CHECK);
         HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));
         tm.mark(T_CLAUSE);
@@ -457,7 +452,6 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
         tm.mark(T_SOLVE);
         HIPCHK(launch_count_active(djobs, (uint32_t)N, dactive, s));
       }
-      conf_launches++;
       if (hipMemcpyAsync(&active, dactive, sizeof(active), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
         rc_loop = RP_ERR_DEVICE;
@@ -476,11 +470,6 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   HIPCHK(hipMemcpyAsync(herr, derr, sizeof(herr), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (herr[0]) return RP_ERR_DEVICE;
-  if (o.op == OP_REPAIR) {
-    scanned = 0;
-    for (size_t q = 0; q < L.ssegs.size(); q++)
-      scanned += (uint64_t)hst[L.seg_job[q]].rounds * (L.ssegs[q].end - L.ssegs[q].beg);
-  }
   res.assign(N, JobResult{});
   for (size_t j = 0; j < N; j++) {
     res[j].st = hst[j];
@@ -538,6 +527,11 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
           break;
         case T_UPLOAD: stats->ms_upload += ms; break;
         case T_RUNS: stats->ms_runs += ms; break;
+        case T_SUMPRE: stats->ms_runs += ms; break;
+        case T_SUMMARY:
+          stats->ms_runs += ms;
+          stats->ms_conf_kernels += ms;
+          break;
         case T_CONFPRE: stats->ms_check += ms; break;
         case T_CHECK:
           stats->ms_check += ms;

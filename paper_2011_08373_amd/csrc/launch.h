@@ -21,7 +21,9 @@ hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const 
                                const uint64_t* off, uint32_t* err, hipStream_t s);
 hipError_t launch_runs_build(const Job* jobs, ConfSeg* segs, int nseg, uint32_t n_btiles,
                              uint32_t* cnt, uint64_t* off, hipStream_t s);
-hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int with_bitmap, hipStream_t s);
+constexpr int IVL_RESOLVE = 0, IVL_CHECK = 1, IVL_ZERO = 2;
+hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int mode, hipStream_t s);
+hipError_t launch_save_j0(const Job* jobs, uint32_t njobs, hipStream_t s);
 // Lays out the round's tiles over the logs of running jobs: ctile_beg of
 // each segment, the total in *tiles.
 hipError_t launch_conf_tiles(const Job* jobs, ConfSeg* segs, int nseg, uint32_t* tiles,

@@ -31,6 +31,7 @@ struct JobInput {
   uint64_t x;                       // assignment (check / clauses)
   std::vector<rp_clause> phi0;      // initial constraint set (repair: option units)
   uint32_t policy = 0, max_rounds = 0;
+  uint32_t solver = 0;              // 0 exact Solve, 1 greedy hitting set (mhs)
 };
 
 struct JobResult {
@@ -53,24 +54,21 @@ struct EngineOpts {
 // Bytes of workspace the engine needs for these jobs.
 size_t engine_workspace(const std::vector<JobInput>& jobs, const EngineOpts& o);
 
-// One job prepared in its own device region (serving): host copies of its
-// device tables, with absolute device pointers.
+// One job prepared in its own device region (serving): a host copy of its
+// device job table entry, with absolute device pointers.
 struct PreparedJob {
   Job job;
-  ConfSeg segs[2];
-  uint32_t nseg = 0;
-  uint64_t n_rec[2] = {0, 0};
 };
 size_t engine_job_bytes(const JobInput& job);
-// Enqueues upload, record generation, sort, run log and the first Solve of
-// one job into `region`; staging must stay alive until the stream is synced.
+// Enqueues upload, record generation, sort, run log, the first-partner table
+// and the first Solve of one job into `region`; staging must stay alive until
+// the stream is synced.
 int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStream_t s,
                        PreparedJob& out, std::vector<uint8_t>& staging);
-// Enqueues one round (Verify, GenerateClause, Solve, active count) over
-// device tables of njobs jobs and nseg logs.  dactive points to two device
-// words: the count of running jobs after the round and the round's tile count.
-int engine_round(const Job* djobs, uint32_t njobs, ConfSeg* dcs, uint32_t nseg, uint32_t maxP,
-                 uint32_t* dactive, hipStream_t s);
+// Enqueues one round (Verify, GenerateClause, Solve, active count) over the
+// device table of njobs prepared jobs; *dactive receives the number of jobs
+// still running after it.
+int engine_round(const Job* djobs, uint32_t njobs, uint32_t* dactive, hipStream_t s);
 
 // Runs the op over all jobs; returns RP_OK or an error status.
 int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws, size_t ws_bytes,

@@ -114,7 +114,6 @@ struct Server {
   uint32_t max_resident = 0;
   // fixed tables at the start of the arena
   Job* d_jobs = nullptr;
-  ConfSeg* d_segs = nullptr;
   JobState* d_states = nullptr;
   uint32_t* d_active = nullptr;
   size_t tables = 0;
@@ -125,7 +124,6 @@ struct Server {
   std::deque<Done> done;
   std::vector<std::vector<uint8_t>> staging;
   std::vector<Job> h_jobs;
-  std::vector<ConfSeg> h_segs;
   std::vector<JobState> h_states;
   uint64_t rounds = 0;
 };
@@ -171,7 +169,7 @@ static std::vector<rp_clause> server_units(const Plan& pl, const rp_repair_opts&
 extern "C" {
 
 size_t rp_server_tables_bytes(uint32_t max_resident) {
-  return sup(max_resident * sizeof(Job)) + sup(2 * max_resident * sizeof(ConfSeg)) +
+  return sup(max_resident * sizeof(Job)) +
          sup(max_resident * sizeof(JobState)) + SALIGN;
 }
 
@@ -189,7 +187,7 @@ rp_status rp_server_create(void* arena, size_t arena_bytes, const rp_repair_opts
                            uint32_t max_resident, void* stream, void** out) {
   if (!arena || !out || max_resident == 0 || max_resident > (1u << 16)) return RP_ERR_INVALID;
   const rp_repair_opts op = opts ? *opts : rp_repair_opts{0, 1, 1, 0, 0};
-  if (op.policy > 1) return RP_ERR_INVALID;
+  if (op.policy > 1 || op.solver > 1) return RP_ERR_INVALID;
   const size_t tb = rp_server_tables_bytes(max_resident);
   if (arena_bytes < tb) return RP_ERR_WORKSPACE;
   Server* sv = new Server();
@@ -200,7 +198,6 @@ rp_status rp_server_create(void* arena, size_t arena_bytes, const rp_repair_opts
   sv->max_resident = max_resident;
   size_t o = 0;
   sv->d_jobs = (Job*)(sv->arena + o); o += sup(max_resident * sizeof(Job));
-  sv->d_segs = (ConfSeg*)(sv->arena + o); o += sup(2 * max_resident * sizeof(ConfSeg));
   sv->d_states = (JobState*)(sv->arena + o); o += sup(max_resident * sizeof(JobState));
   sv->d_active = (uint32_t*)(sv->arena + o); o += SALIGN;
   sv->tables = o;
@@ -220,6 +217,7 @@ rp_status rp_server_submit(void* srv, const rp_kernel* k, uint64_t job_id) {
   j->input.phi0 = server_units(j->plan, sv->opts);
   j->input.policy = sv->opts.policy;
   j->input.max_rounds = sv->opts.max_rounds;
+  j->input.solver = sv->opts.solver;
   j->bytes = sup(engine_job_bytes(j->input));
   if (j->bytes > sv->arena_bytes - sv->tables) return RP_ERR_BUDGET;   // can never fit
   j->t_submit = now_s();
@@ -248,27 +246,11 @@ rp_status rp_server_step(void* srv, uint32_t* n_resident, uint32_t* n_pending) {
   if (n) {
     // 2. one round over every resident job
     sv->h_jobs.resize(n);
-    sv->h_segs.clear();
-    uint32_t maxP = 1;
-    for (uint32_t q = 0; q < n; q++) {
-      SJob& j = *sv->resident[q];
-      sv->h_jobs[q] = j.prep.job;
-      maxP = std::max(maxP, j.plan.P);
-      for (uint32_t g = 0; g < j.prep.nseg; g++) {
-        ConfSeg c = j.prep.segs[g];
-        c.job = q;
-        c.ctile_beg = 0;     // laid out on the device each round
-        sv->h_segs.push_back(c);
-      }
-    }
+    for (uint32_t q = 0; q < n; q++) sv->h_jobs[q] = sv->resident[q]->prep.job;
     if (hipMemcpyAsync(sv->d_jobs, sv->h_jobs.data(), n * sizeof(Job), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
-        (!sv->h_segs.empty() &&
-         hipMemcpyAsync(sv->d_segs, sv->h_segs.data(), sv->h_segs.size() * sizeof(ConfSeg),
-                        hipMemcpyHostToDevice, s) != hipSuccess))
+        hipSuccess)
       return RP_ERR_DEVICE;
-    const int rc = engine_round(sv->d_jobs, n, sv->d_segs, (uint32_t)sv->h_segs.size(), maxP,
-                                sv->d_active, s);
+    const int rc = engine_round(sv->d_jobs, n, sv->d_active, s);
     if (rc != RP_OK) return (rp_status)rc;
     gather_states_kernel<<<(n + 255) / 256, 256, 0, s>>>(sv->d_jobs, n, sv->d_states);
     sv->h_states.resize(n);

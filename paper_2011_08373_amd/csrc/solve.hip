@@ -5,6 +5,10 @@
 // w_s*2^71 + 2^64 + 2^s, so it is additive over slots and the optimum is
 // unique.  It is carried as (hi, lo) = (sum of w_s*128+1, mask).
 //
+// Under the mhs strategy the rounds before the first SAFE take the greedy
+// hitting set of greedy_solve instead, and the round after it the exact
+// query (phase PH_FINAL) that confirms or replaces the greedy answer.
+//
 // One workgroup per job:
 //   1. unit propagation: positive units force a slot on, negative units
 //      force it off, a clause with no literal left proves UNSAT; a slot that
@@ -93,6 +97,91 @@ __device__ __forceinline__ uint64_t pat(int b) {
 
 struct DfsFrame { uint64_t ones, zeros, khi, klo, todo, tried; };
 
+constexpr uint32_t GREEDY_MAX = 16384;   // clauses the greedy step handles (bitset in LDS)
+
+// The mhs strategy's Solve (Section 2.4): the greedy minimal hitting set of
+// the positive clauses of phi -- repeatedly the slot hitting the most clauses
+// not yet hit per unit of weight (exact integer comparison, ties to the lower
+// slot), then every pick whose removal leaves all positive clauses hit is
+// dropped, last pick first.  Returns false (the caller solves exactly) when
+// phi has an empty clause, is too long, or the set breaks a clause of phi.
+__device__ bool greedy_solve(const Job& J, JobState* st, uint32_t n, const rp_clause* C,
+                             uint32_t* s_hit, uint32_t* s_c64, uint32_t* s_pick,
+                             uint32_t* s_best, uint64_t* sm) {
+  const int tid = threadIdx.x;
+  const uint32_t S = J.S;
+  if (n > GREEDY_MAX) return false;
+  const uint32_t nw = (n + 31) / 32;
+  for (uint32_t q = tid; q < nw; q += SV_BLOCK) s_hit[q] = 0;
+  __syncthreads();
+  uint64_t bad = 0;
+  for (uint32_t q = tid; q < n; q += SV_BLOCK) {
+    const rp_clause c = C[q];
+    if (c.pos == 0 && c.neg == 0) bad = 1;
+    if (!(c.pos && !c.neg)) atomicOr(&s_hit[q >> 5], 1u << (q & 31));   // not positive: ignored
+  }
+  if (block_or(bad, sm)) return false;
+  uint64_t x = 0;
+  uint32_t np = 0;
+  for (uint32_t it = 0; it < 64; it++) {
+    if (tid < 64) s_c64[tid] = 0;
+    __syncthreads();
+    for (uint32_t q = tid; q < n; q += SV_BLOCK) {
+      if ((s_hit[q >> 5] >> (q & 31)) & 1) continue;
+      uint64_t p = C[q].pos;
+      while (p) {
+        const uint32_t b = __ffsll((unsigned long long)p) - 1;
+        p &= p - 1;
+        atomicAdd(&s_c64[b], 1u);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int best = -1;
+      for (uint32_t b = 0; b < S; b++) {
+        if (!s_c64[b]) continue;
+        if (best < 0 || (uint64_t)s_c64[b] * J.weights[best] > (uint64_t)s_c64[best] * J.weights[b])
+          best = (int)b;
+      }
+      *s_best = best < 0 ? NONE32 : (uint32_t)best;
+      if (best >= 0) s_pick[np] = (uint32_t)best;
+    }
+    __syncthreads();
+    const uint32_t b = *s_best;
+    if (b == NONE32) break;
+    x |= 1ull << b;
+    np++;
+    for (uint32_t q = tid; q < n; q += SV_BLOCK)
+      if (!((s_hit[q >> 5] >> (q & 31)) & 1) && ((C[q].pos >> b) & 1))
+        atomicOr(&s_hit[q >> 5], 1u << (q & 31));
+    __syncthreads();
+  }
+  for (int k = (int)np - 1; k >= 0; k--) {
+    const uint64_t y = x & ~(1ull << s_pick[k]);
+    uint64_t miss = 0;
+    for (uint32_t q = tid; q < n; q += SV_BLOCK) {
+      const rp_clause c = C[q];
+      if (c.pos && !c.neg && !(c.pos & y)) miss = 1;
+    }
+    if (!block_or(miss, sm)) x = y;
+  }
+  uint64_t viol = 0;
+  for (uint32_t q = tid; q < n; q += SV_BLOCK) {
+    const rp_clause c = C[q];
+    if (!((c.pos & x) || (c.neg & ~x))) viol = 1;
+  }
+  if (block_or(viol, sm)) return false;
+  if (tid == 0) {
+    uint64_t W = 0;
+    for (uint32_t b = 0; b < S; b++)
+      if ((x >> b) & 1) W += J.weights[b];
+    st->x = x;
+    st->weight = W;
+    if (st->max_rounds && st->rounds >= st->max_rounds) st->state = ST_ROUNDS;
+  }
+  return true;
+}
+
 __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__ jobs) {
   __shared__ rp_clause s_cl[SV_LDS_CLAUSES];    // open clauses (restricted), 48 KiB
   __shared__ uint64_t s_lp[SV_LDS_CLAUSES / 2];  // per component: local pos / neg / aux
@@ -105,6 +194,8 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
   __shared__ uint64_t smA[SV_WAVES], smB[SV_WAVES];
   __shared__ uint32_t s_cnt, s_unsat;
   __shared__ DfsFrame s_stack[65];
+  __shared__ uint32_t s_hit[GREEDY_MAX / 32];
+  __shared__ uint32_t s_c64[64], s_pick[64], s_best;
 
   const Job& J = jobs[blockIdx.x];
   JobState* st = J.st;
@@ -114,6 +205,8 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
   const uint64_t all = S >= 64 ? ~0ull : ((1ull << S) - 1);
   const uint32_t n = st->n_phi;
   const rp_clause* C = J.phi;
+  const uint32_t phase = st->phase;
+  if (phase == PH_GREEDY && greedy_solve(J, st, n, C, s_hit, s_c64, s_pick, &s_best, smA)) return;
 
   // ---- 1. propagation
   uint64_t on = 0, off = 0;
@@ -371,6 +464,15 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
     uint64_t W = 0;
     for (uint32_t s = 0; s < S; s++)
       if ((result >> s) & 1) W += J.weights[s];
+    if (phase == PH_FINAL) {
+      // the exact query after the greedy answer was verified SAFE
+      st->phase = PH_EXACT;
+      if (result == st->x) {
+        st->weight = W;
+        st->state = ST_SAFE;
+        return;
+      }
+    }
     st->x = result;
     st->weight = W;
     if (st->max_rounds && st->rounds >= st->max_rounds) st->state = ST_ROUNDS;

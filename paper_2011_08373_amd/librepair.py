@@ -37,7 +37,7 @@ class RpClause(C.Structure):
 
 class RpOpts(C.Structure):
     _fields_ = [("policy", C.c_uint8), ("grid", C.c_uint8), ("inspect", C.c_uint8),
-                ("pad", C.c_uint8), ("max_rounds", C.c_uint32)]
+                ("solver", C.c_uint8), ("max_rounds", C.c_uint32)]
 
 
 class RpOut(C.Structure):
@@ -237,14 +237,15 @@ def min_barriers(cl, weights, n_slots: int, ws=None, stream=None):
 
 
 def repair(km, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int = 0,
-           ws=None, stream=None, traj_cap: int = 4096):
-    """Alg. 1 on the GPU; dict like the oracle's repair()."""
+           ws=None, stream=None, traj_cap: int = 4096, solver: int = 0):
+    """Alg. 1 on the GPU; dict like the oracle's repair().  solver 0: exact
+    Solve every round; 1: the mhs strategy (Section 2.4)."""
     ka = KernelArg(km)
     need = int(_L.rp_workspace_bytes(ka.ref, OP_REPAIR))
     if need == 0:
         return dict(status=ERR_INVALID, ret=ERR_INVALID)
     ptr, size = (ws or _ws).get(need)
-    o = RpOpts(policy, grid, inspect, 0, max_rounds)
+    o = RpOpts(policy, grid, inspect, solver, max_rounds)
     out = RpOut()
     traj = (C.c_uint64 * max(1, traj_cap))()
     st = _L.rp_repair(ka.ref, C.byref(o), C.byref(out), traj, traj_cap, C.c_void_p(ptr), size,
@@ -271,7 +272,7 @@ def batch_workspace_bytes(kms) -> int:
 
 
 def repair_batch(kms, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int = 0,
-                 ws=None, stream=None):
+                 ws=None, stream=None, solver: int = 0):
     """Alg. 1 over many kernels in one batched run; (status, [result dict per kernel]).
     Runs on a dedicated non-default stream unless one is given, so that each
     round can be replayed as a captured graph."""
@@ -279,7 +280,7 @@ def repair_batch(kms, policy: int = 0, grid: int = 1, inspect: int = 1, max_roun
     b = kms if isinstance(kms, BatchArg) else BatchArg(kms)
     need = int(_L.rp_batch_workspace_bytes(b.ptrs, b.n))
     ptr, size = (ws or _ws).get(need)
-    o = RpOpts(policy, grid, inspect, 0, max_rounds)
+    o = RpOpts(policy, grid, inspect, solver, max_rounds)
     outs = (RpOut * max(1, b.n))()
     st_obj = stream if stream is not None else _batch_stream()
     torch.cuda.current_stream().synchronize()
@@ -308,12 +309,12 @@ class Server:
     """Continuous-batching repair server over a torch-allocated device arena."""
 
     def __init__(self, arena_bytes: int, max_resident: int = 1024, policy: int = 0, grid: int = 1,
-                 inspect: int = 1, max_rounds: int = 0, stream=None):
+                 inspect: int = 1, max_rounds: int = 0, stream=None, solver: int = 0):
         import torch
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.Stream()
         torch.cuda.current_stream().synchronize()
-        o = RpOpts(policy, grid, inspect, 0, max_rounds)
+        o = RpOpts(policy, grid, inspect, solver, max_rounds)
         h = C.c_void_p()
         st = _L.rp_server_create(C.c_void_p(self.arena.data_ptr()), int(arena_bytes), C.byref(o),
                                  int(max_resident), C.c_void_p(self.stream.cuda_stream),
