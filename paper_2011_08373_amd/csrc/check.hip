@@ -5,14 +5,15 @@
 //              barrier occurrences before each point (any level, and grid
 //              level only), the divergent enabled slots, and the first
 //              partners under x resolved from the table j0 (or reset).
-// conf_kernel  scan of the run logs (runs.hip).  Runs are in program order
-//              inside a location, so the runs of one interval are contiguous.
-//              Two runs race when one writes and they are not the same single
-//              thread (same-block view) or the same single block (cross-block
-//              view).  In "first" mode a run stops at its first racing
-//              partner (enough for the reduced clause set); in "all" mode
-//              every racing pair goes into a bitmap.  conf_tiles_kernel lays
-//              the round's tiles over the logs of the jobs still running.
+// conf_kernel  scan of the run logs (runs.hip) under x for every racing pair
+//              (the check call).  Runs are in program order inside a
+//              location, so the runs of one interval are contiguous.  Two runs
+//              race when one writes and they are not the same single thread
+//              (same-block view) or the same single block (cross-block view).
+//              conf_tiles_kernel lays the tiles over the logs of the jobs
+//              still running.
+// j0_kernel    the first partner of every point with no barrier enabled,
+//              from which ivl_kernel resolves the first partners under any x.
 // pairs_kernel turns the bitmap into the (level, i, j)-ordered pair list.
 #include <algorithm>
 
@@ -313,6 +314,223 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// First partners with no barrier enabled (the table j0), in one pass over the
+// run logs with no per-run walk.
+//
+// With every barrier off a location is one sub-segment, and the first
+// partner of run r is the first later run q of its location with (W_r or
+// W_q) and (M_r or M_q or id_r != id_q).  Call a "streak" a maximal stretch
+// of single runs of one id (a new location, a multi run or a new id starts
+// one) and, among the writes of a location, a "write streak" likewise.  Then:
+//   - W and M: r races with itself;
+//   - M only: the first write after r;
+//   - single write: the next run, or if it is the same single id, the end of
+//     that run's streak;
+//   - single read: the first write f after r, or if f is the same single id,
+//     the end of f's write streak.
+// Each wave stages 1024 runs in LDS and walks them in chunks of 64 from the
+// last to the first; inside a chunk the candidates come from ballot masks,
+// past it from four wave-wide carries (the next run, its streak end, the
+// first write ahead and that write's write-streak end), which are set up at
+// the end of the range by short probes (a location holds at most one run per
+// point).
+__device__ __forceinline__ uint64_t bits_above(int k) {   // bits k+1..63
+  return k >= 63 ? 0ull : (~0ull << (k + 1));
+}
+__device__ __forceinline__ uint64_t bits_below(int k) {   // bits 0..k-1
+  return k <= 0 ? 0ull : (k >= 64 ? ~0ull : ((1ull << k) - 1));
+}
+__device__ __forceinline__ int low_bit(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+
+__device__ __forceinline__ bool run_single_same(uint64_t a, uint64_t b) {   // same single id
+  return !((a >> RUN_MULTI) & 1) && !((b >> RUN_MULTI) & 1) && (uint32_t)a == (uint32_t)b;
+}
+
+// First position q > a with a streak start (relative to q-1), or n.
+__device__ uint64_t probe_streak_end(const uint64_t* runs, uint64_t a, uint64_t n) {
+  for (uint64_t base = a + 1; base < n; base += 64) {
+    const uint64_t q = base + __lane_id();
+    const uint64_t e = run_at(runs, q, n);
+    const uint64_t pr = q - 1 < n ? runs[q - 1] : RUN_SENTINEL;
+    const bool x = q < n && (((e >> RUN_LOC) & 1) || !run_single_same(e, pr));
+    const uint64_t xm = __ballot(x);
+    if (xm) return base + low_bit(xm);
+  }
+  return n;
+}
+
+// First write q > f with (M_q or id_q != id_f) before the location ends, or NOPOS.
+__device__ uint64_t probe_write_streak_end(const uint64_t* runs, uint64_t f, uint64_t ef, uint64_t n) {
+  for (uint64_t base = f + 1; base < n; base += 64) {
+    const uint64_t e = run_at(runs, base + __lane_id(), n);
+    const uint64_t hm = __ballot(((e >> RUN_W) & 1) && !run_single_same(e, ef) &&
+                                 !((e >> RUN_END) & 1));
+    const uint64_t lm = __ballot((e >> RUN_LOC) & 1);
+    if (hm && (!lm || low_bit(hm) < low_bit(lm))) return base + low_bit(hm);
+    if (lm) return NOPOS;
+  }
+  return NOPOS;
+}
+
+__global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ jobs,
+                                                        const ConfSeg* __restrict__ segs, int nseg,
+                                                        const uint32_t* __restrict__ total_at) {
+  __shared__ uint64_t s_buf[CONF_WAVES][CONF_CHUNKS * 64];
+  extern __shared__ uint32_t s_dyn[];        // [P] first partner
+  const uint32_t total = *total_at;
+  const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
+  const uint32_t t0 = blockIdx.x * per;
+  const uint32_t t1 = min(t0 + per, total);
+  const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
+  uint64_t* buf = s_buf[wv];
+  int cur = -1;
+  uint32_t* s_minj = s_dyn;
+  uint32_t P = 0;
+  for (uint32_t tile = t0; tile < t1; tile++) {
+    int lo = 0, hi = nseg - 1;   // largest segment with ctile_beg <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].ctile_beg <= tile) lo = mid; else hi = mid - 1;
+    }
+    if (lo != cur) {
+      __syncthreads();
+      if (cur >= 0) {
+        const Job& J = jobs[segs[cur].job];
+        uint32_t* g = J.minj + (uint64_t)segs[cur].level * J.P;
+        for (uint32_t i = tid; i < J.P; i += CONF_BLOCK)
+          if (s_minj[i] != NONE32) atomicMin(&g[i], s_minj[i]);
+      }
+      __syncthreads();
+      cur = lo;
+      P = jobs[segs[cur].job].P;
+      for (uint32_t i = tid; i < P; i += CONF_BLOCK) s_minj[i] = NONE32;
+      __syncthreads();
+    }
+    const ConfSeg& sg = segs[cur];
+    const uint64_t n = sg.n_runs_at ? *sg.n_runs_at : sg.n_runs;
+    const uint64_t wbeg = (uint64_t)(tile - sg.ctile_beg) * CONF_TILE + (uint64_t)wv * (CONF_CHUNKS * 64);
+    if (wbeg >= n) continue;
+    const uint64_t wend = min(wbeg + (uint64_t)(CONF_CHUNKS * 64), n);
+    const uint64_t* __restrict__ runs = sg.runs;
+#pragma unroll
+    for (int k = 0; k < CONF_CHUNKS; k++) buf[k * 64 + lane] = run_at(runs, wbeg + k * 64 + lane, n);
+    __builtin_amdgcn_wave_barrier();
+    auto entry = [&](uint64_t q) -> uint64_t {
+      return (q >= wbeg && q < wend) ? buf[q - wbeg] : run_at(runs, q, n);
+    };
+    auto accepts = [&](uint64_t ea, uint64_t eb) -> bool {   // different threads (blocks)
+      return !run_single_same(ea, eb);
+    };
+    // carries for the positions from the end of the range on
+    uint64_t A = wend;                                   // next run
+    const uint64_t eA0 = run_at(runs, wend, n);
+    bool XA = wend >= n || ((eA0 >> RUN_LOC) & 1) || !run_single_same(eA0, buf[wend - 1 - wbeg]);
+    uint64_t SEA = wend < n ? probe_streak_end(runs, wend, n) : n;   // its streak end
+    uint64_t FW = first_write_from(runs, wend, n);       // first write ahead
+    uint64_t NWS = FW != NOPOS ? probe_write_streak_end(runs, FW, runs[FW], n) : NOPOS;
+    const int nch = (int)((wend - wbeg + 63) / 64);
+    for (int c = nch - 1; c >= 0; c--) {
+      const uint64_t p0 = wbeg + (uint64_t)c * 64;
+      const uint64_t e = buf[c * 64 + lane];
+      const bool valid = !((e >> RUN_END) & 1);
+      const uint32_t i = (uint32_t)(e >> RUN_PT) & 0xFFFu;
+      const bool w = (e >> RUN_W) & 1, m = (e >> RUN_MULTI) & 1, ls = (e >> RUN_LOC) & 1;
+      // predecessor (lane 0: the last run of the chunk before, or before the range)
+      uint64_t pe = __shfl_up(e, 1);
+      if (lane == 0) pe = c > 0 ? buf[c * 64 - 1] : (wbeg > 0 ? runs[wbeg - 1] : RUN_SENTINEL);
+      const bool x = ls || !run_single_same(e, pe) || p0 + lane == 0;
+      const uint64_t Xm = __ballot(x);
+      const uint64_t Lm = __ballot(ls);
+      const uint64_t Wm = __ballot(w && valid);
+      // write-streak starts among the writes of the chunk (relative to the
+      // previous write of the chunk; only queried after an earlier write)
+      const uint64_t pwm = Wm & bits_below(lane);
+      const int pw = pwm ? 63 - __clzll((long long)pwm) : 0;
+      const uint64_t epw = __shfl(e, pw);
+      const bool xw = w && valid && pwm &&
+                      ((Lm & bits_above(pw) & bits_below(lane + 1)) || !run_single_same(e, epw));
+      const uint64_t XWm = __ballot(xw);
+      if (valid && i < P) {
+        uint32_t best = NONE32;
+        const uint64_t gt = bits_above(lane);
+        // first write after this run, in the chunk or carried
+        const uint64_t hw = Wm & gt, hl = Lm & gt;
+        uint64_t f = NOPOS;
+        bool f_in = false;
+        if (hw && (!hl || low_bit(hw) < low_bit(hl))) { f = p0 + low_bit(hw); f_in = true; }
+        else if (!hl) f = FW;
+        if (w && m) {
+          best = i;
+        } else if (m) {
+          if (f != NOPOS) best = (uint32_t)(entry(f) >> RUN_PT) & 0xFFFu;
+        } else if (w) {
+          const uint64_t q1 = p0 + lane + 1;
+          const uint64_t e1 = lane < 63 ? buf[c * 64 + lane + 1] : run_at(runs, q1, n);
+          if (q1 < n && !((e1 >> RUN_LOC) & 1)) {
+            uint64_t q = q1;
+            if (!accepts(e, e1)) {
+              const uint64_t hx = lane < 63 ? (Xm & bits_above(lane + 1)) : 0ull;
+              q = hx ? p0 + low_bit(hx) : (lane < 63 && XA ? A : SEA);
+            }
+            if (q < n) {
+              const uint64_t eq = entry(q);
+              if (!((eq >> RUN_LOC) & 1)) best = (uint32_t)(eq >> RUN_PT) & 0xFFFu;
+            }
+          }
+        } else if (f != NOPOS) {
+          const uint64_t ef = entry(f);
+          uint64_t g = f;
+          if (!accepts(e, ef)) {
+            if (f_in) {
+              const int fl = (int)(f - p0);
+              const uint64_t hxw = XWm & bits_above(fl), hl2 = Lm & bits_above(fl);
+              if (hxw && (!hl2 || low_bit(hxw) < low_bit(hl2))) g = p0 + low_bit(hxw);
+              else if (hl2) g = NOPOS;
+              else g = (FW != NOPOS && accepts(ef, entry(FW))) ? FW : NWS;
+            } else {
+              g = NWS;
+            }
+          }
+          if (g != NOPOS) best = (uint32_t)(entry(g) >> RUN_PT) & 0xFFFu;
+        }
+        if (best < P && s_minj[i] > best) atomicMin(&s_minj[i], best);
+      }
+      // carries for the positions from p0 on
+      const uint64_t hx0 = Xm & ~1ull;
+      const uint64_t nSEA = hx0 ? p0 + low_bit(hx0) : (XA ? A : SEA);
+      const bool nXA = Xm & 1ull;
+      const int fl0 = Lm ? low_bit(Lm) : 64;
+      const uint64_t wb = Wm & bits_below(fl0);
+      if (wb) {
+        const int f0 = low_bit(wb);
+        const uint64_t ef0 = buf[c * 64 + f0];
+        const uint64_t hxw = XWm & bits_above(f0), hl2 = Lm & bits_above(f0);
+        uint64_t nn;
+        if (hxw && (!hl2 || low_bit(hxw) < low_bit(hl2))) nn = p0 + low_bit(hxw);
+        else if (hl2) nn = NOPOS;
+        else nn = (FW != NOPOS && accepts(ef0, entry(FW))) ? FW : NWS;
+        FW = p0 + f0;
+        NWS = nn;
+      } else if (Lm) {
+        FW = NOPOS;
+        NWS = NOPOS;
+      }
+      A = p0;
+      XA = nXA;
+      SEA = nSEA;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  if (cur >= 0) {
+    const Job& J = jobs[segs[cur].job];
+    uint32_t* g = J.minj + (uint64_t)segs[cur].level * J.P;
+    for (uint32_t i = tid; i < J.P; i += CONF_BLOCK)
+      if (s_minj[i] != NONE32) atomicMin(&g[i], s_minj[i]);
+  }
+}
+
 // Bitmap rows (level, i) in order -> pair list; one workgroup, rows in
 // contiguous chunks per thread so the block scan keeps row order.
 __global__ __launch_bounds__(1024) void pairs_kernel(const Job* __restrict__ jobs, rp_pair* out,
@@ -386,19 +604,33 @@ hipError_t launch_conf_tiles(const Job* jobs, ConfSeg* segs, int nseg, uint32_t*
 }
 
 hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
-                       int all_pairs, const uint32_t* tiles, hipStream_t s) {
+                       const uint32_t* tiles, hipStream_t s) {
   if (nseg == 0) return hipSuccess;
   const size_t dyn = 2 * (size_t)(max_points ? max_points : 1) * sizeof(uint32_t);
   int dev = 0, ncu = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const hipError_t oe = all_pairs
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conf_kernel<true>, CONF_BLOCK, dyn)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conf_kernel<false>, CONF_BLOCK, dyn);
-  if (oe != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conf_kernel<true>, CONF_BLOCK, dyn) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
   const uint32_t grid = (uint32_t)ncu * (uint32_t)std::min(per_cu, 8);
-  if (all_pairs) conf_kernel<true><<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
-  else conf_kernel<false><<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
+  conf_kernel<true><<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_j0(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
+                     const uint32_t* tiles, hipStream_t s) {
+  if (nseg == 0) return hipSuccess;
+  const size_t dyn = (size_t)(max_points ? max_points : 1) * sizeof(uint32_t);
+  int dev = 0, ncu = 256, per_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, j0_kernel, CONF_BLOCK, dyn) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const uint32_t grid = (uint32_t)ncu * (uint32_t)std::min(per_cu, 8);
+  j0_kernel<<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
   return hipGetLastError();
 }
 

@@ -318,7 +318,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     if (!L.ssegs.empty()) {
       HIPCHK(launch_conf_tiles(djobs, dcs, (int)L.ssegs.size(), derr + 9, s));
       tm.mark(T_SUMPRE);
-      HIPCHK(launch_conf(djobs, dcs, (int)L.ssegs.size(), maxP, 0, derr + 9, s));
+      HIPCHK(launch_j0(djobs, dcs, (int)L.ssegs.size(), maxP, derr + 9, s));
       tm.mark(T_SUMMARY);
     }
     HIPCHK(launch_save_j0(djobs, (uint32_t)N, s));
@@ -393,7 +393,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     HIPCHK(launch_ivl(djobs, (uint32_t)N, IVL_CHECK, s));
     HIPCHK(launch_conf_tiles(djobs, dcs, nseg, dtiles, s));
     tm.mark(T_CONFPRE);
-    HIPCHK(launch_conf(djobs, dcs, nseg, maxP, 1, dtiles, s));
+    HIPCHK(launch_conf(djobs, dcs, nseg, maxP, dtiles, s));
     tm.mark(T_CHECK);
     for (size_t j = 0; j < N; j++)
       HIPCHK(launch_pairs(djobs + j, (rp_pair*)(d + L.o_pairs[j]), (uint64_t*)(d + L.o_ptotal[j]), s));

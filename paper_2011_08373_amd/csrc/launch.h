@@ -28,9 +28,12 @@ hipError_t launch_save_j0(const Job* jobs, uint32_t njobs, hipStream_t s);
 // each segment, the total in *tiles.
 hipError_t launch_conf_tiles(const Job* jobs, ConfSeg* segs, int nseg, uint32_t* tiles,
                              hipStream_t s);
-// Scans the tiles laid out by launch_conf_tiles.
+// Every racing pair under x over the tiles laid out by launch_conf_tiles.
 hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
-                       int all_pairs, const uint32_t* tiles, hipStream_t s);
+                       const uint32_t* tiles, hipStream_t s);
+// First partners with no barrier enabled, into minj (cleared beforehand).
+hipError_t launch_j0(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
+                     const uint32_t* tiles, hipStream_t s);
 hipError_t launch_pairs(const Job* job, rp_pair* out, uint64_t* total, hipStream_t s);
 hipError_t launch_clause(const Job* jobs, uint32_t njobs, int learn, hipStream_t s);
 hipError_t launch_solve(const Job* jobs, uint32_t njobs, hipStream_t s);
