@@ -95,7 +95,7 @@ def kernel_rooflines(stats):
     kernels timed one by one on the library's stream."""
     n = len(stats)
     last = stats[-1]
-    rec, runs = last["records"], last["runs"]
+    rec = last["records"]
     out = {}
 
     def entry(name, bytes_per_launch, total_ms, launches):
@@ -110,8 +110,8 @@ def kernel_rooflines(stats):
     # radix scatter pass: reads and writes 8 B per record
     entry("scatter_kernel", 16 * rec, sum(s["ms_sort_kernels"] for s in stats),
           sum(s["sort_launches"] for s in stats))
-    # conflict scan: reads 8 B per run-log entry
-    entry("conf_kernel", 8 * runs, sum(s["ms_conf_kernels"] for s in stats),
+    # first-partner scan (once per repair): reads 8 B per record
+    entry("j0_kernel", 8 * rec, sum(s["ms_conf_kernels"] for s in stats),
           sum(s["conf_launches"] for s in stats))
     # record generation: writes 8 B per record
     entry("gen_kernel", 8 * rec, sum(s["ms_gen"] for s in stats), n)
@@ -152,7 +152,7 @@ def batched_leg(L, torch, kms):
             "repaired": rep, "unsat": uns, "other": len(kms) - rep - uns,
             "batched_equals_plain": same, "records": bstats["records"],
             "accesses": bstats["accesses"], "rounds": bstats["rounds"],
-            "phases_ms": {k: bstats[k] for k in ("ms_gen", "ms_sort", "ms_runs", "ms_check",
+            "phases_ms": {k: bstats[k] for k in ("ms_gen", "ms_sort", "ms_j0", "ms_check",
                                                  "ms_clause", "ms_solve", "ms_total")},
             "autotuned": tuned}
 
@@ -251,7 +251,7 @@ def main():
         "config": {"workload": "plain-large %s: 256 blocks x 256 threads, 512 points, "
                                "32 slots (8 grid), 2 shared + 2 global arrays of 1M words, "
                                "seed 2" % args.mode,
-                   "accesses": acc, "records": stats[-1]["records"], "runs": stats[-1]["runs"],
+                   "accesses": acc, "records": stats[-1]["records"],
                    "verify_calls": r["rounds"], "repair_status": r["status"]},
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
                                           "kernel", "avg_launch_ms", "bytes_per_launch")},
@@ -262,7 +262,7 @@ def main():
                                       (sum(s["ms_conf_kernels"] for s in stats) / 1e3)
                                       if sum(s["ms_conf_kernels"] for s in stats) > 0 else None),
         "phases_ms": {k: sum(s[k] for s in stats) / len(stats)
-                      for k in ("ms_upload", "ms_gen", "ms_sort", "ms_runs", "ms_check",
+                      for k in ("ms_upload", "ms_gen", "ms_sort", "ms_j0", "ms_check",
                                 "ms_clause", "ms_solve", "ms_total")},
     }
     if args.mode == "literal" and "planted" in set(args.legs.split(",")):
@@ -275,9 +275,9 @@ def main():
         out["planted"] = {"value": kp_acc * rp["rounds"] / (msp / 1e3), "ms_per_step": msp,
                           "verify_calls": rp["rounds"], "repair_status": rp["status"],
                           "weight": rp["weight"],
-                          "conf_kernel_frac": kk["conf_kernel"]["frac"],
+                          "j0_kernel_frac": kk["j0_kernel"]["frac"],
                           "phases_ms": {k: sum(s[k] for s in stp) / len(stp)
-                                        for k in ("ms_gen", "ms_sort", "ms_runs", "ms_check",
+                                        for k in ("ms_gen", "ms_sort", "ms_j0", "ms_check",
                                                   "ms_clause", "ms_solve", "ms_total")}}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(km, r["rounds"])

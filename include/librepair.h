@@ -138,15 +138,15 @@ typedef struct {
   double ms_gen, ms_sort, ms_check, ms_clause, ms_solve, ms_total;
   double ms_sort_pass_max;       /* longest single sort pass */
   double ms_sort_kernels;        /* sum of the radix-pass kernel durations */
-  double ms_runs;                /* run-log build (once per kernel) */
+  double ms_j0;                  /* first partners with no barrier enabled
+                                    (once per kernel) */
   uint64_t records;              /* access records generated (both views) */
   uint64_t accesses;             /* (point, block, thread) accesses */
   uint64_t records_scanned;      /* records read by conflict scans */
   uint32_t sort_passes, sort_launches, rounds, conf_launches;
   double ms_upload;              /* descriptor upload before record generation */
-  double ms_conf_kernels;        /* sum of the conflict-scan kernel durations
-                                    (rounds run outside a graph only) */
-  uint64_t runs;                 /* run-log entries (both views, all kernels) */
+  double ms_conf_kernels;        /* duration of the scan kernel over the
+                                    sorted logs (first partners or all pairs) */
 } rp_stats;
 
 const char* rp_status_string(int status);

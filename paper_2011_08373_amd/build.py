@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "lib", "librepair.so")
-SOURCES = ["gen.hip", "sort.hip", "runs.hip", "check.hip", "clause.hip", "solve.hip",
+SOURCES = ["gen.hip", "sort.hip", "check.hip", "clause.hip", "solve.hip",
            "librepair.cpp", "engine.cpp", "api.cpp", "server.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-result",

@@ -5,11 +5,11 @@
 //              barrier occurrences before each point (any level, and grid
 //              level only), the divergent enabled slots, and the first
 //              partners under x resolved from the table j0 (or reset).
-// conf_kernel  scan of the run logs (runs.hip) under x for every racing pair
-//              (the check call).  Runs are in program order inside a
-//              location, so the runs of one interval are contiguous.  Two runs
-//              race when one writes and they are not the same single thread
-//              (same-block view) or the same single block (cross-block view).
+// conf_kernel  scan of the sorted logs under x for every racing pair (the
+//              check call).  Records are in program order inside a location,
+//              so the records of one interval are contiguous.  Two records
+//              race when one writes and their ids (thread in the same-block
+//              view, block in the cross-block view) differ.
 //              conf_tiles_kernel lays the tiles over the logs of the jobs
 //              still running.
 // j0_kernel    the first partner of every point with no barrier enabled,
@@ -25,8 +25,8 @@ namespace rp {
 constexpr int IVL_BLOCK = 1024;
 constexpr int CONF_BLOCK = 256;
 constexpr int CONF_WAVES = CONF_BLOCK / 64;
-constexpr int CONF_CHUNKS = 16;                          // chunks of 64 runs per wave and tile
-constexpr uint32_t CONF_TILE = CONF_WAVES * CONF_CHUNKS * 64;   // runs per tile
+constexpr int CONF_CHUNKS = 16;                          // chunks of 64 records per wave and tile
+constexpr uint32_t CONF_TILE = CONF_WAVES * CONF_CHUNKS * 64;   // records per tile
 
 // mode IVL_RESOLVE: interval ids under x, then the first partners under x
 //   from the assignment-independent table j0 (see below);
@@ -113,7 +113,7 @@ __device__ __forceinline__ void set_pair(uint64_t* bm, uint32_t wpr, uint32_t P,
   if (!(*wp & bit)) atomicOr((unsigned long long*)wp, (unsigned long long)bit);
 }
 
-// Tile table of one round: runs of the logs of running jobs only, in
+// Tile table of one scan: records of the logs of running jobs only, in
 // segment order; one workgroup.
 __global__ __launch_bounds__(1024) void conf_tiles_kernel(const Job* __restrict__ jobs,
                                                           ConfSeg* segs, uint32_t nseg,
@@ -126,8 +126,7 @@ __global__ __launch_bounds__(1024) void conf_tiles_kernel(const Job* __restrict_
     uint32_t v = 0;
     if (q < nseg) {
       const ConfSeg& sg = segs[q];
-      const uint64_t n = sg.n_runs_at ? *sg.n_runs_at : sg.n_runs;
-      if (jobs[sg.job].st->state == ST_RUN) v = (uint32_t)((n + CONF_TILE - 1) / CONF_TILE);
+      if (jobs[sg.job].st->state == ST_RUN) v = (uint32_t)((sg.n + CONF_TILE - 1) / CONF_TILE);
     }
     uint32_t inc = v;
     for (int o = 1; o < 64; o <<= 1) {
@@ -148,18 +147,83 @@ __global__ __launch_bounds__(1024) void conf_tiles_kernel(const Job* __restrict_
   if (threadIdx.x == 0) *total = run;
 }
 
-__device__ __forceinline__ uint64_t run_at(const uint64_t* runs, uint64_t q, uint64_t n) {
-  return q < n ? runs[q] : RUN_SENTINEL;
+// A sorted log read as a sequence of one-record runs.  Record q becomes the
+// entry  id | point << RUN_PT | writes << RUN_W | first-of-location << RUN_LOC
+// (the id is the thread in the same-block view, the block in the cross-block
+// view); two records of one point at one location are two runs of that point,
+// which races with itself when it writes and their ids differ, and records
+// equal in (point, id) never race with each other.  Past the end: the
+// sentinel.
+struct RecView {
+  const uint64_t* log;
+  uint64_t n;
+  int psh, lsh, ish;       // point field, location, id shifts
+  uint64_t imask;
+  uint32_t pmask;
+  const uint64_t* wb;      // write bit of each point (LDS)
+};
+
+__device__ __forceinline__ uint64_t shr(uint64_t v, int s) { return s >= 64 ? 0ull : v >> s; }
+
+__device__ __forceinline__ RecView rec_view(const Job& J, const ConfSeg& sg, const uint64_t* wb) {
+  RecView v;
+  v.log = sg.log;
+  v.n = sg.n;
+  // same-block view: [array|word|block|point|thread]; location = (array, word, block)
+  // cross-block view: [array|word|point|block|0];     location = (array, word)
+  v.psh = sg.level == 0 ? (int)J.tbits : (int)(J.bbits + J.tbits);
+  v.lsh = v.psh + (int)J.pbits;
+  v.ish = sg.level == 0 ? 0 : (int)J.tbits;
+  v.imask = sg.level == 0 ? ((1ull << J.tbits) - 1) : ((1ull << J.bbits) - 1);
+  v.pmask = (1u << J.pbits) - 1u;
+  v.wb = wb;
+  return v;
+}
+
+__device__ __forceinline__ uint64_t make_entry(const RecView& v, uint64_t rec, uint64_t prev,
+                                               uint64_t q) {
+  if (q >= v.n) return RUN_SENTINEL;
+  const uint32_t i = (uint32_t)shr(rec, v.psh) & v.pmask;
+  const uint64_t id = shr(rec, v.ish) & v.imask;
+  const uint64_t w = (v.wb[i >> 6] >> (i & 63)) & 1;
+  const uint64_t loc = q == 0 || shr(rec, v.lsh) != shr(prev, v.lsh);
+  return id | ((uint64_t)i << RUN_PT) | (w << RUN_W) | (loc << RUN_LOC);
+}
+
+__device__ __forceinline__ uint64_t entry_at(const RecView& v, uint64_t q) {
+  if (q >= v.n) return RUN_SENTINEL;
+  return make_entry(v, v.log[q], q > 0 ? v.log[q - 1] : 0, q);
+}
+
+// Stages records [b, b + 64*K) of a log as entries (all loads first).
+template <int K>
+__device__ __forceinline__ void stage_entries(const RecView& v, uint64_t b, uint64_t* buf) {
+  const int lane = __lane_id();
+  uint64_t r[K], p0;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const uint64_t q = b + k * 64 + lane;
+    r[k] = q < v.n ? v.log[q] : 0;
+  }
+  p0 = (lane == 0 && b > 0 && b - 1 < v.n) ? v.log[b - 1] : 0;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    uint64_t pr = __shfl_up(r[k], 1);
+    const uint64_t last = k > 0 ? __shfl(r[k - 1], 63) : p0;   // every lane takes part
+    if (lane == 0) pr = last;
+    buf[k * 64 + lane] = make_entry(v, r[k], pr, b + k * 64 + lane);
+  }
 }
 
 constexpr uint64_t NOPOS = ~0ull;
 
 // First write run at or after position q, before the next location starts
-// (NOPOS if none): wave-cooperative, 64 runs at a time.  A location holds at
-// most one run per point, so this ends within P / 64 + 1 steps.
-__device__ uint64_t first_write_from(const uint64_t* runs, uint64_t q, uint64_t n) {
+// (NOPOS if none): wave-cooperative, 64 entries at a time; it ends at the
+// end of the location.
+__device__ uint64_t first_write_from(const RecView& v, uint64_t q) {
+  const uint64_t n = v.n;
   for (; q < n; q += 64) {
-    const uint64_t e = run_at(runs, q + __lane_id(), n);
+    const uint64_t e = entry_at(v, q + __lane_id());
     const uint64_t wm = __ballot((e >> RUN_W) & 1);
     const uint64_t lm = __ballot((e >> RUN_LOC) & 1);
     if (wm && (!lm || __ffsll((unsigned long long)wm) < __ffsll((unsigned long long)lm)))
@@ -169,23 +233,20 @@ __device__ uint64_t first_write_from(const uint64_t* runs, uint64_t q, uint64_t 
   return NOPOS;
 }
 
-// Racing partners over the run log.  A sub-segment (one location, one
-// interval) is a contiguous stretch of runs.  Each wave stages a range of
-// 1024 runs in LDS (all loads in flight at once) and walks it in chunks of
-// 64, one run per lane, from the last chunk to the first.  Inside a chunk,
-// ballots give sub-segment starts, writes and multi runs as 64-bit masks, so
-// a lane finds the runs after its own with mask operations.  Past its chunk,
-// a reading run can only race with the first write that follows in its
-// location: the wave carries that position from chunk to chunk (backwards),
-// so a read costs O(1) however long its sub-segment is.  A writing run's next
-// candidate past the chunk is the next run.  Only a candidate rejected for
-// being the same single thread (block) leads to a walk.
+// Racing pairs over a sorted log (the check call, which needs every pair).
+// A sub-segment (one location, one interval) is a contiguous stretch of
+// records.  Each wave stages a range of 1024 records in LDS (all loads in
+// flight at once) and walks it in chunks of 64, one record per lane.  Inside
+// a chunk, ballots give sub-segment starts and writes as 64-bit masks, so a
+// lane takes the records after its own with mask operations; past its chunk
+// it visits the rest of its sub-segment in order.
 template <bool ALL>
 __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict__ jobs,
                                                           const ConfSeg* __restrict__ segs,
                                                           int nseg,
                                                           const uint32_t* __restrict__ total_at) {
   __shared__ uint64_t s_buf[CONF_WAVES][CONF_CHUNKS * 64];
+  __shared__ uint64_t s_wb[MAX_POINTS / 64];
   extern __shared__ uint32_t s_dyn[];        // [P] interval of each point, [P] first partner
   const uint32_t total = *total_at;
   const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
@@ -222,25 +283,25 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
         s_iv[i] = iv[i];
         s_minj[i] = NONE32;
       }
+      for (uint32_t q = tid; q < (P + 63) / 64; q += CONF_BLOCK) s_wb[q] = J.wbits[q];
       __syncthreads();
     }
     const ConfSeg& sg = segs[cur];
-    const uint64_t n = sg.n_runs_at ? *sg.n_runs_at : sg.n_runs;
+    const uint64_t n = sg.n;
     const uint64_t wbeg = (uint64_t)(tile - sg.ctile_beg) * CONF_TILE + (uint64_t)wv * (CONF_CHUNKS * 64);
     if (wbeg >= n) continue;
     const uint64_t wend = min(wbeg + (uint64_t)(CONF_CHUNKS * 64), n);
     const Job& J = jobs[sg.job];
     const uint32_t level = sg.level;
-    const uint64_t* __restrict__ runs = sg.runs;
+    const RecView V = rec_view(J, sg, s_wb);
     // stage the range
-#pragma unroll
-    for (int k = 0; k < CONF_CHUNKS; k++) buf[k * 64 + lane] = run_at(runs, wbeg + k * 64 + lane, n);
+    stage_entries<CONF_CHUNKS>(V, wbeg, buf);
     // first write past the range in the same location
-    uint64_t carry = first_write_from(runs, wend, n);
+    uint64_t carry = first_write_from(V, wend);
     __builtin_amdgcn_wave_barrier();
     // entry at an absolute position: staged or global
     auto entry = [&](uint64_t q) -> uint64_t {
-      return q < wend ? buf[q - wbeg] : run_at(runs, q, n);
+      return q < wend ? buf[q - wbeg] : entry_at(V, q);
     };
     const int nch = (int)((wend - wbeg + 63) / 64);
     for (int c = nch - 1; c >= 0; c--) {
@@ -316,25 +377,24 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
 
 // ---------------------------------------------------------------------------
 // First partners with no barrier enabled (the table j0), in one pass over the
-// run logs with no per-run walk.
+// sorted logs with no per-record walk.
 //
 // With every barrier off a location is one sub-segment, and the first
-// partner of run r is the first later run q of its location with (W_r or
-// W_q) and (M_r or M_q or id_r != id_q).  Call a "streak" a maximal stretch
-// of single runs of one id (a new location, a multi run or a new id starts
-// one) and, among the writes of a location, a "write streak" likewise.  Then:
-//   - W and M: r races with itself;
-//   - M only: the first write after r;
-//   - single write: the next run, or if it is the same single id, the end of
-//     that run's streak;
-//   - single read: the first write f after r, or if f is the same single id,
-//     the end of f's write streak.
-// Each wave stages 1024 runs in LDS and walks them in chunks of 64 from the
-// last to the first; inside a chunk the candidates come from ballot masks,
-// past it from four wave-wide carries (the next run, its streak end, the
-// first write ahead and that write's write-streak end), which are set up at
-// the end of the range by short probes (a location holds at most one run per
-// point).
+// partner of record r is the first later record q of its location with
+// (W_r or W_q) and id_r != id_q.  Call a "streak" a maximal stretch of records
+// of one id (a new location or a new id starts one) and, among the writes of
+// a location, a "write streak" likewise.  Then the first partner of
+//   - a write is the next record, or if that has the same id, the end of its
+//     streak;
+//   - a read is the first write f after it, or if f has the same id, the end
+//     of f's write streak.
+// (A point racing with itself needs no case of its own: its next record with
+// another id is that partner.)  Each wave stages 1024 records in LDS and walks
+// them in chunks of 64 from the last to the first; inside a chunk the
+// candidates come from ballot masks, past it from four wave-wide carries (the
+// next record, its streak end, the first write ahead and that write's
+// write-streak end), set up at the end of the range by short probes that
+// stop at the end of the location.
 __device__ __forceinline__ uint64_t bits_above(int k) {   // bits k+1..63
   return k >= 63 ? 0ull : (~0ull << (k + 1));
 }
@@ -348,11 +408,12 @@ __device__ __forceinline__ bool run_single_same(uint64_t a, uint64_t b) {   // s
 }
 
 // First position q > a with a streak start (relative to q-1), or n.
-__device__ uint64_t probe_streak_end(const uint64_t* runs, uint64_t a, uint64_t n) {
+__device__ uint64_t probe_streak_end(const RecView& v, uint64_t a) {
+  const uint64_t n = v.n;
   for (uint64_t base = a + 1; base < n; base += 64) {
     const uint64_t q = base + __lane_id();
-    const uint64_t e = run_at(runs, q, n);
-    const uint64_t pr = q - 1 < n ? runs[q - 1] : RUN_SENTINEL;
+    const uint64_t e = entry_at(v, q);
+    const uint64_t pr = entry_at(v, q - 1);
     const bool x = q < n && (((e >> RUN_LOC) & 1) || !run_single_same(e, pr));
     const uint64_t xm = __ballot(x);
     if (xm) return base + low_bit(xm);
@@ -361,9 +422,10 @@ __device__ uint64_t probe_streak_end(const uint64_t* runs, uint64_t a, uint64_t 
 }
 
 // First write q > f with (M_q or id_q != id_f) before the location ends, or NOPOS.
-__device__ uint64_t probe_write_streak_end(const uint64_t* runs, uint64_t f, uint64_t ef, uint64_t n) {
+__device__ uint64_t probe_write_streak_end(const RecView& v, uint64_t f, uint64_t ef) {
+  const uint64_t n = v.n;
   for (uint64_t base = f + 1; base < n; base += 64) {
-    const uint64_t e = run_at(runs, base + __lane_id(), n);
+    const uint64_t e = entry_at(v, base + __lane_id());
     const uint64_t hm = __ballot(((e >> RUN_W) & 1) && !run_single_same(e, ef) &&
                                  !((e >> RUN_END) & 1));
     const uint64_t lm = __ballot((e >> RUN_LOC) & 1);
@@ -377,6 +439,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
                                                         const ConfSeg* __restrict__ segs, int nseg,
                                                         const uint32_t* __restrict__ total_at) {
   __shared__ uint64_t s_buf[CONF_WAVES][CONF_CHUNKS * 64];
+  __shared__ uint64_t s_wb[MAX_POINTS / 64];
   extern __shared__ uint32_t s_dyn[];        // [P] first partner
   const uint32_t total = *total_at;
   const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
@@ -403,32 +466,33 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
       }
       __syncthreads();
       cur = lo;
-      P = jobs[segs[cur].job].P;
+      const Job& J = jobs[segs[cur].job];
+      P = J.P;
       for (uint32_t i = tid; i < P; i += CONF_BLOCK) s_minj[i] = NONE32;
+      for (uint32_t q = tid; q < (P + 63) / 64; q += CONF_BLOCK) s_wb[q] = J.wbits[q];
       __syncthreads();
     }
     const ConfSeg& sg = segs[cur];
-    const uint64_t n = sg.n_runs_at ? *sg.n_runs_at : sg.n_runs;
+    const uint64_t n = sg.n;
     const uint64_t wbeg = (uint64_t)(tile - sg.ctile_beg) * CONF_TILE + (uint64_t)wv * (CONF_CHUNKS * 64);
     if (wbeg >= n) continue;
     const uint64_t wend = min(wbeg + (uint64_t)(CONF_CHUNKS * 64), n);
-    const uint64_t* __restrict__ runs = sg.runs;
-#pragma unroll
-    for (int k = 0; k < CONF_CHUNKS; k++) buf[k * 64 + lane] = run_at(runs, wbeg + k * 64 + lane, n);
+    const RecView V = rec_view(jobs[sg.job], sg, s_wb);
+    stage_entries<CONF_CHUNKS>(V, wbeg, buf);
     __builtin_amdgcn_wave_barrier();
     auto entry = [&](uint64_t q) -> uint64_t {
-      return (q >= wbeg && q < wend) ? buf[q - wbeg] : run_at(runs, q, n);
+      return (q >= wbeg && q < wend) ? buf[q - wbeg] : entry_at(V, q);
     };
     auto accepts = [&](uint64_t ea, uint64_t eb) -> bool {   // different threads (blocks)
       return !run_single_same(ea, eb);
     };
     // carries for the positions from the end of the range on
     uint64_t A = wend;                                   // next run
-    const uint64_t eA0 = run_at(runs, wend, n);
+    const uint64_t eA0 = entry_at(V, wend);
     bool XA = wend >= n || ((eA0 >> RUN_LOC) & 1) || !run_single_same(eA0, buf[wend - 1 - wbeg]);
-    uint64_t SEA = wend < n ? probe_streak_end(runs, wend, n) : n;   // its streak end
-    uint64_t FW = first_write_from(runs, wend, n);       // first write ahead
-    uint64_t NWS = FW != NOPOS ? probe_write_streak_end(runs, FW, runs[FW], n) : NOPOS;
+    uint64_t SEA = wend < n ? probe_streak_end(V, wend) : n;   // its streak end
+    uint64_t FW = first_write_from(V, wend);             // first write ahead
+    uint64_t NWS = FW != NOPOS ? probe_write_streak_end(V, FW, entry_at(V, FW)) : NOPOS;
     const int nch = (int)((wend - wbeg + 63) / 64);
     for (int c = nch - 1; c >= 0; c--) {
       const uint64_t p0 = wbeg + (uint64_t)c * 64;
@@ -438,7 +502,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
       const bool w = (e >> RUN_W) & 1, m = (e >> RUN_MULTI) & 1, ls = (e >> RUN_LOC) & 1;
       // predecessor (lane 0: the last run of the chunk before, or before the range)
       uint64_t pe = __shfl_up(e, 1);
-      if (lane == 0) pe = c > 0 ? buf[c * 64 - 1] : (wbeg > 0 ? runs[wbeg - 1] : RUN_SENTINEL);
+      if (lane == 0) pe = c > 0 ? buf[c * 64 - 1] : (wbeg > 0 ? entry_at(V, wbeg - 1) : RUN_SENTINEL);
       const bool x = ls || !run_single_same(e, pe) || p0 + lane == 0;
       const uint64_t Xm = __ballot(x);
       const uint64_t Lm = __ballot(ls);
@@ -466,7 +530,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
           if (f != NOPOS) best = (uint32_t)(entry(f) >> RUN_PT) & 0xFFFu;
         } else if (w) {
           const uint64_t q1 = p0 + lane + 1;
-          const uint64_t e1 = lane < 63 ? buf[c * 64 + lane + 1] : run_at(runs, q1, n);
+          const uint64_t e1 = lane < 63 ? buf[c * 64 + lane + 1] : entry_at(V, q1);
           if (q1 < n && !((e1 >> RUN_LOC) & 1)) {
             uint64_t q = q1;
             if (!accepts(e, e1)) {

@@ -130,27 +130,23 @@ struct GenItem {
   uint32_t seg, pad;
 };
 
-// one log of one job: its sorted records and its run log
+// one log of one job: its sorted records
 struct ConfSeg {
   const uint64_t* log;   // sorted access records
   uint64_t n;            // records
-  uint64_t* runs;        // run log: one entry per (location, point) group
-  uint64_t n_runs;       // written on the device by runs_scan_kernel
   uint32_t job, level;   // level 0 same-block view, 1 cross-block view
-  uint32_t btile_beg;    // first record tile (run-log build)
-  uint32_t ctile_beg;    // first run tile (conflict scan)
-  const uint64_t* n_runs_at;  // where the run count lives when this entry is a copy
+  uint32_t ctile_beg;    // first record tile of the scan (set on the device)
+  uint32_t pad;
 };
 
-// Run-log entry (64 bits): the records of one point at one location, in
-// location order and, inside a location, in program order.
-//   bits  0..31  id of the first record (thread in the same-block view,
-//                block in the cross-block view)
+// Scan entry (64 bits) of one record of a sorted log, in location order and,
+// inside a location, in program order:
+//   bits  0..31  id: the thread (same-block view) or the block (cross-block view)
 //   bits 32..43  point
 //   bit  44      the point writes
-//   bit  45      multi: the run holds two or more threads (same-block view)
-//                or two or more blocks (cross-block view)
-//   bit  46      first run of its location
+//   bit  45      multi: unused (always 0; kept so a run of several ids could
+//                be folded into one entry)
+//   bit  46      first record of its location
 //   bit  47      never set in an entry: marks the sentinel read past a log
 constexpr int RUN_PT = 32, RUN_W = 44, RUN_MULTI = 45, RUN_LOC = 46, RUN_END = 47;
 constexpr uint64_t RUN_SENTINEL = (1ull << RUN_LOC) | (1ull << RUN_END);

@@ -25,8 +25,6 @@ struct Layout {
   std::vector<size_t> o_pts, o_bany, o_bgrid, o_w, o_cpre, o_gpre, o_phi0j, o_wbits;
   size_t o_chunks = 0;
   size_t o_recA = 0, o_recB = 0, o_cnt = 0, o_tot = 0, o_off = 0, o_err = 0;
-  size_t o_rcnt = 0, o_roff = 0;
-  uint32_t n_btiles = 0;
   std::vector<size_t> o_ivl, o_minj, o_j0, o_phi, o_scratch, o_traj, o_bitmap, o_pairs, o_ptotal;
   std::vector<uint32_t> phi_cap, scratch_cap;
   uint64_t n_rec = 0;
@@ -51,8 +49,6 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   L.rb = (uint32_t)pick_digit_bits(key_bits);
   L.passes = (uint32_t)sort_passes(key_bits, (int)L.rb);
   uint64_t rec = 0;
-  uint32_t btiles = 0;
-  const uint32_t btile = runs_tile_size();
   for (size_t j = 0; j < N; j++) {
     const Plan& p = *jobs[j].plan;
     for (int v = 0; v < 2; v++) {
@@ -66,11 +62,9 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
       L.seg_job.push_back((uint32_t)j);
       L.seg_level.push_back((uint32_t)v);
       rec += n;
-      btiles += (uint32_t)((n + btile - 1) / btile);
     }
   }
   L.n_rec = rec;
-  L.n_btiles = btiles;
   // sort chunks (= generation items): whole sort tiles, at most ~64K chunks
   const uint64_t tile = sort_tile_size();
   uint64_t chunk = std::max<uint64_t>(2 * tile, (rec + 65535) / 65536);
@@ -121,8 +115,6 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   // ---- device-only region
   L.o_recA = off; off = up(off + L.n_rec * sizeof(uint64_t));
   L.o_recB = off; off = up(off + L.n_rec * sizeof(uint64_t));   // sort ping-pong, then run log
-  L.o_rcnt = off; off = up(off + (size_t)L.n_btiles * sizeof(uint32_t));
-  L.o_roff = off; off = up(off + (size_t)L.n_btiles * sizeof(uint64_t));
   L.o_cnt = off; off = up(off + L.chunks.size() * (size_t)R * sizeof(uint32_t));
   L.o_tot = off; off = up(off + L.ssegs.size() * (size_t)R * sizeof(uint64_t));
   L.o_off = off; off = up(off + L.chunks.size() * (size_t)R * sizeof(uint64_t));
@@ -249,28 +241,18 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
   std::memcpy(h.data() + L.o_items, L.items.data(), L.items.size() * sizeof(GenItem));
   std::memcpy(h.data() + L.o_chunks, L.chunks.data(), L.chunks.size() * sizeof(SortChunk));
   std::memcpy(h.data() + L.o_ssegs, L.ssegs.data(), L.ssegs.size() * sizeof(SortSeg));
-  // sorted logs end in buffer A after an even number of passes, else B; the
-  // run log goes to the other buffer
+  // sorted logs end in buffer A after an even number of passes, else B
   uint8_t* sorted = d + ((L.passes % 2 == 0) ? L.o_recA : L.o_recB);
-  uint8_t* runbuf = d + ((L.passes % 2 == 0) ? L.o_recB : L.o_recA);
   ConfSeg* hc = (ConfSeg*)(h.data() + L.o_csegs);
-  {
-    uint32_t bt = 0;
-    const uint32_t btile = runs_tile_size();
-    for (size_t q = 0; q < L.ssegs.size(); q++) {
-      ConfSeg c{};
-      c.log = (const uint64_t*)sorted + L.ssegs[q].beg;
-      c.n = L.ssegs[q].end - L.ssegs[q].beg;
-      c.runs = (uint64_t*)runbuf + L.ssegs[q].beg;
-      c.n_runs = 0;
-      c.job = L.seg_job[q];
-      c.level = L.seg_level[q];
-      c.btile_beg = bt;
-      c.ctile_beg = 0;     // laid out on the device each round
-      bt += (uint32_t)((c.n + btile - 1) / btile);
-      hc[q] = c;
-      hj[c.job].log[c.level] = c.log;
-    }
+  for (size_t q = 0; q < L.ssegs.size(); q++) {
+    ConfSeg c{};
+    c.log = (const uint64_t*)sorted + L.ssegs[q].beg;
+    c.n = L.ssegs[q].end - L.ssegs[q].beg;
+    c.job = L.seg_job[q];
+    c.level = L.seg_level[q];
+    c.ctile_beg = 0;     // laid out on the device before each scan
+    hc[q] = c;
+    hj[c.job].log[c.level] = c.log;
   }
   tm.mark(T_START);
   HIPCHK(hipMemcpyAsync(d, h.data(), L.meta, hipMemcpyHostToDevice, s));
@@ -303,11 +285,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     tm.mark(T_SORT);
   }
   tm.mark(T_SORT);
-  // ---- run logs (once per job)
   ConfSeg* dcs = (ConfSeg*)(d + L.o_csegs);
-  HIPCHK(launch_runs_build(djobs, dcs, (int)L.ssegs.size(), L.n_btiles,
-                           (uint32_t*)(d + L.o_rcnt), (uint64_t*)(d + L.o_roff), s));
-  tm.mark(T_RUNS);
   // ---- first partners with no barrier enabled (once per job): every
   // later Verify call resolves its first partners from them
   // (a job without access records keeps the cleared table: no partner)
@@ -526,10 +504,10 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
           }
           break;
         case T_UPLOAD: stats->ms_upload += ms; break;
-        case T_RUNS: stats->ms_runs += ms; break;
-        case T_SUMPRE: stats->ms_runs += ms; break;
+        case T_RUNS: stats->ms_j0 += ms; break;
+        case T_SUMPRE: stats->ms_j0 += ms; break;
         case T_SUMMARY:
-          stats->ms_runs += ms;
+          stats->ms_j0 += ms;
           stats->ms_conf_kernels += ms;
           break;
         case T_CONFPRE: stats->ms_check += ms; break;
@@ -546,11 +524,6 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     if (tm.ev.size() >= 2 && hipEventElapsedTime(&tot, tm.ev.front(), tm.ev.back()) == hipSuccess)
       stats->ms_total = tot;
     stats->records = L.n_rec;
-    if (!L.ssegs.empty()) {
-      std::vector<ConfSeg> cs(L.ssegs.size());
-      if (hipMemcpy(cs.data(), dcs, cs.size() * sizeof(ConfSeg), hipMemcpyDeviceToHost) == hipSuccess)
-        for (const ConfSeg& c : cs) stats->runs += c.n_runs;
-    }
     for (const JobInput& j : jobs) stats->accesses += j.plan->accesses;
     stats->records_scanned = scanned;
     stats->sort_passes = L.passes;

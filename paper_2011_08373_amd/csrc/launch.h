@@ -7,7 +7,6 @@ namespace rp {
 
 uint32_t sort_tile_size();
 uint32_t conf_tile_size();
-uint32_t runs_tile_size();
 
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,
                       const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int passes,
@@ -19,8 +18,6 @@ hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uin
 hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
                                const SortChunk* chunks, uint32_t nchunks, int pass,
                                const uint64_t* off, uint32_t* err, hipStream_t s);
-hipError_t launch_runs_build(const Job* jobs, ConfSeg* segs, int nseg, uint32_t n_btiles,
-                             uint32_t* cnt, uint64_t* off, hipStream_t s);
 constexpr int IVL_RESOLVE = 0, IVL_CHECK = 1, IVL_ZERO = 2;
 hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int mode, hipStream_t s);
 hipError_t launch_save_j0(const Job* jobs, uint32_t njobs, hipStream_t s);

@@ -50,13 +50,12 @@ class RpStats(C.Structure):
     _fields_ = [("ms_gen", C.c_double), ("ms_sort", C.c_double), ("ms_check", C.c_double),
                 ("ms_clause", C.c_double), ("ms_solve", C.c_double), ("ms_total", C.c_double),
                 ("ms_sort_pass_max", C.c_double), ("ms_sort_kernels", C.c_double),
-                ("ms_runs", C.c_double),
+                ("ms_j0", C.c_double),
                 ("records", C.c_uint64),
                 ("accesses", C.c_uint64), ("records_scanned", C.c_uint64),
                 ("sort_passes", C.c_uint32), ("sort_launches", C.c_uint32),
                 ("rounds", C.c_uint32), ("conf_launches", C.c_uint32),
-                ("ms_upload", C.c_double), ("ms_conf_kernels", C.c_double),
-                ("runs", C.c_uint64)]
+                ("ms_upload", C.c_double), ("ms_conf_kernels", C.c_double)]
 
 
 PAIR_DT = np.dtype([("i", "<u2"), ("j", "<u2"), ("level", "u1"), ("pad", "u1")])
