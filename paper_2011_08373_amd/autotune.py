@@ -14,7 +14,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
-CANDIDATES = [(rb, shape) for rb in (8, 9, 10, 11) for shape in (0, 1, 2, 3)]
+CANDIDATES = [(rb, shape) for rb in (8, 9, 10, 11) for shape in (0, 1, 2, 3, 4)]
 
 
 def _arch() -> str:
@@ -52,7 +52,7 @@ def apply(n_accesses: int) -> bool:
 def tune(kms, reps: int = 3, ws=None) -> dict:
     """Time every candidate on a batch (or one kernel) and cache the best."""
     from . import librepair as L
-    batch = isinstance(kms, (list, tuple))
+    batch = isinstance(kms, (list, tuple)) or isinstance(kms, L.BatchArg)
     results = []
     for rb, shape in CANDIDATES:
         L.set_tuning(L.TUNE_SORT_DIGIT_BITS, rb)

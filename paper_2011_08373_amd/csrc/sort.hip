@@ -10,8 +10,11 @@
 //                    digits: the first output slot of every (chunk, digit);
 //   scatter_kernel   per chunk, tiles of records are ranked stably with
 //                    64-lane ballots, staged in LDS in digit order and written
-//                    out as contiguous digit runs.
+//                    out as contiguous digit runs; a persistent grid sized to
+//                    the resident workgroups takes the chunks in turn.
 // No workgroup ever waits on another, so nothing here can stall the grid.
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 
@@ -29,12 +32,15 @@ __global__ void fill_u64_kernel(uint64_t* p, uint64_t n, uint64_t v) {
 template <int RB>
 __global__ __launch_bounds__(256) void count_kernel(const uint64_t* __restrict__ in,
                                                     const SortChunk* __restrict__ chunks,
+                                                    uint32_t nchunks,
                                                     const SortSeg* __restrict__ segs, int pass,
                                                     uint32_t* __restrict__ cnt) {
   constexpr uint32_t R = 1u << RB;
   __shared__ uint32_t hist[R];
-  const SortChunk ch = chunks[blockIdx.x];
+  for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {   // persistent
+  const SortChunk ch = chunks[ci];
   const int shift = (int)segs[ch.seg].shift + pass * RB;
+  __syncthreads();
   for (uint32_t d = threadIdx.x; d < R; d += 256) hist[d] = 0;
   __syncthreads();
   for (uint64_t r0 = ch.beg; r0 < ch.end; r0 += 256) {
@@ -54,8 +60,9 @@ __global__ __launch_bounds__(256) void count_kernel(const uint64_t* __restrict__
     }
   }
   __syncthreads();
-  uint32_t* row = cnt + (size_t)blockIdx.x * R;
+  uint32_t* row = cnt + (size_t)ci * R;
   for (uint32_t d = threadIdx.x; d < R; d += 256) row[d] = hist[d];
+  }
 }
 
 // Column totals: tot[seg][d] = sum over the segment's chunks of cnt[chunk][d].
@@ -123,6 +130,7 @@ template <int RB, int SC_BLOCK, int SC_IPT>
 __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __restrict__ in,
                                                            uint64_t* __restrict__ out,
                                                            const SortChunk* __restrict__ chunks,
+                                                           uint32_t nchunks,
                                                            const SortSeg* __restrict__ segs,
                                                            int pass,
                                                            const uint64_t* __restrict__ off,
@@ -135,15 +143,19 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
   __shared__ uint32_t lstart[R];               // tile-local digit starts
   __shared__ uint32_t tcount[R];
   __shared__ uint64_t grun[R];                 // next output slot per digit
+  __shared__ uint64_t gofs[R];                 // grun - lstart for the tile
   __shared__ uint32_t scan_sm[SC_WAVES];
 
-  const SortChunk ch = chunks[blockIdx.x];
-  const SortSeg sg = segs[ch.seg];
-  const int shift = (int)sg.shift + pass * RB;
   const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
-  for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] = off[(size_t)blockIdx.x * R + d];
   const uint64_t lt = lanemask_lt();
   const uint32_t wbase = (uint32_t)w * 64 * SC_IPT;
+  // persistent: workgroups take chunks in turn
+  for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
+  const SortChunk ch = chunks[ci];
+  const SortSeg sg = segs[ch.seg];
+  const int shift = (int)sg.shift + pass * RB;
+  __syncthreads();
+  for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] = off[(size_t)ci * R + d];
 
   for (uint64_t base = ch.beg; base < ch.end; base += SC_TILE) {
     const uint64_t rem = ch.end - base;
@@ -163,12 +175,17 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
     for (int k = 0; k < SC_IPT; k++) {
       const bool valid = (wbase + k * 64 + lane) < n_here;
       const uint32_t d = digit_at(key[k], shift, R - 1);
-      uint64_t peers = __ballot(valid);
+      const uint64_t act = __ballot(valid);
+      uint64_t peers = act;
+      // every active lane on one digit (long digit runs): no bit matching
+      const uint32_t d0 = __shfl(d, act ? __ffsll((unsigned long long)act) - 1 : 0);
+      if (__ballot(valid && d == d0) != act) {
 #pragma unroll
-      for (int b = 0; b < RB; b++) {
-        const bool bit = (d >> b) & 1;
-        const uint64_t bb = __ballot(bit);
-        peers &= bit ? bb : ~bb;
+        for (int b = 0; b < RB; b++) {
+          const bool bit = (d >> b) & 1;
+          const uint64_t bb = __ballot(bit);
+          peers &= bit ? bb : ~bb;
+        }
       }
       uint32_t before = 0;
       if (valid) before = whist[w][d];
@@ -209,7 +226,10 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
       uint32_t run = pre + inc - local;
       for (uint32_t q = 0; q < PER; q++) {
         const uint32_t d = tid * PER + q;
-        if (d < R) lstart[d] = run;
+        if (d < R) {
+          lstart[d] = run;
+          gofs[d] = grun[d] - run;
+        }
         run += c[q];
       }
     }
@@ -226,7 +246,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
     for (uint32_t p = tid; p < n_here; p += SC_BLOCK) {
       const uint64_t kv = sk[p];
       const uint32_t d = digit_at(kv, shift, R - 1);
-      const uint64_t dst = grun[d] + (p - lstart[d]);
+      const uint64_t dst = gofs[d] + p;
       // a destination outside the segment can only come from inconsistent
       // counts: report it instead of writing
       if (dst >= sg.beg && dst < sg.end) out[dst] = kv;
@@ -235,6 +255,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
     __syncthreads();
     for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] += tcount[d];
     __syncthreads();
+  }
   }
 }
 
@@ -263,18 +284,38 @@ hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uin
   if (nchunks == 0) return hipSuccess;
   const uint32_t R = 1u << rb;
   if (!counts_ready) {
-    RB_SWITCH(rb, (count_kernel<RBV><<<nchunks, 256, 0, s>>>(in, chunks, segs, pass, cnt)));
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const uint32_t grid = std::min<uint32_t>(nchunks, (uint32_t)ncu * 8);
+    RB_SWITCH(rb, (count_kernel<RBV><<<grid, 256, 0, s>>>(in, chunks, nchunks, segs, pass, cnt)));
   }
   RB_SWITCH(rb, (colsum_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot)));
   RB_SWITCH(rb, (colscan_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot, off)));
   return hipGetLastError();
 }
 
-static int g_scatter_variant = 0;
+static int g_scatter_variant = 4;   // 512 threads x 8 records: best measured default
 int scatter_variant(int v, bool set) {
   const int old = g_scatter_variant;
   if (set) g_scatter_variant = v;
   return old;
+}
+
+template <int RB, int BLOCK, int IPT>
+static void scatter_go(uint32_t nchunks, const uint64_t* in, uint64_t* out,
+                       const SortChunk* chunks, const SortSeg* segs, int pass,
+                       const uint64_t* off, uint32_t* err, hipStream_t s) {
+  int dev = 0, ncu = 256, per_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, scatter_kernel<RB, BLOCK, IPT>, BLOCK, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  uint32_t grid = (uint32_t)ncu * (uint32_t)per_cu;
+  if (grid > nchunks) grid = nchunks;
+  scatter_kernel<RB, BLOCK, IPT><<<grid, BLOCK, 0, s>>>(in, out, chunks, nchunks, segs, pass, off, err);
 }
 
 template <int RB>
@@ -282,17 +323,18 @@ static void scatter_launch(int variant, uint32_t nchunks, const uint64_t* in, ui
                            const SortChunk* chunks, const SortSeg* segs, int pass,
                            const uint64_t* off, uint32_t* err, hipStream_t s) {
   switch (variant) {
-    case 1: scatter_kernel<RB, 256, 16><<<nchunks, 256, 0, s>>>(in, out, chunks, segs, pass, off, err); break;
-    case 2: scatter_kernel<RB, 256, 32><<<nchunks, 256, 0, s>>>(in, out, chunks, segs, pass, off, err); break;
+    case 1: scatter_go<RB, 256, 16>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
+    case 2: scatter_go<RB, 256, 32>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
+    case 4: scatter_go<RB, 512, 8>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
     case 3:
       // 16 waves of per-digit counters do not fit LDS beside the tile for
       // wide digits
       if constexpr (RB <= 9) {
-        scatter_kernel<RB, 1024, 8><<<nchunks, 1024, 0, s>>>(in, out, chunks, segs, pass, off, err);
+        scatter_go<RB, 1024, 8>(nchunks, in, out, chunks, segs, pass, off, err, s);
         break;
       }
       [[fallthrough]];
-    default: scatter_kernel<RB, 512, 16><<<nchunks, 512, 0, s>>>(in, out, chunks, segs, pass, off, err); break;
+    default: scatter_go<RB, 512, 16>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
   }
 }
 
