@@ -240,8 +240,9 @@ int rp_set_sort_digit_bits(int bits);
 /* Tuning knobs (process-wide; return the previous value, -1 if rejected):
  *   RP_TUNE_SORT_DIGIT_BITS  0 = automatic, else 8..11;
  *   RP_TUNE_SCATTER_SHAPE    radix-scatter tile: 0 = 512x16, 1 = 256x16,
- *                            2 = 256x32, 3 = 1024x8, 4 = 512x8 (default)
- *                            (threads x records per thread). */
+ *                            2 = 256x32, 3 = 1024x8, 4 = 512x8 (default),
+ *                            5 = 1024x4, 6 = 256x8 (threads x records per
+ *                            thread). */
 enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1 };
 int rp_set_tuning(int knob, int value);
 

@@ -180,12 +180,17 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
       // every active lane on one digit (long digit runs): no bit matching
       const uint32_t d0 = __shfl(d, act ? __ffsll((unsigned long long)act) - 1 : 0);
       if (__ballot(valid && d == d0) != act) {
+        // lanes whose digit differs from this lane's in some bit: for each
+        // bit, its ballot XOR this lane's bit spread over 64 bits
+        uint32_t diff_lo = 0, diff_hi = 0;
 #pragma unroll
         for (int b = 0; b < RB; b++) {
-          const bool bit = (d >> b) & 1;
-          const uint64_t bb = __ballot(bit);
-          peers &= bit ? bb : ~bb;
+          const uint32_t rep = (uint32_t)(((int)(d << (31 - b))) >> 31);   // 0 or ~0
+          const uint64_t bb = __ballot(rep != 0);
+          diff_lo |= (uint32_t)bb ^ rep;
+          diff_hi |= (uint32_t)(bb >> 32) ^ rep;
         }
+        peers &= ~(((uint64_t)diff_hi << 32) | diff_lo);
       }
       uint32_t before = 0;
       if (valid) before = whist[w][d];
@@ -326,6 +331,8 @@ static void scatter_launch(int variant, uint32_t nchunks, const uint64_t* in, ui
     case 1: scatter_go<RB, 256, 16>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
     case 2: scatter_go<RB, 256, 32>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
     case 4: scatter_go<RB, 512, 8>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
+    case 5: scatter_go<RB, 1024, 4>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
+    case 6: scatter_go<RB, 256, 8>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
     case 3:
       // 16 waves of per-digit counters do not fit LDS beside the tile for
       // wide digits
