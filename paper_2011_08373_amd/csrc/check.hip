@@ -446,6 +446,9 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
   const uint32_t t0 = blockIdx.x * per;
   const uint32_t t1 = min(t0 + per, total);
   const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
+  // lane masks: lanes below, above, above lane + 1, at or below
+  const uint64_t lt = bits_below(lane), gt = bits_above(lane), gt1 = bits_above(lane + 1);
+  const uint64_t le = bits_below(lane + 1);
   uint64_t* buf = s_buf[wv];
   int cur = -1;
   uint32_t* s_minj = s_dyn;
@@ -489,74 +492,75 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
     // carries for the positions from the end of the range on
     uint64_t A = wend;                                   // next run
     const uint64_t eA0 = entry_at(V, wend);
-    bool XA = wend >= n || ((eA0 >> RUN_LOC) & 1) || !run_single_same(eA0, buf[wend - 1 - wbeg]);
+    bool XA = wend >= n || ((eA0 >> RUN_LOC) & 1) || (uint32_t)eA0 != (uint32_t)buf[wend - 1 - wbeg];
     uint64_t SEA = wend < n ? probe_streak_end(V, wend) : n;   // its streak end
     uint64_t FW = first_write_from(V, wend);             // first write ahead
     uint64_t NWS = FW != NOPOS ? probe_write_streak_end(V, FW, entry_at(V, FW)) : NOPOS;
     const int nch = (int)((wend - wbeg + 63) / 64);
+    const uint64_t first_pred = wbeg > 0 ? entry_at(V, wbeg - 1) : RUN_SENTINEL;
     for (int c = nch - 1; c >= 0; c--) {
       const uint64_t p0 = wbeg + (uint64_t)c * 64;
       const uint64_t e = buf[c * 64 + lane];
       const bool valid = !((e >> RUN_END) & 1);
       const uint32_t i = (uint32_t)(e >> RUN_PT) & 0xFFFu;
-      const bool w = (e >> RUN_W) & 1, m = (e >> RUN_MULTI) & 1, ls = (e >> RUN_LOC) & 1;
-      // predecessor (lane 0: the last run of the chunk before, or before the range)
+      const bool w = (e >> RUN_W) & 1, ls = (e >> RUN_LOC) & 1;
+      // predecessor (lane 0: the last record of the chunk before, or before the range)
       uint64_t pe = __shfl_up(e, 1);
-      if (lane == 0) pe = c > 0 ? buf[c * 64 - 1] : (wbeg > 0 ? entry_at(V, wbeg - 1) : RUN_SENTINEL);
-      const bool x = ls || !run_single_same(e, pe) || p0 + lane == 0;
+      if (lane == 0) pe = c > 0 ? buf[c * 64 - 1] : first_pred;
+      const bool x = ls || (uint32_t)e != (uint32_t)pe;
       const uint64_t Xm = __ballot(x);
       const uint64_t Lm = __ballot(ls);
       const uint64_t Wm = __ballot(w && valid);
       // write-streak starts among the writes of the chunk (relative to the
       // previous write of the chunk; only queried after an earlier write)
-      const uint64_t pwm = Wm & bits_below(lane);
+      const uint64_t pwm = Wm & lt;
       const int pw = pwm ? 63 - __clzll((long long)pwm) : 0;
       const uint64_t epw = __shfl(e, pw);
       const bool xw = w && valid && pwm &&
-                      ((Lm & bits_above(pw) & bits_below(lane + 1)) || !run_single_same(e, epw));
+                      ((Lm & bits_above(pw) & le) || (uint32_t)e != (uint32_t)epw);
       const uint64_t XWm = __ballot(xw);
       if (valid && i < P) {
-        uint32_t best = NONE32;
-        const uint64_t gt = bits_above(lane);
-        // first write after this run, in the chunk or carried
+        // first candidate: the next record (a write) or the first write
+        // after this record (a read); second, when the first has the same
+        // id: the end of that record's streak (a write) or write streak
+        // (a read)
         const uint64_t hw = Wm & gt, hl = Lm & gt;
-        uint64_t f = NOPOS;
         bool f_in = false;
-        if (hw && (!hl || low_bit(hw) < low_bit(hl))) { f = p0 + low_bit(hw); f_in = true; }
-        else if (!hl) f = FW;
-        if (w && m) {
-          best = i;
-        } else if (m) {
-          if (f != NOPOS) best = (uint32_t)(entry(f) >> RUN_PT) & 0xFFFu;
-        } else if (w) {
-          const uint64_t q1 = p0 + lane + 1;
-          const uint64_t e1 = lane < 63 ? buf[c * 64 + lane + 1] : entry_at(V, q1);
-          if (q1 < n && !((e1 >> RUN_LOC) & 1)) {
-            uint64_t q = q1;
-            if (!accepts(e, e1)) {
-              const uint64_t hx = lane < 63 ? (Xm & bits_above(lane + 1)) : 0ull;
-              q = hx ? p0 + low_bit(hx) : (lane < 63 && XA ? A : SEA);
-            }
-            if (q < n) {
-              const uint64_t eq = entry(q);
-              if (!((eq >> RUN_LOC) & 1)) best = (uint32_t)(eq >> RUN_PT) & 0xFFFu;
-            }
-          }
-        } else if (f != NOPOS) {
-          const uint64_t ef = entry(f);
-          uint64_t g = f;
-          if (!accepts(e, ef)) {
-            if (f_in) {
-              const int fl = (int)(f - p0);
-              const uint64_t hxw = XWm & bits_above(fl), hl2 = Lm & bits_above(fl);
-              if (hxw && (!hl2 || low_bit(hxw) < low_bit(hl2))) g = p0 + low_bit(hxw);
-              else if (hl2) g = NOPOS;
-              else g = (FW != NOPOS && accepts(ef, entry(FW))) ? FW : NWS;
+        uint64_t c1;
+        if (w) {
+          c1 = p0 + lane + 1;
+        } else if (hw && (!hl || low_bit(hw) < low_bit(hl))) {
+          c1 = p0 + low_bit(hw);
+          f_in = true;
+        } else {
+          c1 = hl ? NOPOS : FW;
+        }
+        uint32_t best = NONE32;
+        if (c1 < n) {
+          const uint64_t e1 = entry(c1);
+          if (!((e1 >> RUN_LOC) & 1)) {
+            if ((uint32_t)e1 != (uint32_t)e) {
+              best = (uint32_t)(e1 >> RUN_PT) & 0xFFFu;
             } else {
-              g = NWS;
+              uint64_t c2;
+              if (w) {
+                const uint64_t hx = Xm & gt1;     // streak starts after lane + 1
+                c2 = hx ? p0 + low_bit(hx) : (lane < 63 && XA ? A : SEA);
+              } else if (f_in) {
+                const int fl = (int)(c1 - p0);
+                const uint64_t hxw = XWm & bits_above(fl), hl2 = Lm & bits_above(fl);
+                if (hxw && (!hl2 || low_bit(hxw) < low_bit(hl2))) c2 = p0 + low_bit(hxw);
+                else if (hl2) c2 = NOPOS;
+                else c2 = (FW != NOPOS && (uint32_t)entry(FW) != (uint32_t)e1) ? FW : NWS;
+              } else {
+                c2 = NWS;
+              }
+              if (c2 < n) {
+                const uint64_t e2 = entry(c2);
+                if (!((e2 >> RUN_LOC) & 1)) best = (uint32_t)(e2 >> RUN_PT) & 0xFFFu;
+              }
             }
           }
-          if (g != NOPOS) best = (uint32_t)(entry(g) >> RUN_PT) & 0xFFFu;
         }
         if (best < P && s_minj[i] > best) atomicMin(&s_minj[i], best);
       }

@@ -61,6 +61,7 @@ __device__ __forceinline__ uint32_t block_excl_scan1024(uint32_t v, uint32_t* sm
 }
 
 constexpr uint32_t CL_LDS = 2048;   // clauses merged in LDS; more go through the job's scratch
+constexpr uint32_t CL_BITS = 1024;  // points whose slot bits are staged in LDS
 
 // learn: 0 = only decide SAFE (the check call), 1 = learn and reduce.
 __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict__ jobs, int learn) {
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
   __shared__ uint32_t sm[CL_BLOCK / 64];
   __shared__ uint32_t keep[4096];   // bitset over up to 131072 clauses
   __shared__ rp_clause s_cl[CL_LDS];
+  __shared__ uint64_t s_bits[2][CL_BITS];   // barrier slot bits of each point (P <= CL_BITS)
   const Job& J = jobs[blockIdx.x];
   JobState* st = J.st;
   if (st->state != ST_RUN) return;
@@ -99,6 +101,16 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
     return;
   }
   if (!learn) return;
+  // the slot bits between i and its partner are ORed point by point: from
+  // LDS when the tables fit
+  const bool lds_bits = P <= CL_BITS;
+  if (lds_bits) {
+    for (uint32_t u = tid; u < P; u += CL_BLOCK) {
+      s_bits[0][u] = J.bits_any[u];
+      s_bits[1][u] = J.bits_grid[u];
+    }
+    __syncthreads();
+  }
   // phi first, then the learned clauses: in LDS when they surely fit, else
   // in the job's scratch
   const uint32_t n_phi = st->n_phi;
@@ -115,7 +127,7 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
       } else {
         const uint32_t row = s_first;   // smallest (level, i)
         const uint32_t lv = row / P, i = row % P, j = J.minj[row];
-        const uint64_t* bits = lv ? J.bits_grid : J.bits_any;
+        const uint64_t* bits = lds_bits ? s_bits[lv] : (lv ? J.bits_grid : J.bits_any);
         uint64_t pos = 0;
         for (uint32_t u = i + 1; u < j; u++) pos |= bits[u];
         c.pos = pos;
@@ -129,7 +141,7 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
       const uint32_t j = J.minj[row];
       if (j == NONE32) continue;
       const uint32_t lv = row / P, i = row % P;
-      const uint64_t* bits = lv ? J.bits_grid : J.bits_any;
+      const uint64_t* bits = lds_bits ? s_bits[lv] : (lv ? J.bits_grid : J.bits_any);
       uint64_t pos = 0;
       for (uint32_t u = i + 1; u < j; u++) pos |= bits[u];
       const uint32_t slot = atomicAdd(&s_n, 1u);

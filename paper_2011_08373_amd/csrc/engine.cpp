@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "common.h"
@@ -145,22 +146,46 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   L.total = off;
 }
 
+// Phase timing with hipEvents from a per-thread, per-device pool: creating
+// events costs host time on every call, so they are made once and reused.
+// A timer takes the pool entries above the ones held by timers still alive
+// on the thread, and hands them back when it ends (after the call has
+// synchronised its stream).
+struct EventPool {
+  std::map<int, std::vector<hipEvent_t>> ev;   // by device
+  std::map<int, size_t> top;
+};
+static thread_local EventPool t_pool;
+
 struct Timer {
   std::vector<hipEvent_t> ev;
   std::vector<int> tag;
   hipStream_t s;
   bool ok = true;
   bool on = true;
-  explicit Timer(hipStream_t st, bool enabled = true) : s(st), on(enabled) {}
+  int dev = 0;
+  size_t base = 0;
+  explicit Timer(hipStream_t st, bool enabled = true) : s(st), on(enabled) {
+    if (on && hipGetDevice(&dev) != hipSuccess) on = false;
+    if (on) base = t_pool.top[dev];
+  }
   void mark(int t) {
     if (!on) return;
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) { ok = false; return; }
+    std::vector<hipEvent_t>& pool = t_pool.ev[dev];
+    size_t& top = t_pool.top[dev];
+    if (top == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { ok = false; return; }
+      pool.push_back(e);
+    }
+    hipEvent_t e = pool[top++];
     if (hipEventRecord(e, s) != hipSuccess) ok = false;
     ev.push_back(e);
     tag.push_back(t);
   }
-  ~Timer() { for (hipEvent_t e : ev) (void)hipEventDestroy(e); }
+  ~Timer() {
+    if (on) t_pool.top[dev] = base;
+  }
 };
 
 // phase tags for the stats
