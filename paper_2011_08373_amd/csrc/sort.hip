@@ -48,12 +48,12 @@ __global__ __launch_bounds__(256) void count_kernel(const uint64_t* __restrict__
     const bool valid = r < ch.end;
     const uint32_t d = valid ? digit_at(in[r], shift, R - 1) : 0u;
     const uint64_t act = __ballot(valid);
+    // valid lanes are a prefix of the wave: lane 0 holds the first digit
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    const uint64_t same = __ballot(valid && d == d0);
     if (valid) {
-      const int first = __ffsll((unsigned long long)act) - 1;
-      const uint32_t d0 = __shfl(d, first);
-      const uint64_t same = __ballot(d == d0);
       if (same == act) {
-        if ((int)__lane_id() == first) atomicAdd(&hist[d], (uint32_t)__popcll(act));
+        if (__lane_id() == 0) atomicAdd(&hist[d], (uint32_t)__popcll(act));
       } else {
         atomicAdd(&hist[d], 1u);
       }
@@ -177,8 +177,9 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
       const uint32_t d = digit_at(key[k], shift, R - 1);
       const uint64_t act = __ballot(valid);
       uint64_t peers = act;
-      // every active lane on one digit (long digit runs): no bit matching
-      const uint32_t d0 = __shfl(d, act ? __ffsll((unsigned long long)act) - 1 : 0);
+      // every active lane on one digit (long digit runs): no bit matching;
+      // the valid lanes are a prefix of the wave, so lane 0 holds the first
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
       if (__ballot(valid && d == d0) != act) {
         // lanes whose digit differs from this lane's in some bit: for each
         // bit, its ballot XOR this lane's bit spread over 64 bits
