@@ -7,7 +7,12 @@ points, 32 barrier slots (8 grid-level), two shared and two global arrays of
 1M int32 words.  The metric is race-checked accesses per second: every
 (point, block, thread) access is race-checked once per Verify call.
 
-Two more legs are reported beside the headline (same JSON line):
+More legs are reported beside the headline (same JSON line):
+  planted  the same kernel with a planted safe barrier set (several Verify
+           calls, ends SAFE);
+  stress   4,096 blocks x 1,024 threads, 1,024 points, eight 16M-word arrays
+           (about 2.9G records, a 23 GB log): throughput and kernel
+           rooflines far outside the last-level cache;
   batched  the 1,024-kernel batched workload (planted mode): repaired kernels
            per second of one rp_repair_batch call against the plain
            one-kernel-at-a-time rp_repair loop on the same kernels;
@@ -54,14 +59,15 @@ def cpu_baseline(km, rounds_gpu):
 def run_main(L, torch, km, steps, warmup):
     """Times `steps` full rp_repair calls on one kernel (inputs resident)."""
     ws = L.Workspace()
-    ws.get(L.workspace_bytes(km, L.OP_REPAIR))
+    ka = L.KernelArg(km)          # the C view of the descriptors, built once
+    ws.get(L.workspace_bytes(ka, L.OP_REPAIR))
     for _ in range(warmup):
-        L.repair(km, ws=ws)
+        L.repair(ka, ws=ws)
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        r = L.repair(km, ws=ws)
+        r = L.repair(ka, ws=ws)
         stats.append(L.last_stats())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -90,9 +96,10 @@ def _traffic(kernel):
     return e["bytes_per_launch"]
 
 
-def kernel_rooflines(stats):
+def kernel_rooflines(stats, traffic_prefix=""):
     """Algorithmic bytes per launch / average hipEvent launch time, for the
-    kernels timed one by one on the library's stream."""
+    kernels timed one by one on the library's stream.  Counter traffic is
+    looked up under traffic_prefix + kernel name (it depends on the workload)."""
     n = len(stats)
     last = stats[-1]
     rec = last["records"]
@@ -104,7 +111,7 @@ def kernel_rooflines(stats):
         avg = total_ms / launches
         gbs = bytes_per_launch / (avg / 1e3) / 1e9
         out[name] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic(name),
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic(traffic_prefix + name),
                      "avg_launch_ms": avg, "bytes_per_launch": bytes_per_launch,
                      "ms_per_step": total_ms / n}
     # radix scatter pass: reads and writes 8 B per record
@@ -115,6 +122,29 @@ def kernel_rooflines(stats):
           sum(s["conf_launches"] for s in stats))
     # record generation: writes 8 B per record
     entry("gen_kernel", 8 * rec, sum(s["ms_gen"] for s in stats), n)
+    return out
+
+
+def stress_leg(L, torch, steps):
+    """The stress kernel (4,096 blocks x 1,024 threads, 1,024 points, eight
+    16M-word arrays): a log of about 23 GB, far beyond the 256 MB last-level
+    cache, so the kernel rooflines here are HBM figures."""
+    from paper_2011_08373_amd import synth
+    out = {}
+    for mode in ("literal", "planted"):
+        km = synth.generate("stress", mode=mode)
+        r, ms, stats = run_main(L, torch, km, steps, 1)
+        acc = stats[-1]["accesses"]
+        out[mode] = {"value": acc * r["rounds"] / (ms / 1e3), "unit": "accesses/s",
+                     "ms_per_step": ms, "accesses": acc, "records": stats[-1]["records"],
+                     "verify_calls": r["rounds"], "repair_status": r["status"],
+                     "kernels": kernel_rooflines(stats, "stress/"),
+                     "phases_ms": {k: sum(s[k] for s in stats) / len(stats)
+                                   for k in ("ms_gen", "ms_sort", "ms_j0", "ms_check",
+                                             "ms_clause", "ms_solve", "ms_total")}}
+        torch.cuda.empty_cache()
+    out["workload"] = ("stress: 4096 blocks x 1024 threads, 1024 points (half accesses), "
+                       "64 slots (16 grid), 4 shared + 4 global arrays of 16M words, seed 5")
     return out
 
 
@@ -207,7 +237,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="literal", choices=("literal", "planted"))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--legs", default="main,planted,batched,served")
+    ap.add_argument("--legs", default="main,planted,stress,batched,served")
+    ap.add_argument("--stress-steps", type=int, default=3)
     ap.add_argument("--batched-n", type=int, default=1024)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -287,6 +318,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(km, r["rounds"])
     legs = set(args.legs.split(","))
     torch.cuda.empty_cache()
+    if "stress" in legs:
+        out["stress"] = stress_leg(L, torch, args.stress_steps)
     if "batched" in legs or "served" in legs:
         kms = synth.generate_batch(n=args.batched_n, mode="planted")
         if "batched" in legs:

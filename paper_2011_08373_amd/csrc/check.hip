@@ -184,10 +184,13 @@ __device__ __forceinline__ uint64_t make_entry(const RecView& v, uint64_t rec, u
                                                uint64_t q) {
   if (q >= v.n) return RUN_SENTINEL;
   const uint32_t i = (uint32_t)shr(rec, v.psh) & v.pmask;
-  const uint64_t id = shr(rec, v.ish) & v.imask;
-  const uint64_t w = (v.wb[i >> 6] >> (i & 63)) & 1;
-  const uint64_t loc = q == 0 || shr(rec, v.lsh) != shr(prev, v.lsh);
-  return id | ((uint64_t)i << RUN_PT) | (w << RUN_W) | (loc << RUN_LOC);
+  const uint32_t id = (uint32_t)(shr(rec, v.ish) & v.imask);
+  const uint32_t pid = (uint32_t)(shr(prev, v.ish) & v.imask);
+  const uint32_t w = (reinterpret_cast<const uint32_t*>(v.wb)[i >> 5] >> (i & 31)) & 1u;
+  const uint32_t loc = q == 0 || shr(rec, v.lsh) != shr(prev, v.lsh);
+  const uint32_t x = loc | (id != pid);
+  const uint32_t hi = i | (w << (RUN_W - 32)) | (x << (RUN_X - 32)) | (loc << (RUN_LOC - 32));
+  return (uint64_t)id | ((uint64_t)hi << 32);
 }
 
 __device__ __forceinline__ uint64_t entry_at(const RecView& v, uint64_t q) {
@@ -195,15 +198,21 @@ __device__ __forceinline__ uint64_t entry_at(const RecView& v, uint64_t q) {
   return make_entry(v, v.log[q], q > 0 ? v.log[q - 1] : 0, q);
 }
 
-// Stages records [b, b + 64*K) of a log as entries (all loads first).
+// Stages records [b, b + 64*K) of a log as entries (all loads first); lane 0
+// returns the raw record before b (0 when b == 0).
 template <int K>
-__device__ __forceinline__ void stage_entries(const RecView& v, uint64_t b, uint64_t* buf) {
+__device__ __forceinline__ uint64_t stage_entries(const RecView& v, uint64_t b, uint64_t* buf) {
   const int lane = __lane_id();
   uint64_t r[K], p0;
+  if (b + 64 * K <= v.n) {        // the whole span inside the log: no per-load test
 #pragma unroll
-  for (int k = 0; k < K; k++) {
-    const uint64_t q = b + k * 64 + lane;
-    r[k] = q < v.n ? v.log[q] : 0;
+    for (int k = 0; k < K; k++) r[k] = v.log[b + k * 64 + lane];
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const uint64_t q = b + k * 64 + lane;
+      r[k] = q < v.n ? v.log[q] : 0;
+    }
   }
   p0 = (lane == 0 && b > 0 && b - 1 < v.n) ? v.log[b - 1] : 0;
 #pragma unroll
@@ -213,6 +222,7 @@ __device__ __forceinline__ void stage_entries(const RecView& v, uint64_t b, uint
     if (lane == 0) pr = last;
     buf[k * 64 + lane] = make_entry(v, r[k], pr, b + k * 64 + lane);
   }
+  return p0;
 }
 
 constexpr uint64_t NOPOS = ~0ull;
@@ -311,19 +321,14 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
       const uint32_t i = (uint32_t)(e >> RUN_PT) & 0xFFFu;
       const uint32_t iv = (valid && i < P) ? s_iv[i] : NONE32;
       const uint32_t prev = __shfl_up(iv, 1);
-      const bool w = (e >> RUN_W) & 1, m = (e >> RUN_MULTI) & 1, ls = (e >> RUN_LOC) & 1;
+      const bool w = (e >> RUN_W) & 1, ls = (e >> RUN_LOC) & 1;
       const uint64_t Bm = __ballot(ls || iv != prev);     // sub-segment starts (bit 0 unused)
       const uint64_t Lm = __ballot(ls);
       const uint64_t Wm = __ballot(w);
-      const uint64_t Mm = __ballot(m);
       if (valid && i < P) {
         const uint32_t id = (uint32_t)e;
         uint32_t best = NONE32;
-        if (w && m) {          // two threads (blocks) of one point on one word, one writes
-          if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, i);
-          else best = i;
-        }
-        if (ALL || best == NONE32) {
+        {
           const uint64_t sC = Bm & gt;
           uint64_t cand = sC ? gt & ((sC & (~sC + 1)) - 1) : gt;
           if (!w) cand &= Wm;
@@ -332,7 +337,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
             cand &= cand - 1;
             const uint64_t ej = buf[c * 64 + jj];
             const uint32_t j = (uint32_t)(ej >> RUN_PT) & 0xFFFu;
-            if (j < P && (m || ((Mm >> jj) & 1) || id != (uint32_t)ej)) {
+            if (j < P && id != (uint32_t)ej) {
               if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, j);
               else { best = j; break; }
             }
@@ -348,7 +353,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
               const uint32_t j = (uint32_t)(ej >> RUN_PT) & 0xFFFu;
               if (j >= P || s_iv[j] != iv) break;        // next interval
               const bool wj = (ej >> RUN_W) & 1;
-              if ((w || wj) && (m || ((ej >> RUN_MULTI) & 1) || id != (uint32_t)ej)) {
+              if ((w || wj) && id != (uint32_t)ej) {
                 if (ALL) set_pair(J.bitmap, J.wpr, P, level, i, j);
                 else { best = j; break; }
               }
@@ -382,78 +387,113 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
 // With every barrier off a location is one sub-segment, and the first
 // partner of record r is the first later record q of its location with
 // (W_r or W_q) and id_r != id_q.  Call a "streak" a maximal stretch of records
-// of one id (a new location or a new id starts one) and, among the writes of
-// a location, a "write streak" likewise.  Then the first partner of
+// of one id (a new location or a new id starts one; the entry's X bit) and,
+// among the writes of a location, a "write streak" likewise.  Then the first
+// partner of
 //   - a write is the next record, or if that has the same id, the end of its
 //     streak;
 //   - a read is the first write f after it, or if f has the same id, the end
 //     of f's write streak.
 // (A point racing with itself needs no case of its own: its next record with
-// another id is that partner.)  Each wave stages 1024 records in LDS and walks
-// them in chunks of 64 from the last to the first; inside a chunk the
-// candidates come from ballot masks, past it from four wave-wide carries (the
-// next record, its streak end, the first write ahead and that write's
-// write-streak end), set up at the end of the range by short probes that
-// stop at the end of the location.
-__device__ __forceinline__ uint64_t bits_above(int k) {   // bits k+1..63
+// another id is that partner.)  Each wave stages 512 records in LDS, plus the
+// 64 after them, and walks them in chunks of 64 from the last to the first.
+// Inside a chunk both candidates come from ballot masks; past it from
+// wave-wide carries that hold partner points directly: the first streak start
+// at or after the chunk end and the first one after that, the first write
+// ahead in the location (its id and point) and its write-streak end.  The
+// carries are set up at the end of the range by short walks that start in the
+// staged lookahead chunk and stop at the end of the location.
+
+__device__ __forceinline__ uint32_t low_bit64(uint64_t m) {   // 64 if m == 0
+  return m ? (uint32_t)__builtin_ctzll(m) : 64u;
+}
+__device__ __forceinline__ uint64_t above(uint32_t k) {       // bits k+1..63 (none for k >= 63)
   return k >= 63 ? 0ull : (~0ull << (k + 1));
 }
-__device__ __forceinline__ uint64_t bits_below(int k) {   // bits 0..k-1
-  return k <= 0 ? 0ull : (k >= 64 ? ~0ull : ((1ull << k) - 1));
-}
-__device__ __forceinline__ int low_bit(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
-
-__device__ __forceinline__ bool run_single_same(uint64_t a, uint64_t b) {   // same single id
-  return !((a >> RUN_MULTI) & 1) && !((b >> RUN_MULTI) & 1) && (uint32_t)a == (uint32_t)b;
+// Partner point an entry stands for, NONE32 when it starts another location
+// (sentinels included).
+__device__ __forceinline__ uint32_t partner_of(uint64_t e) {
+  const uint32_t hi = (uint32_t)(e >> 32);
+  return (hi >> (RUN_LOC - 32)) & 1 ? NONE32 : (hi & 0xFFFu);
 }
 
-// First position q > a with a streak start (relative to q-1), or n.
-__device__ uint64_t probe_streak_end(const RecView& v, uint64_t a) {
-  const uint64_t n = v.n;
-  for (uint64_t base = a + 1; base < n; base += 64) {
+// The walks below visit 64-record chunks aligned to the staged range, so the
+// first chunk past the range is the staged lookahead; E(q) is the entry at q.
+// Lanes before the start position take no part in the answer.  Sentinel
+// entries (q >= n) start a streak and a location, so every walk ends at n.
+
+// First streak start at or after q0 (n if none before the end).
+template <class F>
+__device__ uint64_t walk_streak_start(F&& E, uint64_t org, uint64_t q0, uint64_t n) {
+  if (q0 >= n) return n;
+  for (uint64_t base = org + ((q0 - org) & ~63ull); base < n; base += 64) {
     const uint64_t q = base + __lane_id();
-    const uint64_t e = entry_at(v, q);
-    const uint64_t pr = entry_at(v, q - 1);
-    const bool x = q < n && (((e >> RUN_LOC) & 1) || !run_single_same(e, pr));
-    const uint64_t xm = __ballot(x);
-    if (xm) return base + low_bit(xm);
+    const uint64_t xm = __ballot(q >= q0 && ((E(q) >> RUN_X) & 1));
+    if (xm) return base + low_bit64(xm);
   }
   return n;
 }
 
-// First write q > f with (M_q or id_q != id_f) before the location ends, or NOPOS.
-__device__ uint64_t probe_write_streak_end(const RecView& v, uint64_t f, uint64_t ef) {
-  const uint64_t n = v.n;
-  for (uint64_t base = f + 1; base < n; base += 64) {
-    const uint64_t e = entry_at(v, base + __lane_id());
-    const uint64_t hm = __ballot(((e >> RUN_W) & 1) && !run_single_same(e, ef) &&
-                                 !((e >> RUN_END) & 1));
-    const uint64_t lm = __ballot((e >> RUN_LOC) & 1);
-    if (hm && (!lm || low_bit(hm) < low_bit(lm))) return base + low_bit(hm);
+// First write at or after q0 before the next location starts, or NOPOS.
+template <class F>
+__device__ uint64_t walk_first_write(F&& E, uint64_t org, uint64_t q0, uint64_t n) {
+  if (q0 >= n) return NOPOS;
+  for (uint64_t base = org + ((q0 - org) & ~63ull); base < n; base += 64) {
+    const uint64_t q = base + __lane_id();
+    const uint64_t e = E(q);
+    const uint64_t wm = __ballot(q >= q0 && ((e >> RUN_W) & 1));
+    const uint64_t lm = __ballot(q >= q0 && ((e >> RUN_LOC) & 1));
+    if (wm && (!lm || low_bit64(wm) < low_bit64(lm))) return base + low_bit64(wm);
     if (lm) return NOPOS;
   }
   return NOPOS;
 }
 
+// First write q > f whose id differs from f's (id_f) before the location
+// ends, or NOPOS.
+template <class F>
+__device__ uint64_t walk_write_streak_end(F&& E, uint64_t org, uint64_t f, uint32_t id_f,
+                                          uint64_t n) {
+  for (uint64_t base = org + ((f + 1 - org) & ~63ull); base < n; base += 64) {
+    const uint64_t q = base + __lane_id();
+    const uint64_t e = E(q);
+    const uint64_t hm = __ballot(q > f && ((e >> RUN_W) & 1) && (uint32_t)e != id_f);
+    const uint64_t lm = __ballot(q > f && ((e >> RUN_LOC) & 1));
+    if (hm && (!lm || low_bit64(hm) < low_bit64(lm))) return base + low_bit64(hm);
+    if (lm) return NOPOS;
+  }
+  return NOPOS;
+}
+
+// A wave scans its 1024 records of a tile as ranges of J0_CHUNKS chunks: the
+// smaller LDS stage lets more waves share a compute unit, which hides the
+// LDS latency of the dependent lookups.
+constexpr int J0_CHUNKS = 8;
+constexpr uint32_t J0_SPAN = (J0_CHUNKS + 1) * 64;     // staged range + one lookahead chunk
+static_assert(CONF_CHUNKS % J0_CHUNKS == 0, "ranges tile a wave's part of a tile");
+
 __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ jobs,
                                                         const ConfSeg* __restrict__ segs, int nseg,
                                                         const uint32_t* __restrict__ total_at) {
-  __shared__ uint64_t s_buf[CONF_WAVES][CONF_CHUNKS * 64];
+  __shared__ uint64_t s_buf[CONF_WAVES][J0_SPAN];
   __shared__ uint64_t s_wb[MAX_POINTS / 64];
   extern __shared__ uint32_t s_dyn[];        // [P] first partner
   const uint32_t total = *total_at;
   const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
   const uint32_t t0 = blockIdx.x * per;
   const uint32_t t1 = min(t0 + per, total);
-  const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
-  // lane masks: lanes below, above, above lane + 1, at or below
-  const uint64_t lt = bits_below(lane), gt = bits_above(lane), gt1 = bits_above(lane + 1);
-  const uint64_t le = bits_below(lane + 1);
+  // the wave index is uniform across the wave: say so, so that the range
+  // bounds and the chunk loop stay scalar
+  const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t lane = __lane_id();
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));   // lanes below
+  const uint64_t gt = above(lane);                                  // lanes above
   uint64_t* buf = s_buf[wv];
+  const uint32_t* buf_lo = reinterpret_cast<const uint32_t*>(buf);  // ids (low words)
   int cur = -1;
   uint32_t* s_minj = s_dyn;
   uint32_t P = 0;
-  for (uint32_t tile = t0; tile < t1; tile++) {
+  for (uint32_t tile = t0; tile < t1;) {
     int lo = 0, hi = nseg - 1;   // largest segment with ctile_beg <= tile
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -477,118 +517,122 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
     }
     const ConfSeg& sg = segs[cur];
     const uint64_t n = sg.n;
-    const uint64_t wbeg = (uint64_t)(tile - sg.ctile_beg) * CONF_TILE + (uint64_t)wv * (CONF_CHUNKS * 64);
-    if (wbeg >= n) continue;
-    const uint64_t wend = min(wbeg + (uint64_t)(CONF_CHUNKS * 64), n);
     const RecView V = rec_view(jobs[sg.job], sg, s_wb);
-    stage_entries<CONF_CHUNKS>(V, wbeg, buf);
-    __builtin_amdgcn_wave_barrier();
-    auto entry = [&](uint64_t q) -> uint64_t {
-      return (q >= wbeg && q < wend) ? buf[q - wbeg] : entry_at(V, q);
-    };
-    auto accepts = [&](uint64_t ea, uint64_t eb) -> bool {   // different threads (blocks)
-      return !run_single_same(ea, eb);
-    };
-    // carries for the positions from the end of the range on
-    uint64_t A = wend;                                   // next run
-    const uint64_t eA0 = entry_at(V, wend);
-    bool XA = wend >= n || ((eA0 >> RUN_LOC) & 1) || (uint32_t)eA0 != (uint32_t)buf[wend - 1 - wbeg];
-    uint64_t SEA = wend < n ? probe_streak_end(V, wend) : n;   // its streak end
-    uint64_t FW = first_write_from(V, wend);             // first write ahead
-    uint64_t NWS = FW != NOPOS ? probe_write_streak_end(V, FW, entry_at(V, FW)) : NOPOS;
-    const int nch = (int)((wend - wbeg + 63) / 64);
-    const uint64_t first_pred = wbeg > 0 ? entry_at(V, wbeg - 1) : RUN_SENTINEL;
-    for (int c = nch - 1; c >= 0; c--) {
-      const uint64_t p0 = wbeg + (uint64_t)c * 64;
-      const uint64_t e = buf[c * 64 + lane];
-      const bool valid = !((e >> RUN_END) & 1);
-      const uint32_t i = (uint32_t)(e >> RUN_PT) & 0xFFFu;
-      const bool w = (e >> RUN_W) & 1, ls = (e >> RUN_LOC) & 1;
-      // predecessor (lane 0: the last record of the chunk before, or before the range)
-      uint64_t pe = __shfl_up(e, 1);
-      if (lane == 0) pe = c > 0 ? buf[c * 64 - 1] : first_pred;
-      const bool x = ls || (uint32_t)e != (uint32_t)pe;
-      const uint64_t Xm = __ballot(x);
-      const uint64_t Lm = __ballot(ls);
-      const uint64_t Wm = __ballot(w && valid);
-      // write-streak starts among the writes of the chunk (relative to the
-      // previous write of the chunk; only queried after an earlier write)
-      const uint64_t pwm = Wm & lt;
-      const int pw = pwm ? 63 - __clzll((long long)pwm) : 0;
-      const uint64_t epw = __shfl(e, pw);
-      const bool xw = w && valid && pwm &&
-                      ((Lm & bits_above(pw) & le) || (uint32_t)e != (uint32_t)epw);
-      const uint64_t XWm = __ballot(xw);
-      if (valid && i < P) {
-        // first candidate: the next record (a write) or the first write
-        // after this record (a read); second, when the first has the same
-        // id: the end of that record's streak (a write) or write streak
-        // (a read)
-        const uint64_t hw = Wm & gt, hl = Lm & gt;
-        bool f_in = false;
-        uint64_t c1;
-        if (w) {
-          c1 = p0 + lane + 1;
-        } else if (hw && (!hl || low_bit(hw) < low_bit(hl))) {
-          c1 = p0 + low_bit(hw);
-          f_in = true;
-        } else {
-          c1 = hl ? NOPOS : FW;
-        }
-        uint32_t best = NONE32;
-        if (c1 < n) {
-          const uint64_t e1 = entry(c1);
-          if (!((e1 >> RUN_LOC) & 1)) {
-            if ((uint32_t)e1 != (uint32_t)e) {
-              best = (uint32_t)(e1 >> RUN_PT) & 0xFFFu;
-            } else {
-              uint64_t c2;
-              if (w) {
-                const uint64_t hx = Xm & gt1;     // streak starts after lane + 1
-                c2 = hx ? p0 + low_bit(hx) : (lane < 63 && XA ? A : SEA);
-              } else if (f_in) {
-                const int fl = (int)(c1 - p0);
-                const uint64_t hxw = XWm & bits_above(fl), hl2 = Lm & bits_above(fl);
-                if (hxw && (!hl2 || low_bit(hxw) < low_bit(hl2))) c2 = p0 + low_bit(hxw);
-                else if (hl2) c2 = NOPOS;
-                else c2 = (FW != NOPOS && (uint32_t)entry(FW) != (uint32_t)e1) ? FW : NWS;
-              } else {
-                c2 = NWS;
-              }
-              if (c2 < n) {
-                const uint64_t e2 = entry(c2);
-                if (!((e2 >> RUN_LOC) & 1)) best = (uint32_t)(e2 >> RUN_PT) & 0xFFFu;
-              }
-            }
+    // this workgroup's tiles of the segment, as one record span cut into one
+    // contiguous part per wave (whole chunks)
+    const uint32_t tend = cur + 1 < nseg ? min(t1, segs[cur + 1].ctile_beg) : t1;
+    const uint64_t rbeg = (uint64_t)(tile - sg.ctile_beg) * CONF_TILE;
+    const uint64_t rend = min((uint64_t)(tend - sg.ctile_beg) * CONF_TILE, n);
+    tile = tend;
+    const uint64_t part = (rend - rbeg + CONF_WAVES * 64 - 1) / (CONF_WAVES * 64) * 64;
+    const uint64_t s0 = min(rbeg + (uint64_t)wv * part, rend);
+    const uint64_t s1 = min(s0 + part, rend);
+    if (s0 >= s1) continue;
+    // the part is scanned backward in ranges of J0_CHUNKS chunks; the carries
+    // at the end of a range are those left at the start of the range after it
+    const int nr = (int)((s1 - s0 + J0_CHUNKS * 64 - 1) / (J0_CHUNKS * 64));
+    uint32_t pnx0 = NONE32, pnx1 = NONE32, pfw = NONE32, pnws = NONE32, fw_id = 0;
+    uint64_t e_next = RUN_SENTINEL;     // first entry of the range after the current one
+    for (int r = nr - 1; r >= 0; r--) {
+      const uint64_t wbeg = s0 + (uint64_t)r * (J0_CHUNKS * 64);
+      const uint64_t wend = min(wbeg + (uint64_t)(J0_CHUNKS * 64), s1);
+      if (r == nr - 1) {
+        // the part's last range and the chunk after it (the walks' first
+        // step) in LDS; carries for the positions from the end of the part
+        stage_entries<J0_CHUNKS + 1>(V, wbeg, buf);
+        __builtin_amdgcn_wave_barrier();
+        auto entry = [&](uint64_t q) -> uint64_t {
+          return q - wbeg < J0_SPAN ? buf[q - wbeg] : entry_at(V, q);
+        };
+        if (wend < n) {
+          pnx0 = partner_of(entry(walk_streak_start(entry, wbeg, wend, n)));
+          pnx1 = partner_of(entry(walk_streak_start(entry, wbeg, wend + 1, n)));
+          const uint64_t fw = walk_first_write(entry, wbeg, wend, n);
+          if (fw != NOPOS) {
+            const uint64_t efw = entry(fw);
+            fw_id = (uint32_t)efw;
+            pfw = (uint32_t)(efw >> RUN_PT) & 0xFFFu;
+            const uint64_t nws = walk_write_streak_end(entry, wbeg, fw, fw_id, n);
+            pnws = nws != NOPOS ? (uint32_t)(entry(nws) >> RUN_PT) & 0xFFFu : NONE32;
           }
         }
-        if (best < P && s_minj[i] > best) atomicMin(&s_minj[i], best);
+      } else {
+        // a whole range; the entry after it is the first of the range just
+        // scanned (the one candidate read past the range)
+        e_next = buf[0];
+        __builtin_amdgcn_wave_barrier();
+        stage_entries<J0_CHUNKS>(V, wbeg, buf);
+        if (lane == 0) buf[J0_CHUNKS * 64] = e_next;
+        __builtin_amdgcn_wave_barrier();
       }
-      // carries for the positions from p0 on
-      const uint64_t hx0 = Xm & ~1ull;
-      const uint64_t nSEA = hx0 ? p0 + low_bit(hx0) : (XA ? A : SEA);
-      const bool nXA = Xm & 1ull;
-      const int fl0 = Lm ? low_bit(Lm) : 64;
-      const uint64_t wb = Wm & bits_below(fl0);
-      if (wb) {
-        const int f0 = low_bit(wb);
-        const uint64_t ef0 = buf[c * 64 + f0];
-        const uint64_t hxw = XWm & bits_above(f0), hl2 = Lm & bits_above(f0);
-        uint64_t nn;
-        if (hxw && (!hl2 || low_bit(hxw) < low_bit(hl2))) nn = p0 + low_bit(hxw);
-        else if (hl2) nn = NOPOS;
-        else nn = (FW != NOPOS && accepts(ef0, entry(FW))) ? FW : NWS;
-        FW = p0 + f0;
-        NWS = nn;
-      } else if (Lm) {
-        FW = NOPOS;
-        NWS = NOPOS;
+      const int nch = (int)((wend - wbeg + 63) / 64);
+      for (int c = nch - 1; c >= 0; c--) {
+        const uint32_t b0 = (uint32_t)c * 64;
+        const uint64_t e = buf[b0 + lane];
+        const uint32_t id = (uint32_t)e, eh = (uint32_t)(e >> 32);
+        const bool W = (eh >> (RUN_W - 32)) & 1;
+        const bool L = (eh >> (RUN_LOC - 32)) & 1;
+        const bool valid = !((eh >> (RUN_END - 32)) & 1);
+        const uint32_t i = eh & 0xFFFu;
+        const uint64_t Wm = __ballot(W), Lm = __ballot(L), Xm = __ballot((eh >> (RUN_X - 32)) & 1);
+        // first candidate: the next record (a write), or the first write after
+        // this record before a location start (a read): in the chunk, else the
+        // carried one
+        const uint32_t fwl = low_bit64(Wm & gt), lll = low_bit64(Lm & gt);
+        const bool f_in = fwl < lll;
+        const uint32_t c1 = W ? lane + 1 : (f_in ? fwl : 64u);   // chunk-local, 64 = past it
+        const uint64_t e1 = buf[b0 + c1];                          // inside the staged span
+        const bool in1 = W || f_in;
+        const uint32_t id1 = in1 ? (uint32_t)e1 : fw_id;
+        const uint32_t p1 = in1 ? partner_of(e1) : (lll == 64 ? pfw : NONE32);
+        const bool same = id1 == id;
+        // second candidate (first candidate has this record's id): the first
+        // streak start after it (a write) or the first write-streak start or
+        // location start after it (a read)
+        uint64_t XWLm = Lm;
+        if (__ballot(valid && !W && f_in && same && p1 != NONE32)) {
+          // write-streak starts: writes whose id differs from the previous write
+          // of the chunk (a location start in between is caught by Lm first)
+          const uint64_t pm = Wm & lt;
+          const uint32_t pw = pm ? 63u - (uint32_t)__builtin_clzll(pm) : 0u;
+          const uint32_t idpw = buf_lo[2 * (b0 + pw)];
+          XWLm |= __ballot(W && pm && idpw != id);
+        }
+        const uint64_t M = (W ? Xm : XWLm) & above(c1);
+        const uint32_t k2 = low_bit64(M);
+        const uint64_t e2 = buf[b0 + (k2 < 64 ? k2 : 0u)];
+        uint32_t p2;
+        if (k2 < 64) p2 = partner_of(e2);
+        else if (W) p2 = c1 == 64 ? pnx1 : pnx0;
+        else p2 = fw_id != id1 ? pfw : pnws;
+        const uint32_t best = p1 == NONE32 ? NONE32 : (same ? p2 : p1);
+        if (valid && best < P && s_minj[i] > best) atomicMin(&s_minj[i], best);
+        // carries for the positions from b0 on
+        const uint32_t x0 = low_bit64(Xm), x1 = low_bit64(Xm & ~1ull);
+        const uint32_t nx0 = x0 < 64 ? partner_of(((uint64_t)__builtin_amdgcn_readlane(eh, x0)) << 32) : pnx0;
+        pnx1 = x1 < 64 ? partner_of(((uint64_t)__builtin_amdgcn_readlane(eh, x1)) << 32) : pnx0;
+        pnx0 = nx0;
+        const uint32_t fl0 = low_bit64(Lm);
+        const uint64_t wb = fl0 < 64 ? (Wm & ((1ull << fl0) - 1)) : Wm;
+        if (wb) {
+          const uint32_t f0 = low_bit64(wb);
+          const uint32_t nid = __builtin_amdgcn_readlane(id, f0);
+          const uint32_t npt = __builtin_amdgcn_readlane(eh, f0) & 0xFFFu;
+          const uint64_t hm = __ballot(W && id != nid) & above(f0);
+          uint32_t nws;
+          if (hm && low_bit64(hm) < fl0) nws = __builtin_amdgcn_readlane(eh, low_bit64(hm)) & 0xFFFu;
+          else if (fl0 < 64) nws = NONE32;
+          else nws = (pfw != NONE32 && fw_id != nid) ? pfw : pnws;
+          fw_id = nid;
+          pfw = npt;
+          pnws = nws;
+        } else if (fl0 < 64) {
+          pfw = NONE32;
+          pnws = NONE32;
+        }
       }
-      A = p0;
-      XA = nXA;
-      SEA = nSEA;
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   if (cur >= 0) {

@@ -127,7 +127,7 @@ struct SortChunk {
 struct GenItem {
   uint64_t o0, o1;
   uint32_t job, view;    // view 0 same-block log, 1 cross-block log
-  uint32_t seg, pad;
+  uint32_t seg, i0;      // i0: the point holding record o0
 };
 
 // one log of one job: its sorted records
@@ -144,12 +144,12 @@ struct ConfSeg {
 //   bits  0..31  id: the thread (same-block view) or the block (cross-block view)
 //   bits 32..43  point
 //   bit  44      the point writes
-//   bit  45      multi: unused (always 0; kept so a run of several ids could
-//                be folded into one entry)
+//   bit  45      first record of a streak: first of its location, or its id
+//                differs from the previous record's
 //   bit  46      first record of its location
 //   bit  47      never set in an entry: marks the sentinel read past a log
-constexpr int RUN_PT = 32, RUN_W = 44, RUN_MULTI = 45, RUN_LOC = 46, RUN_END = 47;
-constexpr uint64_t RUN_SENTINEL = (1ull << RUN_LOC) | (1ull << RUN_END);
+constexpr int RUN_PT = 32, RUN_W = 44, RUN_X = 45, RUN_LOC = 46, RUN_END = 47;
+constexpr uint64_t RUN_SENTINEL = (1ull << RUN_X) | (1ull << RUN_LOC) | (1ull << RUN_END);
 
 __device__ __forceinline__ uint32_t word_of(const DPoint& p, uint32_t t, uint32_t k) {
   int64_t v = (int64_t)p.a * (int64_t)t + (int64_t)p.b * (int64_t)k + (int64_t)p.c;

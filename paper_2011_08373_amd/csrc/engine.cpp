@@ -73,6 +73,9 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   for (size_t s = 0; s < L.ssegs.size(); s++) {
     const uint64_t n = L.ssegs[s].end - L.ssegs[s].beg;
     L.ssegs[s].chunk_beg = (uint32_t)L.chunks.size();
+    const Plan& pj = *jobs[L.seg_job[s]].plan;
+    const std::vector<uint64_t>& pre = L.seg_level[s] == 0 ? pj.cnt_pre : pj.gcnt_pre;
+    const uint64_t rblk = pj.cnt_pre[pj.P];
     for (uint64_t o0 = 0; o0 < n; o0 += chunk) {
       GenItem it{};
       it.o0 = o0;
@@ -80,6 +83,9 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
       it.job = L.seg_job[s];
       it.view = L.seg_level[s];
       it.seg = (uint32_t)s;
+      // the point holding record o0: the last i < P with pre[i] <= offset
+      const uint64_t first = it.view == 0 ? o0 % rblk : o0;
+      it.i0 = (uint32_t)(std::upper_bound(pre.begin(), pre.begin() + pj.P, first) - pre.begin()) - 1;
       L.items.push_back(it);
       SortChunk c{};
       c.beg = L.ssegs[s].beg + it.o0;
@@ -207,16 +213,53 @@ size_t engine_workspace(const std::vector<JobInput>& jobs, const EngineOpts& o) 
     if ((x) != hipSuccess) return RP_ERR_DEVICE; \
   } while (0)
 
+// Page-locked host staging for the descriptor upload, one per host thread,
+// grown on demand and kept for the life of the thread (never freed: a
+// thread-exit free could run after the runtime is gone).  An event marks the
+// last upload out of it; the next call waits for that event before writing.
+struct PinnedStage {
+  uint8_t* p = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  uint8_t* get(size_t n) {
+    if (pending) {
+      if (!done || hipEventSynchronize(done) != hipSuccess) return nullptr;
+      pending = false;
+    }
+    if (n > cap) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+      if (hipHostMalloc((void**)&p, n < 4096 ? 4096 : n, hipHostMallocDefault) != hipSuccess) {
+        p = nullptr;
+        return nullptr;
+      }
+      cap = n < 4096 ? 4096 : n;
+    }
+    return p;
+  }
+  // the uploads out of the buffer were enqueued on s
+  void in_flight(hipStream_t s) {
+    if (!done && hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) done = nullptr;
+    if (done && hipEventRecord(done, s) == hipSuccess) pending = true;
+    else (void)hipStreamSynchronize(s);
+  }
+};
+thread_local PinnedStage t_stage;
+
 namespace {
 
-// Host staging, upload, record generation, sort and run-log build for the
-// jobs laid out by L in the device buffer d (all enqueued on s, no sync).
+// Host staging (hbuf, L.meta bytes, must stay untouched until the upload
+// enqueued here has run), upload, record generation, sort and first-partner
+// table for the jobs laid out by L in the device buffer d (all enqueued on
+// s, no sync).
 int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const Layout& L,
-                 uint8_t* d, std::vector<uint8_t>& h, hipStream_t s, Timer& tm) {
+                 uint8_t* d, uint8_t* hbuf, hipStream_t s, Timer& tm) {
   const size_t N = jobs.size();
-  h.assign(L.meta, 0);
-  Job* hj = (Job*)(h.data() + L.o_jobs);
-  JobState* hs = (JobState*)(h.data() + L.o_states);
+  std::memset(hbuf, 0, L.meta);
+  Job* hj = (Job*)(hbuf + L.o_jobs);
+  JobState* hs = (JobState*)(hbuf + L.o_states);
   for (size_t j = 0; j < N; j++) {
     const Plan& p = *jobs[j].plan;
     Job& J = hj[j];
@@ -254,21 +297,21 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     S.state = ST_RUN;
     S.max_rounds = jobs[j].max_rounds;
     S.phase = jobs[j].solver ? PH_GREEDY : PH_EXACT;
-    std::memcpy(h.data() + L.o_pts[j], p.pts.data(), p.P * sizeof(DPoint));
-    std::memcpy(h.data() + L.o_wbits[j], p.wbits.data(), p.wbits.size() * sizeof(uint64_t));
-    std::memcpy(h.data() + L.o_bany[j], p.bits_any.data(), p.P * sizeof(uint64_t));
-    std::memcpy(h.data() + L.o_bgrid[j], p.bits_grid.data(), p.P * sizeof(uint64_t));
-    std::memcpy(h.data() + L.o_w[j], p.weights.data(), p.S * sizeof(uint32_t));
-    std::memcpy(h.data() + L.o_cpre[j], p.cnt_pre.data(), (p.P + 1) * sizeof(uint64_t));
-    std::memcpy(h.data() + L.o_gpre[j], p.gcnt_pre.data(), (p.P + 1) * sizeof(uint64_t));
-    std::memcpy(h.data() + L.o_phi0j[j], jobs[j].phi0.data(), jobs[j].phi0.size() * sizeof(rp_clause));
+    std::memcpy(hbuf + L.o_pts[j], p.pts.data(), p.P * sizeof(DPoint));
+    std::memcpy(hbuf + L.o_wbits[j], p.wbits.data(), p.wbits.size() * sizeof(uint64_t));
+    std::memcpy(hbuf + L.o_bany[j], p.bits_any.data(), p.P * sizeof(uint64_t));
+    std::memcpy(hbuf + L.o_bgrid[j], p.bits_grid.data(), p.P * sizeof(uint64_t));
+    std::memcpy(hbuf + L.o_w[j], p.weights.data(), p.S * sizeof(uint32_t));
+    std::memcpy(hbuf + L.o_cpre[j], p.cnt_pre.data(), (p.P + 1) * sizeof(uint64_t));
+    std::memcpy(hbuf + L.o_gpre[j], p.gcnt_pre.data(), (p.P + 1) * sizeof(uint64_t));
+    std::memcpy(hbuf + L.o_phi0j[j], jobs[j].phi0.data(), jobs[j].phi0.size() * sizeof(rp_clause));
   }
-  std::memcpy(h.data() + L.o_items, L.items.data(), L.items.size() * sizeof(GenItem));
-  std::memcpy(h.data() + L.o_chunks, L.chunks.data(), L.chunks.size() * sizeof(SortChunk));
-  std::memcpy(h.data() + L.o_ssegs, L.ssegs.data(), L.ssegs.size() * sizeof(SortSeg));
+  std::memcpy(hbuf + L.o_items, L.items.data(), L.items.size() * sizeof(GenItem));
+  std::memcpy(hbuf + L.o_chunks, L.chunks.data(), L.chunks.size() * sizeof(SortChunk));
+  std::memcpy(hbuf + L.o_ssegs, L.ssegs.data(), L.ssegs.size() * sizeof(SortSeg));
   // sorted logs end in buffer A after an even number of passes, else B
   uint8_t* sorted = d + ((L.passes % 2 == 0) ? L.o_recA : L.o_recB);
-  ConfSeg* hc = (ConfSeg*)(h.data() + L.o_csegs);
+  ConfSeg* hc = (ConfSeg*)(hbuf + L.o_csegs);
   for (size_t q = 0; q < L.ssegs.size(); q++) {
     ConfSeg c{};
     c.log = (const uint64_t*)sorted + L.ssegs[q].beg;
@@ -280,7 +323,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     hj[c.job].log[c.level] = c.log;
   }
   tm.mark(T_START);
-  HIPCHK(hipMemcpyAsync(d, h.data(), L.meta, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d, hbuf, L.meta, hipMemcpyHostToDevice, s));
   for (size_t j = 0; j < N; j++)
     if (!jobs[j].phi0.empty())
       HIPCHK(hipMemcpyAsync(d + L.o_phi[j], d + L.o_phi0j[j],
@@ -348,7 +391,8 @@ int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStrea
   if (bytes < L.total || !region) return RP_ERR_WORKSPACE;
   uint8_t* d = (uint8_t*)region;
   Timer tm(s, false);
-  const int rc = prepare_jobs(v, o, L, d, staging, s, tm);
+  staging.resize(L.meta);
+  const int rc = prepare_jobs(v, o, L, d, staging.data(), s, tm);
   if (rc != RP_OK) return rc;
   HIPCHK(launch_solve((const Job*)(d + L.o_jobs), 1, s));
   std::memcpy(&out.job, staging.data() + L.o_jobs, sizeof(Job));
@@ -371,10 +415,12 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   if (!ws && L.total) return RP_ERR_WORKSPACE;
   const size_t N = jobs.size();
   uint8_t* d = (uint8_t*)ws;
-  std::vector<uint8_t> h;
   Timer tm(s);
   {
+    uint8_t* h = t_stage.get(L.meta);
+    if (!h) return RP_ERR_DEVICE;
     const int rc = prepare_jobs(jobs, o, L, d, h, s, tm);
+    t_stage.in_flight(s);
     if (rc != RP_OK) return rc;
   }
   const Job* djobs = (const Job*)(d + L.o_jobs);

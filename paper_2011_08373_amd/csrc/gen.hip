@@ -8,7 +8,8 @@
 // threads are those with tid % m == r.  Items coincide with the sort's
 // chunks: while writing, an item counts the radix digits of the first sort
 // pass in LDS and stores them as its chunk's count row.  The item's points
-// (up to 256, from its first point on) are staged in LDS first.
+// (up to 256, from its first point on, which the host finds) are staged in
+// LDS first.
 #include "common.h"
 #include "launch.h"
 
@@ -37,6 +38,30 @@ __device__ __forceinline__ void count_digits(uint32_t* hist, uint64_t rec, int s
   }
 }
 
+// Wave-uniform copies (the values are the same in every lane; saying so
+// keeps the per-point arithmetic on the scalar unit).
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+__device__ __forceinline__ DPoint uni_point(const DPoint& p) {
+  static_assert(sizeof(DPoint) == 32, "eight words");
+  DPoint u;
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(&p);
+  uint32_t* d = reinterpret_cast<uint32_t*>(&u);
+#pragma unroll
+  for (int k = 0; k < 8; k++) d[k] = uni(s[k]);
+  return u;
+}
+// x * tid for a wave-uniform x: one 24-bit multiply when x fits (the usual
+// case: strides and guard moduli are small), else a full one; the product is
+// taken mod 2^32 either way.
+__device__ __forceinline__ uint32_t mul_tid(uint32_t x, uint32_t tid) {
+  const int32_t xs = (int32_t)x;
+  if (xs >= -(1 << 23) && xs < (1 << 23)) return (uint32_t)__mul24(xs, (int32_t)tid);
+  return x * tid;
+}
+
 template <int RB>
 __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restrict__ items,
                                                         const Job* __restrict__ jobs,
@@ -48,101 +73,124 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
   __shared__ uint32_t hist[R];
   __shared__ DPoint s_pts[GEN_CACHE];        // points i0, i0+1, ... (mod P) of the item
   __shared__ uint64_t s_cnt[GEN_CACHE];      // their records (per block in the same-block log)
-  __shared__ uint32_t s_i;
+  __shared__ uint64_t s_pre[GEN_CACHE];      // their prefix entries
   const GenItem it = items[blockIdx.x];
   const Job& J = jobs[it.job];
   const SortSeg sg = segs[it.seg];
   const int shift = (int)sg.shift;
   const int count = passes > 0;
+  const uint32_t tid = threadIdx.x;
   uint64_t* out = recs + sg.beg;
-  for (uint32_t q = threadIdx.x; q < R; q += GEN_BLOCK) hist[q] = 0;
+  for (uint32_t q = tid; q < R; q += GEN_BLOCK) hist[q] = 0;
   const uint32_t ks = J.key_shift, tb = J.tbits, bb = J.bbits, pb = J.pbits, nb = J.nbits;
   const uint32_t P = J.P;
-  // first point of the item: largest i with prefix[i] <= offset
   const uint64_t* pre = it.view == 0 ? J.cnt_pre : J.gcnt_pre;
   const uint64_t first = it.view == 0 ? it.o0 % J.rblk : it.o0;
-  if (threadIdx.x == 0) {
-    uint32_t lo = 0, hi = P - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (pre[mid] <= first) lo = mid; else hi = mid - 1;
-    }
-    s_i = lo;
-  }
-  __syncthreads();
-  const uint32_t i0 = s_i;
+  const uint32_t i0 = it.i0;                 // point holding record o0 (set by the host)
   const uint32_t nc = P < GEN_CACHE ? P : GEN_CACHE;
-  for (uint32_t d = threadIdx.x; d < nc; d += GEN_BLOCK) {
+  for (uint32_t d = tid; d < nc; d += GEN_BLOCK) {
     uint32_t i = i0 + d;
     if (i >= P) i -= P;
     s_pts[d] = J.pts[i];
+    s_pre[d] = pre[i];
     s_cnt[d] = pre[i + 1] - pre[i];
   }
   __syncthreads();
-  uint32_t i = i0;
-  uint32_t d = 0;            // cache slot of point i (i0 + d mod P)
-  uint64_t pos = it.o0;
   if (it.view == 0) {
-    // block-major: block k, points in order, executing threads in order
-    uint32_t k = (uint32_t)(it.o0 / J.rblk);
-    uint64_t u0 = first - pre[i];
-    while (pos < it.o1) {
-      const bool cached = d < nc;
-      const uint64_t c = cached ? s_cnt[d] : pre[i + 1] - pre[i];
-      const uint64_t take = (c - u0) < (it.o1 - pos) ? (c - u0) : (it.o1 - pos);
-      if (take) {
-        const DPoint p = cached ? s_pts[d] : J.pts[i];
+    // block-major: block k, points in order, executing threads in order.
+    // Segment s of the item is point (i0 + s) mod P of block k0 + (i0 + s) / P;
+    // its records are a contiguous stretch, and wave w takes segments w,
+    // w + WAVES, ... (a segment usually has a few hundred records, so one wave
+    // covers it in a few steps and the per-segment work is paid once per wave)
+    constexpr uint32_t WAVES = GEN_BLOCK / 64;
+    const uint32_t w = uni(tid >> 6), lane = tid & 63u;
+    const uint64_t rblk = J.rblk;
+    uint32_t k = (uint32_t)(it.o0 / rblk);
+    uint32_t sd = w;                   // segment index (cache slot while < nc)
+    uint32_t si = i0 + w;
+    while (si >= P) { si -= P; k++; }
+    for (;;) {
+      const bool cached = sd < nc;
+      const uint64_t pbeg = uni64(cached ? s_pre[sd] : pre[si]);
+      const uint64_t sbeg = (uint64_t)k * rblk + pbeg;     // first record of the segment
+      if (sbeg >= it.o1) break;
+      const uint64_t c = uni64(cached ? s_cnt[sd] : pre[si + 1] - pre[si]);
+      const uint64_t lo = sbeg > it.o0 ? sbeg : it.o0;
+      const uint64_t hi = sbeg + c < it.o1 ? sbeg + c : it.o1;
+      if (lo < hi) {
+        const DPoint p = uni_point(cached ? s_pts[sd] : J.pts[si]);
         const uint64_t arr = (uint64_t)p.array << nb;
-        const uint64_t low = ((uint64_t)k << (pb + tb)) | ((uint64_t)i << tb);
-        for (uint64_t q0 = 0; q0 < take; q0 += GEN_BLOCK) {
-          const uint64_t q = q0 + threadIdx.x;
+        const uint64_t low = ((uint64_t)k << (pb + tb)) | ((uint64_t)si << tb);
+        // record u0 + q of the point: thread t = r + m*(u0 + q)
+        const uint32_t u0 = (uint32_t)(lo - sbeg);
+        const uint32_t t0 = p.r + p.m * u0;
+        const uint32_t mt = mul_tid(p.m, lane);
+        // power-of-two words: word = (a*t + b*k + c) mod 2^32, masked
+        const bool pow2 = p.flags & PF_POW2;
+        const uint32_t am = (uint32_t)p.a * p.m;
+        const uint32_t at = pow2 ? mul_tid(am, lane) : 0u;
+        const uint32_t cw = (uint32_t)p.a * t0 + (uint32_t)p.b * k + (uint32_t)p.c;
+        const uint32_t wmask = p.words - 1;
+        const uint64_t take = hi - lo;
+        for (uint64_t q0 = 0; q0 < take; q0 += 64) {
+          const uint64_t q = q0 + lane;
           const bool valid = q < take;
-          uint64_t rec = 0;
-          if (valid) {
-            const uint32_t t = p.r + p.m * (uint32_t)(u0 + q);
-            rec = ((arr | word_of(p, t, k)) << ks) | low | t;
-            out[pos + q] = rec;
-          }
+          const uint32_t t = t0 + p.m * (uint32_t)q0 + mt;
+          uint32_t word;
+          if (pow2) word = (cw + am * (uint32_t)q0 + at) & wmask;
+          else word = word_of(p, t, k);
+          const uint64_t rec = ((arr | word) << ks) | low | t;
+          if (valid) out[lo + q] = rec;
           if (count) count_digits<RB>(hist, rec, shift, valid);
         }
       }
-      pos += take;
-      u0 = 0;
-      d++;
-      if (++i == P) { i = 0; k++; }
+      sd += WAVES;
+      si += WAVES;
+      while (si >= P) { si -= P; k++; }
     }
   } else {
     // point-major over GLOBAL access points: point i, blocks in order,
     // executing threads in order (one thread when the word does not depend
     // on it; blocks 0 and 1 only when it does not depend on the block)
+    uint32_t i = i0;
+    uint32_t d = 0;            // cache slot of point i
+    uint64_t pos = it.o0;
     uint64_t j0 = first - pre[i];
     while (pos < it.o1) {
       const bool cached = d < nc;
-      const uint64_t span = cached ? s_cnt[d] : pre[i + 1] - pre[i];
+      const uint64_t span = uni64(cached ? s_cnt[d] : pre[i + 1] - pre[i]);
       const uint64_t take = (span - j0) < (it.o1 - pos) ? (span - j0) : (it.o1 - pos);
       if (take) {
-        const DPoint p = cached ? s_pts[d] : J.pts[i];
+        const DPoint p = uni_point(cached ? s_pts[d] : J.pts[i]);
         const uint32_t cnt = (p.flags & PF_TCONST) ? 1u : p.cnt;
         const uint64_t arr = (uint64_t)p.array << nb;
         const uint64_t pf = (uint64_t)i << (bb + tb);
+        // record j of the point: block j / cnt, its (j mod cnt)-th executing thread
+        const bool cpow2 = (cnt & (cnt - 1)) == 0;
+        const uint32_t csh = 31u - (uint32_t)__builtin_clz(cnt);
+        const bool pow2 = p.flags & PF_POW2;
+        const uint32_t wmask = p.words - 1;
         for (uint64_t q0 = 0; q0 < take; q0 += GEN_BLOCK) {
-          const uint64_t q = q0 + threadIdx.x;
+          const uint64_t q = q0 + tid;
           const bool valid = q < take;
-          uint64_t rec = 0;
-          if (valid) {
-            const uint64_t j = j0 + q;
-            uint32_t kk, u;
-            if (span < (1ull << 32)) {
-              kk = (uint32_t)j / cnt;
-              u = (uint32_t)j - kk * cnt;
-            } else {
-              kk = (uint32_t)(j / cnt);
-              u = (uint32_t)(j - (uint64_t)kk * cnt);
-            }
-            const uint32_t t = p.r + p.m * u;
-            rec = ((arr | word_of(p, t, kk)) << ks) | pf | ((uint64_t)kk << tb);
-            out[pos + q] = rec;
+          const uint64_t j = j0 + q;
+          uint32_t kk, u;
+          if (cpow2 && span < (1ull << 32)) {
+            kk = (uint32_t)j >> csh;
+            u = (uint32_t)j & (cnt - 1);
+          } else if (span < (1ull << 32)) {
+            kk = (uint32_t)j / cnt;
+            u = (uint32_t)j - kk * cnt;
+          } else {
+            kk = (uint32_t)(j / cnt);
+            u = (uint32_t)(j - (uint64_t)kk * cnt);
           }
+          const uint32_t t = p.r + p.m * u;
+          uint32_t word;
+          if (pow2) word = ((uint32_t)p.a * t + (uint32_t)p.b * kk + (uint32_t)p.c) & wmask;
+          else word = word_of(p, t, kk);
+          const uint64_t rec = ((arr | word) << ks) | pf | ((uint64_t)kk << tb);
+          if (valid) out[pos + q] = rec;
           if (count) count_digits<RB>(hist, rec, shift, valid);
         }
       }
@@ -155,7 +203,7 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
   if (!count) return;
   __syncthreads();
   uint32_t* row = item_hist + (size_t)blockIdx.x * R;
-  for (uint32_t q = threadIdx.x; q < R; q += GEN_BLOCK) row[q] = hist[q];
+  for (uint32_t q = tid; q < R; q += GEN_BLOCK) row[q] = hist[q];
 }
 
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,

@@ -43,19 +43,28 @@ __global__ __launch_bounds__(256) void count_kernel(const uint64_t* __restrict__
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < R; d += 256) hist[d] = 0;
   __syncthreads();
-  for (uint64_t r0 = ch.beg; r0 < ch.end; r0 += 256) {
-    const uint64_t r = r0 + threadIdx.x;
-    const bool valid = r < ch.end;
-    const uint32_t d = valid ? digit_at(in[r], shift, R - 1) : 0u;
-    const uint64_t act = __ballot(valid);
-    // valid lanes are a prefix of the wave: lane 0 holds the first digit
-    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-    const uint64_t same = __ballot(valid && d == d0);
-    if (valid) {
-      if (same == act) {
-        if (__lane_id() == 0) atomicAdd(&hist[d], (uint32_t)__popcll(act));
-      } else {
-        atomicAdd(&hist[d], 1u);
+  for (uint64_t r0 = ch.beg; r0 < ch.end; r0 += 4 * 256) {
+    uint64_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {      // four loads in flight per thread
+      const uint64_t r = r0 + k * 256 + threadIdx.x;
+      v[k] = r < ch.end ? in[r] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint64_t r = r0 + k * 256 + threadIdx.x;
+      const bool valid = r < ch.end;
+      const uint32_t d = valid ? digit_at(v[k], shift, R - 1) : 0u;
+      const uint64_t act = __ballot(valid);
+      // valid lanes are a prefix of the wave: lane 0 holds the first digit
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+      const uint64_t same = __ballot(valid && d == d0);
+      if (valid) {
+        if (same == act) {
+          if (__lane_id() == 0) atomicAdd(&hist[d], (uint32_t)__popcll(act));
+        } else {
+          atomicAdd(&hist[d], 1u);
+        }
       }
     }
   }
@@ -149,28 +158,55 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
   const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
   const uint64_t lt = lanemask_lt();
   const uint32_t wbase = (uint32_t)w * 64 * SC_IPT;
-  // persistent: workgroups take chunks in turn
-  for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
-  const SortChunk ch = chunks[ci];
-  const SortSeg sg = segs[ch.seg];
-  const int shift = (int)sg.shift + pass * RB;
-  __syncthreads();
+  // persistent: workgroups take chunks in turn, tile by tile; the keys of the
+  // next tile are loaded while the current one is ranked and written
+  uint32_t ci = blockIdx.x;
+  if (ci >= nchunks) return;
+  SortChunk ch = chunks[ci];
+  SortSeg sg = segs[ch.seg];
+  int shift = (int)sg.shift + pass * RB;
   for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] = off[(size_t)ci * R + d];
-
-  for (uint64_t base = ch.beg; base < ch.end; base += SC_TILE) {
+  uint64_t base = ch.beg;
+  // wave w owns records [w*64*IPT, (w+1)*64*IPT) of the tile; item k of
+  // lane l is record w*64*IPT + k*64 + l (coalesced; rank order = input order)
+  uint64_t key[SC_IPT];
+  {
     const uint64_t rem = ch.end - base;
-    const uint32_t n_here = rem < SC_TILE ? (uint32_t)rem : SC_TILE;
-    for (uint32_t q = tid; q < SC_WAVES * R; q += SC_BLOCK) (&whist[0][0])[q] = 0;
-    __syncthreads();
-    // wave w owns records [w*64*IPT, (w+1)*64*IPT) of the tile; item k of
-    // lane l is record w*64*IPT + k*64 + l (coalesced; rank order = input order)
-    uint64_t key[SC_IPT];
-    uint32_t rank[SC_IPT];
+    const uint32_t n0 = rem < SC_TILE ? (uint32_t)rem : SC_TILE;
 #pragma unroll
     for (int k = 0; k < SC_IPT; k++) {
       const uint32_t idx = wbase + k * 64 + lane;
-      key[k] = idx < n_here ? in[base + idx] : 0;
+      key[k] = idx < n0 ? in[base + idx] : 0;
     }
+  }
+  for (;;) {
+    const uint64_t rem = ch.end - base;
+    const uint32_t n_here = rem < SC_TILE ? (uint32_t)rem : SC_TILE;
+    // the next tile: later in this chunk, else the first of the next chunk
+    uint32_t nci = ci;
+    uint64_t nbase = base + SC_TILE;
+    SortChunk nch = ch;
+    if (nbase >= ch.end) {
+      nci = ci + gridDim.x;
+      if (nci < nchunks) {
+        nch = chunks[nci];
+        nbase = nch.beg;
+      }
+    }
+    const bool has_next = nci < nchunks;
+    uint64_t knext[SC_IPT];
+    {
+      const uint64_t nrem = has_next ? nch.end - nbase : 0;
+      const uint32_t nn = nrem < SC_TILE ? (uint32_t)nrem : SC_TILE;
+#pragma unroll
+      for (int k = 0; k < SC_IPT; k++) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        knext[k] = idx < nn ? in[nbase + idx] : 0;
+      }
+    }
+    for (uint32_t q = tid; q < SC_WAVES * R; q += SC_BLOCK) (&whist[0][0])[q] = 0;
+    __syncthreads();
+    uint32_t rank[SC_IPT];
 #pragma unroll
     for (int k = 0; k < SC_IPT; k++) {
       const bool valid = (wbase + k * 64 + lane) < n_here;
@@ -261,7 +297,17 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
     __syncthreads();
     for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] += tcount[d];
     __syncthreads();
-  }
+    if (!has_next) break;
+    if (nci != ci) {
+      ci = nci;
+      ch = nch;
+      sg = segs[ch.seg];
+      shift = (int)sg.shift + pass * RB;
+      for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] = off[(size_t)ci * R + d];
+    }
+    base = nbase;
+#pragma unroll
+    for (int k = 0; k < SC_IPT; k++) key[k] = knext[k];
   }
 }
 

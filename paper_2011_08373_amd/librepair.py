@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import threading
 
 import numpy as np
 
@@ -127,9 +128,37 @@ class KernelArg:
                           len(self.points), len(self.slots), ptr(self.arrays), ptr(self.guards),
                           ptr(self.points), ptr(self.slots))
 
+        self._need = {}
+
     @property
     def ref(self):
         return C.byref(self.k)
+
+    def need(self, op: int) -> int:
+        """Workspace bytes of op for this model (cached)."""
+        if op not in self._need:
+            self._need[op] = int(_L.rp_workspace_bytes(self.ref, int(op)))
+        return self._need[op]
+
+
+def _arg(km):
+    """A kernel model or a KernelArg already built from one (callers that
+    repeat calls on one model build it once)."""
+    return km if isinstance(km, KernelArg) else KernelArg(km)
+
+
+_tls = threading.local()
+
+
+def _traj(cap: int):
+    """Trajectory output buffer, one per thread and capacity."""
+    cap = max(1, int(cap))
+    bufs = getattr(_tls, "traj", None)
+    if bufs is None:
+        bufs = _tls.traj = {}
+    if cap not in bufs:
+        bufs[cap] = (C.c_uint64 * cap)()
+    return bufs[cap]
 
 
 class Workspace:
@@ -157,17 +186,17 @@ def _stream(stream=None):
 
 
 def validate(km) -> int:
-    return _L.rp_validate(KernelArg(km).ref)
+    return _L.rp_validate(_arg(km).ref)
 
 
 def workspace_bytes(km, op: int) -> int:
-    return int(_L.rp_workspace_bytes(KernelArg(km).ref, int(op)))
+    return _arg(km).need(op)
 
 
 def check(km, x: int = 0, cap: int | None = None, ws=None, stream=None):
     """Verify under x.  Returns (status, pairs, divergent, n_records, n_pairs)
     with pairs a list of (level, i, j) in ascending order (empty unless OK)."""
-    ka = KernelArg(km)
+    ka = _arg(km)
     need = int(_L.rp_workspace_bytes(ka.ref, OP_CHECK))
     if need == 0:
         return ERR_INVALID, [], 0, 0, 0
@@ -190,7 +219,7 @@ def check(km, x: int = 0, cap: int | None = None, ws=None, stream=None):
 
 def first_partners(km, x: int = 0, ws=None, stream=None):
     """(status, first[2][P] as a numpy array, divergent); 0xFFFFFFFF = none."""
-    ka = KernelArg(km)
+    ka = _arg(km)
     need = int(_L.rp_workspace_bytes(ka.ref, OP_FIRST))
     if need == 0:
         return ERR_INVALID, None, 0
@@ -204,7 +233,7 @@ def first_partners(km, x: int = 0, ws=None, stream=None):
 
 def clauses(km, x: int = 0, cap: int | None = None, ws=None, stream=None):
     """(status, [(pos, neg), ...]) reduced and sorted."""
-    ka = KernelArg(km)
+    ka = _arg(km)
     need = int(_L.rp_workspace_bytes(ka.ref, OP_CLAUSES))
     if need == 0:
         return ERR_INVALID, []
@@ -239,14 +268,14 @@ def repair(km, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int
            ws=None, stream=None, traj_cap: int = 4096, solver: int = 0):
     """Alg. 1 on the GPU; dict like the oracle's repair().  solver 0: exact
     Solve every round; 1: the mhs strategy (Section 2.4)."""
-    ka = KernelArg(km)
-    need = int(_L.rp_workspace_bytes(ka.ref, OP_REPAIR))
+    ka = _arg(km)
+    need = ka.need(OP_REPAIR)
     if need == 0:
         return dict(status=ERR_INVALID, ret=ERR_INVALID)
     ptr, size = (ws or _ws).get(need)
     o = RpOpts(policy, grid, inspect, solver, max_rounds)
     out = RpOut()
-    traj = (C.c_uint64 * max(1, traj_cap))()
+    traj = _traj(traj_cap)
     st = _L.rp_repair(ka.ref, C.byref(o), C.byref(out), traj, traj_cap, C.c_void_p(ptr), size,
                       _stream(stream))
     r = dict(status=out.status, assign=out.assign, weight=out.weight, added=out.added,
@@ -324,10 +353,10 @@ class Server:
         self._held = {}
 
     def job_bytes(self, km) -> int:
-        return int(_L.rp_server_job_bytes(KernelArg(km).ref))
+        return int(_L.rp_server_job_bytes(_arg(km).ref))
 
     def submit(self, km, job_id: int) -> int:
-        return _L.rp_server_submit(self.h, KernelArg(km).ref, C.c_uint64(int(job_id)))
+        return _L.rp_server_submit(self.h, _arg(km).ref, C.c_uint64(int(job_id)))
 
     def step(self):
         nr = C.c_uint32(0)
