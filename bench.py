@@ -34,6 +34,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "plain-large": "plain-large %s: 256 blocks x 256 threads, 512 points, 32 slots (8 grid), "
+                   "2 shared + 2 global arrays of 1M words, seed 2",
+    "stress": "stress %s: 4096 blocks x 1024 threads, 1024 points (half accesses), 64 slots "
+              "(16 grid), 4 shared + 4 global arrays of 16M words, seed 5",
+}
 
 
 def _ensure_built():
@@ -143,8 +149,7 @@ def stress_leg(L, torch, steps):
                                    for k in ("ms_gen", "ms_sort", "ms_j0", "ms_check",
                                              "ms_clause", "ms_solve", "ms_total")}}
         torch.cuda.empty_cache()
-    out["workload"] = ("stress: 4096 blocks x 1024 threads, 1024 points (half accesses), "
-                       "64 slots (16 grid), 4 shared + 4 global arrays of 16M words, seed 5")
+    out["workload"] = WORKLOADS["stress"] % "literal and planted"
     return out
 
 
@@ -236,6 +241,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="literal", choices=("literal", "planted"))
+    ap.add_argument("--config", default="plain-large", choices=("plain-large", "stress"),
+                    help="kernel of the headline leg (the stress kernel for profiling runs)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--legs", default="main,planted,stress,batched,served")
     ap.add_argument("--stress-steps", type=int, default=3)
@@ -260,13 +267,13 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    km = synth.generate("plain-large", mode=args.mode)
+    km = synth.generate(args.config, mode=args.mode)
     r, ms, stats = run_main(L, torch, km, args.steps, args.warmup)
     acc = stats[-1]["accesses"]
     km.meta["accesses"] = acc
     checked = acc * r["rounds"]
     value = checked / (ms / 1e3)
-    kern = kernel_rooflines(stats)
+    kern = kernel_rooflines(stats, "" if args.config == "plain-large" else args.config + "/")
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     roof = dict(kern[dom])
     roof["kernel"] = dom
@@ -283,9 +290,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "plain-large %s: 256 blocks x 256 threads, 512 points, "
-                               "32 slots (8 grid), 2 shared + 2 global arrays of 1M words, "
-                               "seed 2" % args.mode,
+        "config": {"workload": WORKLOADS[args.config] % args.mode,
                    "accesses": acc, "records": stats[-1]["records"],
                    "verify_calls": r["rounds"], "repair_status": r["status"]},
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
@@ -300,7 +305,7 @@ def main():
                       for k in ("ms_upload", "ms_gen", "ms_sort", "ms_j0", "ms_check",
                                 "ms_clause", "ms_solve", "ms_total")},
     }
-    if args.mode == "literal" and "planted" in set(args.legs.split(",")):
+    if args.config == "plain-large" and args.mode == "literal" and "planted" in set(args.legs.split(",")):
         # context: the same kernel with a planted safe barrier set (repair
         # runs several Verify calls and ends SAFE)
         kp = synth.generate("plain-large", mode="planted")
@@ -314,7 +319,7 @@ def main():
                           "phases_ms": {k: sum(s[k] for s in stp) / len(stp)
                                         for k in ("ms_gen", "ms_sort", "ms_j0", "ms_check",
                                                   "ms_clause", "ms_solve", "ms_total")}}
-    if not args.no_cpu:
+    if not args.no_cpu and args.config == "plain-large":
         out["cpu_baseline"] = cpu_baseline(km, r["rounds"])
     legs = set(args.legs.split(","))
     torch.cuda.empty_cache()

@@ -4,8 +4,8 @@
       Markdown table of the kernel statistics (calls, average, total, share).
 
   python -m paper_2011_08373_amd.profsum traffic FETCH.csv WRITE.csv KEY MATCH SOURCE COPY_BYTES
-      HBM bytes per launch of the kernel whose name contains MATCH (e.g.
-      "conf_kernel<false>") from two counter-collection runs (one
+      HBM bytes per launch of the kernel named MATCH, or else the one kernel
+      whose name contains it (e.g. "rp::j0_kernel") from two counter-collection runs (one
       with FETCH_SIZE, one with WRITE_SIZE; the counters read KiB per
       dispatch).  Each counter is scaled by what it reads for the largest
       plain device copy of COPY_BYTES bytes in the same run (bench.py
@@ -61,9 +61,12 @@ def traffic(fetch_csv, write_csv, key, match, source, copy_bytes):
             raise SystemExit("no copy kernel in %s: run bench.py with --calib" % path)
         ref = max(copies) * 1024.0            # bytes the counter reads for the copy
         factor = copy_bytes / ref
-        xs = [x for k, xs in v.items() if match in k for x in xs]
-        if not xs:
+        names = [k for k in v if k == match] or [k for k in v if match in k]
+        if not names:
             raise SystemExit("kernel %s not in %s" % (match, path))
+        if len(names) > 1:
+            raise SystemExit("%s names several kernels: %s" % (match, ", ".join(sorted(names))))
+        xs = v[names[0]]
         out[counter] = {"kib_per_dispatch": sum(xs) / len(xs), "dispatches": len(xs),
                         "copy_factor": factor,
                         "bytes_per_launch": sum(xs) / len(xs) * 1024.0 * factor}
