@@ -14,6 +14,7 @@
 //                    the resident workgroups takes the chunks in turn.
 // No workgroup ever waits on another, so nothing here can stall the grid.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "launch.h"
@@ -135,6 +136,14 @@ __global__ __launch_bounds__(256) void colscan_kernel(const uint32_t* __restrict
 
 // Stable scatter of one chunk, tile by tile (SC_BLOCK threads x SC_IPT
 // records per tile).
+// Ballot of v != 0 read straight from v (one compare; the compiler would
+// otherwise rebuild the bit from the digit).
+__device__ __forceinline__ uint64_t ballot_nonzero(uint32_t v) {
+  uint64_t m;
+  asm("v_cmp_ne_u32_e64 %0, 0, %1" : "=s"(m) : "v"(v));
+  return m;
+}
+
 template <int RB, int SC_BLOCK, int SC_IPT>
 __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __restrict__ in,
                                                            uint64_t* __restrict__ out,
@@ -148,7 +157,11 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
   constexpr int SC_WAVES = SC_BLOCK / 64;
   constexpr uint32_t SC_TILE = SC_BLOCK * SC_IPT;
   __shared__ uint64_t sk[SC_TILE];
-  __shared__ uint16_t whist[SC_WAVES][R];      // per-wave counts, then prefixes
+  // per-wave digit counters (32-bit for the LDS adds of the ranking below
+  // when they fit beside the tile, else 16-bit and updated item by item)
+  constexpr bool RANK_ADD = SC_WAVES * R * 4 <= 32768;
+  using HistT = typename std::conditional<RANK_ADD, uint32_t, uint16_t>::type;
+  __shared__ HistT whist[SC_WAVES][R];         // per-wave counts, then prefixes
   __shared__ uint32_t lstart[R];               // tile-local digit starts
   __shared__ uint32_t tcount[R];
   __shared__ uint64_t grun[R];                 // next output slot per digit
@@ -206,7 +219,14 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
     }
     for (uint32_t q = tid; q < SC_WAVES * R; q += SC_BLOCK) (&whist[0][0])[q] = 0;
     __syncthreads();
-    uint32_t rank[SC_IPT];
+    // Rank of each record among the wave's records of its digit, in input
+    // order.  Per item: the lanes with the same digit (peers) from one ballot
+    // per digit bit; the first peer adds the group's size to the wave's
+    // counter of that digit and gets the count before it.  The adds of all
+    // items are issued before any result is used (LDS serves one wave's
+    // operations in order), then each group's base is fetched from its
+    // first lane.
+    uint32_t rank[SC_IPT], gbase[SC_IPT], first[SC_IPT];
 #pragma unroll
     for (int k = 0; k < SC_IPT; k++) {
       const bool valid = (wbase + k * 64 + lane) < n_here;
@@ -218,30 +238,42 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
       const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
       if (__ballot(valid && d == d0) != act) {
         // lanes whose digit differs from this lane's in some bit: for each
-        // bit, its ballot XOR this lane's bit spread over 64 bits
+        // bit, its ballot XOR this lane's bit spread over 32 bits
         uint32_t diff_lo = 0, diff_hi = 0;
 #pragma unroll
         for (int b = 0; b < RB; b++) {
-          const uint32_t rep = (uint32_t)(((int)(d << (31 - b))) >> 31);   // 0 or ~0
-          const uint64_t bb = __ballot(rep != 0);
-          diff_lo |= (uint32_t)bb ^ rep;
-          diff_hi |= (uint32_t)(bb >> 32) ^ rep;
+          const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // 0 or ~0
+          const uint64_t bb = ballot_nonzero(rep);
+          diff_lo = __builtin_amdgcn_bitop3_b32(diff_lo, (uint32_t)bb, rep, 0xF6);   // a | (b ^ c)
+          diff_hi = __builtin_amdgcn_bitop3_b32(diff_hi, (uint32_t)(bb >> 32), rep, 0xF6);
         }
         peers &= ~(((uint64_t)diff_hi << 32) | diff_lo);
       }
-      uint32_t before = 0;
-      if (valid) before = whist[w][d];
-      rank[k] = before + (uint32_t)__popcll(peers & lt);
-      if (valid && (peers & lt) == 0) whist[w][d] = (uint16_t)(before + __popcll(peers));
-      // lanes of a wave run in lock step; keep the next read after this write
-      __builtin_amdgcn_wave_barrier();
+      const uint64_t below = peers & lt;
+      rank[k] = (uint32_t)__popcll(below);
+      if constexpr (RANK_ADD) {
+        first[k] = (uint32_t)__builtin_ctzll(peers | (1ull << 63));   // lowest peer (63 if none)
+        gbase[k] = 0;
+        if (valid && below == 0) gbase[k] = atomicAdd(&whist[w][d], (uint32_t)__popcll(peers));
+      } else {
+        uint32_t before = 0;
+        if (valid) before = whist[w][d];
+        rank[k] += before;
+        if (valid && below == 0) whist[w][d] = (HistT)(before + __popcll(peers));
+        // lanes of a wave run in lock step; keep the next read after this write
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    if constexpr (RANK_ADD) {
+#pragma unroll
+      for (int k = 0; k < SC_IPT; k++) rank[k] += __shfl(gbase[k], (int)first[k]);
     }
     __syncthreads();
     for (uint32_t d = tid; d < R; d += SC_BLOCK) {
       uint32_t run = 0;
       for (int v = 0; v < SC_WAVES; v++) {
         const uint32_t c = whist[v][d];
-        whist[v][d] = (uint16_t)run;
+        whist[v][d] = (HistT)run;
         run += c;
       }
       tcount[d] = run;
