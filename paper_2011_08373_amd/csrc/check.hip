@@ -157,40 +157,52 @@ __global__ __launch_bounds__(1024) void conf_tiles_kernel(const Job* __restrict_
 struct RecView {
   const uint64_t* log;
   uint64_t n;
-  int psh, lsh, ish;       // point field, location, id shifts
-  uint64_t imask;
-  uint32_t pmask;
-  const uint64_t* wb;      // write bit of each point (LDS)
+  int psh, ish;            // point and id field shifts (< 64)
+  uint32_t pmask, imask;   // point and id field masks
+  uint64_t locm, idm;      // location bits, id bits of a record
+  const uint16_t* pw;      // per point: the point | its write bit << 12 (LDS)
 };
 
 __device__ __forceinline__ uint64_t shr(uint64_t v, int s) { return s >= 64 ? 0ull : v >> s; }
 
-__device__ __forceinline__ RecView rec_view(const Job& J, const ConfSeg& sg, const uint64_t* wb) {
+__device__ __forceinline__ RecView rec_view(const Job& J, const ConfSeg& sg, const uint16_t* pw) {
   RecView v;
   v.log = sg.log;
   v.n = sg.n;
   // same-block view: [array|word|block|point|thread]; location = (array, word, block)
   // cross-block view: [array|word|point|block|0];     location = (array, word)
-  v.psh = sg.level == 0 ? (int)J.tbits : (int)(J.bbits + J.tbits);
-  v.lsh = v.psh + (int)J.pbits;
-  v.ish = sg.level == 0 ? 0 : (int)J.tbits;
-  v.imask = sg.level == 0 ? ((1ull << J.tbits) - 1) : ((1ull << J.bbits) - 1);
-  v.pmask = (1u << J.pbits) - 1u;
-  v.wb = wb;
+  const int psh = sg.level == 0 ? (int)J.tbits : (int)(J.bbits + J.tbits);
+  const int lsh = psh + (int)J.pbits;
+  const int ish = sg.level == 0 ? 0 : (int)J.tbits;
+  const uint64_t imask = sg.level == 0 ? ((1ull << J.tbits) - 1) : ((1ull << J.bbits) - 1);
+  // a field at bit 64 or above is empty
+  v.psh = psh < 64 ? psh : 0;
+  v.pmask = psh < 64 ? (1u << J.pbits) - 1u : 0u;
+  v.ish = ish < 64 ? ish : 0;
+  v.imask = ish < 64 ? (uint32_t)imask : 0u;
+  v.locm = lsh < 64 ? ~0ull << lsh : 0ull;
+  v.idm = ish < 64 ? imask << ish : 0ull;
+  v.pw = pw;
   return v;
+}
+
+// Entry of a record from the record itself and the one before it in the log
+// (first: it starts the log).
+__device__ __forceinline__ uint64_t make_entry_of(const RecView& v, uint64_t rec, uint64_t prev,
+                                                  bool first) {
+  const uint64_t df = rec ^ prev;
+  const uint32_t i = (uint32_t)(rec >> v.psh) & v.pmask;
+  const uint32_t id = (uint32_t)(rec >> v.ish) & v.imask;
+  const uint32_t loc = first || (df & v.locm) != 0;
+  const uint32_t x = loc | ((df & v.idm) != 0);
+  const uint32_t hi = v.pw[i] | (x << (RUN_X - 32)) | (loc << (RUN_LOC - 32));
+  return (uint64_t)id | ((uint64_t)hi << 32);
 }
 
 __device__ __forceinline__ uint64_t make_entry(const RecView& v, uint64_t rec, uint64_t prev,
                                                uint64_t q) {
   if (q >= v.n) return RUN_SENTINEL;
-  const uint32_t i = (uint32_t)shr(rec, v.psh) & v.pmask;
-  const uint32_t id = (uint32_t)(shr(rec, v.ish) & v.imask);
-  const uint32_t pid = (uint32_t)(shr(prev, v.ish) & v.imask);
-  const uint32_t w = (reinterpret_cast<const uint32_t*>(v.wb)[i >> 5] >> (i & 31)) & 1u;
-  const uint32_t loc = q == 0 || shr(rec, v.lsh) != shr(prev, v.lsh);
-  const uint32_t x = loc | (id != pid);
-  const uint32_t hi = i | (w << (RUN_W - 32)) | (x << (RUN_X - 32)) | (loc << (RUN_LOC - 32));
-  return (uint64_t)id | ((uint64_t)hi << 32);
+  return make_entry_of(v, rec, prev, q == 0);
 }
 
 __device__ __forceinline__ uint64_t entry_at(const RecView& v, uint64_t q) {
@@ -203,24 +215,31 @@ __device__ __forceinline__ uint64_t entry_at(const RecView& v, uint64_t q) {
 template <int K>
 __device__ __forceinline__ uint64_t stage_entries(const RecView& v, uint64_t b, uint64_t* buf) {
   const int lane = __lane_id();
-  uint64_t r[K], p0;
-  if (b + 64 * K <= v.n) {        // the whole span inside the log: no per-load test
+  uint64_t r[K];
+  const uint64_t p0 = (lane == 0 && b > 0 && b - 1 < v.n) ? v.log[b - 1] : 0;
+  if (b + 64 * K <= v.n) {        // the whole span inside the log: no per-record test
 #pragma unroll
     for (int k = 0; k < K; k++) r[k] = v.log[b + k * 64 + lane];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      uint64_t pr = __shfl_up(r[k], 1);
+      const uint64_t last = k > 0 ? __shfl(r[k - 1], 63) : p0;   // every lane takes part
+      if (lane == 0) pr = last;
+      buf[k * 64 + lane] = make_entry_of(v, r[k], pr, k == 0 && lane == 0 && b == 0);
+    }
   } else {
 #pragma unroll
     for (int k = 0; k < K; k++) {
       const uint64_t q = b + k * 64 + lane;
       r[k] = q < v.n ? v.log[q] : 0;
     }
-  }
-  p0 = (lane == 0 && b > 0 && b - 1 < v.n) ? v.log[b - 1] : 0;
 #pragma unroll
-  for (int k = 0; k < K; k++) {
-    uint64_t pr = __shfl_up(r[k], 1);
-    const uint64_t last = k > 0 ? __shfl(r[k - 1], 63) : p0;   // every lane takes part
-    if (lane == 0) pr = last;
-    buf[k * 64 + lane] = make_entry(v, r[k], pr, b + k * 64 + lane);
+    for (int k = 0; k < K; k++) {
+      uint64_t pr = __shfl_up(r[k], 1);
+      const uint64_t last = k > 0 ? __shfl(r[k - 1], 63) : p0;   // every lane takes part
+      if (lane == 0) pr = last;
+      buf[k * 64 + lane] = make_entry(v, r[k], pr, b + k * 64 + lane);
+    }
   }
   return p0;
 }
@@ -256,7 +275,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
                                                           int nseg,
                                                           const uint32_t* __restrict__ total_at) {
   __shared__ uint64_t s_buf[CONF_WAVES][CONF_CHUNKS * 64];
-  __shared__ uint64_t s_wb[MAX_POINTS / 64];
+  __shared__ uint16_t s_pw[MAX_POINTS];      // point | write bit << 12, per point
   extern __shared__ uint32_t s_dyn[];        // [P] interval of each point, [P] first partner
   const uint32_t total = *total_at;
   const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
@@ -293,7 +312,8 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
         s_iv[i] = iv[i];
         s_minj[i] = NONE32;
       }
-      for (uint32_t q = tid; q < (P + 63) / 64; q += CONF_BLOCK) s_wb[q] = J.wbits[q];
+      for (uint32_t q = tid; q < P; q += CONF_BLOCK)
+        s_pw[q] = (uint16_t)(q | (((J.wbits[q >> 6] >> (q & 63)) & 1) << (RUN_W - 32)));
       __syncthreads();
     }
     const ConfSeg& sg = segs[cur];
@@ -303,7 +323,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
     const uint64_t wend = min(wbeg + (uint64_t)(CONF_CHUNKS * 64), n);
     const Job& J = jobs[sg.job];
     const uint32_t level = sg.level;
-    const RecView V = rec_view(J, sg, s_wb);
+    const RecView V = rec_view(J, sg, s_pw);
     // stage the range
     stage_entries<CONF_CHUNKS>(V, wbeg, buf);
     // first write past the range in the same location
@@ -472,12 +492,13 @@ constexpr int J0_CHUNKS = 8;
 constexpr uint32_t J0_SPAN = (J0_CHUNKS + 1) * 64;     // staged range + one lookahead chunk
 static_assert(CONF_CHUNKS % J0_CHUNKS == 0, "ranges tile a wave's part of a tile");
 
-__global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ jobs,
+// (six waves per SIMD: the register budget that keeps enough waves in
+// flight to cover the dependent LDS reads of the chunk loop)
+__global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void j0_kernel(const Job* __restrict__ jobs,
                                                         const ConfSeg* __restrict__ segs, int nseg,
                                                         const uint32_t* __restrict__ total_at) {
   __shared__ uint64_t s_buf[CONF_WAVES][J0_SPAN];
-  __shared__ uint64_t s_wb[MAX_POINTS / 64];
-  extern __shared__ uint32_t s_dyn[];        // [P] first partner
+  extern __shared__ uint32_t s_dyn[];        // [P] first partner, then [P] point | write bit << 12
   const uint32_t total = *total_at;
   const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
   const uint32_t t0 = blockIdx.x * per;
@@ -492,6 +513,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
   const uint32_t* buf_lo = reinterpret_cast<const uint32_t*>(buf);  // ids (low words)
   int cur = -1;
   uint32_t* s_minj = s_dyn;
+  uint16_t* s_pw = nullptr;
   uint32_t P = 0;
   for (uint32_t tile = t0; tile < t1;) {
     int lo = 0, hi = nseg - 1;   // largest segment with ctile_beg <= tile
@@ -511,13 +533,15 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
       cur = lo;
       const Job& J = jobs[segs[cur].job];
       P = J.P;
+      s_pw = reinterpret_cast<uint16_t*>(s_dyn + P);
       for (uint32_t i = tid; i < P; i += CONF_BLOCK) s_minj[i] = NONE32;
-      for (uint32_t q = tid; q < (P + 63) / 64; q += CONF_BLOCK) s_wb[q] = J.wbits[q];
+      for (uint32_t q = tid; q < P; q += CONF_BLOCK)
+        s_pw[q] = (uint16_t)(q | (((J.wbits[q >> 6] >> (q & 63)) & 1) << (RUN_W - 32)));
       __syncthreads();
     }
     const ConfSeg& sg = segs[cur];
     const uint64_t n = sg.n;
-    const RecView V = rec_view(jobs[sg.job], sg, s_wb);
+    const RecView V = rec_view(jobs[sg.job], sg, s_pw);
     // this workgroup's tiles of the segment, as one record span cut into one
     // contiguous part per wave (whole chunks)
     const uint32_t tend = cur + 1 < nseg ? min(t1, segs[cur + 1].ctile_beg) : t1;
@@ -578,19 +602,19 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
         // first candidate: the next record (a write), or the first write after
         // this record before a location start (a read): in the chunk, else the
         // carried one
-        const uint32_t fwl = low_bit64(Wm & gt), lll = low_bit64(Lm & gt);
-        const bool f_in = fwl < lll;
-        const uint32_t c1 = W ? lane + 1 : (f_in ? fwl : 64u);   // chunk-local, 64 = past it
-        const uint64_t e1 = buf[b0 + c1];                          // inside the staged span
-        const bool in1 = W || f_in;
+        // (for a read: the first write or location start after it; a
+        // location start there means no partner, which partner_of says)
+        const uint32_t c1 = W ? lane + 1 : low_bit64((Wm | Lm) & gt);   // chunk-local, 64 = past it
+        const uint64_t e1 = buf[b0 + c1];                                // inside the staged span
+        const bool in1 = W || c1 < 64;
         const uint32_t id1 = in1 ? (uint32_t)e1 : fw_id;
-        const uint32_t p1 = in1 ? partner_of(e1) : (lll == 64 ? pfw : NONE32);
+        const uint32_t p1 = in1 ? partner_of(e1) : pfw;
         const bool same = id1 == id;
         // second candidate (first candidate has this record's id): the first
         // streak start after it (a write) or the first write-streak start or
         // location start after it (a read)
         uint64_t XWLm = Lm;
-        if (__ballot(valid && !W && f_in && same && p1 != NONE32)) {
+        if (__ballot(valid && !W && c1 < 64 && same && p1 != NONE32)) {
           // write-streak starts: writes whose id differs from the previous write
           // of the chunk (a location start in between is caught by Lm first)
           const uint64_t pm = Wm & lt;
@@ -734,7 +758,8 @@ hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t 
 hipError_t launch_j0(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
                      const uint32_t* tiles, hipStream_t s) {
   if (nseg == 0) return hipSuccess;
-  const size_t dyn = (size_t)(max_points ? max_points : 1) * sizeof(uint32_t);
+  // [P] first partners (u32) and [P] point | write bit (u16)
+  const size_t dyn = (size_t)(max_points ? max_points : 1) * (sizeof(uint32_t) + sizeof(uint16_t));
   int dev = 0, ncu = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
