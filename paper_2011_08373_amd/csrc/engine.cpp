@@ -239,6 +239,25 @@ struct PinnedStage {
     }
     return p;
   }
+  // page-locked space for results read back by this thread's calls (each
+  // call waits for its copies before it returns)
+  uint8_t* rb = nullptr;
+  size_t rb_cap = 0;
+  template <class T = uint32_t>
+  T* readback(size_t n) {
+    if (n > rb_cap) {
+      if (rb) (void)hipHostFree(rb);
+      rb = nullptr;
+      rb_cap = 0;
+      const size_t want = n < 4096 ? 4096 : n;
+      if (hipHostMalloc((void**)&rb, want, hipHostMallocDefault) != hipSuccess) {
+        rb = nullptr;
+        return nullptr;
+      }
+      rb_cap = want;
+    }
+    return reinterpret_cast<T*>(rb);
+  }
   // the uploads out of the buffer were enqueued on s
   void in_flight(hipStream_t s) {
     if (!done && hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) done = nullptr;
@@ -469,25 +488,30 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
       if ((e = launch_solve(djobs, (uint32_t)N, s)) != hipSuccess) return e;
       return launch_count_active(djobs, (uint32_t)N, dactive, s);
     };
-    // one captured graph per round, replayed until every job has a verdict
+    // the first round is launched directly; if jobs remain, the round is
+    // captured once in a graph and replayed until every job has a verdict
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
-    if (o.use_graph && s != nullptr) {
-      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        const hipError_t e = round();
-        const hipError_t ec = hipStreamEndCapture(s, &graph);
-        if (e != hipSuccess || ec != hipSuccess ||
-            hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
-          if (graph) (void)hipGraphDestroy(graph);
-          graph = nullptr;
-          gexec = nullptr;
-          (void)hipGetLastError();
+    bool tried_graph = false;
+    uint32_t* active = t_stage.readback(sizeof(uint32_t));
+    if (!active) return RP_ERR_DEVICE;
+    *active = 1;
+    int rc_loop = RP_OK;
+    while (*active) {
+      if (rounds_run == 1 && !tried_graph && o.use_graph && s != nullptr) {
+        tried_graph = true;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+          const hipError_t e = round();
+          const hipError_t ec = hipStreamEndCapture(s, &graph);
+          if (e != hipSuccess || ec != hipSuccess ||
+              hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            graph = nullptr;
+            gexec = nullptr;
+            (void)hipGetLastError();
+          }
         }
       }
-    }
-    uint32_t active = 1;
-    int rc_loop = RP_OK;
-    while (active) {
       tm.mark(T_ROUND);
       if (gexec) {
         if (hipGraphLaunch(gexec, s) != hipSuccess) { rc_loop = RP_ERR_DEVICE; break; }
@@ -501,7 +525,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
         tm.mark(T_SOLVE);
         HIPCHK(launch_count_active(djobs, (uint32_t)N, dactive, s));
       }
-      if (hipMemcpyAsync(&active, dactive, sizeof(active), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      if (hipMemcpyAsync(active, dactive, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
         rc_loop = RP_ERR_DEVICE;
         break;
@@ -514,10 +538,21 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     if (rc_loop != RP_OK) return rc_loop;
   }
   tm.mark(T_END);
-  HIPCHK(hipMemcpyAsync(hst.data(), d + L.o_states, N * sizeof(JobState), hipMemcpyDeviceToHost, s));
-  uint32_t herr[16];
-  HIPCHK(hipMemcpyAsync(herr, derr, sizeof(herr), hipMemcpyDeviceToHost, s));
+  // job states and the error word, and the start of each job's trajectory
+  // (the usual few rounds), into page-locked memory with one wait
+  const uint32_t traj_head = std::min<uint32_t>(o.traj_cap, 16);
+  uint8_t* rb = (uint8_t*)t_stage.readback(N * sizeof(JobState) + 64 + N * traj_head * sizeof(uint64_t));
+  if (!rb) return RP_ERR_DEVICE;
+  JobState* pst = (JobState*)rb;
+  uint32_t* herr = (uint32_t*)(rb + N * sizeof(JobState));
+  uint64_t* ptraj = (uint64_t*)(rb + N * sizeof(JobState) + 64);
+  HIPCHK(hipMemcpyAsync(pst, d + L.o_states, N * sizeof(JobState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(herr, derr, 64, hipMemcpyDeviceToHost, s));
+  for (size_t j = 0; j < N && traj_head; j++)
+    HIPCHK(hipMemcpyAsync(ptraj + j * traj_head, d + L.o_traj[j], traj_head * sizeof(uint64_t),
+                          hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  std::memcpy(hst.data(), pst, N * sizeof(JobState));
   if (herr[0]) return RP_ERR_DEVICE;
   res.assign(N, JobResult{});
   for (size_t j = 0; j < N; j++) {
@@ -552,7 +587,9 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     if (o.traj_cap) {
       const uint32_t nt = std::min(hst[j].rounds, o.traj_cap);
       res[j].traj.resize(nt);
-      if (nt)
+      if (nt <= traj_head)
+        std::memcpy(res[j].traj.data(), ptraj + j * traj_head, nt * sizeof(uint64_t));
+      else
         HIPCHK(hipMemcpyAsync(res[j].traj.data(), d + L.o_traj[j], nt * sizeof(uint64_t),
                               hipMemcpyDeviceToHost, s));
     }
