@@ -24,7 +24,12 @@ __device__ __forceinline__ bool cl_less(const rp_clause& a, const rp_clause& b) 
   return a.pos != b.pos ? a.pos < b.pos : a.neg < b.neg;
 }
 
-// Bitonic sort of c[0..n2) (n2 a power of two) by one workgroup.
+// Bitonic sort of c[0..n2) (n2 a power of two) by one workgroup.  A step
+// that pairs elements less than 64 apart stays inside one wave's elements
+// (thread t handles t, t + CL_BLOCK, ...): the wave's lanes run in lock step
+// and its LDS operations complete in order, so between two such steps no
+// workgroup barrier is needed; one is needed after a step that pairs
+// elements of different waves and before the next such step.
 __device__ void block_bitonic(rp_clause* c, uint32_t n2) {
   for (uint32_t k = 2; k <= n2; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -36,9 +41,21 @@ __device__ void block_bitonic(rp_clause* c, uint32_t n2) {
           if (up ? cl_less(b, a) : cl_less(a, b)) { c[i] = b; c[l] = a; }
         }
       }
-      __syncthreads();
+      // the next step: (k, j/2), or the first of the next k, (2k, k)
+      const uint32_t nj = j > 1 ? j >> 1 : k;
+      const bool more = j > 1 || (k << 1) <= n2;
+      if (j >= 64 || (more && nj >= 64)) {   // this step or the next crosses waves
+        __syncthreads();
+      } else {
+        // workgroup-scope fences: the compiler must not carry an element
+        // across the step in a register, since another lane may rewrite it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
     }
   }
+  __syncthreads();
 }
 
 __device__ __forceinline__ uint32_t block_excl_scan1024(uint32_t v, uint32_t* sm, uint32_t* total) {
@@ -65,11 +82,16 @@ constexpr uint32_t CL_BITS = 1024;  // points whose slot bits are staged in LDS
 
 // learn: 0 = only decide SAFE (the check call), 1 = learn and reduce.
 __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict__ jobs, int learn) {
-  __shared__ uint32_t s_n, s_races, s_first;
+  __shared__ uint32_t s_n, s_races, s_first, s_nbar;
   __shared__ uint32_t sm[CL_BLOCK / 64];
   __shared__ uint32_t keep[4096];   // bitset over up to 131072 clauses
   __shared__ rp_clause s_cl[CL_LDS];
-  __shared__ uint64_t s_bits[2][CL_BITS];   // barrier slot bits of each point (P <= CL_BITS)
+  // the barrier occurrences in program order (P <= CL_BITS): position,
+  // slot bit (any level, grid level), and for each point the index of the
+  // first occurrence at or after it
+  __shared__ uint16_t s_bpos[CL_BITS];
+  __shared__ uint64_t s_bbit[2][CL_BITS];
+  __shared__ uint16_t s_bnext[CL_BITS + 1];
   const Job& J = jobs[blockIdx.x];
   JobState* st = J.st;
   if (st->state != ST_RUN) return;
@@ -101,16 +123,39 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
     return;
   }
   if (!learn) return;
-  // the slot bits between i and its partner are ORed point by point: from
-  // LDS when the tables fit
+  // the slot bits between i and its partner are ORed over the barrier
+  // occurrences between them (listed in LDS when the tables fit), else point
+  // by point
   const bool lds_bits = P <= CL_BITS;
   if (lds_bits) {
-    for (uint32_t u = tid; u < P; u += CL_BLOCK) {
-      s_bits[0][u] = J.bits_any[u];
-      s_bits[1][u] = J.bits_grid[u];
+    const uint32_t u = tid;                         // P <= CL_BITS == CL_BLOCK
+    const uint64_t ba = u < P ? J.bits_any[u] : 0, bg = u < P ? J.bits_grid[u] : 0;
+    uint32_t nbar;
+    const uint32_t t = block_excl_scan1024(ba != 0, sm, &nbar);
+    if (u < P && ba) {
+      s_bpos[t] = (uint16_t)u;
+      s_bbit[0][t] = ba;
+      s_bbit[1][t] = bg;
+    }
+    if (u < P) s_bnext[u] = (uint16_t)t;
+    if (tid == 0) {
+      s_bnext[P] = (uint16_t)nbar;
+      s_nbar = nbar;
     }
     __syncthreads();
   }
+  const uint32_t nbar = lds_bits ? s_nbar : 0;
+  // slot bits of the barrier occurrences strictly between points i and j
+  auto between = [&](uint32_t lv, uint32_t i, uint32_t j) -> uint64_t {
+    uint64_t pos = 0;
+    if (lds_bits) {
+      for (uint32_t t = s_bnext[i + 1]; t < nbar && s_bpos[t] < j; t++) pos |= s_bbit[lv][t];
+    } else {
+      const uint64_t* bits = lv ? J.bits_grid : J.bits_any;
+      for (uint32_t u = i + 1; u < j; u++) pos |= bits[u];
+    }
+    return pos;
+  };
   // phi first, then the learned clauses: in LDS when they surely fit, else
   // in the job's scratch
   const uint32_t n_phi = st->n_phi;
@@ -127,10 +172,7 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
       } else {
         const uint32_t row = s_first;   // smallest (level, i)
         const uint32_t lv = row / P, i = row % P, j = J.minj[row];
-        const uint64_t* bits = lds_bits ? s_bits[lv] : (lv ? J.bits_grid : J.bits_any);
-        uint64_t pos = 0;
-        for (uint32_t u = i + 1; u < j; u++) pos |= bits[u];
-        c.pos = pos;
+        c.pos = between(lv, i, j);
         c.neg = 0;
       }
       sc[n_phi] = c;
@@ -141,9 +183,7 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
       const uint32_t j = J.minj[row];
       if (j == NONE32) continue;
       const uint32_t lv = row / P, i = row % P;
-      const uint64_t* bits = lds_bits ? s_bits[lv] : (lv ? J.bits_grid : J.bits_any);
-      uint64_t pos = 0;
-      for (uint32_t u = i + 1; u < j; u++) pos |= bits[u];
+      const uint64_t pos = between(lv, i, j);
       const uint32_t slot = atomicAdd(&s_n, 1u);
       rp_clause c;
       c.pos = pos;

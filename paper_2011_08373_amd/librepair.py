@@ -238,7 +238,7 @@ def clauses(km, x: int = 0, cap: int | None = None, ws=None, stream=None):
     if need == 0:
         return ERR_INVALID, []
     ptr, size = (ws or _ws).get(need)
-    cap = 4 * int(km.n_points) + 256 if cap is None else int(cap)
+    cap = 4 * len(ka.points) + 256 if cap is None else int(cap)
     buf = (RpClause * max(1, cap))()
     n = C.c_uint64(0)
     st = _L.rp_clauses(ka.ref, C.c_uint64(int(x)), buf if cap else None, cap, C.byref(n),

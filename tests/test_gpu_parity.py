@@ -185,6 +185,35 @@ def test_plain_large_full_size(L, name, mode):
     assert same_repair(g, o), (g, o)
 
 
+def _many_clause_kernel(seed, n_slots=64):
+    # one block of 64 threads, one shared array; groups of accesses (one
+    # write, or up to eight reads) separated by barrier slots, so every race
+    # has a slot between its points and no clause is empty: a few hundred
+    # learned clauses with many distinct slot sets, and the clause sort of
+    # the Verify round spans several waves of its workgroup
+    rng = np.random.default_rng(seed)
+    pts = []
+    for s in range(n_slots + 1):
+        if rng.random() < 0.4:
+            pts.append(dict(kind=0, is_write=1, a=1, c=int(rng.integers(-2, 3))))
+        else:
+            for _ in range(int(rng.integers(1, 9))):
+                pts.append(dict(kind=0, is_write=0, a=int(rng.integers(0, 2)),
+                                c=int(rng.integers(-2, 3))))
+        if s < n_slots:
+            pts.append(dict(kind=1, slot=s))
+    slots = [(0, 0, int(rng.integers(1, 4))) for _ in range(n_slots)]
+    return synth.make_kernel(1, 64, [(128, 0)], [(1, 0)], pts, slots)
+
+
+def test_clause_sort_many_clauses(L):
+    for seed in range(4):
+        km = _many_clause_kernel(seed)
+        rng = np.random.default_rng(100 + seed)
+        for x in [0] + [int(v) for v in rng.integers(0, 1 << 62, size=3)]:
+            assert L.clauses(km, x) == O.clauses(km, x), (seed, x)
+
+
 def test_edge_empty_and_degenerate(L):
     km = synth.make_kernel(1, 1, [], [(1, 0)], [], [])
     assert L.check(km, 0)[:4] == O.check(km, 0)
