@@ -60,12 +60,17 @@ def tune(kms, reps: int = 3, ws=None) -> dict:
         times = []
         for _ in range(reps):
             if batch:
-                L.repair_batch(kms, ws=ws)
+                ok = L.repair_batch(kms, ws=ws)[0] == 0
             else:
-                L.repair(kms, ws=ws)
+                ok = L.repair(kms, ws=ws)["ret"] in (L.OK, L.UNSAT)
+            if not ok:            # e.g. the workspace cannot hold this digit width
+                break
             s = L.last_stats()
             times.append(s["ms_sort"] + s["ms_gen"])
-        results.append((min(times), rb, shape, L.last_stats()["accesses"]))
+        if len(times) == reps:
+            results.append((min(times), rb, shape, L.last_stats()["accesses"]))
+    if not results:
+        raise RuntimeError("no sort configuration ran")
     results.sort()
     t, rb, shape, acc = results[0]
     data = _load()

@@ -135,10 +135,12 @@ class KernelArg:
         return C.byref(self.k)
 
     def need(self, op: int) -> int:
-        """Workspace bytes of op for this model (cached)."""
-        if op not in self._need:
-            self._need[op] = int(_L.rp_workspace_bytes(self.ref, int(op)))
-        return self._need[op]
+        """Workspace bytes of op for this model (cached while the sort
+        tuning, on which the size depends, is unchanged)."""
+        key = (int(op), _tuning_epoch[0])
+        if key not in self._need:
+            self._need[key] = int(_L.rp_workspace_bytes(self.ref, int(op)))
+        return self._need[key]
 
 
 def _arg(km):
@@ -404,5 +406,9 @@ def set_sort_digit_bits(bits: int) -> int:
     return _L.rp_set_sort_digit_bits(int(bits))
 
 
+_tuning_epoch = [0]      # bumped by every tuning change (workspace sizes depend on it)
+
+
 def set_tuning(knob: int, value: int) -> int:
+    _tuning_epoch[0] += 1
     return _L.rp_set_tuning(int(knob), int(value))
