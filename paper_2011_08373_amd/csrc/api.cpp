@@ -14,11 +14,16 @@ constexpr uint32_t TRAJ_CAP = 4096;
 extern int g_digit_bits_ref(int v, bool set);
 int scatter_variant(int v, bool set);
 
-static std::vector<rp_clause> option_units(const Plan& pl, const rp_repair_opts& o) {
+// The option units of the switches of Section 4.2 (Tab. 3): with grid-level
+// barriers disabled, the grid barriers that instrumentation adds (every grid
+// slot the program does not already hold) stay off; with inspection
+// disabled, pre-existing barriers stay on.  A pre-existing grid barrier is
+// the programmer's and follows the inspection switch alone.
+std::vector<rp_clause> option_units(const Plan& pl, const rp_repair_opts& o) {
   std::vector<rp_clause> u;
   for (uint32_t s = 0; s < pl.S; s++) {
     const uint64_t b = 1ull << s;
-    if (!o.grid && (pl.grid_slots & b)) u.push_back(rp_clause{0, b});
+    if (!o.grid && (pl.grid_slots & b) && !(pl.pre_slots & b)) u.push_back(rp_clause{0, b});
     if (!o.inspect && (pl.pre_slots & b)) u.push_back(rp_clause{b, 0});
   }
   std::sort(u.begin(), u.end(), [](const rp_clause& a, const rp_clause& b) {

@@ -23,6 +23,8 @@ int validate_kernel(const rp_kernel* k);
 void make_plan(const rp_kernel* k, Plan& pl);
 int pick_digit_bits(uint32_t key_bits);
 int sort_passes(uint32_t key_bits, int rb);
+// Unit clauses that the repair options impose before the first Solve.
+std::vector<rp_clause> option_units(const Plan& pl, const rp_repair_opts& o);
 
 enum Op { OP_CHECK = 0, OP_CLAUSES = 1, OP_REPAIR = 2, OP_SOLVE = 3, OP_FIRST = 4 };
 

@@ -153,18 +153,6 @@ static void fill_out(const SJob& j, const JobState& st, rp_repair_out& out) {
   }
 }
 
-static std::vector<rp_clause> server_units(const Plan& pl, const rp_repair_opts& o) {
-  std::vector<rp_clause> u;
-  for (uint32_t s = 0; s < pl.S; s++) {
-    const uint64_t b = 1ull << s;
-    if (!o.grid && (pl.grid_slots & b)) u.push_back(rp_clause{0, b});
-    if (!o.inspect && (pl.pre_slots & b)) u.push_back(rp_clause{b, 0});
-  }
-  std::sort(u.begin(), u.end(), [](const rp_clause& a, const rp_clause& b) {
-    return a.pos != b.pos ? a.pos < b.pos : a.neg < b.neg;
-  });
-  return u;
-}
 
 extern "C" {
 
@@ -214,7 +202,7 @@ rp_status rp_server_submit(void* srv, const rp_kernel* k, uint64_t job_id) {
   j->desc.take(k);
   make_plan(&j->desc.k, j->plan);
   j->input.plan = &j->plan;
-  j->input.phi0 = server_units(j->plan, sv->opts);
+  j->input.phi0 = option_units(j->plan, sv->opts);
   j->input.policy = sv->opts.policy;
   j->input.max_rounds = sv->opts.max_rounds;
   j->input.solver = sv->opts.solver;

@@ -198,6 +198,18 @@ def test_options_grid_and_inspect():
     assert r["status"] == 0 and r["assign"] == 3 and r["removed"] == 0
 
 
+def test_options_preexisting_grid_barrier():
+    # grid-level barriers disabled means no instrumented grid barrier (Section
+    # 2.2); a grid barrier the program already holds is the programmer's:
+    # kept when not inspected, and still a valid repair when inspected
+    km = kernel_from_json(load("grid_barrier_repair"))
+    km.slots["preexisting"][2] = 1
+    for grid, inspect, rounds in ((0, 0, 1), (1, 0, 1), (0, 1, 2), (1, 1, 2)):
+        r = O.repair(km, grid=grid, inspect=inspect)
+        assert (r["status"], r["assign"], r["rounds"]) == (0, 4, rounds), (grid, inspect, r)
+        assert r["added"] == 0 and r["removed"] == 0
+
+
 def test_max_rounds():
     km = kernel_from_json(load("listing1_race"))
     r = O.repair(km, max_rounds=1)
