@@ -7,15 +7,18 @@ points, 32 barrier slots (8 grid-level), two shared and two global arrays of
 1M int32 words.  The metric is race-checked accesses per second: every
 (point, block, thread) access is race-checked once per Verify call.
 
-More legs are reported beside the headline (same JSON line):
+More legs are reported beside the headline (same JSON line; --legs picks):
   planted  the same kernel with a planted safe barrier set (several Verify
            calls, ends SAFE);
   stress   4,096 blocks x 1,024 threads, 1,024 points, eight 16M-word arrays
-           (about 2.9G records, a 23 GB log): throughput and kernel
-           rooflines far outside the last-level cache;
+           (2.0G records after the reduction, a 16 GB log; 2.4G planted):
+           throughput and kernel rooflines far outside the last-level cache;
   batched  the 1,024-kernel batched workload (planted mode): repaired kernels
            per second of one rp_repair_batch call against the plain
            one-kernel-at-a-time rp_repair loop on the same kernels;
+  rounds   Verify calls per kernel over the batched kernels under each
+           learning policy (all traces / one trace per call) and Solve
+           strategy (exact / mhs), and with the option switches;
   served   Poisson arrivals (2,000 jobs/s by default) drawn from the same
            1,024 kernels into a continuous-batching server with a 64 GB
            arena: p50/p99 latency from submission to verdict, throughput.
@@ -62,6 +65,19 @@ def cpu_baseline(km, rounds_gpu):
                 matches_gpu_rounds=r["rounds"] == rounds_gpu)
 
 
+def model_accesses(km):
+    """(point, block, thread) accesses of a kernel model: the size class the
+    autotuner's cache is keyed by."""
+    total = 0
+    for p in km.points:
+        if int(p["kind"]) != 0:
+            continue
+        m, r = (int(v) for v in km.guards[int(p["guard"])])
+        if r < km.threads:
+            total += (km.threads - r + m - 1) // m
+    return total * km.blocks
+
+
 def apply_tuning(L, n_accesses):
     """The autotuner's sort configuration for this size class, else the
     library's defaults (automatic digit width, 512 x 8 scatter tiles)."""
@@ -80,10 +96,7 @@ def run_main(L, torch, km, steps, warmup):
     with the autotuner's sort configuration for its size class."""
     ws = L.Workspace()
     ka = L.KernelArg(km)          # the C view of the descriptors, built once
-    apply_tuning(L, 0)
-    ws.get(L.workspace_bytes(ka, L.OP_REPAIR))
-    L.repair(ka, ws=ws)           # untimed: the access count picks the size class
-    sort_cfg = apply_tuning(L, L.last_stats()["accesses"])
+    sort_cfg = apply_tuning(L, model_accesses(km))
     ws.get(L.workspace_bytes(ka, L.OP_REPAIR))
     for _ in range(warmup):
         L.repair(ka, ws=ws)
@@ -152,7 +165,7 @@ def kernel_rooflines(stats, traffic_prefix=""):
 
 def stress_leg(L, torch, steps):
     """The stress kernel (4,096 blocks x 1,024 threads, 1,024 points, eight
-    16M-word arrays): a log of about 23 GB, far beyond the 256 MB last-level
+    16M-word arrays): a log of 16-20 GB, far beyond the 256 MB last-level
     cache, so the kernel rooflines here are HBM figures."""
     from paper_2011_08373_amd import synth
     out = {}
@@ -215,6 +228,45 @@ def batched_leg(L, torch, kms):
             "autotuned": tuned}
 
 
+def rounds_leg(L, torch, kms):
+    """Verify calls per kernel of the repair loop under each learning policy
+    and Solve strategy (and the paper's option switches), over the batched
+    kernels in one rp_repair_batch call each.  Policy and strategy change
+    only the route: the repaired barrier sets must equal the exact,
+    all-traces ones."""
+    b = L.BatchArg(kms)
+    ws = L.Workspace()
+    configs = [
+        ("exact solve, all traces", dict(policy=0, solver=0)),
+        ("mhs, all traces", dict(policy=0, solver=1)),
+        ("exact solve, one trace", dict(policy=1, solver=0)),
+        ("mhs, one trace", dict(policy=1, solver=1)),
+        ("mhs, one trace, no grid barriers", dict(policy=1, solver=1, grid=0)),
+        ("mhs, one trace, pre-existing barriers kept", dict(policy=1, solver=1, inspect=0)),
+        ("mhs, one trace, both", dict(policy=1, solver=1, grid=0, inspect=0)),
+    ]
+    out, base = {}, None
+    for name, kw in configs:
+        L.repair_batch(b, ws=ws, **kw)                 # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, res = L.repair_batch(b, ws=ws, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        calls = sorted(r["rounds"] for r in res)
+        got = [(r["status"], r["assign"]) for r in res]
+        if base is None:
+            base = got
+        e = {"verify_calls": sum(calls), "per_kernel_mean": sum(calls) / len(calls),
+             "per_kernel_median": calls[len(calls) // 2], "per_kernel_max": calls[-1],
+             "repaired": sum(1 for r in res if r["status"] == 0), "ms": dt * 1e3,
+             "status": st}
+        if "grid" not in kw and "inspect" not in kw:
+            e["same_result_as_exact_all"] = got == base
+        out[name] = e
+    return out
+
+
 def served_leg(L, torch, kms, rate, seconds, arena_gb):
     """Poisson arrivals into the continuous-batching server."""
     from paper_2011_08373_amd import synth
@@ -263,7 +315,7 @@ def main():
     ap.add_argument("--config", default="plain-large", choices=("plain-large", "stress"),
                     help="kernel of the headline leg (the stress kernel for profiling runs)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--legs", default="main,planted,stress,batched,served")
+    ap.add_argument("--legs", default="main,planted,stress,batched,rounds,served")
     ap.add_argument("--stress-steps", type=int, default=3)
     ap.add_argument("--batched-n", type=int, default=1024)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -345,10 +397,12 @@ def main():
     torch.cuda.empty_cache()
     if "stress" in legs:
         out["stress"] = stress_leg(L, torch, args.stress_steps)
-    if "batched" in legs or "served" in legs:
+    if "batched" in legs or "served" in legs or "rounds" in legs:
         kms = synth.generate_batch(n=args.batched_n, mode="planted")
         if "batched" in legs:
             out["batched"] = batched_leg(L, torch, kms)
+        if "rounds" in legs:
+            out["rounds"] = rounds_leg(L, torch, kms)
         if "served" in legs:
             out["served"] = served_leg(L, torch, kms, args.serve_rate, args.serve_seconds,
                                        args.serve_arena_gb)
