@@ -683,14 +683,13 @@ extern "C" int or_repair(const or_kernel* k, const or_opts* o, or_result* out,
     w[s] = k->slots[s].weight;
     if (k->slots[s].preexisting) pre |= 1ull << s;
   }
-  // phi := true, plus the option units: with grid-level barriers disabled
-  // the instrumented grid barriers (grid slots the program does not already
-  // hold) stay off; with inspection disabled the pre-existing barriers stay
-  // on (Section 2.2 adds grid barriers only when their instrumentation is
-  // enabled; Section 4.2 and Tab. 3 name both switches)
+  // phi := true, plus the option units of Section 4.2 (Tab. 3): with
+  // grid-level barriers disabled every grid slot is off; with inspection
+  // disabled every pre-existing barrier is on (a pre-existing grid barrier
+  // under both switches makes the first Solve UNSAT)
   std::vector<or_clause> phi;
   for (u32 s = 0; s < k->n_slots; s++) {
-    if (!opt.grid && k->slots[s].level == GRID && !k->slots[s].preexisting) phi.push_back({0, 1ull << s});
+    if (!opt.grid && k->slots[s].level == GRID) phi.push_back({0, 1ull << s});
     if (!opt.inspect && k->slots[s].preexisting) phi.push_back({1ull << s, 0});
   }
   phi = reduce(phi);

@@ -15,15 +15,15 @@ extern int g_digit_bits_ref(int v, bool set);
 int scatter_variant(int v, bool set);
 
 // The option units of the switches of Section 4.2 (Tab. 3): with grid-level
-// barriers disabled, the grid barriers that instrumentation adds (every grid
-// slot the program does not already hold) stay off; with inspection
-// disabled, pre-existing barriers stay on.  A pre-existing grid barrier is
-// the programmer's and follows the inspection switch alone.
+// barriers disabled every grid slot stays off; with inspection disabled every
+// pre-existing barrier stays on.  A pre-existing grid barrier under both
+// switches is forced both ways, so such a repair is UNSAT at its first Solve,
+// before any Verify call (Alg. 1 solves first).
 std::vector<rp_clause> option_units(const Plan& pl, const rp_repair_opts& o) {
   std::vector<rp_clause> u;
   for (uint32_t s = 0; s < pl.S; s++) {
     const uint64_t b = 1ull << s;
-    if (!o.grid && (pl.grid_slots & b) && !(pl.pre_slots & b)) u.push_back(rp_clause{0, b});
+    if (!o.grid && (pl.grid_slots & b)) u.push_back(rp_clause{0, b});
     if (!o.inspect && (pl.pre_slots & b)) u.push_back(rp_clause{b, 0});
   }
   std::sort(u.begin(), u.end(), [](const rp_clause& a, const rp_clause& b) {
