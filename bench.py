@@ -21,7 +21,11 @@ More legs are reported beside the headline (same JSON line; --legs picks):
            strategy (exact / mhs), and with the option switches;
   served   Poisson arrivals (2,000 jobs/s by default) drawn from the same
            1,024 kernels into a continuous-batching server with a 64 GB
-           arena: p50/p99 latency from submission to verdict, throughput.
+           arena: p50/p99 latency from submission to verdict, throughput;
+  instrumented  1,024 small structured programs (branches, loops, calls,
+           pre-existing barriers) through the library's instrumentation pass
+           and one rp_repair_batch call: host microseconds per program,
+           kernels per second, Verify calls per kernel.
 
 Prints one JSON line.  Inputs are synthetic and seeded; device buffers are
 resident before the timed region starts.
@@ -267,6 +271,41 @@ def rounds_leg(L, torch, kms):
     return out
 
 
+def instrumented_leg(L, torch, n, seed=11):
+    """Structured programs through rp_instrument, then one batched repair
+    under the default strategy and under the paper's (mhs, one trace)."""
+    from paper_2011_08373_amd import synth
+    progs = synth.generate_programs(n, seed=seed)
+    out = {"workload": "instrumented: %d random structured programs (1-4 blocks x 32-128 "
+                       "threads, nested branches, loops of 2-4 trips, calls, pre-existing "
+                       "barriers), grid-level instrumentation on, seed %d" % (n, seed)}
+    L.instrument(progs[0])
+    t = time.perf_counter()
+    inst = [L.instrument(p) for p in progs]
+    ti = time.perf_counter() - t
+    kms = [k for st, k in inst if st == 0]
+    out["instrument_us_per_program"] = ti / n * 1e6
+    out["instrumented"] = len(kms)
+    out["slots_mean"] = sum(k.n_slots for k in kms) / max(1, len(kms))
+    out["points_mean"] = sum(k.n_points for k in kms) / max(1, len(kms))
+    b = L.BatchArg(kms)
+    ws = L.Workspace()
+    for name, kw in (("exact solve, all traces", {}), ("mhs, one trace", dict(policy=1, solver=1))):
+        L.repair_batch(b, ws=ws, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, res = L.repair_batch(b, ws=ws, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        calls = sorted(r["rounds"] for r in res)
+        out[name] = {"kernels_per_s": len(kms) / dt, "ms": dt * 1e3, "status": st,
+                     "repaired": sum(1 for r in res if r["status"] == 0),
+                     "unsat": sum(1 for r in res if r["status"] == 1),
+                     "verify_calls_per_kernel": sum(calls) / max(1, len(calls)),
+                     "verify_calls_max": calls[-1] if calls else 0}
+    return out
+
+
 def served_leg(L, torch, kms, rate, seconds, arena_gb):
     """Poisson arrivals into the continuous-batching server."""
     from paper_2011_08373_amd import synth
@@ -315,7 +354,7 @@ def main():
     ap.add_argument("--config", default="plain-large", choices=("plain-large", "stress"),
                     help="kernel of the headline leg (the stress kernel for profiling runs)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--legs", default="main,planted,stress,batched,rounds,served")
+    ap.add_argument("--legs", default="main,planted,stress,batched,rounds,served,instrumented")
     ap.add_argument("--stress-steps", type=int, default=3)
     ap.add_argument("--batched-n", type=int, default=1024)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -406,6 +445,8 @@ def main():
         if "served" in legs:
             out["served"] = served_leg(L, torch, kms, args.serve_rate, args.serve_seconds,
                                        args.serve_arena_gb)
+    if "instrumented" in legs:
+        out["instrumented"] = instrumented_leg(L, torch, args.batched_n)
     print(json.dumps(out))
 
 

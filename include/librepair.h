@@ -230,6 +230,76 @@ rp_status rp_server_poll(void* server, uint64_t* job_ids, rp_repair_out* outs,
                          double* latency_s, uint32_t cap, uint32_t* n_done);
 rp_status rp_server_destroy(void* server);
 
+/* Instrumentation (Section 2.2) of a structured program into the kernel
+ * model above.
+ *
+ * Program: `functions[0]` is the kernel, the others are device functions it
+ * may call.  Each function is a statement list in which IF and LOOP open a
+ * region that a matching END closes:
+ *   ACCESS   reads (is_write 0) or writes `array` at word
+ *            (a*tid + b*bid + c + d*it) mod words, it = iteration of the
+ *            innermost enclosing loop at run time (0 outside every loop);
+ *   BARRIER  a pre-existing barrier of `level` (RP_BLOCK or RP_GRID);
+ *   IF       body runs on the threads with tid % guards[guard].m ==
+ *            guards[guard].r (a thread-dependent branch; guard {1, 0} is a
+ *            uniform one) -- nested branches take the conjunction;
+ *   LOOP     body runs `count` >= 1 times (a uniform trip count);
+ *   CALL     runs function `count` (1 <= count < n_functions; no recursion).
+ *
+ * Instrumented barriers (barrier variables) are placed in the kernel body
+ * only: before every ACCESS, before every IF (outside the branch, at its
+ * entry point), at the head of every LOOP (first in each iteration) and
+ * before every CALL of a function that reaches an ACCESS -- the places
+ * Section 2.2 names and its example kernel shows (a callee gets no sites of
+ * its own).  Each place gets a BLOCK variable and, when opts->grid is 1, a
+ * GRID variable right after it.  Every pre-existing barrier becomes a
+ * variable of its own level with `preexisting` = 1; one inside a device
+ * function gets one variable per chain of call sites.  Loops are unrolled
+ * and calls inlined: the copies of one place are occurrences of one
+ * variable.  Weight of a variable: gw*gb + lw^ld (Section 2.4; gb = 1 for
+ * GRID, ld = number of enclosing loops, callers' included).
+ *
+ * Output order: points in execution order; slots numbered by first
+ * occurrence; guards numbered by first use, guard 0 = {1, 0}.  The kernel
+ * model is then `{blocks, threads, n_arrays, n_guards, n_points, n_slots,
+ * arrays, guards, points, slots}` with the program's blocks, threads and
+ * arrays.  Output arrays are caller-owned host memory; the needed counts
+ * are always written on RP_OK and RP_ERR_CAPACITY (then nothing else is).
+ * RP_ERR_INVALID: malformed program (unbalanced regions, an index out of
+ * range, recursion, a branch whose conjunction with the enclosing one holds
+ * for no thread or needs a modulus >= 2^32, a weight or word offset that
+ * overflows) or a model beyond the limits (64 slots, 4096 points).
+ * Host-only: no device work, no stream. */
+enum { RP_S_ACCESS = 0, RP_S_BARRIER = 1, RP_S_IF = 2, RP_S_LOOP = 3, RP_S_CALL = 4,
+       RP_S_END = 5 };
+typedef struct {
+  uint8_t kind;       /* RP_S_* */
+  uint8_t is_write;   /* ACCESS */
+  uint8_t level;      /* BARRIER */
+  uint8_t pad;
+  uint16_t array;     /* ACCESS */
+  uint16_t guard;     /* IF */
+  uint32_t count;     /* LOOP: trip count; CALL: callee */
+  int32_t a, b, c, d; /* ACCESS */
+} rp_stmt;                                                               /* 28 B */
+typedef struct { uint32_t n_stmts; const rp_stmt* stmts; } rp_function;
+typedef struct {
+  uint32_t blocks, threads, n_arrays, n_guards, n_functions;
+  const rp_array* arrays;
+  const rp_guard* guards;
+  const rp_function* functions;
+} rp_program;
+typedef struct {
+  uint8_t grid;       /* 1: GRID variables beside the BLOCK ones (CUDA's
+                         grid-level barriers); 0: BLOCK only */
+  uint8_t pad[3];
+  uint32_t gw, lw;    /* weight parameters; the paper's defaults are 12, 10 */
+} rp_instrument_opts;
+rp_status rp_instrument(const rp_program* prog, const rp_instrument_opts* opts,
+                        rp_guard* guards, uint32_t guards_cap, uint32_t* n_guards,
+                        rp_point* points, uint32_t points_cap, uint32_t* n_points,
+                        rp_slot* slots, uint32_t slots_cap, uint32_t* n_slots);
+
 /* Statistics of the last call made on this thread. */
 void rp_last_stats(rp_stats* out);
 

@@ -59,6 +59,26 @@ class RpStats(C.Structure):
                 ("ms_upload", C.c_double), ("ms_conf_kernels", C.c_double)]
 
 
+class RpFunction(C.Structure):
+    _fields_ = [("n_stmts", C.c_uint32), ("stmts", C.c_void_p)]
+
+
+class RpProgram(C.Structure):
+    _fields_ = [("blocks", C.c_uint32), ("threads", C.c_uint32), ("n_arrays", C.c_uint32),
+                ("n_guards", C.c_uint32), ("n_functions", C.c_uint32),
+                ("arrays", C.c_void_p), ("guards", C.c_void_p), ("functions", C.c_void_p)]
+
+
+class RpInstrumentOpts(C.Structure):
+    _fields_ = [("grid", C.c_uint8), ("pad", C.c_uint8 * 3), ("gw", C.c_uint32),
+                ("lw", C.c_uint32)]
+
+
+STMT_DT = np.dtype([("kind", "u1"), ("is_write", "u1"), ("level", "u1"), ("pad", "u1"),
+                    ("array", "<u2"), ("guard", "<u2"), ("count", "<u4"), ("a", "<i4"),
+                    ("b", "<i4"), ("c", "<i4"), ("d", "<i4")], align=True)
+assert STMT_DT.itemsize == 28
+
 PAIR_DT = np.dtype([("i", "<u2"), ("j", "<u2"), ("level", "u1"), ("pad", "u1")])
 assert PAIR_DT.itemsize == 6
 
@@ -100,6 +120,10 @@ _L.rp_last_stats.argtypes = [C.POINTER(RpStats)]
 _L.rp_last_stats.restype = None
 _L.rp_set_sort_digit_bits.argtypes = [C.c_int]
 _L.rp_set_tuning.argtypes = [C.c_int, C.c_int]
+_u32p = C.POINTER(C.c_uint32)
+_L.rp_instrument.argtypes = [C.POINTER(RpProgram), C.POINTER(RpInstrumentOpts),
+                             C.c_void_p, C.c_uint32, _u32p, C.c_void_p, C.c_uint32, _u32p,
+                             C.c_void_p, C.c_uint32, _u32p]
 TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE = 0, 1
 
 
@@ -412,3 +436,46 @@ _tuning_epoch = [0]      # bumped by every tuning change (workspace sizes depend
 def set_tuning(knob: int, value: int) -> int:
     _tuning_epoch[0] += 1
     return _L.rp_set_tuning(int(knob), int(value))
+
+
+def instrument(prog, grid: int = 1, gw: int = 12, lw: int = 10):
+    """rp_instrument on a ``synth.Program``: (status, Kernel or None)."""
+    from . import synth
+    arrays = np.zeros(len(prog.arrays), synth.ARRAY_DT)
+    for n, (w, sp) in enumerate(prog.arrays):
+        arrays[n] = (w, sp)
+    guards = np.zeros(len(prog.guards), synth.GUARD_DT)
+    for n, (m, r) in enumerate(prog.guards):
+        guards[n] = (m, r)
+    bodies = []
+    for fn in prog.functions:
+        b = np.zeros(len(fn), STMT_DT)
+        for n, st in enumerate(fn):
+            b[n] = (st["kind"], st.get("is_write", 0), st.get("level", 0), 0,
+                    st.get("array", 0), st.get("guard", 0), st.get("count", 0),
+                    st.get("a", 0), st.get("b", 0), st.get("c", 0), st.get("d", 0))
+        bodies.append(b)
+    fns = (RpFunction * max(1, len(bodies)))()
+    for n, b in enumerate(bodies):
+        fns[n].n_stmts = len(b)
+        fns[n].stmts = b.ctypes.data if len(b) else None
+    pr = RpProgram(prog.blocks, prog.threads, len(arrays), len(guards), len(bodies),
+                   arrays.ctypes.data if len(arrays) else None,
+                   guards.ctypes.data if len(guards) else None, C.addressof(fns))
+    o = RpInstrumentOpts()
+    o.grid, o.gw, o.lw = grid, gw, lw
+    ng, npt, ns = C.c_uint32(0), C.c_uint32(0), C.c_uint32(0)
+    st = _L.rp_instrument(C.byref(pr), C.byref(o), None, 0, C.byref(ng), None, 0,
+                          C.byref(npt), None, 0, C.byref(ns))
+    if st != ERR_CAPACITY:
+        return st, None
+    g = np.zeros(ng.value, synth.GUARD_DT)
+    pt = np.zeros(npt.value, synth.POINT_DT)
+    sl = np.zeros(ns.value, synth.SLOT_DT)
+    st = _L.rp_instrument(C.byref(pr), C.byref(o), g.ctypes.data, len(g), C.byref(ng),
+                          pt.ctypes.data, len(pt), C.byref(npt), sl.ctypes.data, len(sl),
+                          C.byref(ns))
+    if st != OK:
+        return st, None
+    return st, synth.Kernel(prog.blocks, prog.threads, arrays, g, pt, sl,
+                            dict(prog.meta, instrumented=True, grid=grid))

@@ -27,6 +27,8 @@ Two modes:
 from __future__ import annotations
 
 from dataclasses import dataclass, field
+import math
+
 import numpy as np
 
 ACCESS, BARRIER, NOP = 0, 1, 2
@@ -406,3 +408,141 @@ def poisson_arrivals(rate: float, duration: float, seed: int = 4) -> np.ndarray:
     n = int(rate * duration * 1.5) + 16
     t = np.cumsum(rng.exponential(1.0 / rate, size=n))
     return t[t < duration]
+
+
+# ---------------------------------------------------------------------------
+# Structured programs (the input of the instrumentation pass, Section 2.2)
+# ---------------------------------------------------------------------------
+
+S_ACCESS, S_BARRIER, S_IF, S_LOOP, S_CALL, S_END = 0, 1, 2, 3, 4, 5
+
+
+@dataclass
+class Program:
+    """A structured kernel: ``functions[0]`` is the kernel body, the others
+    are device functions.  A function is a list of statement dicts in which
+    S_IF (``guard``: index into ``guards``) and S_LOOP (``count`` trips) open
+    a region that S_END closes; S_ACCESS has ``array``, ``is_write``, ``a``,
+    ``b``, ``c``, ``d``; S_BARRIER (pre-existing) has ``level``; S_CALL has
+    ``count`` = callee index."""
+    blocks: int
+    threads: int
+    arrays: list
+    guards: list
+    functions: list
+    meta: dict = field(default_factory=dict)
+
+
+def st_access(array, is_write, a=1, b=0, c=0, d=0):
+    return dict(kind=S_ACCESS, array=array, is_write=int(is_write), a=a, b=b, c=c, d=d)
+
+
+def st_barrier(level=BLOCK):
+    return dict(kind=S_BARRIER, level=level)
+
+
+def st_if(guard):
+    return dict(kind=S_IF, guard=guard)
+
+
+def st_loop(count):
+    return dict(kind=S_LOOP, count=count)
+
+
+def st_call(callee):
+    return dict(kind=S_CALL, count=callee)
+
+
+def st_end():
+    return dict(kind=S_END)
+
+
+def random_program(rng, max_sites: int = 20, max_pre: int = 6) -> Program:
+    """A small random structured kernel: nested branches (thread-parity
+    conditions), uniform loops with loop-variable address terms, calls of
+    device functions and pre-existing barriers.  ``max_sites`` bounds the
+    statements of the kernel body that take an instrumented barrier
+    (accesses, branches, loops, calls); ``max_pre`` the pre-existing ones."""
+    B = int(rng.choice([1, 2, 4]))
+    T = int(rng.choice([32, 64, 128]))
+    n_arr = int(rng.integers(1, 4))
+    arrays = []
+    for _ in range(n_arr):
+        space = int(rng.integers(0, 2))
+        words = T * (B if space == GLOBAL else 1) * int(rng.choice([1, 2]))
+        arrays.append((words, space))
+    guards = [(1, 0), (2, 0), (2, 1)]
+    for m in (3, 4):
+        guards.append((m, int(rng.integers(0, m))))
+    state = dict(sites=0, pre=0)
+
+    def access():
+        arr = int(rng.integers(0, n_arr))
+        w = bool(rng.random() < 0.4)
+        a = int(rng.choice([1, 1, 1, -1, 2])) if w else int(rng.choice([1, 1, -1, 0, 2]))
+        b = T if arrays[arr][1] == GLOBAL and (w or rng.random() < 0.7) else 0
+        c = int(rng.integers(-2, 3))
+        d = int(rng.choice([0, 0, 1, 2]))
+        return st_access(arr, w, a, b, c, d)
+
+    def pre_barrier():
+        state["pre"] += 1
+        lv = GRID if B > 1 and rng.random() < 0.25 else BLOCK
+        return st_barrier(lv)
+
+    n_dev = int(rng.integers(0, 3))
+    functions = [None]
+    for _ in range(n_dev):
+        body = []
+        for _ in range(int(rng.integers(1, 4))):
+            r = rng.random()
+            if r < 0.15 and state["pre"] < max_pre:
+                body.append(pre_barrier())
+            elif r < 0.3:
+                body += [st_loop(int(rng.integers(2, 4))), access(), st_end()]
+            else:
+                body.append(access())
+        functions.append(body)
+
+    def block(depth, n, outer):
+        out = []
+        for _ in range(n):
+            if state["sites"] >= max_sites:
+                break
+            r = rng.random()
+            if r < 0.12 and state["pre"] < max_pre:
+                out.append(pre_barrier())
+                continue
+            state["sites"] += 1
+            if r < 0.24 and depth < 2:
+                # nested conditions: the enclosing one again, or one whose
+                # modulus is coprime with it, so some thread takes both
+                cand = [g for g in range(len(guards))
+                        if g == outer or math.gcd(guards[g][0], guards[outer][0]) == 1]
+                g = int(rng.choice(cand))
+                out.append(st_if(g))
+                out += block(depth + 1, int(rng.integers(1, 4)), g if g else outer)
+                out.append(st_end())
+            elif r < 0.34 and depth < 2:
+                out.append(st_loop(int(rng.integers(2, 5))))
+                out += block(depth + 1, int(rng.integers(1, 4)), outer)
+                out.append(st_end())
+            elif r < 0.44 and n_dev:
+                out.append(st_call(int(rng.integers(1, n_dev + 1))))
+            else:
+                out.append(access())
+        return out
+
+    functions[0] = block(0, int(rng.integers(3, 9)), 0)
+    return Program(B, T, arrays, guards, functions)
+
+
+def generate_programs(n: int, seed: int = 11, **kw) -> list:
+    """Programs of the instrumented workload; program i uses
+    SeedSequence(seed).spawn(n)[i]."""
+    out = []
+    for i, child in enumerate(np.random.SeedSequence(seed).spawn(n)):
+        p = random_program(np.random.default_rng(child), **kw)
+        p.meta.update(seed=seed, index=i)
+        out.append(p)
+    return out
