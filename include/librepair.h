@@ -19,7 +19,10 @@
  *     barrier slot `slot` (barrier variable b_slot, Section 2.2); unrolled
  *     copies of one instrumented barrier share the slot.  NOP does nothing;
  *   - every ACCESS and BARRIER is executed by the threads with
- *     tid % guards[guard].m == guards[guard].r (guard {1,0}: all threads);
+ *     tid % guards[guard].m == guards[guard].r (guard {1,0}: all threads)
+ *     of the blocks with bid % block_guards[guard].m ==
+ *     block_guards[guard].r (block_guards NULL: every block) -- a branch
+ *     on blockIdx;
  *   - slots: level BLOCK (orders the threads of one block) or GRID (orders
  *     every pair of threads, Section 2.2), a pre-existing flag (the
  *     programmer's barrier, which the paper also guards so that it may be
@@ -31,8 +34,11 @@
  *     (Section 1); a same-block pair races unless an enabled barrier of any
  *     level occurs strictly between the two points; a pair from different
  *     blocks (GLOBAL arrays only) races unless an enabled GRID barrier does;
- *   - an enabled barrier diverges when some block has 0 < n < threads of its
- *     threads executing it (Section 1, Listing 2);
+ *   - an enabled BLOCK barrier diverges when some block has 0 < n < threads
+ *     of its threads executing it (Section 1, Listing 2); an enabled GRID
+ *     barrier diverges when 0 < n < blocks*threads threads of the grid
+ *     execute it (a grid barrier must be reached by the whole grid; with
+ *     thread-only conditions the two rules agree);
  *   - a race between points i <= j yields the positive clause of the slots
  *     strictly between them (GRID slots only for a cross-block race); a
  *     divergent slot s yields the negative unit {not b_s} (Section 2.4);
@@ -96,6 +102,7 @@ typedef struct {
   const rp_guard* guards;
   const rp_point* points;
   const rp_slot* slots;
+  const rp_guard* block_guards;   /* NULL or [n_guards]: block condition of each guard */
 } rp_kernel;
 
 /* clause: satisfied by x iff (x & pos) != 0 or (~x & neg) != 0 */
@@ -241,8 +248,10 @@ rp_status rp_server_destroy(void* server);
  *            innermost enclosing loop at run time (0 outside every loop);
  *   BARRIER  a pre-existing barrier of `level` (RP_BLOCK or RP_GRID);
  *   IF       body runs on the threads with tid % guards[guard].m ==
- *            guards[guard].r (a thread-dependent branch; guard {1, 0} is a
- *            uniform one) -- nested branches take the conjunction;
+ *            guards[guard].r of the blocks with bid % block_guards[guard].m
+ *            == block_guards[guard].r (block_guards NULL: every block; a
+ *            guard of {1, 0} and {1, 0} is a uniform branch) -- nested
+ *            branches take the conjunction of both parts;
  *   LOOP     body runs `count` >= 1 times (a uniform trip count);
  *   CALL     runs function `count` (1 <= count < n_functions; no recursion).
  *
@@ -260,10 +269,11 @@ rp_status rp_server_destroy(void* server);
  * GRID, ld = number of enclosing loops, callers' included).
  *
  * Output order: points in execution order; slots numbered by first
- * occurrence; guards numbered by first use, guard 0 = {1, 0}.  The kernel
- * model is then `{blocks, threads, n_arrays, n_guards, n_points, n_slots,
- * arrays, guards, points, slots}` with the program's blocks, threads and
- * arrays.  Output arrays are caller-owned host memory; the needed counts
+ * occurrence; guards (a thread part in guards[], a block part in
+ * block_guards[]) numbered by first use, guard 0 = {1, 0} and {1, 0}.  The
+ * kernel model is then `{blocks, threads, n_arrays, n_guards, n_points,
+ * n_slots, arrays, guards, points, slots, block_guards}` with the program's
+ * blocks, threads and arrays.  Output arrays are caller-owned host memory; the needed counts
  * are always written on RP_OK and RP_ERR_CAPACITY (then nothing else is).
  * RP_ERR_INVALID: malformed program (unbalanced regions, an index out of
  * range, recursion, a branch whose conjunction with the enclosing one holds
@@ -288,6 +298,7 @@ typedef struct {
   const rp_array* arrays;
   const rp_guard* guards;
   const rp_function* functions;
+  const rp_guard* block_guards;   /* NULL or [n_guards] */
 } rp_program;
 typedef struct {
   uint8_t grid;       /* 1: GRID variables beside the BLOCK ones (CUDA's
@@ -296,7 +307,8 @@ typedef struct {
   uint32_t gw, lw;    /* weight parameters; the paper's defaults are 12, 10 */
 } rp_instrument_opts;
 rp_status rp_instrument(const rp_program* prog, const rp_instrument_opts* opts,
-                        rp_guard* guards, uint32_t guards_cap, uint32_t* n_guards,
+                        rp_guard* guards, rp_guard* block_guards, uint32_t guards_cap,
+                        uint32_t* n_guards,
                         rp_point* points, uint32_t points_cap, uint32_t* n_points,
                         rp_slot* slots, uint32_t slots_cap, uint32_t* n_slots);
 

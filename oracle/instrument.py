@@ -16,6 +16,8 @@ The paper's rules, as this model takes them:
   * pre-existing barriers are guarded by barrier variables too, so that the
     repair may remove them;
   * weights (Section 2.4): gw*gb + lw^ld.
+A branch condition has a thread part and a block part (each tid or bid
+mod m == r); nested branches meet part by part.
 Sites go into the kernel body only (the example kernel has none inside the
 called function).  Loops are unrolled and calls inlined; a site's copies
 share its variable.
@@ -94,7 +96,11 @@ def _instrument(prog, grid, gw, lw):
     for w, sp in prog.arrays:
         if w < 1 or sp not in (0, 1):
             raise Invalid("array")
-    for m, r in prog.guards:
+    bguards = prog.block_guards if getattr(prog, "block_guards", None) is not None \
+        else [(1, 0)] * len(prog.guards)
+    if len(bguards) != len(prog.guards):
+        raise Invalid("block conditions")
+    for m, r in list(prog.guards) + list(bguards):
         if m < 1 or not 0 <= r < m:
             raise Invalid("guard")
     F = len(prog.functions)
@@ -136,7 +142,8 @@ def _instrument(prog, grid, gw, lw):
     for f in range(F):
         touches(f, frozenset())
 
-    guards = [(1, 0)]
+    # a condition is a pair: (thread residue class, block residue class)
+    guards = [((1, 0), (1, 0))]
     points = []
     slots = []
     slot_ids = {}
@@ -183,10 +190,11 @@ def _instrument(prog, grid, gw, lw):
             elif kind == IF_S:
                 if f == 0:
                     emit_site(path, f, idx, g, depth)
-                inner = residue_meet(g, tuple(prog.guards[st["guard"]]))
-                if inner is None:
+                inner_t = residue_meet(g[0], tuple(prog.guards[st["guard"]]))
+                inner_b = residue_meet(g[1], tuple(bguards[st["guard"]]))
+                if inner_t is None or inner_b is None:
                     raise Invalid("no thread takes the branch")
-                run(body, f, path, inner, depth, it)
+                run(body, f, path, (inner_t, inner_b), depth, it)
             elif kind == LOOP_S:
                 for i in range(st["count"]):
                     if f == 0:
@@ -200,6 +208,8 @@ def _instrument(prog, grid, gw, lw):
                 run(trees[callee], callee, path + ((f, idx),), g, depth, it)
         check_size()
 
-    run(trees[0], 0, (), (1, 0), 0, 0)
-    return synth.make_kernel(prog.blocks, prog.threads, prog.arrays, guards, points, slots,
-                             dict(prog.meta, instrumented=True, grid=grid))
+    run(trees[0], 0, (), ((1, 0), (1, 0)), 0, 0)
+    block_part = [b for _, b in guards]
+    return synth.make_kernel(prog.blocks, prog.threads, prog.arrays, [t for t, _ in guards],
+                             points, slots, dict(prog.meta, instrumented=True, grid=grid),
+                             block_part if any(m > 1 for m, _ in block_part) else None)

@@ -11,7 +11,7 @@
  *   - data race: two threads touch one location, at least one writes, with
  *     no barrier in between (Section 1, Listing 1);
  *   - barrier divergence: a barrier reached by only part of a block
- *     (Section 1, Listing 2);
+ *     (Section 1, Listing 2), a grid-level one by only part of the grid;
  *   - a block-level barrier orders threads of one block, a grid-level
  *     barrier orders every pair of threads (Section 1; Section 2.2);
  *   - instrumented barriers guarded by barrier variables, pre-existing
@@ -60,8 +60,12 @@ int validate(const or_kernel* k) {
     return OR_ERR_INVALID;
   for (u32 a = 0; a < k->n_arrays; a++)
     if (k->arrays[a].words < 1 || k->arrays[a].space > 1) return OR_ERR_INVALID;
-  for (u32 g = 0; g < k->n_guards; g++)
+  for (u32 g = 0; g < k->n_guards; g++) {
     if (k->guards[g].m < 1 || k->guards[g].r >= k->guards[g].m) return OR_ERR_INVALID;
+    if (k->block_guards &&
+        (k->block_guards[g].m < 1 || k->block_guards[g].r >= k->block_guards[g].m))
+      return OR_ERR_INVALID;
+  }
   for (u32 s = 0; s < k->n_slots; s++)
     if (k->slots[s].level > 1 || k->slots[s].preexisting > 1 || k->slots[s].weight < 1)
       return OR_ERR_INVALID;
@@ -90,9 +94,12 @@ int validate(const or_kernel* k) {
 }
 
 // ------------------------------------------------------------ model helpers
-bool active(const or_kernel* k, u32 i, u32 t) {
-  const or_guard& g = k->guards[k->points[i].guard];
-  return t % g.m == g.r;
+// Thread t of block blk executes point i: its guard holds for the thread
+// id and, when the kernel has block conditions, for the block id.
+bool active(const or_kernel* k, u32 i, u32 blk, u32 t) {
+  const u32 g = k->points[i].guard;
+  if (t % k->guards[g].m != k->guards[g].r) return false;
+  return !k->block_guards || blk % k->block_guards[g].m == k->block_guards[g].r;
 }
 
 u64 address(const or_kernel* k, u32 i, u32 blk, u32 t) {
@@ -120,35 +127,65 @@ bool separated(const or_kernel* k, u64 x, u32 i, u32 j, bool grid_only) {
   return false;
 }
 
-// Number of threads of one block that execute a barrier with guard g.
-u64 reached(const or_kernel* k, u32 guard) {
+// Threads of block blk that execute point i.
+u64 reached(const or_kernel* k, u32 i, u32 blk) {
   u64 n = 0;
   for (u32 t = 0; t < k->threads; t++)
-    if (t % k->guards[guard].m == k->guards[guard].r) n++;
+    if (active(k, i, blk, t)) n++;
   return n;
 }
 
-// Slots that diverge when enabled: reached by some but not all threads of
-// a block.  literal: count per block (the guard reads only the thread id,
-// so every block gives the same count).
+// Slots that diverge when enabled.  A block-level barrier diverges when
+// some block has part of its threads reaching it; a grid-level barrier must
+// be reached by every thread of the grid, so it diverges when part of the
+// grid reaches it (Section 1, Listing 2; Section 2.2 for the grid barrier).
+// literal: count every block; otherwise the per-block count is taken once
+// (it does not depend on the block) and the blocks that execute the point
+// are counted from the block condition.
 u64 divergent_if_enabled(const or_kernel* k, bool literal) {
   u64 mask = 0;
   for (u32 u = 0; u < k->n_points; u++) {
     const or_point& p = k->points[u];
     if (p.kind != BARRIER) continue;
-    u32 nb = literal ? k->blocks : 1;
-    for (u32 blk = 0; blk < nb; blk++) {
-      u64 n = reached(k, p.guard);
-      if (n > 0 && n < k->threads) mask |= 1ull << p.slot;
+    bool part_of_a_block = false;
+    u64 total = 0;
+    if (literal) {
+      for (u32 blk = 0; blk < k->blocks; blk++) {
+        const u64 n = reached(k, u, blk);
+        if (n > 0 && n < k->threads) part_of_a_block = true;
+        total += n;
+      }
+    } else {
+      u64 nt = 0;
+      for (u32 t = 0; t < k->threads; t++)
+        if (t % k->guards[p.guard].m == k->guards[p.guard].r) nt++;
+      u64 nb = 0;
+      for (u32 blk = 0; blk < k->blocks; blk++)
+        if (!k->block_guards || blk % k->block_guards[p.guard].m == k->block_guards[p.guard].r) nb++;
+      part_of_a_block = nb > 0 && nt > 0 && nt < k->threads;
+      total = nb * nt;
     }
+    const bool grid = k->slots[p.slot].level == GRID;
+    const bool div = grid ? total > 0 && total < (u64)k->blocks * k->threads : part_of_a_block;
+    if (div) mask |= 1ull << p.slot;
   }
   return mask;
 }
 
+// Executing (block, thread) pairs of every access point: threads meeting
+// the thread condition times blocks meeting the block condition.
 u64 count_records(const or_kernel* k) {
   u64 n = 0;
-  for (u32 i = 0; i < k->n_points; i++)
-    if (k->points[i].kind == ACCESS) n += reached(k, k->points[i].guard) * k->blocks;
+  for (u32 i = 0; i < k->n_points; i++) {
+    if (k->points[i].kind != ACCESS) continue;
+    const u32 g = k->points[i].guard;
+    u64 nt = 0, nb = 0;
+    for (u32 t = 0; t < k->threads; t++)
+      if (t % k->guards[g].m == k->guards[g].r) nt++;
+    for (u32 blk = 0; blk < k->blocks; blk++)
+      if (!k->block_guards || blk % k->block_guards[g].m == k->block_guards[g].r) nb++;
+    n += nt * nb;
+  }
   return n;
 }
 
@@ -170,7 +207,7 @@ void conflicts_literal(const or_kernel* k, u64 x, bool apply_x, PairSet& out) {
     if (k->points[i].kind != ACCESS) continue;
     for (u32 blk = 0; blk < k->blocks; blk++)
       for (u32 t = 0; t < k->threads; t++)
-        if (active(k, i, t)) recs.push_back({i, blk, t});
+        if (active(k, i, blk, t)) recs.push_back({i, blk, t});
   }
   for (size_t r1 = 0; r1 < recs.size(); r1++) {
     for (size_t r2 = r1 + 1; r2 < recs.size(); r2++) {
@@ -205,7 +242,7 @@ void conflicts_grouped(const or_kernel* k, PairSet& out) {
       if (k->points[i].kind != ACCESS) continue;
       for (u32 blk = 0; blk < k->blocks; blk++)
         for (u32 t = 0; t < k->threads; t++)
-          if (active(k, i, t))
+          if (active(k, i, blk, t))
             recs.push_back({k->points[i].array, blk, address(k, i, blk, t), i, t});
     }
     std::sort(recs.begin(), recs.end(), [](const R& a, const R& b) {
@@ -249,7 +286,7 @@ void conflicts_grouped(const or_kernel* k, PairSet& out) {
       if (k->points[i].kind != ACCESS || !is_global(k, i)) continue;
       for (u32 blk = 0; blk < k->blocks; blk++)
         for (u32 t = 0; t < k->threads; t++)
-          if (active(k, i, t))
+          if (active(k, i, blk, t))
             recs.push_back({k->points[i].array, address(k, i, blk, t), i, blk});
     }
     std::sort(recs.begin(), recs.end(), [](const R& a, const R& b) {
@@ -554,7 +591,7 @@ extern "C" int or_pair_conflict(const or_kernel* k, uint32_t i, uint32_t j, int 
   auto collect = [&](u32 p, std::vector<E>& v) {
     for (u32 blk = 0; blk < k->blocks; blk++)
       for (u32 t = 0; t < k->threads; t++)
-        if (active(k, p, t)) {
+        if (active(k, p, blk, t)) {
           u64 a = address(k, p, blk, t);
           if (level == 0) v.push_back({((u64)blk << 32) | a, t});
           else v.push_back({a, blk});

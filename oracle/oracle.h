@@ -35,6 +35,7 @@ typedef struct {
   uint32_t blocks, threads, n_arrays, n_guards, n_points, n_slots;
   const or_array* arrays; const or_guard* guards;
   const or_point* points; const or_slot* slots;
+  const or_guard* block_guards;   /* NULL or [n_guards]: bid % m == r as well */
 } or_kernel;
 typedef struct { uint64_t pos, neg; } or_clause;
 typedef struct { uint16_t i, j; uint8_t level; uint8_t pad; } or_pair;   /* level 0 intra, 1 inter */

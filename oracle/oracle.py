@@ -53,7 +53,8 @@ class _Kernel(C.Structure):
     _fields_ = [("blocks", C.c_uint32), ("threads", C.c_uint32), ("n_arrays", C.c_uint32),
                 ("n_guards", C.c_uint32), ("n_points", C.c_uint32), ("n_slots", C.c_uint32),
                 ("arrays", C.POINTER(_Array)), ("guards", C.POINTER(_Guard)),
-                ("points", C.POINTER(_Point)), ("slots", C.POINTER(_Slot))]
+                ("points", C.POINTER(_Point)), ("slots", C.POINTER(_Slot)),
+                ("block_guards", C.POINTER(_Guard))]
 
 
 class Clause(C.Structure):
@@ -132,8 +133,16 @@ class _Held:
             self.slots[n].level = int(s["level"][n])
             self.slots[n].preexisting = int(s["preexisting"][n])
             self.slots[n].weight = int(s["weight"][n])
+        bg = getattr(km, "block_guards", None)
+        self.block_guards = None
+        if bg is not None:
+            self.block_guards = (_Guard * max(1, len(bg)))()
+            for n in range(len(bg)):
+                self.block_guards[n].m = int(bg["m"][n])
+                self.block_guards[n].r = int(bg["r"][n])
         self.k = _Kernel(int(km.blocks), int(km.threads), len(arrs), len(g), len(p), len(s),
-                         self.arrays, self.guards, self.points, self.slots)
+                         self.arrays, self.guards, self.points, self.slots,
+                         self.block_guards)
 
     @property
     def ptr(self):

@@ -31,6 +31,14 @@
 //     (first id 0; a second id exactly when there are two blocks or more);
 //   - one block: no cross-block view (a race needs two blocks).
 // Records are still emitted in increasing order of their low fields.
+//
+// Block conditions (a guard that also tests bid % bm == br): the same-block
+// view keeps one fixed record count per block, and a block that does not
+// execute a point holds padding records in its place: array id pad_array
+// (one past the kernel's arrays, so the array field may take one more bit),
+// word 0, that block, that point, thread 0.  They form locations of their
+// own with a single id, so they never conflict.  The cross-block view holds
+// the executing blocks only.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -48,7 +56,7 @@ constexpr int MAX_SORT_PASSES = 8;
 // words).
 constexpr uint8_t PF_WRITE = 1, PF_GLOBAL = 2, PF_POW2 = 4, PF_TCONST = 8, PF_BCONST = 16;
 
-struct DPoint {          // 32 B, one per program point
+struct DPoint {          // 40 B, one per program point
   int32_t a, b, c;
   uint32_t words;        // array size (words)
   uint32_t m, r;         // guard: tid % m == r
@@ -56,6 +64,7 @@ struct DPoint {          // 32 B, one per program point
   uint16_t array;
   uint8_t kind;          // RP_ACCESS / RP_BARRIER / RP_NOP
   uint8_t flags;         // PF_*
+  uint32_t bm, br;       // block condition: bid % bm == br
 };
 
 struct JobState {        // device-resident per-job state; the host reads it
@@ -100,7 +109,8 @@ struct Job {
   uint32_t* minj;             // [2][P] first racing partner per point under x
   uint32_t* j0;               // [2][P] first racing partner with no barrier enabled
   uint64_t* bitmap;           // [2][P][wpr] racing pairs (check mode) or null
-  uint32_t wpr, pad1;         // 64-bit words per bitmap row
+  uint32_t wpr;               // 64-bit words per bitmap row
+  uint32_t pad_array;         // array id of padding records (0: none)
   rp_clause* phi;             // [phi_cap]
   rp_clause* scratch;         // [scratch_cap] (power of two)
   uint32_t phi_cap, scratch_cap;

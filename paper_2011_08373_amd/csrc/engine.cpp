@@ -294,6 +294,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     J.gcnt_pre = (const uint64_t*)(d + L.o_gpre[j]);
     J.rblk = p.cnt_pre.empty() ? 0 : p.cnt_pre[p.P];
     J.div_if_enabled = p.div_if_enabled;
+    J.pad_array = p.pad_array;
     J.log[0] = J.log[1] = nullptr;
     J.nlog[0] = p.n_intra;
     J.nlog[1] = p.n_inter;

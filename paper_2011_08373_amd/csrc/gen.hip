@@ -5,7 +5,12 @@
 // only) in point-major order; common.h describes the packing.  Each record
 // is a pure function of (point, block, thread): the word is
 // (a*tid + b*bid + c) mod words (Euclidean residue), and the executing
-// threads are those with tid % m == r.  Items coincide with the sort's
+// threads are those with tid % m == r of the blocks with bid % bm == br.
+// The same-block log keeps the same number of records for every block: a
+// block that does not execute a point gets padding records in its place,
+// all in one location of their own (array id pad_array, word 0, that block)
+// and all of thread 0, so they never conflict with anything.  The
+// cross-block log holds the executing blocks only.  Items coincide with the sort's
 // chunks: while writing, an item counts the radix digits of the first sort
 // pass in LDS and stores them as its chunk's count row.  The item's points
 // (up to 256, from its first point on, which the host finds) are staged in
@@ -45,12 +50,12 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
   return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
 }
 __device__ __forceinline__ DPoint uni_point(const DPoint& p) {
-  static_assert(sizeof(DPoint) == 32, "eight words");
+  static_assert(sizeof(DPoint) == 40, "ten words");
   DPoint u;
   const uint32_t* s = reinterpret_cast<const uint32_t*>(&p);
   uint32_t* d = reinterpret_cast<uint32_t*>(&u);
 #pragma unroll
-  for (int k = 0; k < 8; k++) d[k] = uni(s[k]);
+  for (int k = 0; k < 10; k++) d[k] = uni(s[k]);
   return u;
 }
 // x * tid for a wave-uniform x: one 24-bit multiply when x fits (the usual
@@ -119,29 +124,41 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
       const uint64_t hi = sbeg + c < it.o1 ? sbeg + c : it.o1;
       if (lo < hi) {
         const DPoint p = uni_point(cached ? s_pts[sd] : J.pts[si]);
-        const uint64_t arr = (uint64_t)p.array << nb;
         const uint64_t low = ((uint64_t)k << (pb + tb)) | ((uint64_t)si << tb);
-        // record u0 + q of the point: thread t = r + m*(u0 + q)
-        const uint32_t u0 = (uint32_t)(lo - sbeg);
-        const uint32_t t0 = p.r + p.m * u0;
-        const uint32_t mt = mul_tid(p.m, lane);
-        // power-of-two words: word = (a*t + b*k + c) mod 2^32, masked
-        const bool pow2 = p.flags & PF_POW2;
-        const uint32_t am = (uint32_t)p.a * p.m;
-        const uint32_t at = pow2 ? mul_tid(am, lane) : 0u;
-        const uint32_t cw = (uint32_t)p.a * t0 + (uint32_t)p.b * k + (uint32_t)p.c;
-        const uint32_t wmask = p.words - 1;
-        const uint64_t take = hi - lo;
-        for (uint64_t q0 = 0; q0 < take; q0 += 64) {
-          const uint64_t q = q0 + lane;
-          const bool valid = q < take;
-          const uint32_t t = t0 + p.m * (uint32_t)q0 + mt;
-          uint32_t word;
-          if (pow2) word = (cw + am * (uint32_t)q0 + at) & wmask;
-          else word = word_of(p, t, k);
-          const uint64_t rec = ((arr | word) << ks) | low | t;
-          if (valid) out[lo + q] = rec;
-          if (count) count_digits<RB>(hist, rec, shift, valid);
+        if (p.bm > 1 && k % p.bm != p.br) {
+          // this block does not execute the point: padding
+          const uint64_t rec = (((uint64_t)J.pad_array << nb) << ks) | low;
+          const uint64_t take = hi - lo;
+          for (uint64_t q0 = 0; q0 < take; q0 += 64) {
+            const uint64_t q = q0 + lane;
+            const bool valid = q < take;
+            if (valid) out[lo + q] = rec;
+            if (count) count_digits<RB>(hist, rec, shift, valid);
+          }
+        } else {
+          const uint64_t arr = (uint64_t)p.array << nb;
+          // record u0 + q of the point: thread t = r + m*(u0 + q)
+          const uint32_t u0 = (uint32_t)(lo - sbeg);
+          const uint32_t t0 = p.r + p.m * u0;
+          const uint32_t mt = mul_tid(p.m, lane);
+          // power-of-two words: word = (a*t + b*k + c) mod 2^32, masked
+          const bool pow2 = p.flags & PF_POW2;
+          const uint32_t am = (uint32_t)p.a * p.m;
+          const uint32_t at = pow2 ? mul_tid(am, lane) : 0u;
+          const uint32_t cw = (uint32_t)p.a * t0 + (uint32_t)p.b * k + (uint32_t)p.c;
+          const uint32_t wmask = p.words - 1;
+          const uint64_t take = hi - lo;
+          for (uint64_t q0 = 0; q0 < take; q0 += 64) {
+            const uint64_t q = q0 + lane;
+            const bool valid = q < take;
+            const uint32_t t = t0 + p.m * (uint32_t)q0 + mt;
+            uint32_t word;
+            if (pow2) word = (cw + am * (uint32_t)q0 + at) & wmask;
+            else word = word_of(p, t, k);
+            const uint64_t rec = ((arr | word) << ks) | low | t;
+            if (valid) out[lo + q] = rec;
+            if (count) count_digits<RB>(hist, rec, shift, valid);
+          }
         }
       }
       sd += WAVES;
@@ -149,9 +166,10 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
       while (si >= P) { si -= P; k++; }
     }
   } else {
-    // point-major over GLOBAL access points: point i, blocks in order,
-    // executing threads in order (one thread when the word does not depend
-    // on it; blocks 0 and 1 only when it does not depend on the block)
+    // point-major over GLOBAL access points: point i, executing blocks in
+    // order, executing threads in order (one thread when the word does not
+    // depend on it; the first two executing blocks only when it does not
+    // depend on the block)
     uint32_t i = i0;
     uint32_t d = 0;            // cache slot of point i
     uint64_t pos = it.o0;
@@ -186,6 +204,7 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
             u = (uint32_t)(j - (uint64_t)kk * cnt);
           }
           const uint32_t t = p.r + p.m * u;
+          kk = p.br + p.bm * kk;           // the kk-th executing block
           uint32_t word;
           if (pow2) word = ((uint32_t)p.a * t + (uint32_t)p.b * kk + (uint32_t)p.c) & wmask;
           else word = word_of(p, t, kk);

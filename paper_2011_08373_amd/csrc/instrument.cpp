@@ -14,8 +14,9 @@
 // Expansion.  Loops are unrolled and calls inlined in execution order; one
 // barrier variable is one static site (or one pre-existing barrier per chain
 // of call sites) and its unrolled copies are occurrences of it.  A branch
-// runs its body under the conjunction of its condition (tid % m == r) and
-// the enclosing one, itself a residue class (Chinese remainder theorem).
+// runs its body under the conjunction of its condition (tid % m == r and
+// bid % bm == br) and the enclosing one: each part is again a residue class
+// (Chinese remainder theorem).
 // An access word is (a*tid + b*bid + c + d*it) mod words with it the
 // iteration of the innermost enclosing loop (0 outside loops).  The weight
 // of a variable is gw*gb + lw^ld (Section 2.4), ld the number of loops
@@ -42,13 +43,17 @@ struct SiteKey {
   }
 };
 
+struct Cond {                                 // a guard: thread part, block part
+  rp_guard t, b;
+};
+
 struct Pass {
   const rp_program* p;
   uint8_t grid;
   uint32_t gw, lw;
   std::vector<std::vector<uint32_t>> match;   // per function: END index of each IF/LOOP
   std::vector<int8_t> reaches;                // per function: an access is reachable
-  std::vector<rp_guard> guards;
+  std::vector<Cond> guards;                   // output guard table
   std::vector<rp_point> points;
   std::vector<rp_slot> slots;
   std::map<SiteKey, uint32_t> slot_of;
@@ -90,11 +95,20 @@ struct Pass {
     return true;
   }
 
-  uint16_t guard_id(rp_guard g) {
+  uint16_t guard_id(Cond g) {
     for (size_t i = 0; i < guards.size(); i++)
-      if (guards[i].m == g.m && guards[i].r == g.r) return (uint16_t)i;
+      if (guards[i].t.m == g.t.m && guards[i].t.r == g.t.r && guards[i].b.m == g.b.m &&
+          guards[i].b.r == g.b.r)
+        return (uint16_t)i;
     guards.push_back(g);
     return (uint16_t)(guards.size() - 1);
+  }
+
+  Cond cond_of(uint16_t g) const {
+    Cond c;
+    c.t = p->guards[g];
+    c.b = p->block_guards ? p->block_guards[g] : rp_guard{1, 0};
+    return c;
   }
 
   uint32_t weight(uint8_t level, uint32_t depth) {
@@ -148,7 +162,7 @@ struct Pass {
     if (grid) barrier(f, s, 1, RP_GRID, 0, g, depth);
   }
 
-  void expand(uint32_t f, uint32_t lo, uint32_t hi, rp_guard gcur, uint32_t depth, int64_t it) {
+  void expand(uint32_t f, uint32_t lo, uint32_t hi, Cond gcur, uint32_t depth, int64_t it) {
     const rp_function& fn = p->functions[f];
     int32_t gi = -1;                            // guard index, taken at first use
     auto G = [&]() -> uint16_t {
@@ -179,8 +193,12 @@ struct Pass {
           break;
         case RP_S_IF: {
           if (f == 0) site(f, s, G(), depth);
-          rp_guard inner;
-          if (!compose(gcur, p->guards[st.guard], inner)) { err = RP_ERR_INVALID; return; }
+          Cond inner;
+          const Cond c = cond_of(st.guard);
+          if (!compose(gcur.t, c.t, inner.t) || !compose(gcur.b, c.b, inner.b)) {
+            err = RP_ERR_INVALID;
+            return;
+          }
           const uint32_t end = match[f][s];
           expand(f, s + 1, end, inner, depth, it);
           s = end;
@@ -218,8 +236,12 @@ struct Pass {
     if ((p->n_arrays && !p->arrays) || (p->n_guards && !p->guards)) return RP_ERR_INVALID;
     for (uint32_t a = 0; a < p->n_arrays; a++)
       if (p->arrays[a].words < 1 || p->arrays[a].space > 1) return RP_ERR_INVALID;
-    for (uint32_t g = 0; g < p->n_guards; g++)
+    for (uint32_t g = 0; g < p->n_guards; g++) {
       if (p->guards[g].m < 1 || p->guards[g].r >= p->guards[g].m) return RP_ERR_INVALID;
+      if (p->block_guards && (p->block_guards[g].m < 1 ||
+                              p->block_guards[g].r >= p->block_guards[g].m))
+        return RP_ERR_INVALID;
+    }
     const uint32_t F = p->n_functions;
     match.assign(F, {});
     for (uint32_t f = 0; f < F; f++) {
@@ -298,7 +320,8 @@ struct Pass {
 }  // namespace rp
 
 extern "C" rp_status rp_instrument(const rp_program* prog, const rp_instrument_opts* opts,
-                                   rp_guard* guards, uint32_t guards_cap, uint32_t* n_guards,
+                                   rp_guard* guards, rp_guard* block_guards, uint32_t guards_cap,
+                                   uint32_t* n_guards,
                                    rp_point* points, uint32_t points_cap, uint32_t* n_points,
                                    rp_slot* slots, uint32_t slots_cap, uint32_t* n_slots) {
   using namespace rp;
@@ -311,8 +334,9 @@ extern "C" rp_status rp_instrument(const rp_program* prog, const rp_instrument_o
   if (ps.grid > 1 || ps.lw < 1) return RP_ERR_INVALID;
   int st = ps.check();
   if (st != RP_OK) return (rp_status)st;
-  ps.guards.push_back(rp_guard{1, 0});
-  ps.expand(0, 0, prog->functions[0].n_stmts, rp_guard{1, 0}, 0, 0);
+  const Cond all{rp_guard{1, 0}, rp_guard{1, 0}};
+  ps.guards.push_back(all);
+  ps.expand(0, 0, prog->functions[0].n_stmts, all, 0, 0);
   if (ps.points.size() > (size_t)MAX_POINTS || ps.slots.size() > 64) ps.err = RP_ERR_INVALID;
   if (ps.err != RP_OK) return (rp_status)ps.err;
   *n_guards = (uint32_t)ps.guards.size();
@@ -320,9 +344,13 @@ extern "C" rp_status rp_instrument(const rp_program* prog, const rp_instrument_o
   *n_slots = (uint32_t)ps.slots.size();
   if (ps.guards.size() > guards_cap || ps.points.size() > points_cap || ps.slots.size() > slots_cap)
     return RP_ERR_CAPACITY;
-  if ((ps.guards.size() && !guards) || (ps.points.size() && !points) || (ps.slots.size() && !slots))
+  if ((ps.guards.size() && (!guards || !block_guards)) || (ps.points.size() && !points) ||
+      (ps.slots.size() && !slots))
     return RP_ERR_INVALID;
-  std::memcpy(guards, ps.guards.data(), ps.guards.size() * sizeof(rp_guard));
+  for (size_t g = 0; g < ps.guards.size(); g++) {
+    guards[g] = ps.guards[g].t;
+    block_guards[g] = ps.guards[g].b;
+  }
   std::memcpy(points, ps.points.data(), ps.points.size() * sizeof(rp_point));
   std::memcpy(slots, ps.slots.data(), ps.slots.size() * sizeof(rp_slot));
   return RP_OK;

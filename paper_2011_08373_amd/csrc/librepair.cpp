@@ -36,8 +36,15 @@ int validate_kernel(const rp_kernel* k) {
     if (k->arrays[a].words < 1 || k->arrays[a].space > 1) return RP_ERR_INVALID;
     maxw = std::max<uint64_t>(maxw, k->arrays[a].words);
   }
-  for (uint32_t g = 0; g < k->n_guards; g++)
+  bool bguard = false;
+  for (uint32_t g = 0; g < k->n_guards; g++) {
     if (k->guards[g].m < 1 || k->guards[g].r >= k->guards[g].m) return RP_ERR_INVALID;
+    if (k->block_guards) {
+      if (k->block_guards[g].m < 1 || k->block_guards[g].r >= k->block_guards[g].m)
+        return RP_ERR_INVALID;
+      bguard |= k->block_guards[g].m > 1;
+    }
+  }
   for (uint32_t s = 0; s < k->n_slots; s++)
     if (k->slots[s].level > 1 || k->slots[s].preexisting > 1 || k->slots[s].weight < 1)
       return RP_ERR_INVALID;
@@ -62,7 +69,8 @@ int validate_kernel(const rp_kernel* k) {
     }
   }
   if (next != k->n_slots) return RP_ERR_INVALID;     // every slot occurs
-  const uint32_t total = bits_for(k->n_arrays ? k->n_arrays - 1 : 0) + bits_for(maxw - 1) +
+  // (block conditions add one array id: the location of the padding records)
+  const uint32_t total = bits_for(k->n_arrays ? k->n_arrays - 1 + bguard : 0) + bits_for(maxw - 1) +
                          bits_for(k->blocks - 1) + bits_for(k->n_points ? k->n_points - 1 : 0) +
                          bits_for(k->threads - 1);
   if (total > 64) return RP_ERR_INVALID;
@@ -76,7 +84,13 @@ void make_plan(const rp_kernel* k, Plan& pl) {
   pl.T = k->threads;
   uint64_t maxw = 1;
   for (uint32_t a = 0; a < k->n_arrays; a++) maxw = std::max<uint64_t>(maxw, k->arrays[a].words);
-  pl.abits = bits_for(k->n_arrays ? k->n_arrays - 1 : 0);
+  bool bguard = false;
+  if (k->block_guards)
+    for (uint32_t g = 0; g < k->n_guards; g++) bguard |= k->block_guards[g].m > 1;
+  // padding records of the same-block log (blocks that do not execute a
+  // point) use array id n_arrays
+  pl.pad_array = bguard ? k->n_arrays : 0;
+  pl.abits = bits_for(k->n_arrays ? k->n_arrays - 1 + bguard : 0);
   pl.nbits = bits_for(maxw - 1);
   pl.bbits = bits_for(pl.B - 1);
   pl.pbits = bits_for(pl.P ? pl.P - 1 : 0);
@@ -97,12 +111,20 @@ void make_plan(const rp_kernel* k, Plan& pl) {
     d.kind = p.kind;
     d.flags = 0;
     d.cnt = 0;
+    d.bm = 1;
+    d.br = 0;
+    uint64_t nblk = pl.B;           // blocks executing the point
     if (p.kind != RP_NOP) {
       const rp_guard& g = k->guards[p.guard];
       d.m = g.m;
       d.r = g.r;
       // threads t < T with t % m == r
       d.cnt = g.r < pl.T ? (pl.T - 1 - g.r) / g.m + 1 : 0;
+      if (k->block_guards) {
+        d.bm = k->block_guards[p.guard].m;
+        d.br = k->block_guards[p.guard].r;
+        nblk = d.br < pl.B ? (pl.B - 1 - d.br) / d.bm + 1 : 0;
+      }
     }
     if (p.kind == RP_ACCESS) {
       const rp_array& a = k->arrays[p.array];
@@ -118,12 +140,18 @@ void make_plan(const rp_kernel* k, Plan& pl) {
       const int64_t nw = (int64_t)a.words;
       if ((int64_t)p.a % nw == 0) d.flags |= PF_TCONST;
       if ((int64_t)p.b % nw == 0) d.flags |= PF_BCONST;
-      pl.accesses += (uint64_t)d.cnt * pl.B;
+      pl.accesses += (uint64_t)d.cnt * nblk;
     }
     if (p.kind == RP_BARRIER) {
       pl.bits_any[i] = 1ull << p.slot;
       if (k->slots[p.slot].level == RP_GRID) pl.bits_grid[i] = 1ull << p.slot;
-      if (d.cnt > 0 && d.cnt < pl.T) pl.div_if_enabled |= 1ull << p.slot;
+      // a block barrier must be reached by all threads of each block that
+      // reaches it, a grid barrier by all threads of the grid
+      const uint64_t reach = (uint64_t)d.cnt * nblk;
+      const bool div = k->slots[p.slot].level == RP_GRID
+                           ? reach > 0 && reach < (uint64_t)pl.B * pl.T
+                           : nblk > 0 && d.cnt > 0 && d.cnt < pl.T;
+      if (div) pl.div_if_enabled |= 1ull << p.slot;
     }
     // records emitted per point (the reductions are listed in common.h)
     uint64_t intra = 0, inter = 0;
@@ -132,7 +160,7 @@ void make_plan(const rp_kernel* k, Plan& pl) {
       intra = tc ? std::min<uint64_t>(d.cnt, 2) : d.cnt;
       if ((d.flags & PF_GLOBAL) && pl.B > 1) {
         const uint64_t per_block = tc ? std::min<uint64_t>(d.cnt, 1) : d.cnt;
-        const uint64_t blocks = (d.flags & PF_BCONST) ? 2 : pl.B;
+        const uint64_t blocks = (d.flags & PF_BCONST) ? std::min<uint64_t>(nblk, 2) : nblk;
         inter = per_block * blocks;
       }
     }

@@ -16,6 +16,7 @@ struct Plan {
   std::vector<uint64_t> cnt_pre;    // prefix of same-block records per block over points
   std::vector<uint64_t> gcnt_pre;   // prefix of cross-block records over points
   uint64_t div_if_enabled = 0, grid_slots = 0, pre_slots = 0;
+  uint32_t pad_array = 0;           // array id of padding records (block conditions)
   uint64_t n_intra = 0, n_inter = 0, accesses = 0;
 };
 

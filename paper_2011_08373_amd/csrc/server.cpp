@@ -39,18 +39,23 @@ double now_s() {
 
 struct OwnedKernel {   // deep copy of a descriptor
   std::vector<rp_array> arrays;
-  std::vector<rp_guard> guards;
+  std::vector<rp_guard> guards, block_guards;
   std::vector<rp_point> points;
   std::vector<rp_slot> slots;
   rp_kernel k;
   void take(const rp_kernel* src) {
     arrays.assign(src->arrays, src->arrays + src->n_arrays);
     guards.assign(src->guards, src->guards + src->n_guards);
+    if (src->block_guards)
+      block_guards.assign(src->block_guards, src->block_guards + src->n_guards);
+    else
+      block_guards.clear();
     points.assign(src->points, src->points + src->n_points);
     slots.assign(src->slots, src->slots + src->n_slots);
     k = *src;
     k.arrays = arrays.data();
     k.guards = guards.data();
+    k.block_guards = src->block_guards ? block_guards.data() : nullptr;
     k.points = points.data();
     k.slots = slots.data();
   }

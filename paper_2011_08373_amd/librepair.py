@@ -29,7 +29,7 @@ class RpKernel(C.Structure):
     _fields_ = [("blocks", C.c_uint32), ("threads", C.c_uint32), ("n_arrays", C.c_uint32),
                 ("n_guards", C.c_uint32), ("n_points", C.c_uint32), ("n_slots", C.c_uint32),
                 ("arrays", C.c_void_p), ("guards", C.c_void_p), ("points", C.c_void_p),
-                ("slots", C.c_void_p)]
+                ("slots", C.c_void_p), ("block_guards", C.c_void_p)]
 
 
 class RpClause(C.Structure):
@@ -66,7 +66,8 @@ class RpFunction(C.Structure):
 class RpProgram(C.Structure):
     _fields_ = [("blocks", C.c_uint32), ("threads", C.c_uint32), ("n_arrays", C.c_uint32),
                 ("n_guards", C.c_uint32), ("n_functions", C.c_uint32),
-                ("arrays", C.c_void_p), ("guards", C.c_void_p), ("functions", C.c_void_p)]
+                ("arrays", C.c_void_p), ("guards", C.c_void_p), ("functions", C.c_void_p),
+                ("block_guards", C.c_void_p)]
 
 
 class RpInstrumentOpts(C.Structure):
@@ -122,8 +123,8 @@ _L.rp_set_sort_digit_bits.argtypes = [C.c_int]
 _L.rp_set_tuning.argtypes = [C.c_int, C.c_int]
 _u32p = C.POINTER(C.c_uint32)
 _L.rp_instrument.argtypes = [C.POINTER(RpProgram), C.POINTER(RpInstrumentOpts),
-                             C.c_void_p, C.c_uint32, _u32p, C.c_void_p, C.c_uint32, _u32p,
-                             C.c_void_p, C.c_uint32, _u32p]
+                             C.c_void_p, C.c_void_p, C.c_uint32, _u32p, C.c_void_p, C.c_uint32,
+                             _u32p, C.c_void_p, C.c_uint32, _u32p]
 TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE = 0, 1
 
 
@@ -144,13 +145,17 @@ class KernelArg:
         self.guards = np.ascontiguousarray(km.guards, dtype=synth.GUARD_DT)
         self.points = np.ascontiguousarray(km.points, dtype=synth.POINT_DT)
         self.slots = np.ascontiguousarray(km.slots, dtype=synth.SLOT_DT)
+        bg = getattr(km, "block_guards", None)
+        self.block_guards = None if bg is None else np.ascontiguousarray(bg, dtype=synth.GUARD_DT)
+        if self.block_guards is not None and len(self.block_guards) != len(self.guards):
+            raise ValueError("block_guards needs one entry per guard")
 
         def ptr(a):
-            return a.ctypes.data if a.size else None
+            return a.ctypes.data if a is not None and a.size else None
 
         self.k = RpKernel(int(km.blocks), int(km.threads), len(self.arrays), len(self.guards),
                           len(self.points), len(self.slots), ptr(self.arrays), ptr(self.guards),
-                          ptr(self.points), ptr(self.slots))
+                          ptr(self.points), ptr(self.slots), ptr(self.block_guards))
 
         self._need = {}
 
@@ -447,6 +452,12 @@ def instrument(prog, grid: int = 1, gw: int = 12, lw: int = 10):
     guards = np.zeros(len(prog.guards), synth.GUARD_DT)
     for n, (m, r) in enumerate(prog.guards):
         guards[n] = (m, r)
+    pbg = getattr(prog, "block_guards", None)
+    bguards = None
+    if pbg is not None:
+        bguards = np.zeros(len(pbg), synth.GUARD_DT)
+        for n, (m, r) in enumerate(pbg):
+            bguards[n] = (m, r)
     bodies = []
     for fn in prog.functions:
         b = np.zeros(len(fn), STMT_DT)
@@ -461,21 +472,25 @@ def instrument(prog, grid: int = 1, gw: int = 12, lw: int = 10):
         fns[n].stmts = b.ctypes.data if len(b) else None
     pr = RpProgram(prog.blocks, prog.threads, len(arrays), len(guards), len(bodies),
                    arrays.ctypes.data if len(arrays) else None,
-                   guards.ctypes.data if len(guards) else None, C.addressof(fns))
+                   guards.ctypes.data if len(guards) else None, C.addressof(fns),
+                   bguards.ctypes.data if bguards is not None and len(bguards) else None)
     o = RpInstrumentOpts()
     o.grid, o.gw, o.lw = grid, gw, lw
     ng, npt, ns = C.c_uint32(0), C.c_uint32(0), C.c_uint32(0)
-    st = _L.rp_instrument(C.byref(pr), C.byref(o), None, 0, C.byref(ng), None, 0,
+    st = _L.rp_instrument(C.byref(pr), C.byref(o), None, None, 0, C.byref(ng), None, 0,
                           C.byref(npt), None, 0, C.byref(ns))
     if st != ERR_CAPACITY:
         return st, None
     g = np.zeros(ng.value, synth.GUARD_DT)
+    bg = np.zeros(ng.value, synth.GUARD_DT)
     pt = np.zeros(npt.value, synth.POINT_DT)
     sl = np.zeros(ns.value, synth.SLOT_DT)
-    st = _L.rp_instrument(C.byref(pr), C.byref(o), g.ctypes.data, len(g), C.byref(ng),
-                          pt.ctypes.data, len(pt), C.byref(npt), sl.ctypes.data, len(sl),
-                          C.byref(ns))
+    st = _L.rp_instrument(C.byref(pr), C.byref(o), g.ctypes.data, bg.ctypes.data, len(g),
+                          C.byref(ng), pt.ctypes.data, len(pt), C.byref(npt), sl.ctypes.data,
+                          len(sl), C.byref(ns))
     if st != OK:
         return st, None
+    # no block condition anywhere: the kernel model leaves block_guards out
     return st, synth.Kernel(prog.blocks, prog.threads, arrays, g, pt, sl,
-                            dict(prog.meta, instrumented=True, grid=grid))
+                            dict(prog.meta, instrumented=True, grid=grid),
+                            bg if (bg["m"] > 1).any() else None)

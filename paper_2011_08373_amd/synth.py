@@ -56,6 +56,7 @@ class Kernel:
     points: np.ndarray
     slots: np.ndarray
     meta: dict = field(default_factory=dict)
+    block_guards: np.ndarray | None = None   # [n_guards] (m, r) on bid, or None
 
     @property
     def n_points(self) -> int:
@@ -72,13 +73,16 @@ class Kernel:
     def copy(self) -> "Kernel":
         return Kernel(self.blocks, self.threads, self.arrays.copy(),
                       self.guards.copy(), self.points.copy(), self.slots.copy(),
-                      dict(self.meta))
+                      dict(self.meta),
+                      None if self.block_guards is None else self.block_guards.copy())
 
 
-def make_kernel(blocks, threads, arrays, guards, points, slots, meta=None) -> Kernel:
+def make_kernel(blocks, threads, arrays, guards, points, slots, meta=None,
+                block_guards=None) -> Kernel:
     """Build a Kernel from plain Python lists.
 
-    arrays: [(words, space)], guards: [(m, r)],
+    arrays: [(words, space)], guards: [(m, r)] on the thread id,
+    block_guards: None or [(m, r)] on the block id, one per guard,
     points: [dict(kind=..., is_write=..., array=..., guard=..., slot=..., a=, b=, c=)],
     slots:  [(level, preexisting, weight)].
     """
@@ -96,7 +100,12 @@ def make_kernel(blocks, threads, arrays, guards, points, slots, meta=None) -> Ke
     sl = np.zeros(len(slots), SLOT_DT)
     for n, (lv, pre, w) in enumerate(slots):
         sl[n] = (lv, pre, w)
-    return Kernel(int(blocks), int(threads), arr, gd, pt, sl, dict(meta or {}))
+    bg = None
+    if block_guards is not None:
+        bg = np.zeros(len(block_guards), GUARD_DT)
+        for n, (m, r) in enumerate(block_guards):
+            bg[n] = (m, r)
+    return Kernel(int(blocks), int(threads), arr, gd, pt, sl, dict(meta or {}), bg)
 
 
 # ---------------------------------------------------------------------------
@@ -402,6 +411,20 @@ def generate_batch(n: int | None = None, mode: str = "literal", seed: int | None
     return out
 
 
+def with_block_conditions(km: Kernel, rng, frac: float = 0.4, moduli=(2, 3, 4)) -> Kernel:
+    """A copy of ``km`` whose guards (all but guard 0) get, each with
+    probability ``frac``, a condition bid % m == r on the block id as well."""
+    out = km.copy()
+    bg = np.zeros(len(km.guards), GUARD_DT)
+    bg["m"] = 1
+    for g in range(1, len(km.guards)):
+        if rng.random() < frac:
+            m = int(rng.choice(moduli))
+            bg[g] = (m, int(rng.integers(0, m)))
+    out.block_guards = bg
+    return out
+
+
 def poisson_arrivals(rate: float, duration: float, seed: int = 4) -> np.ndarray:
     """Arrival times (seconds) of a Poisson process of the given rate."""
     rng = np.random.default_rng(seed)
@@ -424,13 +447,15 @@ class Program:
     S_IF (``guard``: index into ``guards``) and S_LOOP (``count`` trips) open
     a region that S_END closes; S_ACCESS has ``array``, ``is_write``, ``a``,
     ``b``, ``c``, ``d``; S_BARRIER (pre-existing) has ``level``; S_CALL has
-    ``count`` = callee index."""
+    ``count`` = callee index.  ``block_guards`` (None, or one (m, r) per
+    guard) adds a condition on the block id to each guard."""
     blocks: int
     threads: int
     arrays: list
     guards: list
     functions: list
     meta: dict = field(default_factory=dict)
+    block_guards: list | None = None
 
 
 def st_access(array, is_write, a=1, b=0, c=0, d=0):
@@ -459,8 +484,9 @@ def st_end():
 
 def random_program(rng, max_sites: int = 20, max_pre: int = 6) -> Program:
     """A small random structured kernel: nested branches (thread-parity
-    conditions), uniform loops with loop-variable address terms, calls of
-    device functions and pre-existing barriers.  ``max_sites`` bounds the
+    conditions, and block-parity ones when there are several blocks),
+    uniform loops with loop-variable address terms, calls of device
+    functions and pre-existing barriers.  ``max_sites`` bounds the
     statements of the kernel body that take an instrumented barrier
     (accesses, branches, loops, calls); ``max_pre`` the pre-existing ones."""
     B = int(rng.choice([1, 2, 4]))
@@ -474,7 +500,21 @@ def random_program(rng, max_sites: int = 20, max_pre: int = 6) -> Program:
     guards = [(1, 0), (2, 0), (2, 1)]
     for m in (3, 4):
         guards.append((m, int(rng.integers(0, m))))
+    # branches on the block id (thread part {1, 0}) when there are blocks
+    bguards = [(1, 0)] * len(guards)
+    if B > 1:
+        for bm, br in ((2, 0), (2, 1), (B, 0)):
+            guards.append((1, 0))
+            bguards.append((bm, br))
     state = dict(sites=0, pre=0)
+
+    def fits(g, outer):
+        # some thread of some block takes both: each part is the enclosing
+        # one again, or has a modulus coprime with it
+        for pa, pb in ((guards[g], guards[outer]), (bguards[g], bguards[outer])):
+            if pa != pb and math.gcd(pa[0], pb[0]) != 1:
+                return False
+        return True
 
     def access():
         arr = int(rng.integers(0, n_arr))
@@ -517,8 +557,7 @@ def random_program(rng, max_sites: int = 20, max_pre: int = 6) -> Program:
             if r < 0.24 and depth < 2:
                 # nested conditions: the enclosing one again, or one whose
                 # modulus is coprime with it, so some thread takes both
-                cand = [g for g in range(len(guards))
-                        if g == outer or math.gcd(guards[g][0], guards[outer][0]) == 1]
+                cand = [g for g in range(len(guards)) if g == outer or fits(g, outer)]
                 g = int(rng.choice(cand))
                 out.append(st_if(g))
                 out += block(depth + 1, int(rng.integers(1, 4)), g if g else outer)
@@ -534,7 +573,8 @@ def random_program(rng, max_sites: int = 20, max_pre: int = 6) -> Program:
         return out
 
     functions[0] = block(0, int(rng.integers(3, 9)), 0)
-    return Program(B, T, arrays, guards, functions)
+    return Program(B, T, arrays, guards, functions,
+                   block_guards=bguards if B > 1 else None)
 
 
 def generate_programs(n: int, seed: int = 11, **kw) -> list:

@@ -7,9 +7,11 @@ hundred records and <= 8 slots.
 import numpy as np
 
 
-def tiny_kernel(rng, max_points=10, max_slots=6, max_threads=8, max_blocks=2, bias=None):
+def tiny_kernel(rng, max_points=10, max_slots=6, max_threads=8, max_blocks=2, bias=None,
+                block_conds=False):
     """Random tiny kernel; ``bias`` favours repairable shapes (injective
-    addresses, denser barriers) so the repair loop has work to do."""
+    addresses, denser barriers) so the repair loop has work to do;
+    ``block_conds`` gives guards a condition on the block id as well."""
     bias = bool(rng.random() < 0.5) if bias is None else bias
     from paper_2011_08373_amd import synth
     B = int(rng.integers(1, max_blocks + 1))
@@ -47,7 +49,27 @@ def tiny_kernel(rng, max_points=10, max_slots=6, max_threads=8, max_blocks=2, bi
                                c=int(rng.integers(-3, 4))))
         else:
             points.append(dict(kind=2))
-    return synth.make_kernel(B, T, arrays, guards, points, slots)
+    bg = None
+    if block_conds:
+        bg = []
+        for _ in guards:
+            if rng.random() < 0.5:
+                m = int(rng.integers(2, 4))
+                bg.append((m, int(rng.integers(0, m))))
+            else:
+                bg.append((1, 0))
+    return synth.make_kernel(B, T, arrays, guards, points, slots, block_guards=bg)
+
+
+def _runs(km, g, k, t):
+    """Thread t of block k executes a point with guard g."""
+    m, r = (int(v) for v in km.guards[g])
+    if t % m != r:
+        return False
+    if km.block_guards is None:
+        return True
+    bm, br = (int(v) for v in km.block_guards[g])
+    return k % bm == br
 
 
 def _records(km):
@@ -62,7 +84,7 @@ def _records(km):
         a, b, c = int(pts["a"][i]), int(pts["b"][i]), int(pts["c"][i])
         for k in range(km.blocks):
             for t in range(km.threads):
-                if t % m == r:
+                if _runs(km, int(pts["guard"][i]), k, t):
                     out.append((i, k, t, arr, (a * t + b * k + c) % n))
     return out
 
@@ -104,11 +126,15 @@ def safe(km, x, conflicts=None):
     for u in range(len(pts)):
         if int(pts["kind"][u]) != 1 or not (x >> int(pts["slot"][u])) & 1:
             continue
-        m, r = (int(v) for v in km.guards[int(pts["guard"][u])])
-        for _k in range(km.blocks):
-            n = sum(1 for t in range(km.threads) if t % m == r)
-            if 0 < n < km.threads:
+        g = int(pts["guard"][u])
+        per_block = [sum(1 for t in range(km.threads) if _runs(km, g, k, t))
+                     for k in range(km.blocks)]
+        if int(km.slots["level"][int(pts["slot"][u])]) == 1:
+            # a grid barrier is reached by the whole grid or by nobody
+            if 0 < sum(per_block) < km.blocks * km.threads:
                 return False
+        elif any(0 < n < km.threads for n in per_block):
+            return False
     return True
 
 

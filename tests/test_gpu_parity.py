@@ -90,6 +90,43 @@ def test_tiny_random_kernels(L):
             assert L.clauses(km, x) == O.clauses(km, x), (seed, x)
 
 
+def test_block_conditions(L):
+    # guards with a condition on the block id (padding records in the
+    # same-block log, executing blocks only in the cross-block log)
+    for seed in range(300):
+        rng = np.random.default_rng(80_000 + seed)
+        km = BF.tiny_kernel(rng, max_blocks=4, block_conds=True)
+        for policy in (0, 1):
+            g = L.repair(km, policy=policy)
+            o = O.repair(km, policy=policy)
+            assert same_repair(g, o), (seed, policy, g, o)
+        for x in rng.integers(0, 1 << max(1, km.n_slots), size=2).tolist():
+            assert L.check(km, x)[:4] == O.check(km, x), (seed, x)
+            assert L.clauses(km, x) == O.clauses(km, x), (seed, x)
+    # kernels of the batched distribution with several generation items and
+    # sort tiles; four arrays, so the padding array id takes one more bit
+    cfg = synth.config("batched")
+    kms = []
+    for seed in range(10):
+        rng = np.random.default_rng(81_000 + seed)
+        c = dict(cfg)
+        c.update(blocks=int(rng.integers(2, 9)), threads=64 * int(rng.integers(1, 5)),
+                 P=int(rng.integers(64, 400)), S=int(rng.integers(4, 24)), S_grid=3)
+        km = synth.with_block_conditions(synth.planted_kernel(c, rng), rng, frac=0.7)
+        kms.append(km)
+        g = L.repair(km)
+        o = O.repair(km)
+        assert same_repair(g, o), (seed, g, o)
+        for x in (0, g["assign"], o["trajectory"][0]):
+            assert L.check(km, x)[:4] == O.check(km, x), (seed, x)
+    st, res = L.repair_batch(kms)
+    assert st == 0
+    for q, km in enumerate(kms):
+        o = O.repair(km)
+        assert {k: res[q][k] for k in REPAIR_KEYS if k != "trajectory"} == \
+            {k: o[k] for k in REPAIR_KEYS if k != "trajectory"}, q
+
+
 def test_tiny_options(L):
     for seed in range(150):
         rng = np.random.default_rng(50_000 + seed)

@@ -26,7 +26,9 @@ def prog(functions, guards=((1, 0),), arrays=((128, SHARED),), blocks=1, threads
 
 
 def same_kernel(k1, k2):
-    return (k1.blocks, k1.threads) == (k2.blocks, k2.threads) and all(
+    bg1 = None if k1.block_guards is None else k1.block_guards.tobytes()
+    bg2 = None if k2.block_guards is None else k2.block_guards.tobytes()
+    return (k1.blocks, k1.threads) == (k2.blocks, k2.threads) and bg1 == bg2 and all(
         np.asarray(getattr(k1, f)).tobytes() == np.asarray(getattr(k2, f)).tobytes()
         for f in ("arrays", "guards", "points", "slots"))
 
@@ -130,6 +132,34 @@ def test_preexisting_barrier_in_a_function_per_call_site():
     assert pre == [0, 1, 0, 0, 1]
     assert k.slots["weight"].tolist() == [1, 13, 10, 10, 22]
     assert k.slots["level"].tolist() == [BLOCK, GRID, BLOCK, BLOCK, GRID]
+
+
+def test_block_branch_with_grid_barrier(L):
+    # if (blockIdx.x % 2 == 0) { A[tid] = ...; g.sync(); } ... B[tid] read by all
+    p = synth.Program(2, 8, [(16, GLOBAL)], [(1, 0), (1, 0)],
+                      [[st_if(1), st_access(0, 1, a=1, b=8), st_barrier(GRID), st_end(),
+                        st_access(0, 0, a=1, b=0)]],
+                      block_guards=[(1, 0), (2, 0)])
+    for inst in (OI.instrument, L.instrument):
+        st, k = inst(p, grid=1)
+        assert st == 0
+        assert [tuple(g) for g in k.guards.tolist()] == [(1, 0), (1, 0)]
+        assert [tuple(g) for g in k.block_guards.tolist()] == [(1, 0), (2, 0)]
+        # the pre-existing grid barrier runs in block 0 only: it diverges
+        pre = int(np.flatnonzero(k.slots["preexisting"])[0])
+        assert O.check(k, 1 << pre)[2] == 1 << pre
+    st, k = OI.instrument(p, grid=1)
+    # block 0 writes words 0..7, every block reads words 0..7 afterwards: the
+    # cross-block race needs a grid barrier that every block reaches -- the
+    # one before the read (slot of the site before the last access)
+    r = O.repair(k)
+    assert r["status"] == 0
+    assert r["removed"] == 1 << pre
+    chosen = [s for s in range(k.n_slots) if (r["assign"] >> s) & 1]
+    assert [int(k.slots["level"][s]) for s in chosen] == [GRID]
+    # that slot's occurrences run in every block
+    occ = [q for q in range(k.n_points) if k.points["kind"][q] == 1 and k.points["slot"][q] == chosen[0]]
+    assert all(k.block_guards[k.points["guard"][q]]["m"] == 1 for q in occ)
 
 
 def test_guard_meet_is_the_residue_class_of_both():

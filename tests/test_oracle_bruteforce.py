@@ -51,6 +51,59 @@ def test_check_literal_grouped_bruteforce(chunk):
                 assert O.pair_conflict(km, i, j, lv) == int((lv, i, j) in conf), (seed, i, j, lv)
 
 
+@pytest.mark.parametrize("chunk", range(4))
+def test_block_conditions_bruteforce(chunk):
+    # guards with a condition on the block id: records of the executing
+    # blocks only; a grid barrier diverges when part of the grid reaches it
+    for seed in range(chunk * 120, (chunk + 1) * 120):
+        rng = np.random.default_rng(40_000 + seed)
+        km = BF.tiny_kernel(rng, max_blocks=4, block_conds=True)
+        assert O.validate(km) == 0, seed
+        conf = BF.conflicting_pairs(km)
+        assert set(O.check(km, 0, literal=True)[1]) == conf, seed
+        for x in [0] + rng.integers(0, 1 << max(1, km.n_slots), size=3).tolist():
+            a = O.check(km, x, literal=True)
+            assert a == O.check(km, x, literal=False), (seed, x)
+            assert (not a[1] and not a[2]) == BF.safe(km, x, conf), (seed, x)
+        best = BF.best_safe(km)
+        for policy in (0, 1):
+            r = O.repair(km, policy=policy)
+            if best is None:
+                assert r["status"] == 1, (seed, policy)
+            else:
+                assert (r["status"], r["assign"]) == (0, best), (seed, policy)
+
+
+def test_grid_divergence_and_block_conditions_pins():
+    # two blocks of 4 threads, one global array of 8 words
+    def kern(block_guards, level, is_write_b=1, b=0):
+        return synth.make_kernel(
+            2, 4, [(8, 1)], [(1, 0), (1, 0)],
+            [dict(kind=0, is_write=1, array=0, guard=1, a=1, b=b, c=0),
+             dict(kind=1, slot=0, guard=1),
+             dict(kind=0, is_write=is_write_b, array=0, guard=0, a=1, b=b, c=0)],
+            [(level, 0, 1)], block_guards=block_guards)
+    # a grid barrier only block 0 reaches diverges; a block barrier does not
+    assert O.check(kern([(1, 0), (2, 0)], 1), 1)[2] == 1
+    assert O.check(kern([(1, 0), (2, 0)], 0), 1)[2] == 0
+    assert O.check(kern([(1, 0), (1, 0)], 1), 1)[2] == 0
+    assert O.check(kern(None, 1), 1)[2] == 0
+    # every block writes words 0..3 at point 0: the two blocks race there
+    # (0 with 0, cross-block) unless only one block executes it
+    st, pairs, div, n = O.check(kern(None, 0), 0)
+    assert (1, 0, 0) in pairs and n == 16
+    st, pairs, div, n = O.check(kern([(1, 0), (2, 1)], 0), 0)
+    assert (1, 0, 0) not in pairs and (1, 0, 2) in pairs and n == 12
+    # the repair: only a grid barrier orders the blocks, and with the write
+    # restricted to block 0 that barrier diverges -> no repair
+    r = O.repair(kern([(1, 0), (2, 0)], 1))
+    assert r["status"] == 1
+    r = O.repair(kern(None, 1))
+    assert r["status"] == 1          # point 0 races with itself across blocks
+    r = O.repair(kern([(1, 0), (2, 0)], 0, b=4))
+    assert r["status"] == 0 and r["assign"] == 0   # block-owned words: no race
+
+
 def test_check_literal_grouped_plain_small():
     for seed in range(0, 1000, 37):
         km = synth.generate("plain-small", seed=seed)
