@@ -324,8 +324,16 @@ int rp_set_sort_digit_bits(int bits);
  *   RP_TUNE_SCATTER_SHAPE    radix-scatter tile: 0 = 512x16, 1 = 256x16,
  *                            2 = 256x32, 3 = 1024x8, 4 = 512x8 (default),
  *                            5 = 1024x4, 6 = 256x8 (threads x records per
- *                            thread). */
-enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1 };
+ *                            thread);
+ *   RP_TUNE_TIMING           hipEvent timing behind rp_last_stats: 0 = none
+ *                            (every ms_* field 0), 1 = the streaming kernels
+ *                            (upload, generation, each radix pass and its
+ *                            scatter, the first-partner scan, the all-pairs
+ *                            scan) and the total (default), 2 = every phase
+ *                            (rounds split into check / clause / solve).
+ *                            Each event recorded on the stream costs a few
+ *                            microseconds of device idle time. */
+enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2 };
 int rp_set_tuning(int knob, int value);
 
 #ifdef __cplusplus

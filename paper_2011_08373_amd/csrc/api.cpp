@@ -338,6 +338,9 @@ int rp_set_tuning(int knob, int value) {
     case RP_TUNE_SCATTER_SHAPE:
       if (value < 0 || value > 6) return -1;
       return scatter_variant(value, true);
+    case RP_TUNE_TIMING:
+      if (value < 0 || value > 2) return -1;
+      return timing_level(value, true);
     default:
       return -1;
   }

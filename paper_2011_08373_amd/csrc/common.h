@@ -124,6 +124,7 @@ struct SortSeg {
   uint64_t beg, end;     // record range
   uint32_t shift;        // key_shift of the job
   uint32_t chunk_beg, chunk_end;  // its chunks
+  uint32_t job, view;    // the job and log (0 same-block, 1 cross-block)
   uint32_t pad;
 };
 

@@ -30,8 +30,8 @@ struct Layout {
   std::vector<uint32_t> phi_cap, scratch_cap;
   uint64_t n_rec = 0;
   uint32_t rb = 8, passes = 0;
-  std::vector<GenItem> items;
-  std::vector<SortChunk> chunks;
+  uint32_t n_chunks = 0;          // sort chunks = generation items (built on the device)
+  uint64_t chunk_len = 0;
   std::vector<SortSeg> ssegs;
   std::vector<uint32_t> seg_job, seg_level;
 };
@@ -59,6 +59,8 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
       s.beg = rec;
       s.end = rec + n;
       s.shift = p.key_shift;
+      s.job = (uint32_t)j;
+      s.view = (uint32_t)v;
       L.ssegs.push_back(s);
       L.seg_job.push_back((uint32_t)j);
       L.seg_level.push_back((uint32_t)v);
@@ -70,38 +72,17 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   const uint64_t tile = sort_tile_size();
   uint64_t chunk = std::max<uint64_t>(2 * tile, (rec + 65535) / 65536);
   chunk = (chunk + tile - 1) / tile * tile;
+  L.chunk_len = chunk;
   for (size_t s = 0; s < L.ssegs.size(); s++) {
-    const uint64_t n = L.ssegs[s].end - L.ssegs[s].beg;
-    L.ssegs[s].chunk_beg = (uint32_t)L.chunks.size();
-    const Plan& pj = *jobs[L.seg_job[s]].plan;
-    const std::vector<uint64_t>& pre = L.seg_level[s] == 0 ? pj.cnt_pre : pj.gcnt_pre;
-    const uint64_t rblk = pj.cnt_pre[pj.P];
-    for (uint64_t o0 = 0; o0 < n; o0 += chunk) {
-      GenItem it{};
-      it.o0 = o0;
-      it.o1 = std::min(n, o0 + chunk);
-      it.job = L.seg_job[s];
-      it.view = L.seg_level[s];
-      it.seg = (uint32_t)s;
-      // the point holding record o0: the last i < P with pre[i] <= offset
-      const uint64_t first = it.view == 0 ? o0 % rblk : o0;
-      it.i0 = (uint32_t)(std::upper_bound(pre.begin(), pre.begin() + pj.P, first) - pre.begin()) - 1;
-      L.items.push_back(it);
-      SortChunk c{};
-      c.beg = L.ssegs[s].beg + it.o0;
-      c.end = L.ssegs[s].beg + it.o1;
-      c.seg = (uint32_t)s;
-      L.chunks.push_back(c);
-    }
-    L.ssegs[s].chunk_end = (uint32_t)L.chunks.size();
+    L.ssegs[s].chunk_beg = L.n_chunks;
+    L.n_chunks += (uint32_t)((L.ssegs[s].end - L.ssegs[s].beg + chunk - 1) / chunk);
+    L.ssegs[s].chunk_end = L.n_chunks;
   }
   const uint32_t R = 1u << L.rb;
   // ---- meta region (uploaded)
   size_t off = 0;
   L.o_jobs = off; off = up(off + N * sizeof(Job));
   L.o_states = off; off = up(off + N * sizeof(JobState));
-  L.o_items = off; off = up(off + L.items.size() * sizeof(GenItem));
-  L.o_chunks = off; off = up(off + L.chunks.size() * sizeof(SortChunk));
   L.o_ssegs = off; off = up(off + L.ssegs.size() * sizeof(SortSeg));
   L.o_csegs = off; off = up(off + L.ssegs.size() * sizeof(ConfSeg));
   L.o_pts.resize(N); L.o_bany.resize(N); L.o_bgrid.resize(N); L.o_w.resize(N);
@@ -120,11 +101,13 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   }
   L.meta = off;
   // ---- device-only region
+  L.o_items = off; off = up(off + (size_t)L.n_chunks * sizeof(GenItem));
+  L.o_chunks = off; off = up(off + (size_t)L.n_chunks * sizeof(SortChunk));
   L.o_recA = off; off = up(off + L.n_rec * sizeof(uint64_t));
   L.o_recB = off; off = up(off + L.n_rec * sizeof(uint64_t));   // sort ping-pong, then run log
-  L.o_cnt = off; off = up(off + L.chunks.size() * (size_t)R * sizeof(uint32_t));
+  L.o_cnt = off; off = up(off + (size_t)L.n_chunks * R * sizeof(uint32_t));
   L.o_tot = off; off = up(off + L.ssegs.size() * (size_t)R * sizeof(uint64_t));
-  L.o_off = off; off = up(off + L.chunks.size() * (size_t)R * sizeof(uint64_t));
+  L.o_off = off; off = up(off + (size_t)L.n_chunks * R * sizeof(uint64_t));
   L.o_err = off; off = up(off + 64);
   L.o_ivl.resize(N); L.o_minj.resize(N); L.o_j0.resize(N); L.o_phi.resize(N); L.o_scratch.resize(N);
   L.o_traj.resize(N); L.o_bitmap.resize(N); L.o_pairs.resize(N); L.o_ptotal.resize(N);
@@ -163,20 +146,23 @@ struct EventPool {
 };
 static thread_local EventPool t_pool;
 
+// A mark records an event when the timer's level reaches the mark's level
+// (1: the streaming kernels and the total, 2: every phase).
 struct Timer {
   std::vector<hipEvent_t> ev;
   std::vector<int> tag;
   hipStream_t s;
   bool ok = true;
   bool on = true;
+  int level = 0;
   int dev = 0;
   size_t base = 0;
-  explicit Timer(hipStream_t st, bool enabled = true) : s(st), on(enabled) {
+  explicit Timer(hipStream_t st, int lvl) : s(st), on(lvl > 0), level(lvl) {
     if (on && hipGetDevice(&dev) != hipSuccess) on = false;
     if (on) base = t_pool.top[dev];
   }
-  void mark(int t) {
-    if (!on) return;
+  void mark(int t, int min_level = 1) {
+    if (!on || level < min_level) return;
     std::vector<hipEvent_t>& pool = t_pool.ev[dev];
     size_t& top = t_pool.top[dev];
     if (top == pool.size()) {
@@ -276,7 +262,9 @@ namespace {
 int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const Layout& L,
                  uint8_t* d, uint8_t* hbuf, hipStream_t s, Timer& tm) {
   const size_t N = jobs.size();
-  std::memset(hbuf, 0, L.meta);
+  // the job and state tables come first and are the only ones not written
+  // in full below
+  std::memset(hbuf, 0, L.o_ssegs);
   Job* hj = (Job*)(hbuf + L.o_jobs);
   JobState* hs = (JobState*)(hbuf + L.o_states);
   for (size_t j = 0; j < N; j++) {
@@ -326,8 +314,6 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     std::memcpy(hbuf + L.o_gpre[j], p.gcnt_pre.data(), (p.P + 1) * sizeof(uint64_t));
     std::memcpy(hbuf + L.o_phi0j[j], jobs[j].phi0.data(), jobs[j].phi0.size() * sizeof(rp_clause));
   }
-  std::memcpy(hbuf + L.o_items, L.items.data(), L.items.size() * sizeof(GenItem));
-  std::memcpy(hbuf + L.o_chunks, L.chunks.data(), L.chunks.size() * sizeof(SortChunk));
   std::memcpy(hbuf + L.o_ssegs, L.ssegs.data(), L.ssegs.size() * sizeof(SortSeg));
   // sorted logs end in buffer A after an even number of passes, else B
   uint8_t* sorted = d + ((L.passes % 2 == 0) ? L.o_recA : L.o_recB);
@@ -349,6 +335,9 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
       HIPCHK(hipMemcpyAsync(d + L.o_phi[j], d + L.o_phi0j[j],
                             jobs[j].phi0.size() * sizeof(rp_clause), hipMemcpyDeviceToDevice, s));
   HIPCHK(launch_fill_u64((uint64_t*)(d + L.o_err), 8, 0, s));
+  HIPCHK(launch_items((const Job*)(d + L.o_jobs), (const SortSeg*)(d + L.o_ssegs),
+                      (uint32_t)L.ssegs.size(), L.n_chunks, L.chunk_len, (GenItem*)(d + L.o_items),
+                      (SortChunk*)(d + L.o_chunks), s));
   tm.mark(T_UPLOAD);
   const Job* djobs = (const Job*)(d + L.o_jobs);
   uint32_t* derr = (uint32_t*)(d + L.o_err);
@@ -356,11 +345,11 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
   const int passes = (int)L.passes;
   const SortSeg* dss = (const SortSeg*)(d + L.o_ssegs);
   const SortChunk* dch = (const SortChunk*)(d + L.o_chunks);
-  const uint32_t nch = (uint32_t)L.chunks.size();
+  const uint32_t nch = L.n_chunks;
   uint32_t* dcnt = (uint32_t*)(d + L.o_cnt);
   uint64_t* dtot = (uint64_t*)(d + L.o_tot);
   uint64_t* doff = (uint64_t*)(d + L.o_off);
-  HIPCHK(launch_gen((int)L.rb, (const GenItem*)(d + L.o_items), (uint32_t)L.items.size(), djobs,
+  HIPCHK(launch_gen((int)L.rb, (const GenItem*)(d + L.o_items), nch, djobs,
                     dss, (uint64_t*)(d + L.o_recA), dcnt, passes > 0 ? 1 : 0, s));
   tm.mark(T_GEN);
   for (int p = 0; p < passes; p++) {
@@ -372,7 +361,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     HIPCHK(launch_sort_scatter((int)L.rb, in, out, dss, dch, nch, p, doff, derr, s));
     tm.mark(T_SORT);
   }
-  tm.mark(T_SORT);
+  tm.mark(T_SORT, 2);
   ConfSeg* dcs = (ConfSeg*)(d + L.o_csegs);
   // ---- first partners with no barrier enabled (once per job): every
   // later Verify call resolves its first partners from them
@@ -410,7 +399,7 @@ int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStrea
   plan_layout(v, o, L);
   if (bytes < L.total || !region) return RP_ERR_WORKSPACE;
   uint8_t* d = (uint8_t*)region;
-  Timer tm(s, false);
+  Timer tm(s, 0);
   staging.resize(L.meta);
   const int rc = prepare_jobs(v, o, L, d, staging.data(), s, tm);
   if (rc != RP_OK) return rc;
@@ -435,7 +424,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   if (!ws && L.total) return RP_ERR_WORKSPACE;
   const size_t N = jobs.size();
   uint8_t* d = (uint8_t*)ws;
-  Timer tm(s);
+  Timer tm(s, timing_level(0, false));
   {
     uint8_t* h = t_stage.get(L.meta);
     if (!h) return RP_ERR_DEVICE;
@@ -446,13 +435,30 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   const Job* djobs = (const Job*)(d + L.o_jobs);
   uint32_t* derr = (uint32_t*)(d + L.o_err);
   ConfSeg* dcs = (ConfSeg*)(d + L.o_csegs);
-  tm.mark(T_RUNS);
+  tm.mark(T_RUNS, 2);
   // ---- per-round kernels
   const int nseg = (int)L.ssegs.size();
   uint32_t* dtiles = derr + 9;     // conf tiles of the all-pairs scan
   uint32_t maxP = 1;
   for (const JobInput& j : jobs) maxP = std::max(maxP, j.plan->P);
   std::vector<JobState> hst(N);
+  // job states, the error word and the start of each job's trajectory (the
+  // usual few rounds) are read back into page-locked memory in one go
+  const uint32_t traj_head = std::min<uint32_t>(o.traj_cap, 16);
+  uint8_t* rb = (uint8_t*)t_stage.readback(N * sizeof(JobState) + 64 + N * traj_head * sizeof(uint64_t));
+  if (!rb) return RP_ERR_DEVICE;
+  JobState* pst = (JobState*)rb;
+  uint32_t* herr = (uint32_t*)(rb + N * sizeof(JobState));
+  uint64_t* ptraj = (uint64_t*)(rb + N * sizeof(JobState) + 64);
+  auto enqueue_results = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(pst, d + L.o_states, N * sizeof(JobState), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(herr, derr, 64, hipMemcpyDeviceToHost, s);
+    for (size_t j = 0; j < N && traj_head && e == hipSuccess; j++)
+      e = hipMemcpyAsync(ptraj + j * traj_head, d + L.o_traj[j], traj_head * sizeof(uint64_t),
+                         hipMemcpyDeviceToHost, s);
+    return e;
+  };
+  bool ended = false, have_results = false;
   // the run logs are scanned once: by the all-pairs scan of a check, else
   // by the first-partner scan of the preparation
   const uint64_t scanned = o.op == OP_SOLVE ? 0 : L.n_rec;
@@ -481,7 +487,7 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   } else {
     uint32_t* dactive = (uint32_t*)(d + L.o_err) + 8;
     HIPCHK(launch_solve(djobs, (uint32_t)N, s));
-    tm.mark(T_SOLVE);
+    tm.mark(T_SOLVE, 2);
     auto round = [&]() -> hipError_t {
       hipError_t e;
       if ((e = launch_ivl(djobs, (uint32_t)N, IVL_RESOLVE, s)) != hipSuccess) return e;
@@ -490,15 +496,17 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
       return launch_count_active(djobs, (uint32_t)N, dactive, s);
     };
     // the first round is launched directly; if jobs remain, the round is
-    // captured once in a graph and replayed until every job has a verdict
+    // captured once in a graph and replayed until every job has a verdict.
+    // A small batch reads every verdict together with the round's count of
+    // running jobs (it sits in the error word), so the round that ends the
+    // loop needs no further wait; a large one reads the count alone.
+    const bool with_results = N <= 64;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     bool tried_graph = false;
-    uint32_t* active = t_stage.readback(sizeof(uint32_t));
-    if (!active) return RP_ERR_DEVICE;
-    *active = 1;
+    uint32_t n_active = 1;
     int rc_loop = RP_OK;
-    while (*active) {
+    while (n_active) {
       if (rounds_run == 1 && !tried_graph && o.use_graph && s != nullptr) {
         tried_graph = true;
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
@@ -513,46 +521,43 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
           }
         }
       }
-      tm.mark(T_ROUND);
+      tm.mark(T_ROUND, 2);
       if (gexec) {
         if (hipGraphLaunch(gexec, s) != hipSuccess) { rc_loop = RP_ERR_DEVICE; break; }
-        tm.mark(T_CHECK);
+        tm.mark(T_CHECK, 2);
       } else {
         HIPCHK(launch_ivl(djobs, (uint32_t)N, IVL_RESOLVE, s));
-        tm.mark(T_CHECK);
+        tm.mark(T_CHECK, 2);
         HIPCHK(launch_clause(djobs, (uint32_t)N, 1, s));
-        tm.mark(T_CLAUSE);
+        tm.mark(T_CLAUSE, 2);
         HIPCHK(launch_solve(djobs, (uint32_t)N, s));
-        tm.mark(T_SOLVE);
+        tm.mark(T_SOLVE, 2);
         HIPCHK(launch_count_active(djobs, (uint32_t)N, dactive, s));
       }
-      if (hipMemcpyAsync(active, dactive, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-          hipStreamSynchronize(s) != hipSuccess) {
+      tm.mark(T_END);           // the last one recorded ends the final round
+      const hipError_t e = with_results
+                               ? enqueue_results()
+                               : hipMemcpyAsync(herr + 8, dactive, sizeof(uint32_t),
+                                                hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         rc_loop = RP_ERR_DEVICE;
         break;
       }
+      n_active = herr[8];
       rounds_run++;
       if (rounds_run > 100000) { rc_loop = RP_ERR_DEVICE; break; }
     }
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (rc_loop != RP_OK) return rc_loop;
+    ended = true;
+    have_results = with_results;
   }
-  tm.mark(T_END);
-  // job states and the error word, and the start of each job's trajectory
-  // (the usual few rounds), into page-locked memory with one wait
-  const uint32_t traj_head = std::min<uint32_t>(o.traj_cap, 16);
-  uint8_t* rb = (uint8_t*)t_stage.readback(N * sizeof(JobState) + 64 + N * traj_head * sizeof(uint64_t));
-  if (!rb) return RP_ERR_DEVICE;
-  JobState* pst = (JobState*)rb;
-  uint32_t* herr = (uint32_t*)(rb + N * sizeof(JobState));
-  uint64_t* ptraj = (uint64_t*)(rb + N * sizeof(JobState) + 64);
-  HIPCHK(hipMemcpyAsync(pst, d + L.o_states, N * sizeof(JobState), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(herr, derr, 64, hipMemcpyDeviceToHost, s));
-  for (size_t j = 0; j < N && traj_head; j++)
-    HIPCHK(hipMemcpyAsync(ptraj + j * traj_head, d + L.o_traj[j], traj_head * sizeof(uint64_t),
-                          hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  if (!ended) tm.mark(T_END);
+  if (!have_results) {
+    HIPCHK(enqueue_results());
+    HIPCHK(hipStreamSynchronize(s));
+  }
   std::memcpy(hst.data(), pst, N * sizeof(JobState));
   if (herr[0]) return RP_ERR_DEVICE;
   res.assign(N, JobResult{});

@@ -225,6 +225,58 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
   for (uint32_t q = tid; q < R; q += GEN_BLOCK) row[q] = hist[q];
 }
 
+// One thread per chunk: its segment (the last with chunk_beg <= c), its
+// record range and the point holding its first record (the last i with
+// pre[i] <= offset, the offset taken within one block for the same-block
+// log).
+__global__ __launch_bounds__(256) void items_kernel(const Job* __restrict__ jobs,
+                                                    const SortSeg* __restrict__ segs, uint32_t nseg,
+                                                    uint32_t nchunks, uint64_t chunk_len,
+                                                    GenItem* __restrict__ items,
+                                                    SortChunk* __restrict__ chunks) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nchunks) return;
+  uint32_t lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (segs[mid].chunk_beg <= c) lo = mid; else hi = mid - 1;
+  }
+  const SortSeg sg = segs[lo];
+  const uint64_t n = sg.end - sg.beg;
+  const uint64_t o0 = (uint64_t)(c - sg.chunk_beg) * chunk_len;
+  const uint64_t o1 = o0 + chunk_len < n ? o0 + chunk_len : n;
+  const Job& J = jobs[sg.job];
+  const uint64_t* pre = sg.view == 0 ? J.cnt_pre : J.gcnt_pre;
+  const uint64_t first = sg.view == 0 ? o0 % J.rblk : o0;
+  uint32_t a = 0, b = J.P;            // the first i in [0, P) with pre[i] > first, or P
+  while (a < b) {
+    const uint32_t mid = (a + b) >> 1;
+    if (pre[mid] <= first) a = mid + 1; else b = mid;
+  }
+  GenItem it;
+  it.o0 = o0;
+  it.o1 = o1;
+  it.job = sg.job;
+  it.view = sg.view;
+  it.seg = lo;
+  it.i0 = a - 1;
+  items[c] = it;
+  SortChunk ch;
+  ch.beg = sg.beg + o0;
+  ch.end = sg.beg + o1;
+  ch.seg = lo;
+  ch.pad = 0;
+  chunks[c] = ch;
+}
+
+hipError_t launch_items(const Job* jobs, const SortSeg* segs, uint32_t nseg, uint32_t nchunks,
+                        uint64_t chunk_len, GenItem* items, SortChunk* chunks, hipStream_t s) {
+  if (nchunks == 0 || nseg == 0) return hipSuccess;
+  items_kernel<<<(nchunks + 255) / 256, 256, 0, s>>>(jobs, segs, nseg, nchunks, chunk_len, items,
+                                                     chunks);
+  return hipGetLastError();
+}
+
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,
                       const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int passes,
                       hipStream_t s) {

@@ -13,6 +13,13 @@
 namespace rp {
 
 static int g_digit_bits = 0;          // 0 = automatic
+static int g_timing = 1;              // RP_TUNE_TIMING
+
+int timing_level(int v, bool set) {
+  const int old = g_timing;
+  if (set) g_timing = v;
+  return old;
+}
 
 int g_digit_bits_ref(int v, bool set) {
   const int old = g_digit_bits;

@@ -23,6 +23,8 @@ struct Plan {
 int validate_kernel(const rp_kernel* k);
 void make_plan(const rp_kernel* k, Plan& pl);
 int pick_digit_bits(uint32_t key_bits);
+// hipEvent timing level of engine calls (RP_TUNE_TIMING); returns the old one
+int timing_level(int v, bool set);
 int sort_passes(uint32_t key_bits, int rb);
 // Unit clauses that the repair options impose before the first Solve.
 std::vector<rp_clause> option_units(const Plan& pl, const rp_repair_opts& o);

@@ -94,6 +94,14 @@ def test_tuning_knobs(L):
         assert L.set_tuning(99, 0) == -1
     finally:
         L.set_tuning(L.TUNE_SORT_DIGIT_BITS, old)
+    old = L.set_tuning(L.TUNE_TIMING, 2)
+    try:
+        assert old == 1                                          # the default
+        assert L.set_tuning(L.TUNE_TIMING, 0) == 2
+        assert L.set_tuning(L.TUNE_TIMING, 3) == -1
+        assert L.set_tuning(L.TUNE_TIMING, -1) == -1
+    finally:
+        L.set_tuning(L.TUNE_TIMING, old)
 
 
 def test_invalid_kernel_does_no_device_work(L):
