@@ -166,8 +166,14 @@ struct Timer {
     std::vector<hipEvent_t>& pool = t_pool.ev[dev];
     size_t& top = t_pool.top[dev];
     if (top == pool.size()) {
+      // timing only: no system-scope fence when the event is recorded (no
+      // cache write-back and invalidation between the timed kernels); the
+      // call synchronises its stream before it reads the times
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) { ok = false; return; }
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
+        ok = false;
+        return;
+      }
       pool.push_back(e);
     }
     hipEvent_t e = pool[top++];
