@@ -332,8 +332,12 @@ int rp_set_sort_digit_bits(int bits);
  *                            scan) and the total (default), 2 = every phase
  *                            (rounds split into check / clause / solve).
  *                            Each event recorded on the stream costs a few
- *                            microseconds of device idle time. */
-enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2 };
+ *                            microseconds of device idle time;
+ *   RP_TUNE_SCATTER_WGS      resident workgroups per compute unit of the
+ *                            persistent radix scatter: 0 = what the
+ *                            occupancy query reports (default), else 1..8. */
+enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2,
+       RP_TUNE_SCATTER_WGS = 3 };
 int rp_set_tuning(int knob, int value);
 
 #ifdef __cplusplus

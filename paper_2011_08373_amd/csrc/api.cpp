@@ -13,6 +13,7 @@ static thread_local rp_stats t_stats;
 constexpr uint32_t TRAJ_CAP = 4096;
 extern int g_digit_bits_ref(int v, bool set);
 int scatter_variant(int v, bool set);
+int scatter_wgs(int v, bool set);
 
 // The option units of the switches of Section 4.2 (Tab. 3): with grid-level
 // barriers disabled every grid slot stays off; with inspection disabled every
@@ -338,6 +339,9 @@ int rp_set_tuning(int knob, int value) {
     case RP_TUNE_SCATTER_SHAPE:
       if (value < 0 || value > 6) return -1;
       return scatter_variant(value, true);
+    case RP_TUNE_SCATTER_WGS:
+      if (value < 0 || value > 8) return -1;
+      return scatter_wgs(value, true);
     case RP_TUNE_TIMING:
       if (value < 0 || value > 2) return -1;
       return timing_level(value, true);

@@ -29,7 +29,13 @@ __global__ void fill_u64_kernel(uint64_t* p, uint64_t n, uint64_t v) {
   for (; i < n; i += stride) p[i] = v;
 }
 
-// Per-chunk digit counts of one pass: cnt[chunk][d].
+// Per-chunk digit counts of one pass: cnt[chunk][d].  Whole batches of
+// CNT_U x 256 records are read with the next batch's loads issued before
+// the current one is counted, so each thread keeps CNT_U loads in flight
+// while it counts; every record is one LDS add (no return value, so the
+// adds do not stall the wave).
+constexpr int CNT_U = 8;
+
 template <int RB>
 __global__ __launch_bounds__(256) void count_kernel(const uint64_t* __restrict__ in,
                                                     const SortChunk* __restrict__ chunks,
@@ -37,41 +43,41 @@ __global__ __launch_bounds__(256) void count_kernel(const uint64_t* __restrict__
                                                     const SortSeg* __restrict__ segs, int pass,
                                                     uint32_t* __restrict__ cnt) {
   constexpr uint32_t R = 1u << RB;
+  constexpr uint64_t BATCH = (uint64_t)CNT_U * 256;
   __shared__ uint32_t hist[R];
+  const uint32_t tid = threadIdx.x;
   for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {   // persistent
-  const SortChunk ch = chunks[ci];
-  const int shift = (int)segs[ch.seg].shift + pass * RB;
-  __syncthreads();
-  for (uint32_t d = threadIdx.x; d < R; d += 256) hist[d] = 0;
-  __syncthreads();
-  for (uint64_t r0 = ch.beg; r0 < ch.end; r0 += 4 * 256) {
-    uint64_t v[4];
+    const SortChunk ch = chunks[ci];
+    const int shift = (int)segs[ch.seg].shift + pass * RB;
+    __syncthreads();
+    for (uint32_t d = tid; d < R; d += 256) hist[d] = 0;
+    __syncthreads();
+    const uint64_t* p = in + ch.beg;
+    const uint64_t n = ch.end - ch.beg;
+    const uint64_t full = n / BATCH * BATCH;
+    uint64_t cur[CNT_U];
+    if (full) {
 #pragma unroll
-    for (int k = 0; k < 4; k++) {      // four loads in flight per thread
-      const uint64_t r = r0 + k * 256 + threadIdx.x;
-      v[k] = r < ch.end ? in[r] : 0;
+      for (int k = 0; k < CNT_U; k++) cur[k] = p[k * 256 + tid];
     }
+    for (uint64_t r0 = 0; r0 < full; r0 += BATCH) {
+      uint64_t nxt[CNT_U];
+      const bool more = r0 + BATCH < full;
+      if (more) {
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-      const uint64_t r = r0 + k * 256 + threadIdx.x;
-      const bool valid = r < ch.end;
-      const uint32_t d = valid ? digit_at(v[k], shift, R - 1) : 0u;
-      const uint64_t act = __ballot(valid);
-      // valid lanes are a prefix of the wave: lane 0 holds the first digit
-      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-      const uint64_t same = __ballot(valid && d == d0);
-      if (valid) {
-        if (same == act) {
-          if (__lane_id() == 0) atomicAdd(&hist[d], (uint32_t)__popcll(act));
-        } else {
-          atomicAdd(&hist[d], 1u);
-        }
+        for (int k = 0; k < CNT_U; k++) nxt[k] = p[r0 + BATCH + k * 256 + tid];
+      }
+#pragma unroll
+      for (int k = 0; k < CNT_U; k++) atomicAdd(&hist[digit_at(cur[k], shift, R - 1)], 1u);
+      if (more) {
+#pragma unroll
+        for (int k = 0; k < CNT_U; k++) cur[k] = nxt[k];
       }
     }
-  }
-  __syncthreads();
-  uint32_t* row = cnt + (size_t)ci * R;
-  for (uint32_t d = threadIdx.x; d < R; d += 256) row[d] = hist[d];
+    for (uint64_t r = full + tid; r < n; r += 256) atomicAdd(&hist[digit_at(p[r], shift, R - 1)], 1u);
+    __syncthreads();
+    uint32_t* row = cnt + (size_t)ci * R;
+    for (uint32_t d = tid; d < R; d += 256) row[d] = hist[d];
   }
 }
 
@@ -385,6 +391,12 @@ int scatter_variant(int v, bool set) {
   if (set) g_scatter_variant = v;
   return old;
 }
+static int g_scatter_wgs = 0;       // workgroups per CU; 0 = the occupancy query's answer
+int scatter_wgs(int v, bool set) {
+  const int old = g_scatter_wgs;
+  if (set) g_scatter_wgs = v;
+  return old;
+}
 
 template <int RB, int BLOCK, int IPT>
 static void scatter_go(uint32_t nchunks, const uint64_t* in, uint64_t* out,
@@ -393,9 +405,11 @@ static void scatter_go(uint32_t nchunks, const uint64_t* in, uint64_t* out,
   int dev = 0, ncu = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, scatter_kernel<RB, BLOCK, IPT>, BLOCK, 0) !=
-          hipSuccess ||
-      per_cu < 1)
+  if (g_scatter_wgs > 0)
+    per_cu = g_scatter_wgs;
+  else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, scatter_kernel<RB, BLOCK, IPT>,
+                                                         BLOCK, 0) != hipSuccess ||
+           per_cu < 1)
     per_cu = 1;
   uint32_t grid = (uint32_t)ncu * (uint32_t)per_cu;
   if (grid > nchunks) grid = nchunks;

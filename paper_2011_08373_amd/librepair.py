@@ -125,7 +125,7 @@ _u32p = C.POINTER(C.c_uint32)
 _L.rp_instrument.argtypes = [C.POINTER(RpProgram), C.POINTER(RpInstrumentOpts),
                              C.c_void_p, C.c_void_p, C.c_uint32, _u32p, C.c_void_p, C.c_uint32,
                              _u32p, C.c_void_p, C.c_uint32, _u32p]
-TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE, TUNE_TIMING = 0, 1, 2
+TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE, TUNE_TIMING, TUNE_SCATTER_WGS = 0, 1, 2, 3
 
 
 def lib():
@@ -439,7 +439,7 @@ _tuning_epoch = [0]      # bumped by every tuning change (workspace sizes depend
 
 
 def set_tuning(knob: int, value: int) -> int:
-    if knob != TUNE_TIMING:          # the sort knobs change workspace sizes
+    if knob in (TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE):   # they change workspace sizes
         _tuning_epoch[0] += 1
     return _L.rp_set_tuning(int(knob), int(value))
 

@@ -102,6 +102,13 @@ def test_tuning_knobs(L):
         assert L.set_tuning(L.TUNE_TIMING, -1) == -1
     finally:
         L.set_tuning(L.TUNE_TIMING, old)
+    old = L.set_tuning(L.TUNE_SCATTER_WGS, 4)
+    try:
+        assert old == 0                                          # the occupancy query
+        assert L.set_tuning(L.TUNE_SCATTER_WGS, 9) == -1
+        assert L.set_tuning(L.TUNE_SCATTER_WGS, 0) == 4
+    finally:
+        L.set_tuning(L.TUNE_SCATTER_WGS, old)
 
 
 def test_invalid_kernel_does_no_device_work(L):
