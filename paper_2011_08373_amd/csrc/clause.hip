@@ -10,7 +10,8 @@
 //     Only the first racing partner j of each point is needed: every later
 //     partner's clause is a superset, hence subsumed;
 //   - phi := reduce(phi + learned): sorted by (pos, neg), duplicates and
-//     subsumed clauses dropped.  A subset precedes its supersets in that
+//     subsumed clauses dropped (a learned empty clause, two racing points
+//     with no barrier slot between them, leaves phi = {empty} at once).  A subset precedes its supersets in that
 //     order, so each clause is tested against earlier ones only.  Up to 2048
 //     clauses are merged in LDS, more in the job's scratch.
 #include "common.h"
@@ -82,7 +83,7 @@ constexpr uint32_t CL_BITS = 1024;  // points whose slot bits are staged in LDS
 
 // learn: 0 = only decide SAFE (the check call), 1 = learn and reduce.
 __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict__ jobs, int learn) {
-  __shared__ uint32_t s_n, s_races, s_first, s_nbar;
+  __shared__ uint32_t s_n, s_races, s_first, s_nbar, s_empty;
   __shared__ uint32_t sm[CL_BLOCK / 64];
   __shared__ uint32_t keep[4096];   // bitset over up to 131072 clauses
   __shared__ rp_clause s_cl[CL_LDS];
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
   const uint32_t P = J.P;
   const uint64_t x = st->x;
   const uint64_t div = st->divergent;
-  if (tid == 0) { s_n = 0; s_races = 0; s_first = NONE32; }
+  if (tid == 0) { s_n = 0; s_races = 0; s_first = NONE32; s_empty = 0; }
   __syncthreads();
   for (uint32_t row = tid; row < 2 * P; row += CL_BLOCK) {
     if (J.minj[row] != NONE32) {
@@ -184,6 +185,7 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
       if (j == NONE32) continue;
       const uint32_t lv = row / P, i = row % P;
       const uint64_t pos = between(lv, i, j);
+      if (pos == 0) s_empty = 1;      // no slot between them: the empty clause
       const uint32_t slot = atomicAdd(&s_n, 1u);
       rp_clause c;
       c.pos = pos;
@@ -199,6 +201,18 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
     }
   }
   __syncthreads();
+  if (s_empty) {
+    // the empty clause subsumes every other: phi reduces to it alone (and
+    // the next Solve proves UNSAT)
+    if (tid == 0) {
+      rp_clause e;
+      e.pos = 0;
+      e.neg = 0;
+      J.phi[0] = e;
+      st->n_phi = 1;
+    }
+    return;
+  }
   const uint32_t n = n_phi + s_n;
   uint32_t n2 = 1;
   while (n2 < n) n2 <<= 1;
@@ -217,15 +231,25 @@ __global__ __launch_bounds__(CL_BLOCK) void clause_kernel(const Job* __restrict_
   // keep = first of its duplicates and not a strict superset of an earlier clause
   for (uint32_t q = tid; q < (n + 31) / 32; q += CL_BLOCK) keep[q] = 0;
   __syncthreads();
+  // (eight earlier clauses are read before any is tested, so the reads of
+  // one step overlap instead of each waiting for the last)
+  auto strict_subset = [](const rp_clause& b, const rp_clause& a) {
+    return (b.pos & ~a.pos) == 0 && (b.neg & ~a.neg) == 0 && (b.pos != a.pos || b.neg != a.neg);
+  };
   for (uint32_t a = tid; a < n; a += CL_BLOCK) {
     const rp_clause ca = sc[a];
     bool k = a == 0 || sc[a - 1].pos != ca.pos || sc[a - 1].neg != ca.neg;
-    for (uint32_t b = 0; k && b < a; b++) {
-      const rp_clause cb = sc[b];
-      if ((cb.pos & ~ca.pos) == 0 && (cb.neg & ~ca.neg) == 0 &&
-          (cb.pos != ca.pos || cb.neg != ca.neg))
-        k = false;
+    uint32_t b = 0;
+    for (; k && b + 8 <= a; b += 8) {
+      rp_clause cb[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) cb[u] = sc[b + u];
+#pragma unroll
+      for (int u = 0; u < 8; u++)
+        if (strict_subset(cb[u], ca)) k = false;
     }
+    for (; k && b < a; b++)
+      if (strict_subset(sc[b], ca)) k = false;
     if (k) atomicOr(&keep[a >> 5], 1u << (a & 31));
   }
   __syncthreads();

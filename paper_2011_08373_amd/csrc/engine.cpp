@@ -409,7 +409,8 @@ int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStrea
   staging.resize(L.meta);
   const int rc = prepare_jobs(v, o, L, d, staging.data(), s, tm);
   if (rc != RP_OK) return rc;
-  HIPCHK(launch_solve((const Job*)(d + L.o_jobs), 1, s));
+  // the first Solve (an empty phi is answered by the initial x = 0)
+  if (!job.phi0.empty()) HIPCHK(launch_solve((const Job*)(d + L.o_jobs), 1, s));
   std::memcpy(&out.job, staging.data() + L.o_jobs, sizeof(Job));
   return RP_OK;
 }
@@ -492,7 +493,11 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
     tm.mark(T_CLAUSE);
   } else {
     uint32_t* dactive = (uint32_t*)(d + L.o_err) + 8;
-    HIPCHK(launch_solve(djobs, (uint32_t)N, s));
+    // the first Solve of Alg. 1: with no option units phi is empty and its
+    // answer is x = 0 (weight 0), which the job states already hold
+    bool any_units = false;
+    for (const JobInput& j : jobs) any_units |= !j.phi0.empty();
+    if (any_units) HIPCHK(launch_solve(djobs, (uint32_t)N, s));
     tm.mark(T_SOLVE, 2);
     auto round = [&]() -> hipError_t {
       hipError_t e;

@@ -33,7 +33,7 @@ enum Op { OP_CHECK = 0, OP_CLAUSES = 1, OP_REPAIR = 2, OP_SOLVE = 3, OP_FIRST = 
 
 struct JobInput {
   const Plan* plan;
-  uint64_t x;                       // assignment (check / clauses)
+  uint64_t x = 0;                   // assignment (check / clauses; a repair starts at 0)
   std::vector<rp_clause> phi0;      // initial constraint set (repair: option units)
   uint32_t policy = 0, max_rounds = 0;
   uint32_t solver = 0;              // 0 exact Solve, 1 greedy hitting set (mhs)
