@@ -25,15 +25,20 @@ __device__ __forceinline__ bool cl_less(const rp_clause& a, const rp_clause& b) 
   return a.pos != b.pos ? a.pos < b.pos : a.neg < b.neg;
 }
 
-// Bitonic sort of c[0..n2) (n2 a power of two) by one workgroup.  A step
-// that pairs elements less than 64 apart stays inside one wave's elements
-// (thread t handles t, t + CL_BLOCK, ...): the wave's lanes run in lock step
-// and its LDS operations complete in order, so between two such steps no
-// workgroup barrier is needed; one is needed after a step that pairs
-// elements of different waves and before the next such step.
+// Bitonic sort of c[0..n2) (n2 a power of two) by one workgroup.  Element i
+// sits in lane i % 64 of wave (i % CL_BLOCK) / 64, so a step that pairs
+// elements less than 64 apart pairs lanes of one wave.  Each merge level k
+// runs its steps with a stride of 64 or more through memory (a workgroup
+// barrier after each), then loads every element once and runs the steps
+// with smaller strides in registers, exchanging partners by lane shuffles,
+// and stores it back: the array crosses LDS once per level for those steps
+// instead of once per step.
 __device__ void block_bitonic(rp_clause* c, uint32_t n2) {
+  const uint32_t lane = __lane_id();
+  const uint32_t wbase = (threadIdx.x >> 6) * 64;
   for (uint32_t k = 2; k <= n2; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+    uint32_t j = k >> 1;
+    for (; j >= 64; j >>= 1) {
       for (uint32_t i = threadIdx.x; i < n2; i += CL_BLOCK) {
         const uint32_t l = i ^ j;
         if (l > i) {
@@ -42,21 +47,34 @@ __device__ void block_bitonic(rp_clause* c, uint32_t n2) {
           if (up ? cl_less(b, a) : cl_less(a, b)) { c[i] = b; c[l] = a; }
         }
       }
-      // the next step: (k, j/2), or the first of the next k, (2k, k)
-      const uint32_t nj = j > 1 ? j >> 1 : k;
-      const bool more = j > 1 || (k << 1) <= n2;
-      if (j >= 64 || (more && nj >= 64)) {   // this step or the next crosses waves
-        __syncthreads();
-      } else {
-        // workgroup-scope fences: the compiler must not carry an element
-        // across the step in a register, since another lane may rewrite it
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      }
+      __syncthreads();
     }
+    // strides j .. 1 (j < 64) inside each wave; lanes past n2 (n2 < 64) take
+    // part in the shuffles with pad values and pair only among themselves
+    for (uint32_t b0 = wbase; b0 < n2; b0 += CL_BLOCK) {
+      const uint32_t i = b0 + lane;
+      rp_clause e;
+      if (i < n2) {
+        e = c[i];
+      } else {
+        e.pos = ~0ull;
+        e.neg = ~0ull;
+      }
+      const bool up = (i & k) == 0;
+      for (uint32_t jj = j; jj > 0; jj >>= 1) {
+        rp_clause p;
+        p.pos = __shfl_xor(e.pos, (int)jj);
+        p.neg = __shfl_xor(e.neg, (int)jj);
+        const bool lower = (i & jj) == 0;
+        // the lower element of a pair keeps the smaller one on an ascending
+        // run, the larger one on a descending run
+        const bool take = (up == lower) ? cl_less(p, e) : cl_less(e, p);
+        if (take) e = p;
+      }
+      if (i < n2) c[i] = e;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 __device__ __forceinline__ uint32_t block_excl_scan1024(uint32_t v, uint32_t* sm, uint32_t* total) {
