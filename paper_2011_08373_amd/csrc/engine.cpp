@@ -68,9 +68,12 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
     }
   }
   L.n_rec = rec;
-  // sort chunks (= generation items): whole sort tiles, at most ~64K chunks
+  // sort chunks (= generation items): whole sort tiles, at most ~16K chunks
+  // (the per-chunk digit counts and offsets of each pass are read and
+  // written by the column scans: fewer, longer chunks keep those tables
+  // small on billion-record logs)
   const uint64_t tile = sort_tile_size();
-  uint64_t chunk = std::max<uint64_t>(2 * tile, (rec + 65535) / 65536);
+  uint64_t chunk = std::max<uint64_t>(2 * tile, (rec + 16383) / 16384);
   chunk = (chunk + tile - 1) / tile * tile;
   L.chunk_len = chunk;
   for (size_t s = 0; s < L.ssegs.size(); s++) {
