@@ -169,7 +169,6 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
   using HistT = typename std::conditional<RANK_ADD, uint32_t, uint16_t>::type;
   __shared__ HistT whist[SC_WAVES][R];         // per-wave counts, then prefixes
   __shared__ uint32_t lstart[R];               // tile-local digit starts
-  __shared__ uint32_t tcount[R];
   __shared__ uint64_t grun[R];                 // next output slot per digit
   __shared__ uint64_t gofs[R];                 // grun - lstart for the tile
   __shared__ uint32_t scan_sm[SC_WAVES];
@@ -188,6 +187,8 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
   uint64_t base = ch.beg;
   // wave w owns records [w*64*IPT, (w+1)*64*IPT) of the tile; item k of
   // lane l is record w*64*IPT + k*64 + l (coalesced; rank order = input order)
+  for (uint32_t q = tid; q < SC_WAVES * R; q += SC_BLOCK) (&whist[0][0])[q] = 0;
+  __syncthreads();
   uint64_t key[SC_IPT];
   {
     const uint64_t rem = ch.end - base;
@@ -223,8 +224,6 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
         knext[k] = idx < nn ? in[nbase + idx] : 0;
       }
     }
-    for (uint32_t q = tid; q < SC_WAVES * R; q += SC_BLOCK) (&whist[0][0])[q] = 0;
-    __syncthreads();
     // Rank of each record among the wave's records of its digit, in input
     // order.  Per item: the lanes with the same digit (peers) from one ballot
     // per digit bit; the first peer adds the group's size to the wave's
@@ -275,24 +274,25 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
       for (int k = 0; k < SC_IPT; k++) rank[k] += __shfl(gbase[k], (int)first[k]);
     }
     __syncthreads();
-    for (uint32_t d = tid; d < R; d += SC_BLOCK) {
-      uint32_t run = 0;
-      for (int v = 0; v < SC_WAVES; v++) {
-        const uint32_t c = whist[v][d];
-        whist[v][d] = (HistT)run;
-        run += c;
-      }
-      tcount[d] = run;
-    }
-    __syncthreads();
-    {  // tile-local exclusive scan of the digit counts
+    {  // per digit: the waves' counts become prefixes over the waves; then
+       // the tile-local exclusive scan over digits gives each digit's start
+       // in the tile and its output offset, and the digit's next output slot
+       // moves past this tile
       constexpr uint32_t PER = (R + SC_BLOCK - 1) / SC_BLOCK;
       uint32_t c[PER];
       uint32_t local = 0;
       for (uint32_t q = 0; q < PER; q++) {
         const uint32_t d = tid * PER + q;
-        c[q] = d < R ? tcount[d] : 0;
-        local += c[q];
+        uint32_t run = 0;
+        if (d < R) {
+          for (int v = 0; v < SC_WAVES; v++) {
+            const uint32_t x = whist[v][d];
+            whist[v][d] = (HistT)run;
+            run += x;
+          }
+        }
+        c[q] = run;
+        local += run;
       }
       uint32_t inc = local;
       for (int o = 1; o < 64; o <<= 1) {
@@ -309,6 +309,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
         if (d < R) {
           lstart[d] = run;
           gofs[d] = grun[d] - run;
+          grun[d] += c[q];
         }
         run += c[q];
       }
@@ -332,8 +333,8 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
       if (dst >= sg.beg && dst < sg.end) out[dst] = kv;
       else atomicOr(err, ERR_RANGE);
     }
-    __syncthreads();
-    for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] += tcount[d];
+    // the wave counters are free again: clear them for the next tile
+    for (uint32_t q = tid; q < SC_WAVES * R; q += SC_BLOCK) (&whist[0][0])[q] = 0;
     __syncthreads();
     if (!has_next) break;
     if (nci != ci) {
