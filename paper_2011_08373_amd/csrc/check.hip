@@ -613,24 +613,27 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
         // second candidate (first candidate has this record's id): the first
         // streak start after it (a write) or the first write-streak start or
         // location start after it (a read)
-        uint64_t XWLm = Lm;
-        if (__ballot(valid && !W && c1 < 64 && same && p1 != NONE32)) {
-          // write-streak starts: writes whose id differs from the previous write
-          // of the chunk (a location start in between is caught by Lm first)
-          const uint64_t pm = Wm & lt;
-          const uint32_t pw = pm ? 63u - (uint32_t)__builtin_clzll(pm) : 0u;
-          const uint32_t idpw = buf_lo[2 * (b0 + pw)];
-          XWLm |= __ballot(W && pm && idpw != id);
+        uint32_t best = p1;
+        if (__ballot(valid && same && p1 != NONE32)) {
+          uint64_t XWLm = Lm;
+          if (__ballot(valid && !W && c1 < 64 && same && p1 != NONE32)) {
+            // write-streak starts: writes whose id differs from the previous write
+            // of the chunk (a location start in between is caught by Lm first)
+            const uint64_t pm = Wm & lt;
+            const uint32_t pw = pm ? 63u - (uint32_t)__builtin_clzll(pm) : 0u;
+            const uint32_t idpw = buf_lo[2 * (b0 + pw)];
+            XWLm |= __ballot(W && pm && idpw != id);
+          }
+          const uint64_t M = (W ? Xm : XWLm) & above(c1);
+          const uint32_t k2 = low_bit64(M);
+          const uint64_t e2 = buf[b0 + (k2 < 64 ? k2 : 0u)];
+          uint32_t p2;
+          if (k2 < 64) p2 = partner_of(e2);
+          else if (W) p2 = c1 == 64 ? pnx1 : pnx0;
+          else p2 = fw_id != id1 ? pfw : pnws;
+          if (same && p1 != NONE32) best = p2;
         }
-        const uint64_t M = (W ? Xm : XWLm) & above(c1);
-        const uint32_t k2 = low_bit64(M);
-        const uint64_t e2 = buf[b0 + (k2 < 64 ? k2 : 0u)];
-        uint32_t p2;
-        if (k2 < 64) p2 = partner_of(e2);
-        else if (W) p2 = c1 == 64 ? pnx1 : pnx0;
-        else p2 = fw_id != id1 ? pfw : pnws;
-        const uint32_t best = p1 == NONE32 ? NONE32 : (same ? p2 : p1);
-        if (valid && best < P && s_minj[i] > best) atomicMin(&s_minj[i], best);
+        if (valid && best < P) atomicMin(&s_minj[i], best);
         // carries for the positions from b0 on
         const uint32_t x0 = low_bit64(Xm), x1 = low_bit64(Xm & ~1ull);
         const uint32_t nx0 = x0 < 64 ? partner_of(((uint64_t)__builtin_amdgcn_readlane(eh, x0)) << 32) : pnx0;
