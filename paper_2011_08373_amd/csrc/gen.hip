@@ -26,21 +26,8 @@ constexpr uint32_t GEN_CACHE = 256;   // points staged in LDS per item
 template <int RB>
 __device__ __forceinline__ void count_digits(uint32_t* hist, uint64_t rec, int shift, bool valid) {
   constexpr uint32_t R = 1u << RB;
-  // the valid lanes of a call are a prefix of the wave: lane 0 is the first
-  const uint64_t act = __ballot(valid);
-  if (!act) return;
-  const uint32_t d = digit_at(rec, shift, R - 1);
-  const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-  if (!valid) return;
-  const int first = 0;
-  // all active lanes on one digit (the usual case for the high digits):
-  // one LDS add for the wave
-  const uint64_t same = __ballot(d == d0);
-  if (same == act) {
-    if ((int)__lane_id() == first) atomicAdd(&hist[d], (uint32_t)__popcll(act));
-  } else {
-    atomicAdd(&hist[d], 1u);
-  }
+  // one LDS add per record, no return value (the adds do not stall the wave)
+  if (valid) atomicAdd(&hist[digit_at(rec, shift, R - 1)], 1u);
 }
 
 // Wave-uniform copies (the values are the same in every lane; saying so
