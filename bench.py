@@ -356,8 +356,8 @@ def served_leg(L, torch, kms, rate, seconds, arena_gb):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--mode", default="literal", choices=("literal", "planted"))
     ap.add_argument("--config", default="plain-large", choices=("plain-large", "stress"),
                     help="kernel of the headline leg (the stress kernel for profiling runs)")
