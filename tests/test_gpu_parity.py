@@ -346,6 +346,42 @@ def test_batch_equals_plain(L):
         assert res2[a] == res[q], (a, q)
 
 
+def test_batch_many_kernels(L):
+    # more than 64 kernels: each round reads back only the count of running
+    # jobs, the verdicts once at the end; several rounds replay the graph
+    kms = [BF.tiny_kernel(np.random.default_rng(90_000 + q), bias=True) for q in range(80)]
+    for kw in (dict(), dict(policy=1)):
+        st, res = L.repair_batch(kms, **kw)
+        assert st == 0
+        assert max(r["rounds"] for r in res) >= 3
+        for q, km in enumerate(kms):
+            o = O.repair(km, **kw)
+            g = {k: res[q][k] for k in REPAIR_KEYS if k != "trajectory"}
+            assert g == {k: o[k] for k in REPAIR_KEYS if k != "trajectory"}, (kw, q)
+
+
+def test_timing_levels(L):
+    km = synth.generate("plain-small", seed=3)
+    old = L.set_tuning(L.TUNE_TIMING, 0)
+    try:
+        r0 = L.repair(km)
+        s = L.last_stats()
+        assert s["ms_total"] == 0 and s["ms_gen"] == 0 and s["ms_sort"] == 0
+        L.set_tuning(L.TUNE_TIMING, 1)
+        r1 = L.repair(km)
+        s = L.last_stats()
+        assert s["ms_total"] > 0 and s["ms_gen"] > 0 and s["ms_sort"] > 0
+        assert s["ms_clause"] == 0                 # rounds are not split at level 1
+        L.set_tuning(L.TUNE_TIMING, 2)
+        r2 = L.repair(km)
+        s = L.last_stats()
+        assert s["ms_total"] > 0 and s["ms_clause"] > 0
+        # timing never changes a result
+        assert same_repair(r0, r1) and same_repair(r1, r2)
+    finally:
+        L.set_tuning(L.TUNE_TIMING, old)
+
+
 def test_batch_policy_and_options(L):
     kms = _mixed_kernels()[:24]
     for kw in (dict(policy=1), dict(grid=0), dict(inspect=0), dict(max_rounds=1)):
