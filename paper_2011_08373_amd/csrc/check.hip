@@ -213,7 +213,8 @@ __device__ __forceinline__ uint64_t entry_at(const RecView& v, uint64_t q) {
 // Stages records [b, b + 64*K) of a log as entries (all loads first); lane 0
 // returns the raw record before b (0 when b == 0).
 template <int K>
-__device__ __forceinline__ uint64_t stage_entries(const RecView& v, uint64_t b, uint64_t* buf) {
+__device__ __forceinline__ uint64_t stage_entries(const RecView& v, uint64_t b, uint64_t* buf,
+                                                  uint64_t* ent = nullptr) {
   const int lane = __lane_id();
   uint64_t r[K];
   const uint64_t p0 = (lane == 0 && b > 0 && b - 1 < v.n) ? v.log[b - 1] : 0;
@@ -225,7 +226,9 @@ __device__ __forceinline__ uint64_t stage_entries(const RecView& v, uint64_t b, 
       uint64_t pr = __shfl_up(r[k], 1);
       const uint64_t last = k > 0 ? __shfl(r[k - 1], 63) : p0;   // every lane takes part
       if (lane == 0) pr = last;
-      buf[k * 64 + lane] = make_entry_of(v, r[k], pr, k == 0 && lane == 0 && b == 0);
+      const uint64_t en = make_entry_of(v, r[k], pr, k == 0 && lane == 0 && b == 0);
+      buf[k * 64 + lane] = en;
+      if (ent) ent[k] = en;
     }
   } else {
 #pragma unroll
@@ -238,7 +241,9 @@ __device__ __forceinline__ uint64_t stage_entries(const RecView& v, uint64_t b, 
       uint64_t pr = __shfl_up(r[k], 1);
       const uint64_t last = k > 0 ? __shfl(r[k - 1], 63) : p0;   // every lane takes part
       if (lane == 0) pr = last;
-      buf[k * 64 + lane] = make_entry(v, r[k], pr, b + k * 64 + lane);
+      const uint64_t en = make_entry(v, r[k], pr, b + k * 64 + lane);
+      buf[k * 64 + lane] = en;
+      if (ent) ent[k] = en;
     }
   }
   return p0;
@@ -557,13 +562,14 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
     const int nr = (int)((s1 - s0 + J0_CHUNKS * 64 - 1) / (J0_CHUNKS * 64));
     uint32_t pnx0 = NONE32, pnx1 = NONE32, pfw = NONE32, pnws = NONE32, fw_id = 0;
     uint64_t e_next = RUN_SENTINEL;     // first entry of the range after the current one
+    uint64_t ent[J0_CHUNKS + 1];        // this lane's entry of each staged chunk
     for (int r = nr - 1; r >= 0; r--) {
       const uint64_t wbeg = s0 + (uint64_t)r * (J0_CHUNKS * 64);
       const uint64_t wend = min(wbeg + (uint64_t)(J0_CHUNKS * 64), s1);
       if (r == nr - 1) {
         // the part's last range and the chunk after it (the walks' first
         // step) in LDS; carries for the positions from the end of the part
-        stage_entries<J0_CHUNKS + 1>(V, wbeg, buf);
+        stage_entries<J0_CHUNKS + 1>(V, wbeg, buf, ent);
         __builtin_amdgcn_wave_barrier();
         auto entry = [&](uint64_t q) -> uint64_t {
           return q - wbeg < J0_SPAN ? buf[q - wbeg] : entry_at(V, q);
@@ -585,14 +591,18 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
         // scanned (the one candidate read past the range)
         e_next = buf[0];
         __builtin_amdgcn_wave_barrier();
-        stage_entries<J0_CHUNKS>(V, wbeg, buf);
+        stage_entries<J0_CHUNKS>(V, wbeg, buf, ent);
         if (lane == 0) buf[J0_CHUNKS * 64] = e_next;
         __builtin_amdgcn_wave_barrier();
       }
       const int nch = (int)((wend - wbeg + 63) / 64);
-      for (int c = nch - 1; c >= 0; c--) {
+      // (unrolled: each chunk's own entry comes from the registers the
+      // staging left it in; the candidates after it are read from LDS)
+#pragma unroll
+      for (int c = J0_CHUNKS - 1; c >= 0; c--) {
+        if (c >= nch) continue;
         const uint32_t b0 = (uint32_t)c * 64;
-        const uint64_t e = buf[b0 + lane];
+        const uint64_t e = ent[c];
         const uint32_t id = (uint32_t)e, eh = (uint32_t)(e >> 32);
         const bool W = (eh >> (RUN_W - 32)) & 1;
         const bool L = (eh >> (RUN_LOC - 32)) & 1;
