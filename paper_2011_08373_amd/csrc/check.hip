@@ -415,17 +415,17 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
 // of one id (a new location or a new id starts one; the entry's X bit) and,
 // among the writes of a location, a "write streak" likewise.  Then the first
 // partner of
-//   - a write is the next record, or if that has the same id, the end of its
-//     streak;
+//   - a write is the end of its streak: the first later record with another
+//     id (the records before it share the write's id);
 //   - a read is the first write f after it, or if f has the same id, the end
 //     of f's write streak.
 // (A point racing with itself needs no case of its own: its next record with
 // another id is that partner.)  Each wave stages 512 records in LDS, plus the
 // 64 after them, and walks them in chunks of 64 from the last to the first.
-// Inside a chunk both candidates come from ballot masks; past it from
+// Inside a chunk the candidates come from ballot masks; past it from
 // wave-wide carries that hold partner points directly: the first streak start
-// at or after the chunk end and the first one after that, the first write
-// ahead in the location (its id and point) and its write-streak end.  The
+// at or after the chunk end, the first write ahead in the location (its id
+// and point) and its write-streak end.  The
 // carries are set up at the end of the range by short walks that start in the
 // staged lookahead chunk and stop at the end of the location.
 
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
     // the part is scanned backward in ranges of J0_CHUNKS chunks; the carries
     // at the end of a range are those left at the start of the range after it
     const int nr = (int)((s1 - s0 + J0_CHUNKS * 64 - 1) / (J0_CHUNKS * 64));
-    uint32_t pnx0 = NONE32, pnx1 = NONE32, pfw = NONE32, pnws = NONE32, fw_id = 0;
+    uint32_t pnx0 = NONE32, pfw = NONE32, pnws = NONE32, fw_id = 0;
     uint64_t e_next = RUN_SENTINEL;     // first entry of the range after the current one
     uint64_t ent[J0_CHUNKS + 1];        // this lane's entry of each staged chunk
     for (int r = nr - 1; r >= 0; r--) {
@@ -576,7 +576,6 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
         };
         if (wend < n) {
           pnx0 = partner_of(entry(walk_streak_start(entry, wbeg, wend, n)));
-          pnx1 = partner_of(entry(walk_streak_start(entry, wbeg, wend + 1, n)));
           const uint64_t fw = walk_first_write(entry, wbeg, wend, n);
           if (fw != NOPOS) {
             const uint64_t efw = entry(fw);
@@ -609,24 +608,23 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
         const bool valid = !((eh >> (RUN_END - 32)) & 1);
         const uint32_t i = eh & 0xFFFu;
         const uint64_t Wm = __ballot(W), Lm = __ballot(L), Xm = __ballot((eh >> (RUN_X - 32)) & 1);
-        // first candidate: the next record (a write), or the first write after
-        // this record before a location start (a read): in the chunk, else the
-        // carried one
-        // (for a read: the first write or location start after it; a
-        // location start there means no partner, which partner_of says)
-        const uint32_t c1 = W ? lane + 1 : low_bit64((Wm | Lm) & gt);   // chunk-local, 64 = past it
-        const uint64_t e1 = buf[b0 + c1];                                // inside the staged span
-        const bool in1 = W || c1 < 64;
+        // first candidate, in the chunk or else the carried one (a location
+        // start there means no partner, which partner_of says): for a write
+        // the first streak start after it -- the first record with another
+        // id, since the records up to it share this one's id -- so it is the
+        // partner; for a read the first write after it
+        const uint32_t c1 = low_bit64((W ? Xm : (Wm | Lm)) & gt);   // chunk-local, 64 = past it
+        const uint64_t e1 = buf[b0 + c1];                            // inside the staged span
+        const bool in1 = c1 < 64;
         const uint32_t id1 = in1 ? (uint32_t)e1 : fw_id;
-        const uint32_t p1 = in1 ? partner_of(e1) : pfw;
-        const bool same = id1 == id;
-        // second candidate (first candidate has this record's id): the first
-        // streak start after it (a write) or the first write-streak start or
-        // location start after it (a read)
+        const uint32_t p1 = in1 ? partner_of(e1) : (W ? pnx0 : pfw);
+        // a read whose first write has its own id: the partner is the first
+        // write-streak start or location start after that write
+        const bool same = !W && id1 == id;
         uint32_t best = p1;
         if (__ballot(valid && same && p1 != NONE32)) {
           uint64_t XWLm = Lm;
-          if (__ballot(valid && !W && c1 < 64 && same && p1 != NONE32)) {
+          if (__ballot(valid && c1 < 64 && same && p1 != NONE32)) {
             // write-streak starts: writes whose id differs from the previous write
             // of the chunk (a location start in between is caught by Lm first)
             const uint64_t pm = Wm & lt;
@@ -634,21 +632,18 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
             const uint32_t idpw = buf_lo[2 * (b0 + pw)];
             XWLm |= __ballot(W && pm && idpw != id);
           }
-          const uint64_t M = (W ? Xm : XWLm) & above(c1);
+          const uint64_t M = XWLm & above(c1);
           const uint32_t k2 = low_bit64(M);
           const uint64_t e2 = buf[b0 + (k2 < 64 ? k2 : 0u)];
           uint32_t p2;
           if (k2 < 64) p2 = partner_of(e2);
-          else if (W) p2 = c1 == 64 ? pnx1 : pnx0;
           else p2 = fw_id != id1 ? pfw : pnws;
           if (same && p1 != NONE32) best = p2;
         }
         if (valid && best < P) atomicMin(&s_minj[i], best);
         // carries for the positions from b0 on
-        const uint32_t x0 = low_bit64(Xm), x1 = low_bit64(Xm & ~1ull);
-        const uint32_t nx0 = x0 < 64 ? partner_of(((uint64_t)__builtin_amdgcn_readlane(eh, x0)) << 32) : pnx0;
-        pnx1 = x1 < 64 ? partner_of(((uint64_t)__builtin_amdgcn_readlane(eh, x1)) << 32) : pnx0;
-        pnx0 = nx0;
+        const uint32_t x0 = low_bit64(Xm);
+        if (x0 < 64) pnx0 = partner_of(((uint64_t)__builtin_amdgcn_readlane(eh, x0)) << 32);
         const uint32_t fl0 = low_bit64(Lm);
         const uint64_t wb = fl0 < 64 ? (Wm & ((1ull << fl0) - 1)) : Wm;
         if (wb) {
