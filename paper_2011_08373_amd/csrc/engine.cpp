@@ -86,6 +86,8 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   size_t off = 0;
   L.o_jobs = off; off = up(off + N * sizeof(Job));
   L.o_states = off; off = up(off + N * sizeof(JobState));
+  // error word, running-job count and scan tile counters: uploaded as zeros
+  L.o_err = off; off = up(off + 64);
   L.o_ssegs = off; off = up(off + L.ssegs.size() * sizeof(SortSeg));
   L.o_csegs = off; off = up(off + L.ssegs.size() * sizeof(ConfSeg));
   L.o_pts.resize(N); L.o_bany.resize(N); L.o_bgrid.resize(N); L.o_w.resize(N);
@@ -111,7 +113,6 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   L.o_cnt = off; off = up(off + (size_t)L.n_chunks * R * sizeof(uint32_t));
   L.o_tot = off; off = up(off + L.ssegs.size() * (size_t)R * sizeof(uint64_t));
   L.o_off = off; off = up(off + (size_t)L.n_chunks * R * sizeof(uint64_t));
-  L.o_err = off; off = up(off + 64);
   L.o_ivl.resize(N); L.o_minj.resize(N); L.o_j0.resize(N); L.o_phi.resize(N); L.o_scratch.resize(N);
   L.o_traj.resize(N); L.o_bitmap.resize(N); L.o_pairs.resize(N); L.o_ptotal.resize(N);
   L.phi_cap.resize(N); L.scratch_cap.resize(N);
@@ -271,8 +272,8 @@ namespace {
 int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const Layout& L,
                  uint8_t* d, uint8_t* hbuf, hipStream_t s, Timer& tm) {
   const size_t N = jobs.size();
-  // the job and state tables come first and are the only ones not written
-  // in full below
+  // the job and state tables and the error words come first and are the
+  // only ones not written in full below
   std::memset(hbuf, 0, L.o_ssegs);
   Job* hj = (Job*)(hbuf + L.o_jobs);
   JobState* hs = (JobState*)(hbuf + L.o_states);
@@ -343,7 +344,6 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     if (!jobs[j].phi0.empty())
       HIPCHK(hipMemcpyAsync(d + L.o_phi[j], d + L.o_phi0j[j],
                             jobs[j].phi0.size() * sizeof(rp_clause), hipMemcpyDeviceToDevice, s));
-  HIPCHK(launch_fill_u64((uint64_t*)(d + L.o_err), 8, 0, s));
   HIPCHK(launch_items((const Job*)(d + L.o_jobs), (const SortSeg*)(d + L.o_ssegs),
                       (uint32_t)L.ssegs.size(), L.n_chunks, L.chunk_len, (GenItem*)(d + L.o_items),
                       (SortChunk*)(d + L.o_chunks), s));
