@@ -11,7 +11,6 @@ uint32_t conf_tile_size();
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,
                       const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int passes,
                       hipStream_t s);
-hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 // generation items and sort chunks: chunk c of segment s covers its records
 // [(c - chunk_beg) * chunk_len, ...) up to the segment's end
 hipError_t launch_items(const Job* jobs, const SortSeg* segs, uint32_t nseg, uint32_t nchunks,

@@ -23,12 +23,6 @@ namespace rp {
 
 constexpr uint32_t SC_MAX_TILE = 8192;   // chunks are multiples of every tile shape
 
-__global__ void fill_u64_kernel(uint64_t* p, uint64_t n, uint64_t v) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = v;
-}
-
 // Per-chunk digit counts of one pass: cnt[chunk][d].  Whole batches of
 // CNT_U x 256 records are read with the next batch's loads issued before
 // the current one is counted, so each thread keeps CNT_U loads in flight
@@ -351,14 +345,6 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
 }
 
 uint32_t sort_tile_size() { return SC_MAX_TILE; }
-
-hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  uint64_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  fill_u64_kernel<<<(uint32_t)blocks, 256, 0, s>>>(p, n, v);
-  return hipGetLastError();
-}
 
 #define RB_SWITCH(rb, CALL)                             \
   switch (rb) {                                         \
