@@ -324,7 +324,8 @@ int rp_set_sort_digit_bits(int bits);
  *   RP_TUNE_SCATTER_SHAPE    radix-scatter tile: 0 = 512x16, 1 = 256x16,
  *                            2 = 256x32, 3 = 1024x8, 4 = 512x8 (default),
  *                            5 = 1024x4, 6 = 256x8 (threads x records per
- *                            thread);
+ *                            thread), 7 = 512x8 with streaming
+ *                            (non-temporal) key loads;
  *   RP_TUNE_TIMING           hipEvent timing behind rp_last_stats: 0 = none
  *                            (every ms_* field 0), 1 = the streaming kernels
  *                            (upload, generation, each radix pass and its

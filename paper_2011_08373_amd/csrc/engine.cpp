@@ -86,7 +86,8 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   size_t off = 0;
   L.o_jobs = off; off = up(off + N * sizeof(Job));
   L.o_states = off; off = up(off + N * sizeof(JobState));
-  // error word, running-job count and scan tile counters: uploaded as zeros
+  // words: 0 error, 8 running-job count, 9 conflict-tile counter, 10 scatter
+  // chunk ticket; uploaded as zeros
   L.o_err = off; off = up(off + 64);
   L.o_ssegs = off; off = up(off + L.ssegs.size() * sizeof(SortSeg));
   L.o_csegs = off; off = up(off + L.ssegs.size() * sizeof(ConfSeg));
@@ -365,9 +366,9 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     const uint64_t* in = (const uint64_t*)(d + ((p % 2 == 0) ? L.o_recA : L.o_recB));
     uint64_t* out = (uint64_t*)(d + ((p % 2 == 0) ? L.o_recB : L.o_recA));
     HIPCHK(launch_sort_scan((int)L.rb, in, dss, (uint32_t)L.ssegs.size(), dch, nch, p, dcnt, dtot,
-                            doff, p == 0, s));
+                            doff, derr + 10, p == 0, s));
     tm.mark(T_SORTPASS);
-    HIPCHK(launch_sort_scatter((int)L.rb, in, out, dss, dch, nch, p, doff, derr, s));
+    HIPCHK(launch_sort_scatter((int)L.rb, in, out, dss, dch, nch, p, doff, derr + 10, derr, s));
     tm.mark(T_SORT);
   }
   tm.mark(T_SORT, 2);

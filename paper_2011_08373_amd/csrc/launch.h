@@ -17,10 +17,13 @@ hipError_t launch_items(const Job* jobs, const SortSeg* segs, uint32_t nseg, uin
                         uint64_t chunk_len, GenItem* items, SortChunk* chunks, hipStream_t s);
 hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uint32_t nseg,
                             const SortChunk* chunks, uint32_t nchunks, int pass, uint32_t* cnt,
-                            uint64_t* tot, uint64_t* off, bool counts_ready, hipStream_t s);
+                            uint64_t* tot, uint64_t* off, uint32_t* ticket, bool counts_ready,
+                            hipStream_t s);
+// ticket: one device word, set to zero by launch_sort_scan of the same pass
 hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
                                const SortChunk* chunks, uint32_t nchunks, int pass,
-                               const uint64_t* off, uint32_t* err, hipStream_t s);
+                               const uint64_t* off, uint32_t* ticket, uint32_t* err,
+                               hipStream_t s);
 constexpr int IVL_RESOLVE = 0, IVL_CHECK = 1, IVL_ZERO = 2;
 hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int mode, hipStream_t s);
 hipError_t launch_save_j0(const Job* jobs, uint32_t njobs, hipStream_t s);

@@ -11,8 +11,12 @@
 //   scatter_kernel   per chunk, tiles of records are ranked stably with
 //                    64-lane ballots, staged in LDS in digit order and written
 //                    out as contiguous digit runs; a persistent grid sized to
-//                    the resident workgroups takes the chunks in turn.
-// No workgroup ever waits on another, so nothing here can stall the grid.
+//                    the resident workgroups takes chunks from a ticket
+//                    counter (reset by the column scan of the same pass), so
+//                    equal chunks that do not divide evenly among the
+//                    workgroups leave no idle tail.
+// No workgroup ever waits on another (a ticket is one atomic add), so nothing
+// here can stall the grid.
 #include <algorithm>
 #include <type_traits>
 
@@ -97,10 +101,13 @@ template <int RB>
 __global__ __launch_bounds__(256) void colscan_kernel(const uint32_t* __restrict__ cnt,
                                                       const SortSeg* __restrict__ segs,
                                                       const uint64_t* __restrict__ tot,
-                                                      uint64_t* __restrict__ off) {
+                                                      uint64_t* __restrict__ off,
+                                                      uint32_t* __restrict__ ticket) {
   constexpr uint32_t R = 1u << RB;
   __shared__ uint64_t sm[4];
   __shared__ uint64_t s_base;
+  // the scatter of this pass hands out its chunks from zero
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;
   const uint32_t seg = blockIdx.x / R, d = blockIdx.x % R;
   const int lane = __lane_id(), w = threadIdx.x >> 6;
   // records of smaller digits in this segment
@@ -144,7 +151,16 @@ __device__ __forceinline__ uint64_t ballot_nonzero(uint32_t v) {
   return m;
 }
 
-template <int RB, int SC_BLOCK, int SC_IPT>
+// Key loads of the scatter: plain, or streaming (non-temporal: the lines are
+// not kept in the caches for reuse), which pays off on logs small enough for
+// the caches to hold the output runs being written.
+template <bool NTL>
+__device__ __forceinline__ uint64_t load_key(const uint64_t* p) {
+  if constexpr (NTL) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <int RB, int SC_BLOCK, int SC_IPT, bool NTL>
 __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __restrict__ in,
                                                            uint64_t* __restrict__ out,
                                                            const SortChunk* __restrict__ chunks,
@@ -152,6 +168,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
                                                            const SortSeg* __restrict__ segs,
                                                            int pass,
                                                            const uint64_t* __restrict__ off,
+                                                           uint32_t* __restrict__ ticket,
                                                            uint32_t* err) {
   constexpr uint32_t R = 1u << RB;
   constexpr int SC_WAVES = SC_BLOCK / 64;
@@ -166,14 +183,23 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
   __shared__ uint64_t grun[R];                 // next output slot per digit
   __shared__ uint64_t gofs[R];                 // grun - lstart for the tile
   __shared__ uint32_t scan_sm[SC_WAVES];
+  __shared__ uint32_t s_next[2];               // chunk tickets, one chunk ahead
 
   const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
   const uint64_t lt = lanemask_lt();
   const uint32_t wbase = (uint32_t)w * 64 * SC_IPT;
-  // persistent: workgroups take chunks in turn, tile by tile; the keys of the
-  // next tile are loaded while the current one is ranked and written
+  // persistent: workgroup b starts with chunk b and then takes chunk
+  // gridDim.x + t for each ticket t it draws.  Thread 0 draws the ticket of
+  // the chunk after next while the first tile of a chunk is ranked (slot
+  // par of s_next; the next chunk's ticket is in slot par ^ 1), so the keys
+  // of the next tile can be loaded, across chunk ends too, while the current
+  // one is ranked and written.  A workgroup's tickets increase, so it stops
+  // at its first ticket past the last chunk and drops no chunk.
   uint32_t ci = blockIdx.x;
   if (ci >= nchunks) return;
+  if (tid == 0) s_next[1] = gridDim.x + atomicAdd(ticket, 1u);
+  uint32_t par = 0;
+  bool first_tile = true;
   SortChunk ch = chunks[ci];
   SortSeg sg = segs[ch.seg];
   int shift = (int)sg.shift + pass * RB;
@@ -190,7 +216,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
 #pragma unroll
     for (int k = 0; k < SC_IPT; k++) {
       const uint32_t idx = wbase + k * 64 + lane;
-      key[k] = idx < n0 ? in[base + idx] : 0;
+      key[k] = idx < n0 ? load_key<NTL>(&in[base + idx]) : 0;
     }
   }
   for (;;) {
@@ -201,7 +227,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
     uint64_t nbase = base + SC_TILE;
     SortChunk nch = ch;
     if (nbase >= ch.end) {
-      nci = ci + gridDim.x;
+      nci = s_next[par ^ 1];
       if (nci < nchunks) {
         nch = chunks[nci];
         nbase = nch.beg;
@@ -215,7 +241,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
 #pragma unroll
       for (int k = 0; k < SC_IPT; k++) {
         const uint32_t idx = wbase + k * 64 + lane;
-        knext[k] = idx < nn ? in[nbase + idx] : 0;
+        knext[k] = idx < nn ? load_key<NTL>(&in[nbase + idx]) : 0;
       }
     }
     // Rank of each record among the wave's records of its digit, in input
@@ -267,6 +293,8 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
 #pragma unroll
       for (int k = 0; k < SC_IPT; k++) rank[k] += __shfl(gbase[k], (int)first[k]);
     }
+    if (first_tile && tid == 0) s_next[par] = gridDim.x + atomicAdd(ticket, 1u);
+    first_tile = false;
     __syncthreads();
     {  // per digit: the waves' counts become prefixes over the waves; then
        // the tile-local exclusive scan over digits gives each digit's start
@@ -333,6 +361,8 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
     if (!has_next) break;
     if (nci != ci) {
       ci = nci;
+      par ^= 1;
+      first_tile = true;
       ch = nch;
       sg = segs[ch.seg];
       shift = (int)sg.shift + pass * RB;
@@ -357,7 +387,8 @@ uint32_t sort_tile_size() { return SC_MAX_TILE; }
 
 hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uint32_t nseg,
                             const SortChunk* chunks, uint32_t nchunks, int pass, uint32_t* cnt,
-                            uint64_t* tot, uint64_t* off, bool counts_ready, hipStream_t s) {
+                            uint64_t* tot, uint64_t* off, uint32_t* ticket, bool counts_ready,
+                            hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
   const uint32_t R = 1u << rb;
   if (!counts_ready) {
@@ -368,7 +399,7 @@ hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uin
     RB_SWITCH(rb, (count_kernel<RBV><<<grid, 256, 0, s>>>(in, chunks, nchunks, segs, pass, cnt)));
   }
   RB_SWITCH(rb, (colsum_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot)));
-  RB_SWITCH(rb, (colscan_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot, off)));
+  RB_SWITCH(rb, (colscan_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot, off, ticket)));
   return hipGetLastError();
 }
 
@@ -385,52 +416,58 @@ int scatter_wgs(int v, bool set) {
   return old;
 }
 
-template <int RB, int BLOCK, int IPT>
+template <int RB, int BLOCK, int IPT, bool NTL = false>
 static void scatter_go(uint32_t nchunks, const uint64_t* in, uint64_t* out,
                        const SortChunk* chunks, const SortSeg* segs, int pass,
-                       const uint64_t* off, uint32_t* err, hipStream_t s) {
+                       const uint64_t* off, uint32_t* ticket, uint32_t* err, hipStream_t s) {
   int dev = 0, ncu = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (g_scatter_wgs > 0)
     per_cu = g_scatter_wgs;
-  else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, scatter_kernel<RB, BLOCK, IPT>,
+  else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, scatter_kernel<RB, BLOCK, IPT, NTL>,
                                                          BLOCK, 0) != hipSuccess ||
            per_cu < 1)
     per_cu = 1;
   uint32_t grid = (uint32_t)ncu * (uint32_t)per_cu;
   if (grid > nchunks) grid = nchunks;
-  scatter_kernel<RB, BLOCK, IPT><<<grid, BLOCK, 0, s>>>(in, out, chunks, nchunks, segs, pass, off, err);
+  scatter_kernel<RB, BLOCK, IPT, NTL><<<grid, BLOCK, 0, s>>>(in, out, chunks, nchunks, segs, pass, off, ticket,
+                                                              err);
 }
 
 template <int RB>
 static void scatter_launch(int variant, uint32_t nchunks, const uint64_t* in, uint64_t* out,
                            const SortChunk* chunks, const SortSeg* segs, int pass,
-                           const uint64_t* off, uint32_t* err, hipStream_t s) {
+                           const uint64_t* off, uint32_t* ticket, uint32_t* err,
+                           hipStream_t s) {
   switch (variant) {
-    case 1: scatter_go<RB, 256, 16>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
-    case 2: scatter_go<RB, 256, 32>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
-    case 4: scatter_go<RB, 512, 8>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
-    case 5: scatter_go<RB, 1024, 4>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
-    case 6: scatter_go<RB, 256, 8>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
+    case 1: scatter_go<RB, 256, 16>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
+    case 2: scatter_go<RB, 256, 32>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
+    case 4: scatter_go<RB, 512, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
+    case 5: scatter_go<RB, 1024, 4>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
+    case 6: scatter_go<RB, 256, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
+    case 7:
+      scatter_go<RB, 512, 8, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
+      break;
     case 3:
       // 16 waves of per-digit counters do not fit LDS beside the tile for
       // wide digits
       if constexpr (RB <= 9) {
-        scatter_go<RB, 1024, 8>(nchunks, in, out, chunks, segs, pass, off, err, s);
+        scatter_go<RB, 1024, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
         break;
       }
       [[fallthrough]];
-    default: scatter_go<RB, 512, 16>(nchunks, in, out, chunks, segs, pass, off, err, s); break;
+    default: scatter_go<RB, 512, 16>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
   }
 }
 
 hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
                                const SortChunk* chunks, uint32_t nchunks, int pass,
-                               const uint64_t* off, uint32_t* err, hipStream_t s) {
+                               const uint64_t* off, uint32_t* ticket, uint32_t* err,
+                               hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
   const int v = g_scatter_variant;
-  RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, pass, off, err, s)));
+  RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, pass, off, ticket, err, s)));
   return hipGetLastError();
 }
 
