@@ -324,8 +324,10 @@ int rp_set_sort_digit_bits(int bits);
  *   RP_TUNE_SCATTER_SHAPE    radix-scatter tile: 0 = 512x16, 1 = 256x16,
  *                            2 = 256x32, 3 = 1024x8, 4 = 512x8 (default),
  *                            5 = 1024x4, 6 = 256x8 (threads x records per
- *                            thread), 7 = 512x8 with streaming
- *                            (non-temporal) key loads;
+ *                            thread), 7 = 512x8, 8 = 1024x8, 9 = 512x16,
+ *                            each with streaming (non-temporal) key loads;
+ *                            1024x8 tiles (3, 8) take 512x16 for digits
+ *                            wider than 9 bits;
  *   RP_TUNE_TIMING           hipEvent timing behind rp_last_stats: 0 = none
  *                            (every ms_* field 0), 1 = the streaming kernels
  *                            (upload, generation, each radix pass and its

@@ -14,7 +14,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
-CANDIDATES = [(rb, shape) for rb in (8, 9, 10, 11) for shape in range(8)]
+CANDIDATES = [(rb, shape) for rb in (8, 9, 10, 11) for shape in range(10)]
 
 
 def _arch() -> str:

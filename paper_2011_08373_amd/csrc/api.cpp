@@ -337,7 +337,7 @@ int rp_set_tuning(int knob, int value) {
       if (value != 0 && (value < 8 || value > 11)) return -1;
       return g_digit_bits_ref(value, true);
     case RP_TUNE_SCATTER_SHAPE:
-      if (value < 0 || value > 7) return -1;
+      if (value < 0 || value > 9) return -1;
       return scatter_variant(value, true);
     case RP_TUNE_SCATTER_WGS:
       if (value < 0 || value > 8) return -1;

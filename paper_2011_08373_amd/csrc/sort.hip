@@ -79,6 +79,8 @@ __global__ __launch_bounds__(256) void count_kernel(const uint64_t* __restrict__
   }
 }
 
+constexpr int CS_K = 8;   // column loads in flight per thread (colsum, colscan)
+
 // Column totals: tot[seg][d] = sum over the segment's chunks of cnt[chunk][d].
 template <int RB>
 __global__ __launch_bounds__(256) void colsum_kernel(const uint32_t* __restrict__ cnt,
@@ -88,8 +90,19 @@ __global__ __launch_bounds__(256) void colsum_kernel(const uint32_t* __restrict_
   __shared__ uint64_t sm[4];
   const uint32_t seg = blockIdx.x / R, d = blockIdx.x % R;
   const uint32_t c0 = segs[seg].chunk_beg, c1 = segs[seg].chunk_end;
+  // CS_K independent loads per thread and step: one memory round trip per
+  // 256 x CS_K chunks of the column, not per 256
   uint64_t s = 0;
-  for (uint32_t c = c0 + threadIdx.x; c < c1; c += 256) s += cnt[(size_t)c * R + d];
+  for (uint32_t cb = c0; cb < c1; cb += 256 * CS_K) {
+    uint32_t v[CS_K];
+#pragma unroll
+    for (int k = 0; k < CS_K; k++) {
+      const uint32_t c = cb + k * 256 + threadIdx.x;
+      v[k] = c < c1 ? cnt[(size_t)c * R + d] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < CS_K; k++) s += v[k];
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   if (__lane_id() == 0) sm[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -120,10 +133,18 @@ __global__ __launch_bounds__(256) void colscan_kernel(const uint32_t* __restrict
   __syncthreads();
   uint64_t run = s_base;
   const uint32_t c0 = segs[seg].chunk_beg, c1 = segs[seg].chunk_end;
-  for (uint32_t cb = c0; cb < c1; cb += 256) {
-    const uint32_t c = cb + threadIdx.x;
-    const uint64_t v = c < c1 ? cnt[(size_t)c * R + d] : 0;
-    uint64_t inc = v;
+  // steps of 256 x CS_K chunks; thread t takes CS_K consecutive chunks of a
+  // step, loaded together, and scans them after the block's scan of the
+  // per-thread sums
+  for (uint32_t cb = c0; cb < c1; cb += 256 * CS_K) {
+    const uint32_t cf = cb + threadIdx.x * CS_K;
+    uint32_t v[CS_K];
+#pragma unroll
+    for (int k = 0; k < CS_K; k++) v[k] = cf + k < c1 ? cnt[(size_t)(cf + k) * R + d] : 0;
+    uint64_t local = 0;
+#pragma unroll
+    for (int k = 0; k < CS_K; k++) local += v[k];
+    uint64_t inc = local;
     for (int o = 1; o < 64; o <<= 1) {
       uint64_t y = __shfl_up(inc, o);
       if (lane >= o) inc += y;
@@ -135,7 +156,12 @@ __global__ __launch_bounds__(256) void colscan_kernel(const uint32_t* __restrict
       if (q < w) pre += sm[q];
       all += sm[q];
     }
-    if (c < c1) off[(size_t)c * R + d] = run + pre + inc - v;
+    uint64_t at = run + pre + inc - local;
+#pragma unroll
+    for (int k = 0; k < CS_K; k++) {
+      if (cf + k < c1) off[(size_t)(cf + k) * R + d] = at;
+      at += v[k];
+    }
     run += all;
     __syncthreads();
   }
@@ -448,6 +474,15 @@ static void scatter_launch(int variant, uint32_t nchunks, const uint64_t* in, ui
     case 6: scatter_go<RB, 256, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
     case 7:
       scatter_go<RB, 512, 8, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
+      break;
+    case 9:
+      scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
+      break;
+    case 8:
+      if constexpr (RB <= 9)
+        scatter_go<RB, 1024, 8, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
+      else
+        scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
       break;
     case 3:
       // 16 waves of per-digit counters do not fit LDS beside the tile for

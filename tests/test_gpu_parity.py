@@ -234,7 +234,7 @@ def test_sort_knobs_full_size(L):
            L.set_tuning(L.TUNE_SCATTER_WGS, 0))
     try:
         for bits in (8, 9, 10, 11):
-            for shape in range(8):
+            for shape in range(10):
                 for wgs in (0, 1):
                     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, bits)
                     L.set_tuning(L.TUNE_SCATTER_SHAPE, shape)

@@ -90,7 +90,7 @@ def test_tuning_knobs(L):
     try:
         assert L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 10) == 9
         assert L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 7) == -1      # out of range
-        assert L.set_tuning(L.TUNE_SCATTER_SHAPE, 8) == -1
+        assert L.set_tuning(L.TUNE_SCATTER_SHAPE, 10) == -1
         assert L.set_tuning(L.TUNE_SCATTER_SHAPE, -1) == -1
         assert L.set_tuning(99, 0) == -1
     finally:
