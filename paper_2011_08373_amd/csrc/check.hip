@@ -504,10 +504,13 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
                                                         const uint32_t* __restrict__ total_at) {
   __shared__ uint64_t s_buf[CONF_WAVES][J0_SPAN];
   extern __shared__ uint32_t s_dyn[];        // [P] first partner, then [P] point | write bit << 12
-  const uint32_t total = *total_at;
-  const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
-  const uint32_t t0 = blockIdx.x * per;
-  const uint32_t t1 = min(t0 + per, total);
+  // the tiles' 64-record chunks, split evenly over the workgroups (whole
+  // tiles per workgroup would leave some with none when there are few tiles
+  // per workgroup)
+  constexpr uint32_t TC = CONF_TILE / 64;     // chunks per tile
+  const uint64_t nunits = (uint64_t)*total_at * TC;
+  const uint64_t u0 = nunits * blockIdx.x / gridDim.x;
+  const uint64_t u1 = nunits * (blockIdx.x + 1) / gridDim.x;
   // the wave index is uniform across the wave: say so, so that the range
   // bounds and the chunk loop stay scalar
   const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -520,7 +523,8 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
   uint32_t* s_minj = s_dyn;
   uint16_t* s_pw = nullptr;
   uint32_t P = 0;
-  for (uint32_t tile = t0; tile < t1;) {
+  for (uint64_t u = u0; u < u1;) {
+    const uint32_t tile = (uint32_t)(u / TC);
     int lo = 0, hi = nseg - 1;   // largest segment with ctile_beg <= tile
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -547,12 +551,13 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
     const ConfSeg& sg = segs[cur];
     const uint64_t n = sg.n;
     const RecView V = rec_view(jobs[sg.job], sg, s_pw);
-    // this workgroup's tiles of the segment, as one record span cut into one
-    // contiguous part per wave (whole chunks)
-    const uint32_t tend = cur + 1 < nseg ? min(t1, segs[cur + 1].ctile_beg) : t1;
-    const uint64_t rbeg = (uint64_t)(tile - sg.ctile_beg) * CONF_TILE;
-    const uint64_t rend = min((uint64_t)(tend - sg.ctile_beg) * CONF_TILE, n);
-    tile = tend;
+    // this workgroup's chunks of the segment, as one record span cut into
+    // one contiguous part per wave (whole chunks)
+    const uint64_t ub = (uint64_t)sg.ctile_beg * TC;
+    const uint64_t uend = cur + 1 < nseg ? min(u1, (uint64_t)segs[cur + 1].ctile_beg * TC) : u1;
+    const uint64_t rbeg = min((u - ub) * 64, n);
+    const uint64_t rend = min((uend - ub) * 64, n);
+    u = uend;
     const uint64_t part = (rend - rbeg + CONF_WAVES * 64 - 1) / (CONF_WAVES * 64) * 64;
     const uint64_t s0 = min(rbeg + (uint64_t)wv * part, rend);
     const uint64_t s1 = min(s0 + part, rend);
