@@ -80,7 +80,9 @@ typedef enum {
   RP_ERR_WORKSPACE = -3,    /* ws smaller than the required size */
   RP_ERR_DEVICE = -4,       /* a HIP call or a device-side check failed */
   RP_ERR_ROUNDS = -5,       /* max_rounds Verify calls made without a verdict */
-  RP_ERR_BUDGET = -6        /* server: the job can never fit the memory budget */
+  RP_ERR_BUDGET = -6,       /* server: the job can never fit the memory budget */
+  RP_ERR_SEARCH = -7        /* the exact solver's branch and bound spent its node
+                               budget (RP_TUNE_SOLVER_NODES) on one component */
 } rp_status;
 
 enum { RP_ACCESS = 0, RP_BARRIER = 1, RP_NOP = 2 };
@@ -210,9 +212,13 @@ rp_status rp_repair(const rp_kernel* k, const rp_repair_opts* opts,
  * every kernel (records, sort, run logs), each round is one captured hipGraph
  * (when `stream` is not NULL) over every kernel still running, and the host
  * reads one 32-bit count per round.  outs[j] gets kernel j's result exactly
- * as rp_repair would give it; a kernel that fails validation gets
- * RP_ERR_INVALID and the others still run.  Returns RP_OK unless the whole
- * call failed.  Workspace: rp_batch_workspace_bytes over the same kernels. */
+ * as rp_repair would give it, status included: a kernel that fails
+ * validation gets RP_ERR_INVALID, one whose constraint set or a table of its
+ * own overflows on the device RP_ERR_CAPACITY, one whose exact search spends
+ * its node budget RP_ERR_SEARCH -- and the others still run to their
+ * verdicts.  Returns RP_OK unless the whole call failed (then every outs[j]
+ * not rejected by validation reads RP_ERR_DEVICE).  Workspace:
+ * rp_batch_workspace_bytes over the same kernels. */
 size_t rp_batch_workspace_bytes(const rp_kernel* const* ks, uint32_t n);
 rp_status rp_repair_batch(const rp_kernel* const* ks, uint32_t n, const rp_repair_opts* opts,
                           rp_repair_out* outs, void* ws, size_t ws_bytes, void* stream);
@@ -338,9 +344,13 @@ int rp_set_sort_digit_bits(int bits);
  *                            microseconds of device idle time;
  *   RP_TUNE_SCATTER_WGS      resident workgroups per compute unit of the
  *                            persistent radix scatter: 0 = what the
- *                            occupancy query reports (default), else 1..8. */
+ *                            occupancy query reports (default), else 1..8;
+ *   RP_TUNE_SOLVER_NODES     log2 of the node budget of the exact solver's
+ *                            branch and bound on one component of the
+ *                            constraint set (4..40, default 28).  A job whose
+ *                            search spends it ends with RP_ERR_SEARCH. */
 enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2,
-       RP_TUNE_SCATTER_WGS = 3 };
+       RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4 };
 int rp_set_tuning(int knob, int value);
 
 #ifdef __cplusplus

@@ -36,7 +36,9 @@
 #include "oracle.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -233,6 +235,59 @@ void conflicts_literal(const or_kernel* k, u64 x, bool apply_x, PairSet& out) {
 // (array, block, address) for the same-block relation and by (array,
 // address) for the cross-block relation; within a location every pair of
 // points is examined.  Independent of any barrier assignment.
+
+// One location of the same-block relation: its records (point i, thread t)
+// sorted by (i, t), one per executing (point, thread).  Points i <= j
+// conflict there when one writes and two distinct threads are involved.
+struct SbRec { u32 i, t; };
+void same_block_location(const or_kernel* k, const SbRec* r, size_t n, PairSet& out) {
+  struct G { u32 i; u64 n; u32 t0; };
+  std::vector<G> pts;
+  for (size_t q = 0; q < n; q++) {
+    if (pts.empty() || pts.back().i != r[q].i) pts.push_back({r[q].i, 0, r[q].t});
+    pts.back().n++;  // distinct threads: one record per (point, block, thread)
+  }
+  for (size_t a = 0; a < pts.size(); a++) {
+    const or_point& pa = k->points[pts[a].i];
+    if (pa.is_write && pts[a].n >= 2) out.set(0, pts[a].i, pts[a].i);
+    for (size_t b = a + 1; b < pts.size(); b++) {
+      const or_point& pb = k->points[pts[b].i];
+      if (!pa.is_write && !pb.is_write) continue;
+      bool one_same_thread = pts[a].n == 1 && pts[b].n == 1 && pts[a].t0 == pts[b].t0;
+      if (!one_same_thread) out.set(0, pts[a].i, pts[b].i);
+    }
+  }
+}
+
+// One location of the cross-block relation (a global array): its records
+// (point i, block) sorted by (i, block), one per executing (point, block,
+// thread).  Points i <= j conflict there when one writes and two distinct
+// blocks are involved.
+struct XbRec { u32 i, blk; };
+void cross_block_location(const or_kernel* k, const XbRec* r, size_t n, PairSet& out) {
+  struct G { u32 i; u64 nblk; u32 b0; };
+  std::vector<G> pts;
+  for (size_t q = 0; q < n; q++) {
+    if (pts.empty() || pts.back().i != r[q].i) {
+      pts.push_back({r[q].i, 1, r[q].blk});
+    } else if (r[q].blk != r[q - 1].blk) {
+      pts.back().nblk++;  // distinct blocks of this point here
+    }
+  }
+  for (size_t a = 0; a < pts.size(); a++) {
+    const or_point& pa = k->points[pts[a].i];
+    if (pa.is_write && pts[a].nblk >= 2) out.set(1, pts[a].i, pts[a].i);
+    for (size_t b = a + 1; b < pts.size(); b++) {
+      const or_point& pb = k->points[pts[b].i];
+      if (!pa.is_write && !pb.is_write) continue;
+      bool one_same_block = pts[a].nblk == 1 && pts[b].nblk == 1 && pts[a].b0 == pts[b].b0;
+      if (!one_same_block) out.set(1, pts[a].i, pts[b].i);
+    }
+  }
+}
+
+// Every location of the whole kernel at once (records of all arrays and
+// blocks materialised together).
 void conflicts_grouped(const or_kernel* k, PairSet& out) {
   // same block
   {
@@ -252,29 +307,16 @@ void conflicts_grouped(const or_kernel* k, PairSet& out) {
       if (a.i != b.i) return a.i < b.i;
       return a.t < b.t;
     });
-    struct G { u32 i; u64 n; u32 t0; };
-    std::vector<G> pts;
+    std::vector<SbRec> loc;
     size_t s = 0;
     while (s < recs.size()) {
       size_t e = s;
       while (e < recs.size() && recs[e].arr == recs[s].arr && recs[e].blk == recs[s].blk &&
              recs[e].addr == recs[s].addr)
         e++;
-      pts.clear();
-      for (size_t r = s; r < e; r++) {
-        if (pts.empty() || pts.back().i != recs[r].i) pts.push_back({recs[r].i, 0, recs[r].t});
-        pts.back().n++;  // distinct threads: one record per (point, block, thread)
-      }
-      for (size_t a = 0; a < pts.size(); a++) {
-        const or_point& pa = k->points[pts[a].i];
-        if (pa.is_write && pts[a].n >= 2) out.set(0, pts[a].i, pts[a].i);
-        for (size_t b = a + 1; b < pts.size(); b++) {
-          const or_point& pb = k->points[pts[b].i];
-          if (!pa.is_write && !pb.is_write) continue;
-          bool one_same_thread = pts[a].n == 1 && pts[b].n == 1 && pts[a].t0 == pts[b].t0;
-          if (!one_same_thread) out.set(0, pts[a].i, pts[b].i);
-        }
-      }
+      loc.clear();
+      for (size_t r = s; r < e; r++) loc.push_back({recs[r].i, recs[r].t});
+      same_block_location(k, loc.data(), loc.size(), out);
       s = e;
     }
   }
@@ -295,33 +337,152 @@ void conflicts_grouped(const or_kernel* k, PairSet& out) {
       if (a.i != b.i) return a.i < b.i;
       return a.blk < b.blk;
     });
-    struct G { u32 i; u64 nblk; u32 b0; };
-    std::vector<G> pts;
+    std::vector<XbRec> loc;
     size_t s = 0;
     while (s < recs.size()) {
       size_t e = s;
       while (e < recs.size() && recs[e].arr == recs[s].arr && recs[e].addr == recs[s].addr) e++;
-      pts.clear();
-      for (size_t r = s; r < e; r++) {
-        if (pts.empty() || pts.back().i != recs[r].i) {
-          pts.push_back({recs[r].i, 1, recs[r].blk});
-        } else if (recs[r].blk != recs[r - 1].blk) {
-          pts.back().nblk++;  // distinct blocks of this point here
-        }
-      }
-      for (size_t a = 0; a < pts.size(); a++) {
-        const or_point& pa = k->points[pts[a].i];
-        if (pa.is_write && pts[a].nblk >= 2) out.set(1, pts[a].i, pts[a].i);
-        for (size_t b = a + 1; b < pts.size(); b++) {
-          const or_point& pb = k->points[pts[b].i];
-          if (!pa.is_write && !pb.is_write) continue;
-          bool one_same_block = pts[a].nblk == 1 && pts[b].nblk == 1 && pts[a].b0 == pts[b].b0;
-          if (!one_same_block) out.set(1, pts[a].i, pts[b].i);
-        }
-      }
+      loc.clear();
+      for (size_t r = s; r < e; r++) loc.push_back({recs[r].i, recs[r].blk});
+      cross_block_location(k, loc.data(), loc.size(), out);
       s = e;
     }
   }
+}
+
+// ----------------------------- conflicts, one array instance at a time
+// The same relation, evaluated per (array, block) for the same-block
+// relation and per (global array, address stripe) for the cross-block one,
+// so that only one such part of the records is held at a time.  The parts
+// are independent (a location lies in exactly one of them), so they are
+// handed out to a pool of host threads, each with its own pair set; the sets
+// are ORed at the end.  Stripe s of an array holds the addresses a with
+// a % stripes == s; the stripe count keeps a part near g_part records.
+int g_route = 0;              // 0: whole kernel at once; 1: one instance at a time
+int g_threads = 0;            // threads of route 1 (0: every host core)
+u64 g_part = 1ull << 25;      // records per cross-block part of route 1
+
+void same_block_part(const or_kernel* k, u32 arr, u32 blk, std::vector<std::pair<u64, SbRec>>& recs,
+                     PairSet& out) {
+  recs.clear();
+  for (u32 i = 0; i < k->n_points; i++) {
+    if (k->points[i].kind != ACCESS || k->points[i].array != arr) continue;
+    for (u32 t = 0; t < k->threads; t++)
+      if (active(k, i, blk, t)) recs.push_back({address(k, i, blk, t), SbRec{i, t}});
+  }
+  std::sort(recs.begin(), recs.end(), [](const std::pair<u64, SbRec>& a,
+                                         const std::pair<u64, SbRec>& b) {
+    if (a.first != b.first) return a.first < b.first;
+    if (a.second.i != b.second.i) return a.second.i < b.second.i;
+    return a.second.t < b.second.t;
+  });
+  std::vector<SbRec> loc;
+  size_t s = 0;
+  while (s < recs.size()) {
+    size_t e = s;
+    while (e < recs.size() && recs[e].first == recs[s].first) e++;
+    loc.clear();
+    for (size_t r = s; r < e; r++) loc.push_back(recs[r].second);
+    same_block_location(k, loc.data(), loc.size(), out);
+    s = e;
+  }
+}
+
+void cross_block_part(const or_kernel* k, u32 arr, u64 stripe, u64 stripes,
+                      std::vector<std::pair<u64, XbRec>>& recs, PairSet& out) {
+  recs.clear();
+  for (u32 i = 0; i < k->n_points; i++) {
+    if (k->points[i].kind != ACCESS || k->points[i].array != arr) continue;
+    for (u32 blk = 0; blk < k->blocks; blk++)
+      for (u32 t = 0; t < k->threads; t++)
+        if (active(k, i, blk, t)) {
+          const u64 a = address(k, i, blk, t);
+          if (a % stripes == stripe) recs.push_back({a, XbRec{i, blk}});
+        }
+  }
+  std::sort(recs.begin(), recs.end(), [](const std::pair<u64, XbRec>& a,
+                                         const std::pair<u64, XbRec>& b) {
+    if (a.first != b.first) return a.first < b.first;
+    if (a.second.i != b.second.i) return a.second.i < b.second.i;
+    return a.second.blk < b.second.blk;
+  });
+  std::vector<XbRec> loc;
+  size_t s = 0;
+  while (s < recs.size()) {
+    size_t e = s;
+    while (e < recs.size() && recs[e].first == recs[s].first) e++;
+    loc.clear();
+    for (size_t r = s; r < e; r++) loc.push_back(recs[r].second);
+    cross_block_location(k, loc.data(), loc.size(), out);
+    s = e;
+  }
+}
+
+void conflicts_per_instance(const or_kernel* k, PairSet& out) {
+  struct Task { u32 arr, blk; u64 stripe, stripes; bool cross; };
+  std::vector<Task> tasks;
+  for (u32 arr = 0; arr < k->n_arrays; arr++) {
+    u64 n_cross = 0;
+    bool used = false;
+    for (u32 i = 0; i < k->n_points; i++) {
+      if (k->points[i].kind != ACCESS || k->points[i].array != arr) continue;
+      used = true;
+      const u32 g = k->points[i].guard;
+      u64 nt = 0, nb = 0;
+      for (u32 t = 0; t < k->threads; t++)
+        if (t % k->guards[g].m == k->guards[g].r) nt++;
+      for (u32 blk = 0; blk < k->blocks; blk++)
+        if (!k->block_guards || blk % k->block_guards[g].m == k->block_guards[g].r) nb++;
+      n_cross += nt * nb;
+    }
+    if (!used) continue;
+    for (u32 blk = 0; blk < k->blocks; blk++) tasks.push_back({arr, blk, 0, 1, false});
+    if (k->arrays[arr].space == GLOBAL && k->blocks > 1) {
+      const u64 stripes = std::max<u64>(1, (n_cross + g_part - 1) / g_part);
+      for (u64 s = 0; s < stripes; s++) tasks.push_back({arr, 0, s, stripes, true});
+    }
+  }
+  unsigned nth = g_threads > 0 ? (unsigned)g_threads : std::thread::hardware_concurrency();
+  if (nth < 1) nth = 1;
+  if (nth > tasks.size()) nth = (unsigned)std::max<size_t>(1, tasks.size());
+  std::atomic<size_t> next(0);
+  std::vector<PairSet> sets(nth, PairSet(k->n_points));
+  auto work = [&](unsigned w) {
+    std::vector<std::pair<u64, SbRec>> sb;
+    std::vector<std::pair<u64, XbRec>> xb;
+    for (;;) {
+      const size_t q = next.fetch_add(1);
+      if (q >= tasks.size()) break;
+      const Task& t = tasks[q];
+      if (t.cross) cross_block_part(k, t.arr, t.stripe, t.stripes, xb, sets[w]);
+      else same_block_part(k, t.arr, t.blk, sb, sets[w]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (unsigned w = 1; w < nth; w++) pool.emplace_back(work, w);
+  work(0);
+  for (std::thread& th : pool) th.join();
+  for (const PairSet& s : sets)
+    for (size_t q = 0; q < s.bits.size(); q++) out.bits[q] |= s.bits[q];
+}
+
+// The conflict relation (independent of x) by the selected route.
+void conflicts(const or_kernel* k, PairSet& out) {
+  if (g_route == 1) conflicts_per_instance(k, out);
+  else conflicts_grouped(k, out);
+}
+
+// Races under x from the conflict relation: the conflicting pairs no
+// enabled barrier separates, in (level, i, j) order.
+void races_from(const or_kernel* k, u64 x, const PairSet& conf, std::vector<or_pair>& out) {
+  out.clear();
+  for (int lv = 0; lv < 2; lv++)
+    for (u32 i = 0; i < k->n_points; i++)
+      for (u32 j = i; j < k->n_points; j++) {
+        if (!conf.get(lv, i, j)) continue;
+        if (separated(k, x, i, j, lv == 1)) continue;
+        out.push_back({(uint16_t)i, (uint16_t)j, (uint8_t)lv, 0});
+      }
 }
 
 // Races under x, emitted in (level, i, j) order.
@@ -329,17 +490,15 @@ void races(const or_kernel* k, u64 x, bool literal, std::vector<or_pair>& out) {
   PairSet ps(k->n_points);
   if (literal) {
     conflicts_literal(k, x, true, ps);
-  } else {
-    conflicts_grouped(k, ps);
+    out.clear();
+    for (int lv = 0; lv < 2; lv++)
+      for (u32 i = 0; i < k->n_points; i++)
+        for (u32 j = i; j < k->n_points; j++)
+          if (ps.get(lv, i, j)) out.push_back({(uint16_t)i, (uint16_t)j, (uint8_t)lv, 0});
+    return;
   }
-  out.clear();
-  for (int lv = 0; lv < 2; lv++)
-    for (u32 i = 0; i < k->n_points; i++)
-      for (u32 j = i; j < k->n_points; j++) {
-        if (!ps.get(lv, i, j)) continue;
-        if (!literal && separated(k, x, i, j, lv == 1)) continue;
-        out.push_back({(uint16_t)i, (uint16_t)j, (uint8_t)lv, 0});
-      }
+  conflicts(k, ps);
+  races_from(k, x, ps, out);
 }
 
 // Positive clause of a race between i and j: the barrier variables of every
@@ -380,15 +539,22 @@ std::vector<or_clause> reduce(std::vector<or_clause> c) {
   return out;
 }
 
-std::vector<or_clause> clauses_under(const or_kernel* k, u64 x) {
+// GenerateClause over every race under x, given the conflict relation.
+std::vector<or_clause> clauses_from(const or_kernel* k, u64 x, const PairSet& conf) {
   std::vector<or_pair> rp;
-  races(k, x, false, rp);
+  races_from(k, x, conf, rp);
   std::vector<or_clause> c;
   for (const or_pair& p : rp) c.push_back({race_clause(k, p.i, p.j, p.level), 0});
   u64 div = divergent_if_enabled(k, false) & x;
   for (u32 s = 0; s < 64; s++)
     if ((div >> s) & 1) c.push_back({0, 1ull << s});
   return reduce(c);
+}
+
+std::vector<or_clause> clauses_under(const or_kernel* k, u64 x) {
+  PairSet conf(k->n_points);
+  conflicts(k, conf);
+  return clauses_from(k, x, conf);
 }
 
 // ------------------------------------------------------------------- solver
@@ -563,6 +729,14 @@ u64 weight_of(const uint32_t* w, u32 S, u64 x) {
 // =========================================================== C entry points
 extern "C" int or_validate(const or_kernel* k) { return validate(k); }
 
+extern "C" int or_set_route(int route, int threads, uint64_t part_records) {
+  const int old = g_route;
+  if (route == 0 || route == 1) g_route = route;
+  g_threads = threads > 0 ? threads : 0;
+  g_part = part_records ? part_records : (1ull << 25);
+  return old;
+}
+
 extern "C" int or_check(const or_kernel* k, uint64_t x, int literal, or_pair* pairs,
                         uint64_t cap, uint64_t* n_pairs, uint64_t* divergent,
                         uint64_t* n_records) {
@@ -735,6 +909,10 @@ extern "C" int or_repair(const or_kernel* k, const or_opts* o, or_result* out,
   u32 rounds = 0;
   bool mhs = opt.solver == 1;              // greedy rounds until the first SAFE
   u64 x = 0;
+  // the conflict relation does not depend on the assignment: it is taken
+  // once, and each Verify call keeps the pairs x leaves unseparated
+  PairSet conf(k->n_points);
+  conflicts(k, conf);
   int st = solve_step(phi, w.data(), k->n_slots, mhs, &x);   // Solve(phi)
   for (;;) {
     if (st == OR_UNSAT) { r.status = OR_UNSAT; break; }      // cannot be repaired
@@ -742,7 +920,7 @@ extern "C" int or_repair(const or_kernel* k, const or_opts* o, or_result* out,
     if (trajectory && rounds < traj_cap) trajectory[rounds] = x;
     rounds++;
     std::vector<or_pair> rp;                                  // Verify(P_sol)
-    races(k, x, false, rp);
+    races_from(k, x, conf, rp);
     u64 div = divergent_if_enabled(k, false) & x;
     if (rp.empty() && div == 0) {                             // SAFE
       if (mhs) {
@@ -766,7 +944,7 @@ extern "C" int or_repair(const or_kernel* k, const or_opts* o, or_result* out,
     }
     std::vector<or_clause> learned;                           // GenerateClause
     if (opt.policy == 0) {
-      learned = clauses_under(k, x);
+      learned = clauses_from(k, x, conf);
     } else if (div) {
       learned.push_back({0, div & (~div + 1)});
     } else {

@@ -1,7 +1,8 @@
 /*
  * CPU oracle for the barrier-repair path (TEST INFRASTRUCTURE ONLY).
  *
- * Plain, slow, single-threaded reference of what the repair path computes.
+ * Plain, slow reference of what the repair path computes (one thread, or
+ * independent array instances spread over host threads, or_set_route).
  * Only the test suite, the smoke entry point and the benchmark's CPU-baseline
  * leg may load it; the product library never links or calls it.  It shares
  * no code, header, table or helper with the HIP library: the structs below
@@ -53,6 +54,16 @@ int or_validate(const or_kernel* k);
 int or_check(const or_kernel* k, uint64_t x, int literal,
              or_pair* pairs, uint64_t cap, uint64_t* n_pairs,
              uint64_t* divergent, uint64_t* n_records);
+
+/* Route of the location-grouped checker behind or_check (literal = 0),
+ * or_clauses, or_full_clauses and or_repair: 0 (default) materialises the
+ * records of the whole kernel and groups them at once; 1 takes one array
+ * instance at a time -- (array, block) for the same-block relation, (global
+ * array, address stripe) for the cross-block one -- on `threads` host
+ * threads (0: every core), which bounds memory on the largest workloads.
+ * A cross-block part holds about `part_records` records (0: 2^25).  Both
+ * routes evaluate the same definition.  Returns the previous route. */
+int or_set_route(int route, int threads, uint64_t part_records);
 
 /* Conflict of one pair of points, independent of any assignment. */
 int or_pair_conflict(const or_kernel* k, uint32_t i, uint32_t j, int level);

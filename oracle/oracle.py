@@ -26,7 +26,7 @@ def build(force: bool = False) -> str:
             os.path.getmtime(src), os.path.getmtime(os.path.join(HERE, "oracle.h"))):
         tmp = LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
-                               "-Wall", "-o", tmp, src])
+                               "-Wall", "-pthread", "-o", tmp, src])
         os.replace(tmp, LIB)
     return LIB
 
@@ -100,6 +100,7 @@ def lib():
         L.or_greedy_mhs.argtypes = [C.POINTER(Clause), C.c_uint64, C.POINTER(C.c_uint32),
                                     C.c_uint32, u64p]
         L.or_safe_literal.argtypes = [K, C.c_uint64]
+        L.or_set_route.argtypes = [C.c_int, C.c_int, C.c_uint64]
         _lib = L
     return _lib
 
@@ -147,6 +148,14 @@ class _Held:
     @property
     def ptr(self):
         return C.byref(self.k)
+
+
+def set_route(route: int, threads: int = 0, part_records: int = 0) -> int:
+    """Location-grouped checker route: 0 whole kernel at once, 1 one array
+    instance at a time on `threads` host threads (0: every core), cross-block
+    parts of about `part_records` records (0: 2^25).  Returns the previous
+    route."""
+    return lib().or_set_route(int(route), int(threads), int(part_records))
 
 
 def validate(km) -> int:

@@ -37,6 +37,28 @@ static void worst_units(const Plan& pl, std::vector<rp_clause>& u) {
   u.assign(2 * pl.S, rp_clause{0, 0});
 }
 
+// The result of one repair job from its final device state.
+void fill_repair_out(const JobState& s, const Plan& pl, rp_repair_out& out) {
+  std::memset(&out, 0, sizeof(out));
+  out.rounds = s.rounds;
+  out.n_clauses = s.n_phi;
+  if (s.state == ST_SAFE) {
+    out.status = RP_OK;
+    out.assign = s.x;
+    out.weight = s.weight;
+    out.added = s.x & ~pl.pre_slots;
+    out.removed = pl.pre_slots & ~s.x;
+  } else if (s.state == ST_UNSAT) {
+    out.status = RP_UNSAT;
+  } else if (s.state == ST_ROUNDS) {
+    out.status = RP_ERR_ROUNDS;
+  } else if (s.state == ST_ERROR) {
+    out.status = job_error_status(s);
+  } else {
+    out.status = RP_ERR_DEVICE;
+  }
+}
+
 }  // namespace rp
 
 using namespace rp;
@@ -53,6 +75,7 @@ const char* rp_status_string(int s) {
     case RP_ERR_DEVICE: return "device error";
     case RP_ERR_ROUNDS: return "round limit reached";
     case RP_ERR_BUDGET: return "job exceeds the memory budget";
+    case RP_ERR_SEARCH: return "search limit: the exact solver's node budget was spent";
     default: return "unknown status";
   }
 }
@@ -93,6 +116,7 @@ rp_status rp_check(const rp_kernel* k, uint64_t x, rp_pair* pairs, uint64_t cap,
   int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
   t_stats = st;
   if (rc != RP_OK) return (rp_status)rc;
+  if (res[0].st.state == ST_ERROR) return (rp_status)job_error_status(res[0].st);
   if (n_pairs) *n_pairs = res[0].n_pairs;
   if (res[0].n_pairs > cap) return RP_ERR_CAPACITY;
   if (res[0].n_pairs) std::memcpy(pairs, res[0].pairs.data(), res[0].n_pairs * sizeof(rp_pair));
@@ -117,6 +141,7 @@ rp_status rp_clauses(const rp_kernel* k, uint64_t x, rp_clause* out, uint64_t ca
   int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
   t_stats = st;
   if (rc != RP_OK) return (rp_status)rc;
+  if (res[0].st.state == ST_ERROR) return (rp_status)job_error_status(res[0].st);
   const uint64_t n = res[0].phi.size();
   if (n_out) *n_out = n;
   if (n > cap) return RP_ERR_CAPACITY;
@@ -140,6 +165,7 @@ rp_status rp_first_partners(const rp_kernel* k, uint64_t x, uint32_t* first,
   int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
   t_stats = st;
   if (rc != RP_OK) return (rp_status)rc;
+  if (res[0].st.state == ST_ERROR) return (rp_status)job_error_status(res[0].st);
   if (pl.P) std::memcpy(first, res[0].first.data(), 2 * (size_t)pl.P * sizeof(uint32_t));
   if (divergent) *divergent = res[0].st.divergent;
   return RP_OK;
@@ -194,6 +220,7 @@ rp_status rp_min_barriers(const rp_clause* clauses, uint64_t n_clauses, const ui
   int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
   t_stats = st;
   if (rc != RP_OK) return (rp_status)rc;
+  if (res[0].st.state == ST_ERROR) return (rp_status)job_error_status(res[0].st);
   if (res[0].st.state == ST_UNSAT) return RP_UNSAT;
   if (assign) *assign = res[0].st.x;
   if (weight) *weight = res[0].st.weight;
@@ -223,23 +250,7 @@ rp_status rp_repair(const rp_kernel* k, const rp_repair_opts* opts, rp_repair_ou
   int rc = engine_run(v, o, ws, ws_bytes, (hipStream_t)stream, res, &st);
   t_stats = st;
   if (rc != RP_OK) return (rp_status)rc;
-  const JobState& s = res[0].st;
-  std::memset(out, 0, sizeof(*out));
-  out->rounds = s.rounds;
-  out->n_clauses = s.n_phi;
-  if (s.state == ST_SAFE) {
-    out->status = RP_OK;
-    out->assign = s.x;
-    out->weight = s.weight;
-    out->added = s.x & ~pl.pre_slots;
-    out->removed = pl.pre_slots & ~s.x;
-  } else if (s.state == ST_UNSAT) {
-    out->status = RP_UNSAT;
-  } else if (s.state == ST_ROUNDS) {
-    out->status = RP_ERR_ROUNDS;
-  } else {
-    out->status = RP_ERR_DEVICE;
-  }
+  fill_repair_out(res[0].st, pl, *out);
   if (traj_cap) {
     const size_t nt = std::min<size_t>(traj_cap, res[0].traj.size());
     std::memcpy(trajectory, res[0].traj.data(), nt * sizeof(uint64_t));
@@ -275,7 +286,10 @@ rp_status rp_repair_batch(const rp_kernel* const* ks, uint32_t n, const rp_repai
   std::vector<uint32_t> idx;
   plans.reserve(n);
   for (uint32_t j = 0; j < n; j++) {
+    // every result reads as a failure until its job has a verdict, so a
+    // call that ends early leaves no job looking repaired
     std::memset(&outs[j], 0, sizeof(outs[j]));
+    outs[j].status = RP_ERR_DEVICE;
     if (validate_kernel(ks[j]) != RP_OK) {
       outs[j].status = RP_ERR_INVALID;   // this job only; the others run
       continue;
@@ -301,23 +315,7 @@ rp_status rp_repair_batch(const rp_kernel* const* ks, uint32_t n, const rp_repai
   t_stats = st;
   if (rc != RP_OK) return (rp_status)rc;
   for (size_t q = 0; q < v.size(); q++) {
-    const JobState& s = res[q].st;
-    rp_repair_out& out = outs[idx[q]];
-    out.rounds = s.rounds;
-    out.n_clauses = s.n_phi;
-    if (s.state == ST_SAFE) {
-      out.status = RP_OK;
-      out.assign = s.x;
-      out.weight = s.weight;
-      out.added = s.x & ~plans[q].pre_slots;
-      out.removed = plans[q].pre_slots & ~s.x;
-    } else if (s.state == ST_UNSAT) {
-      out.status = RP_UNSAT;
-    } else if (s.state == ST_ROUNDS) {
-      out.status = RP_ERR_ROUNDS;
-    } else {
-      out.status = RP_ERR_DEVICE;
-    }
+    fill_repair_out(res[q].st, plans[q], outs[idx[q]]);
   }
   return RP_OK;
 }
@@ -345,6 +343,9 @@ int rp_set_tuning(int knob, int value) {
     case RP_TUNE_TIMING:
       if (value < 0 || value > 2) return -1;
       return timing_level(value, true);
+    case RP_TUNE_SOLVER_NODES:
+      if (value < 4 || value > 40) return -1;
+      return solver_nodes_log2(value, true);
     default:
       return -1;
   }

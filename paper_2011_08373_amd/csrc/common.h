@@ -88,7 +88,10 @@ constexpr uint32_t ST_RUN = 0, ST_SAFE = 1, ST_UNSAT = 2, ST_ERROR = 3, ST_ROUND
 // greedy answer is SAFE; one exact query either confirms it or replaces it,
 // and exact Solve continues.
 constexpr uint32_t PH_EXACT = 0, PH_GREEDY = 1, PH_FINAL = 2;
-constexpr uint32_t ERR_PHI_CAP = 1, ERR_SORT = 2, ERR_SCRATCH = 3, ERR_RANGE = 4;
+// device-side error codes of a job (JobState::err) or of a whole call (the
+// error word): phi or a scratch table full, an out-of-range sort output, the
+// exact solver's node budget spent
+constexpr uint32_t ERR_PHI_CAP = 1, ERR_SORT = 2, ERR_SCRATCH = 3, ERR_RANGE = 4, ERR_NODES = 5;
 
 struct Job {
   uint32_t P, S, B, T;
@@ -117,6 +120,7 @@ struct Job {
   JobState* st;
   uint64_t* traj;             // [traj_cap] assignment verified per round
   uint32_t traj_cap, pad2;
+  uint64_t node_limit;        // nodes the exact solver's branch and bound may visit
 };
 
 // sort segment: one log of one job in the record buffer

@@ -309,6 +309,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     J.st = (JobState*)(d + L.o_states) + j;
     J.traj = o.traj_cap ? (uint64_t*)(d + L.o_traj[j]) : nullptr;
     J.traj_cap = o.traj_cap;
+    J.node_limit = 1ull << solver_nodes_log2(0, false);
     JobState& S = hs[j];
     std::memset(&S, 0, sizeof(S));
     S.x = jobs[j].x;
@@ -578,10 +579,9 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   res.assign(N, JobResult{});
   for (size_t j = 0; j < N; j++) {
     res[j].st = hst[j];
-    if (hst[j].state == ST_ERROR) {
-      return hst[j].err == ERR_PHI_CAP || hst[j].err == ERR_SCRATCH ? RP_ERR_CAPACITY
-                                                                   : RP_ERR_DEVICE;
-    }
+    // a job that failed on the device keeps its own error state; the other
+    // jobs of the call are unaffected and read out as usual
+    if (hst[j].state == ST_ERROR) continue;
     if (o.op == OP_FIRST) {
       res[j].first.resize(2 * (size_t)jobs[j].plan->P);
       if (!res[j].first.empty())

@@ -21,6 +21,20 @@ int timing_level(int v, bool set) {
   return old;
 }
 
+static int g_nodes_log2 = 28;         // RP_TUNE_SOLVER_NODES
+
+int solver_nodes_log2(int v, bool set) {
+  const int old = g_nodes_log2;
+  if (set) g_nodes_log2 = v;
+  return old;
+}
+
+int job_error_status(const JobState& st) {
+  if (st.err == ERR_PHI_CAP || st.err == ERR_SCRATCH) return RP_ERR_CAPACITY;
+  if (st.err == ERR_NODES) return RP_ERR_SEARCH;
+  return RP_ERR_DEVICE;
+}
+
 int g_digit_bits_ref(int v, bool set) {
   const int old = g_digit_bits;
   if (set) g_digit_bits = v;

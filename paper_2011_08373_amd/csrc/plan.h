@@ -26,6 +26,14 @@ int pick_digit_bits(uint32_t key_bits);
 // hipEvent timing level of engine calls (RP_TUNE_TIMING); returns the old one
 int timing_level(int v, bool set);
 int sort_passes(uint32_t key_bits, int rb);
+// Node budget of the exact solver's branch and bound (RP_TUNE_SOLVER_NODES,
+// as log2); returns the old log2.
+int solver_nodes_log2(int v, bool set);
+// Library status of a job that ended in ST_ERROR.
+int job_error_status(const JobState& st);
+struct Plan;
+// rp_repair_out of a repair job from its final state.
+void fill_repair_out(const JobState& s, const Plan& pl, rp_repair_out& out);
 // Unit clauses that the repair options impose before the first Solve.
 std::vector<rp_clause> option_units(const Plan& pl, const rp_repair_opts& o);
 

@@ -138,24 +138,7 @@ struct Server {
 using namespace rp;
 
 static void fill_out(const SJob& j, const JobState& st, rp_repair_out& out) {
-  std::memset(&out, 0, sizeof(out));
-  out.rounds = st.rounds;
-  out.n_clauses = st.n_phi;
-  if (st.state == ST_SAFE) {
-    out.status = RP_OK;
-    out.assign = st.x;
-    out.weight = st.weight;
-    out.added = st.x & ~j.plan.pre_slots;
-    out.removed = j.plan.pre_slots & ~st.x;
-  } else if (st.state == ST_UNSAT) {
-    out.status = RP_UNSAT;
-  } else if (st.state == ST_ROUNDS) {
-    out.status = RP_ERR_ROUNDS;
-  } else if (st.state == ST_ERROR) {
-    out.status = (st.err == ERR_PHI_CAP || st.err == ERR_SCRATCH) ? RP_ERR_CAPACITY : RP_ERR_DEVICE;
-  } else {
-    out.status = RP_ERR_DEVICE;
-  }
+  fill_repair_out(st, j.plan, out);
 }
 
 

@@ -33,7 +33,6 @@ constexpr int SV_BLOCK = 256;
 constexpr int SV_WAVES = SV_BLOCK / 64;
 constexpr uint32_t SV_LDS_CLAUSES = 3072;
 constexpr int ENUM_MAX = 20;
-constexpr uint64_t NODE_LIMIT = 1ull << 28;
 
 struct Key { uint64_t hi, lo; };
 __device__ __forceinline__ bool key_lt(Key a, Key b) { return a.hi != b.hi ? a.hi < b.hi : a.lo < b.lo; }
@@ -389,7 +388,7 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
           if (eval_pending) {
             eval_pending = false;
             nodes++;
-            if (nodes > NODE_LIMIT) { overflow = true; break; }
+            if (nodes > J.node_limit) { overflow = true; break; }
             if (!(found && !key_lt(key, inc))) {
               uint64_t dead = 0, pick = ~0ull, lbmax = 0;
               for (uint32_t q = lane; q < nc; q += 64) {
@@ -441,7 +440,7 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
         }
         (void)inc_x;
         if (lane == 0) {
-          if (overflow) { st->err = ERR_SCRATCH; st->state = ST_ERROR; }
+          if (overflow) { st->err = ERR_NODES; st->state = ST_ERROR; }
           s_unsat = overflow ? 2u : (found ? 1u : 0u);
           smA[0] = inc.hi;
           smB[0] = inc.lo;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "lib", "librepair.so")
 
 OK, UNSAT = 0, 1
 ERR_INVALID, ERR_CAPACITY, ERR_WORKSPACE, ERR_DEVICE, ERR_ROUNDS, ERR_BUDGET = -1, -2, -3, -4, -5, -6
+ERR_SEARCH = -7
 OP_CHECK, OP_CLAUSES, OP_REPAIR, OP_FIRST = 0, 1, 2, 4
 
 if not os.path.exists(LIB_PATH):
@@ -126,6 +127,7 @@ _L.rp_instrument.argtypes = [C.POINTER(RpProgram), C.POINTER(RpInstrumentOpts),
                              C.c_void_p, C.c_void_p, C.c_uint32, _u32p, C.c_void_p, C.c_uint32,
                              _u32p, C.c_void_p, C.c_uint32, _u32p]
 TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE, TUNE_TIMING, TUNE_SCATTER_WGS = 0, 1, 2, 3
+TUNE_SOLVER_NODES = 4
 
 
 def lib():

@@ -381,6 +381,16 @@ def generate(name: str, mode: str = "literal", seed: int | None = None, **over) 
     return k
 
 
+def max_points_kernel(seed: int = 15) -> Kernel:
+    """A kernel at the point limit of the model (4,096 points), in planted
+    mode with the large workload's distributions: 2 blocks x 64 threads,
+    8 shared + 8 global arrays of 256 words, 64 slots (16 grid-level)."""
+    k = generate("plain-large", mode="planted", seed=seed, P=4096, S=64, S_grid=16, blocks=2,
+                 threads=64, arrays=[(256, SHARED)] * 8 + [(256, GLOBAL)] * 8)
+    k.meta.update(config="max-points")
+    return k
+
+
 def batch_shape(rng):
     """Threads log-uniform in [64, 65536] (multiple of 64); points, slots uniform."""
     total = int(round(2.0 ** rng.uniform(6, 16) / 64.0)) * 64

@@ -28,3 +28,24 @@ def listing_fixtures():
 def load(name):
     with open(os.path.join(GOLDEN, name + ".json")) as f:
         return json.load(f)
+
+
+def encode_pairs(pairs, P):
+    """Racing pairs [(level, i, j)] in ascending order as a compact string:
+    the deltas of the codes level*P*P + i*P + j, zlib-compressed, base64."""
+    import base64
+    import zlib
+    codes = [lv * P * P + i * P + j for lv, i, j in pairs]
+    deltas = [codes[0]] + [b - a for a, b in zip(codes, codes[1:])] if codes else []
+    return base64.b64encode(zlib.compress(",".join(map(str, deltas)).encode(), 9)).decode()
+
+
+def decode_pairs(text, P):
+    import base64
+    import zlib
+    raw = zlib.decompress(base64.b64decode(text)).decode()
+    out, code = [], 0
+    for d in (raw.split(",") if raw else []):
+        code += int(d)
+        out.append((code // (P * P), (code // P) % P, code % P))
+    return out

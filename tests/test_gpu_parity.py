@@ -509,34 +509,83 @@ def test_first_partners(L):
         assert (first.astype(np.uint64) == _first_from_pairs(O.check(km, 0)[1], km.n_points)).all()
 
 
-@pytest.mark.parametrize("mode", ["planted", "literal"])
-def test_stress_sampled(L, mode):
-    # 4096 blocks x 1024 threads, 1024 points, 64 slots, eight 16M-word arrays
-    # (about 2.9G access records).  The oracle checks sampled points one pair
-    # at a time: the reported first partner conflicts, earlier candidates do not.
-    km = synth.generate("stress", mode=mode)
-    st, first, div = L.first_partners(km, 0)
-    assert st == 0 and div == 0
-    rng = np.random.default_rng(7)
-    pts = km.points
-    acc = np.flatnonzero(pts["kind"] == 0)
-    glob = np.flatnonzero((pts["kind"] == 0) & (km.arrays["space"][pts["array"]] == 1))
-    for lv, pool in ((0, acc), (1, glob)):
-        for i in rng.choice(pool, 3, replace=False).tolist():
-            j = int(first[lv][i])
-            same = [q for q in acc.tolist() if q >= i and pts["array"][q] == pts["array"][i]]
-            if j != NONE:
-                assert O.pair_conflict(km, i, j, lv) == 1, (lv, i, j)
-                earlier = [q for q in same if q < j]
-            else:
-                earlier = same
-            for q in rng.choice(earlier, min(2, len(earlier)), replace=False).tolist():
-                assert O.pair_conflict(km, i, int(q), lv) == 0, (lv, i, q)
-    r = L.repair(km)
-    if mode == "planted":
-        assert r["status"] == 0
-        w = km.weights
-        ws = sum(int(w[s]) for s in range(km.n_slots) if (km.meta["x_star"] >> s) & 1)
-        assert r["weight"] <= ws
-        st, first, div = L.first_partners(km, r["assign"])
-        assert st == 0 and div == 0 and (first == NONE).all()
+def chain_kernel(n_slots=24):
+    """One block of 64 threads, two shared arrays X and Y; accesses alternate
+    between them with a barrier slot after each: on each array the accesses
+    alternate write A[tid] / read A[tid + 1], so every access races with the
+    next one on its array, two accesses later.  The races give the clauses
+    {s_k, s_k+1}: one constraint component of n_slots slots (a path), wider
+    than the enumeration limit, so Solve takes the branch and bound."""
+    pts = []
+    for k in range(n_slots + 1):
+        arr = k % 2
+        write = (k // 2) % 2 == 0
+        pts.append(dict(kind=0, is_write=int(write), array=arr, a=1, c=0 if write else 1))
+        if k < n_slots:
+            pts.append(dict(kind=1, slot=k))
+    return synth.make_kernel(1, 64, [(128, 0), (128, 0)], [(1, 0)], pts,
+                             [(0, 0, 1 + (s % 3)) for s in range(n_slots)])
+
+
+def test_solver_node_budget(L):
+    # the exact search's node budget is a tuning knob; a component that
+    # needs more nodes ends its job with RP_ERR_SEARCH (a status of its own)
+    km = chain_kernel(24)
+    o = O.repair(km)
+    assert o["status"] == 0
+    g = L.repair(km)
+    assert same_repair(g, o), (g, o)
+    old = L.set_tuning(L.TUNE_SOLVER_NODES, 4)
+    try:
+        g = L.repair(km)
+        assert g["status"] == L.ERR_SEARCH and g["ret"] == L.ERR_SEARCH, g
+        st, full = O.full_clauses(km)
+        s = L.min_barriers(full, km.weights.tolist(), km.n_slots)
+        assert s[0] == L.ERR_SEARCH
+    finally:
+        L.set_tuning(L.TUNE_SOLVER_NODES, old)
+    assert L.min_barriers(full, km.weights.tolist(), km.n_slots) == \
+        O.min_barriers(full, km.weights.tolist(), km.n_slots)
+
+
+def test_batch_job_error_leaves_the_others(L):
+    # one job of a batch fails on the device (its exact search spends the
+    # node budget): it alone reads RP_ERR_SEARCH, every other job finishes
+    # with the oracle's result
+    kms = [synth.generate("plain-small", mode="planted", seed=s) for s in range(6)]
+    kms.insert(3, chain_kernel(24))
+    old = L.set_tuning(L.TUNE_SOLVER_NODES, 4)
+    try:
+        st, res = L.repair_batch(kms)
+    finally:
+        L.set_tuning(L.TUNE_SOLVER_NODES, old)
+    assert st == 0
+    for q, km in enumerate(kms):
+        if q == 3:
+            assert res[q]["status"] == L.ERR_SEARCH
+            continue
+        o = O.repair(km)
+        assert {k: res[q][k] for k in REPAIR_KEYS if k != "trajectory"} == \
+            {k: o[k] for k in REPAIR_KEYS if k != "trajectory"}, q
+
+
+def test_solver_hard_components(L):
+    # random clause sets over 40-64 slots forming one component, with mixed
+    # and negative clauses: the branch and bound against the oracle's
+    rng = np.random.default_rng(16)
+    for trial in range(12):
+        S = int(rng.integers(40, 65))
+        cl = []
+        for s in range(S - 1):                       # a spine keeps it connected
+            cl.append(((1 << s) | (1 << (s + 1)), 0))
+        for _ in range(int(rng.integers(S, 3 * S))):
+            p = 0
+            for _ in range(int(rng.integers(1, 4))):
+                p |= 1 << int(rng.integers(0, S))
+            cl.append((p, 0))
+        for _ in range(int(rng.integers(0, 6))):
+            cl.append((0, 1 << int(rng.integers(0, S))))
+        w = rng.integers(1, 12, size=S).tolist()
+        g = L.min_barriers(cl, w, S)
+        o = O.min_barriers(cl, w, S)
+        assert g == o, trial

@@ -45,10 +45,13 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_status_strings(L):
+    seen = set()
     for st in (L.OK, L.UNSAT, L.ERR_INVALID, L.ERR_CAPACITY, L.ERR_WORKSPACE, L.ERR_DEVICE,
-               L.ERR_ROUNDS, L.ERR_BUDGET):
+               L.ERR_ROUNDS, L.ERR_BUDGET, L.ERR_SEARCH):
         s = L.status_string(st)
-        assert isinstance(s, str) and s
+        assert isinstance(s, str) and s and s != "unknown status"
+        seen.add(s)
+    assert len(seen) == 9
 
 
 def test_validation_without_device(L):
@@ -110,6 +113,14 @@ def test_tuning_knobs(L):
         assert L.set_tuning(L.TUNE_SCATTER_WGS, 0) == 4
     finally:
         L.set_tuning(L.TUNE_SCATTER_WGS, old)
+    old = L.set_tuning(L.TUNE_SOLVER_NODES, 10)
+    try:
+        assert old == 28                                         # 2^28 nodes by default
+        assert L.set_tuning(L.TUNE_SOLVER_NODES, 3) == -1
+        assert L.set_tuning(L.TUNE_SOLVER_NODES, 41) == -1
+        assert L.set_tuning(L.TUNE_SOLVER_NODES, 28) == 10
+    finally:
+        L.set_tuning(L.TUNE_SOLVER_NODES, old)
 
 
 def test_invalid_kernel_does_no_device_work(L):
