@@ -1,27 +1,33 @@
 """Benchmark of the repair hot path on one MI355X.
 
 One step = one full rp_repair call (Alg. 1: record generation, the one-time
-radix sort, then Verify / GenerateClause / Solve rounds until a verdict) on
-the plain-large synthetic kernel: 256 blocks x 256 threads, 512 program
-points, 32 barrier slots (8 grid-level), two shared and two global arrays of
-1M int32 words.  The metric is race-checked accesses per second: every
-(point, block, thread) access is race-checked once per Verify call.
+radix sort and first-partner table, then Verify / GenerateClause / Solve
+rounds until a verdict) on the stress kernel: 4,096 blocks x 1,024 threads,
+1,024 program points (half of them accesses), 64 barrier slots (16
+grid-level), four shared and four global arrays of 16M int32 words, about
+2.0G access records (a 16 GB log, far beyond the 256 MB last-level cache).
+The metric is race-checked accesses per second: every (point, block,
+thread) access is race-checked once per Verify call.
 
 More legs are reported beside the headline (same JSON line; --legs picks):
   planted  the same kernel with a planted safe barrier set (several Verify
-           calls, ends SAFE);
-  stress   4,096 blocks x 1,024 threads, 1,024 points, eight 16M-word arrays
-           (2.0G records after the reduction, a 16 GB log; 2.4G planted):
-           throughput and kernel rooflines far outside the last-level cache;
+           calls, ends SAFE); its per-Verify rate is reported apart from the
+           Verify-call multiplier;
+  plain    the plain-large kernel (256 blocks x 256 threads, 512 points, four
+           1M-word arrays), literal and planted: a 213 MB log that the
+           last-level cache partly holds;
   batched  the 1,024-kernel batched workload (planted mode): repaired kernels
            per second of one rp_repair_batch call against the plain
-           one-kernel-at-a-time rp_repair loop on the same kernels;
+           one-kernel-at-a-time rp_repair loop on the same kernels (both with
+           their descriptors marshalled before the timer starts);
   rounds   Verify calls per kernel over the batched kernels under each
            learning policy (all traces / one trace per call) and Solve
            strategy (exact / mhs), and with the option switches;
-  served   Poisson arrivals (2,000 jobs/s by default) drawn from the same
-           1,024 kernels into a continuous-batching server with a 64 GB
-           arena: p50/p99 latency from submission to verdict, throughput;
+  served   Poisson arrivals drawn from the same 1,024 kernels into a
+           continuous-batching server with a 64 GB arena, at the offered
+           rate and at rates above the plain loop's capacity: p50/p99 latency
+           from submission to verdict and the rate of jobs finished inside
+           the measured window;
   instrumented  1,024 small structured programs (branches, loops, calls,
            pre-existing barriers) through the library's instrumentation pass
            and one rp_repair_batch call: host microseconds per program,
@@ -56,17 +62,62 @@ def _ensure_built():
         hipbuild.build()
 
 
-def cpu_baseline(km, rounds_gpu):
-    """The CPU oracle (single thread) on one full repair of the same kernel."""
+def host_info():
+    """CPU model, logical cores and RAM of the host the oracle runs on."""
+    model, mem = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem = round(int(line.split()[1]) / (1 << 20), 1)
+                    break
+    except OSError:
+        pass
+    return dict(cpu_model=model, nproc=os.cpu_count(), ram_gib=mem)
+
+
+# host threads the oracle may use: the box's CPU share for one GPU
+ORACLE_THREADS = 16
+STRESS_SAMPLE_BLOCKS = 1024
+
+
+def cpu_baseline(name, mode, km_full):
+    """The CPU oracle timed on the host cores on a bounded sample of the
+    headline workload: one full repair (Alg. 1 in the paper's order) of the
+    same kernel model restricted to its first STRESS_SAMPLE_BLOCKS blocks
+    (stress), or of the whole kernel (plain-large, one thread)."""
     from oracle import oracle as O
-    t = time.perf_counter()
-    r = O.repair(km)
-    dt = time.perf_counter() - t
-    acc = int(km.meta.get("accesses", 0))
-    return dict(value=acc * r["rounds"] / dt, unit="race-checked accesses/s", cores=1,
-                kind="oracle", sample="one full repair of the plain-large kernel "
-                "(%d Verify calls, %.1f s)" % (r["rounds"], dt),
-                matches_gpu_rounds=r["rounds"] == rounds_gpu)
+    from paper_2011_08373_amd import synth
+    if name == "stress":
+        threads = max(1, min(ORACLE_THREADS, os.cpu_count() or 1))
+        km = synth.generate(name, mode=mode, blocks=STRESS_SAMPLE_BLOCKS)
+        sample = ("one full repair (per-instance location-grouped checker on %d threads) of "
+                  "the stress kernel's %s model restricted to its first %d of %d blocks "
+                  "(same points, threads and arrays)" % (threads, mode, STRESS_SAMPLE_BLOCKS,
+                                                         km_full.blocks))
+        O.set_route(1, threads)
+    else:
+        threads = 1
+        km = km_full
+        sample = "one full repair of the plain-large %s kernel on one thread" % mode
+        O.set_route(0)
+    try:
+        acc = model_accesses(km)
+        t = time.perf_counter()
+        r = O.repair(km)
+        dt = time.perf_counter() - t
+    finally:
+        O.set_route(0)
+    out = dict(value=acc * r["rounds"] / dt, unit="race-checked accesses/s", cores=threads,
+               kind="oracle", sample=sample + " (%d accesses, %d Verify call(s), %.1f s)"
+               % (acc, r["rounds"], dt), seconds=dt)
+    out.update(host_info())
+    return out
 
 
 def model_accesses(km):
@@ -82,17 +133,19 @@ def model_accesses(km):
     return total * km.blocks
 
 
-def apply_tuning(L, n_accesses):
-    """The autotuner's sort configuration for this size class, else the
-    library's defaults (automatic digit width, 512 x 8 scatter tiles)."""
+def apply_tuning(L, n_accesses, key_bits):
+    """The autotuner's sort configuration for this size class (access count
+    and key width), else the library's defaults (automatic digit width,
+    512 x 8 scatter tiles)."""
     from paper_2011_08373_amd import autotune
-    best = autotune.lookup(n_accesses) if n_accesses else None
+    best = autotune.lookup(n_accesses, key_bits) if n_accesses else None
     if best:
-        autotune.apply(n_accesses)
-        return dict(digit_bits=best["digit_bits"], shape=best["shape"], autotuned=True)
+        autotune.apply(n_accesses, key_bits)
+        return dict(digit_bits=best["digit_bits"], shape=best["shape"], key_bits=key_bits,
+                    autotuned=True)
     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 0)
     L.set_tuning(L.TUNE_SCATTER_SHAPE, 4)
-    return dict(digit_bits="auto", shape=4, autotuned=False)
+    return dict(digit_bits="auto", shape=4, key_bits=key_bits, autotuned=False)
 
 
 def run_main(L, torch, km, steps, warmup):
@@ -103,7 +156,7 @@ def run_main(L, torch, km, steps, warmup):
     for the phase breakdown."""
     ws = L.Workspace()
     ka = L.KernelArg(km)          # the C view of the descriptors, built once
-    sort_cfg = apply_tuning(L, model_accesses(km))
+    sort_cfg = apply_tuning(L, model_accesses(km), L.sort_key_bits(ka))
     ws.get(L.workspace_bytes(ka, L.OP_REPAIR))
     level = L.set_tuning(L.TUNE_TIMING, 1)
     for _ in range(warmup):
@@ -177,24 +230,47 @@ def kernel_rooflines(stats, traffic_prefix=""):
     return out
 
 
-def stress_leg(L, torch, steps):
-    """The stress kernel (4,096 blocks x 1,024 threads, 1,024 points, eight
-    16M-word arrays): a log of 16-20 GB, far beyond the 256 MB last-level
-    cache, so the kernel rooflines here are HBM figures."""
+def phase_roofline(stats):
+    """The race-check phase of one repair (record generation, every radix
+    pass with its counts and column scans, the first-partner scan), timed
+    with the streaming kernels' hipEvents, against its algorithmic bytes:
+    8 B per record written by generation, 16 B per record and radix pass,
+    8 B per record read by the scan."""
+    n = len(stats)
+    last = stats[-1]
+    rec = last["records"]
+    passes = last.get("sort_passes", 0)
+    ms = sum(s["ms_gen"] + s["ms_sort"] + s["ms_j0"] for s in stats) / n
+    if ms <= 0:
+        return None
+    byts = rec * (8 + 16 * passes + 8)
+    gbs = byts / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "ms_per_step": ms, "bytes_per_step": byts,
+            "sort_passes": passes}
+
+
+def kernel_leg(L, torch, name, mode, steps, warmup=1):
+    """Full repairs of one named kernel (the stress kernel's 16-20 GB log is
+    far beyond the 256 MB last-level cache; plain-large's 213 MB log is
+    partly held by it).  `accesses_per_s_per_verify` divides the accesses by
+    the repair time once; `value` multiplies them by the Verify calls, whose
+    rounds after the first cost O(points) on the resident first-partner
+    table."""
     from paper_2011_08373_amd import synth
-    out = {}
-    for mode in ("literal", "planted"):
-        km = synth.generate("stress", mode=mode)
-        r, ms, stats = run_main(L, torch, km, steps, 1)
-        acc = stats[-1]["accesses"]
-        out[mode] = {"value": acc * r["rounds"] / (ms / 1e3), "unit": "accesses/s",
-                     "ms_per_step": ms, "accesses": acc, "records": stats[-1]["records"],
-                     "sort": stats[-1]["sort_config"],
-                     "verify_calls": r["rounds"], "repair_status": r["status"],
-                     "kernels": kernel_rooflines(stats, "stress/"),
-                     "phases_ms": stats[-1]["phases"]}
-        torch.cuda.empty_cache()
-    out["workload"] = WORKLOADS["stress"] % "literal and planted"
+    km = synth.generate(name, mode=mode)
+    r, ms, stats = run_main(L, torch, km, steps, warmup)
+    acc = stats[-1]["accesses"]
+    out = {"workload": WORKLOADS[name] % mode,
+           "value": acc * r["rounds"] / (ms / 1e3), "unit": "race-checked accesses/s",
+           "accesses_per_s_per_verify": acc / (ms / 1e3),
+           "verify_calls": r["rounds"], "ms_per_step": ms, "steps": steps,
+           "accesses": acc, "records": stats[-1]["records"],
+           "sort": stats[-1]["sort_config"], "repair_status": r["status"],
+           "weight": r.get("weight"),
+           "kernels": kernel_rooflines(stats, "" if name == "plain-large" else name + "/"),
+           "phases_ms": stats[-1]["phases"]}
+    torch.cuda.empty_cache()
     return out
 
 
@@ -206,7 +282,7 @@ def batched_leg(L, torch, kms):
     L.repair_batch(b, ws=ws)                       # warm-up
     torch.cuda.synchronize()
     # sort knobs of this size class from the autotuner's cache, if tuned
-    tuned = apply_tuning(L, L.last_stats()["accesses"])["autotuned"]
+    tuned = apply_tuning(L, L.last_stats()["accesses"], L.sort_key_bits(b))["autotuned"]
     if tuned:
         L.repair_batch(b, ws=ws)
         torch.cuda.synchronize()
@@ -215,13 +291,18 @@ def batched_leg(L, torch, kms):
     torch.cuda.synchronize()
     tb = time.perf_counter() - t
     bstats = L.last_stats()
-    # plain loop: one rp_repair per kernel, in order
+    # plain loop: one rp_repair per kernel, in order, with each kernel's C
+    # view and workspace size prepared before the timer (as the batched
+    # call's BatchArg is)
+    kas = b.args
+    # each plain call takes the automatic digit width of its own key
+    L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 0)
     ws1 = L.Workspace()
-    ws1.get(max(L.workspace_bytes(k, L.OP_REPAIR) for k in kms))
-    L.repair(kms[0], ws=ws1)
+    ws1.get(max(ka.need(L.OP_REPAIR) for ka in kas))
+    L.repair(kas[0], ws=ws1)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    plain = [L.repair(k, ws=ws1) for k in kms]
+    plain = [L.repair(ka, ws=ws1) for ka in kas]
     torch.cuda.synchronize()
     tp = time.perf_counter() - t
     same = all(plain[q]["status"] == res[q]["status"] and plain[q]["assign"] == res[q]["assign"]
@@ -314,17 +395,21 @@ def instrumented_leg(L, torch, n, seed=11):
     return out
 
 
-def served_leg(L, torch, kms, rate, seconds, arena_gb):
-    """Poisson arrivals into the continuous-batching server."""
+def served_leg(L, torch, kms, rate, seconds, arena_gb, seed=4):
+    """Poisson arrivals into the continuous-batching server: 1 s of warm-up,
+    then `seconds` measured.  Latency is submission to verdict for the jobs
+    that arrive inside the measured window; throughput counts the verdicts
+    delivered inside it (so it can exceed neither the offered rate by much
+    nor the server's capacity)."""
     from paper_2011_08373_amd import synth
     warm = 1.0
-    arr = synth.poisson_arrivals(rate, warm + seconds, seed=4)
+    arr = synth.poisson_arrivals(rate, warm + seconds, seed=seed)
     srv = L.Server(arena_bytes=int(arena_gb * (1 << 30)), max_resident=1024)
-    lat = {}
+    lat, done_at = {}, {}
     n_sub = 0
     t0 = time.perf_counter()
     max_res = 0
-    limit = warm + seconds + 60.0          # drain the backlog, but not forever
+    limit = warm + seconds + 30.0          # drain the backlog, but not forever
     while len(lat) < len(arr) and time.perf_counter() - t0 < limit:
         now = time.perf_counter() - t0
         while n_sub < len(arr) and arr[n_sub] <= now:
@@ -334,22 +419,23 @@ def served_leg(L, torch, kms, rate, seconds, arena_gb):
             n_sub += 1
         nres, npend = srv.step()
         max_res = max(max_res, nres)
+        t_poll = time.perf_counter() - t0
         for jid, r, l in srv.poll():
             lat[jid] = l
+            done_at[jid] = t_poll
         if nres == 0 and npend == 0 and n_sub < len(arr):
             time.sleep(max(0.0, min(0.001, arr[n_sub] - (time.perf_counter() - t0))))
-    t_end = time.perf_counter() - t0
     srv.close()
     ids = [i for i in range(len(arr)) if arr[i] >= warm]
     ls = sorted(lat[i] for i in ids if i in lat)
+    in_window = sum(1 for t in done_at.values() if warm <= t < warm + seconds)
 
     def pct(p):
         return ls[min(len(ls) - 1, max(0, int(math.ceil(p * len(ls))) - 1))] if ls else None
-    return {"workload": "served: Poisson arrivals at %.0f jobs/s drawn from the batched "
-                        "kernels, %.0f GB arena, 1 s warm-up + %.1f s measured" % (rate, arena_gb, seconds),
-            "jobs_measured": len(ids), "jobs_finished": len(ls),
+    return {"offered_jobs_per_s": rate, "seconds": seconds,
+            "jobs_arrived": len(ids), "jobs_finished": len(ls),
             "p50_s": pct(0.50), "p99_s": pct(0.99),
-            "throughput_jobs_per_s": len(arr) / t_end, "offered_jobs_per_s": rate,
+            "throughput_jobs_per_s": in_window / seconds,
             "max_resident": max_res}
 
 
@@ -359,14 +445,16 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--mode", default="literal", choices=("literal", "planted"))
-    ap.add_argument("--config", default="plain-large", choices=("plain-large", "stress"),
-                    help="kernel of the headline leg (the stress kernel for profiling runs)")
+    ap.add_argument("--config", default="stress", choices=("stress", "plain-large"),
+                    help="kernel of the headline leg")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--legs", default="main,planted,stress,batched,rounds,served,instrumented")
-    ap.add_argument("--stress-steps", type=int, default=3)
+    ap.add_argument("--legs", default="main,planted,plain,batched,rounds,served,instrumented")
+    ap.add_argument("--leg-steps", type=int, default=20,
+                    help="timed repairs of the planted and plain legs")
     ap.add_argument("--batched-n", type=int, default=1024)
-    ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-rates", default="2000,4000,8000",
+                    help="offered Poisson rates (jobs/s) of the served leg")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-arena-gb", type=float, default=64.0)
     ap.add_argument("--calib", action="store_true",
                     help="run a 512 MiB device copy first (reference for byte counters)")
@@ -379,6 +467,7 @@ def main():
     import torch
     from paper_2011_08373_amd import librepair as L, synth
     torch.cuda.set_device(0)
+    legs = set(args.legs.split(","))
     if args.calib:
         a = torch.empty(64 << 20, dtype=torch.int64, device="cuda")
         b = torch.empty_like(a)
@@ -388,7 +477,6 @@ def main():
     km = synth.generate(args.config, mode=args.mode)
     r, ms, stats = run_main(L, torch, km, args.steps, args.warmup)
     acc = stats[-1]["accesses"]
-    km.meta["accesses"] = acc
     checked = acc * r["rounds"]
     value = checked / (ms / 1e3)
     kern = kernel_rooflines(stats, "" if args.config == "plain-large" else args.config + "/")
@@ -415,32 +503,30 @@ def main():
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
                                           "kernel", "avg_launch_ms", "bytes_per_launch")},
         "kernels": kern,
-        # warm: Verify on the resident run log (the conflict-scan kernel of
-        # each round); cold: the whole repair, generation and sort included
-        "warm_check_accesses_per_s": (acc * sum(s["conf_launches"] for s in stats) /
-                                      (sum(s["ms_conf_kernels"] for s in stats) / 1e3)
-                                      if sum(s["ms_conf_kernels"] for s in stats) > 0 else None),
+        # the race-check phase (generation, sort, first-partner table) against
+        # its algorithmic bytes: 8 B written per record by generation, 16 B
+        # per radix pass, 8 B read by the first-partner scan
+        "race_check_phase": phase_roofline(stats),
+        # the once-per-kernel first-partner scan alone: accesses per second of
+        # that scan (later Verify calls reuse its table)
+        "first_partner_scan_accesses_per_s": (
+            acc * sum(s["conf_launches"] for s in stats) /
+            (sum(s["ms_conf_kernels"] for s in stats) / 1e3)
+            if sum(s["ms_conf_kernels"] for s in stats) > 0 else None),
         # one call with every phase timed, after the timed region
         "phases_ms": stats[-1]["phases"],
     }
-    if args.config == "plain-large" and args.mode == "literal" and "planted" in set(args.legs.split(",")):
-        # context: the same kernel with a planted safe barrier set (repair
-        # runs several Verify calls and ends SAFE)
-        kp = synth.generate("plain-large", mode="planted")
-        rp, msp, stp = run_main(L, torch, kp, max(1, args.steps // 2), 1)
-        kp_acc = stp[-1]["accesses"]
-        kk = kernel_rooflines(stp)
-        out["planted"] = {"value": kp_acc * rp["rounds"] / (msp / 1e3), "ms_per_step": msp,
-                          "verify_calls": rp["rounds"], "repair_status": rp["status"],
-                          "weight": rp["weight"],
-                          "j0_kernel_frac": kk["j0_kernel"]["frac"],
-                          "phases_ms": stp[-1]["phases"]}
-    if not args.no_cpu and args.config == "plain-large":
-        out["cpu_baseline"] = cpu_baseline(km, r["rounds"])
-    legs = set(args.legs.split(","))
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.config, args.mode, km)
+    del km
     torch.cuda.empty_cache()
-    if "stress" in legs:
-        out["stress"] = stress_leg(L, torch, args.stress_steps)
+    if "planted" in legs:
+        other = "planted" if args.mode == "literal" else "literal"
+        out["planted" if other == "planted" else "literal"] = kernel_leg(
+            L, torch, args.config, other, args.leg_steps)
+    if "plain" in legs and args.config != "plain-large":
+        out["plain_large"] = {m: kernel_leg(L, torch, "plain-large", m, args.leg_steps)
+                              for m in ("literal", "planted")}
     if "batched" in legs or "served" in legs or "rounds" in legs:
         kms = synth.generate_batch(n=args.batched_n, mode="planted")
         if "batched" in legs:
@@ -448,8 +534,15 @@ def main():
         if "rounds" in legs:
             out["rounds"] = rounds_leg(L, torch, kms)
         if "served" in legs:
-            out["served"] = served_leg(L, torch, kms, args.serve_rate, args.serve_seconds,
-                                       args.serve_arena_gb)
+            runs = [served_leg(L, torch, kms, float(rate), args.serve_seconds,
+                               args.serve_arena_gb)
+                    for rate in args.serve_rates.split(",") if rate]
+            out["served"] = {
+                "workload": "served: Poisson arrivals drawn from the batched kernels, "
+                            "%.0f GB arena, 1 s warm-up + %.1f s measured per rate"
+                            % (args.serve_arena_gb, args.serve_seconds),
+                "runs": runs,
+                "plain_loop_kernels_per_s": out.get("batched", {}).get("kernels_per_s_plain")}
     if "instrumented" in legs:
         out["instrumented"] = instrumented_leg(L, torch, args.batched_n)
     print(json.dumps(out))

@@ -322,8 +322,16 @@ rp_status rp_instrument(const rp_program* prog, const rp_instrument_opts* opts,
 void rp_last_stats(rp_stats* out);
 
 /* Sort autotuning: digit width of the LSD radix passes (0 = automatic,
- * else 8..11 bits).  Process-wide; returns the previous value. */
+ * else 8..11 bits).  Process-wide; returns the previous value.  The
+ * automatic width is the narrowest one (8..10 bits) that sorts the key in
+ * the fewest passes of at most 10 bits. */
 int rp_set_sort_digit_bits(int bits);
+
+/* Bits of the radix sort key of these kernels sorted together (the largest
+ * over them; 0 if one is invalid).  The key is the array id and the word,
+ * with each array's words rotated so that the ones its accesses can reach
+ * start at 0: its width sets the number of radix passes. */
+uint32_t rp_sort_key_bits(const rp_kernel* const* ks, uint32_t n);
 
 /* Tuning knobs (process-wide; return the previous value, -1 if rejected):
  *   RP_TUNE_SORT_DIGIT_BITS  0 = automatic, else 8..11;
@@ -347,7 +355,8 @@ int rp_set_sort_digit_bits(int bits);
  *                            occupancy query reports (default), else 1..8;
  *   RP_TUNE_SOLVER_NODES     log2 of the node budget of the exact solver's
  *                            branch and bound on one component of the
- *                            constraint set (4..40, default 28).  A job whose
+ *                            constraint set, per wave of the workgroup that
+ *                            searches it (4..40, default 28).  A job whose
  *                            search spends it ends with RP_ERR_SEARCH. */
 enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2,
        RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4 };

@@ -1,19 +1,29 @@
 """Autotuner of the radix sort: digit width and scatter tile shape.
 
 For a set of kernels (one size class) it times each (digit bits, tile shape)
-pair with the library's own hipEvent timings of the sort passes and keeps the
-fastest.  Results are cached in tuning.json next to this file, keyed by the
-GPU architecture and a size bucket (log2 of the access count), and applied
-through rp_set_tuning before a run.
+pair with the library's own hipEvent timings of record generation and the
+sort passes and keeps the fastest.  Results are cached in tuning.json next to
+this file, keyed by the GPU architecture and a size class: log2 of the access
+count and the radix key's width in bits (which sets how many passes each
+digit width needs).  They are applied through rp_set_tuning before a run.
+
+    python -m paper_2011_08373_amd.autotune [--out FILE] [workload ...]
+
+tunes the named workloads (default: the stress kernel in both modes, the
+plain-large kernel in both modes and the batched kernels) and rewrites their
+entries (in FILE instead of tuning.json when given; it starts from a copy of
+tuning.json).
 """
 from __future__ import annotations
 
 import json
 import math
 import os
+import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
+_out = [None]                 # where tune() writes (None: CACHE)
 CANDIDATES = [(rb, shape) for rb in (8, 9, 10, 11) for shape in range(10)]
 
 
@@ -23,8 +33,8 @@ def _arch() -> str:
     return getattr(p, "gcnArchName", p.name).split(":")[0]
 
 
-def bucket(n_accesses: int) -> str:
-    return "2^%d" % max(0, int(math.log2(max(1, n_accesses))))
+def bucket(n_accesses: int, key_bits: int) -> str:
+    return "2^%d/k%d" % (max(0, int(math.log2(max(1, n_accesses)))), int(key_bits))
 
 
 def _load() -> dict:
@@ -34,14 +44,14 @@ def _load() -> dict:
     return {}
 
 
-def lookup(n_accesses: int):
-    return _load().get(_arch(), {}).get(bucket(n_accesses))
+def lookup(n_accesses: int, key_bits: int):
+    return _load().get(_arch(), {}).get(bucket(n_accesses, key_bits))
 
 
-def apply(n_accesses: int) -> bool:
+def apply(n_accesses: int, key_bits: int) -> bool:
     """Set the knobs from the cache; False if this size class is not tuned."""
     from . import librepair as L
-    best = lookup(n_accesses)
+    best = lookup(n_accesses, key_bits)
     if not best:
         return False
     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, best["digit_bits"])
@@ -49,12 +59,17 @@ def apply(n_accesses: int) -> bool:
     return True
 
 
-def tune(kms, reps: int = 3, ws=None) -> dict:
+def tune(kms, reps: int = 3, ws=None, candidates=None) -> dict:
     """Time every candidate on a batch (or one kernel) and cache the best."""
     from . import librepair as L
     batch = isinstance(kms, (list, tuple)) or isinstance(kms, L.BatchArg)
+    if batch and not isinstance(kms, L.BatchArg):
+        kms = L.BatchArg(kms)
+    elif not batch:
+        kms = L.KernelArg(kms)
+    key_bits = L.sort_key_bits(kms)
     results = []
-    for rb, shape in CANDIDATES:
+    for rb, shape in candidates or CANDIDATES:
         L.set_tuning(L.TUNE_SORT_DIGIT_BITS, rb)
         L.set_tuning(L.TUNE_SCATTER_SHAPE, shape)
         times = []
@@ -73,10 +88,45 @@ def tune(kms, reps: int = 3, ws=None) -> dict:
         raise RuntimeError("no sort configuration ran")
     results.sort()
     t, rb, shape, acc = results[0]
-    data = _load()
-    data.setdefault(_arch(), {})[bucket(acc)] = dict(digit_bits=rb, shape=shape, ms=t)
-    with open(CACHE, "w") as f:
+    dest = _out[0] or CACHE
+    data = _load() if dest == CACHE or not os.path.exists(dest) else json.load(open(dest))
+    data.setdefault(_arch(), {})[bucket(acc, key_bits)] = dict(digit_bits=rb, shape=shape, ms=t)
+    with open(dest, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, rb)
     L.set_tuning(L.TUNE_SCATTER_SHAPE, shape)
-    return dict(digit_bits=rb, shape=shape, ms=t, table=[(r[1], r[2], r[0]) for r in results])
+    return dict(digit_bits=rb, shape=shape, ms=t, key_bits=key_bits,
+                table=[(r[1], r[2], r[0]) for r in results])
+
+
+WORKLOADS = ("stress-literal", "stress-planted", "plain-large-literal", "plain-large-planted",
+             "batched")
+
+
+def main(argv):
+    import torch
+    from . import librepair as L, synth
+    if argv[:1] == ["--out"]:
+        _out[0] = argv[1]
+        argv = argv[2:]
+    torch.cuda.set_device(0)
+    ws = L.Workspace()
+    for name in argv or WORKLOADS:
+        if name == "batched":
+            kms = synth.generate_batch(mode="planted")
+            reps = 3
+        else:
+            cfg, mode = name.rsplit("-", 1)
+            kms = synth.generate(cfg, mode=mode)
+            reps = 2 if cfg == "stress" else 3
+        r = tune(kms, reps=reps, ws=ws)
+        best = sorted(r["table"], key=lambda e: e[2])[:5]
+        print(json.dumps({"workload": name, "key_bits": r["key_bits"],
+                          "digit_bits": r["digit_bits"], "shape": r["shape"], "ms": r["ms"],
+                          "best5": best}), flush=True)
+        ws.t = None
+        torch.cuda.empty_cache()
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -329,6 +329,18 @@ int rp_set_sort_digit_bits(int bits) {
   return g_digit_bits_ref(bits, true);
 }
 
+uint32_t rp_sort_key_bits(const rp_kernel* const* ks, uint32_t n) {
+  if (n && !ks) return 0;
+  uint32_t kb = 0;
+  for (uint32_t q = 0; q < n; q++) {
+    if (validate_kernel(ks[q]) != RP_OK) return 0;
+    Plan pl;
+    make_plan(ks[q], pl);
+    kb = std::max(kb, pl.key_bits);
+  }
+  return kb;
+}
+
 int rp_set_tuning(int knob, int value) {
   switch (knob) {
     case RP_TUNE_SORT_DIGIT_BITS:

@@ -412,22 +412,25 @@ __global__ __launch_bounds__(CONF_BLOCK) void conf_kernel(const Job* __restrict_
 // With every barrier off a location is one sub-segment, and the first
 // partner of record r is the first later record q of its location with
 // (W_r or W_q) and id_r != id_q.  Call a "streak" a maximal stretch of records
-// of one id (a new location or a new id starts one; the entry's X bit) and,
-// among the writes of a location, a "write streak" likewise.  Then the first
-// partner of
+// of one id (a new location or a new id starts one) and, among the writes of
+// a location, a "write streak" likewise.  Then the first partner of
 //   - a write is the end of its streak: the first later record with another
 //     id (the records before it share the write's id);
 //   - a read is the first write f after it, or if f has the same id, the end
 //     of f's write streak.
 // (A point racing with itself needs no case of its own: its next record with
-// another id is that partner.)  Each wave stages 512 records in LDS, plus the
-// 64 after them, and walks them in chunks of 64 from the last to the first.
-// Inside a chunk the candidates come from ballot masks; past it from
-// wave-wide carries that hold partner points directly: the first streak start
-// at or after the chunk end, the first write ahead in the location (its id
-// and point) and its write-streak end.  The
-// carries are set up at the end of the range by short walks that start in the
-// staged lookahead chunk and stop at the end of the location.
+// another id is that partner.)
+//
+// Each wave takes a contiguous part of a log and walks it backward in chunks
+// of 64 records, one record per lane, straight from registers: a ballot of
+// each compare gives the location starts, streak starts and writes of the
+// chunk as 64-bit masks; a lane's first candidate is the lowest set bit above
+// it, whose point and id come from that lane by a cross-lane permute; past the
+// chunk, wave-wide carries (scalar registers) hold what lies ahead: the
+// partner point of the first streak start, and the first write with its id
+// and the end of its write streak.  The carries at the end of a part come
+// from a short forward walk over the records after it, which stops at the end
+// of the location it starts in.
 
 __device__ __forceinline__ uint32_t low_bit64(uint64_t m) {   // 64 if m == 0
   return m ? (uint32_t)__builtin_ctzll(m) : 64u;
@@ -435,75 +438,174 @@ __device__ __forceinline__ uint32_t low_bit64(uint64_t m) {   // 64 if m == 0
 __device__ __forceinline__ uint64_t above(uint32_t k) {       // bits k+1..63 (none for k >= 63)
   return k >= 63 ? 0ull : (~0ull << (k + 1));
 }
-// Partner point an entry stands for, NONE32 when it starts another location
-// (sentinels included).
-__device__ __forceinline__ uint32_t partner_of(uint64_t e) {
-  const uint32_t hi = (uint32_t)(e >> 32);
-  return (hi >> (RUN_LOC - 32)) & 1 ? NONE32 : (hi & 0xFFFu);
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// The record one lane down (lane 0 gets `first`, the record before the chunk).
+__device__ __forceinline__ uint64_t lane_before(uint64_t v, uint64_t first) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  // DPP wave shift right by one lane; the lane with no source keeps `old`
+  lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)first, (int)lo, 0x138, 0xF, 0xF, false);
+  hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(first >> 32), (int)hi, 0x138, 0xF,
+                                             0xF, false);
+  return ((uint64_t)hi << 32) | lo;
 }
 
-// The walks below visit 64-record chunks aligned to the staged range, so the
-// first chunk past the range is the staged lookahead; E(q) is the entry at q.
-// Lanes before the start position take no part in the answer.  Sentinel
-// entries (q >= n) start a streak and a location, so every walk ends at n.
+__device__ __forceinline__ uint32_t from_lane(uint32_t v, uint32_t l) {   // l < 64, any lane
+  return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(l << 2), (int)v);
+}
 
-// First streak start at or after q0 (n if none before the end).
-template <class F>
-__device__ uint64_t walk_streak_start(F&& E, uint64_t org, uint64_t q0, uint64_t n) {
-  if (q0 >= n) return n;
-  for (uint64_t base = org + ((q0 - org) & ~63ull); base < n; base += 64) {
-    const uint64_t q = base + __lane_id();
-    const uint64_t xm = __ballot(q >= q0 && ((E(q) >> RUN_X) & 1));
-    if (xm) return base + low_bit64(xm);
+// Fields of the records of one log.
+struct J0Fields {
+  int psh, ish;            // point and id field shifts (< 64)
+  uint32_t pmask, imask;   // point and id field masks
+  uint64_t locm, idm;      // location bits, id bits of a record
+};
+
+__device__ __forceinline__ J0Fields j0_fields(const Job& J, const ConfSeg& sg) {
+  // same-block view: [array|word|block|point|thread]; location = (array, word, block)
+  // cross-block view: [array|word|point|block|0];     location = (array, word)
+  J0Fields f;
+  const int psh = sg.level == 0 ? (int)J.tbits : (int)(J.bbits + J.tbits);
+  const int lsh = psh + (int)J.pbits;
+  const int ish = sg.level == 0 ? 0 : (int)J.tbits;
+  const uint64_t imask = sg.level == 0 ? ((1ull << J.tbits) - 1) : ((1ull << J.bbits) - 1);
+  f.psh = psh < 64 ? psh : 0;
+  f.pmask = psh < 64 ? (1u << J.pbits) - 1u : 0u;
+  f.ish = ish < 64 ? ish : 0;
+  f.imask = ish < 64 ? (uint32_t)imask : 0u;
+  f.locm = lsh < 64 ? ~0ull << lsh : 0ull;
+  f.idm = ish < 64 ? imask << ish : 0ull;
+  return f;
+}
+
+// One chunk of 64 records (lane l: record base + l) decoded into wave masks
+// and per-lane point and id.  Lanes past the log end read as location
+// starts, so every search stops there.
+struct J0Chunk {
+  uint64_t Lm, Xm, Wm;     // location starts, streak starts (Lm included), writes
+  uint32_t pt, id;
+  bool W;
+};
+
+__device__ __forceinline__ J0Chunk j0_decode(const J0Fields& f, const uint8_t* s_w, uint64_t rec,
+                                             uint64_t prev, uint64_t q, uint64_t n) {
+  J0Chunk c;
+  const bool valid = q < n;
+  const uint64_t df = rec ^ prev;
+  c.pt = (uint32_t)(rec >> f.psh) & f.pmask;
+  c.id = (uint32_t)(rec >> f.ish) & f.imask;
+  c.W = valid && s_w[c.pt];
+  c.Lm = ballot64(!valid || q == 0 || (df & f.locm) != 0);
+  c.Xm = c.Lm | ballot64((df & f.idm) != 0);
+  c.Wm = ballot64(c.W);
+  return c;
+}
+
+// What lies ahead of a position, for the records before it in its location.
+struct J0Carry {
+  uint32_t x;              // partner point of the first streak start (NONE32: a location start)
+  uint32_t fw, fw_id;      // first write before the location ends (NONE32: none), its id
+  uint32_t ws;             // end of that write's write streak: the first later write with
+                           // another id before the location ends (NONE32: none)
+};
+
+// The carries at the start of a chunk from the chunk and the carries at its
+// end (fields read into locals first, so that they stay in registers).
+__device__ __forceinline__ void j0_carry_update(J0Carry& cr, const J0Chunk& c) {
+  uint32_t x = cr.x, fw = cr.fw, fw_id = cr.fw_id, ws = cr.ws;
+  if (c.Xm) {
+    const uint32_t x0 = low_bit64(c.Xm);
+    const uint32_t px = __builtin_amdgcn_readlane(c.pt, x0);
+    x = ((c.Lm >> x0) & 1) ? NONE32 : px;
   }
-  return n;
-}
-
-// First write at or after q0 before the next location starts, or NOPOS.
-template <class F>
-__device__ uint64_t walk_first_write(F&& E, uint64_t org, uint64_t q0, uint64_t n) {
-  if (q0 >= n) return NOPOS;
-  for (uint64_t base = org + ((q0 - org) & ~63ull); base < n; base += 64) {
-    const uint64_t q = base + __lane_id();
-    const uint64_t e = E(q);
-    const uint64_t wm = __ballot(q >= q0 && ((e >> RUN_W) & 1));
-    const uint64_t lm = __ballot(q >= q0 && ((e >> RUN_LOC) & 1));
-    if (wm && (!lm || low_bit64(wm) < low_bit64(lm))) return base + low_bit64(wm);
-    if (lm) return NOPOS;
+  const uint64_t wl = c.Wm | c.Lm;
+  if (wl) {
+    const uint32_t b = low_bit64(wl);
+    if ((c.Lm >> b) & 1) {
+      fw = NONE32;
+      ws = NONE32;
+    } else {
+      const uint32_t fid = __builtin_amdgcn_readlane(c.id, b);
+      const uint32_t fpt = __builtin_amdgcn_readlane(c.pt, b);
+      const uint64_t after = above(b);
+      const uint64_t hm = ballot64(c.W && c.id != fid) & after;
+      const uint64_t lm = c.Lm & after;
+      const uint32_t h0 = low_bit64(hm);
+      const uint32_t ph = __builtin_amdgcn_readlane(c.pt, h0 & 63u);
+      uint32_t nws;
+      if (hm && h0 < low_bit64(lm)) nws = ph;
+      else if (lm) nws = NONE32;
+      else nws = (fw != NONE32 && fw_id != fid) ? fw : ws;
+      fw = fpt;
+      fw_id = fid;
+      ws = nws;
+    }
   }
-  return NOPOS;
+  cr.x = x;
+  cr.fw = fw;
+  cr.fw_id = fw_id;
+  cr.ws = ws;
 }
 
-// First write q > f whose id differs from f's (id_f) before the location
-// ends, or NOPOS.
-template <class F>
-__device__ uint64_t walk_write_streak_end(F&& E, uint64_t org, uint64_t f, uint32_t id_f,
-                                          uint64_t n) {
-  for (uint64_t base = org + ((f + 1 - org) & ~63ull); base < n; base += 64) {
-    const uint64_t q = base + __lane_id();
-    const uint64_t e = E(q);
-    const uint64_t hm = __ballot(q > f && ((e >> RUN_W) & 1) && (uint32_t)e != id_f);
-    const uint64_t lm = __ballot(q > f && ((e >> RUN_LOC) & 1));
-    if (hm && (!lm || low_bit64(hm) < low_bit64(lm))) return base + low_bit64(hm);
-    if (lm) return NOPOS;
+// Carries at position s (a multiple of 64 from the log start, or n) from
+// the records at and after it: a forward walk, chunk by chunk, until the
+// first streak start, the first write or location start and that write's
+// write-streak end are known.  It stops at the end of the location it
+// starts in (or of the log).
+__device__ J0Carry j0_carry_at(const uint64_t* __restrict__ log, uint64_t n, uint64_t s,
+                               const J0Fields& f, const uint8_t* s_w) {
+  J0Carry cr{NONE32, NONE32, 0, NONE32};
+  if (s >= n) return cr;
+  const uint32_t lane = __lane_id();
+  bool have_x = false, have_fw = false, have_ws = false;
+  uint64_t prev_last = log[s - 1];          // s > 0: a part never starts the walk at 0
+  for (uint64_t base = s; base < n + 64 && !(have_x && have_ws); base += 64) {
+    const uint64_t q = base + lane;
+    const uint64_t rec = q < n ? log[q] : 0;
+    const uint64_t prev = lane_before(rec, prev_last);
+    prev_last = __shfl(rec, 63);
+    const J0Chunk c = j0_decode(f, s_w, rec, prev, q, n);
+    if (!have_x && c.Xm) {
+      const uint32_t x0 = low_bit64(c.Xm);
+      cr.x = ((c.Lm >> x0) & 1) ? NONE32 : __builtin_amdgcn_readlane(c.pt, x0);
+      have_x = true;
+    }
+    uint64_t from = ~0ull;                  // lanes after the first write, if it is here
+    if (!have_fw) {
+      const uint64_t wl = c.Wm | c.Lm;
+      if (!wl) continue;
+      const uint32_t b = low_bit64(wl);
+      have_fw = true;
+      if ((c.Lm >> b) & 1) {
+        have_ws = true;                     // a location start first: no write ahead
+        continue;
+      }
+      cr.fw = __builtin_amdgcn_readlane(c.pt, b);
+      cr.fw_id = __builtin_amdgcn_readlane(c.id, b);
+      from = above(b);
+    }
+    if (!have_ws) {
+      const uint64_t hm = ballot64(c.W && c.id != cr.fw_id) & from;
+      const uint64_t lm = c.Lm & from;
+      if (hm && low_bit64(hm) < low_bit64(lm)) {
+        cr.ws = __builtin_amdgcn_readlane(c.pt, low_bit64(hm));
+        have_ws = true;
+      } else if (lm) {
+        have_ws = true;                     // ws stays NONE32
+      }
+    }
   }
-  return NOPOS;
+  return cr;
 }
 
-// A wave scans its 1024 records of a tile as ranges of J0_CHUNKS chunks: the
-// smaller LDS stage lets more waves share a compute unit, which hides the
-// LDS latency of the dependent lookups.
+// Chunks per range: the records of a range are all loaded before any is
+// decoded (that many loads in flight per lane).
 constexpr int J0_CHUNKS = 8;
-constexpr uint32_t J0_SPAN = (J0_CHUNKS + 1) * 64;     // staged range + one lookahead chunk
-static_assert(CONF_CHUNKS % J0_CHUNKS == 0, "ranges tile a wave's part of a tile");
 
-// (six waves per SIMD: the register budget that keeps enough waves in
-// flight to cover the dependent LDS reads of the chunk loop)
-__global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void j0_kernel(const Job* __restrict__ jobs,
+__global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ jobs,
                                                         const ConfSeg* __restrict__ segs, int nseg,
                                                         const uint32_t* __restrict__ total_at) {
-  __shared__ uint64_t s_buf[CONF_WAVES][J0_SPAN];
-  extern __shared__ uint32_t s_dyn[];        // [P] first partner, then [P] point | write bit << 12
+  extern __shared__ uint32_t s_dyn[];        // [P] first partner, then [P] write bit (bytes)
   // the tiles' 64-record chunks, split evenly over the workgroups (whole
   // tiles per workgroup would leave some with none when there are few tiles
   // per workgroup)
@@ -515,13 +617,11 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
   // bounds and the chunk loop stay scalar
   const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t lane = __lane_id();
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));   // lanes below
   const uint64_t gt = above(lane);                                  // lanes above
-  uint64_t* buf = s_buf[wv];
-  const uint32_t* buf_lo = reinterpret_cast<const uint32_t*>(buf);  // ids (low words)
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));   // lanes below
   int cur = -1;
   uint32_t* s_minj = s_dyn;
-  uint16_t* s_pw = nullptr;
+  uint8_t* s_w = nullptr;
   uint32_t P = 0;
   for (uint64_t u = u0; u < u1;) {
     const uint32_t tile = (uint32_t)(u / TC);
@@ -542,15 +642,17 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
       cur = lo;
       const Job& J = jobs[segs[cur].job];
       P = J.P;
-      s_pw = reinterpret_cast<uint16_t*>(s_dyn + P);
-      for (uint32_t i = tid; i < P; i += CONF_BLOCK) s_minj[i] = NONE32;
-      for (uint32_t q = tid; q < P; q += CONF_BLOCK)
-        s_pw[q] = (uint16_t)(q | (((J.wbits[q >> 6] >> (q & 63)) & 1) << (RUN_W - 32)));
+      s_w = reinterpret_cast<uint8_t*>(s_dyn + P);
+      for (uint32_t i = tid; i < P; i += CONF_BLOCK) {
+        s_minj[i] = NONE32;
+        s_w[i] = (uint8_t)((J.wbits[i >> 6] >> (i & 63)) & 1);
+      }
       __syncthreads();
     }
     const ConfSeg& sg = segs[cur];
     const uint64_t n = sg.n;
-    const RecView V = rec_view(jobs[sg.job], sg, s_pw);
+    const uint64_t* __restrict__ log = sg.log;
+    const J0Fields F = j0_fields(jobs[sg.job], sg);
     // this workgroup's chunks of the segment, as one record span cut into
     // one contiguous part per wave (whole chunks)
     const uint64_t ub = (uint64_t)sg.ctile_beg * TC;
@@ -562,113 +664,66 @@ __global__ __launch_bounds__(CONF_BLOCK) __attribute__((amdgpu_waves_per_eu(6)))
     const uint64_t s0 = min(rbeg + (uint64_t)wv * part, rend);
     const uint64_t s1 = min(s0 + part, rend);
     if (s0 >= s1) continue;
-    // the part is scanned backward in ranges of J0_CHUNKS chunks; the carries
-    // at the end of a range are those left at the start of the range after it
+    J0Carry cr = j0_carry_at(log, n, s1, F, s_w);
+    // the part backward in ranges of J0_CHUNKS chunks
     const int nr = (int)((s1 - s0 + J0_CHUNKS * 64 - 1) / (J0_CHUNKS * 64));
-    uint32_t pnx0 = NONE32, pfw = NONE32, pnws = NONE32, fw_id = 0;
-    uint64_t e_next = RUN_SENTINEL;     // first entry of the range after the current one
-    uint64_t ent[J0_CHUNKS + 1];        // this lane's entry of each staged chunk
     for (int r = nr - 1; r >= 0; r--) {
       const uint64_t wbeg = s0 + (uint64_t)r * (J0_CHUNKS * 64);
-      const uint64_t wend = min(wbeg + (uint64_t)(J0_CHUNKS * 64), s1);
-      if (r == nr - 1) {
-        // the part's last range and the chunk after it (the walks' first
-        // step) in LDS; carries for the positions from the end of the part
-        stage_entries<J0_CHUNKS + 1>(V, wbeg, buf, ent);
-        __builtin_amdgcn_wave_barrier();
-        auto entry = [&](uint64_t q) -> uint64_t {
-          return q - wbeg < J0_SPAN ? buf[q - wbeg] : entry_at(V, q);
-        };
-        if (wend < n) {
-          pnx0 = partner_of(entry(walk_streak_start(entry, wbeg, wend, n)));
-          const uint64_t fw = walk_first_write(entry, wbeg, wend, n);
-          if (fw != NOPOS) {
-            const uint64_t efw = entry(fw);
-            fw_id = (uint32_t)efw;
-            pfw = (uint32_t)(efw >> RUN_PT) & 0xFFFu;
-            const uint64_t nws = walk_write_streak_end(entry, wbeg, fw, fw_id, n);
-            pnws = nws != NOPOS ? (uint32_t)(entry(nws) >> RUN_PT) & 0xFFFu : NONE32;
-          }
-        }
-      } else {
-        // a whole range; the entry after it is the first of the range just
-        // scanned (the one candidate read past the range)
-        e_next = buf[0];
-        __builtin_amdgcn_wave_barrier();
-        stage_entries<J0_CHUNKS>(V, wbeg, buf, ent);
-        if (lane == 0) buf[J0_CHUNKS * 64] = e_next;
-        __builtin_amdgcn_wave_barrier();
-      }
-      const int nch = (int)((wend - wbeg + 63) / 64);
-      // (unrolled: each chunk's own entry comes from the registers the
-      // staging left it in; the candidates after it are read from LDS)
+      const int nch = (int)min((uint64_t)J0_CHUNKS, (s1 - wbeg + 63) / 64);
+      uint64_t rec[J0_CHUNKS];
 #pragma unroll
-      for (int c = J0_CHUNKS - 1; c >= 0; c--) {
-        if (c >= nch) continue;
-        const uint32_t b0 = (uint32_t)c * 64;
-        const uint64_t e = ent[c];
-        const uint32_t id = (uint32_t)e, eh = (uint32_t)(e >> 32);
-        const bool W = (eh >> (RUN_W - 32)) & 1;
-        const bool L = (eh >> (RUN_LOC - 32)) & 1;
-        const bool valid = !((eh >> (RUN_END - 32)) & 1);
-        const uint32_t i = eh & 0xFFFu;
-        const uint64_t Wm = __ballot(W), Lm = __ballot(L), Xm = __ballot((eh >> (RUN_X - 32)) & 1);
-        // first candidate, in the chunk or else the carried one (a location
-        // start there means no partner, which partner_of says): for a write
-        // the first streak start after it -- the first record with another
-        // id, since the records up to it share this one's id -- so it is the
-        // partner; for a read the first write after it
-        const uint32_t c1 = low_bit64((W ? Xm : (Wm | Lm)) & gt);   // chunk-local, 64 = past it
-        const uint64_t e1 = buf[b0 + c1];                            // inside the staged span
-        const bool in1 = c1 < 64;
-        const uint32_t id1 = in1 ? (uint32_t)e1 : fw_id;
-        const uint32_t p1 = in1 ? partner_of(e1) : (W ? pnx0 : pfw);
-        // a read whose first write has its own id: the partner is the first
-        // write-streak start or location start after that write
-        const bool same = !W && id1 == id;
-        uint32_t best = p1;
-        if (__ballot(valid && same && p1 != NONE32)) {
-          uint64_t XWLm = Lm;
-          if (__ballot(valid && c1 < 64 && same && p1 != NONE32)) {
-            // write-streak starts: writes whose id differs from the previous write
-            // of the chunk (a location start in between is caught by Lm first)
-            const uint64_t pm = Wm & lt;
-            const uint32_t pw = pm ? 63u - (uint32_t)__builtin_clzll(pm) : 0u;
-            const uint32_t idpw = buf_lo[2 * (b0 + pw)];
-            XWLm |= __ballot(W && pm && idpw != id);
-          }
-          const uint64_t M = XWLm & above(c1);
-          const uint32_t k2 = low_bit64(M);
-          const uint64_t e2 = buf[b0 + (k2 < 64 ? k2 : 0u)];
-          uint32_t p2;
-          if (k2 < 64) p2 = partner_of(e2);
-          else p2 = fw_id != id1 ? pfw : pnws;
-          if (same && p1 != NONE32) best = p2;
-        }
-        if (valid && best < P) atomicMin(&s_minj[i], best);
-        // carries for the positions from b0 on
-        const uint32_t x0 = low_bit64(Xm);
-        if (x0 < 64) pnx0 = partner_of(((uint64_t)__builtin_amdgcn_readlane(eh, x0)) << 32);
-        const uint32_t fl0 = low_bit64(Lm);
-        const uint64_t wb = fl0 < 64 ? (Wm & ((1ull << fl0) - 1)) : Wm;
-        if (wb) {
-          const uint32_t f0 = low_bit64(wb);
-          const uint32_t nid = __builtin_amdgcn_readlane(id, f0);
-          const uint32_t npt = __builtin_amdgcn_readlane(eh, f0) & 0xFFFu;
-          const uint64_t hm = __ballot(W && id != nid) & above(f0);
-          uint32_t nws;
-          if (hm && low_bit64(hm) < fl0) nws = __builtin_amdgcn_readlane(eh, low_bit64(hm)) & 0xFFFu;
-          else if (fl0 < 64) nws = NONE32;
-          else nws = (pfw != NONE32 && fw_id != nid) ? pfw : pnws;
-          fw_id = nid;
-          pfw = npt;
-          pnws = nws;
-        } else if (fl0 < 64) {
-          pfw = NONE32;
-          pnws = NONE32;
-        }
+      for (int k = 0; k < J0_CHUNKS; k++) {
+        const uint64_t q = wbeg + (uint64_t)k * 64 + lane;
+        rec[k] = (k < nch && q < n) ? log[q] : 0;
       }
-      __builtin_amdgcn_wave_barrier();
+      const uint64_t before = wbeg > 0 ? log[wbeg - 1] : 0;   // the record before the range
+#pragma unroll
+      for (int k = J0_CHUNKS - 1; k >= 0; k--) {
+        if (k >= nch) continue;
+        const uint64_t base = wbeg + (uint64_t)k * 64;
+        const uint64_t first = k > 0 ? (((uint64_t)__builtin_amdgcn_readlane(
+                                              (uint32_t)(rec[k - 1] >> 32), 63) << 32) |
+                                        __builtin_amdgcn_readlane((uint32_t)rec[k - 1], 63))
+                                     : before;
+        const J0Chunk c = j0_decode(F, s_w, rec[k], lane_before(rec[k], first), base + lane, n);
+        // first candidate: for a write the first streak start after it, for
+        // a read the first write or location start after it
+        const uint32_t c1 = low_bit64((c.W ? c.Xm : (c.Wm | c.Lm)) & gt);
+        const uint32_t l1 = c1 & 63u;
+        const uint32_t pt1 = from_lane(c.pt, l1), id1 = from_lane(c.id, l1);
+        const uint32_t cx = cr.x, cfw = cr.fw, cfw_id = cr.fw_id, cws = cr.ws;
+        uint32_t best;
+        bool second = false;           // a read whose first write has its own id
+        if (c1 < 64) {
+          if ((c.Lm >> c1) & 1) best = NONE32;
+          else if (c.W || id1 != c.id) best = pt1;
+          else { best = NONE32; second = true; }
+        } else if (c.W) {
+          best = cx;
+        } else if (cfw == NONE32 || cfw_id != c.id) {
+          best = cfw;
+        } else {
+          best = cws;
+        }
+        if (ballot64(second)) {
+          // write-streak starts in the chunk: writes whose id differs from
+          // the previous write of the chunk (a location start in between is
+          // met first); the end of the streak of the write at c1 is the first
+          // such start or location start after it, else it lies past the chunk
+          const uint64_t pm = c.Wm & lt;
+          const uint32_t pw = pm ? 63u - (uint32_t)__builtin_clzll(pm) : 0u;
+          const uint32_t idpw = from_lane(c.id, pw);
+          const uint64_t WSm = ballot64(c.W && pm != 0 && idpw != c.id);
+          const uint32_t k2 = low_bit64((WSm | c.Lm) & above(c1 < 64 ? c1 : 63));
+          const uint32_t pt2 = from_lane(c.pt, k2 & 63u);
+          if (second) {
+            if (k2 < 64) best = ((c.Lm >> k2) & 1) ? NONE32 : pt2;
+            else best = (cfw != NONE32 && cfw_id != id1) ? cfw : cws;
+          }
+        }
+        if (base + lane < n && best < P) atomicMin(&s_minj[c.pt], best);
+        j0_carry_update(cr, c);
+      }
     }
   }
   __syncthreads();
@@ -771,8 +826,8 @@ hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t 
 hipError_t launch_j0(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
                      const uint32_t* tiles, hipStream_t s) {
   if (nseg == 0) return hipSuccess;
-  // [P] first partners (u32) and [P] point | write bit (u16)
-  const size_t dyn = (size_t)(max_points ? max_points : 1) * (sizeof(uint32_t) + sizeof(uint16_t));
+  // [P] first partners (u32) and [P] write bits (bytes)
+  const size_t dyn = (size_t)(max_points ? max_points : 1) * (sizeof(uint32_t) + sizeof(uint8_t));
   int dev = 0, ncu = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);

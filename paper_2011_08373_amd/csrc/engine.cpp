@@ -25,7 +25,7 @@ struct Layout {
   size_t o_phi0 = 0;
   std::vector<size_t> o_pts, o_bany, o_bgrid, o_w, o_cpre, o_gpre, o_phi0j, o_wbits;
   size_t o_chunks = 0;
-  size_t o_recA = 0, o_recB = 0, o_cnt = 0, o_tot = 0, o_off = 0, o_err = 0;
+  size_t o_recA = 0, o_recB = 0, o_dig = 0, o_cnt = 0, o_tot = 0, o_off = 0, o_err = 0;
   std::vector<size_t> o_ivl, o_minj, o_j0, o_phi, o_scratch, o_traj, o_bitmap, o_pairs, o_ptotal;
   std::vector<uint32_t> phi_cap, scratch_cap;
   uint64_t n_rec = 0;
@@ -111,6 +111,12 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   L.o_chunks = off; off = up(off + (size_t)L.n_chunks * sizeof(SortChunk));
   L.o_recA = off; off = up(off + L.n_rec * sizeof(uint64_t));
   L.o_recB = off; off = up(off + L.n_rec * sizeof(uint64_t));   // sort ping-pong, then run log
+  // each record's digit of the next pass, written by a scatter beside its
+  // output and counted by the next pass (read as whole 16-byte vectors)
+  if (L.passes > 1) {
+    L.o_dig = off;
+    off = up(off + L.n_rec * (L.rb > 8 ? 2 : 1) + 16);
+  }
   L.o_cnt = off; off = up(off + (size_t)L.n_chunks * R * sizeof(uint32_t));
   L.o_tot = off; off = up(off + L.ssegs.size() * (size_t)R * sizeof(uint64_t));
   L.o_off = off; off = up(off + (size_t)L.n_chunks * R * sizeof(uint64_t));
@@ -366,10 +372,12 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
   for (int p = 0; p < passes; p++) {
     const uint64_t* in = (const uint64_t*)(d + ((p % 2 == 0) ? L.o_recA : L.o_recB));
     uint64_t* out = (uint64_t*)(d + ((p % 2 == 0) ? L.o_recB : L.o_recA));
-    HIPCHK(launch_sort_scan((int)L.rb, in, dss, (uint32_t)L.ssegs.size(), dch, nch, p, dcnt, dtot,
+    void* dig = L.passes > 1 ? (void*)(d + L.o_dig) : nullptr;
+    HIPCHK(launch_sort_scan((int)L.rb, dig, dss, (uint32_t)L.ssegs.size(), dch, nch, dcnt, dtot,
                             doff, derr + 10, p == 0, s));
     tm.mark(T_SORTPASS);
-    HIPCHK(launch_sort_scatter((int)L.rb, in, out, dss, dch, nch, p, doff, derr + 10, derr, s));
+    HIPCHK(launch_sort_scatter((int)L.rb, in, out, dss, dch, nch, p, doff, derr + 10, derr,
+                               p + 1 < passes ? dig : nullptr, s));
     tm.mark(T_SORT);
   }
   tm.mark(T_SORT, 2);
@@ -395,28 +403,38 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
 }  // namespace
 
 size_t engine_job_bytes(const JobInput& job) {
-  EngineOpts o;
-  o.op = OP_REPAIR;
   std::vector<JobInput> v{job};
-  return engine_workspace(v, o);
+  return engine_group_bytes(v);
 }
 
-int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStream_t s,
-                       PreparedJob& out, std::vector<uint8_t>& staging) {
+size_t engine_group_bytes(const std::vector<JobInput>& jobs) {
   EngineOpts o;
   o.op = OP_REPAIR;
-  std::vector<JobInput> v{job};
+  return engine_workspace(jobs, o);
+}
+
+int engine_prepare_group(const std::vector<JobInput>& jobs, void* region, size_t bytes,
+                         hipStream_t s, std::vector<PreparedJob>& out,
+                         std::vector<uint8_t>& staging) {
+  EngineOpts o;
+  o.op = OP_REPAIR;
   Layout L;
-  plan_layout(v, o, L);
+  plan_layout(jobs, o, L);
   if (bytes < L.total || !region) return RP_ERR_WORKSPACE;
   uint8_t* d = (uint8_t*)region;
   Timer tm(s, 0);
   staging.resize(L.meta);
-  const int rc = prepare_jobs(v, o, L, d, staging.data(), s, tm);
+  const int rc = prepare_jobs(jobs, o, L, d, staging.data(), s, tm);
   if (rc != RP_OK) return rc;
-  // the first Solve (an empty phi is answered by the initial x = 0)
-  if (!job.phi0.empty()) HIPCHK(launch_solve((const Job*)(d + L.o_jobs), 1, s));
-  std::memcpy(&out.job, staging.data() + L.o_jobs, sizeof(Job));
+  // the first Solve of the jobs with option units (an empty phi is
+  // answered by the initial x = 0): over the whole group, the others are
+  // left as they are by the solver
+  bool any_units = false;
+  for (const JobInput& j : jobs) any_units |= !j.phi0.empty();
+  if (any_units) HIPCHK(launch_solve((const Job*)(d + L.o_jobs), (uint32_t)jobs.size(), s));
+  out.resize(jobs.size());
+  for (size_t j = 0; j < jobs.size(); j++)
+    std::memcpy(&out[j].job, staging.data() + L.o_jobs + j * sizeof(Job), sizeof(Job));
   return RP_OK;
 }
 

@@ -15,14 +15,19 @@ hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job*
 // [(c - chunk_beg) * chunk_len, ...) up to the segment's end
 hipError_t launch_items(const Job* jobs, const SortSeg* segs, uint32_t nseg, uint32_t nchunks,
                         uint64_t chunk_len, GenItem* items, SortChunk* chunks, hipStream_t s);
-hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uint32_t nseg,
-                            const SortChunk* chunks, uint32_t nchunks, int pass, uint32_t* cnt,
+// dig: each record's digit of this pass (1 byte for 8-bit digits, else 2),
+// as the previous pass's scatter wrote it; unused when counts_ready (pass 0
+// takes its counts from record generation)
+hipError_t launch_sort_scan(int rb, const void* dig, const SortSeg* segs, uint32_t nseg,
+                            const SortChunk* chunks, uint32_t nchunks, uint32_t* cnt,
                             uint64_t* tot, uint64_t* off, uint32_t* ticket, bool counts_ready,
                             hipStream_t s);
-// ticket: one device word, set to zero by launch_sort_scan of the same pass
+// ticket: one device word, set to zero by launch_sort_scan of the same pass;
+// dnext: where each output record's digit of the next pass goes (NULL after
+// the last pass)
 hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
                                const SortChunk* chunks, uint32_t nchunks, int pass,
-                               const uint64_t* off, uint32_t* ticket, uint32_t* err,
+                               const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dnext,
                                hipStream_t s);
 constexpr int IVL_RESOLVE = 0, IVL_CHECK = 1, IVL_ZERO = 2;
 hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int mode, hipStream_t s);

@@ -98,6 +98,103 @@ int validate_kernel(const rp_kernel* k) {
   return RP_OK;
 }
 
+// Word compaction.  The sort only has to group records by location: the
+// order of the locations themselves is free.  So each array's words are
+// rotated (w -> (w + off) mod words) so that every word its accesses can
+// touch lands in [0, span), and the word field of the records is only as
+// wide as the largest span: fewer key bits, fewer or narrower radix passes.
+// The touched words of a point lie in the arc of the circle of residues from
+// the smallest to the largest value of a*t + b*k + c over its executing
+// threads and blocks; the rotation moves the largest gap between the union
+// of these arcs to the top of the range.  The rotation is folded into each
+// point's c, so record generation is unchanged.
+namespace {
+struct Arc { uint64_t s, len; };
+
+// [min, max] of x * (r + m*u) over u in [0, n) (n >= 1)
+void lin_range(int64_t x, uint64_t r, uint64_t m, uint64_t n, __int128& lo, __int128& hi) {
+  const __int128 a = (__int128)x * (__int128)r;
+  const __int128 b = (__int128)x * (__int128)m * (__int128)(n - 1);
+  lo = a + (b < 0 ? b : 0);
+  hi = a + (b > 0 ? b : 0);
+}
+}  // namespace
+
+void compact_words(const rp_kernel* k, Plan& pl) {
+  uint64_t span_max = 1;
+  for (uint32_t arr = 0; arr < k->n_arrays; arr++) {
+    const uint64_t N = k->arrays[arr].words;
+    std::vector<Arc> arcs;
+    bool full = N > (1ull << 31);    // rotated offsets must fit the int32 c
+    for (uint32_t i = 0; i < pl.P && !full; i++) {
+      const DPoint& d = pl.pts[i];
+      if (d.kind != RP_ACCESS || d.array != arr || d.cnt == 0) continue;
+      const uint64_t nblk = d.br < pl.B ? (pl.B - 1 - d.br) / d.bm + 1 : 0;
+      if (nblk == 0) continue;
+      __int128 tlo, thi, blo, bhi;
+      lin_range(d.a, d.r, d.m, d.cnt, tlo, thi);
+      lin_range(d.b, d.br, d.bm, nblk, blo, bhi);
+      const __int128 lo = tlo + blo + d.c, hi = thi + bhi + d.c;
+      if (hi - lo + 1 >= (__int128)N) {
+        full = true;
+        break;
+      }
+      __int128 st = lo % (__int128)N;
+      if (st < 0) st += N;
+      const uint64_t s0 = (uint64_t)st, len = (uint64_t)(hi - lo + 1);
+      if (s0 + len <= N) {
+        arcs.push_back(Arc{s0, len});
+      } else {                        // wraps past the top: two pieces
+        arcs.push_back(Arc{s0, N - s0});
+        arcs.push_back(Arc{0, s0 + len - N});
+      }
+    }
+    uint64_t off = 0, span = N;
+    if (!full && !arcs.empty()) {
+      std::sort(arcs.begin(), arcs.end(), [](const Arc& a, const Arc& b) { return a.s < b.s; });
+      // merged, disjoint arcs inside [0, N) in start order
+      std::vector<Arc> m;
+      for (const Arc& a : arcs) {
+        if (!m.empty() && a.s <= m.back().s + m.back().len) {
+          const uint64_t e = std::max(m.back().s + m.back().len, a.s + a.len);
+          m.back().len = e - m.back().s;
+        } else {
+          m.push_back(a);
+        }
+      }
+      // the gap after each merged arc, up to the next one's start (after the
+      // last one it runs round to the first one's start + N)
+      uint64_t best_gap = 0, best_next = 0;
+      for (size_t q = 0; q < m.size(); q++) {
+        const uint64_t end = m[q].s + m[q].len;
+        const uint64_t next = q + 1 < m.size() ? m[q + 1].s : m[0].s + N;
+        const uint64_t gap = next > end ? next - end : 0;
+        if (gap > best_gap) {
+          best_gap = gap;
+          best_next = next % N;
+        }
+      }
+      if (best_gap > 0) {
+        off = (N - best_next) % N;
+        span = N - best_gap;
+      }
+    } else if (!full) {
+      span = 1;                       // no access touches this array
+    }
+    span_max = std::max(span_max, span);
+    if (off == 0) continue;
+    for (uint32_t i = 0; i < pl.P; i++) {
+      DPoint& d = pl.pts[i];
+      if (d.kind != RP_ACCESS || d.array != arr) continue;
+      int64_t c = (int64_t)d.c % (int64_t)N;
+      if (c < 0) c += (int64_t)N;
+      d.c = (int32_t)(((uint64_t)c + off) % N);
+    }
+  }
+  pl.nbits = bits_for(span_max - 1);
+  pl.key_bits = pl.abits + pl.nbits;
+}
+
 void make_plan(const rp_kernel* k, Plan& pl) {
   pl.P = k->n_points;
   pl.S = k->n_slots;
@@ -188,6 +285,7 @@ void make_plan(const rp_kernel* k, Plan& pl) {
     pl.cnt_pre[i + 1] = pl.cnt_pre[i] + intra;
     pl.gcnt_pre[i + 1] = pl.gcnt_pre[i] + inter;
   }
+  compact_words(k, pl);
   pl.weights.assign(pl.S, 0);
   pl.grid_slots = pl.pre_slots = 0;
   for (uint32_t s = 0; s < pl.S; s++) {
@@ -199,10 +297,13 @@ void make_plan(const rp_kernel* k, Plan& pl) {
   pl.n_inter = pl.gcnt_pre[pl.P];
 }
 
+// Automatic digit width: the fewest passes of at most 10 bits, each as
+// narrow as that pass count allows (but at least 8 bits).
 int pick_digit_bits(uint32_t key_bits) {
   if (g_digit_bits) return g_digit_bits;
-  (void)key_bits;
-  return 8;
+  const uint32_t passes = std::max<uint32_t>(1, (key_bits + 9) / 10);
+  const uint32_t rb = (key_bits + passes - 1) / passes;
+  return (int)std::min<uint32_t>(10, std::max<uint32_t>(8, rb));
 }
 
 int sort_passes(uint32_t key_bits, int rb) { return (int)((key_bits + rb - 1) / rb); }

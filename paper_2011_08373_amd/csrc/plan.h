@@ -73,11 +73,15 @@ struct PreparedJob {
   Job job;
 };
 size_t engine_job_bytes(const JobInput& job);
-// Enqueues upload, record generation, sort, run log, the first-partner table
-// and the first Solve of one job into `region`; staging must stay alive until
-// the stream is synced.
-int engine_prepare_job(const JobInput& job, void* region, size_t bytes, hipStream_t s,
-                       PreparedJob& out, std::vector<uint8_t>& staging);
+// Bytes of one region holding a group of jobs prepared together.
+size_t engine_group_bytes(const std::vector<JobInput>& jobs);
+// Enqueues upload, record generation, sort, run logs, the first-partner
+// tables and the first Solve of a group of jobs into one region, with one
+// launch per phase for the whole group; out[j] is job j's device table
+// entry.  staging must stay alive until the stream is synced.
+int engine_prepare_group(const std::vector<JobInput>& jobs, void* region, size_t bytes,
+                         hipStream_t s, std::vector<PreparedJob>& out,
+                         std::vector<uint8_t>& staging);
 // Enqueues one round (Verify, GenerateClause, Solve, active count) over the
 // device table of njobs prepared jobs; *dactive receives the number of jobs
 // still running after it.

@@ -2,11 +2,12 @@
 //
 // Jobs are submitted at any time (the server copies their descriptors).  Each
 // rp_server_step():
-//   1. admits pending jobs in arrival order while the head job's footprint
-//      fits a free range of the arena (first fit) and a resident slot is
-//      free; an admitted job is prepared in its own range (upload, records,
-//      sort, run log, first Solve) -- its logs and clause set then stay
-//      resident until it finishes;
+//   1. admits pending jobs in arrival order while they fit: the jobs
+//      admitted in one step form a group that is laid out in one free range
+//      of the arena (first fit) and prepared together, one launch per phase
+//      for the whole group (upload, records, sort, run logs, first-partner
+//      tables, first Solve) -- their logs and clause sets then stay resident,
+//      and the range is released when the group's last job finishes;
 //   2. runs one round of Alg. 1 (Verify, GenerateClause, Solve) over every
 //      resident job at once, newly admitted ones included;
 //   3. retires the jobs that reached a verdict, frees their ranges and
@@ -32,6 +33,7 @@ namespace rp {
 namespace {
 
 constexpr size_t SALIGN = 256;
+constexpr size_t MAX_GROUP = 256;   // jobs admitted (and prepared together) per step
 size_t sup(size_t x) { return (x + SALIGN - 1) / SALIGN * SALIGN; }
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -66,9 +68,15 @@ struct SJob {
   OwnedKernel desc;
   Plan plan;
   JobInput input;
-  size_t bytes = 0, off = 0;
+  size_t bytes = 0;            // footprint of the job prepared alone
   PreparedJob prep;
   double t_submit = 0;
+  uint32_t group = 0;          // admission group holding its range
+};
+
+struct Group {
+  size_t off = 0, bytes = 0;
+  uint32_t live = 0;           // jobs of the group not yet finished
 };
 
 // first-fit allocator over [0, size)
@@ -127,7 +135,9 @@ struct Server {
   std::vector<std::unique_ptr<SJob>> resident;
   struct Done { uint64_t id; rp_repair_out out; double latency; };
   std::deque<Done> done;
-  std::vector<std::vector<uint8_t>> staging;
+  std::vector<uint8_t> staging;
+  std::map<uint32_t, Group> groups;
+  uint32_t next_group = 0;
   std::vector<Job> h_jobs;
   std::vector<JobState> h_states;
   uint64_t rounds = 0;
@@ -205,18 +215,47 @@ rp_status rp_server_step(void* srv, uint32_t* n_resident, uint32_t* n_pending) {
   Server* sv = (Server*)srv;
   if (!sv) return RP_ERR_INVALID;
   hipStream_t s = sv->s;
-  // 1. admission by footprint, arrival order
-  while (!sv->pending.empty() && sv->resident.size() < sv->max_resident) {
-    SJob& j = *sv->pending.front();
-    size_t off;
-    if (!sv->alloc.alloc(j.bytes, off)) break;
-    j.off = off;
-    sv->staging.emplace_back();
-    const int rc = engine_prepare_job(j.input, sv->arena + off, j.bytes, s, j.prep,
-                                      sv->staging.back());
-    if (rc != RP_OK) return (rp_status)rc;
-    sv->resident.push_back(std::move(sv->pending.front()));
-    sv->pending.pop_front();
+  // 1. admission by footprint, arrival order: the longest prefix of the
+  // pending jobs (up to MAX_GROUP) whose group region fits a free range and
+  // the free slots
+  {
+    std::vector<JobInput> group;
+    size_t n_take = 0, gbytes = 0, off = 0;
+    while (n_take < sv->pending.size() && n_take < MAX_GROUP &&
+           sv->resident.size() + n_take < sv->max_resident) {
+      group.push_back(sv->pending[n_take]->input);
+      const size_t b = sup(engine_group_bytes(group));
+      // the smaller group's range goes back first, so the larger one may
+      // take its place
+      if (n_take) sv->alloc.release(off, gbytes);
+      size_t o;
+      if (!sv->alloc.alloc(b, o)) {
+        group.pop_back();
+        // the range just released holds the smaller group again
+        if (n_take) (void)sv->alloc.alloc(gbytes, off);
+        break;
+      }
+      off = o;
+      gbytes = b;
+      n_take++;
+    }
+    if (n_take) {
+      std::vector<PreparedJob> prep;
+      const int rc = engine_prepare_group(group, sv->arena + off, gbytes, s, prep, sv->staging);
+      if (rc != RP_OK) {
+        sv->alloc.release(off, gbytes);
+        return (rp_status)rc;
+      }
+      const uint32_t gid = sv->next_group++;
+      sv->groups[gid] = Group{off, gbytes, (uint32_t)n_take};
+      for (size_t q = 0; q < n_take; q++) {
+        std::unique_ptr<SJob>& j = sv->pending.front();
+        j->prep = prep[q];
+        j->group = gid;
+        sv->resident.push_back(std::move(j));
+        sv->pending.pop_front();
+      }
+    }
   }
   const uint32_t n = (uint32_t)sv->resident.size();
   if (n) {
@@ -251,13 +290,16 @@ rp_status rp_server_step(void* srv, uint32_t* n_resident, uint32_t* n_pending) {
       fill_out(*j, sv->h_states[q], dn.out);
       dn.latency = t - j->t_submit;
       sv->done.push_back(dn);
-      sv->alloc.release(j->off, j->bytes);
+      auto g = sv->groups.find(j->group);
+      if (g != sv->groups.end() && --g->second.live == 0) {
+        sv->alloc.release(g->second.off, g->second.bytes);
+        sv->groups.erase(g);
+      }
     }
     sv->resident.swap(keep);
   } else if (hipStreamSynchronize(s) != hipSuccess) {
     return RP_ERR_DEVICE;
   }
-  sv->staging.clear();
   if (n_resident) *n_resident = (uint32_t)sv->resident.size();
   if (n_pending) *n_pending = (uint32_t)sv->pending.size();
   return RP_OK;

@@ -20,10 +20,18 @@
 //      holds the six lowest slots' 64 assignments, every clause is evaluated
 //      on whole words with AND/OR, and each word's cheapest feasible pattern
 //      is found through the patterns pre-sorted by key;
-//   4. a wider component is searched depth-first by one wave: branch on the
-//      free positive literals of the open clause with the fewest of them,
-//      prune on key and on a per-clause lower bound; clause tests are spread
-//      over the 64 lanes and combined with cross-lane reductions.
+//   4. a wider component is searched depth-first by all waves of the
+//      workgroup: branch on the free positive literals of the open clause
+//      with the fewest of them, prune on key and on a per-clause lower bound;
+//      clause tests are spread over the 64 lanes and combined with
+//      cross-lane reductions.  The tree's nodes at depth SPLIT_DEPTH are
+//      dealt out to the waves in the order of the search (every wave walks
+//      the levels above it alike, pruning there only dead nodes, so they all
+//      number those nodes the same way); below it each wave searches its own
+//      subtrees, pruning against the smallest weight any wave has found so
+//      far (a shared word) as well as its own best key.  The optimum is
+//      unique, so the smallest of the waves' best keys is the answer whatever
+//      order the waves run in.
 #include "common.h"
 #include "launch.h"
 
@@ -95,6 +103,7 @@ __device__ __forceinline__ uint64_t pat(int b) {
 }
 
 struct DfsFrame { uint64_t ones, zeros, khi, klo, todo, tried; };
+constexpr int SPLIT_DEPTH = 3;           // depth whose nodes are dealt out to the waves
 
 constexpr uint32_t GREEDY_MAX = 16384;   // clauses the greedy step handles (bitset in LDS)
 
@@ -191,8 +200,11 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
   __shared__ uint32_t s_order[64];
   __shared__ uint32_t s_gslot[64];
   __shared__ uint64_t smA[SV_WAVES], smB[SV_WAVES];
-  __shared__ uint32_t s_cnt, s_unsat;
-  __shared__ DfsFrame s_stack[65];
+  __shared__ uint32_t s_cnt;
+  __shared__ DfsFrame s_stack[SV_WAVES][65];
+  __shared__ unsigned long long s_bound;         // smallest weight part found by any wave
+  __shared__ uint32_t s_overflow;
+  __shared__ uint64_t s_inch[SV_WAVES], s_incl[SV_WAVES];
   __shared__ uint32_t s_hit[GREEDY_MAX / 32];
   __shared__ uint32_t s_c64[64], s_pick[64], s_best;
 
@@ -371,12 +383,18 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
       }
       best = block_min_key(best, smA, smB);
     } else {
-      // ---- 4. depth-first branch and bound by wave 0
-      if (wv == 0) {
+      // ---- 4. depth-first branch and bound by every wave
+      if (tid == 0) {
+        s_bound = ~0ull;
+        s_overflow = 0;
+      }
+      __syncthreads();
+      {
+        DfsFrame* stk = s_stack[wv];
         Key inc = {~0ull, ~0ull};
-        uint64_t inc_x = 0;
         bool found = false;
         uint64_t nodes = 0;
+        uint32_t split_idx = 0;      // nodes met at SPLIT_DEPTH so far
         int depth = 0;
         // a frame is pushed only after its node was evaluated: todo holds
         // the free literals of the chosen open clause
@@ -387,9 +405,20 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
         while (true) {
           if (eval_pending) {
             eval_pending = false;
-            nodes++;
+            bool mine = true;
+            if (depth == SPLIT_DEPTH) mine = (split_idx++ % SV_WAVES) == (uint32_t)wv;
+            // above the split every wave evaluates every node alike (no
+            // bound pruning there, so the numbering agrees); below it a node
+            // no better than a known weight is skipped
+            const uint64_t bound = depth >= SPLIT_DEPTH
+                                       ? (uint64_t)__hip_atomic_load(&s_bound, __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_WORKGROUP)
+                                       : ~0ull;
+            if (mine) nodes++;
             if (nodes > J.node_limit) { overflow = true; break; }
-            if (!(found && !key_lt(key, inc))) {
+            const bool skip = !mine || (depth >= SPLIT_DEPTH &&
+                                        ((found && !key_lt(key, inc)) || key.hi > bound));
+            if (!skip) {
               uint64_t dead = 0, pick = ~0ull, lbmax = 0;
               for (uint32_t q = lane; q < nc; q += 64) {
                 const uint64_t lp = s_lp[q], ln = s_ln[q];
@@ -406,15 +435,22 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
               if (!dead) {
                 if (pick == ~0ull) {
                   // every clause holds: a solution
-                  if (!found || key_lt(key, inc)) { inc = key; inc_x = ones; found = true; }
-                } else if (!(found && key.hi + lbmax > inc.hi)) {
+                  if (!found || key_lt(key, inc)) {
+                    inc = key;
+                    found = true;
+                    if (lane == 0)
+                      __hip_atomic_fetch_min(&s_bound, (unsigned long long)key.hi,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                  }
+                } else if (depth < SPLIT_DEPTH ||
+                           !((found && key.hi + lbmax > inc.hi) || key.hi + lbmax > bound)) {
                   const uint32_t q = (uint32_t)(pick & 0xFFFFFFFFu);
                   // every lane writes the same frame, so each lane's later
                   // read follows its own write
                   DfsFrame f;
                   f.ones = ones; f.zeros = zeros; f.khi = key.hi; f.klo = key.lo;
                   f.todo = s_lp[q] & ~zeros; f.tried = 0;
-                  s_stack[depth] = f;
+                  stk[depth] = f;
                   __builtin_amdgcn_wave_barrier();
                   depth++;
                 }
@@ -424,13 +460,13 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
           // next branch of the deepest frame with literals left
           if (depth == 0) break;
           __builtin_amdgcn_wave_barrier();
-          DfsFrame f = s_stack[depth - 1];
+          DfsFrame f = stk[depth - 1];
           if (f.todo == 0) { depth--; continue; }
           const uint64_t sbit = f.todo & (~f.todo + 1);
           const int b = __ffsll((unsigned long long)sbit) - 1;
           __builtin_amdgcn_wave_barrier();
-          s_stack[depth - 1].todo = f.todo & ~sbit;
-          s_stack[depth - 1].tried = f.tried | sbit;
+          stk[depth - 1].todo = f.todo & ~sbit;
+          stk[depth - 1].tried = f.tried | sbit;
           __builtin_amdgcn_wave_barrier();
           ones = f.ones | sbit;
           zeros = f.zeros | f.tried;
@@ -438,18 +474,23 @@ __global__ __launch_bounds__(SV_BLOCK) void solve_kernel(const Job* __restrict__
           key.lo = f.klo | s_kl[b];
           eval_pending = true;
         }
-        (void)inc_x;
         if (lane == 0) {
-          if (overflow) { st->err = ERR_NODES; st->state = ST_ERROR; }
-          s_unsat = overflow ? 2u : (found ? 1u : 0u);
-          smA[0] = inc.hi;
-          smB[0] = inc.lo;
+          if (overflow) atomicOr(&s_overflow, 1u);
+          s_inch[wv] = found ? inc.hi : ~0ull;
+          s_incl[wv] = found ? inc.lo : ~0ull;
         }
       }
       __syncthreads();
-      if (s_unsat == 2u) return;
-      if (s_unsat == 0u) { best.hi = ~0ull; best.lo = ~0ull; }
-      else { best.hi = smA[0]; best.lo = smB[0]; }
+      if (s_overflow) {
+        if (tid == 0) { st->err = ERR_NODES; st->state = ST_ERROR; }
+        return;
+      }
+      best.hi = s_inch[0];
+      best.lo = s_incl[0];
+      for (int q = 1; q < SV_WAVES; q++) {
+        const Key o = {s_inch[q], s_incl[q]};
+        if (key_lt(o, best)) best = o;
+      }
       __syncthreads();
     }
     if (best.hi == ~0ull && best.lo == ~0ull) {

@@ -2,15 +2,19 @@
 //
 // The record buffer is cut into chunks that never straddle a sort segment
 // (one log of one job).  Per digit pass:
-//   count_kernel     per chunk, how many records carry each digit (pass 0
-//                    takes these counts from record generation instead);
+//   count_kernel     per chunk, how many records carry each digit, read
+//                    from the digit array the previous pass's scatter wrote
+//                    beside its output (1 byte per record for 8-bit digits,
+//                    2 above), not from the 8-byte records (pass 0 takes its
+//                    counts from record generation instead);
 //   colsum_kernel    per (segment, digit), the total over the segment's chunks;
 //   colscan_kernel   per (segment, digit), the exclusive scan over the chunks,
 //                    offset by the segment start and the totals of smaller
 //                    digits: the first output slot of every (chunk, digit);
 //   scatter_kernel   per chunk, tiles of records are ranked stably with
 //                    64-lane ballots, staged in LDS in digit order and written
-//                    out as contiguous digit runs; a persistent grid sized to
+//                    out as contiguous digit runs, each record's digit of the
+//                    next pass beside it in the digit array; a persistent grid sized to
 //                    the resident workgroups takes chunks from a ticket
 //                    counter (reset by the column scan of the same pass), so
 //                    equal chunks that do not divide evenly among the
@@ -27,52 +31,53 @@ namespace rp {
 
 constexpr uint32_t SC_MAX_TILE = 8192;   // chunks are multiples of every tile shape
 
-// Per-chunk digit counts of one pass: cnt[chunk][d].  Whole batches of
-// CNT_U x 256 records are read with the next batch's loads issued before
-// the current one is counted, so each thread keeps CNT_U loads in flight
-// while it counts; every record is one LDS add (no return value, so the
-// adds do not stall the wave).
-constexpr int CNT_U = 8;
-
+// Digit of the next pass as stored by the scatter: one byte for 8-bit
+// digits, two for wider ones.
 template <int RB>
-__global__ __launch_bounds__(256) void count_kernel(const uint64_t* __restrict__ in,
+using DigT = typename std::conditional<(RB <= 8), uint8_t, uint16_t>::type;
+
+// Per-chunk digit counts of one pass: cnt[chunk][d], from the digit array
+// (digit of record q at dig[q]).  Each thread reads 16-byte vectors (16 or 8
+// digits), the next one issued before the current one is counted; every
+// digit is one LDS add with no return value (the adds do not stall the
+// wave).  A chunk's first and last vectors may reach past it: those digits
+// are skipped.
+template <int RB>
+__global__ __launch_bounds__(256) void count_kernel(const DigT<RB>* __restrict__ dig,
                                                     const SortChunk* __restrict__ chunks,
                                                     uint32_t nchunks,
-                                                    const SortSeg* __restrict__ segs, int pass,
                                                     uint32_t* __restrict__ cnt) {
   constexpr uint32_t R = 1u << RB;
-  constexpr uint64_t BATCH = (uint64_t)CNT_U * 256;
+  using D = DigT<RB>;
+  constexpr uint32_t V = 16 / sizeof(D);          // digits per vector
   __shared__ uint32_t hist[R];
   const uint32_t tid = threadIdx.x;
   for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {   // persistent
     const SortChunk ch = chunks[ci];
-    const int shift = (int)segs[ch.seg].shift + pass * RB;
     __syncthreads();
     for (uint32_t d = tid; d < R; d += 256) hist[d] = 0;
     __syncthreads();
-    const uint64_t* p = in + ch.beg;
-    const uint64_t n = ch.end - ch.beg;
-    const uint64_t full = n / BATCH * BATCH;
-    uint64_t cur[CNT_U];
-    if (full) {
+    // vectors covering [beg, end), aligned to V digits
+    const uint64_t v0 = ch.beg / V, v1 = (ch.end + V - 1) / V;
+    const uint4* src = reinterpret_cast<const uint4*>(dig);
+    uint64_t v = v0 + tid;
+    uint4 cur = v < v1 ? src[v] : make_uint4(0, 0, 0, 0);
+    while (v < v1) {
+      const uint64_t vn = v + 256;
+      const uint4 nxt = vn < v1 ? src[vn] : make_uint4(0, 0, 0, 0);
+      const D* e = reinterpret_cast<const D*>(&cur);
+      const uint64_t q0 = v * V;
+      if (q0 >= ch.beg && q0 + V <= ch.end) {
 #pragma unroll
-      for (int k = 0; k < CNT_U; k++) cur[k] = p[k * 256 + tid];
-    }
-    for (uint64_t r0 = 0; r0 < full; r0 += BATCH) {
-      uint64_t nxt[CNT_U];
-      const bool more = r0 + BATCH < full;
-      if (more) {
+        for (uint32_t k = 0; k < V; k++) atomicAdd(&hist[e[k]], 1u);
+      } else {
 #pragma unroll
-        for (int k = 0; k < CNT_U; k++) nxt[k] = p[r0 + BATCH + k * 256 + tid];
+        for (uint32_t k = 0; k < V; k++)
+          if (q0 + k >= ch.beg && q0 + k < ch.end) atomicAdd(&hist[e[k]], 1u);
       }
-#pragma unroll
-      for (int k = 0; k < CNT_U; k++) atomicAdd(&hist[digit_at(cur[k], shift, R - 1)], 1u);
-      if (more) {
-#pragma unroll
-        for (int k = 0; k < CNT_U; k++) cur[k] = nxt[k];
-      }
+      cur = nxt;
+      v = vn;
     }
-    for (uint64_t r = full + tid; r < n; r += 256) atomicAdd(&hist[digit_at(p[r], shift, R - 1)], 1u);
     __syncthreads();
     uint32_t* row = cnt + (size_t)ci * R;
     for (uint32_t d = tid; d < R; d += 256) row[d] = hist[d];
@@ -195,7 +200,8 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
                                                            int pass,
                                                            const uint64_t* __restrict__ off,
                                                            uint32_t* __restrict__ ticket,
-                                                           uint32_t* err) {
+                                                           uint32_t* err,
+                                                           DigT<RB>* __restrict__ dnext) {
   constexpr uint32_t R = 1u << RB;
   constexpr int SC_WAVES = SC_BLOCK / 64;
   constexpr uint32_t SC_TILE = SC_BLOCK * SC_IPT;
@@ -378,8 +384,13 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
       const uint64_t dst = gofs[d] + p;
       // a destination outside the segment can only come from inconsistent
       // counts: report it instead of writing
-      if (dst >= sg.beg && dst < sg.end) out[dst] = kv;
-      else atomicOr(err, ERR_RANGE);
+      if (dst >= sg.beg && dst < sg.end) {
+        out[dst] = kv;
+        // the next pass counts its digits from this array
+        if (dnext) dnext[dst] = (DigT<RB>)digit_at(kv, shift + RB, R - 1);
+      } else {
+        atomicOr(err, ERR_RANGE);
+      }
     }
     // the wave counters are free again: clear them for the next tile
     for (uint32_t q = tid; q < SC_WAVES * R; q += SC_BLOCK) (&whist[0][0])[q] = 0;
@@ -411,8 +422,8 @@ uint32_t sort_tile_size() { return SC_MAX_TILE; }
     default: return hipErrorInvalidValue;               \
   }
 
-hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uint32_t nseg,
-                            const SortChunk* chunks, uint32_t nchunks, int pass, uint32_t* cnt,
+hipError_t launch_sort_scan(int rb, const void* dig, const SortSeg* segs, uint32_t nseg,
+                            const SortChunk* chunks, uint32_t nchunks, uint32_t* cnt,
                             uint64_t* tot, uint64_t* off, uint32_t* ticket, bool counts_ready,
                             hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
@@ -422,7 +433,8 @@ hipError_t launch_sort_scan(int rb, const uint64_t* in, const SortSeg* segs, uin
     if (hipGetDevice(&dev) == hipSuccess)
       (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const uint32_t grid = std::min<uint32_t>(nchunks, (uint32_t)ncu * 8);
-    RB_SWITCH(rb, (count_kernel<RBV><<<grid, 256, 0, s>>>(in, chunks, nchunks, segs, pass, cnt)));
+    RB_SWITCH(rb, (count_kernel<RBV><<<grid, 256, 0, s>>>((const DigT<RBV>*)dig, chunks, nchunks,
+                                                          cnt)));
   }
   RB_SWITCH(rb, (colsum_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot)));
   RB_SWITCH(rb, (colscan_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot, off, ticket)));
@@ -445,7 +457,8 @@ int scatter_wgs(int v, bool set) {
 template <int RB, int BLOCK, int IPT, bool NTL = false>
 static void scatter_go(uint32_t nchunks, const uint64_t* in, uint64_t* out,
                        const SortChunk* chunks, const SortSeg* segs, int pass,
-                       const uint64_t* off, uint32_t* ticket, uint32_t* err, hipStream_t s) {
+                       const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dnext,
+                       hipStream_t s) {
   int dev = 0, ncu = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -458,51 +471,52 @@ static void scatter_go(uint32_t nchunks, const uint64_t* in, uint64_t* out,
   uint32_t grid = (uint32_t)ncu * (uint32_t)per_cu;
   if (grid > nchunks) grid = nchunks;
   scatter_kernel<RB, BLOCK, IPT, NTL><<<grid, BLOCK, 0, s>>>(in, out, chunks, nchunks, segs, pass, off, ticket,
-                                                              err);
+                                                              err, (DigT<RB>*)dnext);
 }
 
 template <int RB>
 static void scatter_launch(int variant, uint32_t nchunks, const uint64_t* in, uint64_t* out,
                            const SortChunk* chunks, const SortSeg* segs, int pass,
-                           const uint64_t* off, uint32_t* ticket, uint32_t* err,
+                           const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dn,
                            hipStream_t s) {
   switch (variant) {
-    case 1: scatter_go<RB, 256, 16>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
-    case 2: scatter_go<RB, 256, 32>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
-    case 4: scatter_go<RB, 512, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
-    case 5: scatter_go<RB, 1024, 4>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
-    case 6: scatter_go<RB, 256, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
+    case 1: scatter_go<RB, 256, 16>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
+    case 2: scatter_go<RB, 256, 32>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
+    case 4: scatter_go<RB, 512, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
+    case 5: scatter_go<RB, 1024, 4>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
+    case 6: scatter_go<RB, 256, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
     case 7:
-      scatter_go<RB, 512, 8, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
+      scatter_go<RB, 512, 8, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s);
       break;
     case 9:
-      scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
+      scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s);
       break;
     case 8:
       if constexpr (RB <= 9)
-        scatter_go<RB, 1024, 8, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
+        scatter_go<RB, 1024, 8, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s);
       else
-        scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
+        scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s);
       break;
     case 3:
       // 16 waves of per-digit counters do not fit LDS beside the tile for
       // wide digits
       if constexpr (RB <= 9) {
-        scatter_go<RB, 1024, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s);
+        scatter_go<RB, 1024, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s);
         break;
       }
       [[fallthrough]];
-    default: scatter_go<RB, 512, 16>(nchunks, in, out, chunks, segs, pass, off, ticket, err, s); break;
+    default: scatter_go<RB, 512, 16>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
   }
 }
 
 hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
                                const SortChunk* chunks, uint32_t nchunks, int pass,
-                               const uint64_t* off, uint32_t* ticket, uint32_t* err,
+                               const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dnext,
                                hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
   const int v = g_scatter_variant;
-  RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, pass, off, ticket, err, s)));
+  RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, pass, off, ticket, err,
+                                     dnext, s)));
   return hipGetLastError();
 }
 

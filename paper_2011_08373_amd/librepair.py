@@ -122,6 +122,8 @@ _L.rp_last_stats.argtypes = [C.POINTER(RpStats)]
 _L.rp_last_stats.restype = None
 _L.rp_set_sort_digit_bits.argtypes = [C.c_int]
 _L.rp_set_tuning.argtypes = [C.c_int, C.c_int]
+_L.rp_sort_key_bits.argtypes = [C.POINTER(C.POINTER(RpKernel)), C.c_uint32]
+_L.rp_sort_key_bits.restype = C.c_uint32
 _u32p = C.POINTER(C.c_uint32)
 _L.rp_instrument.argtypes = [C.POINTER(RpProgram), C.POINTER(RpInstrumentOpts),
                              C.c_void_p, C.c_void_p, C.c_uint32, _u32p, C.c_void_p, C.c_uint32,
@@ -321,7 +323,7 @@ class BatchArg:
     """C views of many kernel models."""
 
     def __init__(self, kms):
-        self.args = [KernelArg(k) for k in kms]
+        self.args = [k if isinstance(k, KernelArg) else KernelArg(k) for k in kms]
         self.ptrs = (C.POINTER(RpKernel) * max(1, len(kms)))(
             *[C.pointer(a.k) for a in self.args])
         self.n = len(kms)
@@ -438,6 +440,17 @@ def set_sort_digit_bits(bits: int) -> int:
 
 
 _tuning_epoch = [0]      # bumped by every tuning change (workspace sizes depend on it)
+
+
+def sort_key_bits(kms) -> int:
+    """Radix key bits of one kernel model or of a batch sorted together."""
+    if isinstance(kms, BatchArg):
+        b = kms
+    elif isinstance(kms, (list, tuple)):
+        b = BatchArg(kms)
+    else:
+        b = BatchArg([kms])
+    return int(_L.rp_sort_key_bits(b.ptrs, b.n))
 
 
 def set_tuning(knob: int, value: int) -> int:

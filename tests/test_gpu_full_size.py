@@ -103,20 +103,23 @@ def test_batched_full_size(L, batched_expected, mode):
 
 def test_batched_checked_kernels(L, batched_expected):
     # Verify and GenerateClause at x = 0 on 16 kernels spread over the size
-    # range (the largest, 65,536 threads, included)
+    # range of (point, block, thread) accesses, the largest included
     kms = synth.generate_batch(mode="planted")
     checked = batched_expected["checked"]
     assert len(checked) >= 12
+
+    def accesses(k):
+        return k.blocks * k.threads * int((k.points["kind"] == 0).sum())
     sizes = []
     for q, c in checked.items():
         km = kms[int(q)]
-        sizes.append(km.blocks * km.threads)
+        sizes.append(accesses(km))
         st, pairs, div, nrec, n = L.check(km, 0)
         assert st == 0 and nrec == c["n_records"] and div == c["divergent"], q
         assert [list(p) for p in pairs] == c["pairs"], q
         st, cl = L.clauses(km, 0)
         assert st == 0 and [list(v) for v in cl] == c["clauses"], q
-    assert max(sizes) == max(k.blocks * k.threads for k in kms)
+    assert max(sizes) == max(accesses(k) for k in kms)
 
 
 def test_served_full_size(L, batched_expected):
