@@ -362,6 +362,25 @@ enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 
        RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4 };
 int rp_set_tuning(int knob, int value);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the repair
+ * loop exactly as rp_repair gives it (same arguments, results and statuses),
+ * with no workspace argument.  The device workspace is a fixed array of
+ * rp_noalloc_scratch_bytes() (64 MiB) that the library holds on every GPU it
+ * runs on until the process ends; a kernel whose repair workspace
+ * (rp_workspace_bytes(k, RP_OP_REPAIR)) exceeds it is rejected with
+ * RP_ERR_WORKSPACE before any device work.  The call makes no device or
+ * page-locked allocation (descriptors and results go through ordinary host
+ * memory, rounds are launched without a graph, no timing events; host
+ * planning uses the heap) and synchronises `stream` before it returns.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (from several host threads or streams) race and must be serialised by
+ * the caller.  rp_last_stats is not updated. */
+size_t rp_noalloc_scratch_bytes(void);
+rp_status rp_repair_noalloc(const rp_kernel* k, const rp_repair_opts* opts,
+                            rp_repair_out* out, uint64_t* trajectory, uint32_t traj_cap,
+                            void* stream);
+
 #ifdef __cplusplus
 }
 #endif

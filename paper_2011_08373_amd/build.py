@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "lib", "librepair.so")
 SOURCES = ["gen.hip", "sort.hip", "check.hip", "clause.hip", "solve.hip",
-           "librepair.cpp", "engine.cpp", "api.cpp", "server.cpp", "instrument.cpp"]
+           "librepair.cpp", "engine.cpp", "api.cpp", "server.cpp", "instrument.cpp",
+           "noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-result",
          # packed FP32 instructions are kept out of every code object

@@ -454,8 +454,15 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   if (!ws && L.total) return RP_ERR_WORKSPACE;
   const size_t N = jobs.size();
   uint8_t* d = (uint8_t*)ws;
-  Timer tm(s, timing_level(0, false));
-  {
+  Timer tm(s, o.no_alloc ? 0 : timing_level(0, false));
+  // host staging: page-locked and kept per thread, or (no_alloc) ordinary
+  // memory, which the upload has read before hipMemcpyAsync returns
+  static thread_local std::vector<uint8_t> plain_stage, plain_rb;
+  if (o.no_alloc) {
+    plain_stage.resize(L.meta);
+    const int rc = prepare_jobs(jobs, o, L, d, plain_stage.data(), s, tm);
+    if (rc != RP_OK) return rc;
+  } else {
     uint8_t* h = t_stage.get(L.meta);
     if (!h) return RP_ERR_DEVICE;
     const int rc = prepare_jobs(jobs, o, L, d, h, s, tm);
@@ -475,7 +482,14 @@ int engine_run(const std::vector<JobInput>& jobs, const EngineOpts& o, void* ws,
   // job states, the error word and the start of each job's trajectory (the
   // usual few rounds) are read back into page-locked memory in one go
   const uint32_t traj_head = std::min<uint32_t>(o.traj_cap, 16);
-  uint8_t* rb = (uint8_t*)t_stage.readback(N * sizeof(JobState) + 64 + N * traj_head * sizeof(uint64_t));
+  const size_t rb_bytes = N * sizeof(JobState) + 64 + N * traj_head * sizeof(uint64_t);
+  uint8_t* rb;
+  if (o.no_alloc) {
+    plain_rb.resize(rb_bytes);
+    rb = plain_rb.data();
+  } else {
+    rb = (uint8_t*)t_stage.readback(rb_bytes);
+  }
   if (!rb) return RP_ERR_DEVICE;
   JobState* pst = (JobState*)rb;
   uint32_t* herr = (uint32_t*)(rb + N * sizeof(JobState));

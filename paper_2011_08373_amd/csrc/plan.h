@@ -62,6 +62,8 @@ struct EngineOpts {
   uint32_t traj_cap = 0;
   bool want_pairs = true;
   bool use_graph = true;            // capture each round in a hipGraph (non-null stream)
+  bool no_alloc = false;            // stage through ordinary host memory, record no
+                                    // timing events (no device or page-locked allocation)
 };
 
 // Bytes of workspace the engine needs for these jobs.

@@ -103,6 +103,10 @@ _L.rp_min_barriers.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint32, _
                                C.c_void_p, C.c_size_t, C.c_void_p]
 _L.rp_repair.argtypes = [_K, C.POINTER(RpOpts), C.POINTER(RpOut), C.c_void_p, C.c_uint32,
                          C.c_void_p, C.c_size_t, C.c_void_p]
+_L.rp_noalloc_scratch_bytes.argtypes = []
+_L.rp_noalloc_scratch_bytes.restype = C.c_size_t
+_L.rp_repair_noalloc.argtypes = [_K, C.POINTER(RpOpts), C.POINTER(RpOut), C.c_void_p, C.c_uint32,
+                                 C.c_void_p]
 _L.rp_batch_workspace_bytes.argtypes = [C.POINTER(C.POINTER(RpKernel)), C.c_uint32]
 _L.rp_batch_workspace_bytes.restype = C.c_size_t
 _L.rp_repair_batch.argtypes = [C.POINTER(C.POINTER(RpKernel)), C.c_uint32, C.POINTER(RpOpts),
@@ -313,6 +317,26 @@ def repair(km, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int
     traj = _traj(traj_cap)
     st = _L.rp_repair(ka.ref, C.byref(o), C.byref(out), traj, traj_cap, C.c_void_p(ptr), size,
                       _stream(stream))
+    r = dict(status=out.status, assign=out.assign, weight=out.weight, added=out.added,
+             removed=out.removed, rounds=out.rounds, n_clauses=out.n_clauses, ret=st)
+    r["trajectory"] = [traj[q] for q in range(min(out.rounds, traj_cap))]
+    return r
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of the fixed per-device array rp_repair_noalloc works in."""
+    return int(_L.rp_noalloc_scratch_bytes())
+
+
+def repair_noalloc(km, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int = 0,
+                   stream=None, traj_cap: int = 4096, solver: int = 0):
+    """rp_repair_noalloc: the repair loop with no workspace argument (the
+    library's fixed per-device array); dict like repair()."""
+    ka = _arg(km)
+    o = RpOpts(policy, grid, inspect, solver, max_rounds)
+    out = RpOut()
+    traj = _traj(traj_cap)
+    st = _L.rp_repair_noalloc(ka.ref, C.byref(o), C.byref(out), traj, traj_cap, _stream(stream))
     r = dict(status=out.status, assign=out.assign, weight=out.weight, added=out.added,
              removed=out.removed, rounds=out.rounds, n_clauses=out.n_clauses, ret=st)
     r["trajectory"] = [traj[q] for q in range(min(out.rounds, traj_cap))]
