@@ -357,9 +357,13 @@ uint32_t rp_sort_key_bits(const rp_kernel* const* ks, uint32_t n);
  *                            branch and bound on one component of the
  *                            constraint set, per wave of the workgroup that
  *                            searches it (4..40, default 28).  A job whose
- *                            search spends it ends with RP_ERR_SEARCH. */
+ *                            search spends it ends with RP_ERR_SEARCH;
+ *   RP_TUNE_SCAN_PIPELINE    first-partner scan: 0 = each wave loads a range
+ *                            of records after scanning the one before it
+ *                            (default), 1 = the next range's loads are in
+ *                            flight while a range is scanned. */
 enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2,
-       RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4 };
+       RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4, RP_TUNE_SCAN_PIPELINE = 5 };
 int rp_set_tuning(int knob, int value);
 
 /* For callers that cannot allocate device memory (code under stream

@@ -2,7 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -14,6 +16,7 @@ constexpr uint32_t TRAJ_CAP = 4096;
 extern int g_digit_bits_ref(int v, bool set);
 int scatter_variant(int v, bool set);
 int scatter_wgs(int v, bool set);
+int j0_variant(int v, bool set);
 
 // The option units of the switches of Section 4.2 (Tab. 3): with grid-level
 // barriers disabled every grid slot stays off; with inspection disabled every
@@ -35,6 +38,38 @@ std::vector<rp_clause> option_units(const Plan& pl, const rp_repair_opts& o) {
 
 static void worst_units(const Plan& pl, std::vector<rp_clause>& u) {
   u.assign(2 * pl.S, rp_clause{0, 0});
+}
+
+// The plans of many kernels (validated first), made on a few host threads
+// when there are many: each plan is independent.  plans[j] is valid only
+// where ok[j].
+static void make_plans(const rp_kernel* const* ks, uint32_t n, std::vector<Plan>& plans,
+                       std::vector<uint8_t>& ok) {
+  plans.assign(n, Plan{});
+  ok.assign(n, 0);
+  auto one = [&](uint32_t j) {
+    if (validate_kernel(ks[j]) != RP_OK) return;
+    make_plan(ks[j], plans[j]);
+    ok[j] = 1;
+  };
+  unsigned nth = std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+  if (n < 64 || nth < 2) {
+    for (uint32_t j = 0; j < n; j++) one(j);
+    return;
+  }
+  nth = std::min<unsigned>(nth, n / 32);
+  std::atomic<uint32_t> next(0);
+  auto work = [&]() {
+    for (;;) {
+      const uint32_t j0 = next.fetch_add(16);
+      if (j0 >= n) break;
+      for (uint32_t j = j0; j < std::min(n, j0 + 16); j++) one(j);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (unsigned t = 1; t < nth; t++) pool.emplace_back(work);
+  work();
+  for (std::thread& t : pool) t.join();
 }
 
 // The result of one repair job from its final device state.
@@ -261,16 +296,15 @@ rp_status rp_repair(const rp_kernel* k, const rp_repair_opts* opts, rp_repair_ou
 size_t rp_batch_workspace_bytes(const rp_kernel* const* ks, uint32_t n) {
   if (!ks) return 0;
   std::vector<Plan> plans;
-  plans.reserve(n);
+  std::vector<uint8_t> ok;
+  make_plans(ks, n, plans, ok);
+  std::vector<JobInput> v;
+  v.reserve(n);
   for (uint32_t j = 0; j < n; j++) {
-    if (validate_kernel(ks[j]) != RP_OK) continue;
-    plans.emplace_back();
-    make_plan(ks[j], plans.back());
-  }
-  std::vector<JobInput> v(plans.size());
-  for (size_t j = 0; j < plans.size(); j++) {
-    v[j].plan = &plans[j];
-    worst_units(plans[j], v[j].phi0);
+    if (!ok[j]) continue;
+    v.emplace_back();
+    v.back().plan = &plans[j];
+    worst_units(plans[j], v.back().phi0);
   }
   EngineOpts o;
   o.op = OP_REPAIR;
@@ -283,25 +317,21 @@ rp_status rp_repair_batch(const rp_kernel* const* ks, uint32_t n, const rp_repai
   rp_repair_opts op = opts ? *opts : rp_repair_opts{0, 1, 1, 0, 0};
   if (op.policy > 1 || op.solver > 1) return RP_ERR_INVALID;
   std::vector<Plan> plans;
+  std::vector<uint8_t> ok;
   std::vector<uint32_t> idx;
-  plans.reserve(n);
+  make_plans(ks, n, plans, ok);
   for (uint32_t j = 0; j < n; j++) {
     // every result reads as a failure until its job has a verdict, so a
     // call that ends early leaves no job looking repaired
     std::memset(&outs[j], 0, sizeof(outs[j]));
-    outs[j].status = RP_ERR_DEVICE;
-    if (validate_kernel(ks[j]) != RP_OK) {
-      outs[j].status = RP_ERR_INVALID;   // this job only; the others run
-      continue;
-    }
-    plans.emplace_back();
-    make_plan(ks[j], plans.back());
-    idx.push_back(j);
+    outs[j].status = ok[j] ? RP_ERR_DEVICE : RP_ERR_INVALID;   // invalid: this job only
+    if (ok[j]) idx.push_back(j);
   }
-  std::vector<JobInput> v(plans.size());
-  for (size_t q = 0; q < plans.size(); q++) {
-    v[q].plan = &plans[q];
-    v[q].phi0 = option_units(plans[q], op);
+  std::vector<JobInput> v(idx.size());
+  for (size_t q = 0; q < idx.size(); q++) {
+    const Plan& pl = plans[idx[q]];
+    v[q].plan = &pl;
+    v[q].phi0 = option_units(pl, op);
     v[q].policy = op.policy;
     v[q].max_rounds = op.max_rounds;
     v[q].solver = op.solver;
@@ -315,7 +345,7 @@ rp_status rp_repair_batch(const rp_kernel* const* ks, uint32_t n, const rp_repai
   t_stats = st;
   if (rc != RP_OK) return (rp_status)rc;
   for (size_t q = 0; q < v.size(); q++) {
-    fill_repair_out(res[q].st, plans[q], outs[idx[q]]);
+    fill_repair_out(res[q].st, plans[idx[q]], outs[idx[q]]);
   }
   return RP_OK;
 }
@@ -358,6 +388,9 @@ int rp_set_tuning(int knob, int value) {
     case RP_TUNE_SOLVER_NODES:
       if (value < 4 || value > 40) return -1;
       return solver_nodes_log2(value, true);
+    case RP_TUNE_SCAN_PIPELINE:
+      if (value < 0 || value > 1) return -1;
+      return j0_variant(value, true);
     default:
       return -1;
   }

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(1024) void conf_tiles_kernel(const Job* __restrict_
 // equal in (point, id) never race with each other.  Past the end: the
 // sentinel.
 struct RecView {
-  const uint64_t* log;
+  gptr<uint64_t> log;
   uint64_t n;
   int psh, ish;            // point and id field shifts (< 64)
   uint32_t pmask, imask;   // point and id field masks
@@ -167,7 +167,7 @@ __device__ __forceinline__ uint64_t shr(uint64_t v, int s) { return s >= 64 ? 0u
 
 __device__ __forceinline__ RecView rec_view(const Job& J, const ConfSeg& sg, const uint16_t* pw) {
   RecView v;
-  v.log = sg.log;
+  v.log = as_global(sg.log);
   v.n = sg.n;
   // same-block view: [array|word|block|point|thread]; location = (array, word, block)
   // cross-block view: [array|word|point|block|0];     location = (array, word)
@@ -439,6 +439,8 @@ __device__ __forceinline__ uint64_t above(uint32_t k) {       // bits k+1..63 (n
   return k >= 63 ? 0ull : (~0ull << (k + 1));
 }
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+// Lanes below the lowest set lane of m (all lanes when m is empty).
+__device__ __forceinline__ uint64_t below_first(uint64_t m) { return (m & (0ull - m)) - 1ull; }
 
 // The record one lane down (lane 0 gets `first`, the record before the chunk).
 __device__ __forceinline__ uint64_t lane_before(uint64_t v, uint64_t first) {
@@ -450,7 +452,9 @@ __device__ __forceinline__ uint64_t lane_before(uint64_t v, uint64_t first) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint32_t from_lane(uint32_t v, uint32_t l) {   // l < 64, any lane
+// Value of v in lane l mod 64 (ds_bpermute takes the source lane from the
+// byte address divided by four, modulo the wave size).
+__device__ __forceinline__ uint32_t from_lane(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(l << 2), (int)v);
 }
 
@@ -479,25 +483,31 @@ __device__ __forceinline__ J0Fields j0_fields(const Job& J, const ConfSeg& sg) {
 }
 
 // One chunk of 64 records (lane l: record base + l) decoded into wave masks
-// and per-lane point and id.  Lanes past the log end read as location
-// starts, so every search stops there.
+// and per-lane fields.  valid: this lane holds a record (all lanes but those
+// past the log end; always with FULL).  Lanes past the end read as location
+// starts, so every search stops there, and as non-writes in Wm (their own W,
+// point and id are never used).  Lane 0 of a chunk that starts the log needs
+// no flag of its own: a location start there only bounds searches from lanes
+// before it, and there are none.
 struct J0Chunk {
   uint64_t Lm, Xm, Wm;     // location starts, streak starts (Lm included), writes
   uint32_t pt, id;
-  bool W;
+  bool W, L, valid;        // this lane: a write, a location start, a record
 };
 
+template <bool FULL>
 __device__ __forceinline__ J0Chunk j0_decode(const J0Fields& f, const uint8_t* s_w, uint64_t rec,
-                                             uint64_t prev, uint64_t q, uint64_t n) {
+                                             uint64_t prev, bool valid) {
   J0Chunk c;
-  const bool valid = q < n;
   const uint64_t df = rec ^ prev;
   c.pt = (uint32_t)(rec >> f.psh) & f.pmask;
   c.id = (uint32_t)(rec >> f.ish) & f.imask;
-  c.W = valid && s_w[c.pt];
-  c.Lm = ballot64(!valid || q == 0 || (df & f.locm) != 0);
+  c.W = s_w[c.pt] != 0;
+  c.valid = FULL || valid;
+  c.L = (df & f.locm) != 0 || !c.valid;
+  c.Lm = ballot64(c.L);
   c.Xm = c.Lm | ballot64((df & f.idm) != 0);
-  c.Wm = ballot64(c.W);
+  c.Wm = ballot64(c.W && c.valid);
   return c;
 }
 
@@ -528,12 +538,13 @@ __device__ __forceinline__ void j0_carry_update(J0Carry& cr, const J0Chunk& c) {
       const uint32_t fid = __builtin_amdgcn_readlane(c.id, b);
       const uint32_t fpt = __builtin_amdgcn_readlane(c.pt, b);
       const uint64_t after = above(b);
-      const uint64_t hm = ballot64(c.W && c.id != fid) & after;
+      // (a ballot of a plain compare is the compare's own mask; a ballot of
+      // a conjunction would be rebuilt lane by lane)
+      const uint64_t hm = ballot64(c.id != fid) & c.Wm & after;
       const uint64_t lm = c.Lm & after;
-      const uint32_t h0 = low_bit64(hm);
-      const uint32_t ph = __builtin_amdgcn_readlane(c.pt, h0 & 63u);
+      const uint64_t hml = hm & below_first(lm);               // before the location ends
       uint32_t nws;
-      if (hm && h0 < low_bit64(lm)) nws = ph;
+      if (hml) nws = __builtin_amdgcn_readlane(c.pt, low_bit64(hml));
       else if (lm) nws = NONE32;
       else nws = (fw != NONE32 && fw_id != fid) ? fw : ws;
       fw = fpt;
@@ -552,7 +563,7 @@ __device__ __forceinline__ void j0_carry_update(J0Carry& cr, const J0Chunk& c) {
 // first streak start, the first write or location start and that write's
 // write-streak end are known.  It stops at the end of the location it
 // starts in (or of the log).
-__device__ J0Carry j0_carry_at(const uint64_t* __restrict__ log, uint64_t n, uint64_t s,
+__device__ J0Carry j0_carry_at(gptr<uint64_t> log, uint64_t n, uint64_t s,
                                const J0Fields& f, const uint8_t* s_w) {
   J0Carry cr{NONE32, NONE32, 0, NONE32};
   if (s >= n) return cr;
@@ -564,7 +575,7 @@ __device__ J0Carry j0_carry_at(const uint64_t* __restrict__ log, uint64_t n, uin
     const uint64_t rec = q < n ? log[q] : 0;
     const uint64_t prev = lane_before(rec, prev_last);
     prev_last = __shfl(rec, 63);
-    const J0Chunk c = j0_decode(f, s_w, rec, prev, q, n);
+    const J0Chunk c = j0_decode<false>(f, s_w, rec, prev, q < n);
     if (!have_x && c.Xm) {
       const uint32_t x0 = low_bit64(c.Xm);
       cr.x = ((c.Lm >> x0) & 1) ? NONE32 : __builtin_amdgcn_readlane(c.pt, x0);
@@ -585,7 +596,7 @@ __device__ J0Carry j0_carry_at(const uint64_t* __restrict__ log, uint64_t n, uin
       from = above(b);
     }
     if (!have_ws) {
-      const uint64_t hm = ballot64(c.W && c.id != cr.fw_id) & from;
+      const uint64_t hm = ballot64(c.W && c.id != cr.fw_id) & c.Wm & from;
       const uint64_t lm = c.Lm & from;
       if (hm && low_bit64(hm) < low_bit64(lm)) {
         cr.ws = __builtin_amdgcn_readlane(c.pt, low_bit64(hm));
@@ -599,13 +610,94 @@ __device__ J0Carry j0_carry_at(const uint64_t* __restrict__ log, uint64_t n, uin
 }
 
 // Chunks per range: the records of a range are all loaded before any is
-// decoded (that many loads in flight per lane).
+// decoded (that many loads in flight per lane).  With PIPE the next range's
+// loads are issued before the current range is scanned.
 constexpr int J0_CHUNKS = 8;
 
+// One range of chunks, scanned backward: first partners into s_minj, carries
+// moved to the range start.  rev[j]: this lane's record of chunk
+// J0_CHUNKS - 1 - j (the order of the scan, which is also the order of the
+// loads: the compiler issues the loads of an array in index order); before:
+// the record before the range (any value at the log start).  FULL: every
+// chunk of the range lies inside the log.
+template <bool FULL>
+__device__ __forceinline__ void j0_range(const J0Fields& F, const uint8_t* s_w, uint32_t* s_minj,
+                                         uint32_t P, const uint64_t (&rev)[J0_CHUNKS],
+                                         uint64_t before, uint64_t wbeg, int nch, uint64_t n,
+                                         J0Carry& cr) {
+  const uint32_t lane = __lane_id();
+  const uint64_t gt = above(lane);                                  // lanes above
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));   // lanes below
+#pragma unroll
+  for (int k = J0_CHUNKS - 1; k >= 0; k--) {
+    if (k >= nch) continue;
+    const uint64_t base = wbeg + (uint64_t)k * 64;
+    // readlane yields an int: each half is widened unsigned, or a set bit 31
+    // of the low half would spill into the high one
+    const uint64_t rk = rev[J0_CHUNKS - 1 - k];
+    const uint64_t rp = k > 0 ? rev[J0_CHUNKS - k] : 0;                  // chunk k - 1
+    const uint64_t first =
+        k > 0 ? (((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(rp >> 32), 63) << 32) |
+                 (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)rp, 63))
+              : before;
+    const J0Chunk c = j0_decode<FULL>(F, s_w, rk, lane_before(rk, first), FULL || base + lane < n);
+    // first candidate: for a write the first streak start after it, for
+    // a read the first write or location start after it; in the chunk it is
+    // read from its lane as a partner value (the point, or none where a
+    // location starts), past the chunk it is the carried one.  The lane's
+    // mask is picked without a select of 64-bit values: WL ^ ((Xm ^ WL) & W).
+    const uint64_t WL = c.Wm | c.Lm, E = c.Xm ^ WL;
+    const uint32_t sw = c.W ? ~0u : 0u;
+    const uint32_t mlo = (((uint32_t)E & sw) ^ (uint32_t)WL) & (uint32_t)gt;
+    const uint32_t mhi = (((uint32_t)(E >> 32) & sw) ^ (uint32_t)(WL >> 32)) & (uint32_t)(gt >> 32);
+    const uint32_t c1 = low_bit64(((uint64_t)mhi << 32) | mlo);
+    const bool in1 = c1 < 64;
+    const uint32_t pv = c.L ? NONE32 : c.pt;
+    const uint32_t pv1 = from_lane(pv, c1), id1 = from_lane(c.id, c1);
+    const uint32_t cfw = cr.fw, cfw_id = cr.fw_id, cws = cr.ws;
+    const uint32_t past = (cr.x & sw) | (cfw & ~sw);                // x for a write, fw for a read
+    const uint32_t cand = in1 ? pv1 : past;
+    const uint32_t idc = in1 ? id1 : cfw_id;
+    // a read whose first write has its own id: the partner is the end of
+    // that write's write streak (carried when the write lies past the chunk)
+    const bool second = !c.W && cand != NONE32 && idc == c.id;
+    uint32_t best = second ? cws : cand;
+    // Reads whose first write f lies in the chunk with the read's own id:
+    // the partner is the first write after f with another id before the
+    // location ends.  With write-streak starts (writes whose id differs from
+    // that of the write before them in the chunk; a location start in
+    // between is met first) it is the first such start or location start
+    // after f, else it lies past the chunk: the carried first write if its
+    // id differs, else the end of that write's write streak.  Only chunks
+    // where some read needs it take this step.
+    const uint64_t need =
+        ~c.Wm & ballot64(cand != NONE32) & ballot64(idc == c.id) & ballot64(in1) &
+        (FULL ? ~0ull : ballot64(c.valid));
+    if (need) {
+      const uint64_t pm = c.Wm & lt;                          // writes below this lane
+      const uint32_t pw = pm ? 63u - (uint32_t)__builtin_clzll(pm) : 0u;
+      const uint32_t idpw = from_lane(c.id, pw);
+      // (lanes above the chunk's first write have a write below them)
+      const uint64_t WSm = ballot64(idpw != c.id) & c.Wm & above(low_bit64(c.Wm));
+      const uint32_t k2 = low_bit64((WSm | c.Lm) & above(c1));   // c1 < 64 where needed
+      const uint32_t pv2 = from_lane(pv, k2);
+      if (second && in1)
+        best = k2 < 64 ? pv2 : ((cfw != NONE32 && cfw_id != id1) ? cfw : cws);
+    }
+    if (c.valid && best < P) atomicMin(&s_minj[c.pt], best);
+    j0_carry_update(cr, c);
+  }
+}
+
+template <bool PIPE>
 __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ jobs,
                                                         const ConfSeg* __restrict__ segs, int nseg,
                                                         const uint32_t* __restrict__ total_at) {
-  extern __shared__ uint32_t s_dyn[];        // [P] first partner, then [P] write bit (bytes)
+  // the write bit of each point (bytes; a static array, so that its LDS
+  // address is known when compiling and a point is read with no address
+  // arithmetic) and the first partner of each point (u32, [P] dynamic)
+  __shared__ uint8_t s_w[MAX_POINTS];
+  extern __shared__ uint32_t s_dyn[];
   // the tiles' 64-record chunks, split evenly over the workgroups (whole
   // tiles per workgroup would leave some with none when there are few tiles
   // per workgroup)
@@ -617,11 +709,8 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
   // bounds and the chunk loop stay scalar
   const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t lane = __lane_id();
-  const uint64_t gt = above(lane);                                  // lanes above
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));   // lanes below
   int cur = -1;
   uint32_t* s_minj = s_dyn;
-  uint8_t* s_w = nullptr;
   uint32_t P = 0;
   for (uint64_t u = u0; u < u1;) {
     const uint32_t tile = (uint32_t)(u / TC);
@@ -642,7 +731,6 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
       cur = lo;
       const Job& J = jobs[segs[cur].job];
       P = J.P;
-      s_w = reinterpret_cast<uint8_t*>(s_dyn + P);
       for (uint32_t i = tid; i < P; i += CONF_BLOCK) {
         s_minj[i] = NONE32;
         s_w[i] = (uint8_t)((J.wbits[i >> 6] >> (i & 63)) & 1);
@@ -651,7 +739,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
     }
     const ConfSeg& sg = segs[cur];
     const uint64_t n = sg.n;
-    const uint64_t* __restrict__ log = sg.log;
+    const gptr<uint64_t> log = as_global(sg.log);
     const J0Fields F = j0_fields(jobs[sg.job], sg);
     // this workgroup's chunks of the segment, as one record span cut into
     // one contiguous part per wave (whole chunks)
@@ -667,62 +755,44 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
     J0Carry cr = j0_carry_at(log, n, s1, F, s_w);
     // the part backward in ranges of J0_CHUNKS chunks
     const int nr = (int)((s1 - s0 + J0_CHUNKS * 64 - 1) / (J0_CHUNKS * 64));
+    // a range's loads: the record before it (needed last) first, then its
+    // chunks in the order they are scanned (the last first), so the scan can
+    // start before the whole range has arrived; none is conditional (chunks
+    // past the part are read but not scanned, lanes past the log end read
+    // its last record, and neither value is used)
+    auto load_range = [&](int r, uint64_t (&dst)[J0_CHUNKS], uint64_t& bef) {
+      const uint64_t wb = s0 + (uint64_t)r * (J0_CHUNKS * 64);
+      bef = log[wb > 0 ? wb - 1 : 0];
+#pragma unroll
+      for (int j = 0; j < J0_CHUNKS; j++) {
+        const uint64_t q = wb + (uint64_t)(J0_CHUNKS - 1 - j) * 64 + lane;
+        dst[j] = log[q < n ? q : n - 1];
+      }
+    };
+    auto scan_range = [&](const uint64_t (&rv)[J0_CHUNKS], uint64_t before, uint64_t wbeg,
+                          int nch) {
+      if (wbeg + (uint64_t)nch * 64 <= n)
+        j0_range<true>(F, s_w, s_minj, P, rv, before, wbeg, nch, n, cr);
+      else
+        j0_range<false>(F, s_w, s_minj, P, rv, before, wbeg, nch, n, cr);
+    };
+    uint64_t rev[J0_CHUNKS], before;
+    load_range(nr - 1, rev, before);
     for (int r = nr - 1; r >= 0; r--) {
       const uint64_t wbeg = s0 + (uint64_t)r * (J0_CHUNKS * 64);
       const int nch = (int)min((uint64_t)J0_CHUNKS, (s1 - wbeg + 63) / 64);
-      uint64_t rec[J0_CHUNKS];
+      if constexpr (PIPE) {
+        uint64_t nxt[J0_CHUNKS], nbef = 0;
+        if (r > 0) load_range(r - 1, nxt, nbef);
+        scan_range(rev, before, wbeg, nch);
+        if (r > 0) {
 #pragma unroll
-      for (int k = 0; k < J0_CHUNKS; k++) {
-        const uint64_t q = wbeg + (uint64_t)k * 64 + lane;
-        rec[k] = (k < nch && q < n) ? log[q] : 0;
-      }
-      const uint64_t before = wbeg > 0 ? log[wbeg - 1] : 0;   // the record before the range
-#pragma unroll
-      for (int k = J0_CHUNKS - 1; k >= 0; k--) {
-        if (k >= nch) continue;
-        const uint64_t base = wbeg + (uint64_t)k * 64;
-        const uint64_t first = k > 0 ? (((uint64_t)__builtin_amdgcn_readlane(
-                                              (uint32_t)(rec[k - 1] >> 32), 63) << 32) |
-                                        __builtin_amdgcn_readlane((uint32_t)rec[k - 1], 63))
-                                     : before;
-        const J0Chunk c = j0_decode(F, s_w, rec[k], lane_before(rec[k], first), base + lane, n);
-        // first candidate: for a write the first streak start after it, for
-        // a read the first write or location start after it
-        const uint32_t c1 = low_bit64((c.W ? c.Xm : (c.Wm | c.Lm)) & gt);
-        const uint32_t l1 = c1 & 63u;
-        const uint32_t pt1 = from_lane(c.pt, l1), id1 = from_lane(c.id, l1);
-        const uint32_t cx = cr.x, cfw = cr.fw, cfw_id = cr.fw_id, cws = cr.ws;
-        uint32_t best;
-        bool second = false;           // a read whose first write has its own id
-        if (c1 < 64) {
-          if ((c.Lm >> c1) & 1) best = NONE32;
-          else if (c.W || id1 != c.id) best = pt1;
-          else { best = NONE32; second = true; }
-        } else if (c.W) {
-          best = cx;
-        } else if (cfw == NONE32 || cfw_id != c.id) {
-          best = cfw;
-        } else {
-          best = cws;
+          for (int j = 0; j < J0_CHUNKS; j++) rev[j] = nxt[j];
+          before = nbef;
         }
-        if (ballot64(second)) {
-          // write-streak starts in the chunk: writes whose id differs from
-          // the previous write of the chunk (a location start in between is
-          // met first); the end of the streak of the write at c1 is the first
-          // such start or location start after it, else it lies past the chunk
-          const uint64_t pm = c.Wm & lt;
-          const uint32_t pw = pm ? 63u - (uint32_t)__builtin_clzll(pm) : 0u;
-          const uint32_t idpw = from_lane(c.id, pw);
-          const uint64_t WSm = ballot64(c.W && pm != 0 && idpw != c.id);
-          const uint32_t k2 = low_bit64((WSm | c.Lm) & above(c1 < 64 ? c1 : 63));
-          const uint32_t pt2 = from_lane(c.pt, k2 & 63u);
-          if (second) {
-            if (k2 < 64) best = ((c.Lm >> k2) & 1) ? NONE32 : pt2;
-            else best = (cfw != NONE32 && cfw_id != id1) ? cfw : cws;
-          }
-        }
-        if (base + lane < n && best < P) atomicMin(&s_minj[c.pt], best);
-        j0_carry_update(cr, c);
+      } else {
+        scan_range(rev, before, wbeg, nch);
+        if (r > 0) load_range(r - 1, rev, before);
       }
     }
   }
@@ -823,20 +893,36 @@ hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t 
   return hipGetLastError();
 }
 
-hipError_t launch_j0(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
-                     const uint32_t* tiles, hipStream_t s) {
-  if (nseg == 0) return hipSuccess;
-  // [P] first partners (u32) and [P] write bits (bytes)
-  const size_t dyn = (size_t)(max_points ? max_points : 1) * (sizeof(uint32_t) + sizeof(uint8_t));
+static int g_j0_variant = 0;   // 0: loads of a range after the range before it is scanned,
+                               // 1: the next range's loads in flight during the scan
+int j0_variant(int v, bool set) {
+  const int old = g_j0_variant;
+  if (set) g_j0_variant = v;
+  return old;
+}
+
+template <bool PIPE>
+static hipError_t j0_go(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
+                        const uint32_t* tiles, hipStream_t s) {
+  // [P] first partners (u32); the write bits are a static array
+  const size_t dyn = (size_t)(max_points ? max_points : 1) * sizeof(uint32_t);
   int dev = 0, ncu = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, j0_kernel, CONF_BLOCK, dyn) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, j0_kernel<PIPE>, CONF_BLOCK, dyn) !=
+          hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   const uint32_t grid = (uint32_t)ncu * (uint32_t)std::min(per_cu, 8);
-  j0_kernel<<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
+  j0_kernel<PIPE><<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
   return hipGetLastError();
+}
+
+hipError_t launch_j0(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
+                     const uint32_t* tiles, hipStream_t s) {
+  if (nseg == 0) return hipSuccess;
+  return g_j0_variant == 1 ? j0_go<true>(jobs, segs, nseg, max_points, tiles, s)
+                           : j0_go<false>(jobs, segs, nseg, max_points, tiles, s);
 }
 
 hipError_t launch_pairs(const Job* job, rp_pair* out, uint64_t* total, hipStream_t s) {

@@ -184,4 +184,16 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Global-memory view of a pointer read from a device table.  The compiler
+// must use flat instructions for a pointer of unknown address space, and a
+// flat load also counts against the LDS wait counter: every wait for it then
+// waits for all LDS operations too, and a wait for an LDS result waits for
+// every load in flight.  Loads through this view are global loads.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+  return (gptr<T>)p;
+}
+
 }  // namespace rp

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <vector>
 
@@ -105,81 +106,138 @@ int validate_kernel(const rp_kernel* k) {
 // wide as the largest span: fewer key bits, fewer or narrower radix passes.
 // The touched words of a point lie in the arc of the circle of residues from
 // the smallest to the largest value of a*t + b*k + c over its executing
-// threads and blocks; the rotation moves the largest gap between the union
-// of these arcs to the top of the range.  The rotation is folded into each
-// point's c, so record generation is unchanged.
+// threads and blocks.  The circle is cut into CW_BINS bins; every bin an arc
+// meets is marked, and the rotation moves the longest run of unmarked bins
+// (words no access can touch) to the top of the range.  The rotation is
+// folded into each point's c, so record generation is unchanged.
 namespace {
-struct Arc { uint64_t s, len; };
+constexpr uint32_t CW_BINS = 256;
 
-// [min, max] of x * (r + m*u) over u in [0, n) (n >= 1)
-void lin_range(int64_t x, uint64_t r, uint64_t m, uint64_t n, __int128& lo, __int128& hi) {
-  const __int128 a = (__int128)x * (__int128)r;
-  const __int128 b = (__int128)x * (__int128)m * (__int128)(n - 1);
-  lo = a + (b < 0 ? b : 0);
-  hi = a + (b > 0 ? b : 0);
+// [min, max] of x * (r + m*u) over u in [0, n) (n >= 1); false on overflow
+bool lin_range(int64_t x, uint64_t r, uint64_t m, uint64_t n, int64_t& lo, int64_t& hi) {
+  int64_t a, b;
+  if (r > (uint64_t)INT64_MAX || m * (n - 1) > (uint64_t)INT64_MAX) return false;
+  if (__builtin_mul_overflow(x, (int64_t)r, &a)) return false;
+  if (__builtin_mul_overflow(x, (int64_t)(m * (n - 1)), &b)) return false;
+  int64_t l = 0, h = 0;
+  if (__builtin_add_overflow(a, b < 0 ? b : 0, &l)) return false;
+  if (__builtin_add_overflow(a, b > 0 ? b : 0, &h)) return false;
+  lo = l;
+  hi = h;
+  return true;
 }
 }  // namespace
 
 void compact_words(const rp_kernel* k, Plan& pl) {
-  uint64_t span_max = 1;
-  for (uint32_t arr = 0; arr < k->n_arrays; arr++) {
+  const uint32_t A = k->n_arrays;
+  // per array: bins met by an arc (as a running-sum difference array), or
+  // the whole circle
+  static thread_local std::vector<int32_t> diff;
+  static thread_local std::vector<uint8_t> full, used;
+  diff.assign((size_t)A * (CW_BINS + 1), 0);
+  full.assign(A, 0);
+  used.assign(A, 0);
+  // words per bin, as a shift when the array size is a power of two (the
+  // usual case: no division per access)
+  static thread_local std::vector<uint64_t> bws;
+  static thread_local std::vector<int32_t> bsh;
+  bws.resize(A);
+  bsh.resize(A);
+  for (uint32_t arr = 0; arr < A; arr++) {
     const uint64_t N = k->arrays[arr].words;
-    std::vector<Arc> arcs;
-    bool full = N > (1ull << 31);    // rotated offsets must fit the int32 c
-    for (uint32_t i = 0; i < pl.P && !full; i++) {
-      const DPoint& d = pl.pts[i];
-      if (d.kind != RP_ACCESS || d.array != arr || d.cnt == 0) continue;
-      const uint64_t nblk = d.br < pl.B ? (pl.B - 1 - d.br) / d.bm + 1 : 0;
-      if (nblk == 0) continue;
-      __int128 tlo, thi, blo, bhi;
-      lin_range(d.a, d.r, d.m, d.cnt, tlo, thi);
-      lin_range(d.b, d.br, d.bm, nblk, blo, bhi);
-      const __int128 lo = tlo + blo + d.c, hi = thi + bhi + d.c;
-      if (hi - lo + 1 >= (__int128)N) {
-        full = true;
-        break;
-      }
-      __int128 st = lo % (__int128)N;
-      if (st < 0) st += N;
-      const uint64_t s0 = (uint64_t)st, len = (uint64_t)(hi - lo + 1);
-      if (s0 + len <= N) {
-        arcs.push_back(Arc{s0, len});
-      } else {                        // wraps past the top: two pieces
-        arcs.push_back(Arc{s0, N - s0});
-        arcs.push_back(Arc{0, s0 + len - N});
-      }
+    bws[arr] = (N + CW_BINS - 1) / CW_BINS;
+    const bool p2 = (N & (N - 1)) == 0 && (bws[arr] & (bws[arr] - 1)) == 0;
+    bsh[arr] = p2 ? __builtin_ctzll(bws[arr]) : -1;
+  }
+  for (uint32_t i = 0; i < pl.P; i++) {
+    const DPoint& d = pl.pts[i];
+    if (d.kind != RP_ACCESS || d.cnt == 0) continue;
+    const uint32_t arr = d.array;
+    if (full[arr]) continue;
+    const uint64_t N = k->arrays[arr].words;
+    const uint64_t nblk = d.br < pl.B ? (pl.B - 1 - d.br) / d.bm + 1 : 0;
+    if (nblk == 0) continue;
+    used[arr] = 1;
+    int64_t tlo, thi, blo, bhi, lo, hi;
+    if (N > (1ull << 31) || !lin_range(d.a, d.r, d.m, d.cnt, tlo, thi) ||
+        !lin_range(d.b, d.br, d.bm, nblk, blo, bhi) || __builtin_add_overflow(tlo, blo, &lo) ||
+        __builtin_add_overflow(lo, (int64_t)d.c, &lo) || __builtin_add_overflow(thi, bhi, &hi) ||
+        __builtin_add_overflow(hi, (int64_t)d.c, &hi) || (uint64_t)(hi - lo) + 1 >= N) {
+      full[arr] = 1;   // rotated offsets must fit the int32 c; an arc round the circle
+      continue;
     }
+    const int32_t sh = bsh[arr];
+    int64_t r;
+    if (sh >= 0) {
+      r = lo & (int64_t)(N - 1);
+    } else {
+      r = lo % (int64_t)N;
+      if (r < 0) r += (int64_t)N;
+    }
+    const uint64_t bw = bws[arr];                       // words per bin
+    const uint64_t s0 = (uint64_t)r, e0 = s0 + (uint64_t)(hi - lo);   // last word, may pass N
+    int32_t* df = diff.data() + (size_t)arr * (CW_BINS + 1);
+    auto mark = [&](uint64_t wa, uint64_t wb) {   // words [wa, wb] inside [0, N)
+      df[sh >= 0 ? wa >> sh : wa / bw]++;
+      df[(sh >= 0 ? wb >> sh : wb / bw) + 1]--;
+    };
+    if (e0 < N) {
+      mark(s0, e0);
+    } else {
+      mark(s0, N - 1);
+      mark(0, e0 - N);
+    }
+  }
+  uint64_t span_max = 1;
+  for (uint32_t arr = 0; arr < A; arr++) {
+    const uint64_t N = k->arrays[arr].words;
     uint64_t off = 0, span = N;
-    if (!full && !arcs.empty()) {
-      std::sort(arcs.begin(), arcs.end(), [](const Arc& a, const Arc& b) { return a.s < b.s; });
-      // merged, disjoint arcs inside [0, N) in start order
-      std::vector<Arc> m;
-      for (const Arc& a : arcs) {
-        if (!m.empty() && a.s <= m.back().s + m.back().len) {
-          const uint64_t e = std::max(m.back().s + m.back().len, a.s + a.len);
-          m.back().len = e - m.back().s;
+    if (!used[arr] && !full[arr]) {
+      span = 1;                                    // no access touches this array
+    } else if (!full[arr]) {
+      const uint64_t bw = bws[arr];
+      const uint32_t nb = (uint32_t)((N + bw - 1) / bw);   // bins inside [0, N)
+      const int32_t* df = diff.data() + (size_t)arr * (CW_BINS + 1);
+      // longest circular run of unmarked bins: the runs inside [0, nb), and
+      // the one that wraps (the unmarked tail joined to the unmarked head)
+      static thread_local std::vector<uint8_t> marked;
+      marked.resize(nb);
+      int32_t run = 0;
+      for (uint32_t j = 0; j < nb; j++) {
+        run += df[j];
+        marked[j] = run > 0;
+      }
+      uint32_t head = 0, tail = 0;
+      while (head < nb && !marked[head]) head++;
+      while (tail < nb && !marked[nb - 1 - tail]) tail++;
+      uint32_t best_len = 0, best_end = 0, cur = 0;
+      for (uint32_t j = 0; j < nb; j++) {
+        if (!marked[j]) {
+          if (++cur > best_len) {
+            best_len = cur;
+            best_end = j + 1 == nb ? 0 : j + 1;   // first bin after the run
+          }
         } else {
-          m.push_back(a);
+          cur = 0;
         }
       }
-      // the gap after each merged arc, up to the next one's start (after the
-      // last one it runs round to the first one's start + N)
-      uint64_t best_gap = 0, best_next = 0;
-      for (size_t q = 0; q < m.size(); q++) {
-        const uint64_t end = m[q].s + m[q].len;
-        const uint64_t next = q + 1 < m.size() ? m[q + 1].s : m[0].s + N;
-        const uint64_t gap = next > end ? next - end : 0;
-        if (gap > best_gap) {
-          best_gap = gap;
-          best_next = next % N;
-        }
+      if (head < nb && head + tail > best_len) {   // the wrapping run
+        best_len = head + tail;
+        best_end = head;
       }
-      if (best_gap > 0) {
-        off = (N - best_next) % N;
-        span = N - best_gap;
+      if (head == nb) {
+        span = 1;
+      } else if (best_len > 0) {
+        // words of the gap: bins best_end - best_len .. best_end - 1 (mod nb);
+        // only the last bin of the circle can be narrower than bw
+        const uint64_t last_w = N - (uint64_t)(nb - 1) * bw;
+        const uint32_t first = best_end >= best_len ? best_end - best_len : best_end + nb - best_len;
+        const bool has_last = first + best_len > nb || first + best_len == nb;
+        const uint64_t gap = (uint64_t)(best_len - (has_last ? 1 : 0)) * bw + (has_last ? last_w : 0);
+        const uint64_t next = (uint64_t)best_end * bw;    // first word after the gap
+        off = (N - next % N) % N;
+        span = N - gap;
       }
-    } else if (!full) {
-      span = 1;                       // no access touches this array
     }
     span_max = std::max(span_max, span);
     if (off == 0) continue;
@@ -255,9 +313,11 @@ void make_plan(const rp_kernel* k, Plan& pl) {
       }
       if (a.space == RP_GLOBAL) d.flags |= PF_GLOBAL;
       if ((a.words & (a.words - 1)) == 0) d.flags |= PF_POW2;
+      // a, b multiples of the array size (a mask test for power-of-two sizes)
       const int64_t nw = (int64_t)a.words;
-      if ((int64_t)p.a % nw == 0) d.flags |= PF_TCONST;
-      if ((int64_t)p.b % nw == 0) d.flags |= PF_BCONST;
+      const bool p2 = (a.words & (a.words - 1)) == 0;
+      if (p2 ? (((int64_t)p.a & (nw - 1)) == 0) : ((int64_t)p.a % nw == 0)) d.flags |= PF_TCONST;
+      if (p2 ? (((int64_t)p.b & (nw - 1)) == 0) : ((int64_t)p.b % nw == 0)) d.flags |= PF_BCONST;
       pl.accesses += (uint64_t)d.cnt * nblk;
     }
     if (p.kind == RP_BARRIER) {

@@ -22,6 +22,7 @@ struct Plan {
 
 int validate_kernel(const rp_kernel* k);
 void make_plan(const rp_kernel* k, Plan& pl);
+void compact_words(const rp_kernel* k, Plan& pl);
 int pick_digit_bits(uint32_t key_bits);
 // hipEvent timing level of engine calls (RP_TUNE_TIMING); returns the old one
 int timing_level(int v, bool set);

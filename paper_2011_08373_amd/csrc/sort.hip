@@ -37,11 +37,22 @@ template <int RB>
 using DigT = typename std::conditional<(RB <= 8), uint8_t, uint16_t>::type;
 
 // Per-chunk digit counts of one pass: cnt[chunk][d], from the digit array
-// (digit of record q at dig[q]).  Each thread reads 16-byte vectors (16 or 8
-// digits), the next one issued before the current one is counted; every
+// (digit of record q at dig[q]).  Each thread walks its own contiguous
+// stretch of the chunk (1/256 of it) in 16-byte vectors (16 or 8 digits),
+// CNT_U vectors at a time, the next CNT_U issued before the current ones are
+// counted (so that many loads per lane are in flight while it counts); every
 // digit is one LDS add with no return value (the adds do not stall the
-// wave).  A chunk's first and last vectors may reach past it: those digits
-// are skipped.
+// wave).  Digits of nearby records are often equal or follow a short period,
+// and lanes of one add that hit the same counter (or bank) are served one
+// after another: the lanes' stretches lie far apart, and an odd number of
+// vectors apart, so that a digit pattern with a power-of-two period along the
+// log (records sorted by the digits below this one) puts lanes 16 apart, not
+// all lanes, on one digit; those lanes count into different copies of the
+// histogram (lane / 16 picks the copy, CNT_G copies a bank apart).  A chunk's
+// first and last vectors may reach past it: those digits are skipped.
+constexpr uint32_t CNT_G = 4;
+constexpr int CNT_U = 4;
+
 template <int RB>
 __global__ __launch_bounds__(256) void count_kernel(const DigT<RB>* __restrict__ dig,
                                                     const SortChunk* __restrict__ chunks,
@@ -50,37 +61,58 @@ __global__ __launch_bounds__(256) void count_kernel(const DigT<RB>* __restrict__
   constexpr uint32_t R = 1u << RB;
   using D = DigT<RB>;
   constexpr uint32_t V = 16 / sizeof(D);          // digits per vector
-  __shared__ uint32_t hist[R];
+  constexpr uint32_t HS = R + 1;                 // copy stride: copies of a digit a bank apart
+  __shared__ uint32_t hist[CNT_G * HS];
   const uint32_t tid = threadIdx.x;
+  uint32_t* my = hist + ((tid >> 4) % CNT_G) * HS;
+  const uint4* src = reinterpret_cast<const uint4*>(dig);
   for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {   // persistent
     const SortChunk ch = chunks[ci];
     __syncthreads();
-    for (uint32_t d = tid; d < R; d += 256) hist[d] = 0;
+    for (uint32_t d = tid; d < CNT_G * HS; d += 256) hist[d] = 0;
     __syncthreads();
-    // vectors covering [beg, end), aligned to V digits
+    // vectors covering [beg, end), aligned to V digits; thread tid takes
+    // the tid-th of 256 equal stretches of an odd number of vectors (the
+    // last stretches may be short or empty)
     const uint64_t v0 = ch.beg / V, v1 = (ch.end + V - 1) / V;
-    const uint4* src = reinterpret_cast<const uint4*>(dig);
-    uint64_t v = v0 + tid;
-    uint4 cur = v < v1 ? src[v] : make_uint4(0, 0, 0, 0);
-    while (v < v1) {
-      const uint64_t vn = v + 256;
-      const uint4 nxt = vn < v1 ? src[vn] : make_uint4(0, 0, 0, 0);
-      const D* e = reinterpret_cast<const D*>(&cur);
-      const uint64_t q0 = v * V;
-      if (q0 >= ch.beg && q0 + V <= ch.end) {
+    const uint64_t span = ((v1 - v0 + 255) / 256) | 1u;
+    uint64_t v = v0 + tid * span;
+    const uint64_t ve = v + span < v1 ? v + span : v1;
+    // loads past the stretch read the chunk's last vector (always in
+    // bounds, so no load is conditional) and count nothing
+    const uint64_t vlast = v1 - 1;
+    uint4 cur[CNT_U];
 #pragma unroll
-        for (uint32_t k = 0; k < V; k++) atomicAdd(&hist[e[k]], 1u);
-      } else {
+    for (int u = 0; u < CNT_U; u++) cur[u] = src[v + u < ve ? v + u : vlast];
+    while (v < ve) {
+      const uint64_t vn = v + CNT_U;
+      uint4 nxt[CNT_U];
 #pragma unroll
-        for (uint32_t k = 0; k < V; k++)
-          if (q0 + k >= ch.beg && q0 + k < ch.end) atomicAdd(&hist[e[k]], 1u);
+      for (int u = 0; u < CNT_U; u++) nxt[u] = src[vn + u < ve ? vn + u : vlast];
+      // no branches on the lane: a digit outside the chunk (or in a vector
+      // past the stretch, read as zeros) adds 0
+#pragma unroll
+      for (int u = 0; u < CNT_U; u++) {
+        const D* e = reinterpret_cast<const D*>(&cur[u]);
+        const uint64_t q0 = (v + u) * V;
+        const uint32_t lo = q0 >= ch.beg ? 0u : (uint32_t)min((uint64_t)V, ch.beg - q0);
+        const uint32_t hi = v + u >= ve ? 0u
+                            : (q0 + V <= ch.end ? V : (uint32_t)(ch.end > q0 ? ch.end - q0 : 0));
+#pragma unroll
+        for (uint32_t k = 0; k < V; k++) atomicAdd(&my[e[k]], (k - lo < hi - lo) ? 1u : 0u);
       }
-      cur = nxt;
+#pragma unroll
+      for (int u = 0; u < CNT_U; u++) cur[u] = nxt[u];
       v = vn;
     }
     __syncthreads();
     uint32_t* row = cnt + (size_t)ci * R;
-    for (uint32_t d = tid; d < R; d += 256) row[d] = hist[d];
+    for (uint32_t d = tid; d < R; d += 256) {
+      uint32_t t = 0;
+#pragma unroll
+      for (uint32_t g = 0; g < CNT_G; g++) t += hist[g * HS + d];
+      row[d] = t;
+    }
   }
 }
 
@@ -205,7 +237,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
   constexpr uint32_t R = 1u << RB;
   constexpr int SC_WAVES = SC_BLOCK / 64;
   constexpr uint32_t SC_TILE = SC_BLOCK * SC_IPT;
-  __shared__ uint64_t sk[SC_TILE];
+  __shared__ uint64_t sk[SC_TILE];              // the tile (in digit order after ranking)
   // per-wave digit counters (32-bit for the LDS adds of the ranking below
   // when they fit beside the tile, else 16-bit and updated item by item)
   constexpr bool RANK_ADD = SC_WAVES * R * 4 <= 32768;
@@ -378,20 +410,48 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
       }
     }
     __syncthreads();
-    for (uint32_t p = tid; p < n_here; p += SC_BLOCK) {
-      const uint64_t kv = sk[p];
-      const uint32_t d = digit_at(kv, shift, R - 1);
-      const uint64_t dst = gofs[d] + p;
-      // a destination outside the segment can only come from inconsistent
-      // counts: report it instead of writing
-      if (dst >= sg.beg && dst < sg.end) {
-        out[dst] = kv;
-        // the next pass counts its digits from this array
-        if (dnext) dnext[dst] = (DigT<RB>)digit_at(kv, shift + RB, R - 1);
-      } else {
-        atomicOr(err, ERR_RANGE);
+    // digit runs out to the output (and each record's digit of the next
+    // pass, which the next count pass reads, to dnext).  A destination
+    // outside the segment can only come from inconsistent counts: it is
+    // reported instead of written.  A full tile issues all its LDS reads
+    // before any store.
+    bool bad = false;
+    const uint64_t seg_len = sg.end - sg.beg;
+    if (n_here == SC_TILE) {
+      // four records per thread at a time (registers stay few enough for
+      // the occupancy the LDS allows)
+      static_assert(SC_IPT % 4 == 0, "write-out in groups of four");
+#pragma unroll 1
+      for (int h = 0; h < SC_IPT; h += 4) {
+        uint64_t kv[4], go[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) kv[k] = sk[tid + (h + k) * SC_BLOCK];
+#pragma unroll
+        for (int k = 0; k < 4; k++) go[k] = gofs[digit_at(kv[k], shift, R - 1)];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const uint64_t dst = go[k] + (uint32_t)(tid + (h + k) * SC_BLOCK);
+          if (dst - sg.beg < seg_len) {
+            out[dst] = kv[k];
+            if (dnext) dnext[dst] = (DigT<RB>)digit_at(kv[k], shift + RB, R - 1);
+          } else {
+            bad = true;
+          }
+        }
+      }
+    } else {
+      for (uint32_t p = tid; p < n_here; p += SC_BLOCK) {
+        const uint64_t kv = sk[p];
+        const uint64_t dst = gofs[digit_at(kv, shift, R - 1)] + p;
+        if (dst - sg.beg < seg_len) {
+          out[dst] = kv;
+          if (dnext) dnext[dst] = (DigT<RB>)digit_at(kv, shift + RB, R - 1);
+        } else {
+          bad = true;
+        }
       }
     }
+    if (bad) atomicOr(err, ERR_RANGE);
     // the wave counters are free again: clear them for the next tile
     for (uint32_t q = tid; q < SC_WAVES * R; q += SC_BLOCK) (&whist[0][0])[q] = 0;
     __syncthreads();

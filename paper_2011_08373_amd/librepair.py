@@ -134,6 +134,7 @@ _L.rp_instrument.argtypes = [C.POINTER(RpProgram), C.POINTER(RpInstrumentOpts),
                              _u32p, C.c_void_p, C.c_uint32, _u32p]
 TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE, TUNE_TIMING, TUNE_SCATTER_WGS = 0, 1, 2, 3
 TUNE_SOLVER_NODES = 4
+TUNE_SCAN_PIPELINE = 5
 
 
 def lib():
@@ -351,11 +352,20 @@ class BatchArg:
         self.ptrs = (C.POINTER(RpKernel) * max(1, len(kms)))(
             *[C.pointer(a.k) for a in self.args])
         self.n = len(kms)
+        self._need = {}
+
+    def need(self) -> int:
+        """Workspace bytes of a batched repair of these kernels (cached while
+        the sort tuning, on which the size depends, is unchanged)."""
+        key = _tuning_epoch[0]
+        if key not in self._need:
+            self._need[key] = int(_L.rp_batch_workspace_bytes(self.ptrs, self.n))
+        return self._need[key]
 
 
 def batch_workspace_bytes(kms) -> int:
     b = kms if isinstance(kms, BatchArg) else BatchArg(kms)
-    return int(_L.rp_batch_workspace_bytes(b.ptrs, b.n))
+    return b.need()
 
 
 def repair_batch(kms, policy: int = 0, grid: int = 1, inspect: int = 1, max_rounds: int = 0,
@@ -365,8 +375,7 @@ def repair_batch(kms, policy: int = 0, grid: int = 1, inspect: int = 1, max_roun
     round can be replayed as a captured graph."""
     import torch
     b = kms if isinstance(kms, BatchArg) else BatchArg(kms)
-    need = int(_L.rp_batch_workspace_bytes(b.ptrs, b.n))
-    ptr, size = (ws or _ws).get(need)
+    ptr, size = (ws or _ws).get(b.need())
     o = RpOpts(policy, grid, inspect, solver, max_rounds)
     outs = (RpOut * max(1, b.n))()
     st_obj = stream if stream is not None else _batch_stream()

@@ -3,6 +3,11 @@
   python -m paper_2011_08373_amd.profsum stats RUN_kernel_stats.csv
       Markdown table of the kernel statistics (calls, average, total, share).
 
+  python -m paper_2011_08373_amd.profsum counters RUN_counter_collection.csv RECORDS
+      Markdown table of every counter of a counter-collection run, per
+      kernel: the average per dispatch and per 64 records (RECORDS: the
+      access records one dispatch of the streaming kernels processes).
+
   python -m paper_2011_08373_amd.profsum traffic FETCH.csv WRITE.csv KEY MATCH SOURCE COPY_BYTES
       HBM bytes per launch of the kernel named MATCH, or else the one kernel
       whose name contains it (e.g. "rp::j0_kernel") from two counter-collection runs (one
@@ -52,6 +57,29 @@ def _per_dispatch(path, counter):
     return vals
 
 
+def counters_table(path, records):
+    vals = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        vals[_short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for d in vals.values() for c in d})
+    out = ["| kernel | dispatches | " + " | ".join(names) + " |",
+           "|---|---:|" + "---:|" * len(names)]
+    groups = float(records) / 64.0
+    for k in sorted(vals):
+        d = vals[k]
+        n = max(len(v) for v in d.values())
+        cells = []
+        for c in names:
+            v = d.get(c)
+            if not v:
+                cells.append("")
+                continue
+            avg = sum(v) / len(v)
+            cells.append("%.4g (%.1f / 64 rec)" % (avg, avg / groups))
+        out.append("| %s | %d | %s |" % (k, n, " | ".join(cells)))
+    return "\n".join(out)
+
+
 def traffic(fetch_csv, write_csv, key, match, source, copy_bytes):
     out = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
@@ -89,6 +117,8 @@ def traffic(fetch_csv, write_csv, key, match, source, copy_bytes):
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         print(stats_table(argv[1]))
+    elif len(argv) >= 3 and argv[0] == "counters":
+        print(counters_table(argv[1], float(argv[2])))
     elif len(argv) >= 7 and argv[0] == "traffic":
         print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], argv[5], float(argv[6])),
                          indent=1))

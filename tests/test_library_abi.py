@@ -121,6 +121,13 @@ def test_tuning_knobs(L):
         assert L.set_tuning(L.TUNE_SOLVER_NODES, 28) == 10
     finally:
         L.set_tuning(L.TUNE_SOLVER_NODES, old)
+    old = L.set_tuning(L.TUNE_SCAN_PIPELINE, 1)
+    try:
+        assert old == 0                                          # loads after each range
+        assert L.set_tuning(L.TUNE_SCAN_PIPELINE, 2) == -1
+        assert L.set_tuning(L.TUNE_SCAN_PIPELINE, 0) == 1
+    finally:
+        L.set_tuning(L.TUNE_SCAN_PIPELINE, old)
 
 
 def test_invalid_kernel_does_no_device_work(L):
