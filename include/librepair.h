@@ -361,9 +361,20 @@ uint32_t rp_sort_key_bits(const rp_kernel* const* ks, uint32_t n);
  *   RP_TUNE_SCAN_PIPELINE    first-partner scan: 0 = each wave loads a range
  *                            of records after scanning the one before it
  *                            (default), 1 = the next range's loads are in
- *                            flight while a range is scanned. */
+ *                            flight while a range is scanned;
+ *   RP_TUNE_DIGIT_ORDER      the key digit each radix pass sorts by: 0 = the
+ *                            lowest first, 1 = the highest first (default).
+ *                            Any fixed order keeps every location's records
+ *                            together and in generation order; the order of
+ *                            the locations in the log differs.  Records in
+ *                            generation order share their high digits over
+ *                            long stretches, so the highest-first passes
+ *                            write long runs and the lowest digit (short
+ *                            runs) comes last, when no next-pass digits
+ *                            are stored. */
 enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2,
-       RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4, RP_TUNE_SCAN_PIPELINE = 5 };
+       RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4, RP_TUNE_SCAN_PIPELINE = 5,
+       RP_TUNE_DIGIT_ORDER = 6 };
 int rp_set_tuning(int knob, int value);
 
 /* For callers that cannot allocate device memory (code under stream

@@ -391,6 +391,9 @@ int rp_set_tuning(int knob, int value) {
     case RP_TUNE_SCAN_PIPELINE:
       if (value < 0 || value > 1) return -1;
       return j0_variant(value, true);
+    case RP_TUNE_DIGIT_ORDER:
+      if (value < 0 || value > 1) return -1;
+      return digit_order(value, true);
     default:
       return -1;
   }

@@ -13,8 +13,11 @@
 // The sort key is the top field pair (array, word) at key_shift =
 // tb + bb + pb.  Records are generated in increasing order of their low
 // fields (block-major for the same-block view, point-major for the
-// cross-block view), so a stable LSD radix sort on the key bits leaves the
-// whole log sorted as plain 64-bit integers.  Inside one memory location the
+// cross-block view), so a stable radix sort on the key bits, one digit per
+// pass, leaves the records of each memory location together and in that
+// order (with the lowest digit first the whole log is sorted as plain 64-bit
+// integers; another digit order only changes the order of the locations,
+// which no scan depends on).  Inside one memory location the
 // records are then ordered by point, which is program order: the interval
 // between two enabled barriers is a contiguous run for every assignment, so
 // the log is sorted once per kernel and rescanned per Verify call.

@@ -366,8 +366,13 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
   uint32_t* dcnt = (uint32_t*)(d + L.o_cnt);
   uint64_t* dtot = (uint64_t*)(d + L.o_tot);
   uint64_t* doff = (uint64_t*)(d + L.o_off);
+  // the digit each pass sorts by: lowest first, or highest first (any
+  // fixed order leaves every location's records together and in
+  // generation order, and the scans need nothing more)
+  const bool high_first = digit_order(0, false) != 0;
+  auto digit_of = [&](int p) { return p >= passes ? -1 : (high_first ? passes - 1 - p : p); };
   HIPCHK(launch_gen((int)L.rb, (const GenItem*)(d + L.o_items), nch, djobs,
-                    dss, (uint64_t*)(d + L.o_recA), dcnt, passes > 0 ? 1 : 0, s));
+                    dss, (uint64_t*)(d + L.o_recA), dcnt, digit_of(0), s));
   tm.mark(T_GEN);
   for (int p = 0; p < passes; p++) {
     const uint64_t* in = (const uint64_t*)(d + ((p % 2 == 0) ? L.o_recA : L.o_recB));
@@ -376,8 +381,8 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     HIPCHK(launch_sort_scan((int)L.rb, dig, dss, (uint32_t)L.ssegs.size(), dch, nch, dcnt, dtot,
                             doff, derr + 10, p == 0, s));
     tm.mark(T_SORTPASS);
-    HIPCHK(launch_sort_scatter((int)L.rb, in, out, dss, dch, nch, p, doff, derr + 10, derr,
-                               p + 1 < passes ? dig : nullptr, s));
+    HIPCHK(launch_sort_scatter((int)L.rb, in, out, dss, dch, nch, digit_of(p), digit_of(p + 1),
+                               doff, derr + 10, derr, p + 1 < passes ? dig : nullptr, s));
     tm.mark(T_SORT);
   }
   tm.mark(T_SORT, 2);

@@ -23,11 +23,23 @@ namespace rp {
 constexpr int GEN_BLOCK = 256;
 constexpr uint32_t GEN_CACHE = 256;   // points staged in LDS per item
 
+// Counts the digit of each valid lane's record (the valid lanes are a
+// prefix of the wave): one LDS add for the whole wave when every valid lane
+// has lane 0's digit (the usual case for the key's top digit, which the
+// records of one point and block mostly share; 64 adds to one counter
+// would be served one after another), else one add per record (no return
+// value, so the adds do not stall the wave).
 template <int RB>
 __device__ __forceinline__ void count_digits(uint32_t* hist, uint64_t rec, int shift, bool valid) {
   constexpr uint32_t R = 1u << RB;
-  // one LDS add per record, no return value (the adds do not stall the wave)
-  if (valid) atomicAdd(&hist[digit_at(rec, shift, R - 1)], 1u);
+  const uint32_t d = digit_at(rec, shift, R - 1);
+  const uint64_t act = __builtin_amdgcn_ballot_w64(valid);
+  const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+  if ((__builtin_amdgcn_ballot_w64(d == d0) & act) == act) {
+    if (__lane_id() == 0 && act) atomicAdd(&hist[d0], (uint32_t)__popcll(act));
+  } else if (valid) {
+    atomicAdd(&hist[d], 1u);
+  }
 }
 
 // Wave-uniform copies (the values are the same in every lane; saying so
@@ -60,7 +72,7 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
                                                         const SortSeg* __restrict__ segs,
                                                         uint64_t* __restrict__ recs,
                                                         uint32_t* __restrict__ item_hist,
-                                                        int passes) {
+                                                        int count_digit) {
   constexpr uint32_t R = 1u << RB;
   __shared__ uint32_t hist[R];
   __shared__ DPoint s_pts[GEN_CACHE];        // points i0, i0+1, ... (mod P) of the item
@@ -69,8 +81,8 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
   const GenItem it = items[blockIdx.x];
   const Job& J = jobs[it.job];
   const SortSeg sg = segs[it.seg];
-  const int shift = (int)sg.shift;
-  const int count = passes > 0;
+  const int count = count_digit >= 0;
+  const int shift = (int)sg.shift + (count ? count_digit : 0) * RB;
   const uint32_t tid = threadIdx.x;
   uint64_t* out = recs + sg.beg;
   for (uint32_t q = tid; q < R; q += GEN_BLOCK) hist[q] = 0;
@@ -265,14 +277,14 @@ hipError_t launch_items(const Job* jobs, const SortSeg* segs, uint32_t nseg, uin
 }
 
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,
-                      const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int passes,
+                      const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int count_digit,
                       hipStream_t s) {
   if (n_items == 0) return hipSuccess;
   switch (rb) {
-    case 8: gen_kernel<8><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, passes); break;
-    case 9: gen_kernel<9><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, passes); break;
-    case 10: gen_kernel<10><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, passes); break;
-    case 11: gen_kernel<11><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, passes); break;
+    case 8: gen_kernel<8><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_digit); break;
+    case 9: gen_kernel<9><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_digit); break;
+    case 10: gen_kernel<10><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_digit); break;
+    case 11: gen_kernel<11><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_digit); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -22,6 +22,14 @@ int timing_level(int v, bool set) {
   return old;
 }
 
+static int g_digit_order = 1;         // RP_TUNE_DIGIT_ORDER
+
+int digit_order(int v, bool set) {
+  const int old = g_digit_order;
+  if (set) g_digit_order = v;
+  return old;
+}
+
 static int g_nodes_log2 = 28;         // RP_TUNE_SOLVER_NODES
 
 int solver_nodes_log2(int v, bool set) {

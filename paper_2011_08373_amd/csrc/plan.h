@@ -26,6 +26,9 @@ void compact_words(const rp_kernel* k, Plan& pl);
 int pick_digit_bits(uint32_t key_bits);
 // hipEvent timing level of engine calls (RP_TUNE_TIMING); returns the old one
 int timing_level(int v, bool set);
+// Order of the radix passes' digits (RP_TUNE_DIGIT_ORDER: 0 lowest first,
+// 1 highest first); returns the old setting.
+int digit_order(int v, bool set);
 int sort_passes(uint32_t key_bits, int rb);
 // Node budget of the exact solver's branch and bound (RP_TUNE_SOLVER_NODES,
 // as log2); returns the old log2.

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
                                                            const SortChunk* __restrict__ chunks,
                                                            uint32_t nchunks,
                                                            const SortSeg* __restrict__ segs,
-                                                           int pass,
+                                                           int digit, int ndigit,
                                                            const uint64_t* __restrict__ off,
                                                            uint32_t* __restrict__ ticket,
                                                            uint32_t* err,
@@ -266,7 +266,9 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
   bool first_tile = true;
   SortChunk ch = chunks[ci];
   SortSeg sg = segs[ch.seg];
-  int shift = (int)sg.shift + pass * RB;
+  // this pass's digit, and the next pass's (stored in dnext)
+  int shift = (int)sg.shift + digit * RB;
+  int nshift = (int)sg.shift + ndigit * RB;
   for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] = off[(size_t)ci * R + d];
   uint64_t base = ch.beg;
   // wave w owns records [w*64*IPT, (w+1)*64*IPT) of the tile; item k of
@@ -433,7 +435,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
           const uint64_t dst = go[k] + (uint32_t)(tid + (h + k) * SC_BLOCK);
           if (dst - sg.beg < seg_len) {
             out[dst] = kv[k];
-            if (dnext) dnext[dst] = (DigT<RB>)digit_at(kv[k], shift + RB, R - 1);
+            if (dnext) dnext[dst] = (DigT<RB>)digit_at(kv[k], nshift, R - 1);
           } else {
             bad = true;
           }
@@ -445,7 +447,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
         const uint64_t dst = gofs[digit_at(kv, shift, R - 1)] + p;
         if (dst - sg.beg < seg_len) {
           out[dst] = kv;
-          if (dnext) dnext[dst] = (DigT<RB>)digit_at(kv, shift + RB, R - 1);
+          if (dnext) dnext[dst] = (DigT<RB>)digit_at(kv, nshift, R - 1);
         } else {
           bad = true;
         }
@@ -462,7 +464,8 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
       first_tile = true;
       ch = nch;
       sg = segs[ch.seg];
-      shift = (int)sg.shift + pass * RB;
+      shift = (int)sg.shift + digit * RB;
+      nshift = (int)sg.shift + ndigit * RB;
       for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] = off[(size_t)ci * R + d];
     }
     base = nbase;
@@ -516,7 +519,7 @@ int scatter_wgs(int v, bool set) {
 
 template <int RB, int BLOCK, int IPT, bool NTL = false>
 static void scatter_go(uint32_t nchunks, const uint64_t* in, uint64_t* out,
-                       const SortChunk* chunks, const SortSeg* segs, int pass,
+                       const SortChunk* chunks, const SortSeg* segs, int digit, int ndigit,
                        const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dnext,
                        hipStream_t s) {
   int dev = 0, ncu = 256, per_cu = 0;
@@ -530,52 +533,52 @@ static void scatter_go(uint32_t nchunks, const uint64_t* in, uint64_t* out,
     per_cu = 1;
   uint32_t grid = (uint32_t)ncu * (uint32_t)per_cu;
   if (grid > nchunks) grid = nchunks;
-  scatter_kernel<RB, BLOCK, IPT, NTL><<<grid, BLOCK, 0, s>>>(in, out, chunks, nchunks, segs, pass, off, ticket,
+  scatter_kernel<RB, BLOCK, IPT, NTL><<<grid, BLOCK, 0, s>>>(in, out, chunks, nchunks, segs, digit, ndigit, off, ticket,
                                                               err, (DigT<RB>*)dnext);
 }
 
 template <int RB>
 static void scatter_launch(int variant, uint32_t nchunks, const uint64_t* in, uint64_t* out,
-                           const SortChunk* chunks, const SortSeg* segs, int pass,
+                           const SortChunk* chunks, const SortSeg* segs, int digit, int ndigit,
                            const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dn,
                            hipStream_t s) {
   switch (variant) {
-    case 1: scatter_go<RB, 256, 16>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
-    case 2: scatter_go<RB, 256, 32>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
-    case 4: scatter_go<RB, 512, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
-    case 5: scatter_go<RB, 1024, 4>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
-    case 6: scatter_go<RB, 256, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
+    case 1: scatter_go<RB, 256, 16>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
+    case 2: scatter_go<RB, 256, 32>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
+    case 4: scatter_go<RB, 512, 8>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
+    case 5: scatter_go<RB, 1024, 4>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
+    case 6: scatter_go<RB, 256, 8>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
     case 7:
-      scatter_go<RB, 512, 8, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s);
+      scatter_go<RB, 512, 8, true>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s);
       break;
     case 9:
-      scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s);
+      scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s);
       break;
     case 8:
       if constexpr (RB <= 9)
-        scatter_go<RB, 1024, 8, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s);
+        scatter_go<RB, 1024, 8, true>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s);
       else
-        scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s);
+        scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s);
       break;
     case 3:
       // 16 waves of per-digit counters do not fit LDS beside the tile for
       // wide digits
       if constexpr (RB <= 9) {
-        scatter_go<RB, 1024, 8>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s);
+        scatter_go<RB, 1024, 8>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s);
         break;
       }
       [[fallthrough]];
-    default: scatter_go<RB, 512, 16>(nchunks, in, out, chunks, segs, pass, off, ticket, err, dn, s); break;
+    default: scatter_go<RB, 512, 16>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
   }
 }
 
 hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
-                               const SortChunk* chunks, uint32_t nchunks, int pass,
+                               const SortChunk* chunks, uint32_t nchunks, int digit, int ndigit,
                                const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dnext,
                                hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
   const int v = g_scatter_variant;
-  RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, pass, off, ticket, err,
+  RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err,
                                      dnext, s)));
   return hipGetLastError();
 }

@@ -135,6 +135,7 @@ _L.rp_instrument.argtypes = [C.POINTER(RpProgram), C.POINTER(RpInstrumentOpts),
 TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE, TUNE_TIMING, TUNE_SCATTER_WGS = 0, 1, 2, 3
 TUNE_SOLVER_NODES = 4
 TUNE_SCAN_PIPELINE = 5
+TUNE_DIGIT_ORDER = 6
 
 
 def lib():

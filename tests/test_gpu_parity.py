@@ -225,28 +225,33 @@ def test_plain_large_full_size(L, name, mode):
 def test_sort_knobs_full_size(L):
     # every digit width and scatter tile shape, with the scatter's grid at
     # its resident size and at one workgroup per compute unit (so the
-    # ~1,600 sort chunks of this log are handed out by ticket): the same
-    # races as the oracle's stored result
+    # ~1,600 sort chunks of this log are handed out by ticket), with the
+    # lowest and with the highest key digit sorted first: the same races as
+    # the oracle's stored result
     exp = _expected("plain_large_literal")
     km = synth.generate("plain-large", mode="literal")
     x, c = next(iter(exp["checks"].items()))
     old = (L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 8), L.set_tuning(L.TUNE_SCATTER_SHAPE, 4),
-           L.set_tuning(L.TUNE_SCATTER_WGS, 0))
+           L.set_tuning(L.TUNE_SCATTER_WGS, 0), L.set_tuning(L.TUNE_DIGIT_ORDER, 1))
     try:
-        for bits in (8, 9, 10, 11):
-            for shape in range(10):
-                for wgs in (0, 1):
-                    L.set_tuning(L.TUNE_SORT_DIGIT_BITS, bits)
-                    L.set_tuning(L.TUNE_SCATTER_SHAPE, shape)
-                    L.set_tuning(L.TUNE_SCATTER_WGS, wgs)
-                    g = L.check(km, int(x))
-                    assert g[0] == 0 and g[3] == c["n_records"], (bits, shape, wgs)
-                    assert g[2] == c["divergent"], (bits, shape, wgs)
-                    assert [list(p) for p in g[1]] == c["pairs"], (bits, shape, wgs)
+        for order in (1, 0):
+            for bits in (8, 9, 10, 11):
+                for shape in range(10):
+                    for wgs in (0, 1):
+                        case = (order, bits, shape, wgs)
+                        L.set_tuning(L.TUNE_DIGIT_ORDER, order)
+                        L.set_tuning(L.TUNE_SORT_DIGIT_BITS, bits)
+                        L.set_tuning(L.TUNE_SCATTER_SHAPE, shape)
+                        L.set_tuning(L.TUNE_SCATTER_WGS, wgs)
+                        g = L.check(km, int(x))
+                        assert g[0] == 0 and g[3] == c["n_records"], case
+                        assert g[2] == c["divergent"], case
+                        assert [list(p) for p in g[1]] == c["pairs"], case
     finally:
         L.set_tuning(L.TUNE_SORT_DIGIT_BITS, old[0])
         L.set_tuning(L.TUNE_SCATTER_SHAPE, old[1])
         L.set_tuning(L.TUNE_SCATTER_WGS, old[2])
+        L.set_tuning(L.TUNE_DIGIT_ORDER, old[3])
 
 
 def _many_clause_kernel(seed, n_slots=64):

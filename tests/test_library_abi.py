@@ -128,6 +128,13 @@ def test_tuning_knobs(L):
         assert L.set_tuning(L.TUNE_SCAN_PIPELINE, 0) == 1
     finally:
         L.set_tuning(L.TUNE_SCAN_PIPELINE, old)
+    old = L.set_tuning(L.TUNE_DIGIT_ORDER, 0)
+    try:
+        assert old == 1                                          # highest digit first
+        assert L.set_tuning(L.TUNE_DIGIT_ORDER, 2) == -1
+        assert L.set_tuning(L.TUNE_DIGIT_ORDER, 1) == 0
+    finally:
+        L.set_tuning(L.TUNE_DIGIT_ORDER, old)
 
 
 def test_invalid_kernel_does_no_device_work(L):
