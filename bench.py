@@ -149,11 +149,14 @@ def apply_tuning(L, n_accesses, key_bits):
     best = autotune.lookup(n_accesses, key_bits) if n_accesses else None
     if best:
         autotune.apply(n_accesses, key_bits)
-        return dict(digit_bits=best["digit_bits"], shape=best["shape"], key_bits=key_bits,
-                    autotuned=True)
+        return dict(digit_bits=best["digit_bits"] or "auto",
+                    low_digit_bits=best.get("low_digit_bits", 0), shape=best["shape"],
+                    key_bits=key_bits, autotuned=True)
     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 0)
+    L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 6)
     L.set_tuning(L.TUNE_SCATTER_SHAPE, 4)
-    return dict(digit_bits="auto", shape=4, key_bits=key_bits, autotuned=False)
+    return dict(digit_bits="auto", low_digit_bits=6, shape=4, key_bits=key_bits,
+                autotuned=False)
 
 
 def run_main(L, torch, km, steps, warmup):

@@ -371,10 +371,20 @@ uint32_t rp_sort_key_bits(const rp_kernel* const* ks, uint32_t n);
  *                            long stretches, so the highest-first passes
  *                            write long runs and the lowest digit (short
  *                            runs) comes last, when no next-pass digits
- *                            are stored. */
+ *                            are stored;
+ *   RP_TUNE_LOW_DIGIT_BITS   with the automatic digit width: 6..8 = the
+ *                            lowest digit has that many bits and the rest
+ *                            of the key is split evenly into digits of at
+ *                            most 10 bits (default 6; a tile then writes
+ *                            runs of about 64 records of the lowest digit
+ *                            where consecutive threads touch consecutive
+ *                            words), 0 = digits of one width.  Keys too
+ *                            short for digits of at least 6 bits above it
+ *                            use one width.  The workspace size depends on
+ *                            it. */
 enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2,
        RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4, RP_TUNE_SCAN_PIPELINE = 5,
-       RP_TUNE_DIGIT_ORDER = 6 };
+       RP_TUNE_DIGIT_ORDER = 6, RP_TUNE_LOW_DIGIT_BITS = 7 };
 int rp_set_tuning(int knob, int value);
 
 /* For callers that cannot allocate device memory (code under stream

@@ -1,8 +1,10 @@
-"""Autotuner of the radix sort: digit width and scatter tile shape.
+"""Autotuner of the radix sort: digit widths and scatter tile shape.
 
-For a set of kernels (one size class) it times each (digit bits, tile shape)
+For a set of kernels (one size class) it times each (digits, tile shape)
 pair with the library's own hipEvent timings of record generation and the
-sort passes and keeps the fastest.  Results are cached in tuning.json next to
+sort passes and keeps the fastest.  Digits are either of one width (8..11
+bits) or automatic with a narrow lowest digit (6..8 bits; the rest of the
+key in digits of at most 10 bits).  Results are cached in tuning.json next to
 this file, keyed by the GPU architecture and a size class: log2 of the access
 count and the radix key's width in bits (which sets how many passes each
 digit width needs).  They are applied through rp_set_tuning before a run.
@@ -24,7 +26,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
 _out = [None]                 # where tune() writes (None: CACHE)
-CANDIDATES = [(rb, shape) for rb in (8, 9, 10, 11) for shape in range(10)]
+# (digit bits, lowest digit bits): one width (rb, 0), or automatic widths
+# with a narrow lowest digit (0, low)
+DIGITS = [(0, 6), (0, 7), (0, 8), (8, 0), (9, 0), (10, 0), (11, 0)]
+CANDIDATES = [(dg, shape) for dg in DIGITS for shape in range(10)]
 
 
 def _arch() -> str:
@@ -55,6 +60,7 @@ def apply(n_accesses: int, key_bits: int) -> bool:
     if not best:
         return False
     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, best["digit_bits"])
+    L.set_tuning(L.TUNE_LOW_DIGIT_BITS, best.get("low_digit_bits", 0))
     L.set_tuning(L.TUNE_SCATTER_SHAPE, best["shape"])
     return True
 
@@ -69,8 +75,9 @@ def tune(kms, reps: int = 3, ws=None, candidates=None) -> dict:
         kms = L.KernelArg(kms)
     key_bits = L.sort_key_bits(kms)
     results = []
-    for rb, shape in candidates or CANDIDATES:
+    for (rb, low), shape in candidates or CANDIDATES:
         L.set_tuning(L.TUNE_SORT_DIGIT_BITS, rb)
+        L.set_tuning(L.TUNE_LOW_DIGIT_BITS, low)
         L.set_tuning(L.TUNE_SCATTER_SHAPE, shape)
         times = []
         for _ in range(reps):
@@ -83,20 +90,22 @@ def tune(kms, reps: int = 3, ws=None, candidates=None) -> dict:
             s = L.last_stats()
             times.append(s["ms_sort"] + s["ms_gen"])
         if len(times) == reps:
-            results.append((min(times), rb, shape, L.last_stats()["accesses"]))
+            results.append((min(times), rb, low, shape, L.last_stats()["accesses"]))
     if not results:
         raise RuntimeError("no sort configuration ran")
     results.sort()
-    t, rb, shape, acc = results[0]
+    t, rb, low, shape, acc = results[0]
     dest = _out[0] or CACHE
     data = _load() if dest == CACHE or not os.path.exists(dest) else json.load(open(dest))
-    data.setdefault(_arch(), {})[bucket(acc, key_bits)] = dict(digit_bits=rb, shape=shape, ms=t)
+    data.setdefault(_arch(), {})[bucket(acc, key_bits)] = dict(
+        digit_bits=rb, low_digit_bits=low, shape=shape, ms=t)
     with open(dest, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, rb)
+    L.set_tuning(L.TUNE_LOW_DIGIT_BITS, low)
     L.set_tuning(L.TUNE_SCATTER_SHAPE, shape)
-    return dict(digit_bits=rb, shape=shape, ms=t, key_bits=key_bits,
-                table=[(r[1], r[2], r[0]) for r in results])
+    return dict(digit_bits=rb, low_digit_bits=low, shape=shape, ms=t, key_bits=key_bits,
+                table=[(r[1], r[2], r[3], r[0]) for r in results])
 
 
 WORKLOADS = ("stress-literal", "stress-planted", "plain-large-literal", "plain-large-planted",
@@ -120,10 +129,10 @@ def main(argv):
             kms = synth.generate(cfg, mode=mode)
             reps = 2 if cfg == "stress" else 3
         r = tune(kms, reps=reps, ws=ws)
-        best = sorted(r["table"], key=lambda e: e[2])[:5]
+        best = sorted(r["table"], key=lambda e: e[3])[:5]
         print(json.dumps({"workload": name, "key_bits": r["key_bits"],
-                          "digit_bits": r["digit_bits"], "shape": r["shape"], "ms": r["ms"],
-                          "best5": best}), flush=True)
+                          "digit_bits": r["digit_bits"], "low_digit_bits": r["low_digit_bits"],
+                          "shape": r["shape"], "ms": r["ms"], "best5": best}), flush=True)
         ws.t = None
         torch.cuda.empty_cache()
 

@@ -29,7 +29,8 @@ struct Layout {
   std::vector<size_t> o_ivl, o_minj, o_j0, o_phi, o_scratch, o_traj, o_bitmap, o_pairs, o_ptotal;
   std::vector<uint32_t> phi_cap, scratch_cap;
   uint64_t n_rec = 0;
-  uint32_t rb = 8, passes = 0;
+  uint32_t rb = 8, passes = 0;   // widest digit of the passes (table sizes), passes
+  std::vector<DigitPass> digits;  // the passes' digits in execution order
   uint32_t n_chunks = 0;          // sort chunks = generation items (built on the device)
   uint64_t chunk_len = 0;
   std::vector<SortSeg> ssegs;
@@ -47,8 +48,10 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   // records and sort segments (two logs per job)
   uint32_t key_bits = 0;
   for (const JobInput& j : jobs) key_bits = std::max(key_bits, j.plan->key_bits);
-  L.rb = (uint32_t)pick_digit_bits(key_bits);
-  L.passes = (uint32_t)sort_passes(key_bits, (int)L.rb);
+  L.digits = digit_plan(key_bits);
+  L.passes = (uint32_t)L.digits.size();
+  L.rb = 6;
+  for (const DigitPass& dp : L.digits) L.rb = std::max(L.rb, dp.bits);
   uint64_t rec = 0;
   for (size_t j = 0; j < N; j++) {
     const Plan& p = *jobs[j].plan;
@@ -114,8 +117,11 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   // each record's digit of the next pass, written by a scatter beside its
   // output and counted by the next pass (read as whole 16-byte vectors)
   if (L.passes > 1) {
+    uint32_t wide = 1;            // bytes per stored digit: 2 if any pass after the first has
+    for (uint32_t p = 1; p < L.passes; p++)    // more than 8 bits
+      if (L.digits[p].bits > 8) wide = 2;
     L.o_dig = off;
-    off = up(off + L.n_rec * (L.rb > 8 ? 2 : 1) + 16);
+    off = up(off + L.n_rec * wide + 16);
   }
   L.o_cnt = off; off = up(off + (size_t)L.n_chunks * R * sizeof(uint32_t));
   L.o_tot = off; off = up(off + L.ssegs.size() * (size_t)R * sizeof(uint64_t));
@@ -366,23 +372,25 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
   uint32_t* dcnt = (uint32_t*)(d + L.o_cnt);
   uint64_t* dtot = (uint64_t*)(d + L.o_tot);
   uint64_t* doff = (uint64_t*)(d + L.o_off);
-  // the digit each pass sorts by: lowest first, or highest first (any
-  // fixed order leaves every location's records together and in
-  // generation order, and the scans need nothing more)
-  const bool high_first = digit_order(0, false) != 0;
-  auto digit_of = [&](int p) { return p >= passes ? -1 : (high_first ? passes - 1 - p : p); };
-  HIPCHK(launch_gen((int)L.rb, (const GenItem*)(d + L.o_items), nch, djobs,
-                    dss, (uint64_t*)(d + L.o_recA), dcnt, digit_of(0), s));
+  // each pass's digit (digit_plan: any fixed order of the digits leaves
+  // every location's records together and in generation order, and the
+  // scans need nothing more); generation counts the first pass's digit
+  const std::vector<DigitPass>& dg = L.digits;
+  HIPCHK(launch_gen(passes > 0 ? (int)dg[0].bits : 8, (const GenItem*)(d + L.o_items), nch,
+                    djobs, dss, (uint64_t*)(d + L.o_recA), dcnt,
+                    passes > 0 ? (int)dg[0].lo : -1, s));
   tm.mark(T_GEN);
   for (int p = 0; p < passes; p++) {
     const uint64_t* in = (const uint64_t*)(d + ((p % 2 == 0) ? L.o_recA : L.o_recB));
     uint64_t* out = (uint64_t*)(d + ((p % 2 == 0) ? L.o_recB : L.o_recA));
     void* dig = L.passes > 1 ? (void*)(d + L.o_dig) : nullptr;
-    HIPCHK(launch_sort_scan((int)L.rb, dig, dss, (uint32_t)L.ssegs.size(), dch, nch, dcnt, dtot,
-                            doff, derr + 10, p == 0, s));
+    const bool last = p + 1 == passes;
+    HIPCHK(launch_sort_scan((int)dg[p].bits, dig, dss, (uint32_t)L.ssegs.size(), dch, nch, dcnt,
+                            dtot, doff, derr + 10, p == 0, s));
     tm.mark(T_SORTPASS);
-    HIPCHK(launch_sort_scatter((int)L.rb, in, out, dss, dch, nch, digit_of(p), digit_of(p + 1),
-                               doff, derr + 10, derr, p + 1 < passes ? dig : nullptr, s));
+    HIPCHK(launch_sort_scatter((int)dg[p].bits, in, out, dss, dch, nch, (int)dg[p].lo,
+                               last ? 0 : (int)dg[p + 1].lo, last ? 0 : (int)dg[p + 1].bits,
+                               doff, derr + 10, derr, last ? nullptr : dig, s));
     tm.mark(T_SORT);
   }
   tm.mark(T_SORT, 2);

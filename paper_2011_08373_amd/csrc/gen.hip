@@ -72,7 +72,7 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
                                                         const SortSeg* __restrict__ segs,
                                                         uint64_t* __restrict__ recs,
                                                         uint32_t* __restrict__ item_hist,
-                                                        int count_digit) {
+                                                        int count_lo) {
   constexpr uint32_t R = 1u << RB;
   __shared__ uint32_t hist[R];
   __shared__ DPoint s_pts[GEN_CACHE];        // points i0, i0+1, ... (mod P) of the item
@@ -81,8 +81,8 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
   const GenItem it = items[blockIdx.x];
   const Job& J = jobs[it.job];
   const SortSeg sg = segs[it.seg];
-  const int count = count_digit >= 0;
-  const int shift = (int)sg.shift + (count ? count_digit : 0) * RB;
+  const int count = count_lo >= 0;
+  const int shift = (int)sg.shift + (count ? count_lo : 0);
   const uint32_t tid = threadIdx.x;
   uint64_t* out = recs + sg.beg;
   for (uint32_t q = tid; q < R; q += GEN_BLOCK) hist[q] = 0;
@@ -277,14 +277,16 @@ hipError_t launch_items(const Job* jobs, const SortSeg* segs, uint32_t nseg, uin
 }
 
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,
-                      const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int count_digit,
+                      const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int count_lo,
                       hipStream_t s) {
   if (n_items == 0) return hipSuccess;
   switch (rb) {
-    case 8: gen_kernel<8><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_digit); break;
-    case 9: gen_kernel<9><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_digit); break;
-    case 10: gen_kernel<10><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_digit); break;
-    case 11: gen_kernel<11><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_digit); break;
+    case 6: gen_kernel<6><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_lo); break;
+    case 7: gen_kernel<7><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_lo); break;
+    case 8: gen_kernel<8><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_lo); break;
+    case 9: gen_kernel<9><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_lo); break;
+    case 10: gen_kernel<10><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_lo); break;
+    case 11: gen_kernel<11><<<n_items, GEN_BLOCK, 0, s>>>(items, jobs, segs, recs, item_hist, count_lo); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -8,10 +8,10 @@ namespace rp {
 uint32_t sort_tile_size();
 uint32_t conf_tile_size();
 
-// count_digit: the key digit whose per-chunk counts generation stores in
-// item_hist (the first pass's), -1 for none
+// count_lo: generation stores per-chunk counts of key bits [count_lo,
+// count_lo + rb) (the first pass's digit) in item_hist; -1 for none
 hipError_t launch_gen(int rb, const GenItem* items, uint32_t n_items, const Job* jobs,
-                      const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int count_digit,
+                      const SortSeg* segs, uint64_t* recs, uint32_t* item_hist, int count_lo,
                       hipStream_t s);
 // generation items and sort chunks: chunk c of segment s covers its records
 // [(c - chunk_beg) * chunk_len, ...) up to the segment's end
@@ -24,14 +24,15 @@ hipError_t launch_sort_scan(int rb, const void* dig, const SortSeg* segs, uint32
                             const SortChunk* chunks, uint32_t nchunks, uint32_t* cnt,
                             uint64_t* tot, uint64_t* off, uint32_t* ticket, bool counts_ready,
                             hipStream_t s);
-// digit: the key digit (RB bits from the segment's key shift, 0 lowest)
-// this pass sorts by; ndigit: the next pass's digit, stored per output record
-// in dnext (NULL after the last pass); ticket: one device word, set to zero
-// by launch_sort_scan of the same pass
+// The pass sorts by key bits [lo, lo + rb) above each segment's key shift;
+// the next pass's digit, key bits [nlo, nlo + nbits), is stored per output
+// record in dnext (1 byte for up to 8 bits, else 2; NULL after the last
+// pass); ticket: one device word, set to zero by launch_sort_scan of the
+// same pass
 hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
-                               const SortChunk* chunks, uint32_t nchunks, int digit, int ndigit,
-                               const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dnext,
-                               hipStream_t s);
+                               const SortChunk* chunks, uint32_t nchunks, int lo, int nlo,
+                               int nbits, const uint64_t* off, uint32_t* ticket, uint32_t* err,
+                               void* dnext, hipStream_t s);
 constexpr int IVL_RESOLVE = 0, IVL_CHECK = 1, IVL_ZERO = 2;
 hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int mode, hipStream_t s);
 hipError_t launch_save_j0(const Job* jobs, uint32_t njobs, hipStream_t s);

@@ -374,6 +374,36 @@ int pick_digit_bits(uint32_t key_bits) {
   return (int)std::min<uint32_t>(10, std::max<uint32_t>(8, rb));
 }
 
-int sort_passes(uint32_t key_bits, int rb) { return (int)((key_bits + rb - 1) / rb); }
+static int g_low_digit_bits = 6;      // RP_TUNE_LOW_DIGIT_BITS
+
+int low_digit_bits(int v, bool set) {
+  const int old = g_low_digit_bits;
+  if (set) g_low_digit_bits = v;
+  return old;
+}
+
+std::vector<DigitPass> digit_plan(uint32_t key_bits) {
+  std::vector<DigitPass> v;     // lowest digit first
+  if (key_bits == 0) return v;
+  const uint32_t low = (uint32_t)g_low_digit_bits;
+  // the rest of the key above a narrow lowest digit, in digits of at most
+  // 10 bits but no fewer than 6 (the narrowest digit the kernels take)
+  const uint32_t rest = key_bits > low ? key_bits - low : 0;
+  const uint32_t n = (rest + 9) / 10;
+  if (low != 0 && rest > 0 && rest >= 6 * n && g_digit_bits == 0) {
+    v.push_back(DigitPass{0, low});
+    uint32_t lo = low;
+    for (uint32_t i = 0; i < n; i++) {
+      const uint32_t w = rest / n + (i < rest % n ? 1u : 0u);
+      v.push_back(DigitPass{lo, w});
+      lo += w;
+    }
+  } else {
+    const uint32_t rb = (uint32_t)pick_digit_bits(key_bits);
+    for (uint32_t lo = 0; lo < key_bits; lo += rb) v.push_back(DigitPass{lo, rb});
+  }
+  if (g_digit_order != 0) std::reverse(v.begin(), v.end());
+  return v;
+}
 
 }  // namespace rp

@@ -24,12 +24,24 @@ int validate_kernel(const rp_kernel* k);
 void make_plan(const rp_kernel* k, Plan& pl);
 void compact_words(const rp_kernel* k, Plan& pl);
 int pick_digit_bits(uint32_t key_bits);
+// One radix pass: it sorts by key bits [lo, lo + bits) above the key shift.
+struct DigitPass {
+  uint32_t lo, bits;
+};
+// The radix passes of a key of key_bits bits, in execution order: digits of
+// the automatic or set width (RP_TUNE_SORT_DIGIT_BITS), or with the lowest
+// digit of RP_TUNE_LOW_DIGIT_BITS bits and the rest split evenly into
+// digits of at most 10 bits; highest digit first or lowest first
+// (RP_TUNE_DIGIT_ORDER).
+std::vector<DigitPass> digit_plan(uint32_t key_bits);
+// Width of the lowest digit (RP_TUNE_LOW_DIGIT_BITS, 0 = digits of one
+// width); returns the old setting.
+int low_digit_bits(int v, bool set);
 // hipEvent timing level of engine calls (RP_TUNE_TIMING); returns the old one
 int timing_level(int v, bool set);
 // Order of the radix passes' digits (RP_TUNE_DIGIT_ORDER: 0 lowest first,
 // 1 highest first); returns the old setting.
 int digit_order(int v, bool set);
-int sort_passes(uint32_t key_bits, int rb);
 // Node budget of the exact solver's branch and bound (RP_TUNE_SOLVER_NODES,
 // as log2); returns the old log2.
 int solver_nodes_log2(int v, bool set);

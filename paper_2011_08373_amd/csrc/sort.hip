@@ -229,11 +229,11 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
                                                            const SortChunk* __restrict__ chunks,
                                                            uint32_t nchunks,
                                                            const SortSeg* __restrict__ segs,
-                                                           int digit, int ndigit,
+                                                           int lo, int nlo, int nbits,
                                                            const uint64_t* __restrict__ off,
                                                            uint32_t* __restrict__ ticket,
                                                            uint32_t* err,
-                                                           DigT<RB>* __restrict__ dnext) {
+                                                           void* __restrict__ dnext) {
   constexpr uint32_t R = 1u << RB;
   constexpr int SC_WAVES = SC_BLOCK / 64;
   constexpr uint32_t SC_TILE = SC_BLOCK * SC_IPT;
@@ -266,9 +266,13 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
   bool first_tile = true;
   SortChunk ch = chunks[ci];
   SortSeg sg = segs[ch.seg];
-  // this pass's digit, and the next pass's (stored in dnext)
-  int shift = (int)sg.shift + digit * RB;
-  int nshift = (int)sg.shift + ndigit * RB;
+  // this pass's digit: key bits [lo, lo + RB); the next pass's, stored in
+  // dnext as 1 byte (up to 8 bits) or 2: bits [nlo, nlo + nbits)
+  int shift = (int)sg.shift + lo;
+  int nshift = (int)sg.shift + nlo;
+  const uint32_t nmask = (1u << nbits) - 1u;
+  uint8_t* __restrict__ dn8 = nbits <= 8 ? static_cast<uint8_t*>(dnext) : nullptr;
+  uint16_t* __restrict__ dn16 = nbits > 8 ? static_cast<uint16_t*>(dnext) : nullptr;
   for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] = off[(size_t)ci * R + d];
   uint64_t base = ch.beg;
   // wave w owns records [w*64*IPT, (w+1)*64*IPT) of the tile; item k of
@@ -435,7 +439,8 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
           const uint64_t dst = go[k] + (uint32_t)(tid + (h + k) * SC_BLOCK);
           if (dst - sg.beg < seg_len) {
             out[dst] = kv[k];
-            if (dnext) dnext[dst] = (DigT<RB>)digit_at(kv[k], nshift, R - 1);
+            if (dn8) dn8[dst] = (uint8_t)digit_at(kv[k], nshift, nmask);
+            else if (dn16) dn16[dst] = (uint16_t)digit_at(kv[k], nshift, nmask);
           } else {
             bad = true;
           }
@@ -447,7 +452,8 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
         const uint64_t dst = gofs[digit_at(kv, shift, R - 1)] + p;
         if (dst - sg.beg < seg_len) {
           out[dst] = kv;
-          if (dnext) dnext[dst] = (DigT<RB>)digit_at(kv, nshift, R - 1);
+          if (dn8) dn8[dst] = (uint8_t)digit_at(kv, nshift, nmask);
+          else if (dn16) dn16[dst] = (uint16_t)digit_at(kv, nshift, nmask);
         } else {
           bad = true;
         }
@@ -464,8 +470,8 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
       first_tile = true;
       ch = nch;
       sg = segs[ch.seg];
-      shift = (int)sg.shift + digit * RB;
-      nshift = (int)sg.shift + ndigit * RB;
+      shift = (int)sg.shift + lo;
+      nshift = (int)sg.shift + nlo;
       for (uint32_t d = tid; d < R; d += SC_BLOCK) grun[d] = off[(size_t)ci * R + d];
     }
     base = nbase;
@@ -478,6 +484,8 @@ uint32_t sort_tile_size() { return SC_MAX_TILE; }
 
 #define RB_SWITCH(rb, CALL)                             \
   switch (rb) {                                         \
+    case 6: { constexpr int RBV = 6; CALL; } break;     \
+    case 7: { constexpr int RBV = 7; CALL; } break;     \
     case 8: { constexpr int RBV = 8; CALL; } break;     \
     case 9: { constexpr int RBV = 9; CALL; } break;     \
     case 10: { constexpr int RBV = 10; CALL; } break;   \
@@ -519,7 +527,7 @@ int scatter_wgs(int v, bool set) {
 
 template <int RB, int BLOCK, int IPT, bool NTL = false>
 static void scatter_go(uint32_t nchunks, const uint64_t* in, uint64_t* out,
-                       const SortChunk* chunks, const SortSeg* segs, int digit, int ndigit,
+                       const SortChunk* chunks, const SortSeg* segs, int lo, int nlo, int nbits,
                        const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dnext,
                        hipStream_t s) {
   int dev = 0, ncu = 256, per_cu = 0;
@@ -533,52 +541,52 @@ static void scatter_go(uint32_t nchunks, const uint64_t* in, uint64_t* out,
     per_cu = 1;
   uint32_t grid = (uint32_t)ncu * (uint32_t)per_cu;
   if (grid > nchunks) grid = nchunks;
-  scatter_kernel<RB, BLOCK, IPT, NTL><<<grid, BLOCK, 0, s>>>(in, out, chunks, nchunks, segs, digit, ndigit, off, ticket,
-                                                              err, (DigT<RB>*)dnext);
+  scatter_kernel<RB, BLOCK, IPT, NTL><<<grid, BLOCK, 0, s>>>(in, out, chunks, nchunks, segs, lo, nlo, nbits, off, ticket,
+                                                              err, dnext);
 }
 
 template <int RB>
 static void scatter_launch(int variant, uint32_t nchunks, const uint64_t* in, uint64_t* out,
-                           const SortChunk* chunks, const SortSeg* segs, int digit, int ndigit,
+                           const SortChunk* chunks, const SortSeg* segs, int lo, int nlo, int nbits,
                            const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dn,
                            hipStream_t s) {
   switch (variant) {
-    case 1: scatter_go<RB, 256, 16>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
-    case 2: scatter_go<RB, 256, 32>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
-    case 4: scatter_go<RB, 512, 8>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
-    case 5: scatter_go<RB, 1024, 4>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
-    case 6: scatter_go<RB, 256, 8>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
+    case 1: scatter_go<RB, 256, 16>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s); break;
+    case 2: scatter_go<RB, 256, 32>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s); break;
+    case 4: scatter_go<RB, 512, 8>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s); break;
+    case 5: scatter_go<RB, 1024, 4>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s); break;
+    case 6: scatter_go<RB, 256, 8>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s); break;
     case 7:
-      scatter_go<RB, 512, 8, true>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s);
+      scatter_go<RB, 512, 8, true>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s);
       break;
     case 9:
-      scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s);
+      scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s);
       break;
     case 8:
       if constexpr (RB <= 9)
-        scatter_go<RB, 1024, 8, true>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s);
+        scatter_go<RB, 1024, 8, true>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s);
       else
-        scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s);
+        scatter_go<RB, 512, 16, true>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s);
       break;
     case 3:
       // 16 waves of per-digit counters do not fit LDS beside the tile for
       // wide digits
       if constexpr (RB <= 9) {
-        scatter_go<RB, 1024, 8>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s);
+        scatter_go<RB, 1024, 8>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s);
         break;
       }
       [[fallthrough]];
-    default: scatter_go<RB, 512, 16>(nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err, dn, s); break;
+    default: scatter_go<RB, 512, 16>(nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err, dn, s); break;
   }
 }
 
 hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
-                               const SortChunk* chunks, uint32_t nchunks, int digit, int ndigit,
-                               const uint64_t* off, uint32_t* ticket, uint32_t* err, void* dnext,
-                               hipStream_t s) {
+                               const SortChunk* chunks, uint32_t nchunks, int lo, int nlo,
+                               int nbits, const uint64_t* off, uint32_t* ticket, uint32_t* err,
+                               void* dnext, hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
   const int v = g_scatter_variant;
-  RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, digit, ndigit, off, ticket, err,
+  RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err,
                                      dnext, s)));
   return hipGetLastError();
 }

@@ -136,6 +136,7 @@ TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE, TUNE_TIMING, TUNE_SCATTER_WGS = 0, 1, 
 TUNE_SOLVER_NODES = 4
 TUNE_SCAN_PIPELINE = 5
 TUNE_DIGIT_ORDER = 6
+TUNE_LOW_DIGIT_BITS = 7
 
 
 def lib():
@@ -488,7 +489,8 @@ def sort_key_bits(kms) -> int:
 
 
 def set_tuning(knob: int, value: int) -> int:
-    if knob in (TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE):   # they change workspace sizes
+    if knob in (TUNE_SORT_DIGIT_BITS, TUNE_SCATTER_SHAPE,
+                TUNE_LOW_DIGIT_BITS):   # they change workspace sizes
         _tuning_epoch[0] += 1
     return _L.rp_set_tuning(int(knob), int(value))
 

@@ -223,24 +223,27 @@ def test_plain_large_full_size(L, name, mode):
 
 
 def test_sort_knobs_full_size(L):
-    # every digit width and scatter tile shape, with the scatter's grid at
-    # its resident size and at one workgroup per compute unit (so the
-    # ~1,600 sort chunks of this log are handed out by ticket), with the
-    # lowest and with the highest key digit sorted first: the same races as
-    # the oracle's stored result
+    # every digit plan (one width of 8..11 bits, or a 6..8-bit lowest digit
+    # with the rest in digits of 6 and 7 bits: 19 key bits) and scatter tile
+    # shape, with the scatter's grid at its resident size and at one
+    # workgroup per compute unit (so the ~1,600 sort chunks of this log are
+    # handed out by ticket), with the highest and with the lowest key digit
+    # sorted first: the same races as the oracle's stored result
     exp = _expected("plain_large_literal")
     km = synth.generate("plain-large", mode="literal")
     x, c = next(iter(exp["checks"].items()))
-    old = (L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 8), L.set_tuning(L.TUNE_SCATTER_SHAPE, 4),
-           L.set_tuning(L.TUNE_SCATTER_WGS, 0), L.set_tuning(L.TUNE_DIGIT_ORDER, 1))
+    old = (L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 0), L.set_tuning(L.TUNE_SCATTER_SHAPE, 4),
+           L.set_tuning(L.TUNE_SCATTER_WGS, 0), L.set_tuning(L.TUNE_DIGIT_ORDER, 1),
+           L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 6))
     try:
         for order in (1, 0):
-            for bits in (8, 9, 10, 11):
+            for bits, low in ((0, 6), (0, 7), (0, 8), (8, 0), (9, 0), (10, 0), (11, 0)):
                 for shape in range(10):
                     for wgs in (0, 1):
-                        case = (order, bits, shape, wgs)
+                        case = (order, bits, low, shape, wgs)
                         L.set_tuning(L.TUNE_DIGIT_ORDER, order)
                         L.set_tuning(L.TUNE_SORT_DIGIT_BITS, bits)
+                        L.set_tuning(L.TUNE_LOW_DIGIT_BITS, low)
                         L.set_tuning(L.TUNE_SCATTER_SHAPE, shape)
                         L.set_tuning(L.TUNE_SCATTER_WGS, wgs)
                         g = L.check(km, int(x))
@@ -252,6 +255,7 @@ def test_sort_knobs_full_size(L):
         L.set_tuning(L.TUNE_SCATTER_SHAPE, old[1])
         L.set_tuning(L.TUNE_SCATTER_WGS, old[2])
         L.set_tuning(L.TUNE_DIGIT_ORDER, old[3])
+        L.set_tuning(L.TUNE_LOW_DIGIT_BITS, old[4])
 
 
 def _many_clause_kernel(seed, n_slots=64):

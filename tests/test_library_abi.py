@@ -135,6 +135,14 @@ def test_tuning_knobs(L):
         assert L.set_tuning(L.TUNE_DIGIT_ORDER, 1) == 0
     finally:
         L.set_tuning(L.TUNE_DIGIT_ORDER, old)
+    old = L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 0)
+    try:
+        assert old == 6                                          # a 6-bit lowest digit
+        for bad in (5, 9, -1):
+            assert L.set_tuning(L.TUNE_LOW_DIGIT_BITS, bad) == -1
+        assert L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 8) == 0
+    finally:
+        L.set_tuning(L.TUNE_LOW_DIGIT_BITS, old)
 
 
 def test_invalid_kernel_does_no_device_work(L):
