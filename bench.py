@@ -472,6 +472,9 @@ def main():
     ap.add_argument("--digit-order", type=int, default=None, choices=(0, 1),
                     help="radix digit order: 0 lowest first, 1 highest first "
                          "(default: the library's)")
+    ap.add_argument("--scan-pipeline", type=int, default=None, choices=(0, 1),
+                    help="first-partner scan: 1 issues the next range's loads before "
+                         "the current range is scanned (default: the library's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -483,6 +486,8 @@ def main():
     torch.cuda.set_device(0)
     if args.digit_order is not None:
         L.set_tuning(L.TUNE_DIGIT_ORDER, args.digit_order)
+    if args.scan_pipeline is not None:
+        L.set_tuning(L.TUNE_SCAN_PIPELINE, args.scan_pipeline)
     legs = set(args.legs.split(","))
     if args.calib:
         a = torch.empty(64 << 20, dtype=torch.int64, device="cuda")

@@ -9,8 +9,9 @@
       access records one dispatch of the streaming kernels processes).
 
   python -m paper_2011_08373_amd.profsum traffic FETCH.csv WRITE.csv KEY MATCH SOURCE COPY_BYTES
-      HBM bytes per launch of the kernel named MATCH, or else the one kernel
-      whose name contains it (e.g. "rp::j0_kernel") from two counter-collection runs (one
+      HBM bytes per launch of the kernel named MATCH, or else of the kernels
+      whose names contain it (e.g. "rp::j0_kernel"; several instantiations
+      are averaged over all their dispatches) from two counter-collection runs (one
       with FETCH_SIZE, one with WRITE_SIZE; the counters read KiB per
       dispatch).  Each counter is scaled by what it reads for the largest
       plain device copy of COPY_BYTES bytes in the same run (bench.py
@@ -92,15 +93,16 @@ def traffic(fetch_csv, write_csv, key, match, source, copy_bytes):
         names = [k for k in v if k == match] or [k for k in v if match in k]
         if not names:
             raise SystemExit("kernel %s not in %s" % (match, path))
-        if len(names) > 1:
-            raise SystemExit("%s names several kernels: %s" % (match, ", ".join(sorted(names))))
-        xs = v[names[0]]
+        # several kernels (the instantiations of one kernel for different
+        # digit widths): the average over all their dispatches, as bench.py
+        # averages its launch times over all of them
+        xs = [x for k in sorted(names) for x in v[k]]
         out[counter] = {"kib_per_dispatch": sum(xs) / len(xs), "dispatches": len(xs),
                         "copy_factor": factor,
                         "bytes_per_launch": sum(xs) / len(xs) * 1024.0 * factor}
     with open(os.path.join(ROOT, source), "rb") as fh:
         sha = hashlib.sha256(fh.read()).hexdigest()
-    entry = {"source": source, "sha256": sha, "match": match,
+    entry = {"source": source, "sha256": sha, "match": match, "kernels": sorted(names),
              "fetch_bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"],
              "write_bytes_per_launch": out["WRITE_SIZE"]["bytes_per_launch"],
              "bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"] +
