@@ -359,9 +359,9 @@ uint32_t rp_sort_key_bits(const rp_kernel* const* ks, uint32_t n);
  *                            searches it (4..40, default 28).  A job whose
  *                            search spends it ends with RP_ERR_SEARCH;
  *   RP_TUNE_SCAN_PIPELINE    first-partner scan: 0 = each wave loads a range
- *                            of records after scanning the one before it
- *                            (default), 1 = the next range's loads are in
- *                            flight while a range is scanned;
+ *                            of records after scanning the one before it,
+ *                            1 = the next range's loads are in flight while
+ *                            a range is scanned (default);
  *   RP_TUNE_DIGIT_ORDER      the key digit each radix pass sorts by: 0 = the
  *                            lowest first, 1 = the highest first (default).
  *                            Any fixed order keeps every location's records
@@ -381,10 +381,16 @@ uint32_t rp_sort_key_bits(const rp_kernel* const* ks, uint32_t n);
  *                            words), 0 = digits of one width.  Keys too
  *                            short for digits of at least 6 bits above it
  *                            use one width.  The workspace size depends on
- *                            it. */
+ *                            it;
+ *   RP_TUNE_SCAN_FIELDS      first-partner scan: 0 = where the thread, block
+ *                            and point bits of every job of the call fit in
+ *                            32 bits, the point and id fields are taken from
+ *                            the low 32 bits of each record with 32-bit
+ *                            instructions (default), 1 = always from the
+ *                            whole 64-bit record. */
 enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2,
        RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4, RP_TUNE_SCAN_PIPELINE = 5,
-       RP_TUNE_DIGIT_ORDER = 6, RP_TUNE_LOW_DIGIT_BITS = 7 };
+       RP_TUNE_DIGIT_ORDER = 6, RP_TUNE_LOW_DIGIT_BITS = 7, RP_TUNE_SCAN_FIELDS = 8 };
 int rp_set_tuning(int knob, int value);
 
 /* For callers that cannot allocate device memory (code under stream

@@ -17,6 +17,7 @@ extern int g_digit_bits_ref(int v, bool set);
 int scatter_variant(int v, bool set);
 int scatter_wgs(int v, bool set);
 int j0_variant(int v, bool set);
+int j0_fields_variant(int v, bool set);
 
 // The option units of the switches of Section 4.2 (Tab. 3): with grid-level
 // barriers disabled every grid slot stays off; with inspection disabled every
@@ -397,6 +398,9 @@ int rp_set_tuning(int knob, int value) {
     case RP_TUNE_LOW_DIGIT_BITS:
       if (value != 0 && (value < 6 || value > 8)) return -1;
       return low_digit_bits(value, true);
+    case RP_TUNE_SCAN_FIELDS:
+      if (value < 0 || value > 1) return -1;
+      return j0_fields_variant(value, true);
     default:
       return -1;
   }

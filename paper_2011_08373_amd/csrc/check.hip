@@ -438,9 +438,27 @@ __device__ __forceinline__ uint32_t low_bit64(uint64_t m) {   // 64 if m == 0
 __device__ __forceinline__ uint64_t above(uint32_t k) {       // bits k+1..63 (none for k >= 63)
   return k >= 63 ? 0ull : (~0ull << (k + 1));
 }
+// Lowest set bit of a wave-uniform mask, 0xffffffff when it is empty (the
+// scalar find-first-one gives exactly that, with no test of its own).
+__device__ __forceinline__ uint32_t first_one(uint64_t m) {
+  uint32_t r;
+  asm("s_ff1_i32_b64 %0, %1" : "=s"(r) : "s"(m));
+  return r;
+}
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+// This lane's bit of the wave mask m (the mask itself serves as the lane
+// condition of a select, with no per-lane test).
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+// A wave-uniform value held in a vector register, so that an instruction can
+// take it beside a scalar operand (an instruction reads one scalar register).
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t v) {
+  uint32_t r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+  return r;
+}
 // Lanes below the lowest set lane of m (all lanes when m is empty).
 __device__ __forceinline__ uint64_t below_first(uint64_t m) { return (m & (0ull - m)) - 1ull; }
+
 
 // The record one lane down (lane 0 gets `first`, the record before the chunk).
 __device__ __forceinline__ uint64_t lane_before(uint64_t v, uint64_t first) {
@@ -452,17 +470,34 @@ __device__ __forceinline__ uint64_t lane_before(uint64_t v, uint64_t first) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// The record one lane down, where lane 0 gets lane 63 of `last` (the chunk
+// before): a wave rotate of `last` puts its lane 63 into lane 0, and the wave
+// shift of v leaves that lane as it is.
+__device__ __forceinline__ uint64_t lane_before_chunk(uint64_t v, uint64_t last) {
+  const int rl = __builtin_amdgcn_mov_dpp((int)(uint32_t)last, 0x13C, 0xF, 0xF, false);
+  const int rh = __builtin_amdgcn_mov_dpp((int)(uint32_t)(last >> 32), 0x13C, 0xF, 0xF, false);
+  const uint32_t lo =
+      (uint32_t)__builtin_amdgcn_update_dpp(rl, (int)(uint32_t)v, 0x138, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(rh, (int)(uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Value of v in lane l mod 64 (ds_bpermute takes the source lane from the
 // byte address divided by four, modulo the wave size).
 __device__ __forceinline__ uint32_t from_lane(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(l << 2), (int)v);
 }
 
-// Fields of the records of one log.
+// Fields of the records of one log.  With LO32 (the point and id fields lie
+// in the low 32 bits of every record of the launch) a field is one bit-field
+// extract of the low word, and the id test one 32-bit compare.
 struct J0Fields {
   int psh, ish;            // point and id field shifts (< 64)
   uint32_t pmask, imask;   // point and id field masks
+  uint32_t pw, iw;         // point and id field widths
   uint64_t locm, idm;      // location bits, id bits of a record
+  uint64_t lmax;           // a record pair differs in its location iff their xor > lmax
 };
 
 __device__ __forceinline__ J0Fields j0_fields(const Job& J, const ConfSeg& sg) {
@@ -477,8 +512,11 @@ __device__ __forceinline__ J0Fields j0_fields(const Job& J, const ConfSeg& sg) {
   f.pmask = psh < 64 ? (1u << J.pbits) - 1u : 0u;
   f.ish = ish < 64 ? ish : 0;
   f.imask = ish < 64 ? (uint32_t)imask : 0u;
+  f.pw = psh < 64 ? J.pbits : 0u;
+  f.iw = ish < 64 ? (sg.level == 0 ? J.tbits : J.bbits) : 0u;
   f.locm = lsh < 64 ? ~0ull << lsh : 0ull;
   f.idm = ish < 64 ? imask << ish : 0ull;
+  f.lmax = lsh < 64 ? (1ull << lsh) - 1ull : ~0ull;
   return f;
 }
 
@@ -495,18 +533,26 @@ struct J0Chunk {
   bool W, L, valid;        // this lane: a write, a location start, a record
 };
 
-template <bool FULL>
+template <bool FULL, bool LO32>
 __device__ __forceinline__ J0Chunk j0_decode(const J0Fields& f, const uint8_t* s_w, uint64_t rec,
                                              uint64_t prev, bool valid) {
   J0Chunk c;
   const uint64_t df = rec ^ prev;
-  c.pt = (uint32_t)(rec >> f.psh) & f.pmask;
-  c.id = (uint32_t)(rec >> f.ish) & f.imask;
+  bool idc;
+  if constexpr (LO32) {
+    c.pt = __builtin_amdgcn_ubfe((uint32_t)rec, (uint32_t)f.psh, f.pw);
+    c.id = __builtin_amdgcn_ubfe((uint32_t)rec, (uint32_t)f.ish, f.iw);
+    idc = ((uint32_t)df & (uint32_t)f.idm) != 0;
+  } else {
+    c.pt = (uint32_t)(rec >> f.psh) & f.pmask;
+    c.id = (uint32_t)(rec >> f.ish) & f.imask;
+    idc = (df & f.idm) != 0;
+  }
   c.W = s_w[c.pt] != 0;
   c.valid = FULL || valid;
-  c.L = (df & f.locm) != 0 || !c.valid;
+  c.L = df > f.lmax || !c.valid;
   c.Lm = ballot64(c.L);
-  c.Xm = c.Lm | ballot64((df & f.idm) != 0);
+  c.Xm = c.Lm | ballot64(idc);
   c.Wm = ballot64(c.W && c.valid);
   return c;
 }
@@ -520,42 +566,38 @@ struct J0Carry {
 };
 
 // The carries at the start of a chunk from the chunk and the carries at its
-// end (fields read into locals first, so that they stay in registers).
+// end, as scalar selects with no branch: every lane index below is taken mod
+// 64, so the reads of an empty mask's "first" lane are harmless and their
+// results are not selected.
 __device__ __forceinline__ void j0_carry_update(J0Carry& cr, const J0Chunk& c) {
-  uint32_t x = cr.x, fw = cr.fw, fw_id = cr.fw_id, ws = cr.ws;
-  if (c.Xm) {
-    const uint32_t x0 = low_bit64(c.Xm);
-    const uint32_t px = __builtin_amdgcn_readlane(c.pt, x0);
-    x = ((c.Lm >> x0) & 1) ? NONE32 : px;
-  }
+  // the first streak start: its partner point, none at a location start
+  const uint32_t x0 = first_one(c.Xm) & 63u;
+  const uint32_t px = __builtin_amdgcn_readlane(c.pt, x0);
+  const uint32_t x = c.Xm == 0 ? cr.x : (((c.Lm >> x0) & 1) ? NONE32 : px);
+  // the first write or location start
   const uint64_t wl = c.Wm | c.Lm;
-  if (wl) {
-    const uint32_t b = low_bit64(wl);
-    if ((c.Lm >> b) & 1) {
-      fw = NONE32;
-      ws = NONE32;
-    } else {
-      const uint32_t fid = __builtin_amdgcn_readlane(c.id, b);
-      const uint32_t fpt = __builtin_amdgcn_readlane(c.pt, b);
-      const uint64_t after = above(b);
-      // (a ballot of a plain compare is the compare's own mask; a ballot of
-      // a conjunction would be rebuilt lane by lane)
-      const uint64_t hm = ballot64(c.id != fid) & c.Wm & after;
-      const uint64_t lm = c.Lm & after;
-      const uint64_t hml = hm & below_first(lm);               // before the location ends
-      uint32_t nws;
-      if (hml) nws = __builtin_amdgcn_readlane(c.pt, low_bit64(hml));
-      else if (lm) nws = NONE32;
-      else nws = (fw != NONE32 && fw_id != fid) ? fw : ws;
-      fw = fpt;
-      fw_id = fid;
-      ws = nws;
-    }
-  }
+  const uint32_t b = first_one(wl) & 63u;
+  const uint32_t fid = __builtin_amdgcn_readlane(c.id, b);
+  const uint32_t fpt = __builtin_amdgcn_readlane(c.pt, b);
+  const uint64_t after = ~1ull << b;                         // lanes above b
+  // (a ballot of a plain compare is the compare's own mask)
+  const uint64_t hm = ballot64(c.id != fid) & c.Wm & after;
+  const uint64_t lm = c.Lm & after;
+  // the write's write-streak end: the first later write with another id
+  // before the location ends, else none if the location ends in the chunk,
+  // else what lies past the chunk
+  const uint32_t h = first_one(hm), l = first_one(lm);       // 0xffffffff: none
+  const uint32_t ph = __builtin_amdgcn_readlane(c.pt, h & 63u);
+  // (with no write ahead, fw and ws are both NONE32, so either is right)
+  const uint32_t past = cr.fw_id != fid ? cr.fw : cr.ws;
+  const uint32_t nws = h < l ? ph : (l != NONE32 ? NONE32 : past);
+  const bool loc = (c.Lm >> b) & 1;                          // a location start first
   cr.x = x;
-  cr.fw = fw;
-  cr.fw_id = fw_id;
-  cr.ws = ws;
+  if (wl != 0) {
+    cr.fw = loc ? NONE32 : fpt;
+    cr.fw_id = loc ? cr.fw_id : fid;
+    cr.ws = loc ? NONE32 : nws;
+  }
 }
 
 // Carries at position s (a multiple of 64 from the log start, or n) from
@@ -563,6 +605,7 @@ __device__ __forceinline__ void j0_carry_update(J0Carry& cr, const J0Chunk& c) {
 // first streak start, the first write or location start and that write's
 // write-streak end are known.  It stops at the end of the location it
 // starts in (or of the log).
+template <bool LO32>
 __device__ J0Carry j0_carry_at(gptr<uint64_t> log, uint64_t n, uint64_t s,
                                const J0Fields& f, const uint8_t* s_w) {
   J0Carry cr{NONE32, NONE32, 0, NONE32};
@@ -575,7 +618,7 @@ __device__ J0Carry j0_carry_at(gptr<uint64_t> log, uint64_t n, uint64_t s,
     const uint64_t rec = q < n ? log[q] : 0;
     const uint64_t prev = lane_before(rec, prev_last);
     prev_last = __shfl(rec, 63);
-    const J0Chunk c = j0_decode<false>(f, s_w, rec, prev, q < n);
+    const J0Chunk c = j0_decode<false, LO32>(f, s_w, rec, prev, q < n);
     if (!have_x && c.Xm) {
       const uint32_t x0 = low_bit64(c.Xm);
       cr.x = ((c.Lm >> x0) & 1) ? NONE32 : __builtin_amdgcn_readlane(c.pt, x0);
@@ -618,9 +661,10 @@ constexpr int J0_CHUNKS = 8;
 // moved to the range start.  rev[j]: this lane's record of chunk
 // J0_CHUNKS - 1 - j (the order of the scan, which is also the order of the
 // loads: the compiler issues the loads of an array in index order); before:
-// the record before the range (any value at the log start).  FULL: every
-// chunk of the range lies inside the log.
-template <bool FULL>
+// the record before the range (any value at the log start).  FULL: the
+// range has all J0_CHUNKS chunks, every one inside the log (no per-chunk or
+// per-lane end test).
+template <bool FULL, bool LO32>
 __device__ __forceinline__ void j0_range(const J0Fields& F, const uint8_t* s_w, uint32_t* s_minj,
                                          uint32_t P, const uint64_t (&rev)[J0_CHUNKS],
                                          uint64_t before, uint64_t wbeg, int nch, uint64_t n,
@@ -630,37 +674,40 @@ __device__ __forceinline__ void j0_range(const J0Fields& F, const uint8_t* s_w, 
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));   // lanes below
 #pragma unroll
   for (int k = J0_CHUNKS - 1; k >= 0; k--) {
-    if (k >= nch) continue;
+    if (!FULL && k >= nch) continue;
     const uint64_t base = wbeg + (uint64_t)k * 64;
-    // readlane yields an int: each half is widened unsigned, or a set bit 31
-    // of the low half would spill into the high one
     const uint64_t rk = rev[J0_CHUNKS - 1 - k];
-    const uint64_t rp = k > 0 ? rev[J0_CHUNKS - k] : 0;                  // chunk k - 1
-    const uint64_t first =
-        k > 0 ? (((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(rp >> 32), 63) << 32) |
-                 (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)rp, 63))
-              : before;
-    const J0Chunk c = j0_decode<FULL>(F, s_w, rk, lane_before(rk, first), FULL || base + lane < n);
+    const uint64_t prev = k > 0 ? lane_before_chunk(rk, rev[J0_CHUNKS - k])   // chunk k - 1
+                                : lane_before(rk, before);
+    const J0Chunk c = j0_decode<FULL, LO32>(F, s_w, rk, prev, FULL || base + lane < n);
     // first candidate: for a write the first streak start after it, for
     // a read the first write or location start after it; in the chunk it is
     // read from its lane as a partner value (the point, or none where a
     // location starts), past the chunk it is the carried one.  The lane's
-    // mask is picked without a select of 64-bit values: WL ^ ((Xm ^ WL) & W).
-    const uint64_t WL = c.Wm | c.Lm, E = c.Xm ^ WL;
-    const uint32_t sw = c.W ? ~0u : 0u;
-    const uint32_t mlo = (((uint32_t)E & sw) ^ (uint32_t)WL) & (uint32_t)gt;
-    const uint32_t mhi = (((uint32_t)(E >> 32) & sw) ^ (uint32_t)(WL >> 32)) & (uint32_t)(gt >> 32);
+    // mask, Xm for a write and WL = Wm | Lm for a read, taken above the lane,
+    // is a bit-field insert of Xm into WL & gt under gt of the writes (one
+    // scalar operand per instruction).  Which lanes find a candidate in the
+    // chunk (those below the highest bit of their mask) and the rest of the
+    // lane logic are wave masks, so that each per-lane select takes its
+    // mask from scalar registers.
+    const uint64_t WL = c.Wm | c.Lm;
+    const uint32_t gwl = c.W ? (uint32_t)gt : 0u, gwh = c.W ? (uint32_t)(gt >> 32) : 0u;
+    const uint32_t tlo = (uint32_t)WL & (uint32_t)gt, thi = (uint32_t)(WL >> 32) & (uint32_t)(gt >> 32);
+    const uint32_t mlo = (gwl & (uint32_t)c.Xm) | (~gwl & tlo);
+    const uint32_t mhi = (gwh & (uint32_t)(c.Xm >> 32)) | (~gwh & thi);
     const uint32_t c1 = low_bit64(((uint64_t)mhi << 32) | mlo);
     const bool in1 = c1 < 64;
-    const uint32_t pv = c.L ? NONE32 : c.pt;
+    const uint64_t in1m = ballot64(in1);
+    const uint32_t pv = lane_in(c.Lm) ? NONE32 : c.pt;
     const uint32_t pv1 = from_lane(pv, c1), id1 = from_lane(c.id, c1);
     const uint32_t cfw = cr.fw, cfw_id = cr.fw_id, cws = cr.ws;
-    const uint32_t past = (cr.x & sw) | (cfw & ~sw);                // x for a write, fw for a read
+    const uint32_t past = c.W ? cr.x : cfw;                         // x for a write, fw for a read
     const uint32_t cand = in1 ? pv1 : past;
-    const uint32_t idc = in1 ? id1 : cfw_id;
     // a read whose first write has its own id: the partner is the end of
     // that write's write streak (carried when the write lies past the chunk)
-    const bool second = !c.W && cand != NONE32 && idc == c.id;
+    const uint64_t eqm = (in1m & ballot64(id1 == c.id)) | (~in1m & ballot64(cfw_id == c.id));
+    const uint64_t secm = ~c.Wm & ballot64(cand != NONE32) & eqm;
+    const bool second = lane_in(secm);
     uint32_t best = second ? cws : cand;
     // Reads whose first write f lies in the chunk with the read's own id:
     // the partner is the first write after f with another id before the
@@ -670,26 +717,29 @@ __device__ __forceinline__ void j0_range(const J0Fields& F, const uint8_t* s_w, 
     // after f, else it lies past the chunk: the carried first write if its
     // id differs, else the end of that write's write streak.  Only chunks
     // where some read needs it take this step.
-    const uint64_t need =
-        ~c.Wm & ballot64(cand != NONE32) & ballot64(idc == c.id) & ballot64(in1) &
-        (FULL ? ~0ull : ballot64(c.valid));
+    const uint64_t need = secm & in1m & (FULL ? ~0ull : ballot64(c.valid));
     if (need) {
-      const uint64_t pm = c.Wm & lt;                          // writes below this lane
-      const uint32_t pw = pm ? 63u - (uint32_t)__builtin_clzll(pm) : 0u;
+      // the nearest write below this lane (any lane where there is none:
+      // those lanes are not above the chunk's first write, and WSm drops them)
+      const uint64_t pm = c.Wm & lt;
+      const uint32_t pw = 63u - (uint32_t)__builtin_clzg(pm, 64);
       const uint32_t idpw = from_lane(c.id, pw);
-      // (lanes above the chunk's first write have a write below them)
-      const uint64_t WSm = ballot64(idpw != c.id) & c.Wm & above(low_bit64(c.Wm));
-      const uint32_t k2 = low_bit64((WSm | c.Lm) & above(c1));   // c1 < 64 where needed
+      // (the chunk has a write here: some read's first write lies in it)
+      const uint64_t WSm = ballot64(idpw != c.id) & c.Wm & (~1ull << (first_one(c.Wm) & 63u));
+      // lanes above c1 (c1 < 64 where needed; bit 63 shifts out at c1 = 63)
+      const uint32_t k2 = low_bit64((WSm | c.Lm) & (~1ull << c1));
       const uint32_t pv2 = from_lane(pv, k2);
-      if (second && in1)
-        best = k2 < 64 ? pv2 : ((cfw != NONE32 && cfw_id != id1) ? cfw : cws);
+      if (lane_in(need))
+        best = k2 < 64 ? pv2 : (cfw_id != id1 ? cfw : cws);   // (no write ahead: both NONE32)
     }
-    if (c.valid && best < P) atomicMin(&s_minj[c.pt], best);
+    // every lane takes part (NONE32 leaves the minimum as it is), so the
+    // add needs no lane mask
+    atomicMin(&s_minj[c.pt], FULL || c.valid ? best : NONE32);
     j0_carry_update(cr, c);
   }
 }
 
-template <bool PIPE>
+template <bool PIPE, bool LO32>
 __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ jobs,
                                                         const ConfSeg* __restrict__ segs, int nseg,
                                                         const uint32_t* __restrict__ total_at) {
@@ -740,7 +790,11 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
     const ConfSeg& sg = segs[cur];
     const uint64_t n = sg.n;
     const gptr<uint64_t> log = as_global(sg.log);
-    const J0Fields F = j0_fields(jobs[sg.job], sg);
+    J0Fields F = j0_fields(jobs[sg.job], sg);
+    if constexpr (LO32) {
+      F.pw = in_vgpr(F.pw);
+      F.iw = in_vgpr(F.iw);
+    }
     // this workgroup's chunks of the segment, as one record span cut into
     // one contiguous part per wave (whole chunks)
     const uint64_t ub = (uint64_t)sg.ctile_beg * TC;
@@ -752,7 +806,7 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
     const uint64_t s0 = min(rbeg + (uint64_t)wv * part, rend);
     const uint64_t s1 = min(s0 + part, rend);
     if (s0 >= s1) continue;
-    J0Carry cr = j0_carry_at(log, n, s1, F, s_w);
+    J0Carry cr = j0_carry_at<LO32>(log, n, s1, F, s_w);
     // the part backward in ranges of J0_CHUNKS chunks
     const int nr = (int)((s1 - s0 + J0_CHUNKS * 64 - 1) / (J0_CHUNKS * 64));
     // a range's loads: the record before it (needed last) first, then its
@@ -763,24 +817,33 @@ __global__ __launch_bounds__(CONF_BLOCK) void j0_kernel(const Job* __restrict__ 
     auto load_range = [&](int r, uint64_t (&dst)[J0_CHUNKS], uint64_t& bef) {
       const uint64_t wb = s0 + (uint64_t)r * (J0_CHUNKS * 64);
       bef = log[wb > 0 ? wb - 1 : 0];
+      if (wb + J0_CHUNKS * 64 <= n) {
+        // wholly inside the log: one address, the chunks at immediate offsets
+        const gptr<uint64_t> p = log + wb + lane;
 #pragma unroll
-      for (int j = 0; j < J0_CHUNKS; j++) {
-        const uint64_t q = wb + (uint64_t)(J0_CHUNKS - 1 - j) * 64 + lane;
-        dst[j] = log[q < n ? q : n - 1];
+        for (int j = 0; j < J0_CHUNKS; j++) dst[j] = p[(J0_CHUNKS - 1 - j) * 64];
+      } else {
+#pragma unroll
+        for (int j = 0; j < J0_CHUNKS; j++) {
+          const uint64_t q = wb + (uint64_t)(J0_CHUNKS - 1 - j) * 64 + lane;
+          dst[j] = log[q < n ? q : n - 1];
+        }
       }
     };
     auto scan_range = [&](const uint64_t (&rv)[J0_CHUNKS], uint64_t before, uint64_t wbeg,
                           int nch) {
-      if (wbeg + (uint64_t)nch * 64 <= n)
-        j0_range<true>(F, s_w, s_minj, P, rv, before, wbeg, nch, n, cr);
+      if (nch == J0_CHUNKS && wbeg + (uint64_t)nch * 64 <= n)
+        j0_range<true, LO32>(F, s_w, s_minj, P, rv, before, wbeg, nch, n, cr);
       else
-        j0_range<false>(F, s_w, s_minj, P, rv, before, wbeg, nch, n, cr);
+        j0_range<false, LO32>(F, s_w, s_minj, P, rv, before, wbeg, nch, n, cr);
     };
     uint64_t rev[J0_CHUNKS], before;
     load_range(nr - 1, rev, before);
     for (int r = nr - 1; r >= 0; r--) {
       const uint64_t wbeg = s0 + (uint64_t)r * (J0_CHUNKS * 64);
-      const int nch = (int)min((uint64_t)J0_CHUNKS, (s1 - wbeg + 63) / 64);
+      // (a 32-bit scalar count, so that each chunk's test is one scalar compare)
+      const int nch = __builtin_amdgcn_readfirstlane(
+          (int)min((uint64_t)J0_CHUNKS, (s1 - wbeg + 63) / 64));
       if constexpr (PIPE) {
         uint64_t nxt[J0_CHUNKS], nbef = 0;
         if (r > 0) load_range(r - 1, nxt, nbef);
@@ -893,7 +956,7 @@ hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t 
   return hipGetLastError();
 }
 
-static int g_j0_variant = 0;   // 0: loads of a range after the range before it is scanned,
+static int g_j0_variant = 1;   // 0: loads of a range after the range before it is scanned,
                                // 1: the next range's loads in flight during the scan
 int j0_variant(int v, bool set) {
   const int old = g_j0_variant;
@@ -901,7 +964,14 @@ int j0_variant(int v, bool set) {
   return old;
 }
 
-template <bool PIPE>
+static int g_j0_fields = 0;    // 0: 32-bit fields where they fit, 1: always 64-bit records
+int j0_fields_variant(int v, bool set) {
+  const int old = g_j0_fields;
+  if (set) g_j0_fields = v;
+  return old;
+}
+
+template <bool PIPE, bool LO32>
 static hipError_t j0_go(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
                         const uint32_t* tiles, hipStream_t s) {
   // [P] first partners (u32); the write bits are a static array
@@ -909,20 +979,23 @@ static hipError_t j0_go(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t
   int dev = 0, ncu = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, j0_kernel<PIPE>, CONF_BLOCK, dyn) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, j0_kernel<PIPE, LO32>, CONF_BLOCK, dyn) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   const uint32_t grid = (uint32_t)ncu * (uint32_t)std::min(per_cu, 8);
-  j0_kernel<PIPE><<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
+  j0_kernel<PIPE, LO32><<<grid, CONF_BLOCK, dyn, s>>>(jobs, segs, nseg, tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_j0(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
-                     const uint32_t* tiles, hipStream_t s) {
+                     bool lo32, const uint32_t* tiles, hipStream_t s) {
   if (nseg == 0) return hipSuccess;
-  return g_j0_variant == 1 ? j0_go<true>(jobs, segs, nseg, max_points, tiles, s)
-                           : j0_go<false>(jobs, segs, nseg, max_points, tiles, s);
+  if (lo32 && g_j0_fields == 0)
+    return g_j0_variant == 1 ? j0_go<true, true>(jobs, segs, nseg, max_points, tiles, s)
+                             : j0_go<false, true>(jobs, segs, nseg, max_points, tiles, s);
+  return g_j0_variant == 1 ? j0_go<true, false>(jobs, segs, nseg, max_points, tiles, s)
+                           : j0_go<false, false>(jobs, segs, nseg, max_points, tiles, s);
 }
 
 hipError_t launch_pairs(const Job* job, rp_pair* out, uint64_t* total, hipStream_t s) {

@@ -400,12 +400,17 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
   // (a job without access records keeps the cleared table: no partner)
   if (o.op != OP_CHECK && o.op != OP_SOLVE) {
     uint32_t maxP = 1;
-    for (const JobInput& j : jobs) maxP = std::max(maxP, j.plan->P);
+    bool lo32 = true;
+    for (const JobInput& j : jobs) {
+      maxP = std::max(maxP, j.plan->P);
+      lo32 = lo32 && j.plan->tbits < 32 && j.plan->bbits < 32 &&
+             j.plan->tbits + j.plan->bbits + j.plan->pbits <= 32;
+    }
     HIPCHK(launch_ivl(djobs, (uint32_t)N, IVL_ZERO, s));
     if (!L.ssegs.empty()) {
       HIPCHK(launch_conf_tiles(djobs, dcs, (int)L.ssegs.size(), derr + 9, s));
       tm.mark(T_SUMPRE);
-      HIPCHK(launch_j0(djobs, dcs, (int)L.ssegs.size(), maxP, derr + 9, s));
+      HIPCHK(launch_j0(djobs, dcs, (int)L.ssegs.size(), maxP, lo32, derr + 9, s));
       tm.mark(T_SUMMARY);
     }
     HIPCHK(launch_save_j0(djobs, (uint32_t)N, s));

@@ -44,8 +44,10 @@ hipError_t launch_conf_tiles(const Job* jobs, ConfSeg* segs, int nseg, uint32_t*
 hipError_t launch_conf(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
                        const uint32_t* tiles, hipStream_t s);
 // First partners with no barrier enabled, into minj (cleared beforehand).
+// lo32: the point and id fields of every record lie in its low 32 bits
+// (thread, block and point bits together at most 32, in every job)
 hipError_t launch_j0(const Job* jobs, const ConfSeg* segs, int nseg, uint32_t max_points,
-                     const uint32_t* tiles, hipStream_t s);
+                     bool lo32, const uint32_t* tiles, hipStream_t s);
 hipError_t launch_pairs(const Job* job, rp_pair* out, uint64_t* total, hipStream_t s);
 hipError_t launch_clause(const Job* jobs, uint32_t njobs, int learn, hipStream_t s);
 hipError_t launch_solve(const Job* jobs, uint32_t njobs, hipStream_t s);

@@ -137,6 +137,7 @@ TUNE_SOLVER_NODES = 4
 TUNE_SCAN_PIPELINE = 5
 TUNE_DIGIT_ORDER = 6
 TUNE_LOW_DIGIT_BITS = 7
+TUNE_SCAN_FIELDS = 8
 
 
 def lib():

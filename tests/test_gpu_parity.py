@@ -222,6 +222,27 @@ def test_plain_large_full_size(L, name, mode):
     assert same_repair(g, o), (g, o)
 
 
+@pytest.mark.parametrize("name,mode", [("plain_large_literal", "literal"),
+                                       ("plain_large_planted", "planted")])
+def test_scan_variants_full_size(L, name, mode):
+    # the first-partner scan with the next range's loads in flight or not,
+    # and with the record fields taken from the low word or from the whole
+    # record: the same repair as the oracle's stored result
+    exp = _expected(name)["repair_policy0"]
+    km = synth.generate("plain-large", mode=mode)
+    old = (L.set_tuning(L.TUNE_SCAN_PIPELINE, 0), L.set_tuning(L.TUNE_SCAN_FIELDS, 0))
+    try:
+        for pipe in (0, 1):
+            for fields in (0, 1):
+                L.set_tuning(L.TUNE_SCAN_PIPELINE, pipe)
+                L.set_tuning(L.TUNE_SCAN_FIELDS, fields)
+                g = L.repair(km, policy=0)
+                assert same_repair(g, exp), (pipe, fields, g, exp)
+    finally:
+        L.set_tuning(L.TUNE_SCAN_PIPELINE, old[0])
+        L.set_tuning(L.TUNE_SCAN_FIELDS, old[1])
+
+
 def test_sort_knobs_full_size(L):
     # every digit plan (one width of 8..11 bits, or a 6..8-bit lowest digit
     # with the rest in digits of 6 and 7 bits: 19 key bits) and scatter tile
@@ -503,7 +524,17 @@ def _first_from_pairs(pairs, P):
     return first
 
 
-def test_first_partners(L):
+@pytest.mark.parametrize("pipe,fields", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_first_partners(L, pipe, fields):
+    old = (L.set_tuning(L.TUNE_SCAN_PIPELINE, pipe), L.set_tuning(L.TUNE_SCAN_FIELDS, fields))
+    try:
+        _first_partners_cases(L)
+    finally:
+        L.set_tuning(L.TUNE_SCAN_PIPELINE, old[0])
+        L.set_tuning(L.TUNE_SCAN_FIELDS, old[1])
+
+
+def _first_partners_cases(L):
     for seed in range(200):
         rng = np.random.default_rng(80_000 + seed)
         km = BF.tiny_kernel(rng)

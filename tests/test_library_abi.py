@@ -121,11 +121,11 @@ def test_tuning_knobs(L):
         assert L.set_tuning(L.TUNE_SOLVER_NODES, 28) == 10
     finally:
         L.set_tuning(L.TUNE_SOLVER_NODES, old)
-    old = L.set_tuning(L.TUNE_SCAN_PIPELINE, 1)
+    old = L.set_tuning(L.TUNE_SCAN_PIPELINE, 0)
     try:
-        assert old == 0                                          # loads after each range
+        assert old == 1                                          # next range's loads in flight
         assert L.set_tuning(L.TUNE_SCAN_PIPELINE, 2) == -1
-        assert L.set_tuning(L.TUNE_SCAN_PIPELINE, 0) == 1
+        assert L.set_tuning(L.TUNE_SCAN_PIPELINE, 1) == 0
     finally:
         L.set_tuning(L.TUNE_SCAN_PIPELINE, old)
     old = L.set_tuning(L.TUNE_DIGIT_ORDER, 0)
@@ -143,6 +143,14 @@ def test_tuning_knobs(L):
         assert L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 8) == 0
     finally:
         L.set_tuning(L.TUNE_LOW_DIGIT_BITS, old)
+    old = L.set_tuning(L.TUNE_SCAN_FIELDS, 1)
+    try:
+        assert old == 0                                          # 32-bit fields where they fit
+        assert L.set_tuning(L.TUNE_SCAN_FIELDS, 2) == -1
+        assert L.set_tuning(L.TUNE_SCAN_FIELDS, -1) == -1
+        assert L.set_tuning(L.TUNE_SCAN_FIELDS, 0) == 1
+    finally:
+        L.set_tuning(L.TUNE_SCAN_FIELDS, old)
 
 
 def test_invalid_kernel_does_no_device_work(L):
