@@ -37,80 +37,107 @@ template <int RB>
 using DigT = typename std::conditional<(RB <= 8), uint8_t, uint16_t>::type;
 
 // Per-chunk digit counts of one pass: cnt[chunk][d], from the digit array
-// (digit of record q at dig[q]).  Each thread walks its own contiguous
-// stretch of the chunk (1/256 of it) in 16-byte vectors (16 or 8 digits),
-// CNT_U vectors at a time, the next CNT_U issued before the current ones are
-// counted (so that many loads per lane are in flight while it counts); every
-// digit is one LDS add with no return value (the adds do not stall the
-// wave).  Digits of nearby records are often equal or follow a short period,
-// and lanes of one add that hit the same counter (or bank) are served one
-// after another: the lanes' stretches lie far apart, and an odd number of
-// vectors apart, so that a digit pattern with a power-of-two period along the
-// log (records sorted by the digits below this one) puts lanes 16 apart, not
-// all lanes, on one digit; those lanes count into different copies of the
-// histogram (lane / 16 picks the copy, CNT_G copies a bank apart).  A chunk's
-// first and last vectors may reach past it: those digits are skipped.
-constexpr uint32_t CNT_G = 4;
+// (digit of record q at dig[q]).  The chunk is read in rows of 64 16-byte
+// vectors (V = 16 or 8 digits per lane), one row per load instruction, so
+// each load takes whole lines and no line is fetched twice; wave w of the
+// workgroup takes rows w, w + 4, ... with CNT_U rows in flight per lane and
+// the next CNT_U issued before the current ones are counted.  A lane holds
+// V consecutive records and merges each run of one digit into a single LDS
+// add of the run's length (runs are long where consecutive threads touch
+// consecutive words).  Lanes of one add that hit the same counter are served
+// one after another, so the lanes count into G copies of the histogram,
+// chosen so that lanes sharing a digit in the two common patterns sit in
+// different copies: runs put neighbouring lanes on one digit, and a digit
+// that rises by one per record puts lane l on digit l * V + k (mod R), so
+// lanes R / V apart share it when R / V < 64.  Hence one copy per lane up to
+// 7-bit digits, lane / 4 for 8-bit ones (16 copies; lanes 16 apart share a
+// digit), lane mod G for wider ones (no two lanes of a row share a rising
+// digit).  Copies are R + 1 words apart, so the copies of one digit lie in
+// different banks.  Digits of the chunk's first and last vectors that lie
+// outside it count nothing.
+template <int RB>
+struct CntCopies {
+  static constexpr uint32_t G = RB <= 7 ? 64 : RB == 8 ? 16 : RB <= 10 ? 8 : 4;
+  __device__ static uint32_t of(uint32_t lane) {
+    return RB <= 7 ? lane : RB == 8 ? (lane >> 2) : (lane & (G - 1));
+  }
+};
 constexpr int CNT_U = 4;
+constexpr int CNT_WAVES = 4;
 
 template <int RB>
-__global__ __launch_bounds__(256) void count_kernel(const DigT<RB>* __restrict__ dig,
-                                                    const SortChunk* __restrict__ chunks,
-                                                    uint32_t nchunks,
-                                                    uint32_t* __restrict__ cnt) {
+__global__ __launch_bounds__(64 * CNT_WAVES) void count_kernel(const DigT<RB>* __restrict__ dig,
+                                                               const SortChunk* __restrict__ chunks,
+                                                               uint32_t nchunks,
+                                                               uint32_t* __restrict__ cnt) {
   constexpr uint32_t R = 1u << RB;
   using D = DigT<RB>;
   constexpr uint32_t V = 16 / sizeof(D);          // digits per vector
+  constexpr uint32_t G = CntCopies<RB>::G;
   constexpr uint32_t HS = R + 1;                 // copy stride: copies of a digit a bank apart
-  __shared__ uint32_t hist[CNT_G * HS];
-  const uint32_t tid = threadIdx.x;
-  uint32_t* my = hist + ((tid >> 4) % CNT_G) * HS;
+  constexpr uint32_t NT = 64 * CNT_WAVES;
+  __shared__ uint32_t hist[G * HS];
+  const uint32_t tid = threadIdx.x, lane = __lane_id();
+  const uint32_t w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  uint32_t* my = hist + CntCopies<RB>::of(lane) * HS;
   const uint4* src = reinterpret_cast<const uint4*>(dig);
   for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {   // persistent
     const SortChunk ch = chunks[ci];
     __syncthreads();
-    for (uint32_t d = tid; d < CNT_G * HS; d += 256) hist[d] = 0;
+    for (uint32_t d = tid; d < G * HS; d += NT) hist[d] = 0;
     __syncthreads();
-    // vectors covering [beg, end), aligned to V digits; thread tid takes
-    // the tid-th of 256 equal stretches of an odd number of vectors (the
-    // last stretches may be short or empty)
+    // vectors covering [beg, end), aligned to V digits, in rows of 64
     const uint64_t v0 = ch.beg / V, v1 = (ch.end + V - 1) / V;
-    const uint64_t span = ((v1 - v0 + 255) / 256) | 1u;
-    uint64_t v = v0 + tid * span;
-    const uint64_t ve = v + span < v1 ? v + span : v1;
-    // loads past the stretch read the chunk's last vector (always in
-    // bounds, so no load is conditional) and count nothing
+    const uint64_t nrow = (v1 - v0 + 63) / 64;
+    // loads past the chunk read its last vector (always in bounds, so no
+    // load is conditional) and count nothing
     const uint64_t vlast = v1 - 1;
+    auto row_vec = [&](uint64_t r) { return v0 + r * 64 + lane; };
     uint4 cur[CNT_U];
+    uint64_t r = w;
 #pragma unroll
-    for (int u = 0; u < CNT_U; u++) cur[u] = src[v + u < ve ? v + u : vlast];
-    while (v < ve) {
-      const uint64_t vn = v + CNT_U;
+    for (int u = 0; u < CNT_U; u++) {
+      const uint64_t v = row_vec(r + (uint64_t)u * CNT_WAVES);
+      cur[u] = src[v < v1 ? v : vlast];
+    }
+    for (; r < nrow; r += (uint64_t)CNT_U * CNT_WAVES) {
+      const uint64_t rn = r + (uint64_t)CNT_U * CNT_WAVES;
       uint4 nxt[CNT_U];
 #pragma unroll
-      for (int u = 0; u < CNT_U; u++) nxt[u] = src[vn + u < ve ? vn + u : vlast];
-      // no branches on the lane: a digit outside the chunk (or in a vector
-      // past the stretch, read as zeros) adds 0
+      for (int u = 0; u < CNT_U; u++) {
+        const uint64_t v = row_vec(rn + (uint64_t)u * CNT_WAVES);
+        nxt[u] = src[v < v1 ? v : vlast];
+      }
 #pragma unroll
       for (int u = 0; u < CNT_U; u++) {
         const D* e = reinterpret_cast<const D*>(&cur[u]);
-        const uint64_t q0 = (v + u) * V;
+        const uint64_t v = row_vec(r + (uint64_t)u * CNT_WAVES);
+        const uint64_t q0 = v * V;
+        // digits [lo, hi) of this vector lie in the chunk (none past its end)
         const uint32_t lo = q0 >= ch.beg ? 0u : (uint32_t)min((uint64_t)V, ch.beg - q0);
-        const uint32_t hi = v + u >= ve ? 0u
+        const uint32_t hi = v >= v1 ? 0u
                             : (q0 + V <= ch.end ? V : (uint32_t)(ch.end > q0 ? ch.end - q0 : 0));
+        uint32_t run = 0;
 #pragma unroll
-        for (uint32_t k = 0; k < V; k++) atomicAdd(&my[e[k]], (k - lo < hi - lo) ? 1u : 0u);
+        for (uint32_t k = 0; k < V; k++) {
+          run += (k - lo < hi - lo) ? 1u : 0u;
+          // the run ends at the vector's last digit or before another digit
+          const bool ends = k + 1 == V || e[k + 1] != e[k];
+          if (ends && run != 0) {
+            atomicAdd(&my[e[k]], run);
+            run = 0;
+          }
+        }
       }
 #pragma unroll
       for (int u = 0; u < CNT_U; u++) cur[u] = nxt[u];
-      v = vn;
     }
     __syncthreads();
     uint32_t* row = cnt + (size_t)ci * R;
-    for (uint32_t d = tid; d < R; d += 256) {
+    for (uint32_t d = tid; d < R; d += NT) {
       uint32_t t = 0;
-#pragma unroll
-      for (uint32_t g = 0; g < CNT_G; g++) t += hist[g * HS + d];
+#pragma unroll 8
+      for (uint32_t g = 0; g < G; g++) t += hist[g * HS + d];
       row[d] = t;
     }
   }
@@ -504,8 +531,8 @@ hipError_t launch_sort_scan(int rb, const void* dig, const SortSeg* segs, uint32
     if (hipGetDevice(&dev) == hipSuccess)
       (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const uint32_t grid = std::min<uint32_t>(nchunks, (uint32_t)ncu * 8);
-    RB_SWITCH(rb, (count_kernel<RBV><<<grid, 256, 0, s>>>((const DigT<RBV>*)dig, chunks, nchunks,
-                                                          cnt)));
+    RB_SWITCH(rb, (count_kernel<RBV><<<grid, 64 * CNT_WAVES, 0, s>>>((const DigT<RBV>*)dig, chunks,
+                                                                     nchunks, cnt)));
   }
   RB_SWITCH(rb, (colsum_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot)));
   RB_SWITCH(rb, (colscan_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot, off, ticket)));
