@@ -42,6 +42,30 @@ __device__ __forceinline__ void count_digits(uint32_t* hist, uint64_t rec, int s
   }
 }
 
+// Stores a step's record of this lane and counts its digit.  A full step
+// (every lane of the wave holds a record) needs no lane mask: the store is
+// unconditional and the uniform-digit test compares with every lane.
+template <int RB>
+__device__ __forceinline__ void put_record(uint64_t* out, uint64_t at, uint64_t rec, bool full,
+                                           bool valid, bool count, uint32_t* hist, int shift) {
+  if (full) {
+    out[at] = rec;
+    if (count) {
+      constexpr uint32_t R = 1u << RB;
+      const uint32_t d = digit_at(rec, shift, R - 1);
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+      if (__builtin_amdgcn_ballot_w64(d == d0) == ~0ull) {
+        if (__lane_id() == 0) atomicAdd(&hist[d0], 64u);
+      } else {
+        atomicAdd(&hist[d], 1u);
+      }
+    }
+  } else {
+    if (valid) out[at] = rec;
+    if (count) count_digits<RB>(hist, rec, shift, valid);
+  }
+}
+
 // Wave-uniform copies (the values are the same in every lane; saying so
 // keeps the per-point arithmetic on the scalar unit).
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -131,8 +155,7 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
           for (uint64_t q0 = 0; q0 < take; q0 += 64) {
             const uint64_t q = q0 + lane;
             const bool valid = q < take;
-            if (valid) out[lo + q] = rec;
-            if (count) count_digits<RB>(hist, rec, shift, valid);
+            put_record<RB>(out, lo + q, rec, uni(q0 + 64 <= take) != 0, valid, count, hist, shift);
           }
         } else {
           const uint64_t arr = (uint64_t)p.array << nb;
@@ -155,8 +178,7 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
             if (pow2) word = (cw + am * (uint32_t)q0 + at) & wmask;
             else word = word_of(p, t, k);
             const uint64_t rec = ((arr | word) << ks) | low | t;
-            if (valid) out[lo + q] = rec;
-            if (count) count_digits<RB>(hist, rec, shift, valid);
+            put_record<RB>(out, lo + q, rec, uni(q0 + 64 <= take) != 0, valid, count, hist, shift);
           }
         }
       }
@@ -208,8 +230,7 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
           if (pow2) word = ((uint32_t)p.a * t + (uint32_t)p.b * kk + (uint32_t)p.c) & wmask;
           else word = word_of(p, t, kk);
           const uint64_t rec = ((arr | word) << ks) | pf | ((uint64_t)kk << tb);
-          if (valid) out[pos + q] = rec;
-          if (count) count_digits<RB>(hist, rec, shift, valid);
+          put_record<RB>(out, pos + q, rec, uni(q0 + GEN_BLOCK <= take) != 0, valid, count, hist, shift);
         }
       }
       pos += take;

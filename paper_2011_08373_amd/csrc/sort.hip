@@ -306,6 +306,10 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
   // lane l is record w*64*IPT + k*64 + l (coalesced; rank order = input order)
   for (uint32_t q = tid; q < SC_WAVES * R; q += SC_BLOCK) (&whist[0][0])[q] = 0;
   __syncthreads();
+  // Key loads are never conditional: a slot past the tile reads the tile's
+  // last record (a tile is never empty), whose value goes unused.  A load
+  // under a lane mask would sit behind a branch, and the wait for the
+  // current tile's keys would then also wait for the next tile's loads.
   uint64_t key[SC_IPT];
   {
     const uint64_t rem = ch.end - base;
@@ -313,7 +317,7 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
 #pragma unroll
     for (int k = 0; k < SC_IPT; k++) {
       const uint32_t idx = wbase + k * 64 + lane;
-      key[k] = idx < n0 ? load_key<NTL>(&in[base + idx]) : 0;
+      key[k] = load_key<NTL>(&in[base + (idx < n0 ? idx : n0 - 1)]);
     }
   }
   for (;;) {
@@ -333,12 +337,14 @@ __global__ __launch_bounds__(SC_BLOCK) void scatter_kernel(const uint64_t* __res
     const bool has_next = nci < nchunks;
     uint64_t knext[SC_IPT];
     {
-      const uint64_t nrem = has_next ? nch.end - nbase : 0;
+      // (no next tile: the current tile's first record, unused)
+      const uint64_t nb = has_next ? nbase : base;
+      const uint64_t nrem = has_next ? nch.end - nbase : 1;
       const uint32_t nn = nrem < SC_TILE ? (uint32_t)nrem : SC_TILE;
 #pragma unroll
       for (int k = 0; k < SC_IPT; k++) {
         const uint32_t idx = wbase + k * 64 + lane;
-        knext[k] = idx < nn ? load_key<NTL>(&in[nbase + idx]) : 0;
+        knext[k] = load_key<NTL>(&in[nb + (idx < nn ? idx : nn - 1)]);
       }
     }
     // Rank of each record among the wave's records of its digit, in input
