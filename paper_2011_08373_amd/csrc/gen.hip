@@ -42,28 +42,36 @@ __device__ __forceinline__ void count_digits(uint32_t* hist, uint64_t rec, int s
   }
 }
 
-// Stores a step's record of this lane and counts its digit.  A full step
-// (every lane of the wave holds a record) needs no lane mask: the store is
-// unconditional and the uniform-digit test compares with every lane.
-template <int RB>
-__device__ __forceinline__ void put_record(uint64_t* out, uint64_t at, uint64_t rec, bool full,
-                                           bool valid, bool count, uint32_t* hist, int shift) {
-  if (full) {
-    out[at] = rec;
-    if (count) {
-      constexpr uint32_t R = 1u << RB;
-      const uint32_t d = digit_at(rec, shift, R - 1);
-      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-      if (__builtin_amdgcn_ballot_w64(d == d0) == ~0ull) {
-        if (__lane_id() == 0) atomicAdd(&hist[d0], 64u);
-      } else {
-        atomicAdd(&hist[d], 1u);
-      }
-    }
-  } else {
-    if (valid) out[at] = rec;
-    if (count) count_digits<RB>(hist, rec, shift, valid);
+// Digit counts of a wave's steps.  A step whose valid lanes all carry one
+// digit adds its count to a wave-uniform run (scalar registers), which is
+// added to the LDS counter with one add when the digit changes or the wave
+// is done; other steps add each record on its own.  The valid lanes are a
+// prefix of the wave (lane 0 is always one of them).
+struct DigitRun {
+  uint32_t d = 0, n = 0;
+  __device__ __forceinline__ void flush(uint32_t* hist) {
+    if (n != 0 && __lane_id() == 0) atomicAdd(&hist[d], n);
+    n = 0;
   }
+  __device__ __forceinline__ void add(uint32_t* hist, uint32_t dd, uint32_t k) {
+    if (dd != d) {
+      flush(hist);
+      d = dd;
+    }
+    n += k;
+  }
+};
+template <int RB>
+__device__ __forceinline__ void count_step(uint32_t* hist, DigitRun& run, uint64_t rec, int shift,
+                                           bool valid, uint64_t act) {
+  constexpr uint32_t R = 1u << RB;
+  const uint32_t d = digit_at(rec, shift, R - 1);
+  const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+  if (act == 0) return;                     // a wave wholly past the end
+  if ((__builtin_amdgcn_ballot_w64(d == d0) & act) == act)
+    run.add(hist, d0, (uint32_t)__popcll(act));
+  else if (valid)
+    atomicAdd(&hist[d], 1u);
 }
 
 // Wave-uniform copies (the values are the same in every lane; saying so
@@ -134,6 +142,7 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
     const uint32_t w = uni(tid >> 6), lane = tid & 63u;
     const uint64_t rblk = J.rblk;
     uint32_t k = (uint32_t)(it.o0 / rblk);
+    DigitRun run;
     uint32_t sd = w;                   // segment index (cache slot while < nc)
     uint32_t si = i0 + w;
     while (si >= P) { si -= P; k++; }
@@ -148,15 +157,17 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
       if (lo < hi) {
         const DPoint p = uni_point(cached ? s_pts[sd] : J.pts[si]);
         const uint64_t low = ((uint64_t)k << (pb + tb)) | ((uint64_t)si << tb);
+        // (a segment is one point of one block: fewer than 2^32 records)
+        const uint32_t take = uni((uint32_t)(hi - lo));
+        const uint32_t nfull = take >> 6, rem = take & 63u;
+        uint64_t* const dst = out + lo;
         if (p.bm > 1 && k % p.bm != p.br) {
-          // this block does not execute the point: padding
+          // this block does not execute the point: padding, one record for
+          // the whole segment
           const uint64_t rec = (((uint64_t)J.pad_array << nb) << ks) | low;
-          const uint64_t take = hi - lo;
-          for (uint64_t q0 = 0; q0 < take; q0 += 64) {
-            const uint64_t q = q0 + lane;
-            const bool valid = q < take;
-            put_record<RB>(out, lo + q, rec, uni(q0 + 64 <= take) != 0, valid, count, hist, shift);
-          }
+          for (uint32_t st = 0; st < nfull; st++) dst[st * 64 + lane] = rec;
+          if (lane < rem) dst[nfull * 64 + lane] = rec;
+          if (count) run.add(hist, uni(digit_at(rec, shift, R - 1)), take);
         } else {
           const uint64_t arr = (uint64_t)p.array << nb;
           // record u0 + q of the point: thread t = r + m*(u0 + q)
@@ -169,16 +180,22 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
           const uint32_t at = pow2 ? mul_tid(am, lane) : 0u;
           const uint32_t cw = (uint32_t)p.a * t0 + (uint32_t)p.b * k + (uint32_t)p.c;
           const uint32_t wmask = p.words - 1;
-          const uint64_t take = hi - lo;
-          for (uint64_t q0 = 0; q0 < take; q0 += 64) {
-            const uint64_t q = q0 + lane;
-            const bool valid = q < take;
-            const uint32_t t = t0 + p.m * (uint32_t)q0 + mt;
-            uint32_t word;
-            if (pow2) word = (cw + am * (uint32_t)q0 + at) & wmask;
-            else word = word_of(p, t, k);
-            const uint64_t rec = ((arr | word) << ks) | low | t;
-            put_record<RB>(out, lo + q, rec, uni(q0 + 64 <= take) != 0, valid, count, hist, shift);
+          auto record = [&](uint32_t q0) {
+            const uint32_t t = t0 + p.m * q0 + mt;
+            const uint32_t word = pow2 ? (cw + am * q0 + at) & wmask : word_of(p, t, k);
+            return ((arr | word) << ks) | low | t;
+          };
+          // whole steps with no lane mask, then the tail
+          for (uint32_t st = 0; st < nfull; st++) {
+            const uint64_t rec = record(st * 64);
+            dst[st * 64 + lane] = rec;
+            if (count) count_step<RB>(hist, run, rec, shift, true, ~0ull);
+          }
+          if (rem) {
+            const bool valid = lane < rem;
+            const uint64_t rec = record(nfull * 64);
+            if (valid) dst[nfull * 64 + lane] = rec;
+            if (count) count_step<RB>(hist, run, rec, shift, valid, __ballot(valid));
           }
         }
       }
@@ -186,11 +203,13 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
       si += WAVES;
       while (si >= P) { si -= P; k++; }
     }
+    if (count) run.flush(hist);
   } else {
     // point-major over GLOBAL access points: point i, executing blocks in
     // order, executing threads in order (one thread when the word does not
     // depend on it; the first two executing blocks only when it does not
     // depend on the block)
+    DigitRun run;
     uint32_t i = i0;
     uint32_t d = 0;            // cache slot of point i
     uint64_t pos = it.o0;
@@ -209,9 +228,7 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
         const uint32_t csh = 31u - (uint32_t)__builtin_clz(cnt);
         const bool pow2 = p.flags & PF_POW2;
         const uint32_t wmask = p.words - 1;
-        for (uint64_t q0 = 0; q0 < take; q0 += GEN_BLOCK) {
-          const uint64_t q = q0 + tid;
-          const bool valid = q < take;
+        auto record = [&](uint64_t q) {
           const uint64_t j = j0 + q;
           uint32_t kk, u;
           if (cpow2 && span < (1ull << 32)) {
@@ -229,8 +246,23 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
           uint32_t word;
           if (pow2) word = ((uint32_t)p.a * t + (uint32_t)p.b * kk + (uint32_t)p.c) & wmask;
           else word = word_of(p, t, kk);
-          const uint64_t rec = ((arr | word) << ks) | pf | ((uint64_t)kk << tb);
-          put_record<RB>(out, pos + q, rec, uni(q0 + GEN_BLOCK <= take) != 0, valid, count, hist, shift);
+          return ((arr | word) << ks) | pf | ((uint64_t)kk << tb);
+        };
+        // whole steps of the workgroup with no lane mask, then the tail
+        const uint64_t nfull = uni64(take / GEN_BLOCK);
+        uint64_t* const dst = out + pos;
+        for (uint64_t st = 0; st < nfull; st++) {
+          const uint64_t q = st * GEN_BLOCK + tid;
+          const uint64_t rec = record(q);
+          dst[q] = rec;
+          if (count) count_step<RB>(hist, run, rec, shift, true, ~0ull);
+        }
+        if (nfull * GEN_BLOCK < take) {
+          const uint64_t q = nfull * GEN_BLOCK + tid;
+          const bool valid = q < take;
+          const uint64_t rec = record(q);
+          if (valid) dst[q] = rec;
+          if (count) count_step<RB>(hist, run, rec, shift, valid, __ballot(valid));
         }
       }
       pos += take;
@@ -238,6 +270,7 @@ __global__ __launch_bounds__(GEN_BLOCK) void gen_kernel(const GenItem* __restric
       d++;
       i++;
     }
+    if (count) run.flush(hist);
   }
   if (!count) return;
   __syncthreads();
