@@ -132,8 +132,12 @@ struct SortSeg {
   uint32_t shift;        // key_shift of the job
   uint32_t chunk_beg, chunk_end;  // its chunks
   uint32_t job, view;    // the job and log (0 same-block, 1 cross-block)
-  uint32_t pad;
+  uint32_t cblk_beg;     // its first column block (COL_BLOCK_CHUNKS chunks each)
 };
+
+// Chunks per column block: the column scans of a pass read and write the
+// per-chunk digit tables a block of chunks at a time, every row whole.
+constexpr uint32_t COL_BLOCK_CHUNKS = 32;
 
 // sort chunk: a record range inside one segment, one workgroup per pass
 struct SortChunk {

@@ -32,6 +32,8 @@ struct Layout {
   uint32_t rb = 8, passes = 0;   // widest digit of the passes (table sizes), passes
   std::vector<DigitPass> digits;  // the passes' digits in execution order
   uint32_t n_chunks = 0;          // sort chunks = generation items (built on the device)
+  uint32_t n_cblk = 0, max_cblk = 0;   // column blocks, and the most of one segment
+  size_t o_part = 0;              // per column block and digit: its count, then its base
   uint64_t chunk_len = 0;
   std::vector<SortSeg> ssegs;
   std::vector<uint32_t> seg_job, seg_level;
@@ -83,6 +85,11 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
     L.ssegs[s].chunk_beg = L.n_chunks;
     L.n_chunks += (uint32_t)((L.ssegs[s].end - L.ssegs[s].beg + chunk - 1) / chunk);
     L.ssegs[s].chunk_end = L.n_chunks;
+    const uint32_t nb = (L.ssegs[s].chunk_end - L.ssegs[s].chunk_beg + COL_BLOCK_CHUNKS - 1) /
+                        COL_BLOCK_CHUNKS;
+    L.ssegs[s].cblk_beg = L.n_cblk;
+    L.n_cblk += nb;
+    L.max_cblk = std::max(L.max_cblk, nb);
   }
   const uint32_t R = 1u << L.rb;
   // ---- meta region (uploaded)
@@ -125,6 +132,7 @@ void plan_layout(const std::vector<JobInput>& jobs, const EngineOpts& o, Layout&
   }
   L.o_cnt = off; off = up(off + (size_t)L.n_chunks * R * sizeof(uint32_t));
   L.o_tot = off; off = up(off + L.ssegs.size() * (size_t)R * sizeof(uint64_t));
+  L.o_part = off; off = up(off + (size_t)L.n_cblk * R * sizeof(uint64_t));
   L.o_off = off; off = up(off + (size_t)L.n_chunks * R * sizeof(uint64_t));
   L.o_ivl.resize(N); L.o_minj.resize(N); L.o_j0.resize(N); L.o_phi.resize(N); L.o_scratch.resize(N);
   L.o_traj.resize(N); L.o_bitmap.resize(N); L.o_pairs.resize(N); L.o_ptotal.resize(N);
@@ -385,8 +393,9 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
     uint64_t* out = (uint64_t*)(d + ((p % 2 == 0) ? L.o_recB : L.o_recA));
     void* dig = L.passes > 1 ? (void*)(d + L.o_dig) : nullptr;
     const bool last = p + 1 == passes;
-    HIPCHK(launch_sort_scan((int)dg[p].bits, dig, dss, (uint32_t)L.ssegs.size(), dch, nch, dcnt,
-                            dtot, doff, derr + 10, p == 0, s));
+    HIPCHK(launch_sort_scan((int)dg[p].bits, dig, dss, (uint32_t)L.ssegs.size(), dch, nch,
+                            L.n_cblk, L.max_cblk, dcnt, dtot, (uint64_t*)(d + L.o_part), doff,
+                            derr + 10, p == 0, s));
     tm.mark(T_SORTPASS);
     HIPCHK(launch_sort_scatter((int)dg[p].bits, in, out, dss, dch, nch, (int)dg[p].lo,
                                last ? 0 : (int)dg[p + 1].lo, last ? 0 : (int)dg[p + 1].bits,

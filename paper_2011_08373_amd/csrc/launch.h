@@ -20,10 +20,12 @@ hipError_t launch_items(const Job* jobs, const SortSeg* segs, uint32_t nseg, uin
 // dig: each record's digit of this pass (1 byte for 8-bit digits, else 2),
 // as the previous pass's scatter wrote it; unused when counts_ready (pass 0
 // takes its counts from record generation)
+// n_cblk column blocks over all segments (each segment's from its cblk_beg),
+// at most max_cblk in one segment; part: [n_cblk][2^rb] scratch
 hipError_t launch_sort_scan(int rb, const void* dig, const SortSeg* segs, uint32_t nseg,
-                            const SortChunk* chunks, uint32_t nchunks, uint32_t* cnt,
-                            uint64_t* tot, uint64_t* off, uint32_t* ticket, bool counts_ready,
-                            hipStream_t s);
+                            const SortChunk* chunks, uint32_t nchunks, uint32_t n_cblk,
+                            uint32_t max_cblk, uint32_t* cnt, uint64_t* tot, uint64_t* part,
+                            uint64_t* off, uint32_t* ticket, bool counts_ready, hipStream_t s);
 // The pass sorts by key bits [lo, lo + rb) above each segment's key shift;
 // the next pass's digit, key bits [nlo, nlo + nbits), is stored per output
 // record in dnext (1 byte for up to 8 bits, else 2; NULL after the last

@@ -7,10 +7,11 @@
 //                    beside its output (1 byte per record for 8-bit digits,
 //                    2 above), not from the 8-byte records (pass 0 takes its
 //                    counts from record generation instead);
-//   colsum_kernel    per (segment, digit), the total over the segment's chunks;
-//   colscan_kernel   per (segment, digit), the exclusive scan over the chunks,
-//                    offset by the segment start and the totals of smaller
-//                    digits: the first output slot of every (chunk, digit);
+//   colpart/coltot/colbase/coloff_kernel
+//                    the exclusive scan of the counts per (segment, digit)
+//                    over the chunks, offset by the segment start and the
+//                    totals of smaller digits: the first output slot of
+//                    every (chunk, digit);
 //   scatter_kernel   per chunk, tiles of records are ranked stably with
 //                    64-lane ballots, staged in LDS in digit order and written
 //                    out as contiguous digit runs, each record's digit of the
@@ -143,91 +144,151 @@ __global__ __launch_bounds__(64 * CNT_WAVES) void count_kernel(const DigT<RB>* _
   }
 }
 
-constexpr int CS_K = 8;   // column loads in flight per thread (colsum, colscan)
+// Column scans of a pass: off[c][d] = the segment's start + the records of
+// smaller digits in the segment + the records of digit d in the segment's
+// chunks before c.  The chunks of a segment form column blocks of
+// COL_BLOCK_CHUNKS chunks; every table row (one chunk, all digits) is read
+// or written whole by a workgroup, one digit per thread.
+//   colpart_kernel  per column block and digit, its count (part);
+//   coltot_kernel   per segment and digit, the total over its blocks (tot);
+//   colbase_kernel  per segment and digit, each block's base: the segment's
+//                   start, the smaller digits' totals and the counts of the
+//                   blocks before it (part, in place);
+//   coloff_kernel   per chunk and digit, the block's base plus the counts of
+//                   the block's chunks before it (off).
 
-// Column totals: tot[seg][d] = sum over the segment's chunks of cnt[chunk][d].
-template <int RB>
-__global__ __launch_bounds__(256) void colsum_kernel(const uint32_t* __restrict__ cnt,
-                                                     const SortSeg* __restrict__ segs,
-                                                     uint64_t* __restrict__ tot) {
-  constexpr uint32_t R = 1u << RB;
-  __shared__ uint64_t sm[4];
-  const uint32_t seg = blockIdx.x / R, d = blockIdx.x % R;
-  const uint32_t c0 = segs[seg].chunk_beg, c1 = segs[seg].chunk_end;
-  // CS_K independent loads per thread and step: one memory round trip per
-  // 256 x CS_K chunks of the column, not per 256
-  uint64_t s = 0;
-  for (uint32_t cb = c0; cb < c1; cb += 256 * CS_K) {
-    uint32_t v[CS_K];
-#pragma unroll
-    for (int k = 0; k < CS_K; k++) {
-      const uint32_t c = cb + k * 256 + threadIdx.x;
-      v[k] = c < c1 ? cnt[(size_t)c * R + d] : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < CS_K; k++) s += v[k];
+// The column block's segment (the last with cblk_beg <= b) and chunks.
+__device__ __forceinline__ uint32_t cblk_seg(const SortSeg* segs, uint32_t nseg, uint32_t b) {
+  uint32_t lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (segs[mid].cblk_beg <= b) lo = mid; else hi = mid - 1;
   }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (__lane_id() == 0) sm[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) tot[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+  return lo;
 }
 
-// First output slot of every (chunk, digit).
+constexpr int COL_U = 8;   // table loads in flight per thread
+
 template <int RB>
-__global__ __launch_bounds__(256) void colscan_kernel(const uint32_t* __restrict__ cnt,
+__global__ __launch_bounds__(256) void colpart_kernel(const uint32_t* __restrict__ cnt,
                                                       const SortSeg* __restrict__ segs,
-                                                      const uint64_t* __restrict__ tot,
-                                                      uint64_t* __restrict__ off,
-                                                      uint32_t* __restrict__ ticket) {
+                                                      uint32_t nseg, uint64_t* __restrict__ part) {
   constexpr uint32_t R = 1u << RB;
-  __shared__ uint64_t sm[4];
-  __shared__ uint64_t s_base;
+  const uint32_t b = blockIdx.x;
+  const SortSeg sg = segs[cblk_seg(segs, nseg, b)];
+  const uint32_t c0 = sg.chunk_beg + (b - sg.cblk_beg) * COL_BLOCK_CHUNKS;
+  const uint32_t c1 = min(c0 + COL_BLOCK_CHUNKS, sg.chunk_end);
+  for (uint32_t d = threadIdx.x; d < R; d += 256) {
+    uint64_t t = 0;
+    for (uint32_t c = c0; c < c1; c += COL_U) {
+      uint32_t v[COL_U];
+#pragma unroll
+      for (int k = 0; k < COL_U; k++) v[k] = c + k < c1 ? cnt[(size_t)(c + k) * R + d] : 0u;
+#pragma unroll
+      for (int k = 0; k < COL_U; k++) t += v[k];
+    }
+    part[(size_t)b * R + d] = t;
+  }
+}
+
+// One workgroup per (segment, 64 digits): lane = digit, wave g sums blocks
+// g, g + G, ... of the segment (G waves).
+template <int RB>
+__global__ __launch_bounds__(1024) void coltot_kernel(const SortSeg* __restrict__ segs,
+                                                      const uint64_t* __restrict__ part,
+                                                      uint64_t* __restrict__ tot) {
+  constexpr uint32_t R = 1u << RB;
+  constexpr uint32_t DG = R / 64;               // digit groups per segment
+  __shared__ uint64_t sm[16][64];
+  const uint32_t s = blockIdx.x / DG, d = (blockIdx.x % DG) * 64 + __lane_id();
+  const uint32_t G = blockDim.x >> 6, g = threadIdx.x >> 6;
+  const SortSeg sg = segs[s];
+  const uint32_t nb = (sg.chunk_end - sg.chunk_beg + COL_BLOCK_CHUNKS - 1) / COL_BLOCK_CHUNKS;
+  uint64_t t = 0;
+  for (uint32_t i = g; i < nb; i += G) t += part[(size_t)(sg.cblk_beg + i) * R + d];
+  sm[g][__lane_id()] = t;
+  __syncthreads();
+  if (g == 0) {
+    uint64_t all = 0;
+    for (uint32_t q = 0; q < G; q++) all += sm[q][__lane_id()];
+    tot[(size_t)s * R + d] = all;
+  }
+}
+
+// One workgroup per (segment, 64 digits): lane = digit, wave g owns a
+// contiguous run of the segment's blocks (G waves); the digit's base in the
+// segment comes from the totals of the smaller digits.
+template <int RB>
+__global__ __launch_bounds__(1024) void colbase_kernel(const SortSeg* __restrict__ segs,
+                                                       const uint64_t* __restrict__ tot,
+                                                       uint64_t* __restrict__ part,
+                                                       uint32_t* __restrict__ ticket) {
+  constexpr uint32_t R = 1u << RB;
+  constexpr uint32_t DG = R / 64;
+  __shared__ uint64_t sm[16][64];
+  __shared__ uint64_t s_below[16];
   // the scatter of this pass hands out its chunks from zero
   if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;
-  const uint32_t seg = blockIdx.x / R, d = blockIdx.x % R;
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  // records of smaller digits in this segment
-  uint64_t b = 0;
-  for (uint32_t q = threadIdx.x; q < d; q += 256) b += tot[(size_t)seg * R + q];
-  for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o);
-  if (lane == 0) sm[w] = b;
+  const uint32_t s = blockIdx.x / DG, d0 = (blockIdx.x % DG) * 64;
+  const uint32_t lane = __lane_id(), d = d0 + lane;
+  const uint32_t G = blockDim.x >> 6, g = threadIdx.x >> 6;
+  const SortSeg sg = segs[s];
+  const uint64_t* tt = tot + (size_t)s * R;
+  // records of the digits below this group's 64: every wave sums a share
+  uint64_t below = 0;
+  for (uint32_t q = threadIdx.x; q < d0; q += blockDim.x) below += tt[q];
+  for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
+  if (lane == 0) s_below[g] = below;
+  // this wave's blocks: a contiguous run (a share of ceil(nb / G))
+  const uint32_t nb = (sg.chunk_end - sg.chunk_beg + COL_BLOCK_CHUNKS - 1) / COL_BLOCK_CHUNKS;
+  const uint32_t per = (nb + G - 1) / G;
+  const uint32_t i0 = min(g * per, nb), i1 = min(i0 + per, nb);
+  uint64_t* pd = part + (size_t)sg.cblk_beg * R + d;
+  uint64_t mine = 0;
+  for (uint32_t i = i0; i < i1; i++) mine += pd[(size_t)i * R];
+  sm[g][lane] = mine;
   __syncthreads();
-  if (threadIdx.x == 0) s_base = segs[seg].beg + sm[0] + sm[1] + sm[2] + sm[3];
-  __syncthreads();
-  uint64_t run = s_base;
-  const uint32_t c0 = segs[seg].chunk_beg, c1 = segs[seg].chunk_end;
-  // steps of 256 x CS_K chunks; thread t takes CS_K consecutive chunks of a
-  // step, loaded together, and scans them after the block's scan of the
-  // per-thread sums
-  for (uint32_t cb = c0; cb < c1; cb += 256 * CS_K) {
-    const uint32_t cf = cb + threadIdx.x * CS_K;
-    uint32_t v[CS_K];
+  uint64_t base = sg.beg;
+  for (uint32_t q = 0; q < G; q++) base += s_below[q];
+  // smaller digits of the group (an exclusive scan over the lanes)
+  const uint64_t td = tt[d];
+  uint64_t inc = td;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(inc, o);
+    if (lane >= (uint32_t)o) inc += y;
+  }
+  base += inc - td;
+  for (uint32_t q = 0; q < g; q++) base += sm[q][lane];   // earlier waves' blocks
+  for (uint32_t i = i0; i < i1; i++) {
+    const uint64_t v = pd[(size_t)i * R];
+    pd[(size_t)i * R] = base;
+    base += v;
+  }
+}
+
+template <int RB>
+__global__ __launch_bounds__(256) void coloff_kernel(const uint32_t* __restrict__ cnt,
+                                                     const SortSeg* __restrict__ segs,
+                                                     uint32_t nseg,
+                                                     const uint64_t* __restrict__ part,
+                                                     uint64_t* __restrict__ off) {
+  constexpr uint32_t R = 1u << RB;
+  const uint32_t b = blockIdx.x;
+  const SortSeg sg = segs[cblk_seg(segs, nseg, b)];
+  const uint32_t c0 = sg.chunk_beg + (b - sg.cblk_beg) * COL_BLOCK_CHUNKS;
+  const uint32_t c1 = min(c0 + COL_BLOCK_CHUNKS, sg.chunk_end);
+  for (uint32_t d = threadIdx.x; d < R; d += 256) {
+    uint64_t at = part[(size_t)b * R + d];
+    for (uint32_t c = c0; c < c1; c += COL_U) {
+      uint32_t v[COL_U];
 #pragma unroll
-    for (int k = 0; k < CS_K; k++) v[k] = cf + k < c1 ? cnt[(size_t)(cf + k) * R + d] : 0;
-    uint64_t local = 0;
+      for (int k = 0; k < COL_U; k++) v[k] = c + k < c1 ? cnt[(size_t)(c + k) * R + d] : 0u;
 #pragma unroll
-    for (int k = 0; k < CS_K; k++) local += v[k];
-    uint64_t inc = local;
-    for (int o = 1; o < 64; o <<= 1) {
-      uint64_t y = __shfl_up(inc, o);
-      if (lane >= o) inc += y;
+      for (int k = 0; k < COL_U; k++) {
+        if (c + k < c1) off[(size_t)(c + k) * R + d] = at;
+        at += v[k];
+      }
     }
-    if (lane == 63) sm[w] = inc;
-    __syncthreads();
-    uint64_t pre = 0, all = 0;
-    for (int q = 0; q < 4; q++) {
-      if (q < w) pre += sm[q];
-      all += sm[q];
-    }
-    uint64_t at = run + pre + inc - local;
-#pragma unroll
-    for (int k = 0; k < CS_K; k++) {
-      if (cf + k < c1) off[(size_t)(cf + k) * R + d] = at;
-      at += v[k];
-    }
-    run += all;
-    __syncthreads();
   }
 }
 
@@ -527,9 +588,9 @@ uint32_t sort_tile_size() { return SC_MAX_TILE; }
   }
 
 hipError_t launch_sort_scan(int rb, const void* dig, const SortSeg* segs, uint32_t nseg,
-                            const SortChunk* chunks, uint32_t nchunks, uint32_t* cnt,
-                            uint64_t* tot, uint64_t* off, uint32_t* ticket, bool counts_ready,
-                            hipStream_t s) {
+                            const SortChunk* chunks, uint32_t nchunks, uint32_t n_cblk,
+                            uint32_t max_cblk, uint32_t* cnt, uint64_t* tot, uint64_t* part,
+                            uint64_t* off, uint32_t* ticket, bool counts_ready, hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
   const uint32_t R = 1u << rb;
   if (!counts_ready) {
@@ -540,8 +601,15 @@ hipError_t launch_sort_scan(int rb, const void* dig, const SortSeg* segs, uint32
     RB_SWITCH(rb, (count_kernel<RBV><<<grid, 64 * CNT_WAVES, 0, s>>>((const DigT<RBV>*)dig, chunks,
                                                                      nchunks, cnt)));
   }
-  RB_SWITCH(rb, (colsum_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot)));
-  RB_SWITCH(rb, (colscan_kernel<RBV><<<nseg * R, 256, 0, s>>>(cnt, segs, tot, off, ticket)));
+  // waves per (segment, 64 digits) workgroup: enough that each walks a few
+  // column blocks of the longest segment, at most 16
+  uint32_t G = 1;
+  while (G < 16 && G * 4 < max_cblk) G <<= 1;
+  const uint32_t dgrid = nseg * (R / 64);
+  RB_SWITCH(rb, (colpart_kernel<RBV><<<n_cblk, 256, 0, s>>>(cnt, segs, nseg, part)));
+  RB_SWITCH(rb, (coltot_kernel<RBV><<<dgrid, 64 * G, 0, s>>>(segs, part, tot)));
+  RB_SWITCH(rb, (colbase_kernel<RBV><<<dgrid, 64 * G, 0, s>>>(segs, tot, part, ticket)));
+  RB_SWITCH(rb, (coloff_kernel<RBV><<<n_cblk, 256, 0, s>>>(cnt, segs, nseg, part, off)));
   return hipGetLastError();
 }
 
