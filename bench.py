@@ -151,12 +151,14 @@ def apply_tuning(L, n_accesses, key_bits):
         autotune.apply(n_accesses, key_bits)
         return dict(digit_bits=best["digit_bits"] or "auto",
                     low_digit_bits=best.get("low_digit_bits", 0), shape=best["shape"],
-                    key_bits=key_bits, autotuned=True)
+                    narrow_shape=best.get("narrow_shape", 10), key_bits=key_bits,
+                    autotuned=True)
     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 0)
     L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 6)
     L.set_tuning(L.TUNE_SCATTER_SHAPE, 4)
-    return dict(digit_bits="auto", low_digit_bits=6, shape=4, key_bits=key_bits,
-                autotuned=False)
+    L.set_tuning(L.TUNE_NARROW_SHAPE, 10)
+    return dict(digit_bits="auto", low_digit_bits=6, shape=4, narrow_shape=10,
+                key_bits=key_bits, autotuned=False)
 
 
 def run_main(L, torch, km, steps, warmup):
@@ -329,6 +331,8 @@ def batched_leg(L, torch, kms):
             "accesses": bstats["accesses"], "rounds": bstats["rounds"],
             "phases_ms": {k: bstats[k] for k in ("ms_gen", "ms_sort", "ms_j0", "ms_check",
                                                  "ms_clause", "ms_solve", "ms_total")},
+            # the race-check phase of the batched call, as for the main leg
+            "race_check_phase": phase_roofline([bstats]),
             "autotuned": tuned}
 
 

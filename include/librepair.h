@@ -387,10 +387,16 @@ uint32_t rp_sort_key_bits(const rp_kernel* const* ks, uint32_t n);
  *                            32 bits, the point and id fields are taken from
  *                            the low 32 bits of each record with 32-bit
  *                            instructions (default), 1 = always from the
- *                            whole 64-bit record. */
+ *                            whole 64-bit record;
+ *   RP_TUNE_NARROW_SHAPE     radix-scatter tile of the passes whose digit has
+ *                            at most 7 bits: 0..9 as RP_TUNE_SCATTER_SHAPE,
+ *                            10 = the RP_TUNE_SCATTER_SHAPE tile (default).
+ *                            A narrow digit ranks with fewer ballots and
+ *                            writes longer runs, so its best tile can differ. */
 enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2,
        RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4, RP_TUNE_SCAN_PIPELINE = 5,
-       RP_TUNE_DIGIT_ORDER = 6, RP_TUNE_LOW_DIGIT_BITS = 7, RP_TUNE_SCAN_FIELDS = 8 };
+       RP_TUNE_DIGIT_ORDER = 6, RP_TUNE_LOW_DIGIT_BITS = 7, RP_TUNE_SCAN_FIELDS = 8,
+       RP_TUNE_NARROW_SHAPE = 9 };
 int rp_set_tuning(int knob, int value);
 
 /* For callers that cannot allocate device memory (code under stream

@@ -32,6 +32,18 @@ DIGITS = [(0, 6), (0, 7), (0, 8), (8, 0), (9, 0), (10, 0), (11, 0)]
 CANDIDATES = [(dg, shape) for dg in DIGITS for shape in range(10)]
 
 
+def has_narrow_pass(key_bits: int, digit_bits: int, low_digit_bits: int) -> bool:
+    """Whether the library's digit plan for this key has a pass of at most 7
+    bits (the passes RP_TUNE_NARROW_SHAPE applies to): only automatic widths
+    above a narrow lowest digit give one (digits of one width are 8..11)."""
+    rest = key_bits - low_digit_bits if key_bits > low_digit_bits else 0
+    n = (rest + 9) // 10
+    if digit_bits == 0 and low_digit_bits and rest > 0 and rest >= 6 * n:
+        widths = [low_digit_bits] + [rest // n + (1 if i < rest % n else 0) for i in range(n)]
+        return min(widths) <= 7
+    return False
+
+
 def _arch() -> str:
     import torch
     p = torch.cuda.get_device_properties(0)
@@ -62,6 +74,7 @@ def apply(n_accesses: int, key_bits: int) -> bool:
     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, best["digit_bits"])
     L.set_tuning(L.TUNE_LOW_DIGIT_BITS, best.get("low_digit_bits", 0))
     L.set_tuning(L.TUNE_SCATTER_SHAPE, best["shape"])
+    L.set_tuning(L.TUNE_NARROW_SHAPE, best.get("narrow_shape", 10))
     return True
 
 
@@ -75,6 +88,7 @@ def tune(kms, reps: int = 3, ws=None, candidates=None) -> dict:
         kms = L.KernelArg(kms)
     key_bits = L.sort_key_bits(kms)
     results = []
+    L.set_tuning(L.TUNE_NARROW_SHAPE, 10)
     for (rb, low), shape in candidates or CANDIDATES:
         L.set_tuning(L.TUNE_SORT_DIGIT_BITS, rb)
         L.set_tuning(L.TUNE_LOW_DIGIT_BITS, low)
@@ -95,17 +109,39 @@ def tune(kms, reps: int = 3, ws=None, candidates=None) -> dict:
         raise RuntimeError("no sort configuration ran")
     results.sort()
     t, rb, low, shape, acc = results[0]
+    # then the tile of the narrow-digit passes (at most 7 bits) on their own
+    L.set_tuning(L.TUNE_SORT_DIGIT_BITS, rb)
+    L.set_tuning(L.TUNE_LOW_DIGIT_BITS, low)
+    L.set_tuning(L.TUNE_SCATTER_SHAPE, shape)
+    narrow = 10
+    for ns in range(10 if has_narrow_pass(key_bits, rb, low) else 0):
+        if ns == shape:
+            continue
+        L.set_tuning(L.TUNE_NARROW_SHAPE, ns)
+        times = []
+        for _ in range(reps):
+            if batch:
+                ok = L.repair_batch(kms, ws=ws)[0] == 0
+            else:
+                ok = L.repair(kms, ws=ws)["ret"] in (L.OK, L.UNSAT)
+            if not ok:
+                break
+            s = L.last_stats()
+            times.append(s["ms_sort"] + s["ms_gen"])
+        if len(times) == reps and min(times) < t:
+            t, narrow = min(times), ns
+    L.set_tuning(L.TUNE_NARROW_SHAPE, narrow)
     dest = _out[0] or CACHE
     data = _load() if dest == CACHE or not os.path.exists(dest) else json.load(open(dest))
     data.setdefault(_arch(), {})[bucket(acc, key_bits)] = dict(
-        digit_bits=rb, low_digit_bits=low, shape=shape, ms=t)
+        digit_bits=rb, low_digit_bits=low, shape=shape, narrow_shape=narrow, ms=t)
     with open(dest, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, rb)
     L.set_tuning(L.TUNE_LOW_DIGIT_BITS, low)
     L.set_tuning(L.TUNE_SCATTER_SHAPE, shape)
-    return dict(digit_bits=rb, low_digit_bits=low, shape=shape, ms=t, key_bits=key_bits,
-                table=[(r[1], r[2], r[3], r[0]) for r in results])
+    return dict(digit_bits=rb, low_digit_bits=low, shape=shape, narrow_shape=narrow, ms=t,
+                key_bits=key_bits, table=[(r[1], r[2], r[3], r[0]) for r in results])
 
 
 WORKLOADS = ("stress-literal", "stress-planted", "plain-large-literal", "plain-large-planted",
@@ -132,7 +168,8 @@ def main(argv):
         best = sorted(r["table"], key=lambda e: e[3])[:5]
         print(json.dumps({"workload": name, "key_bits": r["key_bits"],
                           "digit_bits": r["digit_bits"], "low_digit_bits": r["low_digit_bits"],
-                          "shape": r["shape"], "ms": r["ms"], "best5": best}), flush=True)
+                          "shape": r["shape"], "narrow_shape": r["narrow_shape"], "ms": r["ms"],
+                          "best5": best}), flush=True)
         ws.t = None
         torch.cuda.empty_cache()
 

@@ -18,6 +18,7 @@ int scatter_variant(int v, bool set);
 int scatter_wgs(int v, bool set);
 int j0_variant(int v, bool set);
 int j0_fields_variant(int v, bool set);
+int narrow_shape(int v, bool set);
 
 // The option units of the switches of Section 4.2 (Tab. 3): with grid-level
 // barriers disabled every grid slot stays off; with inspection disabled every
@@ -401,6 +402,9 @@ int rp_set_tuning(int knob, int value) {
     case RP_TUNE_SCAN_FIELDS:
       if (value < 0 || value > 1) return -1;
       return j0_fields_variant(value, true);
+    case RP_TUNE_NARROW_SHAPE:
+      if (value < 0 || value > 10) return -1;
+      return narrow_shape(value, true);
     default:
       return -1;
   }

@@ -7,7 +7,7 @@
 //                    beside its output (1 byte per record for 8-bit digits,
 //                    2 above), not from the 8-byte records (pass 0 takes its
 //                    counts from record generation instead);
-//   colpart/coltot/colbase/coloff_kernel
+//   colpart/coltot/colbase(_small)/coloff_kernel
 //                    the exclusive scan of the counts per (segment, digit)
 //                    over the chunks, offset by the segment start and the
 //                    totals of smaller digits: the first output slot of
@@ -263,6 +263,65 @@ __global__ __launch_bounds__(1024) void colbase_kernel(const SortSeg* __restrict
     const uint64_t v = pd[(size_t)i * R];
     pd[(size_t)i * R] = base;
     base += v;
+  }
+}
+
+// Segments of few column blocks (at most COL_SMALL): totals, digit bases
+// and block bases of a whole segment in one workgroup (one launch instead of
+// the two above, whose cost on small logs is mostly the launch).
+constexpr uint32_t COL_SMALL = 32;
+
+template <int RB>
+__global__ __launch_bounds__(1024) void colbase_small_kernel(const SortSeg* __restrict__ segs,
+                                                             uint64_t* __restrict__ part,
+                                                             uint32_t* __restrict__ ticket) {
+  constexpr uint32_t R = 1u << RB;
+  constexpr uint32_t PER = (R + 1023) / 1024;   // consecutive digits per thread
+  __shared__ uint64_t s_tot[R];
+  __shared__ uint64_t s_w[16];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;
+  const SortSeg sg = segs[blockIdx.x];
+  const uint32_t nb = (sg.chunk_end - sg.chunk_beg + COL_BLOCK_CHUNKS - 1) / COL_BLOCK_CHUNKS;
+  uint64_t* pb = part + (size_t)sg.cblk_beg * R;
+  const uint32_t tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+  for (uint32_t d = tid; d < R; d += 1024) {
+    uint64_t t = 0;
+    for (uint32_t i = 0; i < nb; i++) t += pb[(size_t)i * R + d];
+    s_tot[d] = t;
+  }
+  __syncthreads();
+  // exclusive scan over the digits: thread tid owns digits [tid*PER, +PER)
+  uint64_t mine = 0;
+  for (uint32_t q = 0; q < PER; q++) {
+    const uint32_t d = tid * PER + q;
+    if (d < R) mine += s_tot[d];
+  }
+  uint64_t inc = mine;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(inc, o);
+    if (lane >= (uint32_t)o) inc += y;
+  }
+  if (lane == 63) s_w[w] = inc;
+  __syncthreads();
+  uint64_t run = sg.beg + inc - mine;
+  for (uint32_t v = 0; v < w; v++) run += s_w[v];
+  __syncthreads();                      // every s_tot read above is done
+  for (uint32_t q = 0; q < PER; q++) {
+    const uint32_t d = tid * PER + q;
+    if (d < R) {
+      const uint64_t t = s_tot[d];
+      s_tot[d] = run;                   // the digit's first slot in the segment
+      run += t;
+    }
+  }
+  __syncthreads();
+  for (uint32_t d = tid; d < R; d += 1024) {
+    uint64_t at = s_tot[d];
+    for (uint32_t i = 0; i < nb; i++) {
+      const uint64_t v = pb[(size_t)i * R + d];
+      pb[(size_t)i * R + d] = at;
+      at += v;
+    }
   }
 }
 
@@ -607,8 +666,12 @@ hipError_t launch_sort_scan(int rb, const void* dig, const SortSeg* segs, uint32
   while (G < 16 && G * 4 < max_cblk) G <<= 1;
   const uint32_t dgrid = nseg * (R / 64);
   RB_SWITCH(rb, (colpart_kernel<RBV><<<n_cblk, 256, 0, s>>>(cnt, segs, nseg, part)));
-  RB_SWITCH(rb, (coltot_kernel<RBV><<<dgrid, 64 * G, 0, s>>>(segs, part, tot)));
-  RB_SWITCH(rb, (colbase_kernel<RBV><<<dgrid, 64 * G, 0, s>>>(segs, tot, part, ticket)));
+  if (max_cblk <= COL_SMALL) {
+    RB_SWITCH(rb, (colbase_small_kernel<RBV><<<nseg, 1024, 0, s>>>(segs, part, ticket)));
+  } else {
+    RB_SWITCH(rb, (coltot_kernel<RBV><<<dgrid, 64 * G, 0, s>>>(segs, part, tot)));
+    RB_SWITCH(rb, (colbase_kernel<RBV><<<dgrid, 64 * G, 0, s>>>(segs, tot, part, ticket)));
+  }
   RB_SWITCH(rb, (coloff_kernel<RBV><<<n_cblk, 256, 0, s>>>(cnt, segs, nseg, part, off)));
   return hipGetLastError();
 }
@@ -617,6 +680,12 @@ static int g_scatter_variant = 4;   // 512 threads x 8 records: best measured de
 int scatter_variant(int v, bool set) {
   const int old = g_scatter_variant;
   if (set) g_scatter_variant = v;
+  return old;
+}
+static int g_narrow_shape = 10;     // shape of passes with digits of at most 7 bits (10: the same)
+int narrow_shape(int v, bool set) {
+  const int old = g_narrow_shape;
+  if (set) g_narrow_shape = v;
   return old;
 }
 static int g_scatter_wgs = 0;       // workgroups per CU; 0 = the occupancy query's answer
@@ -686,7 +755,7 @@ hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const 
                                int nbits, const uint64_t* off, uint32_t* ticket, uint32_t* err,
                                void* dnext, hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
-  const int v = g_scatter_variant;
+  const int v = rb <= 7 && g_narrow_shape < 10 ? g_narrow_shape : g_scatter_variant;
   RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err,
                                      dnext, s)));
   return hipGetLastError();

@@ -138,6 +138,7 @@ TUNE_SCAN_PIPELINE = 5
 TUNE_DIGIT_ORDER = 6
 TUNE_LOW_DIGIT_BITS = 7
 TUNE_SCAN_FIELDS = 8
+TUNE_NARROW_SHAPE = 9
 
 
 def lib():

@@ -243,6 +243,28 @@ def test_scan_variants_full_size(L, name, mode):
         L.set_tuning(L.TUNE_SCAN_FIELDS, old[1])
 
 
+def test_narrow_shape_full_size(L):
+    # every tile shape for the passes of at most 7-bit digits (plain-large's
+    # 6, 7 and 6-bit passes all take it) under a 1024 x 8 main shape: the
+    # same races as the oracle's stored result
+    exp = _expected("plain_large_literal")
+    km = synth.generate("plain-large", mode="literal")
+    x, c = next(iter(exp["checks"].items()))
+    old = (L.set_tuning(L.TUNE_SCATTER_SHAPE, 3), L.set_tuning(L.TUNE_NARROW_SHAPE, 10),
+           L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 0), L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 6))
+    try:
+        for narrow in range(11):
+            L.set_tuning(L.TUNE_NARROW_SHAPE, narrow)
+            g = L.check(km, int(x))
+            assert g[0] == 0 and g[3] == c["n_records"], narrow
+            assert [list(p) for p in g[1]] == c["pairs"], narrow
+    finally:
+        L.set_tuning(L.TUNE_SCATTER_SHAPE, old[0])
+        L.set_tuning(L.TUNE_NARROW_SHAPE, old[1])
+        L.set_tuning(L.TUNE_SORT_DIGIT_BITS, old[2])
+        L.set_tuning(L.TUNE_LOW_DIGIT_BITS, old[3])
+
+
 def test_sort_knobs_full_size(L):
     # every digit plan (one width of 8..11 bits, or a 6..8-bit lowest digit
     # with the rest in digits of 6 and 7 bits: 19 key bits) and scatter tile

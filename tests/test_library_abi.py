@@ -143,6 +143,14 @@ def test_tuning_knobs(L):
         assert L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 8) == 0
     finally:
         L.set_tuning(L.TUNE_LOW_DIGIT_BITS, old)
+    old = L.set_tuning(L.TUNE_NARROW_SHAPE, 4)
+    try:
+        assert old == 10                                         # the main tile shape
+        for bad in (-1, 11):
+            assert L.set_tuning(L.TUNE_NARROW_SHAPE, bad) == -1
+        assert L.set_tuning(L.TUNE_NARROW_SHAPE, 10) == 4
+    finally:
+        L.set_tuning(L.TUNE_NARROW_SHAPE, old)
     old = L.set_tuning(L.TUNE_SCAN_FIELDS, 1)
     try:
         assert old == 0                                          # 32-bit fields where they fit
@@ -156,3 +164,17 @@ def test_tuning_knobs(L):
 def test_invalid_kernel_does_no_device_work(L):
     bad = synth.make_kernel(0, 8, [(16, 0)], [(1, 0)], [], [])
     assert L.workspace_bytes(bad, L.OP_REPAIR) == 0
+
+
+def test_autotune_narrow_pass_rule():
+    # the tuner sweeps the narrow-digit tile only where the library's digit
+    # plan has a pass of at most 7 bits: automatic widths above a 6..8-bit
+    # lowest digit, the rest split evenly into digits of at most 10 bits
+    from paper_2011_08373_amd.autotune import has_narrow_pass
+    assert has_narrow_pass(24, 0, 6)          # 9, 9, 6
+    assert has_narrow_pass(19, 0, 6)          # 6, 7, 6
+    assert has_narrow_pass(19, 0, 7)          # 6, 6, 7
+    assert not has_narrow_pass(26, 0, 8)      # 9, 9, 8
+    assert not has_narrow_pass(19, 0, 8)      # too short above 8 bits: one width of 10
+    assert not has_narrow_pass(24, 9, 0)      # one width
+    assert not has_narrow_pass(8, 0, 6)       # too short: one width
