@@ -372,7 +372,7 @@ uint32_t rp_sort_key_bits(const rp_kernel* const* ks, uint32_t n);
  *                            write long runs and the lowest digit (short
  *                            runs) comes last, when no next-pass digits
  *                            are stored;
- *   RP_TUNE_LOW_DIGIT_BITS   with the automatic digit width: 6..8 = the
+ *   RP_TUNE_LOW_DIGIT_BITS   with the automatic digit width: 6..9 = the
  *                            lowest digit has that many bits and the rest
  *                            of the key is split evenly into digits of at
  *                            most 10 bits (default 6; a tile then writes

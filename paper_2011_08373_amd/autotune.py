@@ -3,7 +3,7 @@
 For a set of kernels (one size class) it times each (digits, tile shape)
 pair with the library's own hipEvent timings of record generation and the
 sort passes and keeps the fastest.  Digits are either of one width (8..11
-bits) or automatic with a narrow lowest digit (6..8 bits; the rest of the
+bits) or automatic with a narrow lowest digit (6..9 bits; the rest of the
 key in digits of at most 10 bits).  Results are cached in tuning.json next to
 this file, keyed by the GPU architecture and a size class: log2 of the access
 count and the radix key's width in bits (which sets how many passes each
@@ -28,7 +28,7 @@ CACHE = os.path.join(HERE, "tuning.json")
 _out = [None]                 # where tune() writes (None: CACHE)
 # (digit bits, lowest digit bits): one width (rb, 0), or automatic widths
 # with a narrow lowest digit (0, low)
-DIGITS = [(0, 6), (0, 7), (0, 8), (8, 0), (9, 0), (10, 0), (11, 0)]
+DIGITS = [(0, 6), (0, 7), (0, 8), (0, 9), (8, 0), (9, 0), (10, 0), (11, 0)]
 CANDIDATES = [(dg, shape) for dg in DIGITS for shape in range(10)]
 
 

@@ -397,7 +397,7 @@ int rp_set_tuning(int knob, int value) {
       if (value < 0 || value > 1) return -1;
       return digit_order(value, true);
     case RP_TUNE_LOW_DIGIT_BITS:
-      if (value != 0 && (value < 6 || value > 8)) return -1;
+      if (value != 0 && (value < 6 || value > 9)) return -1;
       return low_digit_bits(value, true);
     case RP_TUNE_SCAN_FIELDS:
       if (value < 0 || value > 1) return -1;

@@ -266,8 +266,9 @@ def test_narrow_shape_full_size(L):
 
 
 def test_sort_knobs_full_size(L):
-    # every digit plan (one width of 8..11 bits, or a 6..8-bit lowest digit
-    # with the rest in digits of 6 and 7 bits: 19 key bits) and scatter tile
+    # every digit plan (one width of 8..11 bits, or a 6..9-bit lowest digit
+    # with the rest of the 19 key bits in digits of at most 10 bits, one
+    # width where the rest is too short) and scatter tile
     # shape, with the scatter's grid at its resident size and at one
     # workgroup per compute unit (so the ~1,600 sort chunks of this log are
     # handed out by ticket), with the highest and with the lowest key digit
@@ -280,7 +281,7 @@ def test_sort_knobs_full_size(L):
            L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 6))
     try:
         for order in (1, 0):
-            for bits, low in ((0, 6), (0, 7), (0, 8), (8, 0), (9, 0), (10, 0), (11, 0)):
+            for bits, low in ((0, 6), (0, 7), (0, 8), (0, 9), (8, 0), (9, 0), (10, 0), (11, 0)):
                 for shape in range(10):
                     for wgs in (0, 1):
                         case = (order, bits, low, shape, wgs)

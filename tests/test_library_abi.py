@@ -138,9 +138,9 @@ def test_tuning_knobs(L):
     old = L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 0)
     try:
         assert old == 6                                          # a 6-bit lowest digit
-        for bad in (5, 9, -1):
+        for bad in (5, 10, -1):
             assert L.set_tuning(L.TUNE_LOW_DIGIT_BITS, bad) == -1
-        assert L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 8) == 0
+        assert L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 9) == 0
     finally:
         L.set_tuning(L.TUNE_LOW_DIGIT_BITS, old)
     old = L.set_tuning(L.TUNE_NARROW_SHAPE, 4)
