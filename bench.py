@@ -151,13 +151,13 @@ def apply_tuning(L, n_accesses, key_bits):
         autotune.apply(n_accesses, key_bits)
         return dict(digit_bits=best["digit_bits"] or "auto",
                     low_digit_bits=best.get("low_digit_bits", 0), shape=best["shape"],
-                    narrow_shape=best.get("narrow_shape", 10), key_bits=key_bits,
+                    pass_shapes=best.get("pass_shapes", []), key_bits=key_bits,
                     autotuned=True)
     L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 0)
     L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 6)
     L.set_tuning(L.TUNE_SCATTER_SHAPE, 4)
-    L.set_tuning(L.TUNE_NARROW_SHAPE, 10)
-    return dict(digit_bits="auto", low_digit_bits=6, shape=4, narrow_shape=10,
+    L.set_tuning(L.TUNE_PASS_SHAPES, L.PASS_SHAPES_DEFAULT)
+    return dict(digit_bits="auto", low_digit_bits=6, shape=4, pass_shapes=[],
                 key_bits=key_bits, autotuned=False)
 
 

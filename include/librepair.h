@@ -388,15 +388,22 @@ uint32_t rp_sort_key_bits(const rp_kernel* const* ks, uint32_t n);
  *                            the low 32 bits of each record with 32-bit
  *                            instructions (default), 1 = always from the
  *                            whole 64-bit record;
- *   RP_TUNE_NARROW_SHAPE     radix-scatter tile of the passes whose digit has
- *                            at most 7 bits: 0..9 as RP_TUNE_SCATTER_SHAPE,
- *                            10 = the RP_TUNE_SCATTER_SHAPE tile (default).
- *                            A narrow digit ranks with fewer ballots and
- *                            writes longer runs, so its best tile can differ. */
+ *   RP_TUNE_PASS_SHAPES      radix-scatter tile of each pass: 4 bits per
+ *                            pass in execution order (pass i in bits
+ *                            4i..4i+3, passes 0..6), each 0..9 as
+ *                            RP_TUNE_SCATTER_SHAPE or 15 = the
+ *                            RP_TUNE_SCATTER_SHAPE tile; passes from 7 on
+ *                            take that tile.  Default 0x0FFFFFFF (every
+ *                            pass on it).  A pass whose digit changes
+ *                            slowly along its input (the highest, in
+ *                            generation order) writes long runs and gains
+ *                            from more resident workgroups; one whose digit
+ *                            changes fast writes short runs and gains from
+ *                            longer tiles, so their best tiles differ. */
 enum { RP_TUNE_SORT_DIGIT_BITS = 0, RP_TUNE_SCATTER_SHAPE = 1, RP_TUNE_TIMING = 2,
        RP_TUNE_SCATTER_WGS = 3, RP_TUNE_SOLVER_NODES = 4, RP_TUNE_SCAN_PIPELINE = 5,
        RP_TUNE_DIGIT_ORDER = 6, RP_TUNE_LOW_DIGIT_BITS = 7, RP_TUNE_SCAN_FIELDS = 8,
-       RP_TUNE_NARROW_SHAPE = 9 };
+       RP_TUNE_PASS_SHAPES = 9 };
 int rp_set_tuning(int knob, int value);
 
 /* For callers that cannot allocate device memory (code under stream

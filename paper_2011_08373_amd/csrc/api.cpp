@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "common.h"
+#include "launch.h"
 #include "plan.h"
 
 namespace rp {
@@ -18,7 +19,7 @@ int scatter_variant(int v, bool set);
 int scatter_wgs(int v, bool set);
 int j0_variant(int v, bool set);
 int j0_fields_variant(int v, bool set);
-int narrow_shape(int v, bool set);
+int pass_shapes(int v, bool set);
 
 // The option units of the switches of Section 4.2 (Tab. 3): with grid-level
 // barriers disabled every grid slot stays off; with inspection disabled every
@@ -379,7 +380,7 @@ int rp_set_tuning(int knob, int value) {
       if (value != 0 && (value < 8 || value > 11)) return -1;
       return g_digit_bits_ref(value, true);
     case RP_TUNE_SCATTER_SHAPE:
-      if (value < 0 || value > 9) return -1;
+      if (value < 0 || value > SCATTER_SHAPE_MAX) return -1;
       return scatter_variant(value, true);
     case RP_TUNE_SCATTER_WGS:
       if (value < 0 || value > 8) return -1;
@@ -402,9 +403,13 @@ int rp_set_tuning(int knob, int value) {
     case RP_TUNE_SCAN_FIELDS:
       if (value < 0 || value > 1) return -1;
       return j0_fields_variant(value, true);
-    case RP_TUNE_NARROW_SHAPE:
-      if (value < 0 || value > 10) return -1;
-      return narrow_shape(value, true);
+    case RP_TUNE_PASS_SHAPES:
+      if (value < 0 || value > PASS_SHAPES_DEFAULT) return -1;
+      for (int p = 0; p < 7; p++) {
+        const int v = (value >> (4 * p)) & 15;
+        if (v > SCATTER_SHAPE_MAX && v != 15) return -1;
+      }
+      return pass_shapes(value, true);
     default:
       return -1;
   }

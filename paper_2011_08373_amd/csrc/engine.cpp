@@ -397,7 +397,7 @@ int prepare_jobs(const std::vector<JobInput>& jobs, const EngineOpts& o, const L
                             L.n_cblk, L.max_cblk, dcnt, dtot, (uint64_t*)(d + L.o_part), doff,
                             derr + 10, p == 0, s));
     tm.mark(T_SORTPASS);
-    HIPCHK(launch_sort_scatter((int)dg[p].bits, in, out, dss, dch, nch, (int)dg[p].lo,
+    HIPCHK(launch_sort_scatter((int)dg[p].bits, p, in, out, dss, dch, nch, (int)dg[p].lo,
                                last ? 0 : (int)dg[p + 1].lo, last ? 0 : (int)dg[p + 1].bits,
                                doff, derr + 10, derr, last ? nullptr : dig, s));
     tm.mark(T_SORT);

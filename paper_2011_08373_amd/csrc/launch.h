@@ -30,11 +30,15 @@ hipError_t launch_sort_scan(int rb, const void* dig, const SortSeg* segs, uint32
 // the next pass's digit, key bits [nlo, nlo + nbits), is stored per output
 // record in dnext (1 byte for up to 8 bits, else 2; NULL after the last
 // pass); ticket: one device word, set to zero by launch_sort_scan of the
-// same pass
-hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
-                               const SortChunk* chunks, uint32_t nchunks, int lo, int nlo,
-                               int nbits, const uint64_t* off, uint32_t* ticket, uint32_t* err,
-                               void* dnext, hipStream_t s);
+// same pass; pass: the pass's index in execution order (its tile shape)
+hipError_t launch_sort_scatter(int rb, int pass, const uint64_t* in, uint64_t* out,
+                               const SortSeg* segs, const SortChunk* chunks, uint32_t nchunks,
+                               int lo, int nlo, int nbits, const uint64_t* off, uint32_t* ticket,
+                               uint32_t* err, void* dnext, hipStream_t s);
+// Radix-scatter tile shapes 0..SCATTER_SHAPE_MAX; the per-pass shapes'
+// default (every pass on the common shape)
+constexpr int SCATTER_SHAPE_MAX = 9;
+constexpr int PASS_SHAPES_DEFAULT = 0x0FFFFFFF;
 constexpr int IVL_RESOLVE = 0, IVL_CHECK = 1, IVL_ZERO = 2;
 hipError_t launch_ivl(const Job* jobs, uint32_t njobs, int mode, hipStream_t s);
 hipError_t launch_save_j0(const Job* jobs, uint32_t njobs, hipStream_t s);

@@ -682,10 +682,12 @@ int scatter_variant(int v, bool set) {
   if (set) g_scatter_variant = v;
   return old;
 }
-static int g_narrow_shape = 10;     // shape of passes with digits of at most 7 bits (10: the same)
-int narrow_shape(int v, bool set) {
-  const int old = g_narrow_shape;
-  if (set) g_narrow_shape = v;
+// per-pass shapes: 4 bits per pass in execution order (passes 0..6), 15 =
+// the shape above
+static int g_pass_shapes = PASS_SHAPES_DEFAULT;
+int pass_shapes(int v, bool set) {
+  const int old = g_pass_shapes;
+  if (set) g_pass_shapes = v;
   return old;
 }
 static int g_scatter_wgs = 0;       // workgroups per CU; 0 = the occupancy query's answer
@@ -750,12 +752,13 @@ static void scatter_launch(int variant, uint32_t nchunks, const uint64_t* in, ui
   }
 }
 
-hipError_t launch_sort_scatter(int rb, const uint64_t* in, uint64_t* out, const SortSeg* segs,
-                               const SortChunk* chunks, uint32_t nchunks, int lo, int nlo,
-                               int nbits, const uint64_t* off, uint32_t* ticket, uint32_t* err,
-                               void* dnext, hipStream_t s) {
+hipError_t launch_sort_scatter(int rb, int pass, const uint64_t* in, uint64_t* out,
+                               const SortSeg* segs, const SortChunk* chunks, uint32_t nchunks,
+                               int lo, int nlo, int nbits, const uint64_t* off, uint32_t* ticket,
+                               uint32_t* err, void* dnext, hipStream_t s) {
   if (nchunks == 0) return hipSuccess;
-  const int v = rb <= 7 && g_narrow_shape < 10 ? g_narrow_shape : g_scatter_variant;
+  const int own = pass < 7 ? (g_pass_shapes >> (4 * pass)) & 15 : 15;
+  const int v = own <= SCATTER_SHAPE_MAX ? own : g_scatter_variant;
   RB_SWITCH(rb, (scatter_launch<RBV>(v, nchunks, in, out, chunks, segs, lo, nlo, nbits, off, ticket, err,
                                      dnext, s)));
   return hipGetLastError();

@@ -138,7 +138,18 @@ TUNE_SCAN_PIPELINE = 5
 TUNE_DIGIT_ORDER = 6
 TUNE_LOW_DIGIT_BITS = 7
 TUNE_SCAN_FIELDS = 8
-TUNE_NARROW_SHAPE = 9
+TUNE_PASS_SHAPES = 9
+PASS_SHAPES_DEFAULT = 0x0FFFFFFF     # every radix pass on TUNE_SCATTER_SHAPE's tile
+
+
+def pass_shapes_value(shapes) -> int:
+    """TUNE_PASS_SHAPES value of a per-pass list of tile shapes (execution
+    order; None or 15 = the TUNE_SCATTER_SHAPE tile)."""
+    v = PASS_SHAPES_DEFAULT
+    for p, sh in enumerate(list(shapes)[:7]):
+        if sh is not None:
+            v = (v & ~(15 << (4 * p))) | (int(sh) << (4 * p))
+    return v
 
 
 def lib():

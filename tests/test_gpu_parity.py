@@ -243,24 +243,29 @@ def test_scan_variants_full_size(L, name, mode):
         L.set_tuning(L.TUNE_SCAN_FIELDS, old[1])
 
 
-def test_narrow_shape_full_size(L):
-    # every tile shape for the passes of at most 7-bit digits (plain-large's
-    # 6, 7 and 6-bit passes all take it) under a 1024 x 8 main shape: the
-    # same races as the oracle's stored result
+def test_pass_shapes_full_size(L):
+    # every tile shape on each pass of plain-large's 6, 7 and 6-bit plan in
+    # turn, the other passes on a 1024 x 8 tile, and two per-pass mixes of
+    # its 10 and 9-bit plan: the same races as the oracle's stored result
     exp = _expected("plain_large_literal")
     km = synth.generate("plain-large", mode="literal")
     x, c = next(iter(exp["checks"].items()))
-    old = (L.set_tuning(L.TUNE_SCATTER_SHAPE, 3), L.set_tuning(L.TUNE_NARROW_SHAPE, 10),
+    old = (L.set_tuning(L.TUNE_SCATTER_SHAPE, 3),
+           L.set_tuning(L.TUNE_PASS_SHAPES, L.PASS_SHAPES_DEFAULT),
            L.set_tuning(L.TUNE_SORT_DIGIT_BITS, 0), L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 6))
     try:
-        for narrow in range(11):
-            L.set_tuning(L.TUNE_NARROW_SHAPE, narrow)
+        cases = [(6, [None] * p + [sh]) for p in range(3) for sh in range(10)]
+        cases += [(9, [6, 8]), (9, [7, 0])]
+        for low, shapes in cases:
+            L.set_tuning(L.TUNE_LOW_DIGIT_BITS, low)
+            L.set_tuning(L.TUNE_PASS_SHAPES, L.pass_shapes_value(shapes))
             g = L.check(km, int(x))
-            assert g[0] == 0 and g[3] == c["n_records"], narrow
-            assert [list(p) for p in g[1]] == c["pairs"], narrow
+            assert L.last_stats()["sort_passes"] == (3 if low == 6 else 2), (low, shapes)
+            assert g[0] == 0 and g[3] == c["n_records"], (low, shapes)
+            assert [list(p) for p in g[1]] == c["pairs"], (low, shapes)
     finally:
         L.set_tuning(L.TUNE_SCATTER_SHAPE, old[0])
-        L.set_tuning(L.TUNE_NARROW_SHAPE, old[1])
+        L.set_tuning(L.TUNE_PASS_SHAPES, old[1])
         L.set_tuning(L.TUNE_SORT_DIGIT_BITS, old[2])
         L.set_tuning(L.TUNE_LOW_DIGIT_BITS, old[3])
 

@@ -143,14 +143,16 @@ def test_tuning_knobs(L):
         assert L.set_tuning(L.TUNE_LOW_DIGIT_BITS, 9) == 0
     finally:
         L.set_tuning(L.TUNE_LOW_DIGIT_BITS, old)
-    old = L.set_tuning(L.TUNE_NARROW_SHAPE, 4)
+    old = L.set_tuning(L.TUNE_PASS_SHAPES, L.pass_shapes_value([None, 9, 4]))
     try:
-        assert old == 10                                         # the main tile shape
-        for bad in (-1, 11):
-            assert L.set_tuning(L.TUNE_NARROW_SHAPE, bad) == -1
-        assert L.set_tuning(L.TUNE_NARROW_SHAPE, 10) == 4
+        assert old == L.PASS_SHAPES_DEFAULT                      # every pass on the main tile
+        # a nibble of 10..14, a negative value or bits above pass 6 are rejected
+        for bad in (-1, 0x0FFFFFFA, 0x0FFFFEFF, 0x1FFFFFFF):
+            assert L.set_tuning(L.TUNE_PASS_SHAPES, bad) == -1
+        assert L.set_tuning(L.TUNE_PASS_SHAPES, 0) == 0x0FFFF49F   # passes 0..6 on shape 0
+        assert L.set_tuning(L.TUNE_PASS_SHAPES, L.PASS_SHAPES_DEFAULT) == 0
     finally:
-        L.set_tuning(L.TUNE_NARROW_SHAPE, old)
+        L.set_tuning(L.TUNE_PASS_SHAPES, old)
     old = L.set_tuning(L.TUNE_SCAN_FIELDS, 1)
     try:
         assert old == 0                                          # 32-bit fields where they fit
@@ -166,15 +168,10 @@ def test_invalid_kernel_does_no_device_work(L):
     assert L.workspace_bytes(bad, L.OP_REPAIR) == 0
 
 
-def test_autotune_narrow_pass_rule():
-    # the tuner sweeps the narrow-digit tile only where the library's digit
-    # plan has a pass of at most 7 bits: automatic widths above a 6..8-bit
-    # lowest digit, the rest split evenly into digits of at most 10 bits
-    from paper_2011_08373_amd.autotune import has_narrow_pass
-    assert has_narrow_pass(24, 0, 6)          # 9, 9, 6
-    assert has_narrow_pass(19, 0, 6)          # 6, 7, 6
-    assert has_narrow_pass(19, 0, 7)          # 6, 6, 7
-    assert not has_narrow_pass(26, 0, 8)      # 9, 9, 8
-    assert not has_narrow_pass(19, 0, 8)      # too short above 8 bits: one width of 10
-    assert not has_narrow_pass(24, 9, 0)      # one width
-    assert not has_narrow_pass(8, 0, 6)       # too short: one width
+def test_pass_shapes_value(L):
+    # per-pass tiles pack 4 bits per pass in execution order; unset passes
+    # (None) keep 15, the common tile, and passes past 6 are not encoded
+    assert L.pass_shapes_value([]) == L.PASS_SHAPES_DEFAULT == 0x0FFFFFFF
+    assert L.pass_shapes_value([6, 9]) == 0x0FFFFF96
+    assert L.pass_shapes_value([None, None, 4]) == 0x0FFFF4FF
+    assert L.pass_shapes_value([0] * 9) == 0                  # 7 passes of 4 bits
